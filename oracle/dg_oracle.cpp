@@ -1,0 +1,1025 @@
+// dg_oracle.cpp -- serial FP64 reference implementation of the DGSEM residual.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the oracle against which the HIP
+// path is checked.  Only the test suite, the smoke check and the CPU-baseline
+// leg of the benchmark may load it.  It shares no code, header, table or
+// helper with the GPU library, and it is deliberately plain: loops over
+// elements, sides and nodes in the order the equations are written, no
+// blocking, no fusion.
+//
+// What it computes (paper: "Governing Equations and Numerical Method"):
+//   * compressible Euler / Navier-Stokes-Fourier fluxes, perfect gas
+//     (the caloric EOS is read as p = (gamma-1) rho eps; the printed sign is
+//     garbled);
+//   * the collocated DGSEM weak form, eq. (dgsem_weak), on LG or LGL nodes;
+//   * BR1 lifting of the primitive gradients (u,v,w,T), eq. (dgsem_lifted),
+//     with the central face average;
+//   * the split-form (flux-differencing) volume integral with the
+//     Chandrashekar kinetic-energy-preserving, entropy-conservative two-point
+//     flux (LGL nodes);
+//   * the Rusanov surface flux (the paper's Roe flux is a later addition);
+//     the viscous surface flux is the arithmetic mean of both sides;
+//   * the low-storage RK4(5) scheme of Carpenter and Kennedy;
+//   * the integral kinetic energy E_k (TGV section) and its gradient;
+//   * forward-mode tangents (dual numbers) of the residual and of whole RK
+//     trajectories, from which adjoint checks are built by transposition.
+//
+// Function pins (closed forms, invariants, brute force) live in tests/.
+// Everything with no such pin is listed as "parity unpinned" below:
+//   * (none: every exported routine has at least one pin in tests/)
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+#include <algorithm>
+
+namespace orc {
+
+// ---------------------------------------------------------------------------
+// Scalar types.  The residual is written once as a template and evaluated
+// with plain doubles, with dual numbers (exact directional derivatives) and
+// with an operation-counting double.
+// ---------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+  Dual(double a = 0.0, double b = 0.0) : v(a), d(b) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) {
+  double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+inline Dual& operator*=(Dual& a, Dual b) { a = a * b; return a; }
+inline Dual log(Dual a) { return Dual(std::log(a.v), a.d / a.v); }
+inline Dual sqrt(Dual a) { double s = std::sqrt(a.v); return Dual(s, a.d / (2.0 * s)); }
+inline double val(Dual a) { return a.v; }
+inline double val(double a) { return a; }
+
+// Operation counter: each +,-,* ,/, sqrt, log on a Cnt bumps a counter.
+struct Cnt {
+  double v;
+  Cnt(double a = 0.0) : v(a) {}
+  static uint64_t n_add, n_mul, n_div, n_sqrt, n_log;
+};
+uint64_t Cnt::n_add = 0, Cnt::n_mul = 0, Cnt::n_div = 0, Cnt::n_sqrt = 0, Cnt::n_log = 0;
+inline Cnt operator+(Cnt a, Cnt b) { ++Cnt::n_add; return Cnt(a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { ++Cnt::n_add; return Cnt(a.v - b.v); }
+inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
+inline Cnt operator*(Cnt a, Cnt b) { ++Cnt::n_mul; return Cnt(a.v * b.v); }
+inline Cnt operator/(Cnt a, Cnt b) { ++Cnt::n_div; return Cnt(a.v / b.v); }
+inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
+inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
+inline Cnt& operator*=(Cnt& a, Cnt b) { a = a * b; return a; }
+inline Cnt log(Cnt a) { ++Cnt::n_log; return Cnt(std::log(a.v)); }
+inline Cnt sqrt(Cnt a) { ++Cnt::n_sqrt; return Cnt(std::sqrt(a.v)); }
+inline double val(Cnt a) { return a.v; }
+
+using std::log;
+using std::sqrt;
+
+// max that keeps the first argument on ties; |x| by sign of the value.
+template <class T> inline T maxv(const T& a, const T& b) { return val(a) >= val(b) ? a : b; }
+template <class T> inline T absv(const T& a) { return val(a) >= 0.0 ? a : T(-a); }
+
+// ---------------------------------------------------------------------------
+// 1-D basis (Kopriva, "Implementing Spectral Methods for PDEs", Legendre node
+// algorithms): nodes, weights, differentiation matrix, boundary values.
+// ---------------------------------------------------------------------------
+static void legendre(int n, double x, double& P, double& dP) {
+  // Three-term recurrence for P_n and its derivative.
+  if (n == 0) { P = 1.0; dP = 0.0; return; }
+  if (n == 1) { P = x; dP = 1.0; return; }
+  double Pm2 = 1.0, Pm1 = x, dPm2 = 0.0, dPm1 = 1.0, Pk = 0.0, dPk = 0.0;
+  for (int k = 2; k <= n; ++k) {
+    Pk = ((2.0 * k - 1.0) * x * Pm1 - (k - 1.0) * Pm2) / k;
+    dPk = dPm2 + (2.0 * k - 1.0) * Pm1;
+    Pm2 = Pm1; Pm1 = Pk; dPm2 = dPm1; dPm1 = dPk;
+  }
+  P = Pk; dP = dPk;
+}
+
+struct Basis {
+  int N = 0, type = 0;          // type 0 = Legendre-Gauss, 1 = Legendre-Gauss-Lobatto
+  std::vector<double> x, w;     // nodes and quadrature weights
+  std::vector<double> D;        // D[i*(N+1)+j] = l_j'(x_i)
+  std::vector<double> Lm, Lp;   // l_j(-1), l_j(+1)
+  std::vector<double> DS;       // split operator 2D - e_N e_N^T/w_N + e_0 e_0^T/w_0 (LGL)
+};
+
+static bool make_basis(int N, int type, Basis& B) {
+  if (N < 1 || N > 15 || (type != 0 && type != 1)) return false;
+  const int n = N + 1;
+  B.N = N; B.type = type;
+  B.x.assign(n, 0.0); B.w.assign(n, 0.0);
+  const double pi = std::acos(-1.0);
+  if (type == 0) {
+    // Roots of P_{N+1}; weights 2 / ((1-x^2) P'_{N+1}(x)^2).
+    for (int j = 0; j < n; ++j) {
+      double xj = -std::cos((2.0 * j + 1.0) * pi / (2.0 * N + 2.0));
+      for (int it = 0; it < 100; ++it) {
+        double P, dP; legendre(N + 1, xj, P, dP);
+        double dx = -P / dP; xj += dx;
+        if (std::fabs(dx) <= 1e-16 * std::max(1.0, std::fabs(xj))) break;
+      }
+      double P, dP; legendre(N + 1, xj, P, dP);
+      B.x[j] = xj; B.w[j] = 2.0 / ((1.0 - xj * xj) * dP * dP);
+    }
+  } else {
+    // Endpoints plus the roots of P_N'; weights 2 / (N(N+1) P_N(x)^2).
+    B.x[0] = -1.0; B.x[N] = 1.0;
+    for (int j = 1; j < N; ++j) {
+      double xj = -std::cos(pi * (j + 0.25) / N - 3.0 / (8.0 * N * pi * (j + 0.25)));
+      for (int it = 0; it < 100; ++it) {
+        double P, dP; legendre(N, xj, P, dP);
+        double d2P = (2.0 * xj * dP - N * (N + 1.0) * P) / (1.0 - xj * xj);
+        double dx = -dP / d2P; xj += dx;
+        if (std::fabs(dx) <= 1e-16 * std::max(1.0, std::fabs(xj))) break;
+      }
+      B.x[j] = xj;
+    }
+    for (int j = 0; j < n; ++j) {
+      double P, dP; legendre(N, B.x[j], P, dP);
+      B.w[j] = 2.0 / (N * (N + 1.0) * P * P);
+    }
+  }
+  // Enforce the exact mirror symmetry of the node set.
+  for (int j = 0; j < n / 2; ++j) {
+    double a = 0.5 * (B.x[N - j] - B.x[j]);
+    B.x[j] = -a; B.x[N - j] = a;
+    double ww = 0.5 * (B.w[j] + B.w[N - j]);
+    B.w[j] = ww; B.w[N - j] = ww;
+  }
+  if (n % 2 == 1) B.x[N / 2] = 0.0;
+  // Barycentric weights and the differentiation matrix.
+  std::vector<double> lam(n, 1.0);
+  for (int j = 0; j < n; ++j)
+    for (int k = 0; k < n; ++k)
+      if (k != j) lam[j] /= (B.x[j] - B.x[k]);
+  B.D.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double dij = (lam[j] / lam[i]) / (B.x[i] - B.x[j]);
+      B.D[i * n + j] = dij; s += dij;
+    }
+    B.D[i * n + i] = -s;
+  }
+  // Lagrange polynomials at the interval ends, by the product formula.
+  B.Lm.assign(n, 1.0); B.Lp.assign(n, 1.0);
+  for (int j = 0; j < n; ++j)
+    for (int k = 0; k < n; ++k) {
+      if (k == j) continue;
+      B.Lm[j] *= (-1.0 - B.x[k]) / (B.x[j] - B.x[k]);
+      B.Lp[j] *= (1.0 - B.x[k]) / (B.x[j] - B.x[k]);
+    }
+  B.DS.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) B.DS[i * n + j] = 2.0 * B.D[i * n + j];
+  B.DS[N * n + N] -= 1.0 / B.w[N];
+  B.DS[0] += 1.0 / B.w[0];
+  return true;
+}
+
+// Lagrange basis of an arbitrary node set evaluated at a point.
+static double lagrange(const std::vector<double>& xs, int j, double xi) {
+  double v = 1.0;
+  for (size_t k = 0; k < xs.size(); ++k)
+    if ((int)k != j) v *= (xi - xs[k]) / (xs[j] - xs[k]);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Configuration and mesh.
+// ---------------------------------------------------------------------------
+struct Config {
+  int N = 3, nodes = 0, form = 0, physics = 0;
+  int twopoint = 0;     // 0 = Chandrashekar, 1 = central average (test switch)
+  int dissipation = 1;  // 1 = Rusanov dissipation on, 0 = off (test switch)
+  int mms = 0;          // 1 = add the manufactured-solution source
+  double gamma = 1.4, mu = 0.0, Pr = 0.72, R = 1.0;
+  double mms_A = 0.1, mms_a = 1.0;
+};
+
+// Face-local index convention.  Local face f of a hexahedron: f/2 is the
+// reference direction of its normal, f%2 = 0 is the "-1" end and 1 the "+1"
+// end.  Face-local indices (p,q) are the two tangential volume indices in
+// increasing direction order; l runs along the normal line.
+static inline void vol_ijk(int f, int p, int q, int l, int& i, int& j, int& k) {
+  switch (f / 2) {
+    case 0: i = l; j = p; k = q; break;
+    case 1: i = p; j = l; k = q; break;
+    default: i = p; j = q; k = l; break;
+  }
+}
+// Orientation code o maps the master's (p,q) to the slave's (p',q'):
+// swap if bit 2, then reverse the first index if bit 0, the second if bit 1.
+static inline void orient_fwd(int o, int N, int p, int q, int& pp, int& qq) {
+  int a = (o & 4) ? q : p, b = (o & 4) ? p : q;
+  if (o & 1) a = N - a;
+  if (o & 2) b = N - b;
+  pp = a; qq = b;
+}
+static inline void orient_inv(int o, int N, int pp, int qq, int& p, int& q) {
+  int a = pp, b = qq;
+  if (o & 1) a = N - a;
+  if (o & 2) b = N - b;
+  if (o & 4) { p = b; q = a; } else { p = a; q = b; }
+}
+
+// Carpenter & Kennedy (1994) five-stage, fourth-order 2N-storage scheme.
+static void lserk_coeffs(double* A, double* B, double* C) {
+  const double a[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                       -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+  const double b[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                       1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                       2277821191437.0 / 14882151754819.0};
+  const double c[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                       2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
+  for (int s = 0; s < 5; ++s) { A[s] = a[s]; B[s] = b[s]; C[s] = c[s]; }
+}
+
+struct Solver {
+  Config C;
+  Basis B;
+  int n1 = 0, n2 = 0, n3 = 0;
+  int nElems = 0, Ngeo = 0, nSides = 0;
+  std::vector<double> Xgeo;                  // [3][nElems][Ngeo+1]^3
+  std::vector<int> sideElem, sideLoc, sideOrient;
+  std::vector<int> elemSide, elemSlot;       // [nElems*6]
+  std::vector<double> Vgeo;                  // [n1][Ngeo+1] equispaced -> solution nodes
+  // lazily computed geometry
+  std::vector<std::vector<double>> Ja;       // per element: [9][n3], index 3*r+n
+  std::vector<std::vector<double>> Jdet;     // per element: [n3]
+  std::vector<std::vector<double>> Xnode;    // per element: [3][n3]
+  std::vector<std::vector<double>> nvec;     // per side: [3][n2] master outward n*s
+  std::string err;
+  double lsA[5], lsB[5], lsC[5];
+
+  int node(int i, int j, int k) const { return (k * n1 + j) * n1 + i; }
+  size_t uidx(int v, int e, int nd) const { return ((size_t)v * nElems + e) * n3 + nd; }
+
+  bool setup() {
+    lserk_coeffs(lsA, lsB, lsC);
+    if (!make_basis(C.N, C.nodes, B)) { err = "bad basis"; return false; }
+    if (C.form == 1 && C.nodes != 1) { err = "split form needs LGL nodes"; return false; }
+    n1 = C.N + 1; n2 = n1 * n1; n3 = n2 * n1;
+    std::vector<double> xg(Ngeo + 1);
+    for (int m = 0; m <= Ngeo; ++m) xg[m] = -1.0 + 2.0 * m / Ngeo;
+    Vgeo.assign((size_t)n1 * (Ngeo + 1), 0.0);
+    for (int i = 0; i < n1; ++i)
+      for (int m = 0; m <= Ngeo; ++m) Vgeo[i * (Ngeo + 1) + m] = lagrange(xg, m, B.x[i]);
+    elemSide.assign((size_t)nElems * 6, -1); elemSlot.assign((size_t)nElems * 6, -1);
+    for (int s = 0; s < nSides; ++s)
+      for (int m = 0; m < 2; ++m) {
+        int e = sideElem[2 * s + m], f = sideLoc[2 * s + m];
+        if (e < 0 || e >= nElems || f < 0 || f > 5 || elemSide[e * 6 + f] != -1) { err = "bad connectivity"; return false; }
+        elemSide[e * 6 + f] = s; elemSlot[e * 6 + f] = m;
+      }
+    for (size_t t = 0; t < elemSide.size(); ++t)
+      if (elemSide[t] < 0) { err = "open face"; return false; }
+    Ja.assign(nElems, {}); Jdet.assign(nElems, {}); Xnode.assign(nElems, {}); nvec.assign(nSides, {});
+    return true;
+  }
+
+  // Geometry of element e at the solution nodes (tensor-product interpolation
+  // of the equispaced geometry nodes, one direction at a time).
+  void ensure_geom(int e) {
+    if (!Jdet[e].empty()) return;
+    const int g1 = Ngeo + 1;
+    std::vector<double>& X = Xnode[e];
+    X.assign(3 * (size_t)n3, 0.0);
+    // Geometry is interpolated relative to the element's first geometry node
+    // x0 (all metric terms are invariant under translation); this keeps the
+    // rounding error of the metrics proportional to the element size.
+    double x0[3];
+    for (int d = 0; d < 3; ++d) {
+      const double* xg = &Xgeo[((size_t)d * nElems + e) * g1 * g1 * g1];
+      x0[d] = xg[0];
+      std::vector<double> t1((size_t)g1 * g1 * n1), t2((size_t)g1 * n1 * n1);
+      for (int c = 0; c < g1; ++c)
+        for (int b = 0; b < g1; ++b)
+          for (int i = 0; i < n1; ++i) {
+            double s = 0.0;
+            for (int a = 0; a < g1; ++a) s += Vgeo[i * g1 + a] * (xg[(c * g1 + b) * g1 + a] - x0[d]);
+            t1[(c * g1 + b) * n1 + i] = s;
+          }
+      for (int c = 0; c < g1; ++c)
+        for (int j = 0; j < n1; ++j)
+          for (int i = 0; i < n1; ++i) {
+            double s = 0.0;
+            for (int b = 0; b < g1; ++b) s += Vgeo[j * g1 + b] * t1[(c * g1 + b) * n1 + i];
+            t2[(c * n1 + j) * n1 + i] = s;
+          }
+      for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+          for (int i = 0; i < n1; ++i) {
+            double s = 0.0;
+            for (int c = 0; c < g1; ++c) s += Vgeo[k * g1 + c] * t2[(c * n1 + j) * n1 + i];
+            X[(size_t)d * n3 + node(i, j, k)] = s;
+          }
+    }
+    // d/dxi_r of a nodal field along reference direction r.
+    auto deriv = [&](const double* f, int r, double* out) {
+      for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+          for (int i = 0; i < n1; ++i) {
+            int a = (r == 0) ? i : (r == 1) ? j : k;
+            double s = 0.0;
+            for (int l = 0; l < n1; ++l) {
+              int ii = i, jj = j, kk = k;
+              if (r == 0) ii = l; else if (r == 1) jj = l; else kk = l;
+              s += B.D[a * n1 + l] * f[node(ii, jj, kk)];
+            }
+            out[node(i, j, k)] = s;
+          }
+    };
+    std::vector<double> dX(9 * (size_t)n3);  // dX[3*d+r] = dX_d/dxi_r
+    for (int d = 0; d < 3; ++d)
+      for (int r = 0; r < 3; ++r) deriv(&X[(size_t)d * n3], r, &dX[(size_t)(3 * d + r) * n3]);
+    std::vector<double>& J = Jdet[e];
+    J.assign(n3, 0.0);
+    for (int t = 0; t < n3; ++t) {
+      double a[3][3];
+      for (int d = 0; d < 3; ++d)
+        for (int r = 0; r < 3; ++r) a[d][r] = dX[(size_t)(3 * d + r) * n3 + t];
+      J[t] = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) - a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+             a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+    }
+    // Conservative curl form (Kopriva 2006): Ja^r_n = -[curl_xi (X_l grad_xi X_m)]_r,
+    // (n,m,l) cyclic, with the product collocated at the solution nodes.
+    std::vector<double>& M = Ja[e];
+    M.assign(9 * (size_t)n3, 0.0);
+    std::vector<double> V(3 * (size_t)n3);
+    for (int nn = 0; nn < 3; ++nn) {
+      int m = (nn + 1) % 3, l = (nn + 2) % 3;
+      for (int s = 0; s < 3; ++s)
+        for (int t = 0; t < n3; ++t)
+          V[(size_t)s * n3 + t] = X[(size_t)l * n3 + t] * dX[(size_t)(3 * m + s) * n3 + t];
+      // curl components: c_0 = d1 V2 - d2 V1, c_1 = d2 V0 - d0 V2, c_2 = d0 V1 - d1 V0
+      std::vector<double> a(n3), b(n3);
+      for (int r = 0; r < 3; ++r) {
+        int r1 = (r + 1) % 3, r2 = (r + 2) % 3;
+        deriv(&V[(size_t)r2 * n3], r1, a.data());
+        deriv(&V[(size_t)r1 * n3], r2, b.data());
+        for (int t = 0; t < n3; ++t) M[(size_t)(3 * r + nn) * n3 + t] = -(a[t] - b[t]);
+      }
+    }
+    for (int d = 0; d < 3; ++d)
+      for (int t = 0; t < n3; ++t) X[(size_t)d * n3 + t] += x0[d];
+  }
+
+  void ensure_side(int s) {
+    if (!nvec[s].empty()) return;
+    int e = sideElem[2 * s], f = sideLoc[2 * s];
+    ensure_geom(e);
+    const int d = f / 2;
+    const double sg = (f % 2) ? 1.0 : -1.0;
+    const std::vector<double>& L = (f % 2) ? B.Lp : B.Lm;
+    nvec[s].assign(3 * (size_t)n2, 0.0);
+    for (int q = 0; q < n1; ++q)
+      for (int p = 0; p < n1; ++p)
+        for (int c = 0; c < 3; ++c) {
+          double v = 0.0;
+          for (int l = 0; l < n1; ++l) {
+            int i, j, k; vol_ijk(f, p, q, l, i, j, k);
+            v += L[l] * Ja[e][(size_t)(3 * d + c) * n3 + node(i, j, k)];
+          }
+          nvec[s][(size_t)c * n2 + q * n1 + p] = sg * v;
+        }
+  }
+
+  bool check_jacobians() {
+    for (int e = 0; e < nElems; ++e) {
+      ensure_geom(e);
+      for (int t = 0; t < n3; ++t)
+        if (!(Jdet[e][t] > 0.0)) { err = "non-positive Jacobian"; return false; }
+    }
+    return true;
+  }
+
+  // -------------------------------------------------------------------------
+  // Physics (paper eq. for F; perfect gas).
+  // -------------------------------------------------------------------------
+  template <class T> void prim(const T* U, T& rho, T* u, T& p) const {
+    rho = U[0];
+    for (int d = 0; d < 3; ++d) u[d] = U[1 + d] / rho;
+    p = (C.gamma - 1.0) * (U[4] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+  }
+  // Advective flux in the (not necessarily unit) direction nv.
+  template <class T> void flux_adv(const T* U, const double* nv, T* F) const {
+    T rho, u[3], p; prim(U, rho, u, p);
+    T un = u[0] * nv[0] + u[1] * nv[1] + u[2] * nv[2];
+    F[0] = rho * un;
+    for (int d = 0; d < 3; ++d) F[1 + d] = U[1 + d] * un + p * nv[d];
+    F[4] = (U[4] + p) * un;
+  }
+  // Logarithmic mean (x - y) / (ln x - ln y), with the atanh series near x = y.
+  template <class T> T logmean(const T& x, const T& y) const {
+    T f = (x - y) / (x + y);
+    T u = f * f;
+    if (val(u) < 1e-4)
+      return (x + y) / (2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0))));
+    return (x - y) / (log(x) - log(y));
+  }
+  // Two-point volume flux in direction nv (linear in nv).
+  template <class T> void flux_twopoint(const T* Ua, const T* Ub, const double* nv, T* F) const {
+    if (C.twopoint == 1) {
+      T Fa[5], Fb[5];
+      flux_adv(Ua, nv, Fa); flux_adv(Ub, nv, Fb);
+      for (int v = 0; v < 5; ++v) F[v] = 0.5 * (Fa[v] + Fb[v]);
+      return;
+    }
+    // Chandrashekar (2013): beta = rho/(2p); rho^ln, beta^ln logarithmic
+    // means; p_hat = {rho}/(2{beta}).
+    T ra, ua[3], pa, rb, ub[3], pb;
+    prim(Ua, ra, ua, pa); prim(Ub, rb, ub, pb);
+    T ba = ra / (2.0 * pa), bb = rb / (2.0 * pb);
+    T rho_ln = logmean(ra, rb), beta_ln = logmean(ba, bb);
+    T um[3];
+    for (int d = 0; d < 3; ++d) um[d] = 0.5 * (ua[d] + ub[d]);
+    T phat = 0.5 * (ra + rb) / (2.0 * (0.5 * (ba + bb)));
+    T u2m = 0.5 * ((ua[0] * ua[0] + ua[1] * ua[1] + ua[2] * ua[2]) + (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]));
+    T umn = um[0] * nv[0] + um[1] * nv[1] + um[2] * nv[2];
+    F[0] = rho_ln * umn;
+    for (int d = 0; d < 3; ++d) F[1 + d] = phat * nv[d] + um[d] * F[0];
+    F[4] = F[0] * (1.0 / (2.0 * (C.gamma - 1.0) * beta_ln) - 0.5 * u2m) +
+           (um[0] * F[1] + um[1] * F[2] + um[2] * F[3]);
+  }
+  // Viscous flux G_n(U, grad) in Cartesian direction n; grad[3*a+d] = dq_a/dx_d,
+  // q = (u, v, w, T).  Newtonian stress with Stokes' hypothesis, Fourier heat flux.
+  template <class T> void flux_visc(const T* U, const T* g, int n, T* G) const {
+    T rho, u[3], p; prim(U, rho, u, p);
+    const double mu = C.mu;
+    const double lam = C.mu * C.gamma * C.R / ((C.gamma - 1.0) * C.Pr);
+    T divu = g[0] + g[4] + g[8];
+    T tau[3];
+    for (int a = 0; a < 3; ++a) {
+      tau[a] = mu * (g[3 * a + n] + g[3 * n + a]);
+      if (a == n) tau[a] = tau[a] - (2.0 / 3.0) * mu * divu;
+    }
+    G[0] = T(0.0);
+    for (int a = 0; a < 3; ++a) G[1 + a] = tau[a];
+    G[4] = tau[0] * u[0] + tau[1] * u[1] + tau[2] * u[2] + lam * g[9 + n];
+  }
+
+  // Manufactured solution of the convergence section:
+  // rho = 2 + A sin(2 pi (x+y+z - a t)), rho u = rho, rho e = rho^2.
+  void mms_source(double x, double y, double z, double t, double* Q) const {
+    const double pi = std::acos(-1.0), A = C.mms_A, a = C.mms_a, g = C.gamma;
+    double ph = 2.0 * pi * (x + y + z - a * t);
+    double r = 2.0 + A * std::sin(ph);
+    double r1 = 2.0 * pi * A * std::cos(ph);
+    double r2 = -4.0 * pi * pi * A * std::sin(ph);
+    Q[0] = (3.0 - a) * r1;
+    double qm = (3.0 - a) * r1 + (g - 1.0) * (2.0 * r - 1.5) * r1;
+    Q[1] = qm; Q[2] = qm; Q[3] = qm;
+    Q[4] = (6.0 - 2.0 * a) * r * r1 + 3.0 * (g - 1.0) * (2.0 * r - 1.5) * r1 - 3.0 * C.mu * g * r2 / C.Pr;
+  }
+
+  // -------------------------------------------------------------------------
+  // The residual.  U, Ut: [5][nElems][n3].  If elist is non-empty only those
+  // elements of Ut are written (and only the data they need is computed).
+  // -------------------------------------------------------------------------
+  template <class T> struct Work {
+    std::vector<std::vector<T>> tr;     // per side: [2][5][n2] U traces (master indexing)
+    std::vector<std::vector<T>> g;      // per element: [12][n3] lifted gradients
+    std::vector<std::vector<T>> gtr;    // per side: [2][12][n2] gradient traces
+  };
+
+  template <class T> void side_traces(const T* U, int s, Work<T>& W) {
+    if (!W.tr[s].empty()) return;
+    W.tr[s].assign(2 * 5 * (size_t)n2, T(0.0));
+    for (int m = 0; m < 2; ++m) {
+      int e = sideElem[2 * s + m], f = sideLoc[2 * s + m];
+      const std::vector<double>& L = (f % 2) ? B.Lp : B.Lm;
+      for (int q = 0; q < n1; ++q)
+        for (int p = 0; p < n1; ++p) {
+          int pp = p, qq = q;
+          if (m == 1) orient_fwd(sideOrient[s], C.N, p, q, pp, qq);
+          for (int v = 0; v < 5; ++v) {
+            T acc(0.0);
+            for (int l = 0; l < n1; ++l) {
+              int i, j, k; vol_ijk(f, pp, qq, l, i, j, k);
+              acc += L[l] * U[uidx(v, e, node(i, j, k))];
+            }
+            W.tr[s][((size_t)m * 5 + v) * n2 + q * n1 + p] = acc;
+          }
+        }
+    }
+  }
+
+  template <class T> void lift_elem(const T* U, int e, Work<T>& W) {
+    if (!W.g[e].empty()) return;
+    ensure_geom(e);
+    for (int f = 0; f < 6; ++f) { side_traces(U, elemSide[e * 6 + f], W); ensure_side(elemSide[e * 6 + f]); }
+    std::vector<T> q(4 * (size_t)n3);
+    for (int t = 0; t < n3; ++t) {
+      T Ul[5]; for (int v = 0; v < 5; ++v) Ul[v] = U[uidx(v, e, t)];
+      T rho, u[3], p; prim(Ul, rho, u, p);
+      q[t] = u[0]; q[n3 + t] = u[1]; q[2 * (size_t)n3 + t] = u[2]; q[3 * (size_t)n3 + t] = p / (rho * C.R);
+    }
+    std::vector<T>& g = W.g[e];
+    g.assign(12 * (size_t)n3, T(0.0));
+    const std::vector<double>& M = Ja[e];
+    // Volume part of eq. (dgsem_lifted): -sum_r sum_l (w_l/w_a) D_{l a} (Ja^r_d q)_l.
+    for (int k = 0; k < n1; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+          int t = node(i, j, k);
+          for (int a = 0; a < 4; ++a)
+            for (int d = 0; d < 3; ++d) {
+              T acc(0.0);
+              for (int r = 0; r < 3; ++r) {
+                int ai = (r == 0) ? i : (r == 1) ? j : k;
+                for (int l = 0; l < n1; ++l) {
+                  int ii = i, jj = j, kk = k;
+                  if (r == 0) ii = l; else if (r == 1) jj = l; else kk = l;
+                  int tl = node(ii, jj, kk);
+                  double c = B.w[l] / B.w[ai] * B.D[l * n1 + ai];
+                  acc -= c * (M[(size_t)(3 * r + d) * n3 + tl] * q[(size_t)a * n3 + tl]);
+                }
+              }
+              g[(size_t)(3 * a + d) * n3 + t] = acc;
+            }
+        }
+    // Surface part: (1/w) l(+-1) {q} (n s)_d with the outward normal.
+    for (int f = 0; f < 6; ++f) {
+      int s = elemSide[e * 6 + f], m = elemSlot[e * 6 + f];
+      const std::vector<double>& L = (f % 2) ? B.Lp : B.Lm;
+      for (int qq = 0; qq < n1; ++qq)
+        for (int pp = 0; pp < n1; ++pp) {
+          int p = pp, q2 = qq;
+          if (m == 1) orient_inv(sideOrient[s], C.N, pp, qq, p, q2);
+          int fi = q2 * n1 + p;
+          T qa[4], qb[4];
+          for (int side = 0; side < 2; ++side) {
+            T Ul[5]; for (int v = 0; v < 5; ++v) Ul[v] = W.tr[s][((size_t)side * 5 + v) * n2 + fi];
+            T rho, u[3], pr; prim(Ul, rho, u, pr);
+            T* qx = side == 0 ? qa : qb;
+            qx[0] = u[0]; qx[1] = u[1]; qx[2] = u[2]; qx[3] = pr / (rho * C.R);
+          }
+          double ns[3];
+          for (int c = 0; c < 3; ++c) ns[c] = (m == 0 ? 1.0 : -1.0) * nvec[s][(size_t)c * n2 + fi];
+          for (int l = 0; l < n1; ++l) {
+            int i, j, k; vol_ijk(f, pp, qq, l, i, j, k);
+            int t = node(i, j, k);
+            double c = L[l] / B.w[l];
+            for (int a = 0; a < 4; ++a) {
+              T avg = 0.5 * (qa[a] + qb[a]);
+              for (int d = 0; d < 3; ++d) g[(size_t)(3 * a + d) * n3 + t] += c * (avg * ns[d]);
+            }
+          }
+        }
+    }
+    for (size_t c = 0; c < 12; ++c)
+      for (int t = 0; t < n3; ++t) g[c * n3 + t] = g[c * n3 + t] / Jdet[e][t];
+  }
+
+  template <class T> void side_grad_traces(const T* U, int s, Work<T>& W) {
+    if (!W.gtr[s].empty()) return;
+    W.gtr[s].assign(2 * 12 * (size_t)n2, T(0.0));
+    for (int m = 0; m < 2; ++m) {
+      int e = sideElem[2 * s + m], f = sideLoc[2 * s + m];
+      lift_elem(U, e, W);
+      const std::vector<double>& L = (f % 2) ? B.Lp : B.Lm;
+      for (int q = 0; q < n1; ++q)
+        for (int p = 0; p < n1; ++p) {
+          int pp = p, qq = q;
+          if (m == 1) orient_fwd(sideOrient[s], C.N, p, q, pp, qq);
+          for (int c = 0; c < 12; ++c) {
+            T acc(0.0);
+            for (int l = 0; l < n1; ++l) {
+              int i, j, k; vol_ijk(f, pp, qq, l, i, j, k);
+              acc += L[l] * W.g[e][(size_t)c * n3 + node(i, j, k)];
+            }
+            W.gtr[s][((size_t)m * 12 + c) * n2 + q * n1 + p] = acc;
+          }
+        }
+    }
+  }
+
+  // Outward (master) surface flux Phi at every face node of side s: [5][n2].
+  template <class T> void side_flux(const T* U, int s, Work<T>& W, std::vector<T>& Phi) {
+    side_traces(U, s, W);
+    ensure_side(s);
+    if (C.physics == 1) side_grad_traces(U, s, W);
+    Phi.assign(5 * (size_t)n2, T(0.0));
+    for (int fi = 0; fi < n2; ++fi) {
+      T UL[5], UR[5];
+      for (int v = 0; v < 5; ++v) {
+        UL[v] = W.tr[s][(size_t)v * n2 + fi];
+        UR[v] = W.tr[s][((size_t)5 + v) * n2 + fi];
+      }
+      double nv[3], nh[3];
+      for (int c = 0; c < 3; ++c) nv[c] = nvec[s][(size_t)c * n2 + fi];
+      double sA = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+      for (int c = 0; c < 3; ++c) nh[c] = nv[c] / sA;
+      T Fc[5];
+      if (C.form == 1) {
+        flux_twopoint(UL, UR, nv, Fc);
+      } else {
+        T FL[5], FR[5];
+        flux_adv(UL, nv, FL); flux_adv(UR, nv, FR);
+        for (int v = 0; v < 5; ++v) Fc[v] = 0.5 * (FL[v] + FR[v]);
+      }
+      T lmax(0.0);
+      if (C.dissipation) {
+        T rl, ul[3], pl, rr, ur[3], pr;
+        prim(UL, rl, ul, pl); prim(UR, rr, ur, pr);
+        T cl = sqrt(C.gamma * pl / rl), cr = sqrt(C.gamma * pr / rr);
+        T unl = ul[0] * nh[0] + ul[1] * nh[1] + ul[2] * nh[2];
+        T unr = ur[0] * nh[0] + ur[1] * nh[1] + ur[2] * nh[2];
+        lmax = maxv(T(absv(unl) + cl), T(absv(unr) + cr));
+      }
+      for (int v = 0; v < 5; ++v) Phi[(size_t)v * n2 + fi] = Fc[v] - 0.5 * (lmax * sA) * (UR[v] - UL[v]);
+      if (C.physics == 1) {
+        T gL[12], gR[12];
+        for (int c = 0; c < 12; ++c) {
+          gL[c] = W.gtr[s][(size_t)c * n2 + fi];
+          gR[c] = W.gtr[s][((size_t)12 + c) * n2 + fi];
+        }
+        for (int n = 0; n < 3; ++n) {
+          T GL[5], GR[5];
+          flux_visc(UL, gL, n, GL); flux_visc(UR, gR, n, GR);
+          for (int v = 0; v < 5; ++v) Phi[(size_t)v * n2 + fi] -= 0.5 * (GL[v] + GR[v]) * nv[n];
+        }
+      }
+    }
+  }
+
+  template <class T> void residual_elem(const T* U, int e, Work<T>& W, std::vector<std::vector<T>>& sflux,
+                                        T* Ut, double t) {
+    ensure_geom(e);
+    const std::vector<double>& M = Ja[e];
+    std::vector<T> V(5 * (size_t)n3, T(0.0));
+    auto Uat = [&](int tt, T* out) { for (int v = 0; v < 5; ++v) out[v] = U[uidx(v, e, tt)]; };
+    // Contravariant fluxes Ftilde^r = sum_n Ja^r_n F_n at every node.
+    // (weak form: advective + viscous; split form: viscous only)
+    std::vector<T> Ft(15 * (size_t)n3, T(0.0));
+    for (int tt = 0; tt < n3; ++tt) {
+      T Ul[5]; Uat(tt, Ul);
+      for (int r = 0; r < 3; ++r) {
+        double nv[3] = {M[(size_t)(3 * r + 0) * n3 + tt], M[(size_t)(3 * r + 1) * n3 + tt], M[(size_t)(3 * r + 2) * n3 + tt]};
+        T F[5] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
+        if (C.form == 0) flux_adv(Ul, nv, F);
+        if (C.physics == 1) {
+          T gl[12];
+          for (int c = 0; c < 12; ++c) gl[c] = W.g[e][(size_t)c * n3 + tt];
+          for (int n = 0; n < 3; ++n) {
+            T G[5]; flux_visc(Ul, gl, n, G);
+            for (int v = 0; v < 5; ++v) F[v] = F[v] - G[v] * nv[n];
+          }
+        }
+        for (int v = 0; v < 5; ++v) Ft[(size_t)(5 * r + v) * n3 + tt] = F[v];
+      }
+    }
+    for (int k = 0; k < n1; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+          int tt = node(i, j, k);
+          for (int r = 0; r < 3; ++r) {
+            int a = (r == 0) ? i : (r == 1) ? j : k;
+            for (int l = 0; l < n1; ++l) {
+              int ii = i, jj = j, kk = k;
+              if (r == 0) ii = l; else if (r == 1) jj = l; else kk = l;
+              int tl = node(ii, jj, kk);
+              // weak-form volume term: sum_l (w_l/w_a) D_{l a} Ftilde^r_l
+              double c = B.w[l] / B.w[a] * B.D[l * n1 + a];
+              for (int v = 0; v < 5; ++v) V[(size_t)v * n3 + tt] += c * Ft[(size_t)(5 * r + v) * n3 + tl];
+              if (C.form == 1 && l != a) {
+                // flux differencing: -sum_l DS_{a l} F#(U_tt, U_tl) . avg(Ja^r)
+                T Ua[5], Ub[5]; Uat(tt, Ua); Uat(tl, Ub);
+                double nv[3];
+                for (int c2 = 0; c2 < 3; ++c2)
+                  nv[c2] = 0.5 * (M[(size_t)(3 * r + c2) * n3 + tt] + M[(size_t)(3 * r + c2) * n3 + tl]);
+                T F[5]; flux_twopoint(Ua, Ub, nv, F);
+                double ds = B.DS[a * n1 + l];
+                for (int v = 0; v < 5; ++v) V[(size_t)v * n3 + tt] -= ds * F[v];
+              }
+            }
+          }
+        }
+    // Surface term: -(1/w) l(+-1) Phi_out for each of the six faces.
+    for (int f = 0; f < 6; ++f) {
+      int s = elemSide[e * 6 + f], m = elemSlot[e * 6 + f];
+      const std::vector<double>& L = (f % 2) ? B.Lp : B.Lm;
+      const std::vector<T>& Phi = sflux[s];
+      for (int qq = 0; qq < n1; ++qq)
+        for (int pp = 0; pp < n1; ++pp) {
+          int p = pp, q2 = qq;
+          if (m == 1) orient_inv(sideOrient[s], C.N, pp, qq, p, q2);
+          int fi = q2 * n1 + p;
+          for (int l = 0; l < n1; ++l) {
+            int i, j, k; vol_ijk(f, pp, qq, l, i, j, k);
+            int tt = node(i, j, k);
+            double c = L[l] / B.w[l];
+            for (int v = 0; v < 5; ++v) {
+              T ph = (m == 0) ? Phi[(size_t)v * n2 + fi] : T(-Phi[(size_t)v * n2 + fi]);
+              V[(size_t)v * n3 + tt] -= c * ph;
+            }
+          }
+        }
+    }
+    for (int v = 0; v < 5; ++v)
+      for (int tt = 0; tt < n3; ++tt) Ut[uidx(v, e, tt)] = V[(size_t)v * n3 + tt] / Jdet[e][tt];
+    if (C.mms) {
+      for (int tt = 0; tt < n3; ++tt) {
+        double Q[5];
+        mms_source(Xnode[e][tt], Xnode[e][n3 + tt], Xnode[e][2 * (size_t)n3 + tt], t, Q);
+        for (int v = 0; v < 5; ++v) Ut[uidx(v, e, tt)] += Q[v];
+      }
+    }
+  }
+
+  template <class T> void rhs(const T* U, T* Ut, double t, const std::vector<int>& elist) {
+    Work<T> W;
+    W.tr.assign(nSides, {}); W.gtr.assign(nSides, {}); W.g.assign(nElems, {});
+    std::vector<int> el = elist;
+    if (el.empty()) { el.resize(nElems); for (int e = 0; e < nElems; ++e) el[e] = e; }
+    std::vector<std::vector<T>> sflux(nSides);
+    for (int e : el) {
+      if (C.physics == 1) lift_elem(U, e, W);
+      for (int f = 0; f < 6; ++f) {
+        int s = elemSide[e * 6 + f];
+        if (sflux[s].empty()) side_flux(U, s, W, sflux[s]);
+      }
+    }
+    for (int e : el) residual_elem(U, e, W, sflux, Ut, t);
+  }
+
+  template <class T> void lift_all(const T* U, T* gout) {
+    Work<T> W;
+    W.tr.assign(nSides, {}); W.gtr.assign(nSides, {}); W.g.assign(nElems, {});
+    for (int e = 0; e < nElems; ++e) {
+      lift_elem(U, e, W);
+      for (size_t c = 0; c < 12; ++c)
+        for (int t = 0; t < n3; ++t) gout[(c * nElems + e) * n3 + t] = W.g[e][c * n3 + t];
+    }
+  }
+
+  // LSERK4(5), 2N-storage: dU <- A_s dU + dt R(U, t + c_s dt); U <- U + B_s dU.
+  template <class T> void lserk(T* U, int nsteps, double dt, double t0) {
+    const size_t n = (size_t)5 * nElems * n3;
+    std::vector<T> dU(n, T(0.0)), R(n);
+    std::vector<int> all;
+    double t = t0;
+    for (int step = 0; step < nsteps; ++step) {
+      for (int s = 0; s < 5; ++s) {
+        rhs(U, R.data(), t + lsC[s] * dt, all);
+        for (size_t i = 0; i < n; ++i) {
+          dU[i] = lsA[s] * dU[i] + dt * R[i];
+          U[i] = U[i] + lsB[s] * dU[i];
+        }
+      }
+      t += dt;
+    }
+  }
+
+  // Integral kinetic energy (TGV section) with collocated quadrature:
+  // E_k = sum w_i w_j w_k J |m|^2/rho / (2 rho0 U0^2 |Omega|),  |Omega| = sum w J.
+  template <class T> T kinetic_energy(const T* U, double rho0U0sq) {
+    T acc(0.0);
+    double vol = 0.0;
+    for (int e = 0; e < nElems; ++e) {
+      ensure_geom(e);
+      for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+          for (int i = 0; i < n1; ++i) {
+            int tt = node(i, j, k);
+            double wJ = B.w[i] * B.w[j] * B.w[k] * Jdet[e][tt];
+            T rho = U[uidx(0, e, tt)];
+            T m2 = U[uidx(1, e, tt)] * U[uidx(1, e, tt)] + U[uidx(2, e, tt)] * U[uidx(2, e, tt)] +
+                   U[uidx(3, e, tt)] * U[uidx(3, e, tt)];
+            acc += wJ * (m2 / rho);
+            vol += wJ;
+          }
+    }
+    return acc / (2.0 * rho0U0sq * vol);
+  }
+
+  // Fixed time step (CFL = cfl; viscous restriction with the same number).
+  double timestep(const double* U, double cfl) {
+    double amax = 0.0, vmax = 0.0;
+    for (int e = 0; e < nElems; ++e) {
+      ensure_geom(e);
+      for (int tt = 0; tt < n3; ++tt) {
+        double Ul[5];
+        for (int v = 0; v < 5; ++v) Ul[v] = U[uidx(v, e, tt)];
+        double rho, u[3], p; prim(Ul, rho, u, p);
+        double c = std::sqrt(C.gamma * p / rho);
+        double J = Jdet[e][tt];
+        double sa = 0.0, sv = 0.0;
+        for (int r = 0; r < 3; ++r) {
+          const double* M = &Ja[e][(size_t)(3 * r) * n3 + tt];
+          double a0 = M[0], a1 = M[(size_t)n3], a2 = M[2 * (size_t)n3];
+          double nrm2 = a0 * a0 + a1 * a1 + a2 * a2;
+          sa += std::fabs(a0 * u[0] + a1 * u[1] + a2 * u[2]) + c * std::sqrt(nrm2);
+          sv += nrm2;
+        }
+        amax = std::max(amax, sa / J);
+        vmax = std::max(vmax, C.mu / rho * std::max(4.0 / 3.0, C.gamma / C.Pr) * sv / (J * J));
+      }
+    }
+    double dt = cfl * 2.0 / ((C.N + 1.0) * amax);
+    if (C.physics == 1 && vmax > 0.0) dt = std::min(dt, cfl * 4.0 / ((C.N + 1.0) * (C.N + 1.0) * vmax));
+    return dt;
+  }
+};
+
+}  // namespace orc
+
+using orc::Solver;
+
+// ---------------------------------------------------------------------------
+// C interface used by the test suite (through ctypes).
+// icfg = {N, nodes, form, physics, twopoint, dissipation, mms}
+// dcfg = {gamma, mu, Pr, R, mms_A, mms_a}
+// ---------------------------------------------------------------------------
+extern "C" {
+
+static thread_local std::string g_err;
+
+const char* orc_last_error() { return g_err.c_str(); }
+
+int orc_basis(int N, int type, double* x, double* w, double* D, double* Lm, double* Lp, double* DS) {
+  orc::Basis B;
+  if (!orc::make_basis(N, type, B)) return 1;
+  int n = N + 1;
+  for (int i = 0; i < n; ++i) { x[i] = B.x[i]; w[i] = B.w[i]; Lm[i] = B.Lm[i]; Lp[i] = B.Lp[i]; }
+  for (int i = 0; i < n * n; ++i) { D[i] = B.D[i]; DS[i] = B.DS[i]; }
+  return 0;
+}
+
+void* orc_create(const int* icfg, const double* dcfg, int nElems, int Ngeo, const double* Xgeo, int nSides,
+                 const int* sideElem, const int* sideLoc, const int* sideOrient) {
+  Solver* S = new Solver();
+  S->C.N = icfg[0]; S->C.nodes = icfg[1]; S->C.form = icfg[2]; S->C.physics = icfg[3];
+  S->C.twopoint = icfg[4]; S->C.dissipation = icfg[5]; S->C.mms = icfg[6];
+  S->C.gamma = dcfg[0]; S->C.mu = dcfg[1]; S->C.Pr = dcfg[2]; S->C.R = dcfg[3];
+  S->C.mms_A = dcfg[4]; S->C.mms_a = dcfg[5];
+  S->nElems = nElems; S->Ngeo = Ngeo; S->nSides = nSides;
+  if (nElems <= 0 || Ngeo < 1 || nSides * 2 != nElems * 6) { g_err = "bad sizes"; delete S; return nullptr; }
+  S->Xgeo.assign(Xgeo, Xgeo + (size_t)3 * nElems * (Ngeo + 1) * (Ngeo + 1) * (Ngeo + 1));
+  S->sideElem.assign(sideElem, sideElem + 2 * (size_t)nSides);
+  S->sideLoc.assign(sideLoc, sideLoc + 2 * (size_t)nSides);
+  S->sideOrient.assign(sideOrient, sideOrient + nSides);
+  if (!S->setup()) { g_err = S->err; delete S; return nullptr; }
+  return S;
+}
+
+int orc_check_jacobians(void* h) {
+  Solver* S = (Solver*)h;
+  if (!S->check_jacobians()) { g_err = S->err; return 1; }
+  return 0;
+}
+
+void orc_destroy(void* h) { delete (Solver*)h; }
+
+void orc_lserk_coeffs(double* A, double* B, double* C) { orc::lserk_coeffs(A, B, C); }
+
+// Node coordinates [3][nElems][n3], Jacobian [nElems][n3], metrics [9][nElems][n3].
+void orc_geometry(void* h, double* xyz, double* J, double* Ja) {
+  Solver* S = (Solver*)h;
+  for (int e = 0; e < S->nElems; ++e) {
+    S->ensure_geom(e);
+    for (int t = 0; t < S->n3; ++t) {
+      if (xyz) for (int d = 0; d < 3; ++d) xyz[((size_t)d * S->nElems + e) * S->n3 + t] = S->Xnode[e][(size_t)d * S->n3 + t];
+      if (J) J[(size_t)e * S->n3 + t] = S->Jdet[e][t];
+      if (Ja) for (int c = 0; c < 9; ++c) Ja[((size_t)c * S->nElems + e) * S->n3 + t] = S->Ja[e][(size_t)c * S->n3 + t];
+    }
+  }
+}
+
+// Master-outward scaled normals n*s at face nodes: [3][nSides][n2].
+void orc_face_normals(void* h, double* nv) {
+  Solver* S = (Solver*)h;
+  for (int s = 0; s < S->nSides; ++s) {
+    S->ensure_side(s);
+    for (int c = 0; c < 3; ++c)
+      for (int t = 0; t < S->n2; ++t) nv[((size_t)c * S->nSides + s) * S->n2 + t] = S->nvec[s][(size_t)c * S->n2 + t];
+  }
+}
+
+int orc_rhs(void* h, const double* U, double* Ut, double t) {
+  Solver* S = (Solver*)h;
+  std::vector<int> all;
+  S->rhs<double>(U, Ut, t, all);
+  return 0;
+}
+
+// Residual of a list of elements only; Ut is the full-size array, only the
+// listed elements are written.
+int orc_rhs_elems(void* h, const double* U, double* Ut, double t, int nlist, const int* list) {
+  Solver* S = (Solver*)h;
+  std::vector<int> el(list, list + nlist);
+  for (int e : el)
+    if (e < 0 || e >= S->nElems) { g_err = "element out of range"; return 1; }
+  if (el.empty()) return 0;
+  S->rhs<double>(U, Ut, t, el);
+  return 0;
+}
+
+// Lifted gradients [12][nElems][n3], component 3*a+d = d q_a / d x_d, q=(u,v,w,T).
+int orc_lift(void* h, const double* U, double* g) {
+  Solver* S = (Solver*)h;
+  S->lift_all<double>(U, g);
+  return 0;
+}
+
+// Tangent of the residual: dUt = (dR/dU) dU.
+int orc_rhs_jvp(void* h, const double* U, const double* dU, double* Ut, double* dUt, double t) {
+  Solver* S = (Solver*)h;
+  size_t n = (size_t)5 * S->nElems * S->n3;
+  std::vector<orc::Dual> X(n), Y(n);
+  for (size_t i = 0; i < n; ++i) X[i] = orc::Dual(U[i], dU[i]);
+  std::vector<int> all;
+  S->rhs<orc::Dual>(X.data(), Y.data(), t, all);
+  for (size_t i = 0; i < n; ++i) { if (Ut) Ut[i] = Y[i].v; dUt[i] = Y[i].d; }
+  return 0;
+}
+
+int orc_lserk(void* h, double* U, int nsteps, double dt, double t0) {
+  Solver* S = (Solver*)h;
+  S->lserk<double>(U, nsteps, dt, t0);
+  return 0;
+}
+
+// Tangent of a whole trajectory: U <- U(T), dU <- (dU(T)/dU(0)) dU.
+int orc_lserk_jvp(void* h, double* U, double* dU, int nsteps, double dt, double t0) {
+  Solver* S = (Solver*)h;
+  size_t n = (size_t)5 * S->nElems * S->n3;
+  std::vector<orc::Dual> X(n);
+  for (size_t i = 0; i < n; ++i) X[i] = orc::Dual(U[i], dU[i]);
+  S->lserk<orc::Dual>(X.data(), nsteps, dt, t0);
+  for (size_t i = 0; i < n; ++i) { U[i] = X[i].v; dU[i] = X[i].d; }
+  return 0;
+}
+
+double orc_kinetic_energy(void* h, const double* U, double rho0U0sq) {
+  Solver* S = (Solver*)h;
+  return S->kinetic_energy<double>(U, rho0U0sq);
+}
+
+// Directional derivative of E_k: returns dE_k/dU . dU.
+double orc_kinetic_energy_jvp(void* h, const double* U, const double* dU, double rho0U0sq) {
+  Solver* S = (Solver*)h;
+  size_t n = (size_t)5 * S->nElems * S->n3;
+  std::vector<orc::Dual> X(n);
+  for (size_t i = 0; i < n; ++i) X[i] = orc::Dual(U[i], dU[i]);
+  return S->kinetic_energy<orc::Dual>(X.data(), rho0U0sq).d;
+}
+
+double orc_timestep(void* h, const double* U, double cfl) {
+  Solver* S = (Solver*)h;
+  return S->timestep(U, cfl);
+}
+
+// Operation counts of one residual evaluation: {add/sub, mul, div, sqrt, log}.
+int orc_rhs_opcount(void* h, const double* U, uint64_t* counts) {
+  Solver* S = (Solver*)h;
+  size_t n = (size_t)5 * S->nElems * S->n3;
+  std::vector<orc::Cnt> X(n), Y(n);
+  for (size_t i = 0; i < n; ++i) X[i] = orc::Cnt(U[i]);
+  for (int e = 0; e < S->nElems; ++e) S->ensure_geom(e);
+  for (int s = 0; s < S->nSides; ++s) S->ensure_side(s);
+  orc::Cnt::n_add = orc::Cnt::n_mul = orc::Cnt::n_div = orc::Cnt::n_sqrt = orc::Cnt::n_log = 0;
+  std::vector<int> all;
+  S->rhs<orc::Cnt>(X.data(), Y.data(), 0.0, all);
+  counts[0] = orc::Cnt::n_add; counts[1] = orc::Cnt::n_mul; counts[2] = orc::Cnt::n_div;
+  counts[3] = orc::Cnt::n_sqrt; counts[4] = orc::Cnt::n_log;
+  return 0;
+}
+
+// Point functions for unit pins.
+void orc_flux_twopoint(const int* icfg, const double* dcfg, const double* Ua, const double* Ub, const double* nv,
+                       double* F) {
+  Solver S;
+  S.C.twopoint = icfg[4]; S.C.gamma = dcfg[0];
+  S.flux_twopoint<double>(Ua, Ub, nv, F);
+}
+void orc_flux_adv(const double* dcfg, const double* U, const double* nv, double* F) {
+  Solver S; S.C.gamma = dcfg[0];
+  S.flux_adv<double>(U, nv, F);
+}
+void orc_flux_visc(const double* dcfg, const double* U, const double* g, int n, double* G) {
+  Solver S; S.C.gamma = dcfg[0]; S.C.mu = dcfg[1]; S.C.Pr = dcfg[2]; S.C.R = dcfg[3];
+  S.flux_visc<double>(U, g, n, G);
+}
+double orc_logmean(double x, double y) {
+  Solver S;
+  return S.logmean<double>(x, y);
+}
+void orc_mms_source(const double* dcfg, double x, double y, double z, double t, double* Q) {
+  Solver S; S.C.gamma = dcfg[0]; S.C.mu = dcfg[1]; S.C.Pr = dcfg[2]; S.C.R = dcfg[3];
+  S.C.mms_A = dcfg[4]; S.C.mms_a = dcfg[5];
+  S.mms_source(x, y, z, t, Q);
+}
+
+}  // extern "C"

@@ -1,0 +1,248 @@
+"""ctypes wrapper around the serial FP64 oracle (dg_oracle.cpp).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg.  The product path never imports this module.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "dg_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (portable x86-64, no FMA contraction)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-Wall",
+               "-o", tmp, SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        L.orc_last_error.restype = ctypes.c_char_p
+        L.orc_create.restype = ctypes.c_void_p
+        L.orc_create.argtypes = [_ip, _dp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _ip, _ip, _ip]
+        for name in ("orc_destroy",):
+            getattr(L, name).argtypes = [ctypes.c_void_p]
+        L.orc_check_jacobians.argtypes = [ctypes.c_void_p]
+        L.orc_geometry.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.orc_face_normals.argtypes = [ctypes.c_void_p, _dp]
+        L.orc_rhs.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double]
+        L.orc_rhs_elems.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip]
+        L.orc_lift.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_rhs_jvp.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.c_double]
+        L.orc_lserk.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_lserk_jvp.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_kinetic_energy.restype = ctypes.c_double
+        L.orc_kinetic_energy.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
+        L.orc_kinetic_energy_jvp.restype = ctypes.c_double
+        L.orc_kinetic_energy_jvp.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double]
+        L.orc_timestep.restype = ctypes.c_double
+        L.orc_timestep.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
+        L.orc_rhs_opcount.argtypes = [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_uint64)]
+        L.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_lserk_coeffs.argtypes = [_dp, _dp, _dp]
+        L.orc_flux_twopoint.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
+        L.orc_flux_adv.argtypes = [_dp, _dp, _dp, _dp]
+        L.orc_flux_visc.argtypes = [_dp, _dp, _dp, ctypes.c_int, _dp]
+        L.orc_logmean.restype = ctypes.c_double
+        L.orc_logmean.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_mms_source.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    assert a.dtype == np.int32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_ip)
+
+
+def basis(N, nodes):
+    n = N + 1
+    x, w, Lm, Lp = (np.zeros(n) for _ in range(4))
+    D, DS = np.zeros((n, n)), np.zeros((n, n))
+    rc = lib().orc_basis(N, nodes, _d(x), _d(w), _d(D), _d(Lm), _d(Lp), _d(DS))
+    if rc:
+        raise ValueError("bad basis request")
+    return dict(x=x, w=w, D=D, Lm=Lm, Lp=Lp, DS=DS)
+
+
+def lserk_coeffs():
+    A, B, C = np.zeros(5), np.zeros(5), np.zeros(5)
+    lib().orc_lserk_coeffs(_d(A), _d(B), _d(C))
+    return A, B, C
+
+
+def _cfg_arrays(cfg):
+    icfg = np.array([cfg.get("N", 3), cfg.get("nodes", 0), cfg.get("form", 0), cfg.get("physics", 0),
+                     cfg.get("twopoint", 0), cfg.get("dissipation", 1), cfg.get("mms", 0)], dtype=np.int32)
+    dcfg = np.array([cfg.get("gamma", 1.4), cfg.get("mu", 0.0), cfg.get("Pr", 0.72), cfg.get("R", 1.0),
+                     cfg.get("mms_A", 0.1), cfg.get("mms_a", 1.0)], dtype=np.float64)
+    return icfg, dcfg
+
+
+def flux_twopoint(Ua, Ub, nv, gamma=1.4, central=False):
+    icfg, dcfg = _cfg_arrays(dict(twopoint=1 if central else 0, gamma=gamma))
+    F = np.zeros(5)
+    lib().orc_flux_twopoint(_i(icfg), _d(dcfg), _d(np.ascontiguousarray(Ua, dtype=np.float64)),
+                            _d(np.ascontiguousarray(Ub, dtype=np.float64)),
+                            _d(np.ascontiguousarray(nv, dtype=np.float64)), _d(F))
+    return F
+
+
+def flux_adv(U, nv, gamma=1.4):
+    _, dcfg = _cfg_arrays(dict(gamma=gamma))
+    F = np.zeros(5)
+    lib().orc_flux_adv(_d(dcfg), _d(np.ascontiguousarray(U, dtype=np.float64)),
+                       _d(np.ascontiguousarray(nv, dtype=np.float64)), _d(F))
+    return F
+
+
+def flux_visc(U, g, n, gamma=1.4, mu=1e-2, Pr=0.72, R=1.0):
+    _, dcfg = _cfg_arrays(dict(gamma=gamma, mu=mu, Pr=Pr, R=R))
+    G = np.zeros(5)
+    lib().orc_flux_visc(_d(dcfg), _d(np.ascontiguousarray(U, dtype=np.float64)),
+                        _d(np.ascontiguousarray(g, dtype=np.float64)), int(n), _d(G))
+    return G
+
+
+def logmean(x, y):
+    return lib().orc_logmean(float(x), float(y))
+
+
+def mms_source(x, y, z, t, gamma=1.4, mu=1e-3, Pr=0.72, R=1.0, A=0.1, a=1.0):
+    _, dcfg = _cfg_arrays(dict(gamma=gamma, mu=mu, Pr=Pr, R=R, mms_A=A, mms_a=a))
+    Q = np.zeros(5)
+    lib().orc_mms_source(_d(dcfg), float(x), float(y), float(z), float(t), _d(Q))
+    return Q
+
+
+class Oracle:
+    """One discretisation (config + mesh) in the oracle."""
+
+    def __init__(self, cfg: dict, mesh):
+        self.cfg = dict(cfg)
+        self.mesh = mesh
+        self.N = int(cfg["N"])
+        self.n1 = self.N + 1
+        self.nElems = mesh.nElems
+        self.nSides = mesh.nSides
+        icfg, dcfg = _cfg_arrays(cfg)
+        X = np.ascontiguousarray(mesh.X, dtype=np.float64)
+        self._keep = (X, mesh.sideElem, mesh.sideLoc, mesh.sideOrient)
+        h = lib().orc_create(_i(icfg), _d(dcfg), mesh.nElems, mesh.Ngeo, _d(X), mesh.nSides,
+                             _i(mesh.sideElem), _i(mesh.sideLoc), _i(mesh.sideOrient))
+        if not h:
+            raise ValueError("oracle: " + lib().orc_last_error().decode())
+        self.h = ctypes.c_void_p(h)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_destroy(h)
+            self.h = None
+
+    @property
+    def state_shape(self):
+        return (5, self.nElems, self.n1, self.n1, self.n1)
+
+    def check_jacobians(self):
+        if lib().orc_check_jacobians(self.h):
+            raise ValueError(lib().orc_last_error().decode())
+
+    def geometry(self):
+        n = self.n1
+        xyz = np.zeros((3, self.nElems, n, n, n))
+        J = np.zeros((self.nElems, n, n, n))
+        Ja = np.zeros((9, self.nElems, n, n, n))
+        lib().orc_geometry(self.h, _d(xyz), _d(J), _d(Ja))
+        return xyz, J, Ja
+
+    def coords(self):
+        return self.geometry()[0]
+
+    def face_normals(self):
+        nv = np.zeros((3, self.nSides, self.n1, self.n1))
+        lib().orc_face_normals(self.h, _d(nv))
+        return nv
+
+    def rhs(self, U, t=0.0):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        Ut = np.zeros_like(U)
+        lib().orc_rhs(self.h, _d(U), _d(Ut), float(t))
+        return Ut
+
+    def rhs_elems(self, U, elems, t=0.0):
+        """Residual of the listed elements only: array [5][len(elems)][n][n][n]."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        el = np.ascontiguousarray(np.asarray(elems, dtype=np.int32))
+        Ut = np.zeros_like(U)
+        if lib().orc_rhs_elems(self.h, _d(U), _d(Ut), float(t), int(el.size), _i(el)):
+            raise ValueError(lib().orc_last_error().decode())
+        return Ut[:, el]
+
+    def lift(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        n = self.n1
+        g = np.zeros((12, self.nElems, n, n, n))
+        lib().orc_lift(self.h, _d(U), _d(g))
+        return g
+
+    def rhs_jvp(self, U, dU, t=0.0):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        dU = np.ascontiguousarray(dU, dtype=np.float64).reshape(U.shape)
+        Ut, dUt = np.zeros_like(U), np.zeros_like(U)
+        lib().orc_rhs_jvp(self.h, _d(U), _d(dU), _d(Ut), _d(dUt), float(t))
+        return Ut, dUt
+
+    def lserk(self, U, nsteps, dt, t0=0.0):
+        U = np.array(U, dtype=np.float64, copy=True, order="C")
+        lib().orc_lserk(self.h, _d(U), int(nsteps), float(dt), float(t0))
+        return U
+
+    def lserk_jvp(self, U, dU, nsteps, dt, t0=0.0):
+        U = np.array(U, dtype=np.float64, copy=True, order="C")
+        dU = np.array(dU, dtype=np.float64, copy=True, order="C").reshape(U.shape)
+        lib().orc_lserk_jvp(self.h, _d(U), _d(dU), int(nsteps), float(dt), float(t0))
+        return U, dU
+
+    def kinetic_energy(self, U, rho0U0sq=1.0):
+        return lib().orc_kinetic_energy(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), float(rho0U0sq))
+
+    def kinetic_energy_jvp(self, U, dU, rho0U0sq=1.0):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        dU = np.ascontiguousarray(dU, dtype=np.float64).reshape(U.shape)
+        return lib().orc_kinetic_energy_jvp(self.h, _d(U), _d(dU), float(rho0U0sq))
+
+    def timestep(self, U, cfl=0.9):
+        return lib().orc_timestep(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), float(cfl))
+
+    def opcount(self, U):
+        c = (ctypes.c_uint64 * 5)()
+        lib().orc_rhs_opcount(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), c)
+        return dict(add=c[0], mul=c[1], div=c[2], sqrt=c[3], log=c[4])
