@@ -1,0 +1,189 @@
+"""Benchmark of the DGSEM residual hot path on one MI355X.
+
+A step is one LSERK4(5) time step (five evaluations of the whole residual:
+BR1 lifting, surface fluxes, split-form volume integral, surface lift,
+Jacobian scaling, RK update) of the Navier-Stokes Taylor-Green vortex
+workload: N=7 on Lobatto nodes, 16^3 periodic hexahedra on [-pi,pi]^3,
+Ma 0.1, Re 1600, Pr 0.72, FP64.  The metric is the paper's PID
+(wall time / (RK stages * DOF), one GPU), lower is better.
+
+Printed as one JSON line.  Besides the contract fields it carries the
+FP32-flux PID on the same workload, the dominant kernel's roofline figures
+(HIP events around every launch of the timed region) and the serial FP64
+oracle timed on a bounded sample of the same workload on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "ns_split_lgl_n7_16x16x16_tgv"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-sample-elems", type=int, default=2048)
+    return ap.parse_args()
+
+
+def workload_cfg(name):
+    from paper_2605_28627_amd import inputs as I
+    w = I.WORKLOADS[name]
+    return w, dict(N=w["N"], nodes=w["nodes"], form=w["form"], physics=w["physics"], mu=w["mu"], Pr=0.72,
+                   gamma=1.4, R=1.0)
+
+
+def volume_kernel_bytes_per_dof(w):
+    """Compulsory HBM bytes of one launch of the residual/RK kernel, per node.
+
+    Reads: U (5), metrics Ja (9) and 1/J (1), dU (5), and per face node of
+    each of the element's 6 faces both sides' traces (2 x 5) and the face
+    normal + area (4); Navier-Stokes adds the lifted gradients (12) and both
+    sides' gradient traces (2 x 12).  Writes: dU (5), U (5) and the element's
+    own traces of the new state (5 per face node).  8 bytes each.
+    """
+    n1 = w["N"] + 1
+    fpn = 6 * n1 * n1 / n1 ** 3          # face nodes of one element per volume node
+    reads = 5 + 9 + 1 + 5 + fpn * (10 + 4)
+    writes = 5 + 5 + fpn * 5
+    if w["physics"] == 1:
+        reads += 12 + fpn * 24
+    return 8.0 * (reads + writes)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this "
+                                   "build (the path shards by elements, see DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2605_28627_amd import dgx
+    from paper_2605_28627_amd import inputs as I
+    from paper_2605_28627_amd.solver import DGSolver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w, cfg = workload_cfg(args.workload)
+    mesh = I.workload_mesh(args.workload)
+    s = DGSolver(cfg, mesh, dev)
+    dof = s.nElems * s.npe
+    xyz = s.coords()
+    U0 = s.to_device(I.workload_state(args.workload, xyz))
+    dt = s.timestep(U0, 0.9)
+
+    def timed(solver, steps, warmup, profile):
+        U = U0.clone()
+        dU = torch.zeros_like(U)
+        if warmup:
+            solver.rk_step(U, dU, dt, warmup)
+        torch.cuda.synchronize()
+        if profile:
+            dgx.dg_profile(solver.ctx, 1)
+        t0 = time.perf_counter()
+        solver.rk_step(U, dU, dt, steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        prof = {}
+        if profile:
+            for fam in ("trace", "lift", "volume", "other"):
+                prof[fam] = dgx.dg_profile_query(solver.ctx, fam)
+            dgx.dg_profile(solver.ctx, 0)
+        if solver.check_state(U) != 0:
+            raise RuntimeError("non-physical state after the timed steps")
+        return t, prof
+
+    t64, prof = timed(s, args.steps, args.warmup, profile=True)
+    pid64 = t64 / (5 * args.steps * dof)
+    vol_ms, vol_n = prof["volume"]
+    vol_avg_s = vol_ms * 1e-3 / max(vol_n, 1)
+    lift_ms, lift_n = prof["lift"]
+    bytes_launch = volume_kernel_bytes_per_dof(w) * dof
+    achieved_gbs = bytes_launch / vol_avg_s / 1e9
+
+    result = {
+        "metric": "PID (s per DOF per RK stage) FP64 vs FP32-mixed; adjoint/forward cost",
+        "value": pid64,
+        "unit": "s/(DOF*stage)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t64 / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (Taylor-Green vortex initial condition evaluated at the mesh nodes)",
+        "config": {"workload": args.workload, "N": w["N"], "nodes": "LGL", "elements": list(w["K"]),
+                   "dof": dof, "physics": "navier-stokes" if w["physics"] else "euler",
+                   "volume_form": "split" if w["form"] else "weak", "dt": dt},
+        "dof_updates_per_s": 1.0 / pid64,
+        "kernels_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in prof.items()},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_volume (split form, Navier-Stokes, RK stage)",
+            "achieved": achieved_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved_gbs / HBM_PEAK_GBS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": bytes_launch,
+            "avg_launch_ms": vol_avg_s * 1e3,
+            "launches": vol_n,
+        },
+    }
+    if lift_n:
+        result["kernels_ms_per_launch"]["lift"] = lift_ms / lift_n
+    if not args.no_fp32:
+        cfg32 = dict(cfg, precision=1)
+        s32 = DGSolver(cfg32, mesh, dev)
+        t32, _ = timed(s32, args.steps, args.warmup, profile=False)
+        result["pid_fp32_flux"] = t32 / (5 * args.steps * dof)
+        result["fp32_speedup"] = t64 / t32
+        s32.close()
+    result["adjoint_forward_cost"] = None
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(args, cfg, mesh, xyz, pid64)
+    print(json.dumps(result), flush=True)
+    s.close()
+
+
+def cpu_baseline(args, cfg, mesh, xyz, pid_gpu):
+    """The serial FP64 oracle on the host: residual of a contiguous block of
+    elements of the same workload (one RK stage's worth of work per node)."""
+    from oracle import oracle as O
+    from paper_2605_28627_amd import inputs as I
+    o = O.Oracle(cfg, mesh)
+    U = I.workload_state(args.workload, xyz)
+    nel = min(args.cpu_sample_elems, mesh.nElems)
+    el = list(range(nel))
+    t0 = time.perf_counter()
+    o.rhs_elems(U, el)
+    t = time.perf_counter() - t0
+    npe = (cfg["N"] + 1) ** 3
+    pid = t / (nel * npe)
+    return {"value": pid, "unit": "s/(DOF*stage)", "cores": 1, "kind": "oracle",
+            "sample": f"one residual evaluation of elements 0..{nel - 1} of the {mesh.nElems}-element workload "
+                      f"({nel * npe} DOF, serial, includes the lifting of their neighbours), {t:.1f} s",
+            "gpu_over_cpu_per_rank": pid / pid_gpu}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/* dgx.h -- C-ABI of the MI355X (gfx950) DGSEM residual library.
+ *
+ * The library evaluates the semi-discrete residual dU/dt of the collocated
+ * discontinuous Galerkin spectral element method on hexahedral meshes and
+ * advances it with the low-storage RK4(5) scheme (paper: "Governing
+ * Equations and Numerical Method"; weak form eq. dgsem_weak, BR1 lifting
+ * eq. dgsem_lifted, entropy-stable split form with the Chandrashekar flux,
+ * RK4-5 of Carpenter and Kennedy).  The host-side ownership model follows
+ * the paper's porting strategy (device memory is owned by the library and
+ * held by the caller through an opaque handle; "Porting Strategy", memory
+ * management listing); the kernels themselves are this library's own.
+ *
+ * Conventions
+ *   - Every function returns a dg_status; nothing throws across the ABI.
+ *     On failure dg_last_error(ctx) holds a message (per context; for a
+ *     failing dg_create it is the thread's last message, ctx = NULL).
+ *   - State arrays are float64, C-contiguous, U[v][e][k][j][i] with
+ *     v in (rho, rho u, rho v, rho w, rho e) and i fastest; length
+ *     5 * nElems * (N+1)^3.  State, residual, RK register and adjoint
+ *     buffers are caller-owned DEVICE memory.
+ *   - Mesh input is host memory.  Geometry nodes are equispaced,
+ *     X[d][e][c][b][a] on -1 + 2a/Ngeo, a fastest.  Side s joins the master
+ *     (side_elem[2s], side_loc[2s]) and the slave (side_elem[2s+1],
+ *     side_loc[2s+1]).  Local face f: f/2 is the reference direction of the
+ *     normal, f%2 == 1 the +1 end.  Face-local indices (p,q) are the two
+ *     tangential volume indices in increasing direction order.
+ *     side_orient[s] maps master (p,q) to slave (p',q'): swap if bit 2,
+ *     then reverse the first index if bit 0 and the second if bit 1.
+ *   - Streams are hipStream_t passed as void* (NULL = default stream).  All
+ *     device work of a call is enqueued on that stream; calls return
+ *     without synchronising unless stated.  A context is not thread-safe;
+ *     use one context per stream.
+ *   - Scratch memory is a caller-bound workspace (dg_workspace_bytes /
+ *     dg_bind_workspace); calls that need it fail with DG_ERR_STATE when
+ *     none is bound.  Calls that share a context share its workspace, so
+ *     they must not overlap in time on different streams.
+ */
+#ifndef DGX_H
+#define DGX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_ctx dg_ctx;
+
+typedef enum {
+  DG_OK = 0,
+  DG_ERR_ARG = 1,          /* invalid argument (null pointer, size, enum)      */
+  DG_ERR_MESH = 2,         /* invalid mesh: connectivity, non-positive Jacobian */
+  DG_ERR_HIP = 3,          /* a HIP runtime call failed; message has the text  */
+  DG_ERR_NONPHYSICAL = 4,  /* rho <= 0, p <= 0 or a non-finite value           */
+  DG_ERR_NOMEM = 5,        /* device allocation failed                          */
+  DG_ERR_UNSUPPORTED = 6,  /* valid but not built (e.g. N outside 1..7)         */
+  DG_ERR_STATE = 7         /* call order: no mesh uploaded / no workspace       */
+} dg_status;
+
+enum { DG_NODES_GAUSS = 0, DG_NODES_LOBATTO = 1 };
+enum { DG_FORM_WEAK = 0, DG_FORM_SPLIT = 1 };
+enum { DG_PHYS_EULER = 0, DG_PHYS_NAVIER_STOKES = 1 };
+enum { DG_RIEMANN_RUSANOV = 0, DG_RIEMANN_CENTRAL = 1 };
+enum { DG_TWOPOINT_CHANDRASHEKAR = 0, DG_TWOPOINT_CENTRAL = 1 };
+enum { DG_PREC_FP64 = 0, DG_PREC_FP32_FLUX = 1 };
+
+typedef struct {
+  int N;            /* polynomial degree, 1..7                                       */
+  int nodes;        /* DG_NODES_*; the split form requires Lobatto nodes             */
+  int volume_form;  /* DG_FORM_*                                                     */
+  int physics;      /* DG_PHYS_*                                                     */
+  int riemann;      /* DG_RIEMANN_*: Rusanov, or its central part alone (tests)       */
+  int twopoint;     /* DG_TWOPOINT_*: Chandrashekar, or the flux average (tests)      */
+  int precision;    /* DG_PREC_*: FP64, or FP32 flux arithmetic with FP64 state,
+                       metrics, pressure recovery, metric contraction and update     */
+  double gamma;     /* ratio of specific heats                                        */
+  double mu;        /* constant dynamic viscosity (Navier-Stokes)                     */
+  double Pr;        /* Prandtl number                                                 */
+  double R;         /* specific gas constant                                          */
+} dg_config;
+
+/* Context ------------------------------------------------------------------ */
+
+/* Validates cfg and creates a context (host memory only; no device work).
+ * DG_ERR_ARG for bad enums or gamma <= 1, mu < 0, Pr <= 0, R <= 0;
+ * DG_ERR_UNSUPPORTED for N outside the built range or split form on Gauss nodes. */
+dg_status dg_create(const dg_config* cfg, dg_ctx** out);
+
+/* Frees all library-owned host and device memory of ctx (NULL is a no-op). */
+dg_status dg_destroy(dg_ctx* ctx);
+
+/* Message of the last failing call on ctx, or of the calling thread when ctx is NULL. */
+const char* dg_last_error(const dg_ctx* ctx);
+
+/* The five-stage coefficients A, B, c of LSERK4(5) (Carpenter and Kennedy 1994). */
+dg_status dg_lserk_coefficients(double* A5, double* B5, double* c5);
+
+/* Mesh and metrics ------------------------------------------------------------ */
+
+/* Host part of the mesh set-up: validates connectivity, builds the per-element
+ * face table, interpolates the geometry to the solution nodes and computes the
+ * metric terms in conservative curl form (paper: mapping chi, Jacobian J,
+ * contravariant fluxes; Kopriva 2006 curl form), the Jacobian and the master
+ * face normals.  No device work.  DG_ERR_MESH on bad connectivity or a
+ * non-positive Jacobian at any node. */
+dg_status dg_set_mesh(dg_ctx* ctx, int nElems, int Ngeo, const double* X, int nSides,
+                      const int* side_elem, const int* side_loc, const int* side_orient);
+
+/* dg_set_mesh followed by the upload of metrics and connectivity to
+ * library-owned device memory on the current device. */
+dg_status dg_upload_mesh(dg_ctx* ctx, int nElems, int Ngeo, const double* X, int nSides,
+                         const int* side_elem, const int* side_loc, const int* side_orient);
+
+/* Optional override of the metric terms after dg_upload_mesh (host arrays):
+ * Ja[9][nElems][n3] (component 3r+n = Ja^r_n), sJ[nElems][n3] = 1/J,
+ * nvec[3][nSides][n2] = master-outward n*s at face nodes in master (p,q) order. */
+dg_status dg_upload_metrics(dg_ctx* ctx, const double* Ja, const double* sJ, const double* nvec);
+
+/* Host copies of the metrics computed by dg_set_mesh (any pointer may be NULL):
+ * xyz[3][nElems][n3], Ja[9][nElems][n3], sJ[nElems][n3], nvec[3][nSides][n2]. */
+dg_status dg_get_metrics(const dg_ctx* ctx, double* xyz, double* Ja, double* sJ, double* nvec);
+
+/* Node coordinates xyz[3][nElems][n3] (host) for building initial states. */
+dg_status dg_node_coords(const dg_ctx* ctx, double* xyz_host);
+
+/* Sizes: number of elements, sides, nodes per element, state length. */
+dg_status dg_sizes(const dg_ctx* ctx, int* nElems, int* nSides, int* nodes_per_elem, size_t* state_len);
+
+/* Workspace ------------------------------------------------------------------- */
+
+/* Bytes of device scratch the context needs (face traces, lifted gradients,
+ * RK stage states of the adjoint, reduction partials).  Valid after a mesh is set. */
+size_t dg_workspace_bytes(const dg_ctx* ctx);
+
+/* Binds caller-owned device memory of at least dg_workspace_bytes bytes,
+ * 256-byte aligned.  The library never frees it. */
+dg_status dg_bind_workspace(dg_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Residual and time stepping -------------------------------------------------- */
+
+/* Ut = dU/dt(U): prolongation to faces, Riemann and viscous surface fluxes,
+ * BR1 lifting (Navier-Stokes), weak or split volume integral, surface lift,
+ * Jacobian scaling (paper eq. dgsem_weak / dgsem_lifted).  U and Ut are device
+ * arrays of the state length; they must not alias.  t is unused (autonomous). */
+dg_status dg_rhs(dg_ctx* ctx, const double* U, double* Ut, double t, void* stream);
+
+/* Lifted gradients g[12][nElems][n3] (device), component 3a+d = d q_a / d x_d
+ * with q = (u, v, w, T) (paper eq. dgsem_lifted).  Navier-Stokes contexts only. */
+dg_status dg_lift(dg_ctx* ctx, const double* U, double* g, void* stream);
+
+/* nsteps steps of LSERK4(5) with fixed dt, in place: per stage
+ * dU <- A_s dU + dt R(U); U <- U + B_s dU.  dU is the 2N-storage register
+ * (device, state length); it is zeroed by the call before the first stage. */
+dg_status dg_rk_step(dg_ctx* ctx, double* U, double* dU, double t, double dt, int nsteps, void* stream);
+
+/* Adjoint --------------------------------------------------------------------- */
+
+/* out = (dR/dU)^T lam at the state U (device arrays, state length).  This is
+ * the exact transpose of the discrete residual's Jacobian; at the kinks of
+ * the Rusanov flux (|u.n|, max of the two wave speeds) the branch taken by
+ * the forward evaluation is differentiated, ties going to the master side. */
+dg_status dg_adjoint_rhs(dg_ctx* ctx, const double* U, const double* lam, double* out, void* stream);
+
+/* Reverse of one LSERK4(5) step from state Un (device): on entry lamU holds
+ * dJ/dU^{n+1}; on exit dJ/dU^n.  Stage states are recomputed from Un into the
+ * workspace.  lamdU is a device register of the state length (scratch). */
+dg_status dg_adjoint_rk_step(dg_ctx* ctx, const double* Un, double* lamU, double* lamdU, double t, double dt,
+                             void* stream);
+
+/* Functionals and checks ------------------------------------------------------ */
+
+/* Integral kinetic energy E_k = sum_e sum w_i w_j w_k J |m|^2/rho / (2 rho0U0sq |Omega|),
+ * |Omega| = sum w J (paper, TGV section).  Writes one double to out_dev. */
+dg_status dg_kinetic_energy(dg_ctx* ctx, const double* U, double rho0U0sq, double* out_dev, void* stream);
+
+/* grad = scale * dE_k/dU (device, state length). */
+dg_status dg_kinetic_energy_grad(dg_ctx* ctx, const double* U, double rho0U0sq, double scale, double* grad,
+                                 void* stream);
+
+/* Fixed time step from the state (paper: CFL = 0.9 for the advective and the
+ * viscous restriction; the formula is this library's reading):
+ *   dt_a = cfl min(2/(N+1), 8/(N+1)^2) / max sum_r (|Ja^r.u| + c|Ja^r|)/J
+ *   dt_v = cfl 32/(N+1)^4 / max (mu/rho) max(4/3, gamma/Pr) sum_r |Ja^r|^2/J^2
+ * dt = min(dt_a, dt_v) (dt_v for Navier-Stokes only).  Synchronises the
+ * stream and writes the host double dt_out. */
+dg_status dg_timestep(dg_ctx* ctx, const double* U, double cfl, double* dt_out, void* stream);
+
+/* DG_ERR_NONPHYSICAL if any node has rho <= 0, p <= 0 or a non-finite
+ * conserved value; synchronises the stream. */
+dg_status dg_check_state(dg_ctx* ctx, const double* U, void* stream);
+
+/* Profiling ------------------------------------------------------------------- */
+
+/* Per-kernel device timing (the analogue of the paper's per-kernel device
+ * events, "Intra-GPU Parallelism"): while enabled, every launch of the
+ * context is bracketed by two hipEvents on its stream.  Enabling resets
+ * the accumulated times.  dg_profile_query synchronises the device, then
+ * returns the summed milliseconds and launch count of the kernel family
+ * named by `kernel` ("trace", "lift", "volume", "adjoint", "other").
+ * Unknown names give DG_ERR_ARG. */
+dg_status dg_profile(dg_ctx* ctx, int enable);
+dg_status dg_profile_query(dg_ctx* ctx, const char* kernel, double* total_ms, long* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGX_H */

@@ -1,0 +1,75 @@
+// dgx_inst.hip -- launchers of the residual kernels for one polynomial degree.
+// Compiled once per degree with -DDGX_INST_N=<N>; the launchers are named
+// launch_*_N<N> and dispatched at run time by dgx_launch.hip.
+#include "dgx_kernels.hpp"
+
+#ifndef DGX_INST_N
+#error "DGX_INST_N must be defined"
+#endif
+
+#define DGX_CAT2(a, b) a##b
+#define DGX_CAT(a, b) DGX_CAT2(a, b)
+#define DGX_NAME(base) DGX_CAT(base, DGX_CAT(_N, DGX_INST_N))
+
+namespace dgx {
+
+constexpr int kN = DGX_INST_N;
+
+hipError_t DGX_NAME(launch_trace)(const Cfg& c, const Geo& g, const double* U, double* Utr, hipStream_t s) {
+  const dim3 grid(g.nElems), block(Shape<kN>::nth);
+  if (c.nodes == 1)
+    hipLaunchKernelGGL((k_trace<kN, 1>), grid, block, 0, s, g, U, Utr);
+  else
+    hipLaunchKernelGGL((k_trace<kN, 0>), grid, block, 0, s, g, U, Utr);
+  return hipGetLastError();
+}
+
+hipError_t DGX_NAME(launch_lift)(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* Utr,
+                                 double* gout, double* gtr, hipStream_t s) {
+  const dim3 grid(g.nElems), block(Shape<kN>::nth);
+  if (c.nodes == 1)
+    hipLaunchKernelGGL((k_lift<kN, 1>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+  else
+    hipLaunchKernelGGL((k_lift<kN, 0>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+  return hipGetLastError();
+}
+
+template <int NODES, int FORM, int PHYS, int PREC>
+static void vol_mode(int mode, const Geo& g, const Phys& p, const double* U, const double* Utr, const double* gin,
+                     const double* gtr, double* Ut, double* Uio, double* dU, double* Utr_next, double A, double B,
+                     double dt, hipStream_t s) {
+  const dim3 grid(g.nElems), block(Shape<kN>::nth);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, PREC, 0>), grid, block, 0, s, g, p, U, Utr, gin, gtr, Ut,
+                       Uio, dU, Utr_next, A, B, dt);
+  else
+    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, PREC, 1>), grid, block, 0, s, g, p, U, Utr, gin, gtr, Ut,
+                       Uio, dU, Utr_next, A, B, dt);
+}
+
+template <int NODES, int FORM>
+static void vol_phys(const Cfg& c, int mode, const Geo& g, const Phys& p, const double* U, const double* Utr,
+                     const double* gin, const double* gtr, double* Ut, double* Uio, double* dU, double* Utr_next,
+                     double A, double B, double dt, hipStream_t s) {
+  if (c.physics == 0) {
+    if (c.precision == 0) vol_mode<NODES, FORM, 0, 0>(mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    else vol_mode<NODES, FORM, 0, 1>(mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  } else {
+    if (c.precision == 0) vol_mode<NODES, FORM, 1, 0>(mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    else vol_mode<NODES, FORM, 1, 1>(mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  }
+}
+
+hipError_t DGX_NAME(launch_volume)(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U,
+                                   const double* Utr, const double* gin, const double* gtr, double* Ut, double* Uio,
+                                   double* dU, double* Utr_next, double A, double B, double dt, hipStream_t s) {
+  if (c.nodes == 0)
+    vol_phys<0, 0>(c, mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  else if (c.form == 0)
+    vol_phys<1, 0>(c, mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  else
+    vol_phys<1, 1>(c, mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  return hipGetLastError();
+}
+
+}  // namespace dgx

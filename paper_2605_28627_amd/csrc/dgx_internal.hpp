@@ -1,0 +1,92 @@
+// dgx_internal.hpp -- internal types shared by the host runtime and the HIP
+// kernels of the DGSEM residual library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dgx {
+
+// Largest polynomial degree with compiled kernels and the basis storage size.
+constexpr int kMaxN = 7;
+constexpr int kMaxN1 = kMaxN + 1;
+
+// Device copy of the 1-D operators of one context (all FP64).
+struct DevBasis {
+  double w[kMaxN1];               // quadrature weights
+  double winv[kMaxN1];            // 1 / w
+  double Lm[kMaxN1], Lp[kMaxN1];  // l_j(-1), l_j(+1)
+  double Dhat[kMaxN1 * kMaxN1];   // Dhat[a*n1+l] = (w_l / w_a) D_{l a}  (weak-form volume operator)
+  double DS[kMaxN1 * kMaxN1];     // DS[a*n1+l] = 2 D_{a l} - e_N e_N^T / w_N + e_0 e_0^T / w_0  (split form)
+  double D[kMaxN1 * kMaxN1];      // D[a*n1+l] = l_l'(x_a)
+};
+
+// Per-element face table entry: side index, slot (0 master / 1 slave), orientation.
+__host__ __device__ inline int efc_pack(int side, int slot, int orient) { return (side << 4) | (slot << 3) | orient; }
+__host__ __device__ inline int efc_side(int v) { return v >> 4; }
+__host__ __device__ inline int efc_slot(int v) { return (v >> 3) & 1; }
+__host__ __device__ inline int efc_orient(int v) { return v & 7; }
+
+// Slave face-local (pp,qq) -> master (p,q) under orientation o (inverse of the
+// master->slave map: swap if bit 2, then reverse first if bit 0, second if bit 1).
+__host__ __device__ inline void orient_to_master(int o, int N, int pp, int qq, int& p, int& q) {
+  int a = (o & 1) ? N - pp : pp;
+  int b = (o & 2) ? N - qq : qq;
+  if (o & 4) { p = b; q = a; } else { p = a; q = b; }
+}
+
+// Physical constants and switches seen by the kernels.
+struct Phys {
+  double gamma, gm1, mu, lam, R, Rinv, Pr;  // lam = mu gamma R / ((gamma-1) Pr): heat conductivity
+  int riemann;                          // 0 Rusanov, 1 central part only
+  int twopoint;                         // 0 Chandrashekar, 1 flux average
+};
+
+// Everything a kernel needs about the discretisation.
+struct Geo {
+  int nElems, nSides;
+  const double* Ja;      // [9][nElems][n3]
+  const double* sJ;      // [nElems][n3]
+  const double* face;    // [4][nSides][n2]: unit normal (3), surface element
+  const int* efc;        // [nElems][6]
+  const DevBasis* basis;
+};
+
+// Kernel-side workspace pointers.
+struct Work {
+  double* Utr[2];        // ping-pong U traces: [2 slots][5][nSides][n2]
+  double* gtr;           // gradient traces:     [2 slots][12][nSides][n2]
+  double* g;             // lifted gradients:    [12][nElems][n3]
+  double* red;           // reduction partials
+  int* flag;             // state-check flag
+};
+
+struct Cfg {
+  int N, nodes, form, physics, precision;
+};
+
+// Launchers (defined in the kernel translation units).  Each returns the
+// result of hipGetLastError() after the launch.
+hipError_t launch_trace(const Cfg& c, const Geo& g, const double* U, double* Utr, hipStream_t s);
+hipError_t launch_lift(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* Utr, double* gout,
+                       double* gtr, hipStream_t s);
+// mode 0: Ut = R(U).  mode 1: dU = A dU + dt R(U); U += B dU; traces of the new U -> Utr_next.
+hipError_t launch_volume(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U, const double* Utr,
+                         const double* gin, const double* gtr, double* Ut, double* Uio, double* dU, double* Utr_next,
+                         double A, double B, double dt, hipStream_t s);
+
+hipError_t launch_fill(double* x, size_t n, double v, hipStream_t s);
+hipError_t launch_fill_int(int* x, size_t n, int v, hipStream_t s);
+hipError_t launch_kinetic_energy(const Cfg& c, const Geo& g, const double* U, double* partial, double* out,
+                                 double scale, hipStream_t s);
+hipError_t launch_kinetic_energy_grad(const Cfg& c, const Geo& g, const double* U, double* grad, double cJ,
+                                      hipStream_t s);
+hipError_t launch_timestep(const Cfg& c, const Geo& g, const Phys& p, const double* U, double* partial,
+                           double* out2, hipStream_t s);
+hipError_t launch_check_state(const Cfg& c, const Geo& g, const Phys& p, const double* U, int* flag,
+                              hipStream_t s);
+int reduction_blocks();
+
+}  // namespace dgx

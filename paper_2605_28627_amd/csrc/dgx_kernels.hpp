@@ -1,0 +1,731 @@
+// dgx_kernels.hpp -- HIP kernels of the DGSEM residual for gfx950.
+//
+// Layout: one workgroup per element, one work-item per volume node
+// (i fastest), the element tile and its face data staged in LDS.  Faces are
+// handled inside the element's workgroup: each side's flux is evaluated by
+// both adjacent elements from the same master-ordered inputs with the same
+// instructions, so both see bit-identical values and no atomics are needed.
+//
+// Operators (paper, "Governing Equations and Numerical Method"):
+//   weak volume term   V_a += sum_l Dhat[a][l] F~^r_l,  Dhat[a][l] = (w_l/w_a) D_{l a}
+//   split volume term  V_a -= sum_l DS[a][l] F#(U_a, U_l) . avg(Ja^r)
+//   surface term       V_a -= (1/w_a) (l_a(-1) Phi^- + l_a(+1) Phi^+)   (outward Phi)
+//   BR1 lifting        J g = -sum_l Dhat[a][l] (Ja^r_d q)_l + (1/w_a) l_a(+-1) {q} (n s)_d
+//   residual           U_t = (V + S) / J
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dgx_internal.hpp"
+
+namespace dgx {
+
+template <int N>
+struct Shape {
+  static constexpr int n1 = N + 1;
+  static constexpr int n2 = n1 * n1;
+  static constexpr int n3 = n2 * n1;
+  static constexpr int nth = ((n3 + 63) / 64) * 64;   // work-items per element (whole wavefronts)
+  static constexpr int nface = 6 * n2;                 // face nodes of one element
+};
+
+template <int N>
+__device__ __forceinline__ int nidx(int i, int j, int k) { return (k * (N + 1) + j) * (N + 1) + i; }
+
+// Volume node at position a along reference direction r, tangential face indices (pp, qq).
+template <int N>
+__device__ __forceinline__ int line_node(int r, int a, int pp, int qq) {
+  return r == 0 ? nidx<N>(a, pp, qq) : (r == 1 ? nidx<N>(pp, a, qq) : nidx<N>(pp, qq, a));
+}
+
+// Copy the basis into LDS (cooperatively).
+__device__ __forceinline__ void load_basis(DevBasis* dst, const DevBasis* src, int t, int nth) {
+  const double* s = reinterpret_cast<const double*>(src);
+  double* d = reinterpret_cast<double*>(dst);
+  constexpr int nd = sizeof(DevBasis) / sizeof(double);
+  for (int x = t; x < nd; x += nth) d[x] = s[x];
+}
+
+__device__ __forceinline__ size_t tr_index(int slot, int v, int nvar, int nSides, int side, int n2, int fi) {
+  return (((size_t)slot * nvar + v) * nSides + side) * n2 + fi;
+}
+
+// ---------------------------------------------------------------------------
+// Point physics.  FT is the flux arithmetic type (double, or float in the
+// FP32-flux mode); states, metrics and all accumulations are double.
+// ---------------------------------------------------------------------------
+struct Prim {
+  double rho, u[3], p;
+};
+
+__device__ __forceinline__ Prim cons2prim(const double U[5], double gm1) {
+  Prim q;
+  q.rho = U[0];
+  const double ri = 1.0 / U[0];
+  q.u[0] = U[1] * ri; q.u[1] = U[2] * ri; q.u[2] = U[3] * ri;
+  q.p = gm1 * (U[4] - 0.5 * q.rho * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]));
+  return q;
+}
+
+// Logarithmic mean (x - y)/(ln x - ln y) from precomputed logarithms; the
+// atanh series (x+y)/(2 + u(2/3 + u(2/5 + u 2/7))), u = ((x-y)/(x+y))^2, below
+// the threshold (1e-4 in double; 1e-2 in float where the truncation u^4/9 is
+// below the float rounding).
+template <typename FT>
+__device__ __forceinline__ FT log_mean(FT x, FT y, FT lx, FT ly) {
+  const FT thr = sizeof(FT) == 8 ? FT(1e-4) : FT(1e-2);
+  FT f = (x - y) / (x + y);
+  FT u = f * f;
+  if (u < thr) return (x + y) / (FT(2) + u * (FT(2.0 / 3.0) + u * (FT(2.0 / 5.0) + u * FT(2.0 / 7.0))));
+  return (x - y) / (lx - ly);
+}
+// Reciprocal of the logarithmic mean.
+template <typename FT>
+__device__ __forceinline__ FT inv_log_mean(FT x, FT y, FT lx, FT ly) {
+  const FT thr = sizeof(FT) == 8 ? FT(1e-4) : FT(1e-2);
+  FT f = (x - y) / (x + y);
+  FT u = f * f;
+  if (u < thr) return (FT(2) + u * (FT(2.0 / 3.0) + u * (FT(2.0 / 5.0) + u * FT(2.0 / 7.0)))) / (x + y);
+  return (lx - ly) / (x - y);
+}
+
+// Per-node data a two-point flux needs from a partner node.
+struct Aux {
+  double rho, u[3], beta, lrho, lbeta, k;   // k = |u|^2
+};
+
+// Chandrashekar's kinetic-energy-preserving, entropy-conservative flux in the
+// direction n (not normalised): F_rho = rho^ln {u}.n, F_m = p_hat n + {u} F_rho,
+// F_E = F_rho (1/(2 (gamma-1) beta^ln) - {|u|^2}/2) + {u}.F_m.
+template <typename FT>
+__device__ __forceinline__ void chandrashekar(const Aux& a, const Aux& b, const double n[3], double c1, double F[5]) {
+  const FT rho_ln = log_mean<FT>(FT(a.rho), FT(b.rho), FT(a.lrho), FT(b.lrho));
+  const FT ibeta_ln = inv_log_mean<FT>(FT(a.beta), FT(b.beta), FT(a.lbeta), FT(b.lbeta));
+  const FT phat = FT(0.5) * (FT(a.rho) + FT(b.rho)) / (FT(a.beta) + FT(b.beta));
+  const FT X = ibeta_ln * FT(c1) - FT(0.25) * (FT(a.k) + FT(b.k));
+  const double um0 = 0.5 * (a.u[0] + b.u[0]), um1 = 0.5 * (a.u[1] + b.u[1]), um2 = 0.5 * (a.u[2] + b.u[2]);
+  const double umn = um0 * n[0] + um1 * n[1] + um2 * n[2];
+  const double Fr = double(rho_ln) * umn;
+  const double ph = double(phat);
+  F[0] = Fr;
+  F[1] = ph * n[0] + um0 * Fr;
+  F[2] = ph * n[1] + um1 * Fr;
+  F[3] = ph * n[2] + um2 * Fr;
+  F[4] = Fr * double(X) + (um0 * F[1] + um1 * F[2] + um2 * F[3]);
+}
+
+__device__ __forceinline__ Aux make_aux(const Prim& q) {
+  Aux a;
+  a.rho = q.rho; a.u[0] = q.u[0]; a.u[1] = q.u[1]; a.u[2] = q.u[2];
+  a.beta = 0.5 * q.rho / q.p;
+  a.lrho = log(q.rho);
+  a.lbeta = log(a.beta);
+  a.k = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+  return a;
+}
+
+// Advective flux of U in direction n (not normalised).
+template <typename FT>
+__device__ __forceinline__ void euler_flux(const double U[5], const Prim& q, const double n[3], double F[5]) {
+  if constexpr (sizeof(FT) == 8) {
+    const double un = q.u[0] * n[0] + q.u[1] * n[1] + q.u[2] * n[2];
+    F[0] = U[0] * un;
+    F[1] = U[1] * un + q.p * n[0];
+    F[2] = U[2] * un + q.p * n[1];
+    F[3] = U[3] * un + q.p * n[2];
+    F[4] = (U[4] + q.p) * un;
+  } else {
+    // Cartesian flux components in float, contraction with the metric in double.
+    const float r = float(q.rho), u0 = float(q.u[0]), u1 = float(q.u[1]), u2 = float(q.u[2]), p = float(q.p);
+    const float H = float(U[4]) + p;
+    const float uu[3] = {u0, u1, u2};
+    double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float ud = uu[d];
+      const float ru = r * ud;
+      acc[0] += n[d] * double(ru);
+      acc[1] += n[d] * double(ru * u0 + (d == 0 ? p : 0.0f));
+      acc[2] += n[d] * double(ru * u1 + (d == 1 ? p : 0.0f));
+      acc[3] += n[d] * double(ru * u2 + (d == 2 ? p : 0.0f));
+      acc[4] += n[d] * double(H * ud);
+    }
+    for (int v = 0; v < 5; ++v) F[v] = acc[v];
+  }
+}
+
+// Viscous flux G_d (d = 0..2) for the momentum and energy components (v = 1..4),
+// contracted with n: Gn[v-1] = sum_d n_d G_d[v].  g[3a+d] = dq_a/dx_d, q = (u,v,w,T).
+template <typename FT>
+__device__ __forceinline__ void viscous_flux(const Prim& q, const double g[12], const Phys& P, const double n[3],
+                                             double Gn[4]) {
+  const FT mu = FT(P.mu), lam = FT(P.lam);
+  FT gg[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) gg[c] = FT(g[c]);
+  const FT divu = gg[0] + gg[4] + gg[8];
+  FT tau[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) tau[a][d] = mu * (gg[3 * a + d] + gg[3 * d + a]);
+  const FT t2 = FT(2.0 / 3.0) * mu * divu;
+  tau[0][0] -= t2; tau[1][1] -= t2; tau[2][2] -= t2;
+  const FT u0 = FT(q.u[0]), u1 = FT(q.u[1]), u2 = FT(q.u[2]);
+  double acc[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    acc[0] += n[d] * double(tau[0][d]);
+    acc[1] += n[d] * double(tau[1][d]);
+    acc[2] += n[d] * double(tau[2][d]);
+    acc[3] += n[d] * double(tau[d][0] * u0 + tau[d][1] * u1 + tau[d][2] * u2 + lam * gg[9 + d]);
+  }
+  Gn[0] = acc[0]; Gn[1] = acc[1]; Gn[2] = acc[2]; Gn[3] = acc[3];
+}
+
+// Outward (master) surface flux at one face node:
+// Phi = [F*(UL,UR).n - lambda_max/2 (UR-UL)] s - 1/2 (G(UL,gL) + G(UR,gR)).n s
+template <typename FT, int FORM, int PHYS>
+__device__ __forceinline__ void surface_flux(const double UL[5], const double UR[5], const double* gL,
+                                             const double* gR, const double nh[3], double s, const Phys& P,
+                                             double Phi[5]) {
+  const Prim qL = cons2prim(UL, P.gm1), qR = cons2prim(UR, P.gm1);
+  const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
+  if constexpr (FORM == 0) {
+    double FL[5], FR[5];
+    euler_flux<FT>(UL, qL, nv, FL);
+    euler_flux<FT>(UR, qR, nv, FR);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Phi[v] = 0.5 * (FL[v] + FR[v]);
+  } else {
+    if (P.twopoint == 0) {
+      const Aux aL = make_aux(qL), aR = make_aux(qR);
+      chandrashekar<FT>(aL, aR, nv, 0.5 / P.gm1, Phi);
+    } else {
+      double FL[5], FR[5];
+      euler_flux<FT>(UL, qL, nv, FL);
+      euler_flux<FT>(UR, qR, nv, FR);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Phi[v] = 0.5 * (FL[v] + FR[v]);
+    }
+  }
+  if (P.riemann == 0) {
+    const FT cL = sqrt(FT(P.gamma) * FT(qL.p) / FT(qL.rho));
+    const FT cR = sqrt(FT(P.gamma) * FT(qR.p) / FT(qR.rho));
+    const FT unL = FT(qL.u[0] * nh[0] + qL.u[1] * nh[1] + qL.u[2] * nh[2]);
+    const FT unR = FT(qR.u[0] * nh[0] + qR.u[1] * nh[1] + qR.u[2] * nh[2]);
+    const FT lL = fabs(unL) + cL, lR = fabs(unR) + cR;
+    const double lmax = double(lL >= lR ? lL : lR);
+    const double hs = 0.5 * (lmax * s);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Phi[v] -= hs * (UR[v] - UL[v]);
+  }
+  if constexpr (PHYS == 1) {
+    double GL[4], GR[4];
+    viscous_flux<FT>(qL, gL, P, nv, GL);
+    viscous_flux<FT>(qR, gR, P, nv, GR);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Phi[1 + v] -= 0.5 * (GL[v] + GR[v]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Trace kernel: U at the element faces -> Utr[slot][5][side][master (p,q)].
+// ---------------------------------------------------------------------------
+template <int N, int NODES>
+__global__ __launch_bounds__(Shape<N>::nth) void k_trace(Geo G, const double* __restrict__ U,
+                                                         double* __restrict__ Utr) {
+  using S = Shape<N>;
+  constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
+  const int e = blockIdx.x, t = threadIdx.x;
+  const int nE = G.nElems, nS = G.nSides;
+  if constexpr (NODES == 1) {
+    if (t >= n3) return;
+    const int i = t % n1, j = (t / n1) % n1, k = t / n2;
+    const int idx[3] = {i, j, k};
+    double u[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int a = idx[r];
+      if (a != 0 && a != N) continue;
+      const int f = 2 * r + (a == N ? 1 : 0);
+      const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+      const int info = G.efc[e * 6 + f];
+      const int side = efc_side(info), slot = efc_slot(info);
+      int p = pp, q = qq;
+      if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Utr[tr_index(slot, v, 5, nS, side, n2, q * n1 + p)] = u[v];
+    }
+  } else {
+    __shared__ double su[5 * n3];
+    __shared__ DevBasis sb;
+    load_basis(&sb, G.basis, t, S::nth);
+    if (t < n3)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) su[v * n3 + t] = U[((size_t)v * nE + e) * n3 + t];
+    __syncthreads();
+    for (int ft = t; ft < S::nface; ft += S::nth) {
+      const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
+      const double* L = (f & 1) ? sb.Lp : sb.Lm;
+      const int info = G.efc[e * 6 + f];
+      const int side = efc_side(info), slot = efc_slot(info);
+      int p = pp, q = qq;
+      if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < n1; ++a) acc += L[a] * su[v * n3 + line_node<N>(r, a, pp, qq)];
+        Utr[tr_index(slot, v, 5, nS, side, n2, q * n1 + p)] = acc;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BR1 lifting kernel (paper eq. dgsem_lifted): g = grad (u, v, w, T) -> gout,
+// and its face traces -> gtr[slot][12][side][master (p,q)].
+// ---------------------------------------------------------------------------
+template <int N, int NODES>
+__global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const double* __restrict__ U,
+                                                        const double* __restrict__ Utr, double* __restrict__ gout,
+                                                        double* __restrict__ gtr) {
+  using S = Shape<N>;
+  constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
+  constexpr int SZ = (13 * n3 > 7 * S::nface ? 13 * n3 : 7 * S::nface);
+  constexpr int SZ2 = (12 * n3 > SZ ? 12 * n3 : SZ);
+  __shared__ double sm[SZ2];
+  __shared__ double sf[7 * S::nface];
+  __shared__ DevBasis sb;
+  const int e = blockIdx.x, t = threadIdx.x;
+  const int nE = G.nElems, nS = G.nSides;
+  load_basis(&sb, G.basis, t, S::nth);
+  double* sq = sm;            // [4][n3]
+  double* sja = sm + 4 * n3;  // [9][n3]
+  const bool act = t < n3;
+  const int i = t % n1, j = (t / n1) % n1, k = t / n2;
+  double sJ = 0.0;
+  if (act) {
+    double u[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+    const Prim q = cons2prim(u, P.gm1);
+    sq[0 * n3 + t] = q.u[0];
+    sq[1 * n3 + t] = q.u[1];
+    sq[2 * n3 + t] = q.u[2];
+    sq[3 * n3 + t] = q.p / (q.rho * P.R);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) sja[c * n3 + t] = G.Ja[((size_t)c * nE + e) * n3 + t];
+    sJ = G.sJ[(size_t)e * n3 + t];
+  }
+  // face averages {q} and outward n s for this element's faces
+  for (int ft = t; ft < S::nface; ft += S::nth) {
+    const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
+    const int info = G.efc[e * 6 + f];
+    const int side = efc_side(info), slot = efc_slot(info);
+    int p = pp, q = qq;
+    if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
+    const int fi = q * n1 + p;
+    double UL[5], UR[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      UL[v] = Utr[tr_index(0, v, 5, nS, side, n2, fi)];
+      UR[v] = Utr[tr_index(1, v, 5, nS, side, n2, fi)];
+    }
+    const Prim a = cons2prim(UL, P.gm1), b = cons2prim(UR, P.gm1);
+    sf[(f * 7 + 0) * n2 + rr] = 0.5 * (a.u[0] + b.u[0]);
+    sf[(f * 7 + 1) * n2 + rr] = 0.5 * (a.u[1] + b.u[1]);
+    sf[(f * 7 + 2) * n2 + rr] = 0.5 * (a.u[2] + b.u[2]);
+    sf[(f * 7 + 3) * n2 + rr] = 0.5 * (a.p / (a.rho * P.R) + b.p / (b.rho * P.R));
+    const double sgn = slot ? -1.0 : 1.0;
+    const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sf[(f * 7 + 4 + c) * n2 + rr] = sgn * (G.face[((size_t)c * nS + side) * n2 + fi] * s);
+  }
+  __syncthreads();
+  double acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = 0.0;
+  if (act) {
+    const int idx[3] = {i, j, k};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int a = idx[r];
+      const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+#pragma unroll
+      for (int l = 0; l < n1; ++l) {
+        const int tl = line_node<N>(r, l, pp, qq);
+        const double c = sb.Dhat[a * n1 + l];
+        const double j0 = sja[(3 * r + 0) * n3 + tl], j1 = sja[(3 * r + 1) * n3 + tl], j2 = sja[(3 * r + 2) * n3 + tl];
+#pragma unroll
+        for (int qa = 0; qa < 4; ++qa) {
+          const double cq = c * sq[qa * n3 + tl];
+          acc[3 * qa + 0] -= cq * j0;
+          acc[3 * qa + 1] -= cq * j1;
+          acc[3 * qa + 2] -= cq * j2;
+        }
+      }
+      // surface terms of the two faces normal to r
+#pragma unroll
+      for (int side2 = 0; side2 < 2; ++side2) {
+        const int f = 2 * r + side2;
+        double L;
+        if constexpr (NODES == 1) {
+          if (a != (side2 ? N : 0)) continue;
+          L = sb.winv[a];
+        } else {
+          L = sb.winv[a] * (side2 ? sb.Lp[a] : sb.Lm[a]);
+        }
+        const int rr = qq * n1 + pp;
+        const double n0 = sf[(f * 7 + 4) * n2 + rr], n1v = sf[(f * 7 + 5) * n2 + rr], n2v = sf[(f * 7 + 6) * n2 + rr];
+#pragma unroll
+        for (int qa = 0; qa < 4; ++qa) {
+          const double avg = L * sf[(f * 7 + qa) * n2 + rr];
+          acc[3 * qa + 0] += avg * n0;
+          acc[3 * qa + 1] += avg * n1v;
+          acc[3 * qa + 2] += avg * n2v;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      acc[c] *= sJ;
+      gout[((size_t)c * nE + e) * n3 + t] = acc[c];
+    }
+  }
+  // gradient traces
+  if constexpr (NODES == 1) {
+    if (act) {
+      const int idx[3] = {i, j, k};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int a = idx[r];
+        if (a != 0 && a != N) continue;
+        const int f = 2 * r + (a == N ? 1 : 0);
+        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+        const int info = G.efc[e * 6 + f];
+        const int side = efc_side(info), slot = efc_slot(info);
+        int p = pp, q = qq;
+        if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gtr[tr_index(slot, c, 12, nS, side, n2, q * n1 + p)] = acc[c];
+      }
+    }
+  } else {
+    __syncthreads();
+    if (act)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sm[c * n3 + t] = acc[c];
+    __syncthreads();
+    for (int ft = t; ft < S::nface; ft += S::nth) {
+      const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
+      const double* L = (f & 1) ? sb.Lp : sb.Lm;
+      const int info = G.efc[e * 6 + f];
+      const int side = efc_side(info), slot = efc_slot(info);
+      int p = pp, q = qq;
+      if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
+      for (int c = 0; c < 12; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < n1; ++a) s += L[a] * sm[c * n3 + line_node<N>(r, a, pp, qq)];
+        gtr[tr_index(slot, c, 12, nS, side, n2, q * n1 + p)] = s;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residual kernel: volume integral (weak or split), surface fluxes, surface
+// lift, Jacobian scaling; MODE 0 writes U_t, MODE 1 applies one LSERK stage
+// and writes the face traces of the new state for the next stage.
+// ---------------------------------------------------------------------------
+template <int N, int NODES, int FORM, int PHYS, int PREC, int MODE>
+__global__ __launch_bounds__(Shape<N>::nth) void k_volume(Geo G, Phys P, const double* __restrict__ U,
+                                                          const double* __restrict__ Utr,
+                                                          const double* __restrict__ gin,
+                                                          const double* __restrict__ gtr, double* __restrict__ Ut,
+                                                          double* __restrict__ Uio, double* __restrict__ dU,
+                                                          double* __restrict__ Utr_next, double A, double B,
+                                                          double dt) {
+  using S = Shape<N>;
+  using FT = typename std::conditional<PREC == 1, float, double>::type;
+  constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
+  constexpr int SZ_SPLIT = 17 * n3;                 // aux (8) + Ja (9)
+  constexpr int SZ_WEAK = 15 * n3;                  // contravariant fluxes
+  constexpr int SZ_VISC = 12 * n3;                  // viscous contravariant fluxes (split form)
+  constexpr int SZ_FACE = 5 * S::nface;             // surface fluxes
+  constexpr int SZ_NEWU = 5 * n3;                   // new state (Gauss-node traces)
+  constexpr int SZ0 = FORM == 1 ? SZ_SPLIT : SZ_WEAK;
+  constexpr int SZ1 = SZ0 > SZ_FACE ? SZ0 : SZ_FACE;
+  constexpr int SZ2 = (PHYS == 1 && FORM == 1 && SZ_VISC > SZ1) ? SZ_VISC : SZ1;
+  constexpr int SZ = SZ2 > SZ_NEWU ? SZ2 : SZ_NEWU;
+  __shared__ double sm[SZ];
+  __shared__ DevBasis sb;
+  const int e = blockIdx.x, t = threadIdx.x;
+  const int nE = G.nElems, nS = G.nSides;
+  load_basis(&sb, G.basis, t, S::nth);
+  const bool act = t < n3;
+  const int i = t % n1, j = (t / n1) % n1, k = t / n2;
+  const int idx[3] = {i, j, k};
+  double u[5] = {0, 0, 0, 0, 0};
+  double ja[9];
+  double acc[5] = {0, 0, 0, 0, 0};
+  Prim q{};
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ja[c] = G.Ja[((size_t)c * nE + e) * n3 + t];
+    q = cons2prim(u, P.gm1);
+  }
+  if constexpr (FORM == 0) {
+    // weak form: F~^r = Ja^r . (f - G) at every node, then Dhat contraction
+    if (act) {
+      double gl[12];
+      if constexpr (PHYS == 1) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gl[c] = gin[((size_t)c * nE + e) * n3 + t];
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double nv[3] = {ja[3 * r], ja[3 * r + 1], ja[3 * r + 2]};
+        double F[5];
+        euler_flux<FT>(u, q, nv, F);
+        if constexpr (PHYS == 1) {
+          double Gn[4];
+          viscous_flux<FT>(q, gl, P, nv, Gn);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) F[1 + v] -= Gn[v];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm[(5 * r + v) * n3 + t] = F[v];
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int a = idx[r];
+        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+#pragma unroll
+        for (int l = 0; l < n1; ++l) {
+          const int tl = line_node<N>(r, l, pp, qq);
+          const double c = sb.Dhat[a * n1 + l];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] += c * sm[(5 * r + v) * n3 + tl];
+        }
+      }
+    }
+    __syncthreads();
+  } else {
+    // split form: flux differencing with the two-point flux and averaged metrics
+    double* saux = sm;            // [8][n3]
+    double* sja = sm + 8 * n3;    // [9][n3]
+    if (act) {
+      const Aux a = make_aux(q);
+      saux[0 * n3 + t] = a.rho;
+      saux[1 * n3 + t] = a.u[0];
+      saux[2 * n3 + t] = a.u[1];
+      saux[3 * n3 + t] = a.u[2];
+      saux[4 * n3 + t] = a.beta;
+      saux[5 * n3 + t] = a.lrho;
+      saux[6 * n3 + t] = a.lbeta;
+      saux[7 * n3 + t] = a.k;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) sja[c * n3 + t] = ja[c];
+    }
+    __syncthreads();
+    if (act) {
+      Aux me;
+      me.rho = saux[0 * n3 + t]; me.u[0] = saux[1 * n3 + t]; me.u[1] = saux[2 * n3 + t];
+      me.u[2] = saux[3 * n3 + t]; me.beta = saux[4 * n3 + t]; me.lrho = saux[5 * n3 + t];
+      me.lbeta = saux[6 * n3 + t]; me.k = saux[7 * n3 + t];
+      const double c1 = 0.5 / P.gm1;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int a = idx[r];
+        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+        for (int l = 0; l < n1; ++l) {
+          if (l == a) continue;
+          const int tl = line_node<N>(r, l, pp, qq);
+          Aux ot;
+          ot.rho = saux[0 * n3 + tl]; ot.u[0] = saux[1 * n3 + tl]; ot.u[1] = saux[2 * n3 + tl];
+          ot.u[2] = saux[3 * n3 + tl]; ot.beta = saux[4 * n3 + tl]; ot.lrho = saux[5 * n3 + tl];
+          ot.lbeta = saux[6 * n3 + tl]; ot.k = saux[7 * n3 + tl];
+          const double nv[3] = {0.5 * (ja[3 * r] + sja[(3 * r) * n3 + tl]),
+                                0.5 * (ja[3 * r + 1] + sja[(3 * r + 1) * n3 + tl]),
+                                0.5 * (ja[3 * r + 2] + sja[(3 * r + 2) * n3 + tl])};
+          double F[5];
+          if (P.twopoint == 0) {
+            chandrashekar<FT>(me, ot, nv, c1, F);
+          } else {
+            double uo[5];
+            // central average of the two physical fluxes
+            const double ro = ot.rho;
+            uo[0] = ro; uo[1] = ro * ot.u[0]; uo[2] = ro * ot.u[1]; uo[3] = ro * ot.u[2];
+            const double po = 0.5 * ro / ot.beta;
+            uo[4] = po / P.gm1 + 0.5 * ro * ot.k;
+            Prim qo; qo.rho = ro; qo.u[0] = ot.u[0]; qo.u[1] = ot.u[1]; qo.u[2] = ot.u[2]; qo.p = po;
+            double Fa[5], Fb[5];
+            euler_flux<FT>(u, q, nv, Fa);
+            euler_flux<FT>(uo, qo, nv, Fb);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) F[v] = 0.5 * (Fa[v] + Fb[v]);
+          }
+          const double ds = sb.DS[a * n1 + l];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] -= ds * F[v];
+        }
+      }
+    }
+    __syncthreads();
+    if constexpr (PHYS == 1) {
+      // viscous part in weak form: acc -= sum_l Dhat[a][l] G~^r_l
+      if (act) {
+        double gl[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gl[c] = gin[((size_t)c * nE + e) * n3 + t];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const double nv[3] = {ja[3 * r], ja[3 * r + 1], ja[3 * r + 2]};
+          double Gn[4];
+          viscous_flux<FT>(q, gl, P, nv, Gn);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) sm[(4 * r + v) * n3 + t] = Gn[v];
+        }
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const int a = idx[r];
+          const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+#pragma unroll
+          for (int l = 0; l < n1; ++l) {
+            const int tl = line_node<N>(r, l, pp, qq);
+            const double c = sb.Dhat[a * n1 + l];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[1 + v] -= c * sm[(4 * r + v) * n3 + tl];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // surface fluxes of the six faces -> LDS (own face-local order, outward sign)
+  double* sphi = sm;  // [6][5][n2]
+  for (int ft = t; ft < S::nface; ft += S::nth) {
+    const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
+    const int info = G.efc[e * 6 + f];
+    const int side = efc_side(info), slot = efc_slot(info);
+    int p = pp, qm = qq;
+    if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+    const int fi = qm * n1 + p;
+    double UL[5], UR[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      UL[v] = Utr[tr_index(0, v, 5, nS, side, n2, fi)];
+      UR[v] = Utr[tr_index(1, v, 5, nS, side, n2, fi)];
+    }
+    double gL[12], gR[12];
+    if constexpr (PHYS == 1) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        gL[c] = gtr[tr_index(0, c, 12, nS, side, n2, fi)];
+        gR[c] = gtr[tr_index(1, c, 12, nS, side, n2, fi)];
+      }
+    }
+    const double nh[3] = {G.face[((size_t)0 * nS + side) * n2 + fi], G.face[((size_t)1 * nS + side) * n2 + fi],
+                          G.face[((size_t)2 * nS + side) * n2 + fi]};
+    const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
+    double Phi[5];
+    surface_flux<FT, FORM, PHYS>(UL, UR, gL, gR, nh, s, P, Phi);
+    const double sgn = slot ? -1.0 : 1.0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sphi[(f * 5 + v) * n2 + rr] = sgn * Phi[v];
+  }
+  __syncthreads();
+  double Unew[5];
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int a = idx[r];
+      const int rr = (r == 2 ? j : k) * n1 + (r == 0 ? j : i);
+      if constexpr (NODES == 1) {
+        if (a == 0) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] -= sb.winv[0] * sphi[((2 * r) * 5 + v) * n2 + rr];
+        }
+        if (a == N) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] -= sb.winv[N] * sphi[((2 * r + 1) * 5 + v) * n2 + rr];
+        }
+      } else {
+        const double cm = sb.winv[a] * sb.Lm[a], cp = sb.winv[a] * sb.Lp[a];
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          acc[v] -= cm * sphi[((2 * r) * 5 + v) * n2 + rr] + cp * sphi[((2 * r + 1) * 5 + v) * n2 + rr];
+      }
+    }
+    const double sJ = G.sJ[(size_t)e * n3 + t];
+    if constexpr (MODE == 0) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ut[((size_t)v * nE + e) * n3 + t] = acc[v] * sJ;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const size_t gi = ((size_t)v * nE + e) * n3 + t;
+        const double d = A * dU[gi] + dt * (acc[v] * sJ);
+        dU[gi] = d;
+        Unew[v] = u[v] + B * d;
+        Uio[gi] = Unew[v];
+      }
+    }
+  }
+  if constexpr (MODE == 1) {
+    // traces of the new state for the next stage
+    if constexpr (NODES == 1) {
+      if (act) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const int a = idx[r];
+          if (a != 0 && a != N) continue;
+          const int f = 2 * r + (a == N ? 1 : 0);
+          const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+          const int info = G.efc[e * 6 + f];
+          const int side = efc_side(info), slot = efc_slot(info);
+          int p = pp, qm = qq;
+          if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Utr_next[tr_index(slot, v, 5, nS, side, n2, qm * n1 + p)] = Unew[v];
+        }
+      }
+    } else {
+      __syncthreads();
+      if (act)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm[v * n3 + t] = Unew[v];
+      __syncthreads();
+      for (int ft = t; ft < S::nface; ft += S::nth) {
+        const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
+        const double* L = (f & 1) ? sb.Lp : sb.Lm;
+        const int info = G.efc[e * 6 + f];
+        const int side = efc_side(info), slot = efc_slot(info);
+        int p = pp, qm = qq;
+        if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          double s = 0.0;
+#pragma unroll
+          for (int a = 0; a < n1; ++a) s += L[a] * sm[v * n3 + line_node<N>(r, a, pp, qq)];
+          Utr_next[tr_index(slot, v, 5, nS, side, n2, qm * n1 + p)] = s;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace dgx

@@ -1,0 +1,109 @@
+"""DGSolver: one discretisation on the GPU (context, mesh, workspace) over the C-ABI.
+
+PyTorch provides device memory and streams only; every step of the residual,
+the time stepping and the adjoint runs in the HIP library.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import dgx
+
+CONFIG_KEYS = ("N", "nodes", "volume_form", "physics", "riemann", "twopoint", "precision", "gamma", "mu", "Pr", "R")
+
+
+def config_from_dict(d: dict) -> dgx.dg_config:
+    """Accepts the library's key names and the short names used by the workloads (form)."""
+    kw = {k: d[k] for k in CONFIG_KEYS if k in d}
+    if "form" in d and "volume_form" not in d:
+        kw["volume_form"] = d["form"]
+    if "dissipation" in d and "riemann" not in d:
+        kw["riemann"] = 0 if d["dissipation"] else 1
+    return dgx.make_config(**kw)
+
+
+class DGSolver:
+    def __init__(self, cfg: dict, mesh, device: str | torch.device = "cuda"):
+        self.device = torch.device(device)
+        self.cfg = dict(cfg)
+        self.ctx = dgx.dg_create(config_from_dict(cfg))
+        try:
+            with torch.cuda.device(self.device):
+                dgx.dg_upload_mesh(self.ctx, mesh)
+            self.nElems, self.nSides, self.npe, self.state_len = dgx.dg_sizes(self.ctx)
+            self.n1 = round(self.npe ** (1 / 3))
+            nb = dgx.dg_workspace_bytes(self.ctx)
+            # over-allocate so the bound pointer is 256-byte aligned
+            self._ws_raw = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+            off = (-self._ws_raw.data_ptr()) % 256
+            self.ws = self._ws_raw[off:off + nb]
+            dgx.dg_bind_workspace(self.ctx, self.ws)
+        except Exception:
+            dgx.dg_destroy(self.ctx)
+            self.ctx = None
+            raise
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            dgx.dg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def state_shape(self):
+        return (5, self.nElems, self.n1, self.n1, self.n1)
+
+    def coords(self) -> np.ndarray:
+        return dgx.dg_node_coords(self.ctx)
+
+    def metrics(self):
+        return dgx.dg_get_metrics(self.ctx)
+
+    def upload_metrics(self, Ja, sJ, nvec):
+        dgx.dg_upload_metrics(self.ctx, Ja, sJ, nvec)
+
+    def to_device(self, U: np.ndarray) -> torch.Tensor:
+        return torch.from_numpy(np.ascontiguousarray(U, dtype=np.float64)).to(self.device).reshape(self.state_shape)
+
+    def empty_state(self) -> torch.Tensor:
+        return torch.empty(self.state_shape, dtype=torch.float64, device=self.device)
+
+    def rhs(self, U: torch.Tensor, Ut: torch.Tensor | None = None, t: float = 0.0) -> torch.Tensor:
+        Ut = self.empty_state() if Ut is None else Ut
+        dgx.dg_rhs(self.ctx, U, Ut, t)
+        return Ut
+
+    def lift(self, U: torch.Tensor) -> torch.Tensor:
+        g = torch.empty((12, self.nElems, self.n1, self.n1, self.n1), dtype=torch.float64, device=self.device)
+        dgx.dg_lift(self.ctx, U, g)
+        return g
+
+    def rk_step(self, U: torch.Tensor, dU: torch.Tensor, dt: float, nsteps: int = 1, t: float = 0.0):
+        dgx.dg_rk_step(self.ctx, U, dU, t, dt, nsteps)
+
+    def adjoint_rhs(self, U: torch.Tensor, lam: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self.empty_state() if out is None else out
+        dgx.dg_adjoint_rhs(self.ctx, U, lam, out)
+        return out
+
+    def kinetic_energy(self, U: torch.Tensor, rho0U0sq: float = 1.0) -> torch.Tensor:
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        dgx.dg_kinetic_energy(self.ctx, U, out, rho0U0sq)
+        return out
+
+    def kinetic_energy_grad(self, U: torch.Tensor, rho0U0sq: float = 1.0, scale: float = 1.0) -> torch.Tensor:
+        g = self.empty_state()
+        dgx.dg_kinetic_energy_grad(self.ctx, U, g, rho0U0sq, scale)
+        return g
+
+    def timestep(self, U: torch.Tensor, cfl: float = 0.9) -> float:
+        return dgx.dg_timestep(self.ctx, U, cfl)
+
+    def check_state(self, U: torch.Tensor) -> int:
+        return dgx.dg_check_state(self.ctx, U)

@@ -1,0 +1,244 @@
+"""GPU parity of the HIP residual path against the oracle (through the C-ABI).
+
+* small meshes (several elements, ragged work-item tails for N=3 faces and
+  N=5 volumes, rotated frames, curved elements): residual, lifted gradients
+  and LSERK trajectories equal the oracle's to 1e-12 per variable
+  (max |gpu - oracle| / max |oracle|) on seeded states with O(1) residuals,
+  with the oracle's metric terms uploaded so that only the kernels differ;
+* the library's own metrics: same comparison within the metric rounding;
+* free-stream preservation, conservation and bitwise determinism on the GPU;
+* the bench workload at full size (NS split form, N=7, 16^3): sampled
+  elements against the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2605_28627_amd import inputs as I
+from tests.helpers import quad_weights3, rel_err_per_var
+
+pytestmark = pytest.mark.gpu
+PI = np.pi
+
+
+def _say(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def S(torch_cuda):
+    from paper_2605_28627_amd.solver import DGSolver
+    return DGSolver
+
+
+def _cfg(N, nodes, form, physics, **kw):
+    c = dict(N=N, nodes=nodes, form=form, physics=physics, mu=0.02 if physics else 0.0)
+    c.update(kw)
+    return c
+
+
+CASES = [
+    # N, nodes, form, physics, curved, rotate_seed
+    (3, 0, 0, 0, 0.0, 7),
+    (3, 0, 0, 1, 0.0, 7),
+    (1, 1, 0, 0, 0.0, 5),
+    (2, 1, 1, 1, 0.1, 5),
+    (4, 1, 0, 0, 0.1, 9),
+    (4, 1, 0, 1, 0.1, 9),
+    (5, 1, 1, 0, 0.1, 11),
+    (5, 1, 1, 1, 0.1, 11),
+    (6, 0, 0, 1, 0.0, 4),
+    (7, 1, 1, 1, 0.0, 3),
+    (7, 1, 1, 0, 0.1, 3),
+]
+
+
+def _setup(S, orc, case, K=(3, 2, 2), upload=True, **kw):
+    N, nodes, form, physics, curved, rot = case
+    mesh = I.box_mesh(K, (-PI,) * 3, (PI,) * 3, Ngeo=N if curved else 1, curved_amp=curved, rotate_seed=rot)
+    cfg = _cfg(N, nodes, form, physics, **kw)
+    o = orc.Oracle(cfg, mesh)
+    s = S(cfg, mesh)
+    if upload:
+        _, J, Ja = o.geometry()
+        s.upload_metrics(Ja, 1.0 / J, o.face_normals())
+    return o, s, mesh
+
+
+@pytest.mark.parametrize("case", CASES, ids=[str(c) for c in CASES])
+def test_rhs_matches_oracle(S, orc, case):
+    _say("rhs", case)
+    o, s, _ = _setup(S, orc, case)
+    U = I.smooth_random_state(o.coords(), 31, amp=0.2)
+    R_orc = o.rhs(U)
+    Ug = s.to_device(U)
+    R_gpu = s.rhs(Ug).cpu().numpy()
+    err = rel_err_per_var(R_gpu, R_orc)
+    _say("rhs", case, "rel err", err)
+    assert np.all(err < 1e-12), err
+    # bitwise reproducible (no atomics, no order dependence)
+    R2 = s.rhs(Ug).cpu().numpy()
+    assert np.array_equal(R_gpu, R2)
+
+
+@pytest.mark.parametrize("case", CASES[:2] + CASES[6:8], ids=[str(c) for c in CASES[:2] + CASES[6:8]])
+def test_rhs_switches_match_oracle(S, orc, case):
+    """Central surface flux and the central two-point switch."""
+    _say("switches", case)
+    o_kw = [dict(dissipation=0), dict(twopoint=1)] if case[2] == 1 else [dict(dissipation=0)]
+    for kw in o_kw:
+        gkw = dict(riemann=1) if "dissipation" in kw else dict(twopoint=1)
+        N, nodes, form, physics, curved, rot = case
+        mesh = I.box_mesh((2, 2, 3), (-PI,) * 3, (PI,) * 3, Ngeo=N if curved else 1, curved_amp=curved,
+                          rotate_seed=rot)
+        o = orc.Oracle(_cfg(N, nodes, form, physics, **kw), mesh)
+        s = S(_cfg(N, nodes, form, physics, **gkw), mesh)
+        _, J, Ja = o.geometry()
+        s.upload_metrics(Ja, 1.0 / J, o.face_normals())
+        U = I.smooth_random_state(o.coords(), 32, amp=0.2)
+        err = rel_err_per_var(s.rhs(s.to_device(U)).cpu().numpy(), o.rhs(U))
+        _say("switches", case, kw, err)
+        assert np.all(err < 1e-12), (kw, err)
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[5], CASES[9]], ids=str)
+def test_lift_matches_oracle(S, orc, case):
+    _say("lift", case)
+    o, s, _ = _setup(S, orc, case)
+    U = I.smooth_random_state(o.coords(), 33, amp=0.2)
+    g_orc = o.lift(U)
+    g_gpu = s.lift(s.to_device(U)).cpu().numpy()
+    err = rel_err_per_var(g_gpu, g_orc)
+    _say("lift", case, err.max())
+    assert np.all(err < 1e-12), err
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[3], CASES[6], CASES[9]], ids=str)
+def test_rk_steps_match_oracle(S, orc, case):
+    _say("rk", case)
+    o, s, _ = _setup(S, orc, case)
+    U0 = I.smooth_random_state(o.coords(), 34, amp=0.2)
+    dt = o.timestep(U0, 0.9)
+    nsteps = 3
+    U_orc = o.lserk(U0, nsteps, dt)
+    Ug = s.to_device(U0)
+    dUg = s.empty_state()
+    s.rk_step(Ug, dUg, dt, nsteps)
+    U_gpu = Ug.cpu().numpy()
+    err = rel_err_per_var(U_gpu - U0, U_orc - U0)
+    _say("rk", case, err)
+    assert np.all(err < 1e-11), err
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[7], CASES[9]], ids=str)
+def test_library_metrics_parity(S, orc, case):
+    """With the library's own host metrics the residuals agree within the metric rounding."""
+    o, s, _ = _setup(S, orc, case, upload=False)
+    U = I.smooth_random_state(o.coords(), 35, amp=0.2)
+    err = rel_err_per_var(s.rhs(s.to_device(U)).cpu().numpy(), o.rhs(U))
+    _say("library metrics", case, err)
+    assert np.all(err < 1e-10), err
+
+
+@pytest.mark.parametrize("case", [(5, 1, 1, 1, 0.1, 21), (5, 1, 0, 0, 0.1, 21), (3, 0, 0, 0, 0.0, 21)], ids=str)
+def test_free_stream_and_conservation(S, orc, case):
+    _say("fsp", case)
+    o, s, _ = _setup(S, orc, case, K=(3, 3, 3), upload=False)
+    xyz, Ja, sJ, _ = s.metrics()
+    U = np.zeros(s.state_shape)
+    rho, u, p = 1.0, np.array([0.1, 0.2, -0.1]), 71.43
+    U[0], U[1:4] = rho, (rho * u)[:, None, None, None, None]
+    U[4] = p / 0.4 + 0.5 * rho * u @ u
+    R = s.rhs(s.to_device(U)).cpu().numpy()
+    b = orc.basis(case[0], case[1])
+    Dhat = (b["w"][:, None] / b["w"][None, :]) * b["D"]
+    f = np.abs(orc.flux_adv(U[:, 0, 0, 0, 0], np.ones(3))).max() + np.abs(U[:, 0, 0, 0, 0]).max()
+    scale = 3 * f * np.abs(Ja).max() * np.abs(Dhat).sum(0).max() * sJ.max()
+    _say("fsp", case, np.abs(R).max() / scale)
+    assert np.abs(R).max() < 1e-13 * scale
+    U2 = I.smooth_random_state(xyz, 36, amp=0.2)
+    R2 = s.rhs(s.to_device(U2)).cpu().numpy()
+    W = quad_weights3(b["w"]) / sJ
+    for v in range(5):
+        assert abs((W * R2[v]).sum()) < 1e-13 * (W * np.abs(R2[v])).sum()
+
+
+def test_functionals(S, orc, torch_cuda):
+    case = (5, 1, 1, 0, 0.0, None)
+    o, s, _ = _setup(S, orc, case, K=(2, 2, 2))
+    U = I.tgv_state(o.coords())
+    Ug = s.to_device(U)
+    ek = s.kinetic_energy(Ug).item()
+    assert abs(ek - o.kinetic_energy(U)) < 1e-14
+    d = np.random.default_rng(3).uniform(-1, 1, U.shape)
+    g = s.kinetic_energy_grad(Ug).cpu().numpy()
+    assert abs((g * d).sum() - o.kinetic_energy_jvp(U, d)) < 1e-13 * abs(o.kinetic_energy_jvp(U, d))
+    assert abs(s.timestep(Ug, 0.9) / o.timestep(U, 0.9) - 1.0) < 1e-13
+    o2, s2, _ = _setup(S, orc, (4, 1, 1, 1, 0.1, 3), K=(2, 2, 2), mu=0.5)
+    U2 = I.smooth_random_state(o2.coords(), 2, amp=0.2)
+    assert abs(s2.timestep(s2.to_device(U2), 0.9) / o2.timestep(U2, 0.9) - 1.0) < 1e-13
+    # state check: physical state passes; host-forced non-physical values are reported
+    assert s.check_state(Ug) == 0
+    bad = U.copy()
+    bad[0, 1, 2, 3, 4] = -1.0
+    from paper_2605_28627_amd import dgx
+    assert s.check_state(s.to_device(bad)) == dgx.DG_ERR_NONPHYSICAL
+    bad = U.copy()
+    bad[4, 0, 0, 0, 0] = np.nan
+    assert s.check_state(s.to_device(bad)) == dgx.DG_ERR_NONPHYSICAL
+
+
+def test_bench_workload_full_size_sampled(S, orc, torch_cuda):
+    """NS split form, N=7, 16^3 on [-pi,pi]^3 (the benchmark's workload) at full size:
+    sampled elements (including the periodic seams) against the oracle."""
+    name = "ns_split_lgl_n7_16x16x16_tgv"
+    w = I.WORKLOADS[name]
+    mesh = I.workload_mesh(name)
+    cfg = dict(N=w["N"], nodes=w["nodes"], form=w["form"], physics=w["physics"], mu=w["mu"])
+    _say("full size", name, "oracle geometry")
+    o = orc.Oracle(cfg, mesh)
+    xyz, J, Ja = o.geometry()
+    s = S(cfg, mesh)
+    s.upload_metrics(Ja, 1.0 / J, o.face_normals())
+    sample = [0, 15, 255, 2047, 4095, 1234, 3000]
+    # (a) seeded per-node random state: the residual is as large as the flux
+    # terms it is made of, so the 1e-12 per-variable bar applies directly
+    U = I.random_state(s.state_shape[1:], 41)
+    R_gpu = s.rhs(s.to_device(U)).cpu().numpy()[:, sample]
+    R_orc = o.rhs_elems(U, sample)
+    err = rel_err_per_var(R_gpu, R_orc)
+    _say("full size random state", err)
+    assert np.all(err < 1e-12), err
+    # (b) smooth states (a seeded smooth field, the Taylor-Green vortex): on the
+    # fine mesh the residual is a small difference of much larger flux terms,
+    # so the bound is 64 eps of the size of those terms (|DS| row sums times
+    # the flux and metric magnitudes over J) plus the 1e-12 relative bound
+    b = orc.basis(7, 1)
+    for label, U in (("smooth", I.smooth_random_state(xyz, 41, amp=0.2)), ("tgv", I.tgv_state(xyz))):
+        R_gpu = s.rhs(s.to_device(U)).cpu().numpy()[:, sample]
+        R_orc = o.rhs_elems(U, sample)
+        fmax = max(np.abs(orc.flux_adv(U[:, e, 0, 0, 0], np.ones(3))).max() for e in sample)
+        scale = np.abs(b["DS"]).sum(1).max() * fmax * np.abs(Ja).max() / J.min()
+        diff = np.abs(R_gpu - R_orc).max(axis=(1, 2, 3, 4))
+        _say("full size", label, "diff", diff, "rel", rel_err_per_var(R_gpu, R_orc), "term scale", scale)
+        assert np.all(diff < 1e-12 * np.abs(R_orc).max(axis=(1, 2, 3, 4)) + 64 * 2.2e-16 * scale)
+    # (c) the time-stepping kernel at full size conserves every variable
+    Ug = s.to_device(U)
+    dUg = s.empty_state()
+    W = quad_weights3(b["w"]) * J
+    tot0 = [(W * U[v]).sum() for v in range(5)]
+    s.rk_step(Ug, dUg, 1e-3, 2)
+    U1 = Ug.cpu().numpy()
+    for v in range(5):
+        change = np.abs(W * (U1[v] - U[v])).sum()
+        tol = 1e-12 * change + 1e-14 * (W * np.abs(U[v])).sum() + 1e-15
+        assert abs((W * U1[v]).sum() - tot0[v]) < tol, (v, abs((W * U1[v]).sum() - tot0[v]), tol)

@@ -237,3 +237,49 @@ def test_timestep_scaling(orc):
         o = orc.Oracle(dict(N=3, nodes=1, physics=1, mu=10.0), I.box_mesh((K,) * 3, (0,) * 3, (1,) * 3))
         dtv.append(o.timestep(st(o)))
     assert abs(dtv[0] / dtv[1] - 4.0) < 1e-12
+
+
+def _growth(orc, cfg, U_fn, dt_fac=1.0, iters=30):
+    """Growth factor per step of the linearised LSERK4(5) step (power iteration
+    with the oracle's tangent) at dt_fac times the oracle's CFL-0.9 time step."""
+    mesh = I.box_mesh((2, 2, 2), (-PI,) * 3, (PI,) * 3)
+    o = orc.Oracle(cfg, mesh)
+    U = U_fn(o)
+    dt = o.timestep(U, 0.9) * dt_fac
+    d = np.random.default_rng(0).normal(size=U.shape)
+    d /= np.linalg.norm(d)
+    g = []
+    for _ in range(iters):
+        _, d = o.lserk_jvp(U, d, 1, dt)
+        n = np.linalg.norm(d)
+        g.append(n)
+        d /= n
+    return float(np.mean(g[-5:]))
+
+
+def _uniform(o, u=(1.0, 0.3, 0.0), p=71.43):
+    U = np.zeros(o.state_shape)
+    U[0], U[1:4] = 1.0, np.array(u)[:, None, None, None, None]
+    U[4] = p / 0.4 + 0.5 * np.dot(u, u)
+    return U
+
+
+@pytest.mark.parametrize("N", [1, 3, 5, 7])
+def test_timestep_is_linearly_stable(orc, N):
+    """The time-step reading keeps LSERK4(5) stable (advective, Ma 0.1 background)."""
+    g = _growth(orc, dict(N=N, nodes=1, form=1, physics=0), _uniform)
+    assert g < 1.002, g
+
+
+def test_timestep_is_not_overly_conservative(orc):
+    """At N=7 twice the time step is unstable: the scaling sits near the limit."""
+    g = _growth(orc, dict(N=7, nodes=1, form=1, physics=0), _uniform, dt_fac=2.0)
+    assert g > 1.05, g
+
+
+@pytest.mark.parametrize("N", [3, 7])
+def test_viscous_timestep_is_linearly_stable(orc, N):
+    cfg = dict(N=N, nodes=1, form=1, physics=1, mu=2.0)
+    slow = lambda o: _uniform(o, (0.1, 0.0, 0.0), 1.0)
+    assert _growth(orc, cfg, slow) < 1.002
+    assert _growth(orc, cfg, slow, dt_fac=2.5) > 1.05
