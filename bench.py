@@ -59,6 +59,28 @@ def copy_calibration():
                                            "copies": 5}}), flush=True)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_volume_ns_split_n7_16x16x16_tgv.md")
+VOLUME_KERNEL = "void dgx::k_volume<7, 1, 1, 1, 0, 1>"
+
+
+def measured_traffic(kernel):
+    """Calibrated HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a
+    plain copy of known size) from the committed rocprofv3 summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        txt = open(PROFILE).read()
+        meta = json.loads(re.search(r"```json\n(.*?)\n```", txt, re.S).group(1))
+        src = open(os.path.join(ROOT, "paper_2605_28627_amd", "csrc", "dgx_kernels.hpp"), "rb").read()
+        if hashlib.sha256(src).hexdigest()[:16] != meta["source_sha256_16"]:
+            return None
+        k = meta["kernels"][kernel]
+        return k["read"] + k["write"]
+    except (OSError, KeyError, AttributeError, ValueError):
+        return None
+
+
 def workload_cfg(name):
     from paper_2605_28627_amd import inputs as I
     w = I.WORKLOADS[name]
@@ -163,7 +185,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(VOLUME_KERNEL) if args.workload == WORKLOAD else None,
             "algorithmic_bytes_per_launch": bytes_launch,
             "avg_launch_ms": vol_avg_s * 1e3,
             "launches": vol_n,
