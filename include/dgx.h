@@ -132,8 +132,15 @@ dg_status dg_sizes(const dg_ctx* ctx, int* nElems, int* nSides, int* nodes_per_e
  * RK stage states of the adjoint, reduction partials).  Valid after a mesh is set. */
 size_t dg_workspace_bytes(const dg_ctx* ctx);
 
+/* Bytes of device scratch that the adjoint calls need (the forward scratch
+ * plus four recomputed stage states, an RK register, an adjoint residual and,
+ * for Navier-Stokes, the gradient adjoint).  Valid after a mesh is set. */
+size_t dg_workspace_bytes_adjoint(const dg_ctx* ctx);
+
 /* Binds caller-owned device memory of at least dg_workspace_bytes bytes,
- * 256-byte aligned.  The library never frees it. */
+ * 256-byte aligned.  The library never frees it.  With at least
+ * dg_workspace_bytes_adjoint bytes the adjoint calls are enabled; without,
+ * they fail with DG_ERR_STATE. */
 dg_status dg_bind_workspace(dg_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /* Residual and time stepping -------------------------------------------------- */
@@ -155,15 +162,21 @@ dg_status dg_rk_step(dg_ctx* ctx, double* U, double* dU, double t, double dt, in
 
 /* Adjoint --------------------------------------------------------------------- */
 
-/* out = (dR/dU)^T lam at the state U (device arrays, state length).  This is
- * the exact transpose of the discrete residual's Jacobian; at the kinks of
- * the Rusanov flux (|u.n|, max of the two wave speeds) the branch taken by
- * the forward evaluation is differentiated, ties going to the master side. */
+/* out = (dR/dU)^T lam at the state U (device arrays, state length; out must
+ * not alias U or lam).  This is the transpose of the discrete residual's
+ * Jacobian (not in the paper: a discrete adjoint of its residual); at the
+ * kinks of the Rusanov flux (|u.n|, max of the two wave speeds) and of the
+ * log-mean branch switch the branch taken by the forward evaluation is
+ * differentiated, ties going to the master side.  FP64 contexts only; needs
+ * a workspace of dg_workspace_bytes_adjoint bytes. */
 dg_status dg_adjoint_rhs(dg_ctx* ctx, const double* U, const double* lam, double* out, void* stream);
 
-/* Reverse of one LSERK4(5) step from state Un (device): on entry lamU holds
- * dJ/dU^{n+1}; on exit dJ/dU^n.  Stage states are recomputed from Un into the
- * workspace.  lamdU is a device register of the state length (scratch). */
+/* Reverse of one LSERK4(5) step of size dt from state Un (device): on entry
+ * lamU holds dJ/dU^{n+1}; on exit dJ/dU^n.  The stage inputs Y_0..Y_4 are
+ * recomputed from Un into the workspace; then, with lamdU = B_4 lamU, for
+ * s = 4..0: lamU += dt (dR/dU(Y_s))^T lamdU and lamdU = A_s lamdU + B_{s-1} lamU.
+ * lamdU is a caller-owned device register of the state length (scratch).
+ * Needs a workspace of dg_workspace_bytes_adjoint bytes. */
 dg_status dg_adjoint_rk_step(dg_ctx* ctx, const double* Un, double* lamU, double* lamdU, double t, double dt,
                              void* stream);
 

@@ -1,0 +1,95 @@
+"""Discrete adjoint of LSERK4(5) trajectories behind torch.autograd.
+
+`trajectory(solver, U0, dt, nsteps)` returns U(T) and is differentiable with
+respect to U0; the backward pass runs the library's hand-written adjoint
+(dg_adjoint_rk_step, which recomputes each step's stage states) over the
+steps in reverse, recomputing the step states segment by segment from
+checkpoints kept during the forward pass.  `kinetic_energy(solver, U)` is the
+paper's integral kinetic energy E_k and its gradient, both evaluated by the
+library.  PyTorch is used for memory and the autograd graph only.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import dgx
+
+
+def checkpoint_interval(solver, nsteps: int, memory_fraction: float = 0.5) -> int:
+    """Steps between checkpoints.  With k, the backward pass holds nsteps/k
+    checkpoints plus k recomputed step states; k = sqrt(nsteps) minimises
+    that, raised if needed so that both sets fit in a fraction of free HBM."""
+    state_bytes = solver.state_len * 8
+    free, _ = torch.cuda.mem_get_info(solver.device)
+    budget = max(int(free * memory_fraction) // state_bytes, 4)
+    k = max(1, int(math.ceil(math.sqrt(nsteps))))
+    while math.ceil(nsteps / k) + k > budget and k < nsteps:
+        k += 1
+    return k
+
+
+class _Trajectory(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U0, solver, dt, nsteps, every):
+        U = U0.detach().clone()
+        dU = torch.empty_like(U)
+        ckpts = {}
+        for n in range(nsteps):
+            if n % every == 0:
+                ckpts[n] = U.clone()
+            solver.rk_step(U, dU, dt, 1)
+        ctx.solver, ctx.dt, ctx.nsteps, ctx.every, ctx.ckpts = solver, dt, nsteps, every, ckpts
+        return U
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        solver, dt, nsteps, every = ctx.solver, ctx.dt, ctx.nsteps, ctx.every
+        lamU = grad_out.detach().contiguous().clone()
+        lamdU = torch.empty_like(lamU)
+        dU = torch.empty_like(lamU)
+        starts = sorted(ctx.ckpts.keys())
+        for s0 in reversed(starts):
+            s1 = min(s0 + every, nsteps)
+            states = [ctx.ckpts[s0]]
+            U = ctx.ckpts[s0].clone()
+            for _ in range(s0, s1 - 1):
+                solver.rk_step(U, dU, dt, 1)
+                states.append(U.clone())
+            for n in reversed(range(s0, s1)):
+                solver.adjoint_rk_step(states[n - s0], lamU, lamdU, dt)
+            del states
+        ctx.ckpts = None
+        return lamU, None, None, None, None
+
+
+def trajectory(solver, U0: torch.Tensor, dt: float, nsteps: int, checkpoint_every: int | None = None):
+    """U(T) after nsteps LSERK4(5) steps of size dt; differentiable in U0."""
+    if not getattr(solver, "adjoint", False):
+        raise ValueError("the solver was created without the adjoint workspace (DGSolver(..., adjoint=True))")
+    every = checkpoint_every or checkpoint_interval(solver, nsteps)
+    return _Trajectory.apply(U0, solver, float(dt), int(nsteps), int(every))
+
+
+class _KineticEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U, solver, rho0U0sq):
+        ctx.save_for_backward(U)
+        ctx.solver, ctx.rho0U0sq = solver, rho0U0sq
+        out = torch.empty(1, dtype=torch.float64, device=U.device)
+        dgx.dg_kinetic_energy(solver.ctx, U.detach().contiguous(), out, rho0U0sq)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (U,) = ctx.saved_tensors
+        g = torch.empty_like(U)
+        dgx.dg_kinetic_energy_grad(ctx.solver.ctx, U.detach().contiguous(), g, ctx.rho0U0sq,
+                                   float(grad_out.reshape(-1)[0].item()))
+        return g, None, None
+
+
+def kinetic_energy(solver, U: torch.Tensor, rho0U0sq: float = 1.0) -> torch.Tensor:
+    """E_k = sum w J |m|^2/rho / (2 rho0 U0^2 |Omega|), shape (1,); differentiable in U."""
+    return _KineticEnergy.apply(U, solver, float(rho0U0sq))

@@ -14,6 +14,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgx.so")
+CHECK_LIB = os.path.join(HERE, "libdgx_pointwise_check.so")
 BUILD = os.path.join(HERE, "_build")
 DEGREES = range(1, 8)
 
@@ -47,7 +48,20 @@ def build(jobs: int | None = None) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_pointwise_check()
     return LIB
+
+
+def build_pointwise_check() -> str:
+    """Host build of the point physics and its VJPs, for the CPU test suite."""
+    tmp = CHECK_LIB + ".tmp"
+    cmd = [HIPCC, "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+           "-I", os.path.join(HERE, "..", "include"), os.path.join(CSRC, "dgx_pointwise_check.cpp"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"host build of the point physics failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, CHECK_LIB)
+    return CHECK_LIB
 
 
 def clean():

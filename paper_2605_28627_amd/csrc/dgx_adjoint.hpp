@@ -1,0 +1,423 @@
+// dgx_adjoint.hpp -- discrete adjoint of the DGSEM residual: out = (dR/dU)^T lam.
+//
+// Same layout as the forward kernels (one workgroup per element, one
+// work-item per node, element data in LDS).  With lt = lam / J:
+//   surface:  each element writes t = -(1/w) l(+-1) lt along its normal lines
+//             (k_adj_trace); the side flux's adjoint is t_master - t_slave;
+//   volume:   weak form  F~^r_l gets sum_a Dhat[a][l] lt_a (transposed
+//             contraction along the line); split form: node m gets
+//             -sum_l J_A(m,l)^T (DS[m][l] lt_m + DS[l][m] lt_l), J_A the
+//             Jacobian of F#(U_m, U_l) in its first argument (F# is symmetric);
+//   lifting (Navier-Stokes): the gradient adjoint gb from the viscous terms
+//             flows back through g = lift(U) (k_adj_lift_trace/_volume).
+// The Rusanov kinks are differentiated on the branch the forward takes.
+#pragma once
+
+#include "dgx_kernels.hpp"
+
+namespace dgx {
+
+// Per-element surface adjoint t = -(1/w_a) l_a(+-1) (sJ lam)_a summed along the normal line.
+template <int N, int NODES>
+__global__ __launch_bounds__(Shape<N>::nth) void k_adj_trace(Geo G, const double* __restrict__ lam,
+                                                             double* __restrict__ Lbar) {
+  using S = Shape<N>;
+  constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
+  __shared__ double sl[5 * n3];
+  __shared__ DevBasis sb;
+  const int e = blockIdx.x, t = threadIdx.x;
+  const int nE = G.nElems, nS = G.nSides;
+  load_basis(&sb, G.basis, t, S::nth);
+  if (t < n3) {
+    const double sJ = G.sJ[(size_t)e * n3 + t];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sl[v * n3 + t] = sJ * lam[((size_t)v * nE + e) * n3 + t];
+  }
+  __syncthreads();
+  for (int ft = t; ft < S::nface; ft += S::nth) {
+    const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
+    const int info = G.efc[e * 6 + f];
+    const int side = efc_side(info), slot = efc_slot(info);
+    int p = pp, q = qq;
+    if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double acc = 0.0;
+      if constexpr (NODES == 1) {
+        const int a = (f & 1) ? N : 0;
+        acc = -sb.winv[a] * sl[v * n3 + line_node<N>(r, a, pp, qq)];
+      } else {
+        const double* L = (f & 1) ? sb.Lp : sb.Lm;
+#pragma unroll
+        for (int a = 0; a < n1; ++a) acc -= sb.winv[a] * L[a] * sl[v * n3 + line_node<N>(r, a, pp, qq)];
+      }
+      Lbar[tr_index(slot, v, 5, nS, side, n2, q * n1 + p)] = acc;
+    }
+  }
+}
+
+// Volume and surface adjoint of the residual; Navier-Stokes also writes the
+// gradient adjoint gbar[12][e][node] (from the viscous volume and surface terms).
+template <int N, int NODES, int FORM, int PHYS>
+__global__ __launch_bounds__(Shape<N>::nth) void k_adj_volume(Geo G, Phys P, const double* __restrict__ U,
+                                                              const double* __restrict__ lam,
+                                                              const double* __restrict__ Utr,
+                                                              const double* __restrict__ Lbar,
+                                                              const double* __restrict__ gin,
+                                                              const double* __restrict__ gtr,
+                                                              double* __restrict__ out, double* __restrict__ gbar) {
+  using S = Shape<N>;
+  constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
+  constexpr int NF = PHYS == 1 ? 17 : 5;                           // face adjoint values per face node
+  constexpr int SZ_V = FORM == 1 ? 22 * n3 : 5 * n3;                 // lt (5) [+ aux (8) + Ja (9)]
+  constexpr int SZ_F = NF * S::nface;
+  constexpr int SZ = SZ_V > SZ_F ? SZ_V : SZ_F;
+  __shared__ double sm[SZ];
+  __shared__ DevBasis sb;
+  const int e = blockIdx.x, t = threadIdx.x;
+  const int nE = G.nElems, nS = G.nSides;
+  load_basis(&sb, G.basis, t, S::nth);
+  const bool act = t < n3;
+  const int i = t % n1, j = (t / n1) % n1, k = t / n2;
+  const int idx[3] = {i, j, k};
+  double u[5] = {0, 0, 0, 0, 0}, ja[9], Ub[5] = {0, 0, 0, 0, 0}, ub[3] = {0, 0, 0}, gb[12], gl[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) gb[c] = 0.0;
+  Prim q{};
+  double* sl = sm;  // [5][n3] lam / J
+  if (act) {
+    const double sJ = G.sJ[(size_t)e * n3 + t];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      u[v] = U[((size_t)v * nE + e) * n3 + t];
+      sl[v * n3 + t] = sJ * lam[((size_t)v * nE + e) * n3 + t];
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ja[c] = G.Ja[((size_t)c * nE + e) * n3 + t];
+    q = cons2prim(u, P.gm1);
+    if constexpr (PHYS == 1) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) gl[c] = gin[((size_t)c * nE + e) * n3 + t];
+    }
+  }
+  Aux me{};
+  if constexpr (FORM == 1) {
+    double* saux = sm + 5 * n3;
+    double* sja = sm + 13 * n3;
+    if (act) {
+      me = make_aux(q);
+      saux[0 * n3 + t] = me.rho; saux[1 * n3 + t] = me.u[0]; saux[2 * n3 + t] = me.u[1];
+      saux[3 * n3 + t] = me.u[2]; saux[4 * n3 + t] = me.beta; saux[5 * n3 + t] = me.lrho;
+      saux[6 * n3 + t] = me.lbeta; saux[7 * n3 + t] = me.k;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) sja[c * n3 + t] = ja[c];
+    }
+  }
+  __syncthreads();
+  if (act) {
+    // transposed weak-form contraction Lam^r = sum_a Dhat[a][l] lt_a along each line
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int l = idx[r];
+      const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+      double Lam[5] = {0, 0, 0, 0, 0};
+      if (FORM == 0 || PHYS == 1) {
+#pragma unroll
+        for (int a = 0; a < n1; ++a) {
+          const double c = sb.Dhat[a * n1 + l];
+          const int ta = line_node<N>(r, a, pp, qq);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Lam[v] += c * sl[v * n3 + ta];
+        }
+      }
+      const double nv[3] = {ja[3 * r], ja[3 * r + 1], ja[3 * r + 2]};
+      if constexpr (FORM == 0) {
+        double Ue[5];
+        euler_flux_vjp(u, q, nv, Lam, P.gm1, Ue);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Ub[v] += Ue[v];
+      }
+      if constexpr (PHYS == 1) {
+        const double Gnb[4] = {-Lam[1], -Lam[2], -Lam[3], -Lam[4]};
+        double gq[12], uq[3];
+        viscous_flux_vjp(q, gl, P, nv, Gnb, gq, uq);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gb[c] += gq[c];
+        ub[0] += uq[0]; ub[1] += uq[1]; ub[2] += uq[2];
+      }
+    }
+    if constexpr (FORM == 1) {
+      const double* saux = sm + 5 * n3;
+      const double* sja = sm + 13 * n3;
+      const double c1 = 0.5 / P.gm1;
+      AuxBar ab{};
+      double lm[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) lm[v] = sl[v * n3 + t];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int a = idx[r];
+        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+        for (int l = 0; l < n1; ++l) {
+          if (l == a) continue;
+          const int tl = line_node<N>(r, l, pp, qq);
+          Aux ot;
+          ot.rho = saux[0 * n3 + tl]; ot.u[0] = saux[1 * n3 + tl]; ot.u[1] = saux[2 * n3 + tl];
+          ot.u[2] = saux[3 * n3 + tl]; ot.beta = saux[4 * n3 + tl]; ot.lrho = saux[5 * n3 + tl];
+          ot.lbeta = saux[6 * n3 + tl]; ot.k = saux[7 * n3 + tl];
+          const double nv[3] = {0.5 * (ja[3 * r] + sja[(3 * r) * n3 + tl]),
+                                0.5 * (ja[3 * r + 1] + sja[(3 * r + 1) * n3 + tl]),
+                                0.5 * (ja[3 * r + 2] + sja[(3 * r + 2) * n3 + tl])};
+          const double dml = sb.DS[a * n1 + l], dlm = sb.DS[l * n1 + a];
+          double w[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) w[v] = -(dml * lm[v] + dlm * sl[v * n3 + tl]);
+          if (P.twopoint == 0) {
+            AuxBar d;
+            chandrashekar_vjp_a(me, ot, nv, c1, w, d);
+            ab.rho += d.rho; ab.u[0] += d.u[0]; ab.u[1] += d.u[1]; ab.u[2] += d.u[2];
+            ab.beta += d.beta; ab.lrho += d.lrho; ab.lbeta += d.lbeta; ab.k += d.k;
+          } else {
+            // central average: d/dU_m of 1/2 f(U_m).n
+            const double wh[5] = {0.5 * w[0], 0.5 * w[1], 0.5 * w[2], 0.5 * w[3], 0.5 * w[4]};
+            double Ue[5];
+            euler_flux_vjp(u, q, nv, wh, P.gm1, Ue);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) Ub[v] += Ue[v];
+          }
+        }
+      }
+      if (P.twopoint == 0) {
+        double Ua[5];
+        aux_vjp(q, me, ab, P.gm1, Ua);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Ub[v] += Ua[v];
+      }
+    }
+  }
+  __syncthreads();
+  // surface: adjoint of each side's flux, own trace part into LDS
+  double* sfb = sm;  // [6][NF][n2]
+  for (int ft = t; ft < S::nface; ft += S::nth) {
+    const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
+    const int info = G.efc[e * 6 + f];
+    const int side = efc_side(info), slot = efc_slot(info);
+    int p = pp, qm = qq;
+    if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+    const int fi = qm * n1 + p;
+    double UL[5], UR[5], Phib[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      UL[v] = Utr[tr_index(0, v, 5, nS, side, n2, fi)];
+      UR[v] = Utr[tr_index(1, v, 5, nS, side, n2, fi)];
+      Phib[v] = Lbar[tr_index(0, v, 5, nS, side, n2, fi)] - Lbar[tr_index(1, v, 5, nS, side, n2, fi)];
+    }
+    double gL[12], gR[12];
+    if constexpr (PHYS == 1) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        gL[c] = gtr[tr_index(0, c, 12, nS, side, n2, fi)];
+        gR[c] = gtr[tr_index(1, c, 12, nS, side, n2, fi)];
+      }
+    }
+    const double nh[3] = {G.face[((size_t)0 * nS + side) * n2 + fi], G.face[((size_t)1 * nS + side) * n2 + fi],
+                          G.face[((size_t)2 * nS + side) * n2 + fi]};
+    const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
+    double ULb[5], URb[5], gLb[12], gRb[12];
+    surface_flux_vjp<FORM, PHYS>(UL, UR, gL, gR, nh, s, P, Phib, ULb, URb, gLb, gRb);
+    const double* mine = slot ? URb : ULb;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sfb[(f * NF + v) * n2 + rr] = mine[v];
+    if constexpr (PHYS == 1) {
+      const double* gm = slot ? gRb : gLb;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sfb[(f * NF + 5 + c) * n2 + rr] = gm[c];
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int a = idx[r];
+      const int rr = (r == 2 ? j : k) * n1 + (r == 0 ? j : i);
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const int f = 2 * r + sd;
+        double L;
+        if constexpr (NODES == 1) {
+          if (a != (sd ? N : 0)) continue;
+          L = 1.0;
+        } else {
+          L = sd ? sb.Lp[a] : sb.Lm[a];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Ub[v] += L * sfb[(f * NF + v) * n2 + rr];
+        if constexpr (PHYS == 1) {
+#pragma unroll
+          for (int c = 0; c < 12; ++c) gb[c] += L * sfb[(f * NF + 5 + c) * n2 + rr];
+        }
+      }
+    }
+    if constexpr (PHYS == 1) {
+      double Uu[5];
+      prim_vjp(q, P.gm1, 0.0, ub, 0.0, Uu);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ub[v] += Uu[v];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) gbar[((size_t)c * nE + e) * n3 + t] = gb[c];
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out[((size_t)v * nE + e) * n3 + t] = Ub[v];
+  }
+}
+
+// Lifting adjoint, face part: Qbar[slot][4][side][fi] = sum_a (1/w_a) l_a(+-1) sum_d (sJ gbar)_{q,d} (n s)_d,out.
+template <int N, int NODES>
+__global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_trace(Geo G, const double* __restrict__ gbar,
+                                                                  double* __restrict__ Qbar) {
+  using S = Shape<N>;
+  constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
+  __shared__ double sg[12 * n3];
+  __shared__ DevBasis sb;
+  const int e = blockIdx.x, t = threadIdx.x;
+  const int nE = G.nElems, nS = G.nSides;
+  load_basis(&sb, G.basis, t, S::nth);
+  if (t < n3) {
+    const double sJ = G.sJ[(size_t)e * n3 + t];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sg[c * n3 + t] = sJ * gbar[((size_t)c * nE + e) * n3 + t];
+  }
+  __syncthreads();
+  for (int ft = t; ft < S::nface; ft += S::nth) {
+    const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
+    const int info = G.efc[e * 6 + f];
+    const int side = efc_side(info), slot = efc_slot(info);
+    int p = pp, q = qq;
+    if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
+    const int fi = q * n1 + p;
+    const double sgn = slot ? -1.0 : 1.0;
+    const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
+    double no[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) no[c] = sgn * (G.face[((size_t)c * nS + side) * n2 + fi] * s);
+    double acc[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < n1; ++a) {
+      double L;
+      if constexpr (NODES == 1) {
+        if (a != ((f & 1) ? N : 0)) continue;
+        L = sb.winv[a];
+      } else {
+        L = sb.winv[a] * ((f & 1) ? sb.Lp[a] : sb.Lm[a]);
+      }
+      const int ta = line_node<N>(r, a, pp, qq);
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+        acc[qa] += L * (sg[(3 * qa) * n3 + ta] * no[0] + sg[(3 * qa + 1) * n3 + ta] * no[1] +
+                        sg[(3 * qa + 2) * n3 + ta] * no[2]);
+    }
+#pragma unroll
+    for (int qa = 0; qa < 4; ++qa) Qbar[tr_index(slot, qa, 4, nS, side, n2, fi)] = acc[qa];
+  }
+}
+
+// Lifting adjoint, volume and face parts: out += (dq/dU)^T qbar.
+template <int N, int NODES>
+__global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_volume(Geo G, Phys P, const double* __restrict__ U,
+                                                                   const double* __restrict__ Utr,
+                                                                   const double* __restrict__ gbar,
+                                                                   const double* __restrict__ Qbar,
+                                                                   double* __restrict__ out) {
+  using S = Shape<N>;
+  constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
+  constexpr int SZ = 12 * n3 > 5 * S::nface ? 12 * n3 : 5 * S::nface;
+  __shared__ double sm[SZ];
+  __shared__ DevBasis sb;
+  const int e = blockIdx.x, t = threadIdx.x;
+  const int nE = G.nElems, nS = G.nSides;
+  load_basis(&sb, G.basis, t, S::nth);
+  const bool act = t < n3;
+  const int i = t % n1, j = (t / n1) % n1, k = t / n2;
+  const int idx[3] = {i, j, k};
+  double* sg = sm;
+  if (act) {
+    const double sJ = G.sJ[(size_t)e * n3 + t];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sg[c * n3 + t] = sJ * gbar[((size_t)c * nE + e) * n3 + t];
+  }
+  __syncthreads();
+  double Ub[5] = {0, 0, 0, 0, 0};
+  if (act) {
+    double u[5], ja[9];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ja[c] = G.Ja[((size_t)c * nE + e) * n3 + t];
+    double qb[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int l = idx[r];
+      const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+      double T[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) T[c] = 0.0;
+#pragma unroll
+      for (int a = 0; a < n1; ++a) {
+        const double c = sb.Dhat[a * n1 + l];
+        const int ta = line_node<N>(r, a, pp, qq);
+#pragma unroll
+        for (int cc = 0; cc < 12; ++cc) T[cc] += c * sg[cc * n3 + ta];
+      }
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+        qb[qa] -= ja[3 * r] * T[3 * qa] + ja[3 * r + 1] * T[3 * qa + 1] + ja[3 * r + 2] * T[3 * qa + 2];
+    }
+    const Prim q = cons2prim(u, P.gm1);
+    qvars_vjp(q, P.gm1, P.Rinv, qb, Ub);
+  }
+  __syncthreads();
+  double* sfb = sm;  // [6][5][n2]
+  for (int ft = t; ft < S::nface; ft += S::nth) {
+    const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
+    const int info = G.efc[e * 6 + f];
+    const int side = efc_side(info), slot = efc_slot(info);
+    int p = pp, qm = qq;
+    if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+    const int fi = qm * n1 + p;
+    double Uo[5], qb[4];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Uo[v] = Utr[tr_index(slot, v, 5, nS, side, n2, fi)];
+#pragma unroll
+    for (int qa = 0; qa < 4; ++qa)
+      qb[qa] = 0.5 * (Qbar[tr_index(0, qa, 4, nS, side, n2, fi)] + Qbar[tr_index(1, qa, 4, nS, side, n2, fi)]);
+    double Ut[5];
+    qvars_vjp(cons2prim(Uo, P.gm1), P.gm1, P.Rinv, qb, Ut);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sfb[(f * 5 + v) * n2 + rr] = Ut[v];
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int a = idx[r];
+      const int rr = (r == 2 ? j : k) * n1 + (r == 0 ? j : i);
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const int f = 2 * r + sd;
+        double L;
+        if constexpr (NODES == 1) {
+          if (a != (sd ? N : 0)) continue;
+          L = 1.0;
+        } else {
+          L = sd ? sb.Lp[a] : sb.Lm[a];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Ub[v] += L * sfb[(f * 5 + v) * n2 + rr];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out[((size_t)v * nE + e) * n3 + t] += Ub[v];
+  }
+}
+
+}  // namespace dgx

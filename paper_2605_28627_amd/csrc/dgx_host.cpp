@@ -513,6 +513,9 @@ dg_status dg_sizes(const dg_ctx* cc, int* nElems, int* nSides, int* npe, size_t*
 // ---------------------------------------------------------------------------
 struct WsLayout {
   size_t utr[2], gtr, g, red, flag, total;
+  // adjoint region: recomputed stage states Y_1..Y_4, forward RK register,
+  // adjoint residual, gradient adjoint (Navier-Stokes)
+  size_t Y[4], dUf, aout, gbar, total_adjoint;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -528,6 +531,12 @@ static WsLayout ws_layout(const dg_ctx* c) {
   L.red = off; off += align256((size_t)(2 * reduction_blocks() + 8) * sizeof(double));
   L.flag = off; off += 256;
   L.total = off;
+  const size_t st = align256(5 * nv * sizeof(double));
+  for (int k = 0; k < 4; ++k) { L.Y[k] = off; off += st; }
+  L.dUf = off; off += st;
+  L.aout = off; off += st;
+  L.gbar = off; off += ns ? align256(12 * nv * sizeof(double)) : 0;
+  L.total_adjoint = off;
   return L;
 }
 
@@ -536,12 +545,18 @@ size_t dg_workspace_bytes(const dg_ctx* c) {
   return ws_layout(c).total;
 }
 
+size_t dg_workspace_bytes_adjoint(const dg_ctx* c) {
+  if (!c || !c->mesh_set) return 0;
+  return ws_layout(c).total_adjoint;
+}
+
 dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes) {
   if (!c) return fail(nullptr, DG_ERR_ARG, "dg_bind_workspace: null context");
   if (!c->mesh_set) return fail(c, DG_ERR_STATE, "dg_bind_workspace: no mesh");
   if (!dev_ptr) return fail(c, DG_ERR_ARG, "dg_bind_workspace: null pointer");
   if (((uintptr_t)dev_ptr & 255) != 0) return fail(c, DG_ERR_ARG, "dg_bind_workspace: pointer not 256-byte aligned");
   if (bytes < ws_layout(c).total) return fail(c, DG_ERR_ARG, "dg_bind_workspace: workspace too small");
+  // a workspace of at least dg_workspace_bytes_adjoint also enables the adjoint calls
   c->ws = (char*)dev_ptr;
   c->ws_bytes = bytes;
   return DG_OK;
@@ -663,15 +678,89 @@ dg_status dg_rk_step(dg_ctx* c, double* U, double* dU, double t, double dt, int 
   return DG_OK;
 }
 
+static dg_status ready_adjoint(dg_ctx* c, const char* who) {
+  dg_status st = ready(c, who);
+  if (st != DG_OK) return st;
+  if (c->cfg.precision != DG_PREC_FP64) return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": FP64 contexts only");
+  if (c->ws_bytes < ws_layout(c).total_adjoint)
+    return fail(c, DG_ERR_STATE, std::string(who) + ": bound workspace is smaller than dg_workspace_bytes_adjoint");
+  return DG_OK;
+}
+
+// out = (dR/dU(U))^T lam, with the forward traces (and gradients) of U recomputed.
+static dg_status adjoint_residual(dg_ctx* c, const double* U, const double* lam, double* out, hipStream_t s) {
+  Cfg k = kcfg(c);
+  Geo g = kgeo(c);
+  Work w = kwork(c);
+  WsLayout L = ws_layout(c);
+  double* gbar = k.physics == DG_PHYS_NAVIER_STOKES ? (double*)(c->ws + L.gbar) : nullptr;
+  {
+    ProfScope ps(c, FAM_TRACE, s);
+    LAUNCHCHK(c, launch_trace(k, g, U, w.Utr[0], s));
+  }
+  if (k.physics == DG_PHYS_NAVIER_STOKES) {
+    ProfScope ps(c, FAM_LIFT, s);
+    LAUNCHCHK(c, launch_lift(k, g, c->phys, U, w.Utr[0], w.g, w.gtr, s));
+  }
+  ProfScope ps(c, FAM_ADJOINT, s);
+  LAUNCHCHK(c, launch_adjoint(k, g, c->phys, U, lam, w.Utr[0], w.Utr[1], w.g, w.gtr, out, gbar, s));
+  return DG_OK;
+}
+
 dg_status dg_adjoint_rhs(dg_ctx* c, const double* U, const double* lam, double* out, void* stream) {
-  (void)U; (void)lam; (void)out; (void)stream;
-  return fail(c, DG_ERR_UNSUPPORTED, "dg_adjoint_rhs: not built yet");
+  dg_status st = ready_adjoint(c, "dg_adjoint_rhs");
+  if (st != DG_OK) return st;
+  if (!U || !lam || !out) return fail(c, DG_ERR_ARG, "dg_adjoint_rhs: null pointer");
+  if (out == U || out == lam) return fail(c, DG_ERR_ARG, "dg_adjoint_rhs: out aliases an input");
+  return adjoint_residual(c, U, lam, out, (hipStream_t)stream);
 }
 
 dg_status dg_adjoint_rk_step(dg_ctx* c, const double* Un, double* lamU, double* lamdU, double t, double dt,
                              void* stream) {
-  (void)Un; (void)lamU; (void)lamdU; (void)t; (void)dt; (void)stream;
-  return fail(c, DG_ERR_UNSUPPORTED, "dg_adjoint_rk_step: not built yet");
+  dg_status st = ready_adjoint(c, "dg_adjoint_rk_step");
+  if (st != DG_OK) return st;
+  if (!Un || !lamU || !lamdU) return fail(c, DG_ERR_ARG, "dg_adjoint_rk_step: null pointer");
+  if (lamU == lamdU || Un == lamU || Un == lamdU) return fail(c, DG_ERR_ARG, "dg_adjoint_rk_step: aliasing arrays");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, DG_ERR_ARG, "dg_adjoint_rk_step: dt");
+  (void)t;
+  hipStream_t s = (hipStream_t)stream;
+  double A[5], B[5], C[5];
+  dg_lserk_coefficients(A, B, C);
+  WsLayout L = ws_layout(c);
+  Work w = kwork(c);
+  const size_t n = (size_t)5 * c->nElems * c->n3;
+  const double* Y[5];
+  Y[0] = Un;
+  for (int k = 0; k < 4; ++k) Y[k + 1] = (const double*)(c->ws + L.Y[k]);
+  double* dUf = (double*)(c->ws + L.dUf);
+  double* aout = (double*)(c->ws + L.aout);
+  // recompute the stage inputs Y_1..Y_4 of this step
+  {
+    ProfScope ps(c, FAM_OTHER, s);
+    LAUNCHCHK(c, launch_fill(dUf, n, 0.0, s));
+  }
+  {
+    ProfScope ps(c, FAM_TRACE, s);
+    LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), Un, w.Utr[0], s));
+  }
+  int cur = 0;
+  for (int k = 0; k < 4; ++k) {
+    st = stage(c, 1, Y[k], nullptr, const_cast<double*>(Y[k + 1]), dUf, cur, A[k], B[k], dt, s);
+    if (st != DG_OK) return st;
+    cur ^= 1;
+  }
+  // reverse sweep: lamdU = B_4 lamU; per stage s: lamU += dt J(Y_s)^T lamdU; lamdU = A_s lamdU + B_{s-1} lamU
+  {
+    ProfScope ps(c, FAM_OTHER, s);
+    LAUNCHCHK(c, launch_scale_copy(n, lamU, lamdU, B[4], s));
+  }
+  for (int k = 4; k >= 0; --k) {
+    st = adjoint_residual(c, Y[k], lamdU, aout, s);
+    if (st != DG_OK) return st;
+    ProfScope ps(c, FAM_OTHER, s);
+    LAUNCHCHK(c, launch_adj_rk_update(n, aout, lamU, lamdU, dt, A[k], k > 0 ? B[k - 1] : 0.0, s));
+  }
+  return DG_OK;
 }
 
 dg_status dg_kinetic_energy(dg_ctx* c, const double* U, double rho0U0sq, double* out_dev, void* stream) {

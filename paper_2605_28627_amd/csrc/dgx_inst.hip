@@ -1,6 +1,7 @@
 // dgx_inst.hip -- launchers of the residual kernels for one polynomial degree.
 // Compiled once per degree with -DDGX_INST_N=<N>; the launchers are named
 // launch_*_N<N> and dispatched at run time by dgx_launch.hip.
+#include "dgx_adjoint.hpp"
 #include "dgx_kernels.hpp"
 
 #ifndef DGX_INST_N
@@ -69,6 +70,39 @@ hipError_t DGX_NAME(launch_volume)(const Cfg& c, const Geo& g, const Phys& p, in
     vol_phys<1, 0>(c, mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
   else
     vol_phys<1, 1>(c, mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  return hipGetLastError();
+}
+
+hipError_t DGX_NAME(launch_adjoint)(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* lam,
+                                    const double* Utr, double* Lbar, const double* gin, double* gtr, double* out,
+                                    double* gbar, hipStream_t s) {
+  const dim3 grid(g.nElems), block(Shape<kN>::nth);
+  // per-element surface adjoints
+  if (c.nodes == 1)
+    hipLaunchKernelGGL((k_adj_trace<kN, 1>), grid, block, 0, s, g, lam, Lbar);
+  else
+    hipLaunchKernelGGL((k_adj_trace<kN, 0>), grid, block, 0, s, g, lam, Lbar);
+  // volume + surface adjoint
+#define DGX_ADJ(NODES, FORM, PHYS) \
+  hipLaunchKernelGGL((k_adj_volume<kN, NODES, FORM, PHYS>), grid, block, 0, s, g, p, U, lam, Utr, Lbar, gin, gtr, out, gbar)
+  if (c.nodes == 0) {
+    if (c.physics == 0) DGX_ADJ(0, 0, 0); else DGX_ADJ(0, 0, 1);
+  } else if (c.form == 0) {
+    if (c.physics == 0) DGX_ADJ(1, 0, 0); else DGX_ADJ(1, 0, 1);
+  } else {
+    if (c.physics == 0) DGX_ADJ(1, 1, 0); else DGX_ADJ(1, 1, 1);
+  }
+#undef DGX_ADJ
+  if (c.physics == 1) {
+    // lifting adjoint; gtr has been consumed and now holds Qbar
+    if (c.nodes == 1) {
+      hipLaunchKernelGGL((k_adj_lift_trace<kN, 1>), grid, block, 0, s, g, gbar, gtr);
+      hipLaunchKernelGGL((k_adj_lift_volume<kN, 1>), grid, block, 0, s, g, p, U, Utr, gbar, gtr, out);
+    } else {
+      hipLaunchKernelGGL((k_adj_lift_trace<kN, 0>), grid, block, 0, s, g, gbar, gtr);
+      hipLaunchKernelGGL((k_adj_lift_volume<kN, 0>), grid, block, 0, s, g, p, U, Utr, gbar, gtr, out);
+    }
+  }
   return hipGetLastError();
 }
 

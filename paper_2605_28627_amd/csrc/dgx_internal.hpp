@@ -77,6 +77,14 @@ hipError_t launch_volume(const Cfg& c, const Geo& g, const Phys& p, int mode, co
                          const double* gin, const double* gtr, double* Ut, double* Uio, double* dU, double* Utr_next,
                          double A, double B, double dt, hipStream_t s);
 
+// out = (dR/dU)^T lam; Utr holds the traces of U, Lbar/gtr/gbar are scratch
+// (Navier-Stokes: gin/gtr hold the forward lifted gradients and their traces).
+hipError_t launch_adjoint(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* lam,
+                          const double* Utr, double* Lbar, const double* gin, double* gtr, double* out, double* gbar,
+                          hipStream_t s);
+hipError_t launch_adj_rk_update(size_t n, const double* out, double* lamU, double* lamdU, double dt, double A,
+                                double Bnext, hipStream_t s);
+hipError_t launch_scale_copy(size_t n, const double* x, double* y, double a, hipStream_t s);
 hipError_t launch_fill(double* x, size_t n, double v, hipStream_t s);
 hipError_t launch_fill_int(int* x, size_t n, int v, hipStream_t s);
 hipError_t launch_kinetic_energy(const Cfg& c, const Geo& g, const double* U, double* partial, double* out,

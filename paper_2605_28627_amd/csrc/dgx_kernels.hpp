@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dgx_internal.hpp"
+#include "dgx_pointwise.hpp"
 
 namespace dgx {
 
@@ -48,185 +49,6 @@ __device__ __forceinline__ void load_basis(DevBasis* dst, const DevBasis* src, i
 
 __device__ __forceinline__ size_t tr_index(int slot, int v, int nvar, int nSides, int side, int n2, int fi) {
   return (((size_t)slot * nvar + v) * nSides + side) * n2 + fi;
-}
-
-// ---------------------------------------------------------------------------
-// Point physics.  FT is the flux arithmetic type (double, or float in the
-// FP32-flux mode); states, metrics and all accumulations are double.
-// ---------------------------------------------------------------------------
-struct Prim {
-  double rho, u[3], p;
-};
-
-__device__ __forceinline__ Prim cons2prim(const double U[5], double gm1) {
-  Prim q;
-  q.rho = U[0];
-  const double ri = 1.0 / U[0];
-  q.u[0] = U[1] * ri; q.u[1] = U[2] * ri; q.u[2] = U[3] * ri;
-  q.p = gm1 * (U[4] - 0.5 * q.rho * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]));
-  return q;
-}
-
-// Logarithmic mean (x - y)/(ln x - ln y) from precomputed logarithms; the
-// atanh series (x+y)/(2 + u(2/3 + u(2/5 + u 2/7))), u = ((x-y)/(x+y))^2, below
-// the threshold (1e-4 in double; 1e-2 in float where the truncation u^4/9 is
-// below the float rounding).
-template <typename FT>
-__device__ __forceinline__ FT log_mean(FT x, FT y, FT lx, FT ly) {
-  const FT thr = sizeof(FT) == 8 ? FT(1e-4) : FT(1e-2);
-  FT f = (x - y) / (x + y);
-  FT u = f * f;
-  if (u < thr) return (x + y) / (FT(2) + u * (FT(2.0 / 3.0) + u * (FT(2.0 / 5.0) + u * FT(2.0 / 7.0))));
-  return (x - y) / (lx - ly);
-}
-// Reciprocal of the logarithmic mean.
-template <typename FT>
-__device__ __forceinline__ FT inv_log_mean(FT x, FT y, FT lx, FT ly) {
-  const FT thr = sizeof(FT) == 8 ? FT(1e-4) : FT(1e-2);
-  FT f = (x - y) / (x + y);
-  FT u = f * f;
-  if (u < thr) return (FT(2) + u * (FT(2.0 / 3.0) + u * (FT(2.0 / 5.0) + u * FT(2.0 / 7.0)))) / (x + y);
-  return (lx - ly) / (x - y);
-}
-
-// Per-node data a two-point flux needs from a partner node.
-struct Aux {
-  double rho, u[3], beta, lrho, lbeta, k;   // k = |u|^2
-};
-
-// Chandrashekar's kinetic-energy-preserving, entropy-conservative flux in the
-// direction n (not normalised): F_rho = rho^ln {u}.n, F_m = p_hat n + {u} F_rho,
-// F_E = F_rho (1/(2 (gamma-1) beta^ln) - {|u|^2}/2) + {u}.F_m.
-template <typename FT>
-__device__ __forceinline__ void chandrashekar(const Aux& a, const Aux& b, const double n[3], double c1, double F[5]) {
-  const FT rho_ln = log_mean<FT>(FT(a.rho), FT(b.rho), FT(a.lrho), FT(b.lrho));
-  const FT ibeta_ln = inv_log_mean<FT>(FT(a.beta), FT(b.beta), FT(a.lbeta), FT(b.lbeta));
-  const FT phat = FT(0.5) * (FT(a.rho) + FT(b.rho)) / (FT(a.beta) + FT(b.beta));
-  const FT X = ibeta_ln * FT(c1) - FT(0.25) * (FT(a.k) + FT(b.k));
-  const double um0 = 0.5 * (a.u[0] + b.u[0]), um1 = 0.5 * (a.u[1] + b.u[1]), um2 = 0.5 * (a.u[2] + b.u[2]);
-  const double umn = um0 * n[0] + um1 * n[1] + um2 * n[2];
-  const double Fr = double(rho_ln) * umn;
-  const double ph = double(phat);
-  F[0] = Fr;
-  F[1] = ph * n[0] + um0 * Fr;
-  F[2] = ph * n[1] + um1 * Fr;
-  F[3] = ph * n[2] + um2 * Fr;
-  F[4] = Fr * double(X) + (um0 * F[1] + um1 * F[2] + um2 * F[3]);
-}
-
-__device__ __forceinline__ Aux make_aux(const Prim& q) {
-  Aux a;
-  a.rho = q.rho; a.u[0] = q.u[0]; a.u[1] = q.u[1]; a.u[2] = q.u[2];
-  a.beta = 0.5 * q.rho / q.p;
-  a.lrho = log(q.rho);
-  a.lbeta = log(a.beta);
-  a.k = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
-  return a;
-}
-
-// Advective flux of U in direction n (not normalised).
-template <typename FT>
-__device__ __forceinline__ void euler_flux(const double U[5], const Prim& q, const double n[3], double F[5]) {
-  if constexpr (sizeof(FT) == 8) {
-    const double un = q.u[0] * n[0] + q.u[1] * n[1] + q.u[2] * n[2];
-    F[0] = U[0] * un;
-    F[1] = U[1] * un + q.p * n[0];
-    F[2] = U[2] * un + q.p * n[1];
-    F[3] = U[3] * un + q.p * n[2];
-    F[4] = (U[4] + q.p) * un;
-  } else {
-    // Cartesian flux components in float, contraction with the metric in double.
-    const float r = float(q.rho), u0 = float(q.u[0]), u1 = float(q.u[1]), u2 = float(q.u[2]), p = float(q.p);
-    const float H = float(U[4]) + p;
-    const float uu[3] = {u0, u1, u2};
-    double acc[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const float ud = uu[d];
-      const float ru = r * ud;
-      acc[0] += n[d] * double(ru);
-      acc[1] += n[d] * double(ru * u0 + (d == 0 ? p : 0.0f));
-      acc[2] += n[d] * double(ru * u1 + (d == 1 ? p : 0.0f));
-      acc[3] += n[d] * double(ru * u2 + (d == 2 ? p : 0.0f));
-      acc[4] += n[d] * double(H * ud);
-    }
-    for (int v = 0; v < 5; ++v) F[v] = acc[v];
-  }
-}
-
-// Viscous flux G_d (d = 0..2) for the momentum and energy components (v = 1..4),
-// contracted with n: Gn[v-1] = sum_d n_d G_d[v].  g[3a+d] = dq_a/dx_d, q = (u,v,w,T).
-template <typename FT>
-__device__ __forceinline__ void viscous_flux(const Prim& q, const double g[12], const Phys& P, const double n[3],
-                                             double Gn[4]) {
-  const FT mu = FT(P.mu), lam = FT(P.lam);
-  FT gg[12];
-#pragma unroll
-  for (int c = 0; c < 12; ++c) gg[c] = FT(g[c]);
-  const FT divu = gg[0] + gg[4] + gg[8];
-  FT tau[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) tau[a][d] = mu * (gg[3 * a + d] + gg[3 * d + a]);
-  const FT t2 = FT(2.0 / 3.0) * mu * divu;
-  tau[0][0] -= t2; tau[1][1] -= t2; tau[2][2] -= t2;
-  const FT u0 = FT(q.u[0]), u1 = FT(q.u[1]), u2 = FT(q.u[2]);
-  double acc[4] = {0, 0, 0, 0};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    acc[0] += n[d] * double(tau[0][d]);
-    acc[1] += n[d] * double(tau[1][d]);
-    acc[2] += n[d] * double(tau[2][d]);
-    acc[3] += n[d] * double(tau[d][0] * u0 + tau[d][1] * u1 + tau[d][2] * u2 + lam * gg[9 + d]);
-  }
-  Gn[0] = acc[0]; Gn[1] = acc[1]; Gn[2] = acc[2]; Gn[3] = acc[3];
-}
-
-// Outward (master) surface flux at one face node:
-// Phi = [F*(UL,UR).n - lambda_max/2 (UR-UL)] s - 1/2 (G(UL,gL) + G(UR,gR)).n s
-template <typename FT, int FORM, int PHYS>
-__device__ __forceinline__ void surface_flux(const double UL[5], const double UR[5], const double* gL,
-                                             const double* gR, const double nh[3], double s, const Phys& P,
-                                             double Phi[5]) {
-  const Prim qL = cons2prim(UL, P.gm1), qR = cons2prim(UR, P.gm1);
-  const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
-  if constexpr (FORM == 0) {
-    double FL[5], FR[5];
-    euler_flux<FT>(UL, qL, nv, FL);
-    euler_flux<FT>(UR, qR, nv, FR);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) Phi[v] = 0.5 * (FL[v] + FR[v]);
-  } else {
-    if (P.twopoint == 0) {
-      const Aux aL = make_aux(qL), aR = make_aux(qR);
-      chandrashekar<FT>(aL, aR, nv, 0.5 / P.gm1, Phi);
-    } else {
-      double FL[5], FR[5];
-      euler_flux<FT>(UL, qL, nv, FL);
-      euler_flux<FT>(UR, qR, nv, FR);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) Phi[v] = 0.5 * (FL[v] + FR[v]);
-    }
-  }
-  if (P.riemann == 0) {
-    const FT cL = sqrt(FT(P.gamma) * FT(qL.p) / FT(qL.rho));
-    const FT cR = sqrt(FT(P.gamma) * FT(qR.p) / FT(qR.rho));
-    const FT unL = FT(qL.u[0] * nh[0] + qL.u[1] * nh[1] + qL.u[2] * nh[2]);
-    const FT unR = FT(qR.u[0] * nh[0] + qR.u[1] * nh[1] + qR.u[2] * nh[2]);
-    const FT lL = fabs(unL) + cL, lR = fabs(unR) + cR;
-    const double lmax = double(lL >= lR ? lL : lR);
-    const double hs = 0.5 * (lmax * s);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) Phi[v] -= hs * (UR[v] - UL[v]);
-  }
-  if constexpr (PHYS == 1) {
-    double GL[4], GR[4];
-    viscous_flux<FT>(qL, gL, P, nv, GL);
-    viscous_flux<FT>(qR, gR, P, nv, GR);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Phi[1 + v] -= 0.5 * (GL[v] + GR[v]);
-  }
 }
 
 // ---------------------------------------------------------------------------

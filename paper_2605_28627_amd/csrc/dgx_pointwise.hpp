@@ -1,0 +1,419 @@
+// dgx_pointwise.hpp -- point physics of the DGSEM residual and its adjoint
+// (host and device): conservative -> primitive, the advective, two-point,
+// Rusanov and viscous fluxes, and their vector-Jacobian products.
+//
+// FT is the flux arithmetic type (double, or float in the FP32-flux mode);
+// states, metrics and all accumulations are double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <type_traits>
+
+#include "dgx_internal.hpp"
+
+namespace dgx {
+
+// ---------------------------------------------------------------------------
+// Point physics.  FT is the flux arithmetic type (double, or float in the
+// FP32-flux mode); states, metrics and all accumulations are double.
+// ---------------------------------------------------------------------------
+struct Prim {
+  double rho, u[3], p;
+};
+
+__host__ __device__ inline Prim cons2prim(const double U[5], double gm1) {
+  Prim q;
+  q.rho = U[0];
+  const double ri = 1.0 / U[0];
+  q.u[0] = U[1] * ri; q.u[1] = U[2] * ri; q.u[2] = U[3] * ri;
+  q.p = gm1 * (U[4] - 0.5 * q.rho * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]));
+  return q;
+}
+
+// Logarithmic mean (x - y)/(ln x - ln y) from precomputed logarithms; the
+// atanh series (x+y)/(2 + u(2/3 + u(2/5 + u 2/7))), u = ((x-y)/(x+y))^2, below
+// the threshold (1e-4 in double; 1e-2 in float where the truncation u^4/9 is
+// below the float rounding).
+template <typename FT>
+__host__ __device__ inline FT log_mean(FT x, FT y, FT lx, FT ly) {
+  const FT thr = sizeof(FT) == 8 ? FT(1e-4) : FT(1e-2);
+  FT f = (x - y) / (x + y);
+  FT u = f * f;
+  if (u < thr) return (x + y) / (FT(2) + u * (FT(2.0 / 3.0) + u * (FT(2.0 / 5.0) + u * FT(2.0 / 7.0))));
+  return (x - y) / (lx - ly);
+}
+// Reciprocal of the logarithmic mean.
+template <typename FT>
+__host__ __device__ inline FT inv_log_mean(FT x, FT y, FT lx, FT ly) {
+  const FT thr = sizeof(FT) == 8 ? FT(1e-4) : FT(1e-2);
+  FT f = (x - y) / (x + y);
+  FT u = f * f;
+  if (u < thr) return (FT(2) + u * (FT(2.0 / 3.0) + u * (FT(2.0 / 5.0) + u * FT(2.0 / 7.0)))) / (x + y);
+  return (lx - ly) / (x - y);
+}
+
+// Per-node data a two-point flux needs from a partner node.
+struct Aux {
+  double rho, u[3], beta, lrho, lbeta, k;   // k = |u|^2
+};
+
+// Chandrashekar's kinetic-energy-preserving, entropy-conservative flux in the
+// direction n (not normalised): F_rho = rho^ln {u}.n, F_m = p_hat n + {u} F_rho,
+// F_E = F_rho (1/(2 (gamma-1) beta^ln) - {|u|^2}/2) + {u}.F_m.
+template <typename FT>
+__host__ __device__ inline void chandrashekar(const Aux& a, const Aux& b, const double n[3], double c1, double F[5]) {
+  const FT rho_ln = log_mean<FT>(FT(a.rho), FT(b.rho), FT(a.lrho), FT(b.lrho));
+  const FT ibeta_ln = inv_log_mean<FT>(FT(a.beta), FT(b.beta), FT(a.lbeta), FT(b.lbeta));
+  const FT phat = FT(0.5) * (FT(a.rho) + FT(b.rho)) / (FT(a.beta) + FT(b.beta));
+  const FT X = ibeta_ln * FT(c1) - FT(0.25) * (FT(a.k) + FT(b.k));
+  const double um0 = 0.5 * (a.u[0] + b.u[0]), um1 = 0.5 * (a.u[1] + b.u[1]), um2 = 0.5 * (a.u[2] + b.u[2]);
+  const double umn = um0 * n[0] + um1 * n[1] + um2 * n[2];
+  const double Fr = double(rho_ln) * umn;
+  const double ph = double(phat);
+  F[0] = Fr;
+  F[1] = ph * n[0] + um0 * Fr;
+  F[2] = ph * n[1] + um1 * Fr;
+  F[3] = ph * n[2] + um2 * Fr;
+  F[4] = Fr * double(X) + (um0 * F[1] + um1 * F[2] + um2 * F[3]);
+}
+
+__host__ __device__ inline Aux make_aux(const Prim& q) {
+  Aux a;
+  a.rho = q.rho; a.u[0] = q.u[0]; a.u[1] = q.u[1]; a.u[2] = q.u[2];
+  a.beta = 0.5 * q.rho / q.p;
+  a.lrho = log(q.rho);
+  a.lbeta = log(a.beta);
+  a.k = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+  return a;
+}
+
+// Advective flux of U in direction n (not normalised).
+template <typename FT>
+__host__ __device__ inline void euler_flux(const double U[5], const Prim& q, const double n[3], double F[5]) {
+  if constexpr (sizeof(FT) == 8) {
+    const double un = q.u[0] * n[0] + q.u[1] * n[1] + q.u[2] * n[2];
+    F[0] = U[0] * un;
+    F[1] = U[1] * un + q.p * n[0];
+    F[2] = U[2] * un + q.p * n[1];
+    F[3] = U[3] * un + q.p * n[2];
+    F[4] = (U[4] + q.p) * un;
+  } else {
+    // Cartesian flux components in float, contraction with the metric in double.
+    const float r = float(q.rho), u0 = float(q.u[0]), u1 = float(q.u[1]), u2 = float(q.u[2]), p = float(q.p);
+    const float H = float(U[4]) + p;
+    const float uu[3] = {u0, u1, u2};
+    double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float ud = uu[d];
+      const float ru = r * ud;
+      acc[0] += n[d] * double(ru);
+      acc[1] += n[d] * double(ru * u0 + (d == 0 ? p : 0.0f));
+      acc[2] += n[d] * double(ru * u1 + (d == 1 ? p : 0.0f));
+      acc[3] += n[d] * double(ru * u2 + (d == 2 ? p : 0.0f));
+      acc[4] += n[d] * double(H * ud);
+    }
+    for (int v = 0; v < 5; ++v) F[v] = acc[v];
+  }
+}
+
+// Viscous flux G_d (d = 0..2) for the momentum and energy components (v = 1..4),
+// contracted with n: Gn[v-1] = sum_d n_d G_d[v].  g[3a+d] = dq_a/dx_d, q = (u,v,w,T).
+template <typename FT>
+__host__ __device__ inline void viscous_flux(const Prim& q, const double g[12], const Phys& P, const double n[3],
+                                             double Gn[4]) {
+  const FT mu = FT(P.mu), lam = FT(P.lam);
+  FT gg[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) gg[c] = FT(g[c]);
+  const FT divu = gg[0] + gg[4] + gg[8];
+  FT tau[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) tau[a][d] = mu * (gg[3 * a + d] + gg[3 * d + a]);
+  const FT t2 = FT(2.0 / 3.0) * mu * divu;
+  tau[0][0] -= t2; tau[1][1] -= t2; tau[2][2] -= t2;
+  const FT u0 = FT(q.u[0]), u1 = FT(q.u[1]), u2 = FT(q.u[2]);
+  double acc[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    acc[0] += n[d] * double(tau[0][d]);
+    acc[1] += n[d] * double(tau[1][d]);
+    acc[2] += n[d] * double(tau[2][d]);
+    acc[3] += n[d] * double(tau[d][0] * u0 + tau[d][1] * u1 + tau[d][2] * u2 + lam * gg[9 + d]);
+  }
+  Gn[0] = acc[0]; Gn[1] = acc[1]; Gn[2] = acc[2]; Gn[3] = acc[3];
+}
+
+// Outward (master) surface flux at one face node:
+// Phi = [F*(UL,UR).n - lambda_max/2 (UR-UL)] s - 1/2 (G(UL,gL) + G(UR,gR)).n s
+template <typename FT, int FORM, int PHYS>
+__host__ __device__ inline void surface_flux(const double UL[5], const double UR[5], const double* gL,
+                                             const double* gR, const double nh[3], double s, const Phys& P,
+                                             double Phi[5]) {
+  const Prim qL = cons2prim(UL, P.gm1), qR = cons2prim(UR, P.gm1);
+  const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
+  if constexpr (FORM == 0) {
+    double FL[5], FR[5];
+    euler_flux<FT>(UL, qL, nv, FL);
+    euler_flux<FT>(UR, qR, nv, FR);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Phi[v] = 0.5 * (FL[v] + FR[v]);
+  } else {
+    if (P.twopoint == 0) {
+      const Aux aL = make_aux(qL), aR = make_aux(qR);
+      chandrashekar<FT>(aL, aR, nv, 0.5 / P.gm1, Phi);
+    } else {
+      double FL[5], FR[5];
+      euler_flux<FT>(UL, qL, nv, FL);
+      euler_flux<FT>(UR, qR, nv, FR);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Phi[v] = 0.5 * (FL[v] + FR[v]);
+    }
+  }
+  if (P.riemann == 0) {
+    const FT cL = sqrt(FT(P.gamma) * FT(qL.p) / FT(qL.rho));
+    const FT cR = sqrt(FT(P.gamma) * FT(qR.p) / FT(qR.rho));
+    const FT unL = FT(qL.u[0] * nh[0] + qL.u[1] * nh[1] + qL.u[2] * nh[2]);
+    const FT unR = FT(qR.u[0] * nh[0] + qR.u[1] * nh[1] + qR.u[2] * nh[2]);
+    const FT lL = fabs(unL) + cL, lR = fabs(unR) + cR;
+    const double lmax = double(lL >= lR ? lL : lR);
+    const double hs = 0.5 * (lmax * s);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Phi[v] -= hs * (UR[v] - UL[v]);
+  }
+  if constexpr (PHYS == 1) {
+    double GL[4], GR[4];
+    viscous_flux<FT>(qL, gL, P, nv, GL);
+    viscous_flux<FT>(qR, gR, P, nv, GR);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Phi[1 + v] -= 0.5 * (GL[v] + GR[v]);
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Vector-Jacobian products (reverse mode, FP64).  Each function returns
+// (d(w . f)/d input) for the forward function f of the same name above, with
+// the branch taken by the forward evaluation (log-mean series/direct, the
+// larger Rusanov wave speed, the sign of u.n with +1 at 0).
+// ---------------------------------------------------------------------------
+
+// (rho, u, p) -> U: adjoints rb, ub[3], pb of the primitive variables.
+__host__ __device__ inline void prim_vjp(const Prim& q, double gm1, double rb, const double ub[3], double pb,
+                                         double Ub[5]) {
+  const double ri = 1.0 / q.rho;
+  const double k = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+  Ub[4] = gm1 * pb;
+  Ub[1] = ub[0] * ri - gm1 * pb * q.u[0];
+  Ub[2] = ub[1] * ri - gm1 * pb * q.u[1];
+  Ub[3] = ub[2] * ri - gm1 * pb * q.u[2];
+  Ub[0] = rb - (ub[0] * q.u[0] + ub[1] * q.u[1] + ub[2] * q.u[2]) * ri + 0.5 * gm1 * pb * k;
+}
+
+// Adjoint of the lifted variables q = (u, v, w, T = p/(rho R)).
+__host__ __device__ inline void qvars_vjp(const Prim& q, double gm1, double Rinv, const double qb[4], double Ub[5]) {
+  const double ri = 1.0 / q.rho;
+  const double T = q.p * ri * Rinv;
+  const double pb = qb[3] * ri * Rinv;
+  const double rb = -qb[3] * T * ri;
+  prim_vjp(q, gm1, rb, qb, pb, Ub);
+}
+
+// Adjoint of Aux = (rho, u, beta = rho/(2p), ln rho, ln beta, |u|^2).
+struct AuxBar {
+  double rho, u[3], beta, lrho, lbeta, k;
+};
+
+__host__ __device__ inline void aux_vjp(const Prim& q, const Aux& a, const AuxBar& b, double gm1, double Ub[5]) {
+  const double betab = b.beta + b.lbeta / a.beta;
+  double rb = b.rho + b.lrho / a.rho + betab * 0.5 / q.p;
+  const double pb = -betab * a.beta / q.p;
+  const double ub[3] = {b.u[0] + 2.0 * q.u[0] * b.k, b.u[1] + 2.0 * q.u[1] * b.k, b.u[2] + 2.0 * q.u[2] * b.k};
+  prim_vjp(q, gm1, rb, ub, pb, Ub);
+}
+
+// d/dx and d/dlx of the logarithmic mean (same branch as the forward).
+__host__ __device__ inline void log_mean_grad(double x, double y, double lx, double ly, double& dx, double& dlx) {
+  const double f = (x - y) / (x + y);
+  const double u = f * f;
+  if (u < 1e-4) {
+    const double P = 2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0)));
+    const double dP = 2.0 / 3.0 + u * (4.0 / 5.0 + u * (6.0 / 7.0));
+    const double s = x + y;
+    const double du = 2.0 * f * (2.0 * y / (s * s));
+    dx = 1.0 / P - s / (P * P) * dP * du;
+    dlx = 0.0;
+  } else {
+    const double dl = lx - ly;
+    dx = 1.0 / dl;
+    dlx = -((x - y) / dl) / dl;
+  }
+}
+// d/dx and d/dlx of the reciprocal logarithmic mean.
+__host__ __device__ inline void inv_log_mean_grad(double x, double y, double lx, double ly, double& dx, double& dlx) {
+  const double f = (x - y) / (x + y);
+  const double u = f * f;
+  if (u < 1e-4) {
+    const double P = 2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0)));
+    const double dP = 2.0 / 3.0 + u * (4.0 / 5.0 + u * (6.0 / 7.0));
+    const double s = x + y;
+    const double du = 2.0 * f * (2.0 * y / (s * s));
+    dx = dP * du / s - P / (s * s);
+    dlx = 0.0;
+  } else {
+    const double d = x - y;
+    dx = -((lx - ly) / d) / d;
+    dlx = 1.0 / d;
+  }
+}
+
+// d(w . F#(a, b; n))/d aux_a for Chandrashekar's flux (FP64 forward).
+__host__ __device__ inline void chandrashekar_vjp_a(const Aux& a, const Aux& b, const double n[3], double c1,
+                                                    const double w[5], AuxBar& ab) {
+  const double rho_ln = log_mean<double>(a.rho, b.rho, a.lrho, b.lrho);
+  const double ibl = inv_log_mean<double>(a.beta, b.beta, a.lbeta, b.lbeta);
+  const double S = a.beta + b.beta;
+  const double phat = 0.5 * (a.rho + b.rho) / S;
+  const double X = ibl * c1 - 0.25 * (a.k + b.k);
+  const double um[3] = {0.5 * (a.u[0] + b.u[0]), 0.5 * (a.u[1] + b.u[1]), 0.5 * (a.u[2] + b.u[2])};
+  const double umn = um[0] * n[0] + um[1] * n[1] + um[2] * n[2];
+  const double Fr = rho_ln * umn;
+  double Fm[3];
+  for (int d = 0; d < 3; ++d) Fm[d] = phat * n[d] + um[d] * Fr;
+  // reverse sweep
+  double Fmb[3];
+  for (int d = 0; d < 3; ++d) Fmb[d] = w[1 + d] + w[4] * um[d];
+  const double Frb = w[0] + w[4] * X + (Fmb[0] * um[0] + Fmb[1] * um[1] + Fmb[2] * um[2]);
+  const double Xb = w[4] * Fr;
+  const double phatb = Fmb[0] * n[0] + Fmb[1] * n[1] + Fmb[2] * n[2];
+  const double rlnb = Frb * umn;
+  const double umnb = Frb * rho_ln;
+  double umb[3];
+  for (int d = 0; d < 3; ++d) umb[d] = w[4] * Fm[d] + Fmb[d] * Fr + umnb * n[d];
+  for (int d = 0; d < 3; ++d) ab.u[d] = 0.5 * umb[d];
+  const double iblb = c1 * Xb;
+  ab.k = -0.25 * Xb;
+  ab.rho = 0.5 * phatb / S;
+  ab.beta = -phatb * phat / S;
+  double dx, dlx;
+  log_mean_grad(a.rho, b.rho, a.lrho, b.lrho, dx, dlx);
+  ab.rho += rlnb * dx;
+  ab.lrho = rlnb * dlx;
+  inv_log_mean_grad(a.beta, b.beta, a.lbeta, b.lbeta, dx, dlx);
+  ab.beta += iblb * dx;
+  ab.lbeta = iblb * dlx;
+}
+
+// d(w . f(U).n)/dU for the advective flux in direction n (FP64 forward).
+__host__ __device__ inline void euler_flux_vjp(const double U[5], const Prim& q, const double n[3], const double w[5],
+                                               double gm1, double Ub[5]) {
+  const double un = q.u[0] * n[0] + q.u[1] * n[1] + q.u[2] * n[2];
+  double unb = w[0] * U[0] + w[1] * U[1] + w[2] * U[2] + w[3] * U[3] + w[4] * (U[4] + q.p);
+  const double pb = w[1] * n[0] + w[2] * n[1] + w[3] * n[2] + w[4] * un;
+  // direct dependence on the conserved entries
+  double Ud[5] = {w[0] * un, w[1] * un, w[2] * un, w[3] * un, w[4] * un};
+  const double ub[3] = {unb * n[0], unb * n[1], unb * n[2]};
+  double Up[5];
+  prim_vjp(q, gm1, 0.0, ub, pb, Up);
+  for (int v = 0; v < 5; ++v) Ub[v] = Ud[v] + Up[v];
+}
+
+// Adjoint of the contracted viscous flux Gn[v] = sum_d n_d G_d[1+v]:
+// gb[12] receives d(Gnb . Gn)/dg, ub[3] the velocity part (energy equation).
+__host__ __device__ inline void viscous_flux_vjp(const Prim& q, const double g[12], const Phys& P, const double n[3],
+                                                 const double Gnb[4], double gb[12], double ub[3]) {
+  const double mu = P.mu, lam = P.lam;
+  const double divu = g[0] + g[4] + g[8];
+  double tau[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int d = 0; d < 3; ++d) tau[a][d] = mu * (g[3 * a + d] + g[3 * d + a]);
+  const double t2 = (2.0 / 3.0) * mu * divu;
+  tau[0][0] -= t2; tau[1][1] -= t2; tau[2][2] -= t2;
+  double taub[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int d = 0; d < 3; ++d) taub[a][d] = n[d] * Gnb[a];
+  for (int d = 0; d < 3; ++d)
+    for (int a = 0; a < 3; ++a) taub[d][a] += n[d] * Gnb[3] * q.u[a];
+  for (int a = 0; a < 3; ++a) {
+    ub[a] = 0.0;
+    for (int d = 0; d < 3; ++d) ub[a] += n[d] * Gnb[3] * tau[d][a];
+  }
+  for (int c = 0; c < 12; ++c) gb[c] = 0.0;
+  for (int d = 0; d < 3; ++d) gb[9 + d] = lam * n[d] * Gnb[3];
+  double divb = 0.0;
+  for (int a = 0; a < 3; ++a) divb -= (2.0 / 3.0) * mu * taub[a][a];
+  for (int a = 0; a < 3; ++a)
+    for (int d = 0; d < 3; ++d) {
+      gb[3 * a + d] += mu * taub[a][d];
+      gb[3 * d + a] += mu * taub[a][d];
+    }
+  gb[0] += divb; gb[4] += divb; gb[8] += divb;
+}
+
+// Adjoint of the surface flux (FP64): ULb, URb, and for Navier-Stokes gLb, gRb.
+template <int FORM, int PHYS>
+__host__ __device__ inline void surface_flux_vjp(const double UL[5], const double UR[5], const double* gL,
+                                                 const double* gR, const double nh[3], double s, const Phys& P,
+                                                 const double Phib[5], double ULb[5], double URb[5], double* gLb,
+                                                 double* gRb) {
+  const Prim qL = cons2prim(UL, P.gm1), qR = cons2prim(UR, P.gm1);
+  const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
+  // central part
+  if (FORM == 0 || P.twopoint == 1) {
+    const double wh[5] = {0.5 * Phib[0], 0.5 * Phib[1], 0.5 * Phib[2], 0.5 * Phib[3], 0.5 * Phib[4]};
+    euler_flux_vjp(UL, qL, nv, wh, P.gm1, ULb);
+    euler_flux_vjp(UR, qR, nv, wh, P.gm1, URb);
+  } else {
+    const Aux aL = make_aux(qL), aR = make_aux(qR);
+    AuxBar bL, bR;
+    chandrashekar_vjp_a(aL, aR, nv, 0.5 / P.gm1, Phib, bL);
+    chandrashekar_vjp_a(aR, aL, nv, 0.5 / P.gm1, Phib, bR);
+    aux_vjp(qL, aL, bL, P.gm1, ULb);
+    aux_vjp(qR, aR, bR, P.gm1, URb);
+  }
+  // Rusanov dissipation
+  if (P.riemann == 0) {
+    const double cL = sqrt(P.gamma * qL.p / qL.rho), cR = sqrt(P.gamma * qR.p / qR.rho);
+    const double unL = qL.u[0] * nh[0] + qL.u[1] * nh[1] + qL.u[2] * nh[2];
+    const double unR = qR.u[0] * nh[0] + qR.u[1] * nh[1] + qR.u[2] * nh[2];
+    const double lL = fabs(unL) + cL, lR = fabs(unR) + cR;
+    const bool left = lL >= lR;
+    const double lmax = left ? lL : lR;
+    const double hs = 0.5 * (lmax * s);
+    double lb = 0.0;
+    for (int v = 0; v < 5; ++v) {
+      URb[v] -= hs * Phib[v];
+      ULb[v] += hs * Phib[v];
+      lb -= 0.5 * s * Phib[v] * (UR[v] - UL[v]);
+    }
+    const Prim& qa = left ? qL : qR;
+    const double una = left ? unL : unR;
+    const double ca = left ? cL : cR;
+    const double sg = una >= 0.0 ? 1.0 : -1.0;
+    const double ub[3] = {lb * sg * nh[0], lb * sg * nh[1], lb * sg * nh[2]};
+    const double cb = lb;
+    const double pb = cb * P.gamma / (2.0 * ca * qa.rho);
+    const double rb = -cb * P.gamma * qa.p / (2.0 * ca * qa.rho * qa.rho);
+    double Ub[5];
+    prim_vjp(qa, P.gm1, rb, ub, pb, Ub);
+    double* tgt = left ? ULb : URb;
+    for (int v = 0; v < 5; ++v) tgt[v] += Ub[v];
+  }
+  if constexpr (PHYS == 1) {
+    const double Gnb[4] = {-0.5 * Phib[1], -0.5 * Phib[2], -0.5 * Phib[3], -0.5 * Phib[4]};
+    double ubL[3], ubR[3];
+    viscous_flux_vjp(qL, gL, P, nv, Gnb, gLb, ubL);
+    viscous_flux_vjp(qR, gR, P, nv, Gnb, gRb, ubR);
+    double Ub[5];
+    prim_vjp(qL, P.gm1, 0.0, ubL, 0.0, Ub);
+    for (int v = 0; v < 5; ++v) ULb[v] += Ub[v];
+    prim_vjp(qR, P.gm1, 0.0, ubR, 0.0, Ub);
+    for (int v = 0; v < 5; ++v) URb[v] += Ub[v];
+  }
+}
+
+}  // namespace dgx

@@ -1,0 +1,96 @@
+// dgx_pointwise_check.cpp -- host build of the library's point physics and its
+// vector-Jacobian products, exported for the CPU test suite only (the product
+// path runs these functions inside the HIP kernels).
+#include "dgx_pointwise.hpp"
+
+using namespace dgx;
+
+static Phys make_phys(const double* c) {
+  // c = {gamma, mu, Pr, R, riemann, twopoint}
+  Phys P{};
+  P.gamma = c[0]; P.gm1 = c[0] - 1.0; P.mu = c[1]; P.Pr = c[2]; P.R = c[3]; P.Rinv = 1.0 / c[3];
+  P.lam = c[1] * c[0] * c[3] / ((c[0] - 1.0) * c[2]);
+  P.riemann = (int)c[4]; P.twopoint = (int)c[5];
+  return P;
+}
+
+extern "C" {
+
+void pw_chandrashekar(const double* Ua, const double* Ub, const double* n, const double* c, double* F) {
+  Phys P = make_phys(c);
+  Aux a = make_aux(cons2prim(Ua, P.gm1)), b = make_aux(cons2prim(Ub, P.gm1));
+  chandrashekar<double>(a, b, n, 0.5 / P.gm1, F);
+}
+
+void pw_chandrashekar_f32(const double* Ua, const double* Ub, const double* n, const double* c, double* F) {
+  Phys P = make_phys(c);
+  Aux a = make_aux(cons2prim(Ua, P.gm1)), b = make_aux(cons2prim(Ub, P.gm1));
+  chandrashekar<float>(a, b, n, 0.5 / P.gm1, F);
+}
+
+void pw_chandrashekar_vjp_a(const double* Ua, const double* Ub, const double* n, const double* c, const double* w,
+                            double* Uab) {
+  Phys P = make_phys(c);
+  Prim qa = cons2prim(Ua, P.gm1);
+  Aux a = make_aux(qa), b = make_aux(cons2prim(Ub, P.gm1));
+  AuxBar ab;
+  chandrashekar_vjp_a(a, b, n, 0.5 / P.gm1, w, ab);
+  aux_vjp(qa, a, ab, P.gm1, Uab);
+}
+
+void pw_euler_flux(const double* U, const double* n, const double* c, double* F) {
+  Phys P = make_phys(c);
+  euler_flux<double>(U, cons2prim(U, P.gm1), n, F);
+}
+
+void pw_euler_flux_vjp(const double* U, const double* n, const double* c, const double* w, double* Ub) {
+  Phys P = make_phys(c);
+  euler_flux_vjp(U, cons2prim(U, P.gm1), n, w, P.gm1, Ub);
+}
+
+void pw_viscous_flux(const double* U, const double* g, const double* n, const double* c, double* Gn) {
+  Phys P = make_phys(c);
+  viscous_flux<double>(cons2prim(U, P.gm1), g, P, n, Gn);
+}
+
+void pw_viscous_flux_vjp(const double* U, const double* g, const double* n, const double* c, const double* Gnb,
+                         double* gb, double* Ub) {
+  Phys P = make_phys(c);
+  Prim q = cons2prim(U, P.gm1);
+  double ub[3];
+  viscous_flux_vjp(q, g, P, n, Gnb, gb, ub);
+  prim_vjp(q, P.gm1, 0.0, ub, 0.0, Ub);
+}
+
+void pw_qvars(const double* U, const double* c, double* qv) {
+  Phys P = make_phys(c);
+  Prim q = cons2prim(U, P.gm1);
+  qv[0] = q.u[0]; qv[1] = q.u[1]; qv[2] = q.u[2]; qv[3] = q.p / (q.rho * P.R);
+}
+
+void pw_qvars_vjp(const double* U, const double* c, const double* qb, double* Ub) {
+  Phys P = make_phys(c);
+  qvars_vjp(cons2prim(U, P.gm1), P.gm1, P.Rinv, qb, Ub);
+}
+
+// form 0 weak / 1 split; phys 0 Euler / 1 Navier-Stokes
+void pw_surface_flux(int form, int phys, const double* UL, const double* UR, const double* gL, const double* gR,
+                     const double* nh, double s, const double* c, double* Phi) {
+  Phys P = make_phys(c);
+  if (form == 0 && phys == 0) surface_flux<double, 0, 0>(UL, UR, gL, gR, nh, s, P, Phi);
+  if (form == 0 && phys == 1) surface_flux<double, 0, 1>(UL, UR, gL, gR, nh, s, P, Phi);
+  if (form == 1 && phys == 0) surface_flux<double, 1, 0>(UL, UR, gL, gR, nh, s, P, Phi);
+  if (form == 1 && phys == 1) surface_flux<double, 1, 1>(UL, UR, gL, gR, nh, s, P, Phi);
+}
+
+void pw_surface_flux_vjp(int form, int phys, const double* UL, const double* UR, const double* gL, const double* gR,
+                         const double* nh, double s, const double* c, const double* Phib, double* ULb, double* URb,
+                         double* gLb, double* gRb) {
+  Phys P = make_phys(c);
+  if (form == 0 && phys == 0) surface_flux_vjp<0, 0>(UL, UR, gL, gR, nh, s, P, Phib, ULb, URb, gLb, gRb);
+  if (form == 0 && phys == 1) surface_flux_vjp<0, 1>(UL, UR, gL, gR, nh, s, P, Phib, ULb, URb, gLb, gRb);
+  if (form == 1 && phys == 0) surface_flux_vjp<1, 0>(UL, UR, gL, gR, nh, s, P, Phib, ULb, URb, gLb, gRb);
+  if (form == 1 && phys == 1) surface_flux_vjp<1, 1>(UL, UR, gL, gR, nh, s, P, Phib, ULb, URb, gLb, gRb);
+}
+
+}  // extern "C"

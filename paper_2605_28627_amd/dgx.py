@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_MESH", 3: "DG_ERR_HIP", 
 # public symbols of include/dgx.h
 SYMBOLS = ["dg_create", "dg_destroy", "dg_last_error", "dg_lserk_coefficients", "dg_set_mesh", "dg_upload_mesh",
            "dg_upload_metrics", "dg_get_metrics", "dg_node_coords", "dg_sizes", "dg_workspace_bytes",
-           "dg_bind_workspace", "dg_rhs", "dg_lift", "dg_rk_step", "dg_adjoint_rhs", "dg_adjoint_rk_step",
+           "dg_workspace_bytes_adjoint", "dg_bind_workspace", "dg_rhs", "dg_lift", "dg_rk_step", "dg_adjoint_rhs", "dg_adjoint_rk_step",
            "dg_kinetic_energy", "dg_kinetic_energy_grad", "dg_timestep", "dg_check_state", "dg_profile",
            "dg_profile_query"]
 
@@ -61,6 +61,7 @@ _sig = {
     "dg_node_coords": (ctypes.c_int, [_vp, _dp]),
     "dg_sizes": (ctypes.c_int, [_vp, _ip, _ip, _ip, ctypes.POINTER(_sz)]),
     "dg_workspace_bytes": (_sz, [_vp]),
+    "dg_workspace_bytes_adjoint": (_sz, [_vp]),
     "dg_bind_workspace": (ctypes.c_int, [_vp, _vp, _sz]),
     "dg_rhs": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp]),
     "dg_lift": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -193,6 +194,10 @@ def dg_node_coords(ctx):
 
 def dg_workspace_bytes(ctx):
     return int(_L.dg_workspace_bytes(ctx))
+
+
+def dg_workspace_bytes_adjoint(ctx):
+    return int(_L.dg_workspace_bytes_adjoint(ctx))
 
 
 def dg_bind_workspace(ctx, ws_tensor):

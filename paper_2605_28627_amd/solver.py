@@ -24,7 +24,7 @@ def config_from_dict(d: dict) -> dgx.dg_config:
 
 
 class DGSolver:
-    def __init__(self, cfg: dict, mesh, device: str | torch.device = "cuda"):
+    def __init__(self, cfg: dict, mesh, device: str | torch.device = "cuda", adjoint: bool = False):
         self.device = torch.device(device)
         self.cfg = dict(cfg)
         self.ctx = dgx.dg_create(config_from_dict(cfg))
@@ -33,7 +33,8 @@ class DGSolver:
                 dgx.dg_upload_mesh(self.ctx, mesh)
             self.nElems, self.nSides, self.npe, self.state_len = dgx.dg_sizes(self.ctx)
             self.n1 = round(self.npe ** (1 / 3))
-            nb = dgx.dg_workspace_bytes(self.ctx)
+            nb = dgx.dg_workspace_bytes_adjoint(self.ctx) if adjoint else dgx.dg_workspace_bytes(self.ctx)
+            self.adjoint = adjoint
             # over-allocate so the bound pointer is 256-byte aligned
             self._ws_raw = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
             off = (-self._ws_raw.data_ptr()) % 256
@@ -91,6 +92,9 @@ class DGSolver:
         out = self.empty_state() if out is None else out
         dgx.dg_adjoint_rhs(self.ctx, U, lam, out)
         return out
+
+    def adjoint_rk_step(self, Un: torch.Tensor, lamU: torch.Tensor, lamdU: torch.Tensor, dt: float, t: float = 0.0):
+        dgx.dg_adjoint_rk_step(self.ctx, Un, lamU, lamdU, t, dt)
 
     def kinetic_energy(self, U: torch.Tensor, rho0U0sq: float = 1.0) -> torch.Tensor:
         out = torch.empty(1, dtype=torch.float64, device=self.device)

@@ -1,0 +1,142 @@
+"""CPU checks of the library's point physics (host build of the same header
+the kernels use): forward fluxes against the oracle's, and every hand-written
+vector-Jacobian product against central differences of the forward code,
+<w, J d> = <J^T w, d>, on both branches of the log mean and of Rusanov's
+wave-speed maximum."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+G = 1.4
+C = np.array([G, 0.02, 0.72, 1.0, 0.0, 0.0])    # gamma, mu, Pr, R, riemann, twopoint
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+@pytest.fixture(scope="module")
+def pw():
+    path = os.path.join(ROOT, "paper_2605_28627_amd", "libdgx_pointwise_check.so")
+    if not os.path.exists(path):
+        from paper_2605_28627_amd import build
+        build.build_pointwise_check()
+    return ctypes.CDLL(path)
+
+
+def P(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a.ctypes.data_as(_dp)
+
+
+def state(rng, scale=1.0, base=None):
+    if base is not None:
+        return base * (1 + scale * rng.uniform(-1, 1, 5))
+    rho = rng.uniform(0.6, 1.6)
+    u = rng.uniform(-0.8, 0.8, 3)
+    p = rng.uniform(0.6, 1.6)
+    return np.array([rho, *(rho * u), p / (G - 1) + 0.5 * rho * u @ u])
+
+
+def call(f, nout, *args):
+    out = np.zeros(nout)
+    f(*[P(a) if isinstance(a, np.ndarray) else a for a in args], P(out))
+    return out
+
+
+def fd_dot(fwd, x, d, w, eps=1e-6):
+    return w @ ((fwd(x + eps * d) - fwd(x - eps * d)) / (2 * eps))
+
+
+def test_forward_matches_oracle(pw, orc):
+    rng = np.random.default_rng(0)
+    for _ in range(30):
+        a, b = state(rng), state(rng)
+        n = rng.normal(size=3)
+        F = call(pw.pw_chandrashekar, 5, a, b, n, C)
+        assert np.allclose(F, orc.flux_twopoint(a, b, n), rtol=1e-13, atol=1e-13)
+        F = call(pw.pw_euler_flux, 5, a, n, C)
+        assert np.allclose(F, orc.flux_adv(a, n), rtol=1e-13, atol=1e-13)
+        g = rng.normal(size=12)
+        Gn = call(pw.pw_viscous_flux, 4, a, g, n, C)
+        ref = sum(n[d] * orc.flux_visc(a, g, d, mu=C[1], Pr=C[2]) for d in range(3))
+        assert np.allclose(Gn, ref[1:], rtol=1e-13, atol=1e-13)
+    # float two-point flux: float-level agreement
+    a, b = state(rng), state(rng)
+    n = rng.normal(size=3)
+    F32 = call(pw.pw_chandrashekar_f32, 5, a, b, n, C)
+    assert np.allclose(F32, orc.flux_twopoint(a, b, n), rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("near", [False, True], ids=["direct-branch", "series-branch"])
+def test_chandrashekar_vjp(pw, near):
+    rng = np.random.default_rng(1)
+    for _ in range(40):
+        a = state(rng)
+        b = state(rng, 1e-4, a) if near else state(rng)
+        n = rng.normal(size=3)
+        w = rng.normal(size=5)
+        d = rng.normal(size=5) * np.abs(a)
+        vjp = call(pw.pw_chandrashekar_vjp_a, 5, a, b, n, C, w)
+        ref = fd_dot(lambda x: call(pw.pw_chandrashekar, 5, x, b, n, C), a, d, w, eps=1e-7 if near else 1e-6)
+        assert abs(vjp @ d - ref) < 1e-7 * (abs(ref) + np.abs(vjp).max() * np.abs(d).max()), (vjp @ d, ref)
+
+
+def test_euler_and_viscous_vjp(pw):
+    rng = np.random.default_rng(2)
+    for _ in range(40):
+        U = state(rng)
+        n = rng.normal(size=3)
+        w = rng.normal(size=5)
+        d = rng.normal(size=5)
+        vjp = call(pw.pw_euler_flux_vjp, 5, U, n, C, w)
+        ref = fd_dot(lambda x: call(pw.pw_euler_flux, 5, x, n, C), U, d, w)
+        assert abs(vjp @ d - ref) < 1e-8 * (1 + abs(ref))
+        g = rng.normal(size=12)
+        wg = rng.normal(size=4)
+        gb, Ub = np.zeros(12), np.zeros(5)
+        pw.pw_viscous_flux_vjp(P(U), P(g), P(n), P(C), P(wg), P(gb), P(Ub))
+        dg = rng.normal(size=12)
+        ref_g = fd_dot(lambda x: call(pw.pw_viscous_flux, 4, U, x, n, C), g, dg, wg)
+        assert abs(gb @ dg - ref_g) < 1e-8 * (1 + abs(ref_g))
+        ref_U = fd_dot(lambda x: call(pw.pw_viscous_flux, 4, x, g, n, C), U, d, wg)
+        assert abs(Ub @ d - ref_U) < 1e-8 * (1 + abs(ref_U))
+        qb = rng.normal(size=4)
+        vq = call(pw.pw_qvars_vjp, 5, U, C, qb)
+        ref_q = fd_dot(lambda x: call(pw.pw_qvars, 4, x, C), U, d, qb)
+        assert abs(vq @ d - ref_q) < 1e-8 * (1 + abs(ref_q))
+
+
+@pytest.mark.parametrize("form,phys", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("riemann", [0, 1])
+def test_surface_flux_vjp(pw, form, phys, riemann):
+    rng = np.random.default_rng(3 + form + 2 * phys)
+    c = C.copy()
+    c[4] = riemann
+    for it in range(40):
+        UL = state(rng)
+        UR = state(rng, 1e-5, UL) if it % 3 == 0 else state(rng)
+        if it % 5 == 1:
+            UR = UL.copy()
+            UR[1:4] *= -1.0          # equal wave speeds on both sides: tie goes to the master side
+            UR = UR * (1 + 1e-3 * rng.uniform(-1, 1, 5))
+        gL, gR = rng.normal(size=12), rng.normal(size=12)
+        nh = rng.normal(size=3)
+        nh /= np.linalg.norm(nh)
+        s = rng.uniform(0.5, 2.0)
+        w = rng.normal(size=5)
+        ULb, URb, gLb, gRb = np.zeros(5), np.zeros(5), np.zeros(12), np.zeros(12)
+        pw.pw_surface_flux_vjp(form, phys, P(UL), P(UR), P(gL), P(gR), P(nh), ctypes.c_double(s), P(c), P(w),
+                               P(ULb), P(URb), P(gLb), P(gRb))
+
+        def fwd(UL_, UR_, gL_, gR_):
+            out = np.zeros(5)
+            pw.pw_surface_flux(form, phys, P(UL_), P(UR_), P(gL_), P(gR_), P(nh), ctypes.c_double(s), P(c), P(out))
+            return out
+
+        dL, dR, dgL, dgR = (rng.normal(size=k) for k in (5, 5, 12, 12))
+        eps = 1e-7
+        ref = w @ ((fwd(UL + eps * dL, UR + eps * dR, gL + eps * dgL, gR + eps * dgR) -
+                    fwd(UL - eps * dL, UR - eps * dR, gL - eps * dgL, gR - eps * dgR)) / (2 * eps))
+        got = ULb @ dL + URb @ dR + (gLb @ dgL + gRb @ dgR if phys else 0.0)
+        assert abs(got - ref) < 1e-6 * (1 + abs(ref)), (it, got, ref)
