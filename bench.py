@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=4)
     ap.add_argument("--cpu-sample-elems", type=int, default=4096)
     ap.add_argument("--cpu-repeats", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -131,7 +133,7 @@ def main():
     U0 = s.to_device(I.workload_state(args.workload, xyz))
     dt = s.timestep(U0, 0.9)
 
-    def timed(solver, steps, warmup, profile):
+    def timed(solver, steps, warmup, profile, keep=None):
         U = U0.clone()
         dU = torch.zeros_like(U)
         if warmup:
@@ -150,9 +152,12 @@ def main():
             dgx.dg_profile(solver.ctx, 0)
         if solver.check_state(U) != 0:
             raise RuntimeError("non-physical state after the timed steps")
+        if keep is not None:
+            keep.append(U)
         return t, prof
 
-    t64, prof = timed(s, args.steps, args.warmup, profile=True)
+    final64 = []
+    t64, prof = timed(s, args.steps, args.warmup, profile=True, keep=final64)
     pid64 = t64 / (5 * args.steps * dof)
     vol_ms, vol_n = prof["volume"]
     vol_avg_s = vol_ms * 1e-3 / max(vol_n, 1)
@@ -196,15 +201,56 @@ def main():
     if not args.no_fp32:
         cfg32 = dict(cfg, precision=1)
         s32 = DGSolver(cfg32, mesh, dev)
-        t32, _ = timed(s32, args.steps, args.warmup, profile=False)
+        final32 = []
+        t32, _ = timed(s32, args.steps, args.warmup, profile=False, keep=final32)
         result["pid_fp32_flux"] = t32 / (5 * args.steps * dof)
         result["fp32_speedup"] = t64 / t32
+        # relative L2 error per variable of the FP32-flux path against the FP64 path
+        # (which matches the oracle to 1e-12): residual of the initial state, and
+        # the state after warmup + timed steps
+        R64, R32 = s.rhs(U0), s32.rhs(U0)
+        d_state = final32[0] - final64[0]
+        d_ref = final64[0] - U0
+        result["fp32_l2_error"] = {
+            "residual_rel_per_var": [float((R32[v] - R64[v]).norm() / R64[v].norm()) for v in range(5)],
+            "state_rel_to_change_per_var": [float(d_state[v].norm() / max(float(d_ref[v].norm()), 1e-300))
+                                            for v in range(5)],
+            "state_rel_per_var": [float(d_state[v].norm() / final64[0][v].norm()) for v in range(5)],
+            "steps": args.steps + args.warmup,
+        }
         s32.close()
-    result["adjoint_forward_cost"] = None
+    result["adjoint_forward_cost"] = adjoint_cost(cfg, mesh, dev, U0, dt, args) if not args.no_adjoint else None
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args, cfg, mesh, xyz, pid64)
     print(json.dumps(result), flush=True)
     s.close()
+
+
+def adjoint_cost(cfg, mesh, dev, U0, dt, args):
+    """Backward (reverse sweep with recomputation) over forward time of the
+    gradient of E_k(T) through args.adjoint_steps steps of the same workload."""
+    import torch
+    from paper_2605_28627_amd.autograd import kinetic_energy, trajectory
+    from paper_2605_28627_amd.solver import DGSolver
+    sa = DGSolver(cfg, mesh, dev, adjoint=True)
+    n = args.adjoint_steps
+    every = max(1, int(round(n ** 0.5)))
+    times = []
+    for rep in range(2):          # the first repetition warms up
+        U = U0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = kinetic_energy(sa, trajectory(sa, U, dt, n, checkpoint_every=every))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+    sa.close()
+    tf, tb = times[-1]
+    return {"value": tb / tf, "steps": n, "checkpoint_every": every, "forward_s": tf, "backward_s": tb,
+            "note": "backward includes the recomputation of step and stage states"}
 
 
 def cpu_baseline(args, cfg, mesh, xyz, pid_gpu):

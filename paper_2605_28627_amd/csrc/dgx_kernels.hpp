@@ -263,9 +263,19 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
 // Residual kernel: volume integral (weak or split), surface fluxes, surface
 // lift, Jacobian scaling; MODE 0 writes U_t, MODE 1 applies one LSERK stage
 // and writes the face traces of the new state for the next stage.
+//
+// Phases, so that live ranges do not stack (registers and LDS decide how
+// many elements share a CU):
+//   1. surface fluxes of the six faces -> LDS (before any volume state is live);
+//   2. per-node two-point data -> LDS (split form), viscous contravariant
+//      fluxes G~^r in registers (Navier-Stokes);
+//   3. per direction r: the metric row Ja^r (and G~^r) -> LDS, then flux
+//      differencing along r (split) or the D-hat contraction of F~^r (weak);
+//   4. surface lift, 1/J, and the output or the RK stage;
+//   5. face traces of the new state (RK stage).
 // ---------------------------------------------------------------------------
 template <int N, int NODES, int FORM, int PHYS, int PREC, int MODE>
-__global__ __launch_bounds__(Shape<N>::nth) void k_volume(Geo G, Phys P, const double* __restrict__ U,
+__global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void k_volume(Geo G, Phys P, const double* __restrict__ U,
                                                           const double* __restrict__ Utr,
                                                           const double* __restrict__ gin,
                                                           const double* __restrict__ gtr, double* __restrict__ Ut,
@@ -275,170 +285,18 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_volume(Geo G, Phys P, const d
   using S = Shape<N>;
   using FT = typename std::conditional<PREC == 1, float, double>::type;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
-  constexpr int SZ_SPLIT = 17 * n3;                 // aux (8) + Ja (9)
-  constexpr int SZ_WEAK = 15 * n3;                  // contravariant fluxes
-  constexpr int SZ_VISC = 12 * n3;                  // viscous contravariant fluxes (split form)
-  constexpr int SZ_FACE = 5 * S::nface;             // surface fluxes
-  constexpr int SZ_NEWU = 5 * n3;                   // new state (Gauss-node traces)
-  constexpr int SZ0 = FORM == 1 ? SZ_SPLIT : SZ_WEAK;
-  constexpr int SZ1 = SZ0 > SZ_FACE ? SZ0 : SZ_FACE;
-  constexpr int SZ2 = (PHYS == 1 && FORM == 1 && SZ_VISC > SZ1) ? SZ_VISC : SZ1;
-  constexpr int SZ = SZ2 > SZ_NEWU ? SZ2 : SZ_NEWU;
+  constexpr int NV = PHYS == 1 ? 4 : 0;                              // viscous values per node and direction
+  constexpr int SZ_SPLIT = (8 + 3 + NV) * n3;                        // aux + Ja^r + G~^r
+  constexpr int SZ_WEAK = 5 * n3;                                    // F~^r
+  constexpr int SZ_V = FORM == 1 ? SZ_SPLIT : SZ_WEAK;
+  constexpr int SZ = SZ_V > 5 * n3 ? SZ_V : 5 * n3;                  // also holds the new state (Gauss traces)
+  __shared__ double sphi[5 * S::nface];
   __shared__ double sm[SZ];
   __shared__ DevBasis sb;
   const int e = blockIdx.x, t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
   load_basis(&sb, G.basis, t, S::nth);
-  const bool act = t < n3;
-  const int i = t % n1, j = (t / n1) % n1, k = t / n2;
-  const int idx[3] = {i, j, k};
-  double u[5] = {0, 0, 0, 0, 0};
-  double ja[9];
-  double acc[5] = {0, 0, 0, 0, 0};
-  Prim q{};
-  if (act) {
-#pragma unroll
-    for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) ja[c] = G.Ja[((size_t)c * nE + e) * n3 + t];
-    q = cons2prim(u, P.gm1);
-  }
-  if constexpr (FORM == 0) {
-    // weak form: F~^r = Ja^r . (f - G) at every node, then Dhat contraction
-    if (act) {
-      double gl[12];
-      if constexpr (PHYS == 1) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) gl[c] = gin[((size_t)c * nE + e) * n3 + t];
-      }
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const double nv[3] = {ja[3 * r], ja[3 * r + 1], ja[3 * r + 2]};
-        double F[5];
-        euler_flux<FT>(u, q, nv, F);
-        if constexpr (PHYS == 1) {
-          double Gn[4];
-          viscous_flux<FT>(q, gl, P, nv, Gn);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) F[1 + v] -= Gn[v];
-        }
-#pragma unroll
-        for (int v = 0; v < 5; ++v) sm[(5 * r + v) * n3 + t] = F[v];
-      }
-    }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const int a = idx[r];
-        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
-#pragma unroll
-        for (int l = 0; l < n1; ++l) {
-          const int tl = line_node<N>(r, l, pp, qq);
-          const double c = sb.Dhat[a * n1 + l];
-#pragma unroll
-          for (int v = 0; v < 5; ++v) acc[v] += c * sm[(5 * r + v) * n3 + tl];
-        }
-      }
-    }
-    __syncthreads();
-  } else {
-    // split form: flux differencing with the two-point flux and averaged metrics
-    double* saux = sm;            // [8][n3]
-    double* sja = sm + 8 * n3;    // [9][n3]
-    if (act) {
-      const Aux a = make_aux(q);
-      saux[0 * n3 + t] = a.rho;
-      saux[1 * n3 + t] = a.u[0];
-      saux[2 * n3 + t] = a.u[1];
-      saux[3 * n3 + t] = a.u[2];
-      saux[4 * n3 + t] = a.beta;
-      saux[5 * n3 + t] = a.lrho;
-      saux[6 * n3 + t] = a.lbeta;
-      saux[7 * n3 + t] = a.k;
-#pragma unroll
-      for (int c = 0; c < 9; ++c) sja[c * n3 + t] = ja[c];
-    }
-    __syncthreads();
-    if (act) {
-      Aux me;
-      me.rho = saux[0 * n3 + t]; me.u[0] = saux[1 * n3 + t]; me.u[1] = saux[2 * n3 + t];
-      me.u[2] = saux[3 * n3 + t]; me.beta = saux[4 * n3 + t]; me.lrho = saux[5 * n3 + t];
-      me.lbeta = saux[6 * n3 + t]; me.k = saux[7 * n3 + t];
-      const double c1 = 0.5 / P.gm1;
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const int a = idx[r];
-        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
-        for (int l = 0; l < n1; ++l) {
-          if (l == a) continue;
-          const int tl = line_node<N>(r, l, pp, qq);
-          Aux ot;
-          ot.rho = saux[0 * n3 + tl]; ot.u[0] = saux[1 * n3 + tl]; ot.u[1] = saux[2 * n3 + tl];
-          ot.u[2] = saux[3 * n3 + tl]; ot.beta = saux[4 * n3 + tl]; ot.lrho = saux[5 * n3 + tl];
-          ot.lbeta = saux[6 * n3 + tl]; ot.k = saux[7 * n3 + tl];
-          const double nv[3] = {0.5 * (ja[3 * r] + sja[(3 * r) * n3 + tl]),
-                                0.5 * (ja[3 * r + 1] + sja[(3 * r + 1) * n3 + tl]),
-                                0.5 * (ja[3 * r + 2] + sja[(3 * r + 2) * n3 + tl])};
-          double F[5];
-          if (P.twopoint == 0) {
-            chandrashekar<FT>(me, ot, nv, c1, F);
-          } else {
-            double uo[5];
-            // central average of the two physical fluxes
-            const double ro = ot.rho;
-            uo[0] = ro; uo[1] = ro * ot.u[0]; uo[2] = ro * ot.u[1]; uo[3] = ro * ot.u[2];
-            const double po = 0.5 * ro / ot.beta;
-            uo[4] = po / P.gm1 + 0.5 * ro * ot.k;
-            Prim qo; qo.rho = ro; qo.u[0] = ot.u[0]; qo.u[1] = ot.u[1]; qo.u[2] = ot.u[2]; qo.p = po;
-            double Fa[5], Fb[5];
-            euler_flux<FT>(u, q, nv, Fa);
-            euler_flux<FT>(uo, qo, nv, Fb);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) F[v] = 0.5 * (Fa[v] + Fb[v]);
-          }
-          const double ds = sb.DS[a * n1 + l];
-#pragma unroll
-          for (int v = 0; v < 5; ++v) acc[v] -= ds * F[v];
-        }
-      }
-    }
-    __syncthreads();
-    if constexpr (PHYS == 1) {
-      // viscous part in weak form: acc -= sum_l Dhat[a][l] G~^r_l
-      if (act) {
-        double gl[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) gl[c] = gin[((size_t)c * nE + e) * n3 + t];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          const double nv[3] = {ja[3 * r], ja[3 * r + 1], ja[3 * r + 2]};
-          double Gn[4];
-          viscous_flux<FT>(q, gl, P, nv, Gn);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) sm[(4 * r + v) * n3 + t] = Gn[v];
-        }
-      }
-      __syncthreads();
-      if (act) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          const int a = idx[r];
-          const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
-#pragma unroll
-          for (int l = 0; l < n1; ++l) {
-            const int tl = line_node<N>(r, l, pp, qq);
-            const double c = sb.Dhat[a * n1 + l];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[1 + v] -= c * sm[(4 * r + v) * n3 + tl];
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  // surface fluxes of the six faces -> LDS (own face-local order, outward sign)
-  double* sphi = sm;  // [6][5][n2]
+  // 1. surface fluxes (own face-local order, outward sign)
   for (int ft = t; ft < S::nface; ft += S::nth) {
     const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
     const int info = G.efc[e * 6 + f];
@@ -452,24 +310,144 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_volume(Geo G, Phys P, const d
       UL[v] = Utr[tr_index(0, v, 5, nS, side, n2, fi)];
       UR[v] = Utr[tr_index(1, v, 5, nS, side, n2, fi)];
     }
-    double gL[12], gR[12];
-    if constexpr (PHYS == 1) {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        gL[c] = gtr[tr_index(0, c, 12, nS, side, n2, fi)];
-        gR[c] = gtr[tr_index(1, c, 12, nS, side, n2, fi)];
-      }
-    }
     const double nh[3] = {G.face[((size_t)0 * nS + side) * n2 + fi], G.face[((size_t)1 * nS + side) * n2 + fi],
                           G.face[((size_t)2 * nS + side) * n2 + fi]};
     const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
     double Phi[5];
-    surface_flux<FT, FORM, PHYS>(UL, UR, gL, gR, nh, s, P, Phi);
+    surface_flux_adv<FT, FORM>(UL, UR, nh, s, P, Phi);
+    if constexpr (PHYS == 1) {
+      const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
+#pragma unroll 1
+      for (int sd = 0; sd < 2; ++sd) {
+        double gg[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gg[c] = gtr[tr_index(sd, c, 12, nS, side, n2, fi)];
+        double Gn[4];
+        viscous_flux<FT>(cons2prim(sd ? UR : UL, P.gm1), gg, P, nv, Gn);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Phi[1 + v] -= 0.5 * Gn[v];
+      }
+    }
     const double sgn = slot ? -1.0 : 1.0;
 #pragma unroll
     for (int v = 0; v < 5; ++v) sphi[(f * 5 + v) * n2 + rr] = sgn * Phi[v];
   }
-  __syncthreads();
+  // 2. own state
+  const bool act = t < n3;
+  const int i = t % n1, j = (t / n1) % n1, k = t / n2;
+  const int idx[3] = {i, j, k};
+  double u[5] = {0, 0, 0, 0, 0};
+  double acc[5] = {0, 0, 0, 0, 0};
+  Prim q{};
+  double Gt[3][4];
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+    q = cons2prim(u, P.gm1);
+    if constexpr (PHYS == 1) {
+      double gl[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) gl[c] = gin[((size_t)c * nE + e) * n3 + t];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double nv[3] = {G.Ja[((size_t)(3 * r) * nE + e) * n3 + t], G.Ja[((size_t)(3 * r + 1) * nE + e) * n3 + t],
+                              G.Ja[((size_t)(3 * r + 2) * nE + e) * n3 + t]};
+        viscous_flux<FT>(q, gl, P, nv, Gt[r]);
+      }
+    }
+  }
+  Aux me{};
+  if constexpr (FORM == 1) {
+    if (act) {
+      me = make_aux(q);
+      sm[0 * n3 + t] = me.rho; sm[1 * n3 + t] = me.u[0]; sm[2 * n3 + t] = me.u[1]; sm[3 * n3 + t] = me.u[2];
+      sm[4 * n3 + t] = me.beta; sm[5 * n3 + t] = me.lrho; sm[6 * n3 + t] = me.lbeta; sm[7 * n3 + t] = me.k;
+    }
+  }
+  // 3. volume integral, one reference direction at a time
+#pragma unroll 1
+  for (int r = 0; r < 3; ++r) {
+    double jr[3] = {0, 0, 0};
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) jr[c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
+    }
+    if constexpr (FORM == 1) {
+      double* sja = sm + 8 * n3;
+      double* sgv = sm + 11 * n3;
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sja[c * n3 + t] = jr[c];
+        if constexpr (PHYS == 1) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) sgv[v * n3 + t] = Gt[r][v];
+        }
+      }
+      __syncthreads();
+      if (act) {
+        const int a = idx[r];
+        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+        const double c1 = 0.5 / P.gm1;
+        for (int l = 0; l < n1; ++l) {
+          const int tl = line_node<N>(r, l, pp, qq);
+          if constexpr (PHYS == 1) {
+            // viscous part in weak form: acc -= Dhat[a][l] G~^r_l
+            const double c = sb.Dhat[a * n1 + l];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[1 + v] -= c * sgv[v * n3 + tl];
+          }
+          if (l == a) continue;
+          Aux ot;
+          ot.rho = sm[0 * n3 + tl]; ot.u[0] = sm[1 * n3 + tl]; ot.u[1] = sm[2 * n3 + tl];
+          ot.u[2] = sm[3 * n3 + tl]; ot.beta = sm[4 * n3 + tl]; ot.lrho = sm[5 * n3 + tl];
+          ot.lbeta = sm[6 * n3 + tl]; ot.k = sm[7 * n3 + tl];
+          const double nv[3] = {0.5 * (jr[0] + sja[0 * n3 + tl]), 0.5 * (jr[1] + sja[1 * n3 + tl]),
+                                0.5 * (jr[2] + sja[2 * n3 + tl])};
+          double F[5];
+          if (P.twopoint == 0) {
+            chandrashekar<FT>(me, ot, nv, c1, F);
+          } else {
+            // central average of the two physical fluxes (states rebuilt from the staged data)
+            double Fa[5], Fb[5];
+            aux_flux<FT>(me, P.gm1, nv, Fa);
+            aux_flux<FT>(ot, P.gm1, nv, Fb);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) F[v] = 0.5 * (Fa[v] + Fb[v]);
+          }
+          const double ds = sb.DS[a * n1 + l];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] -= ds * F[v];
+        }
+      }
+      __syncthreads();
+    } else {
+      // weak form: F~^r = Ja^r . (f - G) at every node, then the Dhat contraction
+      if (act) {
+        double F[5];
+        euler_flux<FT>(u, q, jr, F);
+        if constexpr (PHYS == 1) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) F[1 + v] -= Gt[r][v];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm[v * n3 + t] = F[v];
+      }
+      __syncthreads();
+      if (act) {
+        const int a = idx[r];
+        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+#pragma unroll
+        for (int l = 0; l < n1; ++l) {
+          const int tl = line_node<N>(r, l, pp, qq);
+          const double c = sb.Dhat[a * n1 + l];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] += c * sm[v * n3 + tl];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // 4. surface lift, Jacobian, output
   double Unew[5];
   if (act) {
 #pragma unroll
@@ -502,13 +480,13 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_volume(Geo G, Phys P, const d
         const size_t gi = ((size_t)v * nE + e) * n3 + t;
         const double d = A * dU[gi] + dt * (acc[v] * sJ);
         dU[gi] = d;
-        Unew[v] = u[v] + B * d;
+        Unew[v] = U[gi] + B * d;   // re-read (cached): keeps U out of the registers of phase 3
         Uio[gi] = Unew[v];
       }
     }
   }
+  // 5. traces of the new state for the next stage
   if constexpr (MODE == 1) {
-    // traces of the new state for the next stage
     if constexpr (NODES == 1) {
       if (act) {
 #pragma unroll
@@ -526,7 +504,6 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_volume(Geo G, Phys P, const d
         }
       }
     } else {
-      __syncthreads();
       if (act)
 #pragma unroll
         for (int v = 0; v < 5; ++v) sm[v * n3 + t] = Unew[v];

@@ -54,6 +54,39 @@ __host__ __device__ inline FT inv_log_mean(FT x, FT y, FT lx, FT ly) {
   return (lx - ly) / (x - y);
 }
 
+// Reciprocal: hardware estimate refined by two Newton steps on the device
+// (within an ulp of 1/x for the normal, finite x used here); exact division
+// on the host.
+__host__ __device__ inline double rcp_nr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+__host__ __device__ inline float rcp_nr(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+#else
+  return 1.0f / x;
+#endif
+}
+
+// 1/P(u) for P(u) = 2 + u(2/3 + u(2/5 + u 2/7)) in [2, 2+1e-4): Newton from 1/2.
+template <typename FT>
+__host__ __device__ inline FT inv_series(FT P) {
+  FT r = FT(0.5);
+  r = r * (FT(2) - P * r);
+  r = r * (FT(2) - P * r);
+  if (sizeof(FT) == 8) r = r * (FT(2) - P * r);
+  return r;
+}
+
 // Per-node data a two-point flux needs from a partner node.
 struct Aux {
   double rho, u[3], beta, lrho, lbeta, k;   // k = |u|^2
@@ -62,11 +95,30 @@ struct Aux {
 // Chandrashekar's kinetic-energy-preserving, entropy-conservative flux in the
 // direction n (not normalised): F_rho = rho^ln {u}.n, F_m = p_hat n + {u} F_rho,
 // F_E = F_rho (1/(2 (gamma-1) beta^ln) - {|u|^2}/2) + {u}.F_m.
+// The log means are evaluated with two reciprocals per pair, 1/(rho_a+rho_b)
+// and 1/(beta_a+beta_b) (the second also gives p_hat); the series branch
+// divides by P(u) through inv_series, the direct branch needs one more.
 template <typename FT>
 __host__ __device__ inline void chandrashekar(const Aux& a, const Aux& b, const double n[3], double c1, double F[5]) {
-  const FT rho_ln = log_mean<FT>(FT(a.rho), FT(b.rho), FT(a.lrho), FT(b.lrho));
-  const FT ibeta_ln = inv_log_mean<FT>(FT(a.beta), FT(b.beta), FT(a.lbeta), FT(b.lbeta));
-  const FT phat = FT(0.5) * (FT(a.rho) + FT(b.rho)) / (FT(a.beta) + FT(b.beta));
+  const FT thr = sizeof(FT) == 8 ? FT(1e-4) : FT(1e-2);
+  const FT sr = FT(a.rho) + FT(b.rho), dr = FT(a.rho) - FT(b.rho);
+  const FT sb = FT(a.beta) + FT(b.beta), db = FT(a.beta) - FT(b.beta);
+  const FT rsr = rcp_nr(sr), rsb = rcp_nr(sb);
+  const FT fr = dr * rsr, ur = fr * fr;
+  const FT fb = db * rsb, ub2 = fb * fb;
+  FT rho_ln, ibeta_ln;
+  if (ur < thr) {
+    const FT P = FT(2) + ur * (FT(2.0 / 3.0) + ur * (FT(2.0 / 5.0) + ur * FT(2.0 / 7.0)));
+    rho_ln = sr * inv_series<FT>(P);
+  } else {
+    rho_ln = dr * rcp_nr(FT(a.lrho) - FT(b.lrho));
+  }
+  if (ub2 < thr) {
+    ibeta_ln = (FT(2) + ub2 * (FT(2.0 / 3.0) + ub2 * (FT(2.0 / 5.0) + ub2 * FT(2.0 / 7.0)))) * rsb;
+  } else {
+    ibeta_ln = (FT(a.lbeta) - FT(b.lbeta)) * rcp_nr(db);
+  }
+  const FT phat = FT(0.5) * sr * rsb;
   const FT X = ibeta_ln * FT(c1) - FT(0.25) * (FT(a.k) + FT(b.k));
   const double um0 = 0.5 * (a.u[0] + b.u[0]), um1 = 0.5 * (a.u[1] + b.u[1]), um2 = 0.5 * (a.u[2] + b.u[2]);
   const double umn = um0 * n[0] + um1 * n[1] + um2 * n[2];
@@ -87,6 +139,20 @@ __host__ __device__ inline Aux make_aux(const Prim& q) {
   a.lbeta = log(a.beta);
   a.k = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
   return a;
+}
+
+// Advective flux in direction n of the state described by a two-point record
+// (rho, u, beta = rho/(2p), |u|^2).
+template <typename FT>
+__host__ __device__ inline void aux_flux(const Aux& a, double gm1, const double n[3], double F[5]) {
+  const double p = 0.5 * a.rho / a.beta;
+  const double un = a.u[0] * n[0] + a.u[1] * n[1] + a.u[2] * n[2];
+  const double H = p / gm1 + 0.5 * a.rho * a.k + p;
+  F[0] = a.rho * un;
+  F[1] = a.rho * a.u[0] * un + p * n[0];
+  F[2] = a.rho * a.u[1] * un + p * n[1];
+  F[3] = a.rho * a.u[2] * un + p * n[2];
+  F[4] = H * un;
 }
 
 // Advective flux of U in direction n (not normalised).
@@ -148,31 +214,22 @@ __host__ __device__ inline void viscous_flux(const Prim& q, const double g[12], 
   Gn[0] = acc[0]; Gn[1] = acc[1]; Gn[2] = acc[2]; Gn[3] = acc[3];
 }
 
-// Outward (master) surface flux at one face node:
-// Phi = [F*(UL,UR).n - lambda_max/2 (UR-UL)] s - 1/2 (G(UL,gL) + G(UR,gR)).n s
-template <typename FT, int FORM, int PHYS>
-__host__ __device__ inline void surface_flux(const double UL[5], const double UR[5], const double* gL,
-                                             const double* gR, const double nh[3], double s, const Phys& P,
-                                             double Phi[5]) {
+// Advective part of the outward (master) surface flux at one face node:
+// Phi = [F*(UL,UR).n - lambda_max/2 (UR-UL)] s.
+template <typename FT, int FORM>
+__host__ __device__ inline void surface_flux_adv(const double UL[5], const double UR[5], const double nh[3], double s,
+                                                 const Phys& P, double Phi[5]) {
   const Prim qL = cons2prim(UL, P.gm1), qR = cons2prim(UR, P.gm1);
   const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
-  if constexpr (FORM == 0) {
+  if (FORM == 1 && P.twopoint == 0) {
+    const Aux aL = make_aux(qL), aR = make_aux(qR);
+    chandrashekar<FT>(aL, aR, nv, 0.5 / P.gm1, Phi);
+  } else {
     double FL[5], FR[5];
     euler_flux<FT>(UL, qL, nv, FL);
     euler_flux<FT>(UR, qR, nv, FR);
 #pragma unroll
     for (int v = 0; v < 5; ++v) Phi[v] = 0.5 * (FL[v] + FR[v]);
-  } else {
-    if (P.twopoint == 0) {
-      const Aux aL = make_aux(qL), aR = make_aux(qR);
-      chandrashekar<FT>(aL, aR, nv, 0.5 / P.gm1, Phi);
-    } else {
-      double FL[5], FR[5];
-      euler_flux<FT>(UL, qL, nv, FL);
-      euler_flux<FT>(UR, qR, nv, FR);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) Phi[v] = 0.5 * (FL[v] + FR[v]);
-    }
   }
   if (P.riemann == 0) {
     const FT cL = sqrt(FT(P.gamma) * FT(qL.p) / FT(qL.rho));
@@ -185,15 +242,24 @@ __host__ __device__ inline void surface_flux(const double UL[5], const double UR
 #pragma unroll
     for (int v = 0; v < 5; ++v) Phi[v] -= hs * (UR[v] - UL[v]);
   }
+}
+
+// Outward (master) surface flux at one face node:
+// Phi = [F*(UL,UR).n - lambda_max/2 (UR-UL)] s - 1/2 (G(UL,gL) + G(UR,gR)).n s
+template <typename FT, int FORM, int PHYS>
+__host__ __device__ inline void surface_flux(const double UL[5], const double UR[5], const double* gL,
+                                             const double* gR, const double nh[3], double s, const Phys& P,
+                                             double Phi[5]) {
+  surface_flux_adv<FT, FORM>(UL, UR, nh, s, P, Phi);
   if constexpr (PHYS == 1) {
+    const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
     double GL[4], GR[4];
-    viscous_flux<FT>(qL, gL, P, nv, GL);
-    viscous_flux<FT>(qR, gR, P, nv, GR);
+    viscous_flux<FT>(cons2prim(UL, P.gm1), gL, P, nv, GL);
+    viscous_flux<FT>(cons2prim(UR, P.gm1), gR, P, nv, GR);
 #pragma unroll
     for (int v = 0; v < 4; ++v) Phi[1 + v] -= 0.5 * (GL[v] + GR[v]);
   }
 }
-
 
 // ---------------------------------------------------------------------------
 // Vector-Jacobian products (reverse mode, FP64).  Each function returns
