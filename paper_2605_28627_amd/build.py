@@ -32,24 +32,29 @@ def _compile(src, obj, extra=()):
     return obj
 
 
-def build(jobs: int | None = None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    units = [(os.path.join(CSRC, "dgx_host.cpp"), os.path.join(BUILD, "dgx_host.o"), ()),
-             (os.path.join(CSRC, "dgx_launch.hip"), os.path.join(BUILD, "dgx_launch.o"), ())]
+def build(jobs: int | None = None, defines=(), out: str | None = None, build_dir: str | None = None) -> str:
+    """Compile and link libdgx.so (defines: extra -D options, e.g. tuning switches)."""
+    bdir = build_dir or BUILD
+    os.makedirs(bdir, exist_ok=True)
+    dflags = tuple(f"-D{d}" for d in defines)
+    units = [(os.path.join(CSRC, "dgx_host.cpp"), os.path.join(bdir, "dgx_host.o"), dflags),
+             (os.path.join(CSRC, "dgx_launch.hip"), os.path.join(bdir, "dgx_launch.o"), dflags)]
     for n in DEGREES:
-        units.append((os.path.join(CSRC, "dgx_inst.hip"), os.path.join(BUILD, f"dgx_inst_N{n}.o"),
-                      (f"-DDGX_INST_N={n}",)))
+        units.append((os.path.join(CSRC, "dgx_inst.hip"), os.path.join(bdir, f"dgx_inst_N{n}.o"),
+                      (f"-DDGX_INST_N={n}",) + dflags))
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda u: _compile(*u), units))
-    tmp = LIB + ".tmp"
+    target = out or LIB
+    tmp = target + ".tmp"
     cmd = [HIPCC, "-shared", "--offload-arch=gfx950", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    build_pointwise_check()
-    return LIB
+    os.replace(tmp, target)
+    if out is None:
+        build_pointwise_check()
+    return target
 
 
 def build_pointwise_check() -> str:

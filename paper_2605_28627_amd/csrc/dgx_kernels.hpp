@@ -274,6 +274,12 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
 //   4. surface lift, 1/J, and the output or the RK stage;
 //   5. face traces of the new state (RK stage).
 // ---------------------------------------------------------------------------
+// Symmetric evaluation of two-point pairs on lines that lie inside one
+// wavefront (see k_volume); 0 evaluates every ordered pair.
+#ifndef DGX_SYMMETRIC_PAIRS
+#define DGX_SYMMETRIC_PAIRS 1
+#endif
+
 template <int N, int NODES, int FORM, int PHYS, int PREC, int MODE>
 __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void k_volume(Geo G, Phys P, const double* __restrict__ U,
                                                           const double* __restrict__ Utr,
@@ -290,6 +296,9 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
   constexpr int SZ_WEAK = 5 * n3;                                    // F~^r
   constexpr int SZ_V = FORM == 1 ? SZ_SPLIT : SZ_WEAK;
   constexpr int SZ = SZ_V > 5 * n3 ? SZ_V : 5 * n3;                  // also holds the new state (Gauss traces)
+  // lines along xi and eta (all three for n1 = 4) lie inside one wavefront
+  // when n1 is a power of two and an element fills whole wavefronts
+  constexpr bool kSymLines = DGX_SYMMETRIC_PAIRS && (n1 == 4 || n1 == 8) && (n3 % 64 == 0);
   __shared__ double sphi[5 * S::nface];
   __shared__ double sm[SZ];
   __shared__ DevBasis sb;
@@ -364,8 +373,9 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
       sm[4 * n3 + t] = me.beta; sm[5 * n3 + t] = me.lrho; sm[6 * n3 + t] = me.lbeta; sm[7 * n3 + t] = me.k;
     }
   }
-  // 3. volume integral, one reference direction at a time
-#pragma unroll 1
+  // 3. volume integral, one reference direction at a time (unrolled, so
+  // that G~^r is indexed statically rather than through register indexing)
+#pragma unroll
   for (int r = 0; r < 3; ++r) {
     double jr[3] = {0, 0, 0};
     if (act) {
@@ -388,22 +398,14 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
         const int a = idx[r];
         const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
         const double c1 = 0.5 / P.gm1;
-        for (int l = 0; l < n1; ++l) {
-          const int tl = line_node<N>(r, l, pp, qq);
-          if constexpr (PHYS == 1) {
-            // viscous part in weak form: acc -= Dhat[a][l] G~^r_l
-            const double c = sb.Dhat[a * n1 + l];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[1 + v] -= c * sgv[v * n3 + tl];
-          }
-          if (l == a) continue;
+        // two-point flux F#(U_a, U_l) . avg(Ja^r) with the partner node tl
+        auto pair_flux = [&](int tl, double F[5]) {
           Aux ot;
           ot.rho = sm[0 * n3 + tl]; ot.u[0] = sm[1 * n3 + tl]; ot.u[1] = sm[2 * n3 + tl];
           ot.u[2] = sm[3 * n3 + tl]; ot.beta = sm[4 * n3 + tl]; ot.lrho = sm[5 * n3 + tl];
           ot.lbeta = sm[6 * n3 + tl]; ot.k = sm[7 * n3 + tl];
           const double nv[3] = {0.5 * (jr[0] + sja[0 * n3 + tl]), 0.5 * (jr[1] + sja[1 * n3 + tl]),
                                 0.5 * (jr[2] + sja[2 * n3 + tl])};
-          double F[5];
           if (P.twopoint == 0) {
             chandrashekar<FT>(me, ot, nv, c1, F);
           } else {
@@ -414,9 +416,56 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
 #pragma unroll
             for (int v = 0; v < 5; ++v) F[v] = 0.5 * (Fa[v] + Fb[v]);
           }
-          const double ds = sb.DS[a * n1 + l];
+        };
+        if (kSymLines && (n1 == 4 || r < 2)) {
+          // The line lies inside this wavefront, its nodes kStride apart in
+          // lanes.  F# is symmetric in its two states, so the pair (a, a+d) is
+          // evaluated once, by the lane of a: it keeps -DS[a][a+d] F and hands
+          // -DS[a+d][a] F to the lane of a+d, receiving the share of the pair
+          // (a-d, a) in turn.  The pair at distance n1/2 is met from both ends
+          // and each lane keeps its own share.
+          if constexpr (PHYS == 1) {
+            // viscous part in weak form: acc -= Dhat[a][l] G~^r_l
+            for (int l = 0; l < n1; ++l) {
+              const int tl = line_node<N>(r, l, pp, qq);
+              const double c = sb.Dhat[a * n1 + l];
 #pragma unroll
-          for (int v = 0; v < 5; ++v) acc[v] -= ds * F[v];
+              for (int v = 0; v < 4; ++v) acc[1 + v] -= c * sgv[v * n3 + tl];
+            }
+          }
+          const int lane = t & 63;
+          const int str = r == 0 ? 1 : (r == 1 ? n1 : n2);
+#pragma unroll 1
+          for (int d = 1; d <= n1 / 2; ++d) {
+            const int b = (a + d) & (n1 - 1);
+            double F[5];
+            pair_flux(line_node<N>(r, b, pp, qq), F);
+            const double dab = sb.DS[a * n1 + b];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) acc[v] -= dab * F[v];
+            if (d < n1 / 2) {
+              const double dba = sb.DS[b * n1 + a];
+              const int src = lane + (((a - d) & (n1 - 1)) - a) * str;
+#pragma unroll
+              for (int v = 0; v < 5; ++v) acc[v] += __shfl(-dba * F[v], src);
+            }
+          }
+        } else {
+          for (int l = 0; l < n1; ++l) {
+            const int tl = line_node<N>(r, l, pp, qq);
+            if constexpr (PHYS == 1) {
+              // viscous part in weak form: acc -= Dhat[a][l] G~^r_l
+              const double c = sb.Dhat[a * n1 + l];
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[1 + v] -= c * sgv[v * n3 + tl];
+            }
+            if (l == a) continue;
+            double F[5];
+            pair_flux(tl, F);
+            const double ds = sb.DS[a * n1 + l];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) acc[v] -= ds * F[v];
+          }
         }
       }
       __syncthreads();

@@ -12,6 +12,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: it loads its own HIP runtime (libamdhip64 and the HSA runtime),
+# and libdgx.so must resolve to that already-loaded copy.  Loaded the other
+# way round, the process holds two HIP runtimes and the second sees no device.
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdgx.so")
