@@ -65,17 +65,27 @@ PROFILE = os.path.join(ROOT, "profiles", "k_volume_ns_split_n7_16x16x16_tgv.md")
 VOLUME_KERNEL = "void dgx::k_volume<7, 1, 1, 1, 0, 1>"
 
 
+KERNEL_SOURCES = ("dgx_kernels.hpp", "dgx_pointwise.hpp", "dgx_internal.hpp", "dgx_inst.hip")
+
+
+def kernel_source_hash():
+    """sha256[:16] over the sources the residual kernels are compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2605_28627_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel):
     """Calibrated HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a
     plain copy of known size) from the committed rocprofv3 summary, or None
     when the kernel source has changed since the counters were taken."""
-    import hashlib
     import re
     try:
         txt = open(PROFILE).read()
         meta = json.loads(re.search(r"```json\n(.*?)\n```", txt, re.S).group(1))
-        src = open(os.path.join(ROOT, "paper_2605_28627_amd", "csrc", "dgx_kernels.hpp"), "rb").read()
-        if hashlib.sha256(src).hexdigest()[:16] != meta["source_sha256_16"]:
+        if kernel_source_hash() != meta["source_sha256_16"]:
             return None
         k = meta["kernels"][kernel]
         return k["read"] + k["write"]
@@ -95,16 +105,17 @@ def volume_kernel_bytes_per_dof(w):
 
     Reads: U (5), metrics Ja (9) and 1/J (1), dU (5), and per face node of
     each of the element's 6 faces both sides' traces (2 x 5) and the face
-    normal + area (4); Navier-Stokes adds the lifted gradients (12) and both
-    sides' gradient traces (2 x 12).  Writes: dU (5), U (5) and the element's
-    own traces of the new state (5 per face node).  8 bytes each.
+    normal + area (4); Navier-Stokes adds the contravariant viscous fluxes
+    G~^r (12) and both sides' face-normal viscous fluxes (2 x 4), formed by
+    the lifting kernel.  Writes: dU (5), U (5) and the element's own traces
+    of the new state (5 per face node).  8 bytes each.
     """
     n1 = w["N"] + 1
     fpn = 6 * n1 * n1 / n1 ** 3          # face nodes of one element per volume node
     reads = 5 + 9 + 1 + 5 + fpn * (10 + 4)
     writes = 5 + 5 + fpn * 5
     if w["physics"] == 1:
-        reads += 12 + fpn * 24
+        reads += 12 + fpn * 8
     return 8.0 * (reads + writes)
 
 

@@ -613,7 +613,7 @@ static dg_status stage(dg_ctx* c, int mode, const double* U, double* Ut, double*
   Work w = kwork(c);
   if (c->cfg.physics == DG_PHYS_NAVIER_STOKES) {
     ProfScope ps(c, FAM_LIFT, s);
-    LAUNCHCHK(c, launch_lift(k, g, c->phys, U, w.Utr[cur], w.g, w.gtr, s));
+    LAUNCHCHK(c, launch_lift(k, 1, g, c->phys, U, w.Utr[cur], w.g, w.gtr, s));
   }
   ProfScope ps(c, FAM_VOLUME, s);
   LAUNCHCHK(c, launch_volume(k, g, c->phys, mode, U, w.Utr[cur], w.g, w.gtr, Ut, Uio, dU, w.Utr[cur ^ 1], A, B, dt, s));
@@ -643,7 +643,7 @@ dg_status dg_lift(dg_ctx* c, const double* U, double* gout, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   Work w = kwork(c);
   LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), U, w.Utr[0], s));
-  LAUNCHCHK(c, launch_lift(kcfg(c), kgeo(c), c->phys, U, w.Utr[0], gout, w.gtr, s));
+  LAUNCHCHK(c, launch_lift(kcfg(c), 0, kgeo(c), c->phys, U, w.Utr[0], gout, w.gtr, s));
   return DG_OK;
 }
 
@@ -700,7 +700,7 @@ static dg_status adjoint_residual(dg_ctx* c, const double* U, const double* lam,
   }
   if (k.physics == DG_PHYS_NAVIER_STOKES) {
     ProfScope ps(c, FAM_LIFT, s);
-    LAUNCHCHK(c, launch_lift(k, g, c->phys, U, w.Utr[0], w.g, w.gtr, s));
+    LAUNCHCHK(c, launch_lift(k, 0, g, c->phys, U, w.Utr[0], w.g, w.gtr, s));
   }
   ProfScope ps(c, FAM_ADJOINT, s);
   LAUNCHCHK(c, launch_adjoint(k, g, c->phys, U, lam, w.Utr[0], w.Utr[1], w.g, w.gtr, out, gbar, s));

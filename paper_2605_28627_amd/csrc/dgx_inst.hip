@@ -25,51 +25,62 @@ hipError_t DGX_NAME(launch_trace)(const Cfg& c, const Geo& g, const double* U, d
   return hipGetLastError();
 }
 
-hipError_t DGX_NAME(launch_lift)(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* Utr,
-                                 double* gout, double* gtr, hipStream_t s) {
+template <int NODES>
+static void lift_emit(const Cfg& c, int emit, const Geo& g, const Phys& p, const double* U, const double* Utr,
+                      double* gout, double* gtr, hipStream_t s) {
   const dim3 grid(g.nElems), block(Shape<kN>::nth);
-  if (c.nodes == 1)
-    hipLaunchKernelGGL((k_lift<kN, 1>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+  if (emit == 0)
+    hipLaunchKernelGGL((k_lift<kN, NODES, 0, 0>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+  else if (c.precision == 0)
+    hipLaunchKernelGGL((k_lift<kN, NODES, 1, 0>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
   else
-    hipLaunchKernelGGL((k_lift<kN, 0>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+    hipLaunchKernelGGL((k_lift<kN, NODES, 1, 1>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+}
+
+hipError_t DGX_NAME(launch_lift)(const Cfg& c, int emit, const Geo& g, const Phys& p, const double* U,
+                                 const double* Utr, double* gout, double* gtr, hipStream_t s) {
+  if (c.nodes == 1)
+    lift_emit<1>(c, emit, g, p, U, Utr, gout, gtr, s);
+  else
+    lift_emit<0>(c, emit, g, p, U, Utr, gout, gtr, s);
   return hipGetLastError();
 }
 
 template <int NODES, int FORM, int PHYS, int PREC>
-static void vol_mode(int mode, const Geo& g, const Phys& p, const double* U, const double* Utr, const double* gin,
-                     const double* gtr, double* Ut, double* Uio, double* dU, double* Utr_next, double A, double B,
+static void vol_mode(int mode, const Geo& g, const Phys& p, const double* U, const double* Utr, const double* gvn,
+                     const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next, double A, double B,
                      double dt, hipStream_t s) {
   const dim3 grid(g.nElems), block(Shape<kN>::nth);
   if (mode == 0)
-    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, PREC, 0>), grid, block, 0, s, g, p, U, Utr, gin, gtr, Ut,
+    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, PREC, 0>), grid, block, 0, s, g, p, U, Utr, gvn, gvf, Ut,
                        Uio, dU, Utr_next, A, B, dt);
   else
-    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, PREC, 1>), grid, block, 0, s, g, p, U, Utr, gin, gtr, Ut,
+    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, PREC, 1>), grid, block, 0, s, g, p, U, Utr, gvn, gvf, Ut,
                        Uio, dU, Utr_next, A, B, dt);
 }
 
 template <int NODES, int FORM>
 static void vol_phys(const Cfg& c, int mode, const Geo& g, const Phys& p, const double* U, const double* Utr,
-                     const double* gin, const double* gtr, double* Ut, double* Uio, double* dU, double* Utr_next,
+                     const double* gvn, const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next,
                      double A, double B, double dt, hipStream_t s) {
   if (c.physics == 0) {
-    if (c.precision == 0) vol_mode<NODES, FORM, 0, 0>(mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
-    else vol_mode<NODES, FORM, 0, 1>(mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    if (c.precision == 0) vol_mode<NODES, FORM, 0, 0>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    else vol_mode<NODES, FORM, 0, 1>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   } else {
-    if (c.precision == 0) vol_mode<NODES, FORM, 1, 0>(mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
-    else vol_mode<NODES, FORM, 1, 1>(mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    if (c.precision == 0) vol_mode<NODES, FORM, 1, 0>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    else vol_mode<NODES, FORM, 1, 1>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   }
 }
 
 hipError_t DGX_NAME(launch_volume)(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U,
-                                   const double* Utr, const double* gin, const double* gtr, double* Ut, double* Uio,
+                                   const double* Utr, const double* gvn, const double* gvf, double* Ut, double* Uio,
                                    double* dU, double* Utr_next, double A, double B, double dt, hipStream_t s) {
   if (c.nodes == 0)
-    vol_phys<0, 0>(c, mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    vol_phys<0, 0>(c, mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   else if (c.form == 0)
-    vol_phys<1, 0>(c, mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    vol_phys<1, 0>(c, mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   else
-    vol_phys<1, 1>(c, mode, g, p, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    vol_phys<1, 1>(c, mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   return hipGetLastError();
 }
 

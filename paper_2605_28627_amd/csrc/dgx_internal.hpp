@@ -70,11 +70,16 @@ struct Cfg {
 // Launchers (defined in the kernel translation units).  Each returns the
 // result of hipGetLastError() after the launch.
 hipError_t launch_trace(const Cfg& c, const Geo& g, const double* U, double* Utr, hipStream_t s);
-hipError_t launch_lift(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* Utr, double* gout,
-                       double* gtr, hipStream_t s);
+// BR1 lifting.  emit 0: gradients g [12][nE][n3] and their traces
+// [2][12][nSides][n2].  emit 1: the viscous fluxes the residual needs,
+// G~^r [4r+v][nE][n3] and the per-side face-normal fluxes [2][4][nSides][n2]
+// (in the buffers of g and of the traces).
+hipError_t launch_lift(const Cfg& c, int emit, const Geo& g, const Phys& p, const double* U, const double* Utr,
+                       double* gout, double* gtr, hipStream_t s);
 // mode 0: Ut = R(U).  mode 1: dU = A dU + dt R(U); U += B dU; traces of the new U -> Utr_next.
+// Navier-Stokes: gvn, gvf are the viscous fluxes written by launch_lift(emit 1).
 hipError_t launch_volume(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U, const double* Utr,
-                         const double* gin, const double* gtr, double* Ut, double* Uio, double* dU, double* Utr_next,
+                         const double* gvn, const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next,
                          double A, double B, double dt, hipStream_t s);
 
 // out = (dR/dU)^T lam; Utr holds the traces of U, Lbar/gtr/gbar are scratch

@@ -108,14 +108,19 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace(Geo G, const double* __
 }
 
 // ---------------------------------------------------------------------------
-// BR1 lifting kernel (paper eq. dgsem_lifted): g = grad (u, v, w, T) -> gout,
-// and its face traces -> gtr[slot][12][side][master (p,q)].
+// BR1 lifting kernel (paper eq. dgsem_lifted), g = grad (u, v, w, T).
+// EMIT 0: g -> gout[12][nE][n3] and its face traces -> gtr[slot][12][side][fi].
+// EMIT 1: what the residual consumes instead of g, formed here once per node:
+//   gout[4r+v][nE][n3] = G~^r_v = Ja^r . G_v(q, g)      (contravariant viscous flux)
+//   gtr[slot][4][side][fi] = G_v(q_tr, g_tr) . n s       (per side, master normal)
+// with q_tr the state trace of that side; FT is the flux arithmetic type.
 // ---------------------------------------------------------------------------
-template <int N, int NODES>
+template <int N, int NODES, int EMIT, int PREC>
 __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const double* __restrict__ U,
                                                         const double* __restrict__ Utr, double* __restrict__ gout,
                                                         double* __restrict__ gtr) {
   using S = Shape<N>;
+  using FT = typename std::conditional<PREC == 1, float, double>::type;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
   constexpr int SZ = (13 * n3 > 7 * S::nface ? 13 * n3 : 7 * S::nface);
   constexpr int SZ2 = (12 * n3 > SZ ? 12 * n3 : SZ);
@@ -130,11 +135,12 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
   const bool act = t < n3;
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   double sJ = 0.0;
+  Prim q{};
   if (act) {
     double u[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
-    const Prim q = cons2prim(u, P.gm1);
+    q = cons2prim(u, P.gm1);
     sq[0 * n3 + t] = q.u[0];
     sq[1 * n3 + t] = q.u[1];
     sq[2 * n3 + t] = q.u[2];
@@ -148,9 +154,9 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
     const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
     const int info = G.efc[e * 6 + f];
     const int side = efc_side(info), slot = efc_slot(info);
-    int p = pp, q = qq;
-    if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
-    const int fi = q * n1 + p;
+    int p = pp, qm = qq;
+    if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+    const int fi = qm * n1 + p;
     double UL[5], UR[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -213,11 +219,35 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
       }
     }
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      acc[c] *= sJ;
-      gout[((size_t)c * nE + e) * n3 + t] = acc[c];
+    for (int c = 0; c < 12; ++c) acc[c] *= sJ;
+    if constexpr (EMIT == 0) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) gout[((size_t)c * nE + e) * n3 + t] = acc[c];
+    } else {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double jr[3] = {sja[(3 * r + 0) * n3 + t], sja[(3 * r + 1) * n3 + t], sja[(3 * r + 2) * n3 + t]};
+        double Gr[4];
+        viscous_flux<FT>(q, acc, P, jr, Gr);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gout[((size_t)(4 * r + v) * nE + e) * n3 + t] = Gr[v];
+      }
     }
   }
+  // face-normal viscous flux of one side from the gradient trace gf
+  auto emit_face = [&](int slot, int side, int fi, const double gf[12]) {
+    double ut[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ut[v] = Utr[tr_index(slot, v, 5, nS, side, n2, fi)];
+    const double nh[3] = {G.face[((size_t)0 * nS + side) * n2 + fi], G.face[((size_t)1 * nS + side) * n2 + fi],
+                          G.face[((size_t)2 * nS + side) * n2 + fi]};
+    const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
+    const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
+    double Gn[4];
+    viscous_flux<FT>(cons2prim(ut, P.gm1), gf, P, nv, Gn);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gtr[tr_index(slot, v, 4, nS, side, n2, fi)] = Gn[v];
+  };
   // gradient traces
   if constexpr (NODES == 1) {
     if (act) {
@@ -230,10 +260,14 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
         const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
         const int info = G.efc[e * 6 + f];
         const int side = efc_side(info), slot = efc_slot(info);
-        int p = pp, q = qq;
-        if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
+        int p = pp, qm = qq;
+        if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+        if constexpr (EMIT == 0) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) gtr[tr_index(slot, c, 12, nS, side, n2, q * n1 + p)] = acc[c];
+          for (int c = 0; c < 12; ++c) gtr[tr_index(slot, c, 12, nS, side, n2, qm * n1 + p)] = acc[c];
+        } else {
+          emit_face(slot, side, qm * n1 + p, acc);
+        }
       }
     }
   } else {
@@ -247,13 +281,25 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
       const double* L = (f & 1) ? sb.Lp : sb.Lm;
       const int info = G.efc[e * 6 + f];
       const int side = efc_side(info), slot = efc_slot(info);
-      int p = pp, q = qq;
-      if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
-      for (int c = 0; c < 12; ++c) {
-        double s = 0.0;
+      int p = pp, qm = qq;
+      if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+      if constexpr (EMIT == 0) {
+        for (int c = 0; c < 12; ++c) {
+          double s = 0.0;
 #pragma unroll
-        for (int a = 0; a < n1; ++a) s += L[a] * sm[c * n3 + line_node<N>(r, a, pp, qq)];
-        gtr[tr_index(slot, c, 12, nS, side, n2, q * n1 + p)] = s;
+          for (int a = 0; a < n1; ++a) s += L[a] * sm[c * n3 + line_node<N>(r, a, pp, qq)];
+          gtr[tr_index(slot, c, 12, nS, side, n2, qm * n1 + p)] = s;
+        }
+      } else {
+        double gf[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          double s = 0.0;
+#pragma unroll
+          for (int a = 0; a < n1; ++a) s += L[a] * sm[c * n3 + line_node<N>(r, a, pp, qq)];
+          gf[c] = s;
+        }
+        emit_face(slot, side, qm * n1 + p, gf);
       }
     }
   }
@@ -264,11 +310,13 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
 // lift, Jacobian scaling; MODE 0 writes U_t, MODE 1 applies one LSERK stage
 // and writes the face traces of the new state for the next stage.
 //
+// Navier-Stokes: the viscous fluxes come from the lifting kernel (EMIT 1):
+// gvn holds G~^r at every node, gvf the face-normal flux of each side.
+//
 // Phases, so that live ranges do not stack (registers and LDS decide how
 // many elements share a CU):
 //   1. surface fluxes of the six faces -> LDS (before any volume state is live);
-//   2. per-node two-point data -> LDS (split form), viscous contravariant
-//      fluxes G~^r in registers (Navier-Stokes);
+//   2. per-node two-point data -> LDS (split form);
 //   3. per direction r: the metric row Ja^r (and G~^r) -> LDS, then flux
 //      differencing along r (split) or the D-hat contraction of F~^r (weak);
 //   4. surface lift, 1/J, and the output or the RK stage;
@@ -283,8 +331,8 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
 template <int N, int NODES, int FORM, int PHYS, int PREC, int MODE>
 __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void k_volume(Geo G, Phys P, const double* __restrict__ U,
                                                           const double* __restrict__ Utr,
-                                                          const double* __restrict__ gin,
-                                                          const double* __restrict__ gtr, double* __restrict__ Ut,
+                                                          const double* __restrict__ gvn,
+                                                          const double* __restrict__ gvf, double* __restrict__ Ut,
                                                           double* __restrict__ Uio, double* __restrict__ dU,
                                                           double* __restrict__ Utr_next, double A, double B,
                                                           double dt) {
@@ -325,17 +373,11 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
     double Phi[5];
     surface_flux_adv<FT, FORM>(UL, UR, nh, s, P, Phi);
     if constexpr (PHYS == 1) {
-      const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
-#pragma unroll 1
-      for (int sd = 0; sd < 2; ++sd) {
-        double gg[12];
+      // face-normal viscous fluxes of the two sides, formed by the lifting
 #pragma unroll
-        for (int c = 0; c < 12; ++c) gg[c] = gtr[tr_index(sd, c, 12, nS, side, n2, fi)];
-        double Gn[4];
-        viscous_flux<FT>(cons2prim(sd ? UR : UL, P.gm1), gg, P, nv, Gn);
+      for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Phi[1 + v] -= 0.5 * Gn[v];
-      }
+        for (int v = 0; v < 4; ++v) Phi[1 + v] -= 0.5 * gvf[tr_index(sd, v, 4, nS, side, n2, fi)];
     }
     const double sgn = slot ? -1.0 : 1.0;
 #pragma unroll
@@ -348,22 +390,10 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
   double u[5] = {0, 0, 0, 0, 0};
   double acc[5] = {0, 0, 0, 0, 0};
   Prim q{};
-  double Gt[3][4];
   if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
     q = cons2prim(u, P.gm1);
-    if constexpr (PHYS == 1) {
-      double gl[12];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) gl[c] = gin[((size_t)c * nE + e) * n3 + t];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const double nv[3] = {G.Ja[((size_t)(3 * r) * nE + e) * n3 + t], G.Ja[((size_t)(3 * r + 1) * nE + e) * n3 + t],
-                              G.Ja[((size_t)(3 * r + 2) * nE + e) * n3 + t]};
-        viscous_flux<FT>(q, gl, P, nv, Gt[r]);
-      }
-    }
   }
   Aux me{};
   if constexpr (FORM == 1) {
@@ -373,8 +403,8 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
       sm[4 * n3 + t] = me.beta; sm[5 * n3 + t] = me.lrho; sm[6 * n3 + t] = me.lbeta; sm[7 * n3 + t] = me.k;
     }
   }
-  // 3. volume integral, one reference direction at a time (unrolled, so
-  // that G~^r is indexed statically rather than through register indexing)
+  // 3. volume integral, one reference direction at a time (unrolled: the
+  // line strides and the symmetric-pair choice are then constants)
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     double jr[3] = {0, 0, 0};
@@ -390,7 +420,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
         for (int c = 0; c < 3; ++c) sja[c * n3 + t] = jr[c];
         if constexpr (PHYS == 1) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) sgv[v * n3 + t] = Gt[r][v];
+          for (int v = 0; v < 4; ++v) sgv[v * n3 + t] = gvn[((size_t)(4 * r + v) * nE + e) * n3 + t];
         }
       }
       __syncthreads();
@@ -476,7 +506,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
         euler_flux<FT>(u, q, jr, F);
         if constexpr (PHYS == 1) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) F[1 + v] -= Gt[r][v];
+          for (int v = 0; v < 4; ++v) F[1 + v] -= gvn[((size_t)(4 * r + v) * nE + e) * n3 + t];
         }
 #pragma unroll
         for (int v = 0; v < 5; ++v) sm[v * n3 + t] = F[v];

@@ -8,8 +8,8 @@ namespace dgx {
 
 #define DGX_DECL(n)                                                                                           \
   hipError_t launch_trace_N##n(const Cfg&, const Geo&, const double*, double*, hipStream_t);                 \
-  hipError_t launch_lift_N##n(const Cfg&, const Geo&, const Phys&, const double*, const double*, double*,   \
-                              double*, hipStream_t);                                                          \
+  hipError_t launch_lift_N##n(const Cfg&, int, const Geo&, const Phys&, const double*, const double*,      \
+                              double*, double*, hipStream_t);                                                 \
   hipError_t launch_volume_N##n(const Cfg&, const Geo&, const Phys&, int, const double*, const double*,      \
                                 const double*, const double*, double*, double*, double*, double*, double,   \
                                 double, double, hipStream_t);                                                  \
@@ -42,9 +42,9 @@ hipError_t launch_trace(const Cfg& c, const Geo& g, const double* U, double* Utr
 #undef ARGS
 }
 
-hipError_t launch_lift(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* Utr, double* gout,
-                       double* gtr, hipStream_t s) {
-#define ARGS (c, g, p, U, Utr, gout, gtr, s)
+hipError_t launch_lift(const Cfg& c, int emit, const Geo& g, const Phys& p, const double* U, const double* Utr,
+                       double* gout, double* gtr, hipStream_t s) {
+#define ARGS (c, emit, g, p, U, Utr, gout, gtr, s)
   DGX_SWITCH(launch_lift)
 #undef ARGS
 }
