@@ -353,6 +353,41 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
   const int e = blockIdx.x, t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
   load_basis(&sb, G.basis, t, S::nth);
+  const bool act = t < n3;
+  const int i = t % n1, j = (t / n1) % n1, k = t / n2;
+  const int idx[3] = {i, j, k};
+  // Loads of the own state and of direction 0's metric row (and G~^0) are
+  // issued first, so that their latency overlaps the surface fluxes; each
+  // direction then prefetches the next one's while it computes.
+  double u[5] = {0, 0, 0, 0, 0};
+  double jn[3] = {0, 0, 0};
+  double gn[4] = {0, 0, 0, 0};
+  // the last direction prefetches what the RK update reads instead
+  double sJn = 0.0, dUn[5] = {0, 0, 0, 0, 0}, Un[5] = {0, 0, 0, 0, 0};
+  auto fetch_end = [&]() {
+    sJn = G.sJ[(size_t)e * n3 + t];
+    if constexpr (MODE == 1) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const size_t gi = ((size_t)v * nE + e) * n3 + t;
+        dUn[v] = dU[gi];
+        Un[v] = U[gi];
+      }
+    }
+  };
+  auto fetch_dir = [&](int r) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) jn[c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
+    if constexpr (PHYS == 1) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) gn[v] = gvn[((size_t)(4 * r + v) * nE + e) * n3 + t];
+    }
+  };
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+    fetch_dir(0);
+  }
   // 1. surface fluxes (own face-local order, outward sign)
   for (int ft = t; ft < S::nface; ft += S::nth) {
     const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
@@ -384,17 +419,9 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
     for (int v = 0; v < 5; ++v) sphi[(f * 5 + v) * n2 + rr] = sgn * Phi[v];
   }
   // 2. own state
-  const bool act = t < n3;
-  const int i = t % n1, j = (t / n1) % n1, k = t / n2;
-  const int idx[3] = {i, j, k};
-  double u[5] = {0, 0, 0, 0, 0};
   double acc[5] = {0, 0, 0, 0, 0};
   Prim q{};
-  if (act) {
-#pragma unroll
-    for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
-    q = cons2prim(u, P.gm1);
-  }
+  if (act) q = cons2prim(u, P.gm1);
   Aux me{};
   if constexpr (FORM == 1) {
     if (act) {
@@ -407,11 +434,8 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
   // line strides and the symmetric-pair choice are then constants)
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    double jr[3] = {0, 0, 0};
-    if (act) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) jr[c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
-    }
+    const double jr[3] = {jn[0], jn[1], jn[2]};
+    const double gv[4] = {gn[0], gn[1], gn[2], gn[3]};
     if constexpr (FORM == 1) {
       double* sja = sm + 8 * n3;
       double* sgv = sm + 11 * n3;
@@ -420,10 +444,14 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
         for (int c = 0; c < 3; ++c) sja[c * n3 + t] = jr[c];
         if constexpr (PHYS == 1) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) sgv[v * n3 + t] = gvn[((size_t)(4 * r + v) * nE + e) * n3 + t];
+          for (int v = 0; v < 4; ++v) sgv[v * n3 + t] = gv[v];
         }
       }
       __syncthreads();
+      if (act) {
+        if (r < 2) fetch_dir(r + 1);
+        else fetch_end();
+      }
       if (act) {
         const int a = idx[r];
         const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
@@ -506,12 +534,16 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
         euler_flux<FT>(u, q, jr, F);
         if constexpr (PHYS == 1) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) F[1 + v] -= gvn[((size_t)(4 * r + v) * nE + e) * n3 + t];
+          for (int v = 0; v < 4; ++v) F[1 + v] -= gv[v];
         }
 #pragma unroll
         for (int v = 0; v < 5; ++v) sm[v * n3 + t] = F[v];
       }
       __syncthreads();
+      if (act) {
+        if (r < 2) fetch_dir(r + 1);
+        else fetch_end();
+      }
       if (act) {
         const int a = idx[r];
         const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
@@ -549,7 +581,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
           acc[v] -= cm * sphi[((2 * r) * 5 + v) * n2 + rr] + cp * sphi[((2 * r + 1) * 5 + v) * n2 + rr];
       }
     }
-    const double sJ = G.sJ[(size_t)e * n3 + t];
+    const double sJ = sJn;
     if constexpr (MODE == 0) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ut[((size_t)v * nE + e) * n3 + t] = acc[v] * sJ;
@@ -557,9 +589,9 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const size_t gi = ((size_t)v * nE + e) * n3 + t;
-        const double d = A * dU[gi] + dt * (acc[v] * sJ);
+        const double d = A * dUn[v] + dt * (acc[v] * sJ);
         dU[gi] = d;
-        Unew[v] = U[gi] + B * d;   // re-read (cached): keeps U out of the registers of phase 3
+        Unew[v] = Un[v] + B * d;
         Uio[gi] = Unew[v];
       }
     }
