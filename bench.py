@@ -8,19 +8,23 @@ Ma 0.1, Re 1600, Pr 0.72, FP64.  The metric is the paper's PID
 (wall time / (RK stages * DOF), one GPU), lower is better.
 
 Printed as one JSON line.  Besides the contract fields it carries the
-FP32-flux PID on the same workload, the dominant kernel's roofline figures
-(HIP events around every launch of the timed region) and the serial FP64
+FP32-flux PID on the same workload and its error against the FP64 path,
+the adjoint/forward cost, the residual kernel's roofline figures (HIP events
+around every launch of the timed region; HBM bytes from the algorithmic
+count, FP64 FLOPs from the committed rocprofv3 counters) and the serial FP64
 oracle timed on a bounded sample of the same workload on the host.
+
+Other workloads (--workload, --K, --state) and repetitions (--reps, median)
+serve the per-configuration measurements.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
-
-import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -28,6 +32,7 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "ns_split_lgl_n7_16x16x16_tgv"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+KERNEL_SOURCES = ("dgx_kernels.hpp", "dgx_pointwise.hpp", "dgx_internal.hpp", "dgx_inst.hip")
 
 
 def parse():
@@ -35,11 +40,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--reps", type=int, default=1, help="timed repetitions of --steps steps; the median is reported")
     ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--K", default=None, help="element counts K1,K2,K3 replacing the workload's")
+    ap.add_argument("--state", default=None, choices=[None, "freestream"], help="replace the initial state")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=4)
+    ap.add_argument("--checkpoint-every", type=int, default=None)
     ap.add_argument("--cpu-sample-elems", type=int, default=4096)
     ap.add_argument("--cpu-repeats", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -61,11 +70,23 @@ def copy_calibration():
                                            "copies": 5}}), flush=True)
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_volume_ns_split_n7_16x16x16_tgv.md")
-VOLUME_KERNEL = "void dgx::k_volume<7, 1, 1, 1, 0, 1>"
-
-
-KERNEL_SOURCES = ("dgx_kernels.hpp", "dgx_pointwise.hpp", "dgx_internal.hpp", "dgx_inst.hip")
+def measured_copy_gbs():
+    """Read + write rate of a plain 1 GiB device copy (the practical HBM ceiling for context)."""
+    import torch
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del a, b
+    return 16.0 * n / (ms * 1e-3) / 1e9
 
 
 def kernel_source_hash():
@@ -77,18 +98,21 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """Calibrated HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a
-    plain copy of known size) from the committed rocprofv3 summary, or None
-    when the kernel source has changed since the counters were taken."""
+def profile_path(workload):
+    return os.path.join(ROOT, "profiles", f"k_volume_{workload}.md")
+
+
+def profile_counters(workload, kernel):
+    """Counters of one kernel from the committed rocprofv3 summary of a workload:
+    calibrated HBM bytes read and written and FP64 FLOPs per launch, or None
+    when there is none or the kernel sources have changed since it was taken."""
     import re
     try:
-        txt = open(PROFILE).read()
+        txt = open(profile_path(workload)).read()
         meta = json.loads(re.search(r"```json\n(.*?)\n```", txt, re.S).group(1))
         if kernel_source_hash() != meta["source_sha256_16"]:
             return None
-        k = meta["kernels"][kernel]
-        return k["read"] + k["write"]
+        return meta["kernels"][kernel]
     except (OSError, KeyError, AttributeError, ValueError):
         return None
 
@@ -98,6 +122,10 @@ def workload_cfg(name):
     w = I.WORKLOADS[name]
     return w, dict(N=w["N"], nodes=w["nodes"], form=w["form"], physics=w["physics"], mu=w["mu"], Pr=0.72,
                    gamma=1.4, R=1.0)
+
+
+def volume_kernel_name(w, precision=0):
+    return f"void dgx::k_volume<{w['N']}, {w['nodes']}, {w['form']}, {w['physics']}, {precision}, 1>"
 
 
 def volume_kernel_bytes_per_dof(w):
@@ -137,44 +165,54 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     w, cfg = workload_cfg(args.workload)
-    mesh = I.workload_mesh(args.workload)
+    K = tuple(int(x) for x in args.K.split(",")) if args.K else tuple(w["K"])
+    mesh = I.workload_mesh(args.workload, K=K)
     s = DGSolver(cfg, mesh, dev)
     dof = s.nElems * s.npe
     xyz = s.coords()
-    U0 = s.to_device(I.workload_state(args.workload, xyz))
+    U0 = s.init_state(I.workload_state(args.workload, xyz, state=args.state))
     dt = s.timestep(U0, 0.9)
 
-    def timed(solver, steps, warmup, profile, keep=None):
-        U = U0.clone()
-        dU = torch.zeros_like(U)
-        if warmup:
-            solver.rk_step(U, dU, dt, warmup)
-        torch.cuda.synchronize()
-        if profile:
-            dgx.dg_profile(solver.ctx, 1)
-        t0 = time.perf_counter()
-        solver.rk_step(U, dU, dt, steps)
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        prof = {}
-        if profile:
-            for fam in ("trace", "lift", "volume", "other"):
-                prof[fam] = dgx.dg_profile_query(solver.ctx, fam)
-            dgx.dg_profile(solver.ctx, 0)
-        if solver.check_state(U) != 0:
-            raise RuntimeError("non-physical state after the timed steps")
+    def timed(solver, profile, keep=None):
+        """args.reps repetitions of (warmup, then args.steps timed steps) from U0;
+        returns the wall times and, with profile, the per-family kernel event
+        times of the first repetition's timed region."""
+        times, prof = [], {}
+        for rep in range(args.reps):
+            U = U0.clone()
+            dU = torch.zeros_like(U)
+            if args.warmup:
+                solver.rk_step(U, dU, dt, args.warmup)
+            torch.cuda.synchronize()
+            events = profile and rep == 0
+            if events:
+                dgx.dg_profile(solver.ctx, 1)
+            t0 = time.perf_counter()
+            solver.rk_step(U, dU, dt, args.steps)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            if events:
+                for fam in ("trace", "lift", "volume", "other"):
+                    prof[fam] = dgx.dg_profile_query(solver.ctx, fam)
+                dgx.dg_profile(solver.ctx, 0)
+            if solver.check_state(U) != 0:
+                raise RuntimeError("non-physical state after the timed steps")
         if keep is not None:
             keep.append(U)
-        return t, prof
+        return times, prof
 
     final64 = []
-    t64, prof = timed(s, args.steps, args.warmup, profile=True, keep=final64)
+    times64, prof = timed(s, profile=True, keep=final64)
+    t64 = statistics.median(times64)
     pid64 = t64 / (5 * args.steps * dof)
     vol_ms, vol_n = prof["volume"]
     vol_avg_s = vol_ms * 1e-3 / max(vol_n, 1)
     lift_ms, lift_n = prof["lift"]
     bytes_launch = volume_kernel_bytes_per_dof(w) * dof
     achieved_gbs = bytes_launch / vol_avg_s / 1e9
+    kname = volume_kernel_name(w)
+    counters = profile_counters(args.workload, kname) if (args.K is None and args.state is None) else None
+    form = ("split form" if w["form"] else "weak form") + (", Navier-Stokes" if w["physics"] else ", Euler")
 
     result = {
         "metric": "PID (s per DOF per RK stage) FP64 vs FP32-mixed; adjoint/forward cost",
@@ -188,32 +226,46 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (Taylor-Green vortex initial condition evaluated at the mesh nodes)",
-        "config": {"workload": args.workload, "N": w["N"], "nodes": "LGL", "elements": list(w["K"]),
-                   "dof": dof, "physics": "navier-stokes" if w["physics"] else "euler",
-                   "volume_form": "split" if w["form"] else "weak", "dt": dt},
+        "data": "synthetic (" + ("free stream" if args.state == "freestream" else
+                                 {"tgv": "Taylor-Green vortex", "tgv_noise": "Taylor-Green vortex with seeded "
+                                  "velocity noise", "density_wave": "advected density wave"}[w["state"]]) +
+                " initial condition evaluated at the mesh nodes)",
+        "config": {"workload": args.workload, "N": w["N"], "nodes": "LGL" if w["nodes"] else "LG",
+                   "elements": list(K), "dof": dof, "physics": "navier-stokes" if w["physics"] else "euler",
+                   "volume_form": "split" if w["form"] else "weak", "curved": bool(w["curved"]), "dt": dt,
+                   "state": args.state or w["state"]},
         "dof_updates_per_s": 1.0 / pid64,
+        "reps": args.reps,
+        "ms_per_step_reps": [1e3 * t / args.steps for t in times64],
         "kernels_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in prof.items()},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_volume (split form, Navier-Stokes, RK stage)",
+            "kernel": f"k_volume ({form}, RK stage)",
             "achieved": achieved_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": measured_traffic(VOLUME_KERNEL) if args.workload == WORKLOAD else None,
+            "traffic": (counters["read"] + counters["write"]) if counters else None,
             "algorithmic_bytes_per_launch": bytes_launch,
             "avg_launch_ms": vol_avg_s * 1e3,
             "launches": vol_n,
+            "measured_copy_GBs": measured_copy_gbs(),
         },
     }
+    if counters and counters.get("flops"):
+        tf = counters["flops"] / vol_avg_s / 1e12
+        result["roofline_fp64_valu"] = {"achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                        "frac": tf / FP64_PEAK_TFLOPS, "flops_per_launch": counters["flops"],
+                                        "source": "SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 x 64 lanes (FMA x 2) "
+                                                  "from the committed rocprofv3 summary"}
     if lift_n:
         result["kernels_ms_per_launch"]["lift"] = lift_ms / lift_n
     if not args.no_fp32:
         cfg32 = dict(cfg, precision=1)
         s32 = DGSolver(cfg32, mesh, dev)
         final32 = []
-        t32, _ = timed(s32, args.steps, args.warmup, profile=False, keep=final32)
+        times32, _ = timed(s32, profile=False, keep=final32)
+        t32 = statistics.median(times32)
         result["pid_fp32_flux"] = t32 / (5 * args.steps * dof)
         result["fp32_speedup"] = t64 / t32
         # relative L2 error per variable of the FP32-flux path against the FP64 path
@@ -223,12 +275,14 @@ def main():
         d_state = final32[0] - final64[0]
         d_ref = final64[0] - U0
         result["fp32_l2_error"] = {
-            "residual_rel_per_var": [float((R32[v] - R64[v]).norm() / R64[v].norm()) for v in range(5)],
+            "residual_rel_per_var": [float((R32[v] - R64[v]).norm() / max(float(R64[v].norm()), 1e-300))
+                                     for v in range(5)],
             "state_rel_to_change_per_var": [float(d_state[v].norm() / max(float(d_ref[v].norm()), 1e-300))
                                             for v in range(5)],
             "state_rel_per_var": [float(d_state[v].norm() / final64[0][v].norm()) for v in range(5)],
             "steps": args.steps + args.warmup,
         }
+        del R64, R32, d_state, d_ref, final32
         s32.close()
     result["adjoint_forward_cost"] = adjoint_cost(cfg, mesh, dev, U0, dt, args) if not args.no_adjoint else None
     if not args.no_cpu_baseline:
@@ -241,11 +295,11 @@ def adjoint_cost(cfg, mesh, dev, U0, dt, args):
     """Backward (reverse sweep with recomputation) over forward time of the
     gradient of E_k(T) through args.adjoint_steps steps of the same workload."""
     import torch
-    from paper_2605_28627_amd.autograd import kinetic_energy, trajectory
+    from paper_2605_28627_amd.autograd import checkpoint_interval, kinetic_energy, trajectory
     from paper_2605_28627_amd.solver import DGSolver
     sa = DGSolver(cfg, mesh, dev, adjoint=True)
     n = args.adjoint_steps
-    every = max(1, int(round(n ** 0.5)))
+    every = args.checkpoint_every or checkpoint_interval(sa, n)
     times = []
     for rep in range(2):          # the first repetition warms up
         U = U0.clone().requires_grad_(True)
@@ -258,6 +312,7 @@ def adjoint_cost(cfg, mesh, dev, U0, dt, args):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         times.append((t1 - t0, t2 - t1))
+        del U, J
     sa.close()
     tf, tb = times[-1]
     return {"value": tb / tf, "steps": n, "checkpoint_every": every, "forward_s": tf, "backward_s": tb,
@@ -270,7 +325,7 @@ def cpu_baseline(args, cfg, mesh, xyz, pid_gpu):
     from oracle import oracle as O
     from paper_2605_28627_amd import inputs as I
     o = O.Oracle(cfg, mesh)
-    U = I.workload_state(args.workload, xyz)
+    U = I.workload_state(args.workload, xyz, state=args.state)
     nel = min(args.cpu_sample_elems, mesh.nElems)
     el = list(range(nel))
     t0 = time.perf_counter()

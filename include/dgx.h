@@ -143,6 +143,18 @@ size_t dg_workspace_bytes_adjoint(const dg_ctx* ctx);
  * they fail with DG_ERR_STATE. */
 dg_status dg_bind_workspace(dg_ctx* ctx, void* dev_ptr, size_t bytes);
 
+/* State ------------------------------------------------------------------------ */
+
+/* Initial state (paper: the solution is set from the initial condition before
+ * time stepping).  Copies U_src, conserved variables in the layout
+ * U[5][nElems][n3] and of the state length, into the caller-owned device array
+ * U: from host memory when src_is_device == 0 (pageable or pinned), from
+ * device memory otherwise (U_src == U is allowed and copies nothing).  Then
+ * checks U as dg_check_state does and returns DG_ERR_NONPHYSICAL if a node has
+ * rho <= 0, p <= 0 or a non-finite value (U still holds the copied values).
+ * Needs a bound workspace; synchronises the stream. */
+dg_status dg_init_state(dg_ctx* ctx, const double* U_src, int src_is_device, double* U, void* stream);
+
 /* Residual and time stepping -------------------------------------------------- */
 
 /* Ut = dU/dt(U): prolongation to faces, Riemann and viscous surface fluxes,

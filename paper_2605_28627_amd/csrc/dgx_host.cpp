@@ -808,6 +808,18 @@ dg_status dg_timestep(dg_ctx* c, const double* U, double cfl, double* dt_out, vo
   return DG_OK;
 }
 
+dg_status dg_init_state(dg_ctx* c, const double* U_src, int src_is_device, double* U, void* stream) {
+  dg_status st = ready(c, "dg_init_state");
+  if (st != DG_OK) return st;
+  if (!U_src || !U) return fail(c, DG_ERR_ARG, "dg_init_state: null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = sizeof(double) * 5 * (size_t)c->nElems * c->n3;
+  if (U_src != U) {
+    HIPCHK(c, hipMemcpyAsync(U, U_src, bytes, src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  }
+  return dg_check_state(c, U, stream);
+}
+
 dg_status dg_check_state(dg_ctx* c, const double* U, void* stream) {
   dg_status st = ready(c, "dg_check_state");
   if (st != DG_OK) return st;

@@ -33,7 +33,7 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_MESH", 3: "DG_ERR_HIP", 
 # public symbols of include/dgx.h
 SYMBOLS = ["dg_create", "dg_destroy", "dg_last_error", "dg_lserk_coefficients", "dg_set_mesh", "dg_upload_mesh",
            "dg_upload_metrics", "dg_get_metrics", "dg_node_coords", "dg_sizes", "dg_workspace_bytes",
-           "dg_workspace_bytes_adjoint", "dg_bind_workspace", "dg_rhs", "dg_lift", "dg_rk_step", "dg_adjoint_rhs", "dg_adjoint_rk_step",
+           "dg_workspace_bytes_adjoint", "dg_bind_workspace", "dg_init_state", "dg_rhs", "dg_lift", "dg_rk_step", "dg_adjoint_rhs", "dg_adjoint_rk_step",
            "dg_kinetic_energy", "dg_kinetic_energy_grad", "dg_timestep", "dg_check_state", "dg_profile",
            "dg_profile_query"]
 
@@ -67,6 +67,7 @@ _sig = {
     "dg_workspace_bytes": (_sz, [_vp]),
     "dg_workspace_bytes_adjoint": (_sz, [_vp]),
     "dg_bind_workspace": (ctypes.c_int, [_vp, _vp, _sz]),
+    "dg_init_state": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
     "dg_rhs": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp]),
     "dg_lift": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "dg_rk_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _vp]),
@@ -206,6 +207,23 @@ def dg_workspace_bytes_adjoint(ctx):
 
 def dg_bind_workspace(ctx, ws_tensor):
     _check(ctx, _L.dg_bind_workspace(ctx, ctypes.c_void_p(ws_tensor.data_ptr()), ws_tensor.numel() * ws_tensor.element_size()))
+
+
+def dg_init_state(ctx, U_src, U, stream=None):
+    """Copies U_src (a float64 numpy array on the host, or a contiguous float64
+    CUDA tensor) into the device state U and checks it; DG_ERR_NONPHYSICAL raises."""
+    import torch
+    n = dg_sizes(ctx)[3]
+    if isinstance(U_src, np.ndarray):
+        src = np.ascontiguousarray(U_src, dtype=np.float64)
+        if src.size != n:
+            raise ValueError(f"U_src has {src.size} elements, expected {n}")
+        ptr, on_dev = ctypes.cast(src.ctypes.data, _vp), 0
+    elif isinstance(U_src, torch.Tensor):
+        ptr, on_dev = _dev(U_src, n, "U_src"), 1
+    else:
+        raise TypeError("U_src must be a numpy array or a CUDA tensor")
+    _check(ctx, _L.dg_init_state(ctx, ptr, on_dev, _dev(U, n, "U"), _stream(stream)))
 
 
 def dg_rhs(ctx, U, Ut, t=0.0, stream=None):

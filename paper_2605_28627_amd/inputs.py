@@ -246,6 +246,14 @@ def tgv_state(xyz, gamma=1.4, Ma=0.1, rho0=1.0, U0=1.0, L=1.0, noise_amp=0.0, no
     return prim_to_cons(rho, u, v, w, p, gamma)
 
 
+def freestream_state(xyz, gamma=1.4, Ma=0.1, rho0=1.0, U0=1.0):
+    """Uniform flow along x at Mach Ma (p = rho0 U0^2 / (gamma Ma^2)): the
+    paper's performance runs start from a free stream."""
+    one = np.ones(xyz.shape[1:])
+    p0 = rho0 * U0 ** 2 / (gamma * Ma ** 2)
+    return prim_to_cons(rho0 * one, U0 * one, 0 * one, 0 * one, p0 * one, gamma)
+
+
 def density_wave_state(xyz, t=0.0, gamma=1.4):
     """rho = 2 + 0.1 sin(pi (x+y+z - 3t)), u=v=w=1, p=1: an exact Euler solution."""
     rho = 2.0 + 0.1 * np.sin(np.pi * (xyz[0] + xyz[1] + xyz[2] - 3.0 * t))
@@ -327,8 +335,11 @@ def workload_mesh(name, K=None):
     return box_mesh(K, w["lo"], w["hi"], Ngeo=Ngeo, curved_amp=w["curved"])
 
 
-def workload_state(name, xyz, gamma=1.4):
+def workload_state(name, xyz, gamma=1.4, state=None):
+    """Initial state of a workload; state="freestream" replaces it by a free stream."""
     w = WORKLOADS[name]
+    if state == "freestream":
+        return freestream_state(xyz, gamma)
     if w["state"] == "density_wave":
         return density_wave_state(xyz, 0.0, gamma)
     if w["state"] == "tgv":

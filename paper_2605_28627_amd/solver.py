@@ -70,7 +70,15 @@ class DGSolver:
         dgx.dg_upload_metrics(self.ctx, Ja, sJ, nvec)
 
     def to_device(self, U: np.ndarray) -> torch.Tensor:
+        """Any host array of the state shape (a state, an adjoint vector, a direction) on the device."""
         return torch.from_numpy(np.ascontiguousarray(U, dtype=np.float64)).to(self.device).reshape(self.state_shape)
+
+    def init_state(self, U, out: torch.Tensor | None = None) -> torch.Tensor:
+        """A device state from a host array or a device tensor, copied and checked
+        (rho > 0, p > 0, finite) by dg_init_state; a non-physical state raises."""
+        out = self.empty_state() if out is None else out
+        dgx.dg_init_state(self.ctx, U, out)
+        return out
 
     def empty_state(self) -> torch.Tensor:
         return torch.empty(self.state_shape, dtype=torch.float64, device=self.device)

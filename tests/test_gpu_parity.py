@@ -80,7 +80,7 @@ def test_rhs_matches_oracle(S, orc, case):
     o, s, _ = _setup(S, orc, case)
     U = I.smooth_random_state(o.coords(), 31, amp=0.2)
     R_orc = o.rhs(U)
-    Ug = s.to_device(U)
+    Ug = s.init_state(U)
     R_gpu = s.rhs(Ug).cpu().numpy()
     err = rel_err_per_var(R_gpu, R_orc)
     _say("rhs", case, "rel err", err)
@@ -130,13 +130,43 @@ def test_rk_steps_match_oracle(S, orc, case):
     dt = o.timestep(U0, 0.9)
     nsteps = 3
     U_orc = o.lserk(U0, nsteps, dt)
-    Ug = s.to_device(U0)
+    Ug = s.init_state(U0)
     dUg = s.empty_state()
     s.rk_step(Ug, dUg, dt, nsteps)
     U_gpu = Ug.cpu().numpy()
     err = rel_err_per_var(U_gpu - U0, U_orc - U0)
     _say("rk", case, err)
     assert np.all(err < 1e-11), err
+
+
+def test_init_state(S, orc, torch_cuda):
+    """dg_init_state: host and device sources give the same bits, an aliased
+    source only checks, and non-physical or non-finite states are refused."""
+    import torch
+    from paper_2605_28627_amd import dgx
+    _say("init_state")
+    o, s, _ = _setup(S, orc, CASES[6])
+    U = I.smooth_random_state(o.coords(), 35, amp=0.2)
+    Uh = s.init_state(U)
+    assert np.array_equal(Uh.cpu().numpy(), U)
+    Ud = s.init_state(Uh)
+    assert np.array_equal(Ud.cpu().numpy(), U)
+    assert s.init_state(Ud, out=Ud) is Ud
+    assert np.array_equal(Ud.cpu().numpy(), U)
+    for bad in ("rho", "p", "nan"):
+        B = U.copy()
+        if bad == "rho":
+            B[0, 1, 0, 0, 0] = -1.0
+        elif bad == "p":
+            B[4, 0, 1, 1, 1] = 0.0
+        else:
+            B[2, 0, 0, 1, 0] = np.nan
+        with pytest.raises(dgx.DGError) as ex:
+            s.init_state(B)
+        assert ex.value.status == dgx.DG_ERR_NONPHYSICAL
+    with pytest.raises(ValueError):
+        s.init_state(U[:, :1])
+    torch.cuda.synchronize()
 
 
 @pytest.mark.parametrize("case", [CASES[0], CASES[7], CASES[9]], ids=str)
