@@ -35,6 +35,11 @@ FP64_PEAK_TFLOPS = 78.6
 KERNEL_SOURCES = ("dgx_kernels.hpp", "dgx_pointwise.hpp", "dgx_internal.hpp", "dgx_inst.hip")
 
 
+def _log(*a):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +56,8 @@ def parse():
     ap.add_argument("--checkpoint-every", type=int, default=None)
     ap.add_argument("--cpu-sample-elems", type=int, default=4096)
     ap.add_argument("--cpu-repeats", type=int, default=3)
+    ap.add_argument("--cpu-procs", type=int, default=1,
+                    help="also run this many independent oracle processes at once (aggregate host throughput)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     return ap.parse_args()
@@ -128,7 +135,7 @@ def volume_kernel_name(w, precision=0):
     return f"void dgx::k_volume<{w['N']}, {w['nodes']}, {w['form']}, {w['physics']}, {precision}, 1>"
 
 
-def volume_kernel_bytes_per_dof(w):
+def volume_kernel_bytes_per_dof(w, precision=0):
     """Compulsory HBM bytes of one launch of the residual/RK kernel, per node.
 
     Reads: U (5), metrics Ja (9) and 1/J (1), dU (5), and per face node of
@@ -136,14 +143,15 @@ def volume_kernel_bytes_per_dof(w):
     normal + area (4); Navier-Stokes adds the contravariant viscous fluxes
     G~^r (12) and both sides' face-normal viscous fluxes (2 x 4), formed by
     the lifting kernel.  Writes: dU (5), U (5) and the element's own traces
-    of the new state (5 per face node).  8 bytes each.
+    of the new state (5 per face node).  8 bytes each, except the viscous
+    fluxes in the FP32-flux mode (4 bytes).
     """
     n1 = w["N"] + 1
     fpn = 6 * n1 * n1 / n1 ** 3          # face nodes of one element per volume node
     reads = 5 + 9 + 1 + 5 + fpn * (10 + 4)
     writes = 5 + 5 + fpn * 5
     if w["physics"] == 1:
-        reads += 12 + fpn * 8
+        reads += (12 + fpn * 8) * (0.5 if precision == 1 else 1.0)
     return 8.0 * (reads + writes)
 
 
@@ -166,7 +174,9 @@ def main():
     torch.cuda.set_device(dev)
     w, cfg = workload_cfg(args.workload)
     K = tuple(int(x) for x in args.K.split(",")) if args.K else tuple(w["K"])
+    _log("mesh", args.workload, K)
     mesh = I.workload_mesh(args.workload, K=K)
+    _log("solver set-up")
     s = DGSolver(cfg, mesh, dev)
     dof = s.nElems * s.npe
     xyz = s.coords()
@@ -179,6 +189,7 @@ def main():
         times of the first repetition's timed region."""
         times, prof = [], {}
         for rep in range(args.reps):
+            _log("timing", "fp32-flux" if solver.cfg.get("precision") else "fp64", "repetition", rep + 1, "of", args.reps)
             U = U0.clone()
             dU = torch.zeros_like(U)
             if args.warmup:
@@ -264,9 +275,10 @@ def main():
         cfg32 = dict(cfg, precision=1)
         s32 = DGSolver(cfg32, mesh, dev)
         final32 = []
-        times32, _ = timed(s32, profile=False, keep=final32)
+        times32, prof32 = timed(s32, profile=True, keep=final32)
         t32 = statistics.median(times32)
         result["pid_fp32_flux"] = t32 / (5 * args.steps * dof)
+        result["kernels_ms_per_launch_fp32_flux"] = {k: (v[0] / max(v[1], 1)) for k, v in prof32.items()}
         result["fp32_speedup"] = t64 / t32
         # relative L2 error per variable of the FP32-flux path against the FP64 path
         # (which matches the oracle to 1e-12): residual of the initial state, and
@@ -284,8 +296,10 @@ def main():
         }
         del R64, R32, d_state, d_ref, final32
         s32.close()
+    _log("adjoint" if not args.no_adjoint else "adjoint skipped")
     result["adjoint_forward_cost"] = adjoint_cost(cfg, mesh, dev, U0, dt, args) if not args.no_adjoint else None
     if not args.no_cpu_baseline:
+        _log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(args, cfg, mesh, xyz, pid64)
     print(json.dumps(result), flush=True)
     s.close()
@@ -302,6 +316,7 @@ def adjoint_cost(cfg, mesh, dev, U0, dt, args):
     every = args.checkpoint_every or checkpoint_interval(sa, n)
     times = []
     for rep in range(2):          # the first repetition warms up
+        _log("adjoint repetition", rep + 1, "of 2:", n, "steps, checkpoints every", every)
         U = U0.clone().requires_grad_(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -319,9 +334,26 @@ def adjoint_cost(cfg, mesh, dev, U0, dt, args):
             "note": "backward includes the recomputation of step and stage states"}
 
 
+def _oracle_sample_time(workload, K, state, nel, repeats):
+    """Seconds for `repeats` oracle residuals of elements 0..nel-1 of a workload
+    (run in a process of its own for the all-cores figure)."""
+    from oracle import oracle as O
+    from paper_2605_28627_amd import inputs as I
+    _, cfg = workload_cfg(workload)
+    mesh = I.workload_mesh(workload, K=K)
+    o = O.Oracle(cfg, mesh)
+    U = I.workload_state(workload, o.coords(), state=state)
+    el = list(range(nel))
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        o.rhs_elems(U, el)
+    return time.perf_counter() - t0
+
+
 def cpu_baseline(args, cfg, mesh, xyz, pid_gpu):
     """The serial FP64 oracle on the host: residual of a contiguous block of
-    elements of the same workload (one RK stage's worth of work per node)."""
+    elements of the same workload (one RK stage's worth of work per node), on
+    one thread; with --cpu-procs P > 1 also P such processes at once."""
     from oracle import oracle as O
     from paper_2605_28627_amd import inputs as I
     o = O.Oracle(cfg, mesh)
@@ -334,10 +366,30 @@ def cpu_baseline(args, cfg, mesh, xyz, pid_gpu):
     t = time.perf_counter() - t0
     npe = (cfg["N"] + 1) ** 3
     pid = t / (args.cpu_repeats * nel * npe)
-    return {"value": pid, "unit": "s/(DOF*stage)", "cores": 1, "kind": "oracle",
-            "sample": f"{args.cpu_repeats} residual evaluations of elements 0..{nel - 1} of the {mesh.nElems}-element "
-                      f"workload ({nel * npe} DOF each, serial, one thread), {t:.1f} s",
-            "gpu_over_cpu_per_rank": pid / pid_gpu}
+    out = {"value": pid, "unit": "s/(DOF*stage)", "cores": 1, "kind": "oracle",
+           "sample": f"{args.cpu_repeats} residual evaluations of elements 0..{nel - 1} of the {mesh.nElems}-element "
+                     f"workload ({nel * npe} DOF each, serial, one thread), {t:.1f} s",
+           "gpu_over_cpu_per_rank": pid / pid_gpu}
+    if args.cpu_procs > 1:
+        import multiprocessing as mp
+        K = tuple(int(x) for x in args.K.split(",")) if args.K else None
+        P = args.cpu_procs
+        with mp.get_context("spawn").Pool(P) as pool:
+            t0 = time.perf_counter()
+            ts = pool.starmap(_oracle_sample_time, [(args.workload, K, args.state, nel, args.cpu_repeats)] * P)
+            wall = time.perf_counter() - t0
+        pid_all = max(ts) / (P * args.cpu_repeats * nel * npe)
+        out["all_cores"] = {"procs": P, "pid_aggregate": pid_all, "dof_updates_per_s": 1.0 / pid_all,
+                            "per_process_s": ts, "wall_s_incl_setup": wall,
+                            "gpu_over_all_cores": pid_all / pid_gpu,
+                            "note": "independent oracle processes on the same sample at once; aggregate over the "
+                                    "slowest process's timed loop (set-up excluded)"}
+        try:
+            out["host"] = {"nproc": os.cpu_count(), "model": next(
+                l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))}
+        except (OSError, StopIteration):
+            pass
+    return out
 
 
 if __name__ == "__main__":

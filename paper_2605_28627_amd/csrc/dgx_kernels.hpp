@@ -107,13 +107,32 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace(Geo G, const double* __
   }
 }
 
+// Viscous fluxes passed from the lifting to the residual kernel are stored in
+// double (PREC 0) or, in the FP32-flux mode (PREC 1), as float in the same
+// buffers (element i of the float array), like the gradients they come from.
+template <int PREC>
+__device__ inline void st_visc(double* p, size_t i, double v) {
+  if constexpr (PREC == 1)
+    reinterpret_cast<float*>(p)[i] = float(v);
+  else
+    p[i] = v;
+}
+template <int PREC>
+__device__ inline double ld_visc(const double* p, size_t i) {
+  if constexpr (PREC == 1)
+    return double(reinterpret_cast<const float*>(p)[i]);
+  else
+    return p[i];
+}
+
 // ---------------------------------------------------------------------------
 // BR1 lifting kernel (paper eq. dgsem_lifted), g = grad (u, v, w, T).
 // EMIT 0: g -> gout[12][nE][n3] and its face traces -> gtr[slot][12][side][fi].
 // EMIT 1: what the residual consumes instead of g, formed here once per node:
 //   gout[4r+v][nE][n3] = G~^r_v = Ja^r . G_v(q, g)      (contravariant viscous flux)
 //   gtr[slot][4][side][fi] = G_v(q_tr, g_tr) . n s       (per side, master normal)
-// with q_tr the state trace of that side; FT is the flux arithmetic type.
+// with q_tr the state trace of that side; FT is the flux arithmetic type, and
+// with PREC 1 both are stored as float (st_visc).
 // ---------------------------------------------------------------------------
 template <int N, int NODES, int EMIT, int PREC>
 __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const double* __restrict__ U,
@@ -230,7 +249,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
         double Gr[4];
         viscous_flux<FT>(q, acc, P, jr, Gr);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) gout[((size_t)(4 * r + v) * nE + e) * n3 + t] = Gr[v];
+        for (int v = 0; v < 4; ++v) st_visc<PREC>(gout, ((size_t)(4 * r + v) * nE + e) * n3 + t, Gr[v]);
       }
     }
   }
@@ -246,7 +265,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
     double Gn[4];
     viscous_flux<FT>(cons2prim(ut, P.gm1), gf, P, nv, Gn);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) gtr[tr_index(slot, v, 4, nS, side, n2, fi)] = Gn[v];
+    for (int v = 0; v < 4; ++v) st_visc<PREC>(gtr, tr_index(slot, v, 4, nS, side, n2, fi), Gn[v]);
   };
   // gradient traces
   if constexpr (NODES == 1) {
@@ -360,8 +379,9 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
   // issued first, so that their latency overlaps the surface fluxes; each
   // direction then prefetches the next one's while it computes.
   double u[5] = {0, 0, 0, 0, 0};
+  using VT = typename std::conditional<PREC == 1, float, double>::type;   // stored viscous flux type
   double jn[3] = {0, 0, 0};
-  double gn[4] = {0, 0, 0, 0};
+  VT gn[4] = {0, 0, 0, 0};
   // the last direction prefetches what the RK update reads instead
   double sJn = 0.0, dUn[5] = {0, 0, 0, 0, 0}, Un[5] = {0, 0, 0, 0, 0};
   auto fetch_end = [&]() {
@@ -380,7 +400,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
     for (int c = 0; c < 3; ++c) jn[c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
     if constexpr (PHYS == 1) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) gn[v] = gvn[((size_t)(4 * r + v) * nE + e) * n3 + t];
+      for (int v = 0; v < 4; ++v) gn[v] = reinterpret_cast<const VT*>(gvn)[((size_t)(4 * r + v) * nE + e) * n3 + t];
     }
   };
   if (act) {
@@ -412,7 +432,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Phi[1 + v] -= 0.5 * gvf[tr_index(sd, v, 4, nS, side, n2, fi)];
+        for (int v = 0; v < 4; ++v) Phi[1 + v] -= 0.5 * ld_visc<PREC>(gvf, tr_index(sd, v, 4, nS, side, n2, fi));
     }
     const double sgn = slot ? -1.0 : 1.0;
 #pragma unroll
@@ -435,7 +455,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     const double jr[3] = {jn[0], jn[1], jn[2]};
-    const double gv[4] = {gn[0], gn[1], gn[2], gn[3]};
+    const double gv[4] = {double(gn[0]), double(gn[1]), double(gn[2]), double(gn[3])};
     if constexpr (FORM == 1) {
       double* sja = sm + 8 * n3;
       double* sgv = sm + 11 * n3;
