@@ -138,7 +138,8 @@ def volume_kernel_name(w, precision=0):
 def volume_kernel_bytes_per_dof(w, precision=0):
     """Compulsory HBM bytes of one launch of the residual/RK kernel, per node.
 
-    Reads: U (5), metrics Ja (9) and 1/J (1), dU (5), and per face node of
+    Reads: U (5), metrics Ja (9) and 1/J (1), dU (5, except in the first of
+    the five stages, whose A is 0: 4 on average), and per face node of
     each of the element's 6 faces both sides' traces (2 x 5) and the face
     normal + area (4); Navier-Stokes adds the contravariant viscous fluxes
     G~^r (12) and both sides' face-normal viscous fluxes (2 x 4), formed by
@@ -148,7 +149,7 @@ def volume_kernel_bytes_per_dof(w, precision=0):
     """
     n1 = w["N"] + 1
     fpn = 6 * n1 * n1 / n1 ** 3          # face nodes of one element per volume node
-    reads = 5 + 9 + 1 + 5 + fpn * (10 + 4)
+    reads = 5 + 9 + 1 + 4 + fpn * (10 + 4)
     writes = 5 + 5 + fpn * 5
     if w["physics"] == 1:
         reads += (12 + fpn * 8) * (0.5 if precision == 1 else 1.0)
@@ -296,6 +297,9 @@ def main():
         }
         del R64, R32, d_state, d_ref, final32
         s32.close()
+        del s32
+    del final64
+    torch.cuda.empty_cache()
     _log("adjoint" if not args.no_adjoint else "adjoint skipped")
     result["adjoint_forward_cost"] = adjoint_cost(cfg, mesh, dev, U0, dt, args) if not args.no_adjoint else None
     if not args.no_cpu_baseline:

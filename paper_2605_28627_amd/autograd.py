@@ -17,16 +17,29 @@ import torch
 from . import dgx
 
 
-def checkpoint_interval(solver, nsteps: int, memory_fraction: float = 0.5) -> int:
+# state-sized registers the trajectory holds besides the checkpoints and the
+# recomputed states: the forward state and RK register, the input gradient,
+# and in the backward pass lambda_U, lambda_dU, the RK register and the
+# recomputation state
+_EXTRA_STATES = 7
+
+
+def checkpoint_interval(solver, nsteps: int, memory_fraction: float = 0.8) -> int:
     """Steps between checkpoints.  With k, the backward pass holds nsteps/k
     checkpoints plus k recomputed step states; k = sqrt(nsteps) minimises
-    that, raised if needed so that both sets fit in a fraction of free HBM."""
+    that, raised if needed so that both sets (and the other state-sized
+    registers) fit in a fraction of the free HBM (torch's cached blocks count
+    as free)."""
     state_bytes = solver.state_len * 8
     free, _ = torch.cuda.mem_get_info(solver.device)
-    budget = max(int(free * memory_fraction) // state_bytes, 4)
+    free += torch.cuda.memory_reserved(solver.device) - torch.cuda.memory_allocated(solver.device)
+    budget = int(free * memory_fraction) // state_bytes - _EXTRA_STATES
     k = max(1, int(math.ceil(math.sqrt(nsteps))))
     while math.ceil(nsteps / k) + k > budget and k < nsteps:
         k += 1
+    if math.ceil(nsteps / k) + k > budget:
+        raise MemoryError(f"{nsteps} steps need at least {math.ceil(nsteps / k) + k + _EXTRA_STATES} states of "
+                          f"{state_bytes / 2**30:.2f} GiB; about {int(free * memory_fraction) // state_bytes} fit")
     return k
 
 

@@ -390,7 +390,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const size_t gi = ((size_t)v * nE + e) * n3 + t;
-        dUn[v] = dU[gi];
+        dUn[v] = A != 0.0 ? dU[gi] : 0.0;   // the first LSERK stage has A = 0: no read
         Un[v] = U[gi];
       }
     }

@@ -46,9 +46,12 @@ class DGSolver:
             raise
 
     def close(self):
+        """Destroys the context and drops the workspace (the solver is unusable afterwards)."""
         if getattr(self, "ctx", None) is not None:
             dgx.dg_destroy(self.ctx)
             self.ctx = None
+        self.ws = None
+        self._ws_raw = None
 
     def __del__(self):
         try:
