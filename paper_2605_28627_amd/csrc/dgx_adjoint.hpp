@@ -58,21 +58,38 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_trace(Geo G, const double
 
 // Volume and surface adjoint of the residual; Navier-Stokes also writes the
 // gradient adjoint gbar[12][e][node] (from the viscous volume and surface terms).
+//
+// Phases, so that live ranges do not stack:
+//   1. each side's flux adjoint (own part) -> LDS, accumulated by the nodes;
+//   2. the weak-form parts along every line (Euler weak form; the viscous
+//      volume term), after which gbar is written and the gradients are dead;
+//   3. split form: per direction r the metric row -> LDS, then the pairs.
+//      The weight of the pair (m, l) is w = -(DS[m][l] lt_m + DS[l][m] lt_l)
+//      for both of its nodes, and F# is symmetric, so one reverse sweep of
+//      F#(U_m, U_l) gives node m its first-argument and node l its
+//      second-argument adjoint.  On lines inside one wavefront the lane of m
+//      evaluates (m, m+d) once and hands the partner's share over a shuffle,
+//      as the forward kernel does.
+// Waves per SIMD requested for 512-work-item adjoint kernels: 1 leaves the
+// register file to one element per CU (the Jacobian chain stays in registers),
+// 4 would cap it at 128 VGPRs for two elements per CU and spill.
+#ifndef DGX_ADJ_WAVES
+#define DGX_ADJ_WAVES 1
+#endif
 template <int N, int NODES, int FORM, int PHYS>
-__global__ __launch_bounds__(Shape<N>::nth) void k_adj_volume(Geo G, Phys P, const double* __restrict__ U,
-                                                              const double* __restrict__ lam,
-                                                              const double* __restrict__ Utr,
-                                                              const double* __restrict__ Lbar,
-                                                              const double* __restrict__ gin,
-                                                              const double* __restrict__ gtr,
-                                                              double* __restrict__ out, double* __restrict__ gbar) {
+__global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVES : 1)) void k_adj_volume(
+    Geo G, Phys P, const double* __restrict__ U, const double* __restrict__ lam, const double* __restrict__ Utr,
+    const double* __restrict__ Lbar, const double* __restrict__ gin, const double* __restrict__ gtr,
+    double* __restrict__ out, double* __restrict__ gbar) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
   constexpr int NF = PHYS == 1 ? 17 : 5;                           // face adjoint values per face node
-  constexpr int SZ_V = FORM == 1 ? 22 * n3 : 5 * n3;                 // lt (5) [+ aux (8) + Ja (9)]
   constexpr int SZ_F = NF * S::nface;
-  constexpr int SZ = SZ_V > SZ_F ? SZ_V : SZ_F;
-  __shared__ double sm[SZ];
+  constexpr int SZ_V = FORM == 1 ? 11 * n3 : 0;                      // aux (8) + one metric row (3)
+  constexpr int SZ_B = SZ_F > SZ_V ? SZ_F : SZ_V;
+  constexpr bool kSymLines = DGX_SYMMETRIC_PAIRS && (n1 == 4 || n1 == 8) && (n3 % 64 == 0);
+  __shared__ double sl[5 * n3];   // lam / J
+  __shared__ double sB[SZ_B];     // surface adjoints, then aux + metric row
   __shared__ DevBasis sb;
   const int e = blockIdx.x, t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
@@ -80,124 +97,12 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_volume(Geo G, Phys P, con
   const bool act = t < n3;
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   const int idx[3] = {i, j, k};
-  double u[5] = {0, 0, 0, 0, 0}, ja[9], Ub[5] = {0, 0, 0, 0, 0}, ub[3] = {0, 0, 0}, gb[12], gl[12];
-#pragma unroll
-  for (int c = 0; c < 12; ++c) gb[c] = 0.0;
-  Prim q{};
-  double* sl = sm;  // [5][n3] lam / J
   if (act) {
     const double sJ = G.sJ[(size_t)e * n3 + t];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      u[v] = U[((size_t)v * nE + e) * n3 + t];
-      sl[v * n3 + t] = sJ * lam[((size_t)v * nE + e) * n3 + t];
-    }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) ja[c] = G.Ja[((size_t)c * nE + e) * n3 + t];
-    q = cons2prim(u, P.gm1);
-    if constexpr (PHYS == 1) {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) gl[c] = gin[((size_t)c * nE + e) * n3 + t];
-    }
+    for (int v = 0; v < 5; ++v) sl[v * n3 + t] = sJ * lam[((size_t)v * nE + e) * n3 + t];
   }
-  Aux me{};
-  if constexpr (FORM == 1) {
-    double* saux = sm + 5 * n3;
-    double* sja = sm + 13 * n3;
-    if (act) {
-      me = make_aux(q);
-      saux[0 * n3 + t] = me.rho; saux[1 * n3 + t] = me.u[0]; saux[2 * n3 + t] = me.u[1];
-      saux[3 * n3 + t] = me.u[2]; saux[4 * n3 + t] = me.beta; saux[5 * n3 + t] = me.lrho;
-      saux[6 * n3 + t] = me.lbeta; saux[7 * n3 + t] = me.k;
-#pragma unroll
-      for (int c = 0; c < 9; ++c) sja[c * n3 + t] = ja[c];
-    }
-  }
-  __syncthreads();
-  if (act) {
-    // transposed weak-form contraction Lam^r = sum_a Dhat[a][l] lt_a along each line
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const int l = idx[r];
-      const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
-      double Lam[5] = {0, 0, 0, 0, 0};
-      if (FORM == 0 || PHYS == 1) {
-#pragma unroll
-        for (int a = 0; a < n1; ++a) {
-          const double c = sb.Dhat[a * n1 + l];
-          const int ta = line_node<N>(r, a, pp, qq);
-#pragma unroll
-          for (int v = 0; v < 5; ++v) Lam[v] += c * sl[v * n3 + ta];
-        }
-      }
-      const double nv[3] = {ja[3 * r], ja[3 * r + 1], ja[3 * r + 2]};
-      if constexpr (FORM == 0) {
-        double Ue[5];
-        euler_flux_vjp(u, q, nv, Lam, P.gm1, Ue);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) Ub[v] += Ue[v];
-      }
-      if constexpr (PHYS == 1) {
-        const double Gnb[4] = {-Lam[1], -Lam[2], -Lam[3], -Lam[4]};
-        double gq[12], uq[3];
-        viscous_flux_vjp(q, gl, P, nv, Gnb, gq, uq);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) gb[c] += gq[c];
-        ub[0] += uq[0]; ub[1] += uq[1]; ub[2] += uq[2];
-      }
-    }
-    if constexpr (FORM == 1) {
-      const double* saux = sm + 5 * n3;
-      const double* sja = sm + 13 * n3;
-      const double c1 = 0.5 / P.gm1;
-      AuxBar ab{};
-      double lm[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) lm[v] = sl[v * n3 + t];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const int a = idx[r];
-        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
-        for (int l = 0; l < n1; ++l) {
-          if (l == a) continue;
-          const int tl = line_node<N>(r, l, pp, qq);
-          Aux ot;
-          ot.rho = saux[0 * n3 + tl]; ot.u[0] = saux[1 * n3 + tl]; ot.u[1] = saux[2 * n3 + tl];
-          ot.u[2] = saux[3 * n3 + tl]; ot.beta = saux[4 * n3 + tl]; ot.lrho = saux[5 * n3 + tl];
-          ot.lbeta = saux[6 * n3 + tl]; ot.k = saux[7 * n3 + tl];
-          const double nv[3] = {0.5 * (ja[3 * r] + sja[(3 * r) * n3 + tl]),
-                                0.5 * (ja[3 * r + 1] + sja[(3 * r + 1) * n3 + tl]),
-                                0.5 * (ja[3 * r + 2] + sja[(3 * r + 2) * n3 + tl])};
-          const double dml = sb.DS[a * n1 + l], dlm = sb.DS[l * n1 + a];
-          double w[5];
-#pragma unroll
-          for (int v = 0; v < 5; ++v) w[v] = -(dml * lm[v] + dlm * sl[v * n3 + tl]);
-          if (P.twopoint == 0) {
-            AuxBar d;
-            chandrashekar_vjp_a(me, ot, nv, c1, w, d);
-            ab.rho += d.rho; ab.u[0] += d.u[0]; ab.u[1] += d.u[1]; ab.u[2] += d.u[2];
-            ab.beta += d.beta; ab.lrho += d.lrho; ab.lbeta += d.lbeta; ab.k += d.k;
-          } else {
-            // central average: d/dU_m of 1/2 f(U_m).n
-            const double wh[5] = {0.5 * w[0], 0.5 * w[1], 0.5 * w[2], 0.5 * w[3], 0.5 * w[4]};
-            double Ue[5];
-            euler_flux_vjp(u, q, nv, wh, P.gm1, Ue);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) Ub[v] += Ue[v];
-          }
-        }
-      }
-      if (P.twopoint == 0) {
-        double Ua[5];
-        aux_vjp(q, me, ab, P.gm1, Ua);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) Ub[v] += Ua[v];
-      }
-    }
-  }
-  __syncthreads();
-  // surface: adjoint of each side's flux, own trace part into LDS
-  double* sfb = sm;  // [6][NF][n2]
+  // 1. surface: adjoint of each side's flux, own trace part into LDS
   for (int ft = t; ft < S::nface; ft += S::nth) {
     const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
     const int info = G.efc[e * 6 + f];
@@ -227,14 +132,18 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_volume(Geo G, Phys P, con
     surface_flux_vjp<FORM, PHYS>(UL, UR, gL, gR, nh, s, P, Phib, ULb, URb, gLb, gRb);
     const double* mine = slot ? URb : ULb;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) sfb[(f * NF + v) * n2 + rr] = mine[v];
+    for (int v = 0; v < 5; ++v) sB[(f * NF + v) * n2 + rr] = mine[v];
     if constexpr (PHYS == 1) {
       const double* gm = slot ? gRb : gLb;
 #pragma unroll
-      for (int c = 0; c < 12; ++c) sfb[(f * NF + 5 + c) * n2 + rr] = gm[c];
+      for (int c = 0; c < 12; ++c) sB[(f * NF + 5 + c) * n2 + rr] = gm[c];
     }
   }
   __syncthreads();
+  double Ub[5] = {0, 0, 0, 0, 0};
+  double gb[PHYS == 1 ? 12 : 1];
+#pragma unroll
+  for (int c = 0; c < (PHYS == 1 ? 12 : 1); ++c) gb[c] = 0.0;
   if (act) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -251,21 +160,178 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_volume(Geo G, Phys P, con
           L = sd ? sb.Lp[a] : sb.Lm[a];
         }
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Ub[v] += L * sfb[(f * NF + v) * n2 + rr];
+        for (int v = 0; v < 5; ++v) Ub[v] += L * sB[(f * NF + v) * n2 + rr];
         if constexpr (PHYS == 1) {
 #pragma unroll
-          for (int c = 0; c < 12; ++c) gb[c] += L * sfb[(f * NF + 5 + c) * n2 + rr];
+          for (int c = 0; c < 12; ++c) gb[c] += L * sB[(f * NF + 5 + c) * n2 + rr];
         }
       }
     }
-    if constexpr (PHYS == 1) {
-      double Uu[5];
-      prim_vjp(q, P.gm1, 0.0, ub, 0.0, Uu);
+  }
+  __syncthreads();
+  // 2. weak-form parts: Lam^r = sum_a Dhat[a][l] lt_a along each line
+  if (FORM == 0 || PHYS == 1) {
+    if (act) {
+      double u[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Ub[v] += Uu[v];
+      for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+      const Prim q = cons2prim(u, P.gm1);
+      double ub[3] = {0, 0, 0};
+      double gl[PHYS == 1 ? 12 : 1];
+      if constexpr (PHYS == 1) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) gbar[((size_t)c * nE + e) * n3 + t] = gb[c];
+        for (int c = 0; c < 12; ++c) gl[c] = gin[((size_t)c * nE + e) * n3 + t];
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int l = idx[r];
+        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+        double Lam[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < n1; ++a) {
+          const double c = sb.Dhat[a * n1 + l];
+          const int ta = line_node<N>(r, a, pp, qq);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Lam[v] += c * sl[v * n3 + ta];
+        }
+        const double nv[3] = {G.Ja[((size_t)(3 * r) * nE + e) * n3 + t], G.Ja[((size_t)(3 * r + 1) * nE + e) * n3 + t],
+                              G.Ja[((size_t)(3 * r + 2) * nE + e) * n3 + t]};
+        if constexpr (FORM == 0) {
+          double Ue[5];
+          euler_flux_vjp(u, q, nv, Lam, P.gm1, Ue);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Ub[v] += Ue[v];
+        }
+        if constexpr (PHYS == 1) {
+          const double Gnb[4] = {-Lam[1], -Lam[2], -Lam[3], -Lam[4]};
+          double gq[12], uq[3];
+          viscous_flux_vjp(q, gl, P, nv, Gnb, gq, uq);
+#pragma unroll
+          for (int c = 0; c < 12; ++c) gb[c] += gq[c];
+          ub[0] += uq[0]; ub[1] += uq[1]; ub[2] += uq[2];
+        }
+      }
+      if constexpr (PHYS == 1) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gbar[((size_t)c * nE + e) * n3 + t] = gb[c];
+        double Uu[5];
+        prim_vjp(q, P.gm1, 0.0, ub, 0.0, Uu);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Ub[v] += Uu[v];
+      }
     }
+  }
+  // 3. split form: flux differencing adjoint
+  if constexpr (FORM == 1) {
+    double* saux = sB;
+    double* sja = sB + 8 * n3;
+    Aux me{};
+    double lm[5] = {0, 0, 0, 0, 0};
+    if (act) {
+      double u[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+      me = make_aux(cons2prim(u, P.gm1));
+      saux[0 * n3 + t] = me.rho; saux[1 * n3 + t] = me.u[0]; saux[2 * n3 + t] = me.u[1];
+      saux[3 * n3 + t] = me.u[2]; saux[4 * n3 + t] = me.beta; saux[5 * n3 + t] = me.lrho;
+      saux[6 * n3 + t] = me.lbeta; saux[7 * n3 + t] = me.k;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) lm[v] = sl[v * n3 + t];
+    }
+    const double c1 = 0.5 / P.gm1;
+    AuxBar ab{};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      double jr[3] = {0, 0, 0};
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          jr[c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
+          sja[c * n3 + t] = jr[c];
+        }
+      }
+      __syncthreads();
+      if (act) {
+        const int a = idx[r];
+        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+        auto partner = [&](int tl, Aux& ot, double nv[3]) {
+          ot.rho = saux[0 * n3 + tl]; ot.u[0] = saux[1 * n3 + tl]; ot.u[1] = saux[2 * n3 + tl];
+          ot.u[2] = saux[3 * n3 + tl]; ot.beta = saux[4 * n3 + tl]; ot.lrho = saux[5 * n3 + tl];
+          ot.lbeta = saux[6 * n3 + tl]; ot.k = saux[7 * n3 + tl];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) nv[c] = 0.5 * (jr[c] + sja[c * n3 + tl]);
+        };
+        if (P.twopoint == 0 && kSymLines && (n1 == 4 || r < 2)) {
+          const int lane = t & 63;
+          const int str = r == 0 ? 1 : (r == 1 ? n1 : n2);
+#pragma unroll 1
+          for (int d = 1; d <= n1 / 2; ++d) {
+            const int b = (a + d) & (n1 - 1);
+            const int tl = line_node<N>(r, b, pp, qq);
+            Aux ot;
+            double nv[3];
+            partner(tl, ot, nv);
+            const double dab = sb.DS[a * n1 + b], dba = sb.DS[b * n1 + a];
+            double w[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) w[v] = -(dab * lm[v] + dba * sl[v * n3 + tl]);
+            AuxBar da, db;
+            chandrashekar_vjp_ab(me, ot, nv, c1, w, da, db);
+            ab.rho += da.rho; ab.u[0] += da.u[0]; ab.u[1] += da.u[1]; ab.u[2] += da.u[2];
+            ab.beta += da.beta; ab.lrho += da.lrho; ab.lbeta += da.lbeta; ab.k += da.k;
+            if (d < n1 / 2) {
+              // the lane of a - d hands over its partner share for node a
+              const int src = lane + (((a - d) & (n1 - 1)) - a) * str;
+              ab.rho += __shfl(db.rho, src); ab.u[0] += __shfl(db.u[0], src); ab.u[1] += __shfl(db.u[1], src);
+              ab.u[2] += __shfl(db.u[2], src); ab.beta += __shfl(db.beta, src); ab.lrho += __shfl(db.lrho, src);
+              ab.lbeta += __shfl(db.lbeta, src); ab.k += __shfl(db.k, src);
+            }
+          }
+        } else {
+#pragma unroll 1
+          for (int l = 0; l < n1; ++l) {
+            if (l == a) continue;
+            const int tl = line_node<N>(r, l, pp, qq);
+            Aux ot;
+            double nv[3];
+            partner(tl, ot, nv);
+            const double dml = sb.DS[a * n1 + l], dlm = sb.DS[l * n1 + a];
+            double w[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) w[v] = -(dml * lm[v] + dlm * sl[v * n3 + tl]);
+            if (P.twopoint == 0) {
+              AuxBar d;
+              chandrashekar_vjp_a(me, ot, nv, c1, w, d);
+              ab.rho += d.rho; ab.u[0] += d.u[0]; ab.u[1] += d.u[1]; ab.u[2] += d.u[2];
+              ab.beta += d.beta; ab.lrho += d.lrho; ab.lbeta += d.lbeta; ab.k += d.k;
+            } else {
+              // central average: d/dU_m of 1/2 f(U_m).n (own state re-read from cache)
+              double u[5];
+#pragma unroll
+              for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+              const double wh[5] = {0.5 * w[0], 0.5 * w[1], 0.5 * w[2], 0.5 * w[3], 0.5 * w[4]};
+              double Ue[5];
+              euler_flux_vjp(u, cons2prim(u, P.gm1), nv, wh, P.gm1, Ue);
+#pragma unroll
+              for (int v = 0; v < 5; ++v) Ub[v] += Ue[v];
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (act && P.twopoint == 0) {
+      double u[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+      const Prim q = cons2prim(u, P.gm1);
+      double Ua[5];
+      aux_vjp(q, me, ab, P.gm1, Ua);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ub[v] += Ua[v];
+    }
+  }
+  if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) out[((size_t)v * nE + e) * n3 + t] = Ub[v];
   }

@@ -337,6 +337,100 @@ __host__ __device__ inline void inv_log_mean_grad(double x, double y, double lx,
   }
 }
 
+// Both arguments' partial derivatives of the logarithmic mean L(x, y; lx, ly)
+// (same branch as the forward): d/dx, d/dlx, d/dy, d/dly.
+__host__ __device__ inline void log_mean_grad2(double x, double y, double lx, double ly, double& dx, double& dlx,
+                                               double& dy, double& dly) {
+  const double s = x + y;
+  const double f = (x - y) / s;
+  const double u = f * f;
+  if (u < 1e-4) {
+    const double P = 2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0)));
+    const double dP = 2.0 / 3.0 + u * (4.0 / 5.0 + u * (6.0 / 7.0));
+    const double iP = 1.0 / P;
+    const double c = s * iP * iP * dP * 4.0 * f / (s * s);   // s/P^2 dP/du * 2f * 2/s^2
+    dx = iP - c * y;
+    dy = iP + c * x;
+    dlx = 0.0;
+    dly = 0.0;
+  } else {
+    const double idl = 1.0 / (lx - ly);
+    const double q = (x - y) * idl * idl;
+    dx = idl;
+    dy = -idl;
+    dlx = -q;
+    dly = q;
+  }
+}
+// Both arguments' partial derivatives of the reciprocal logarithmic mean.
+__host__ __device__ inline void inv_log_mean_grad2(double x, double y, double lx, double ly, double& dx, double& dlx,
+                                                   double& dy, double& dly) {
+  const double s = x + y;
+  const double f = (x - y) / s;
+  const double u = f * f;
+  if (u < 1e-4) {
+    const double P = 2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0)));
+    const double dP = 2.0 / 3.0 + u * (4.0 / 5.0 + u * (6.0 / 7.0));
+    const double is = 1.0 / s;
+    const double c = dP * 4.0 * f * is * is * is;             // dP/du * 2f * 2/s^2 / s
+    const double base = -P * is * is;
+    dx = base + c * y;
+    dy = base - c * x;
+    dlx = 0.0;
+    dly = 0.0;
+  } else {
+    const double id = 1.0 / (x - y);
+    const double q = (lx - ly) * id * id;
+    dx = -q;
+    dy = q;
+    dlx = id;
+    dly = -id;
+  }
+}
+
+// d(w . F#(a, b; n))/d aux_a and d aux_b for Chandrashekar's flux in one
+// reverse sweep (FP64 forward).  The averages are symmetric, so the two
+// argument adjoints share every term except the log-mean derivatives.
+__host__ __device__ inline void chandrashekar_vjp_ab(const Aux& a, const Aux& b, const double n[3], double c1,
+                                                     const double w[5], AuxBar& aa, AuxBar& bb) {
+  const double rho_ln = log_mean<double>(a.rho, b.rho, a.lrho, b.lrho);
+  const double ibl = inv_log_mean<double>(a.beta, b.beta, a.lbeta, b.lbeta);
+  const double S = a.beta + b.beta;
+  const double iS = 1.0 / S;
+  const double phat = 0.5 * (a.rho + b.rho) * iS;
+  const double X = ibl * c1 - 0.25 * (a.k + b.k);
+  const double um[3] = {0.5 * (a.u[0] + b.u[0]), 0.5 * (a.u[1] + b.u[1]), 0.5 * (a.u[2] + b.u[2])};
+  const double umn = um[0] * n[0] + um[1] * n[1] + um[2] * n[2];
+  const double Fr = rho_ln * umn;
+  // reverse sweep
+  double Fmb[3];
+  for (int d = 0; d < 3; ++d) Fmb[d] = w[1 + d] + w[4] * um[d];
+  const double Frb = w[0] + w[4] * X + (Fmb[0] * um[0] + Fmb[1] * um[1] + Fmb[2] * um[2]);
+  const double Xb = w[4] * Fr;
+  const double phatb = Fmb[0] * n[0] + Fmb[1] * n[1] + Fmb[2] * n[2];
+  const double rlnb = Frb * umn;
+  const double umnb = Frb * rho_ln;
+  for (int d = 0; d < 3; ++d) {
+    const double Fm = phat * n[d] + um[d] * Fr;
+    const double umb = w[4] * Fm + Fmb[d] * Fr + umnb * n[d];
+    aa.u[d] = bb.u[d] = 0.5 * umb;
+  }
+  const double iblb = c1 * Xb;
+  aa.k = bb.k = -0.25 * Xb;
+  const double rho_p = 0.5 * phatb * iS, beta_p = -phatb * phat * iS;
+  double dx, dlx, dy, dly;
+  log_mean_grad2(a.rho, b.rho, a.lrho, b.lrho, dx, dlx, dy, dly);
+  aa.rho = rho_p + rlnb * dx;
+  bb.rho = rho_p + rlnb * dy;
+  aa.lrho = rlnb * dlx;
+  bb.lrho = rlnb * dly;
+  inv_log_mean_grad2(a.beta, b.beta, a.lbeta, b.lbeta, dx, dlx, dy, dly);
+  aa.beta = beta_p + iblb * dx;
+  bb.beta = beta_p + iblb * dy;
+  aa.lbeta = iblb * dlx;
+  bb.lbeta = iblb * dly;
+}
+
 // d(w . F#(a, b; n))/d aux_a for Chandrashekar's flux (FP64 forward).
 __host__ __device__ inline void chandrashekar_vjp_a(const Aux& a, const Aux& b, const double n[3], double c1,
                                                     const double w[5], AuxBar& ab) {
@@ -436,8 +530,7 @@ __host__ __device__ inline void surface_flux_vjp(const double UL[5], const doubl
   } else {
     const Aux aL = make_aux(qL), aR = make_aux(qR);
     AuxBar bL, bR;
-    chandrashekar_vjp_a(aL, aR, nv, 0.5 / P.gm1, Phib, bL);
-    chandrashekar_vjp_a(aR, aL, nv, 0.5 / P.gm1, Phib, bR);
+    chandrashekar_vjp_ab(aL, aR, nv, 0.5 / P.gm1, Phib, bL, bR);
     aux_vjp(qL, aL, bL, P.gm1, ULb);
     aux_vjp(qR, aR, bR, P.gm1, URb);
   }

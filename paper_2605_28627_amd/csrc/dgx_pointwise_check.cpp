@@ -38,6 +38,17 @@ void pw_chandrashekar_vjp_a(const double* Ua, const double* Ub, const double* n,
   aux_vjp(qa, a, ab, P.gm1, Uab);
 }
 
+void pw_chandrashekar_vjp_ab(const double* Ua, const double* Ub, const double* n, const double* c, const double* w,
+                             double* Uab, double* Ubb) {
+  Phys P = make_phys(c);
+  Prim qa = cons2prim(Ua, P.gm1), qb = cons2prim(Ub, P.gm1);
+  Aux a = make_aux(qa), b = make_aux(qb);
+  AuxBar aa, bb;
+  chandrashekar_vjp_ab(a, b, n, 0.5 / P.gm1, w, aa, bb);
+  aux_vjp(qa, a, aa, P.gm1, Uab);
+  aux_vjp(qb, b, bb, P.gm1, Ubb);
+}
+
 void pw_euler_flux(const double* U, const double* n, const double* c, double* F) {
   Phys P = make_phys(c);
   euler_flux<double>(U, cons2prim(U, P.gm1), n, F);

@@ -82,6 +82,29 @@ def test_chandrashekar_vjp(pw, near):
         assert abs(vjp @ d - ref) < 1e-7 * (abs(ref) + np.abs(vjp).max() * np.abs(d).max()), (vjp @ d, ref)
 
 
+@pytest.mark.parametrize("near", [False, True])
+def test_chandrashekar_vjp_both_arguments(pw, near):
+    """The one-sweep VJP with respect to both states: each side against central
+    differences in that state, and the first side equal to the one-sided VJP."""
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        a = state(rng)
+        b = state(rng, 1e-4, a) if near else state(rng)
+        n = rng.normal(size=3)
+        w = rng.normal(size=5)
+        Uab, Ubb = np.zeros(5), np.zeros(5)
+        pw.pw_chandrashekar_vjp_ab(P(a), P(b), P(n), P(C), P(w), P(Uab), P(Ubb))
+        one = call(pw.pw_chandrashekar_vjp_a, 5, a, b, n, C, w)
+        assert np.allclose(Uab, one, rtol=1e-12, atol=1e-12 * np.abs(one).max())
+        eps = 1e-7 if near else 1e-6
+        da = rng.normal(size=5) * np.abs(a)
+        db = rng.normal(size=5) * np.abs(b)
+        ref_a = fd_dot(lambda x: call(pw.pw_chandrashekar, 5, x, b, n, C), a, da, w, eps=eps)
+        ref_b = fd_dot(lambda x: call(pw.pw_chandrashekar, 5, a, x, n, C), b, db, w, eps=eps)
+        assert abs(Uab @ da - ref_a) < 1e-7 * (abs(ref_a) + np.abs(Uab).max() * np.abs(da).max())
+        assert abs(Ubb @ db - ref_b) < 1e-7 * (abs(ref_b) + np.abs(Ubb).max() * np.abs(db).max())
+
+
 def test_euler_and_viscous_vjp(pw):
     rng = np.random.default_rng(2)
     for _ in range(40):
