@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--K", default=None, help="element counts K1,K2,K3 replacing the workload's")
     ap.add_argument("--state", default=None, choices=[None, "freestream"], help="replace the initial state")
+    ap.add_argument("--integrator", type=int, default=0, choices=[0, 1],
+                    help="0 = LSERK4(5) (5 stages), 1 = LSERK4-14 (14 stages)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -174,6 +176,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     w, cfg = workload_cfg(args.workload)
+    cfg["integrator"] = args.integrator
+    nst = len(dgx.dg_rk_coefficients(args.integrator)[0])
     K = tuple(int(x) for x in args.K.split(",")) if args.K else tuple(w["K"])
     _log("mesh", args.workload, K)
     mesh = I.workload_mesh(args.workload, K=K)
@@ -216,7 +220,7 @@ def main():
     final64 = []
     times64, prof = timed(s, profile=True, keep=final64)
     t64 = statistics.median(times64)
-    pid64 = t64 / (5 * args.steps * dof)
+    pid64 = t64 / (nst * args.steps * dof)
     vol_ms, vol_n = prof["volume"]
     vol_avg_s = vol_ms * 1e-3 / max(vol_n, 1)
     lift_ms, lift_n = prof["lift"]
@@ -245,8 +249,10 @@ def main():
         "config": {"workload": args.workload, "N": w["N"], "nodes": "LGL" if w["nodes"] else "LG",
                    "elements": list(K), "dof": dof, "physics": "navier-stokes" if w["physics"] else "euler",
                    "volume_form": "split" if w["form"] else "weak", "curved": bool(w["curved"]), "dt": dt,
+                   "integrator": ("LSERK4(5)", "LSERK4-14")[args.integrator], "stages_per_step": nst,
                    "state": args.state or w["state"]},
         "dof_updates_per_s": 1.0 / pid64,
+        "simulated_time_per_wall_s": dt * args.steps / t64,
         "reps": args.reps,
         "ms_per_step_reps": [1e3 * t / args.steps for t in times64],
         "kernels_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in prof.items()},
@@ -278,7 +284,7 @@ def main():
         final32 = []
         times32, prof32 = timed(s32, profile=True, keep=final32)
         t32 = statistics.median(times32)
-        result["pid_fp32_flux"] = t32 / (5 * args.steps * dof)
+        result["pid_fp32_flux"] = t32 / (nst * args.steps * dof)
         result["kernels_ms_per_launch_fp32_flux"] = {k: (v[0] / max(v[1], 1)) for k, v in prof32.items()}
         result["fp32_speedup"] = t64 / t32
         # relative L2 error per variable of the FP32-flux path against the FP64 path

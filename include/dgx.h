@@ -63,6 +63,11 @@ enum { DG_PHYS_EULER = 0, DG_PHYS_NAVIER_STOKES = 1 };
 enum { DG_RIEMANN_RUSANOV = 0, DG_RIEMANN_CENTRAL = 1 };
 enum { DG_TWOPOINT_CHANDRASHEKAR = 0, DG_TWOPOINT_CENTRAL = 1 };
 enum { DG_PREC_FP64 = 0, DG_PREC_FP32_FLUX = 1 };
+/* Low-storage explicit RK scheme (paper: time integration section): the
+ * five-stage LSERK4(5) of Carpenter and Kennedy, or the fourteen-stage
+ * LSERK4-14 of Niegemann, Diehl and Busch that the paper's production runs use. */
+enum { DG_RK_LSERK45 = 0, DG_RK_LSERK414 = 1 };
+#define DG_RK_MAX_STAGES 14
 
 typedef struct {
   int N;            /* polynomial degree, 1..7                                       */
@@ -73,6 +78,7 @@ typedef struct {
   int twopoint;     /* DG_TWOPOINT_*: Chandrashekar, or the flux average (tests)      */
   int precision;    /* DG_PREC_*: FP64, or FP32 flux arithmetic with FP64 state,
                        metrics, pressure recovery, metric contraction and update     */
+  int integrator;   /* DG_RK_*: the low-storage RK scheme of dg_rk_step               */
   double gamma;     /* ratio of specific heats                                        */
   double mu;        /* constant dynamic viscosity (Navier-Stokes)                     */
   double Pr;        /* Prandtl number                                                 */
@@ -94,6 +100,10 @@ const char* dg_last_error(const dg_ctx* ctx);
 
 /* The five-stage coefficients A, B, c of LSERK4(5) (Carpenter and Kennedy 1994). */
 dg_status dg_lserk_coefficients(double* A5, double* B5, double* c5);
+
+/* Coefficients A, B, c of the scheme DG_RK_* (arrays of DG_RK_MAX_STAGES
+ * entries; the first *nstages are written).  DG_ERR_ARG for an unknown scheme. */
+dg_status dg_rk_coefficients(int integrator, double* A, double* B, double* c, int* nstages);
 
 /* Mesh and metrics ------------------------------------------------------------ */
 
@@ -133,8 +143,9 @@ dg_status dg_sizes(const dg_ctx* ctx, int* nElems, int* nSides, int* nodes_per_e
 size_t dg_workspace_bytes(const dg_ctx* ctx);
 
 /* Bytes of device scratch that the adjoint calls need (the forward scratch
- * plus four recomputed stage states, an RK register, an adjoint residual and,
- * for Navier-Stokes, the gradient adjoint).  Valid after a mesh is set. */
+ * plus the recomputed stage states, four for LSERK4(5) and thirteen for
+ * LSERK4-14, an RK register, an adjoint residual and, for Navier-Stokes, the
+ * gradient adjoint).  Valid after a mesh is set. */
 size_t dg_workspace_bytes_adjoint(const dg_ctx* ctx);
 
 /* Binds caller-owned device memory of at least dg_workspace_bytes bytes,
@@ -167,7 +178,8 @@ dg_status dg_rhs(dg_ctx* ctx, const double* U, double* Ut, double t, void* strea
  * with q = (u, v, w, T) (paper eq. dgsem_lifted).  Navier-Stokes contexts only. */
 dg_status dg_lift(dg_ctx* ctx, const double* U, double* g, void* stream);
 
-/* nsteps steps of LSERK4(5) with fixed dt, in place: per stage
+/* nsteps steps of the context's low-storage RK scheme (LSERK4(5) or
+ * LSERK4-14) with fixed dt, in place: per stage s
  * dU <- A_s dU + dt R(U); U <- U + B_s dU.  dU is the 2N-storage register
  * (device, state length); it is zeroed by the call before the first stage. */
 dg_status dg_rk_step(dg_ctx* ctx, double* U, double* dU, double t, double dt, int nsteps, void* stream);
@@ -183,10 +195,11 @@ dg_status dg_rk_step(dg_ctx* ctx, double* U, double* dU, double t, double dt, in
  * a workspace of dg_workspace_bytes_adjoint bytes. */
 dg_status dg_adjoint_rhs(dg_ctx* ctx, const double* U, const double* lam, double* out, void* stream);
 
-/* Reverse of one LSERK4(5) step of size dt from state Un (device): on entry
- * lamU holds dJ/dU^{n+1}; on exit dJ/dU^n.  The stage inputs Y_0..Y_4 are
- * recomputed from Un into the workspace; then, with lamdU = B_4 lamU, for
- * s = 4..0: lamU += dt (dR/dU(Y_s))^T lamdU and lamdU = A_s lamdU + B_{s-1} lamU.
+/* Reverse of one step of size dt of the context's RK scheme (S stages) from
+ * state Un (device): on entry lamU holds dJ/dU^{n+1}; on exit dJ/dU^n.  The
+ * stage inputs Y_0..Y_{S-1} are recomputed from Un into the workspace; then,
+ * with lamdU = B_{S-1} lamU, for s = S-1..0: lamU += dt (dR/dU(Y_s))^T lamdU
+ * and lamdU = A_s lamdU + B_{s-1} lamU.
  * lamdU is a caller-owned device register of the state length (scratch).
  * Needs a workspace of dg_workspace_bytes_adjoint bytes. */
 dg_status dg_adjoint_rk_step(dg_ctx* ctx, const double* Un, double* lamU, double* lamdU, double t, double dt,
@@ -204,10 +217,12 @@ dg_status dg_kinetic_energy_grad(dg_ctx* ctx, const double* U, double rho0U0sq, 
 
 /* Fixed time step from the state (paper: CFL = 0.9 for the advective and the
  * viscous restriction; the formula is this library's reading):
- *   dt_a = cfl min(2/(N+1), 8/(N+1)^2) / max sum_r (|Ja^r.u| + c|Ja^r|)/J
- *   dt_v = cfl 32/(N+1)^4 / max (mu/rho) max(4/3, gamma/Pr) sum_r |Ja^r|^2/J^2
- * dt = min(dt_a, dt_v) (dt_v for Navier-Stokes only).  Synchronises the
- * stream and writes the host double dt_out. */
+ *   dt_a = cfl S min(2/(N+1), 8/(N+1)^2) / max sum_r (|Ja^r.u| + c|Ja^r|)/J
+ *   dt_v = cfl S 32/(N+1)^4 / max (mu/rho) max(4/3, gamma/Pr) sum_r |Ja^r|^2/J^2
+ * dt = min(dt_a, dt_v) (dt_v for Navier-Stokes only), with S = 1 for
+ * LSERK4(5) and S = 3.75 for LSERK4-14, whose stability limit on the DG
+ * spectrum is 3.98 times larger.  Synchronises the stream and writes the
+ * host double dt_out. */
 dg_status dg_timestep(dg_ctx* ctx, const double* U, double cfl, double* dt_out, void* stream);
 
 /* DG_ERR_NONPHYSICAL if any node has rho <= 0, p <= 0 or a non-finite

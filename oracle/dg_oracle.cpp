@@ -203,6 +203,7 @@ struct Config {
   int twopoint = 0;     // 0 = Chandrashekar, 1 = central average (test switch)
   int dissipation = 1;  // 1 = Rusanov dissipation on, 0 = off (test switch)
   int mms = 0;          // 1 = add the manufactured-solution source
+  int integrator = 0;   // 0 = LSERK4(5) (Carpenter & Kennedy), 1 = LSERK4-14 (Niegemann, Diehl & Busch)
   double gamma = 1.4, mu = 0.0, Pr = 0.72, R = 1.0;
   double mms_A = 0.1, mms_a = 1.0;
 };
@@ -245,6 +246,31 @@ static void lserk_coeffs(double* A, double* B, double* C) {
   for (int s = 0; s < 5; ++s) { A[s] = a[s]; B[s] = b[s]; C[s] = c[s]; }
 }
 
+// Niegemann, Diehl & Busch (2012) fourteen-stage, fourth-order 2N-storage
+// scheme with a stability region fitted to DG spectra (their RK4-14 table).
+static void lserk14_coeffs(double* A, double* B, double* C) {
+  const double a[14] = {0.0, -0.7188012108672410, -0.7785331173421570, -0.0053282796654044,
+                        -0.8552979934029281, -3.9564138245774565, -1.5780575380587385, -2.0837094552574054,
+                        -0.7483334182761610, -0.7032861106563359, 0.0013917096117681, -0.0932075369637460,
+                        -0.9514200470875948, -7.1151571693922548};
+  const double b[14] = {0.0367762454319673, 0.3136296607553959, 0.1531848691869027, 0.0030097086818182,
+                        0.3326293790646110, 0.2440251405350864, 0.3718879239592277, 0.6204126221582444,
+                        0.1524043173028741, 0.0760894927419266, 0.0077604214040978, 0.0024647284755382,
+                        0.0780348340049386, 5.5059777270269628};
+  const double c[14] = {0.0, 0.0367762454319673, 0.1249685262725025, 0.2446177702277698,
+                        0.2476149531070420, 0.2969311120382472, 0.3978149645802642, 0.5270854589440328,
+                        0.6981269994175695, 0.8190890835352128, 0.8527059887098624, 0.8604711817462826,
+                        0.8627060376969976, 0.8734213127600976};
+  for (int s = 0; s < 14; ++s) { A[s] = a[s]; B[s] = b[s]; C[s] = c[s]; }
+}
+
+// Coefficients of the chosen scheme; returns its number of stages (0 if unknown).
+static int rk_coeffs(int integrator, double* A, double* B, double* C) {
+  if (integrator == 0) { lserk_coeffs(A, B, C); return 5; }
+  if (integrator == 1) { lserk14_coeffs(A, B, C); return 14; }
+  return 0;
+}
+
 struct Solver {
   Config C;
   Basis B;
@@ -260,13 +286,15 @@ struct Solver {
   std::vector<std::vector<double>> Xnode;    // per element: [3][n3]
   std::vector<std::vector<double>> nvec;     // per side: [3][n2] master outward n*s
   std::string err;
-  double lsA[5], lsB[5], lsC[5];
+  double lsA[14], lsB[14], lsC[14];
+  int nstages = 5;
 
   int node(int i, int j, int k) const { return (k * n1 + j) * n1 + i; }
   size_t uidx(int v, int e, int nd) const { return ((size_t)v * nElems + e) * n3 + nd; }
 
   bool setup() {
-    lserk_coeffs(lsA, lsB, lsC);
+    nstages = rk_coeffs(C.integrator, lsA, lsB, lsC);
+    if (nstages == 0) { err = "unknown integrator"; return false; }
     if (!make_basis(C.N, C.nodes, B)) { err = "bad basis"; return false; }
     if (C.form == 1 && C.nodes != 1) { err = "split form needs LGL nodes"; return false; }
     n1 = C.N + 1; n2 = n1 * n1; n3 = n2 * n1;
@@ -764,14 +792,15 @@ struct Solver {
     }
   }
 
-  // LSERK4(5), 2N-storage: dU <- A_s dU + dt R(U, t + c_s dt); U <- U + B_s dU.
+  // Low-storage RK (LSERK4(5) or LSERK4-14), 2N-storage, per stage s:
+  // dU <- A_s dU + dt R(U, t + c_s dt); U <- U + B_s dU.
   template <class T> void lserk(T* U, int nsteps, double dt, double t0) {
     const size_t n = (size_t)5 * nElems * n3;
     std::vector<T> dU(n, T(0.0)), R(n);
     std::vector<int> all;
     double t = t0;
     for (int step = 0; step < nsteps; ++step) {
-      for (int s = 0; s < 5; ++s) {
+      for (int s = 0; s < nstages; ++s) {
         rhs(U, R.data(), t + lsC[s] * dt, all);
         for (size_t i = 0; i < n; ++i) {
           dU[i] = lsA[s] * dU[i] + dt * R[i];
@@ -833,9 +862,12 @@ struct Solver {
         vmax = std::max(vmax, C.mu / rho * std::max(4.0 / 3.0, C.gamma / C.Pr) * sv / (J * J));
       }
     }
+    // LSERK4-14: its stability region reaches 3.98 times further along the
+    // DG spectrum (eigenvalues of the linearised operator), step scaled by 3.75
     const double n1 = C.N + 1.0;
-    double dt = cfl * std::min(2.0 / n1, 8.0 / (n1 * n1)) / amax;
-    if (C.physics == 1 && vmax > 0.0) dt = std::min(dt, cfl * 32.0 / (n1 * n1 * n1 * n1 * vmax));
+    const double sc = cfl * (C.integrator == 1 ? 3.75 : 1.0);
+    double dt = sc * std::min(2.0 / n1, 8.0 / (n1 * n1)) / amax;
+    if (C.physics == 1 && vmax > 0.0) dt = std::min(dt, sc * 32.0 / (n1 * n1 * n1 * n1 * vmax));
     return dt;
   }
 };
@@ -846,7 +878,7 @@ using orc::Solver;
 
 // ---------------------------------------------------------------------------
 // C interface used by the test suite (through ctypes).
-// icfg = {N, nodes, form, physics, twopoint, dissipation, mms}
+// icfg = {N, nodes, form, physics, twopoint, dissipation, mms, integrator}
 // dcfg = {gamma, mu, Pr, R, mms_A, mms_a}
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -868,7 +900,7 @@ void* orc_create(const int* icfg, const double* dcfg, int nElems, int Ngeo, cons
                  const int* sideElem, const int* sideLoc, const int* sideOrient) {
   Solver* S = new Solver();
   S->C.N = icfg[0]; S->C.nodes = icfg[1]; S->C.form = icfg[2]; S->C.physics = icfg[3];
-  S->C.twopoint = icfg[4]; S->C.dissipation = icfg[5]; S->C.mms = icfg[6];
+  S->C.twopoint = icfg[4]; S->C.dissipation = icfg[5]; S->C.mms = icfg[6]; S->C.integrator = icfg[7];
   S->C.gamma = dcfg[0]; S->C.mu = dcfg[1]; S->C.Pr = dcfg[2]; S->C.R = dcfg[3];
   S->C.mms_A = dcfg[4]; S->C.mms_a = dcfg[5];
   S->nElems = nElems; S->Ngeo = Ngeo; S->nSides = nSides;
@@ -890,6 +922,7 @@ int orc_check_jacobians(void* h) {
 void orc_destroy(void* h) { delete (Solver*)h; }
 
 void orc_lserk_coeffs(double* A, double* B, double* C) { orc::lserk_coeffs(A, B, C); }
+int orc_rk_coeffs(int integrator, double* A, double* B, double* C) { return orc::rk_coeffs(integrator, A, B, C); }
 
 // Node coordinates [3][nElems][n3], Jacobian [nElems][n3], metrics [9][nElems][n3].
 void orc_geometry(void* h, double* xyz, double* J, double* Ja) {

@@ -60,6 +60,8 @@ def lib():
         L.orc_timestep.restype = ctypes.c_double
         L.orc_timestep.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
         L.orc_rhs_opcount.argtypes = [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_uint64)]
+        L.orc_rk_coeffs.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+        L.orc_rk_coeffs.restype = ctypes.c_int
         L.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_lserk_coeffs.argtypes = [_dp, _dp, _dp]
         L.orc_flux_twopoint.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
@@ -92,6 +94,15 @@ def basis(N, nodes):
     return dict(x=x, w=w, D=D, Lm=Lm, Lp=Lp, DS=DS)
 
 
+def rk_coeffs(integrator):
+    """A, B, c of the low-storage scheme: 0 = LSERK4(5), 1 = LSERK4-14."""
+    A, B, C = np.zeros(14), np.zeros(14), np.zeros(14)
+    ns = lib().orc_rk_coeffs(int(integrator), _d(A), _d(B), _d(C))
+    if ns == 0:
+        raise ValueError("unknown integrator")
+    return A[:ns], B[:ns], C[:ns]
+
+
 def lserk_coeffs():
     A, B, C = np.zeros(5), np.zeros(5), np.zeros(5)
     lib().orc_lserk_coeffs(_d(A), _d(B), _d(C))
@@ -100,7 +111,8 @@ def lserk_coeffs():
 
 def _cfg_arrays(cfg):
     icfg = np.array([cfg.get("N", 3), cfg.get("nodes", 0), cfg.get("form", 0), cfg.get("physics", 0),
-                     cfg.get("twopoint", 0), cfg.get("dissipation", 1), cfg.get("mms", 0)], dtype=np.int32)
+                     cfg.get("twopoint", 0), cfg.get("dissipation", 1), cfg.get("mms", 0),
+                     cfg.get("integrator", 0)], dtype=np.int32)
     dcfg = np.array([cfg.get("gamma", 1.4), cfg.get("mu", 0.0), cfg.get("Pr", 0.72), cfg.get("R", 1.0),
                      cfg.get("mms_A", 0.1), cfg.get("mms_a", 1.0)], dtype=np.float64)
     return icfg, dcfg

@@ -27,11 +27,13 @@ if not os.path.exists(LIB_PATH):
 _L = ctypes.CDLL(LIB_PATH)
 
 DG_OK, DG_ERR_ARG, DG_ERR_MESH, DG_ERR_HIP, DG_ERR_NONPHYSICAL, DG_ERR_NOMEM, DG_ERR_UNSUPPORTED, DG_ERR_STATE = range(8)
+DG_RK_LSERK45, DG_RK_LSERK414 = 0, 1
+DG_RK_MAX_STAGES = 14
 STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_MESH", 3: "DG_ERR_HIP", 4: "DG_ERR_NONPHYSICAL",
                 5: "DG_ERR_NOMEM", 6: "DG_ERR_UNSUPPORTED", 7: "DG_ERR_STATE"}
 
 # public symbols of include/dgx.h
-SYMBOLS = ["dg_create", "dg_destroy", "dg_last_error", "dg_lserk_coefficients", "dg_set_mesh", "dg_upload_mesh",
+SYMBOLS = ["dg_create", "dg_destroy", "dg_last_error", "dg_lserk_coefficients", "dg_rk_coefficients", "dg_set_mesh", "dg_upload_mesh",
            "dg_upload_metrics", "dg_get_metrics", "dg_node_coords", "dg_sizes", "dg_workspace_bytes",
            "dg_workspace_bytes_adjoint", "dg_bind_workspace", "dg_init_state", "dg_rhs", "dg_lift", "dg_rk_step", "dg_adjoint_rhs", "dg_adjoint_rk_step",
            "dg_kinetic_energy", "dg_kinetic_energy_grad", "dg_timestep", "dg_check_state", "dg_profile",
@@ -41,7 +43,8 @@ SYMBOLS = ["dg_create", "dg_destroy", "dg_last_error", "dg_lserk_coefficients", 
 class dg_config(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("nodes", ctypes.c_int), ("volume_form", ctypes.c_int),
                 ("physics", ctypes.c_int), ("riemann", ctypes.c_int), ("twopoint", ctypes.c_int),
-                ("precision", ctypes.c_int), ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
+                ("precision", ctypes.c_int), ("integrator", ctypes.c_int), ("gamma", ctypes.c_double),
+                ("mu", ctypes.c_double),
                 ("Pr", ctypes.c_double), ("R", ctypes.c_double)]
 
 
@@ -58,6 +61,7 @@ _sig = {
     "dg_destroy": (ctypes.c_int, [_vp]),
     "dg_last_error": (ctypes.c_char_p, [_vp]),
     "dg_lserk_coefficients": (ctypes.c_int, [_dp, _dp, _dp]),
+    "dg_rk_coefficients": (ctypes.c_int, [ctypes.c_int, _dp, _dp, _dp, _ip]),
     "dg_set_mesh": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _ip, _ip, _ip]),
     "dg_upload_mesh": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _ip, _ip, _ip]),
     "dg_upload_metrics": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
@@ -123,9 +127,9 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_config(N, nodes=1, volume_form=0, physics=0, riemann=0, twopoint=0, precision=0, gamma=1.4, mu=0.0,
-                Pr=0.72, R=1.0):
-    return dg_config(N, nodes, volume_form, physics, riemann, twopoint, precision, gamma, mu, Pr, R)
+def make_config(N, nodes=1, volume_form=0, physics=0, riemann=0, twopoint=0, precision=0, integrator=0, gamma=1.4,
+                mu=0.0, Pr=0.72, R=1.0):
+    return dg_config(N, nodes, volume_form, physics, riemann, twopoint, precision, integrator, gamma, mu, Pr, R)
 
 
 def dg_create(cfg: dg_config):
@@ -147,6 +151,14 @@ def dg_lserk_coefficients():
     A, B, C = np.zeros(5), np.zeros(5), np.zeros(5)
     _check(None, _L.dg_lserk_coefficients(_hd(A), _hd(B), _hd(C)))
     return A, B, C
+
+
+def dg_rk_coefficients(integrator):
+    """(A, B, c) of the scheme DG_RK_* (length = its number of stages)."""
+    A, B, C = (np.zeros(DG_RK_MAX_STAGES) for _ in range(3))
+    ns = ctypes.c_int(0)
+    _check(None, _L.dg_rk_coefficients(int(integrator), _hd(A), _hd(B), _hd(C), ctypes.byref(ns)))
+    return A[:ns.value], B[:ns.value], C[:ns.value]
 
 
 def _mesh_args(mesh):

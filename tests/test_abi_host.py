@@ -61,6 +61,22 @@ def test_lserk_coefficients_match_oracle(dgx, orc):
     assert np.array_equal(A, Ao) and np.array_equal(B, Bo) and np.array_equal(C, Co)
 
 
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_rk_coefficients_match_oracle(dgx, orc, integrator):
+    """The library's tables equal the oracle's (pinned there by the order conditions)."""
+    got = dgx.dg_rk_coefficients(integrator)
+    want = orc.rk_coeffs(integrator)
+    assert len(got[0]) == (5, 14)[integrator]
+    for g, w in zip(got, want):
+        assert np.array_equal(g, w)
+    with pytest.raises(dgx.DGError) as ei:
+        dgx.dg_rk_coefficients(7)
+    assert ei.value.status == dgx.DG_ERR_ARG
+    with pytest.raises(dgx.DGError) as ei:
+        dgx.dg_create(dgx.make_config(3, integrator=2))
+    assert ei.value.status == dgx.DG_ERR_ARG
+
+
 @pytest.mark.parametrize("N,nodes,curved,rot", [(3, 0, 0.0, None), (5, 1, 0.1, 7), (7, 1, 0.1, 3), (4, 0, 0.0, 9)])
 def test_host_metrics_match_oracle(dgx, orc, N, nodes, curved, rot):
     mesh = I.box_mesh((3, 2, 2), (-PI,) * 3, (PI,) * 3, Ngeo=N if curved else 1, curved_amp=curved, rotate_seed=rot)

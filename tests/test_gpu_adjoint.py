@@ -118,6 +118,28 @@ def test_adjoint_rk_step(S, orc, case, ):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("case", [CASES[0], CASES[6]], ids=str)
+def test_adjoint_rk14_step(S, orc, case):
+    """Reverse of one LSERK4-14 step (13 recomputed stage states) against the
+    oracle's tangent of the same step."""
+    o, s = _pair(S, orc, case, integrator=1)
+    U = I.smooth_random_state(o.coords(), 59, amp=0.2)
+    dt = o.timestep(U, 0.9)
+    rng = np.random.default_rng(60)
+    lam1 = rng.normal(size=U.shape)
+    d = rng.normal(size=U.shape)
+    import torch
+    lamU = s.to_device(lam1)
+    lamdU = torch.empty_like(lamU)
+    s.adjoint_rk_step(s.to_device(U), lamU, lamdU, dt)
+    a = (lamU.cpu().numpy() * d).sum()
+    _, dT = o.lserk_jvp(U, d, 1, dt)
+    b = (lam1 * dT).sum()
+    err = abs(a - b) / np.abs(lam1 * dT).sum()
+    _say(case, "rk14 step adjoint rel err", err)
+    assert err < 1e-12
+
+
 @pytest.mark.parametrize("case", [(3, 1, 1, 0, 0.0, None), (3, 1, 1, 1, 0.1, 2)], ids=str)
 def test_trajectory_gradient_vs_oracle(S, orc, case):
     import torch

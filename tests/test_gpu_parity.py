@@ -139,6 +139,23 @@ def test_rk_steps_match_oracle(S, orc, case):
     assert np.all(err < 1e-11), err
 
 
+@pytest.mark.parametrize("case", [CASES[0], CASES[6], CASES[9]], ids=str)
+def test_rk14_steps_and_timestep_match_oracle(S, orc, case):
+    """LSERK4-14: three steps and the time step against the oracle's."""
+    _say("rk14", case)
+    o, s, _ = _setup(S, orc, case, integrator=1)
+    U0 = I.smooth_random_state(o.coords(), 36, amp=0.2)
+    dt = o.timestep(U0, 0.9)
+    Ug = s.init_state(U0)
+    assert abs(s.timestep(Ug, 0.9) / dt - 1.0) < 1e-13
+    U_orc = o.lserk(U0, 3, dt)
+    dUg = s.empty_state()
+    s.rk_step(Ug, dUg, dt, 3)
+    err = rel_err_per_var(Ug.cpu().numpy() - U0, U_orc - U0)
+    _say("rk14", case, err)
+    assert np.all(err < 1e-11), err
+
+
 def test_init_state(S, orc, torch_cuda):
     """dg_init_state: host and device sources give the same bits, an aliased
     source only checks, and non-physical or non-finite states are refused."""

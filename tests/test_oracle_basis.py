@@ -94,6 +94,32 @@ def _butcher_from_2n(A, B):
     return a[:s], a[s]
 
 
+def test_lserk14_order_conditions(orc):
+    """LSERK4-14 (Niegemann, Diehl & Busch): the same eight conditions.  The
+    published coefficients carry 16 significant digits, so the conditions
+    hold to about 5e-14 (sums of 14 terms of size up to 7); c to round-off."""
+    A, B, C = orc.rk_coeffs(1)
+    assert len(A) == 14
+    a, b = _butcher_from_2n(A, B)
+    c = a.sum(1)
+    assert np.abs(c - C).max() < 1e-14
+    conds = [
+        (b.sum(), 1.0),
+        (b @ c, 1 / 2),
+        (b @ c ** 2, 1 / 3),
+        (b @ (a @ c), 1 / 6),
+        (b @ c ** 3, 1 / 4),
+        (b @ (c * (a @ c)), 1 / 8),
+        (b @ (a @ c ** 2), 1 / 12),
+        (b @ (a @ (a @ c)), 1 / 24),
+    ]
+    for got, want in conds:
+        assert abs(got - want) < 1e-13, (got, want)
+    assert A[0] == 0.0
+    A5, B5, C5 = orc.rk_coeffs(0)
+    assert np.array_equal(np.concatenate([A5, B5, C5]), np.concatenate(orc.lserk_coeffs()))
+
+
 def test_lserk_order_conditions(orc):
     A, B, C = orc.lserk_coeffs()
     a, b = _butcher_from_2n(A, B)

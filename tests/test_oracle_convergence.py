@@ -64,8 +64,9 @@ def test_mms_navier_stokes_h_convergence(orc):
     assert abs(eoc[-1] - gold[3, 2]) < 0.5
 
 
-def test_lserk_fourth_order_in_time(orc):
-    cfg = dict(N=3, nodes=1, form=1, physics=0)
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_lserk_fourth_order_in_time(orc, integrator):
+    cfg = dict(N=3, nodes=1, form=1, physics=0, integrator=integrator)
     mesh = I.box_mesh((2,) * 3, (0,) * 3, (2,) * 3)
     o = orc.Oracle(cfg, mesh)
     U0 = I.density_wave_state(o.coords())

@@ -277,6 +277,43 @@ def test_timestep_is_not_overly_conservative(orc):
     assert g > 1.05, g
 
 
+@pytest.mark.parametrize("integrator", [0, 1])
+@pytest.mark.parametrize("case", ["advective", "viscous"])
+def test_timestep_stability_by_eigenvalues(orc, integrator, case):
+    """On one periodic N=3 element the linearised residual is assembled from the
+    oracle's exact tangents; its eigenvalues lambda and the scheme's stability
+    polynomial R (built from the 2N-storage coefficients) give max |R(dt lambda)|:
+    at most 1 at the time-step reading, above 1 at 2.5 times the step (the
+    reading sits within a factor 2.5 of the limit, for LSERK4(5) and LSERK4-14
+    alike; measured limits 1.7-2.4 times the reading)."""
+    mesh = I.box_mesh((1, 1, 1), (-PI,) * 3, (PI,) * 3)
+    if case == "advective":
+        cfg, u, p = dict(N=3, nodes=1, form=1, physics=0), (1.0, 0.3, 0.0), 71.43
+    else:
+        cfg, u, p = dict(N=3, nodes=1, form=1, physics=1, mu=2.0), (0.1, 0.0, 0.0), 1.0
+    o = orc.Oracle(dict(cfg, integrator=integrator), mesh)
+    U = _uniform(o, u, p)
+    n = U.size
+    Jm = np.zeros((n, n))
+    for col in range(n):
+        e = np.zeros(n)
+        e[col] = 1.0
+        Jm[:, col] = o.rhs_jvp(U, e.reshape(U.shape))[1].ravel()
+    lam = np.linalg.eigvals(Jm)
+    A, B, _ = orc.rk_coeffs(integrator)
+
+    def amp(z):
+        y, d = np.ones_like(z), np.zeros_like(z)
+        for a, b in zip(A, B):
+            d = a * d + z * y
+            y = y + b * d
+        return np.abs(y).max()
+
+    dt = o.timestep(U, 0.9)
+    assert amp(dt * lam) <= 1.0 + 1e-12
+    assert amp(2.5 * dt * lam) > 1.0 + 1e-6
+
+
 @pytest.mark.parametrize("N", [3, 7])
 def test_viscous_timestep_is_linearly_stable(orc, N):
     cfg = dict(N=N, nodes=1, form=1, physics=1, mu=2.0)
