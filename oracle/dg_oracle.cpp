@@ -201,10 +201,12 @@ static double lagrange(const std::vector<double>& xs, int j, double xi) {
 struct Config {
   int N = 3, nodes = 0, form = 0, physics = 0;
   int twopoint = 0;     // 0 = Chandrashekar, 1 = central average (test switch)
-  int dissipation = 1;  // 1 = Rusanov dissipation on, 0 = off (test switch)
+  int dissipation = 1;  // 1 = Rusanov, 0 = none (test switch), 2 = Roe with the Harten-Hyman entropy fix
   int mms = 0;          // 1 = add the manufactured-solution source
   int integrator = 0;   // 0 = LSERK4(5) (Carpenter & Kennedy), 1 = LSERK4-14 (Niegemann, Diehl & Busch)
+  int viscosity = 0;    // 0 = constant mu, 1 = Sutherland's law mu(T)
   double gamma = 1.4, mu = 0.0, Pr = 0.72, R = 1.0;
+  double Tref = 1.0, Ts = 110.4 / 273.15;   // Sutherland: reference temperature, S / Tref
   double mms_A = 0.1, mms_a = 1.0;
 };
 
@@ -480,12 +482,21 @@ struct Solver {
     F[4] = F[0] * (1.0 / (2.0 * (C.gamma - 1.0) * beta_ln) - 0.5 * u2m) +
            (um[0] * F[1] + um[1] * F[2] + um[2] * F[3]);
   }
+  // Dynamic viscosity at temperature temp: constant, or Sutherland's law
+  // mu = mu_ref (T/Tref)^(3/2) (1 + S/Tref) / (T/Tref + S/Tref) with mu_ref = C.mu
+  // the viscosity at Tref (the TGV section's temperature-dependent viscosity).
+  template <class T> T viscosity(const T& temp) const {
+    if (C.viscosity == 0) return T(C.mu);
+    const T th = temp / C.Tref;
+    return C.mu * th * sqrt(th) * (1.0 + C.Ts) / (th + C.Ts);
+  }
   // Viscous flux G_n(U, grad) in Cartesian direction n; grad[3*a+d] = dq_a/dx_d,
-  // q = (u, v, w, T).  Newtonian stress with Stokes' hypothesis, Fourier heat flux.
+  // q = (u, v, w, T).  Newtonian stress with Stokes' hypothesis, Fourier heat
+  // flux with the conductivity of constant Prandtl number.
   template <class T> void flux_visc(const T* U, const T* g, int n, T* G) const {
     T rho, u[3], p; prim(U, rho, u, p);
-    const double mu = C.mu;
-    const double lam = C.mu * C.gamma * C.R / ((C.gamma - 1.0) * C.Pr);
+    const T mu = viscosity(T(p / (rho * C.R)));
+    const T lam = mu * (C.gamma * C.R / ((C.gamma - 1.0) * C.Pr));
     T divu = g[0] + g[4] + g[8];
     T tau[3];
     for (int a = 0; a < 3; ++a) {
@@ -495,6 +506,61 @@ struct Solver {
     G[0] = T(0.0);
     for (int a = 0; a < 3; ++a) G[1 + a] = tau[a];
     G[4] = tau[0] * u[0] + tau[1] * u[1] + tau[2] * u[2] + lam * g[9 + n];
+  }
+
+  // Roe's linearisation (Roe 1981) across a face with unit normal nh: Roe
+  // averages, the five waves (two acoustic, entropy, two shear) and their
+  // strengths.  mode 0: D = |A~|(UR-UL), with the Harten & Hyman (1983)
+  // entropy fix on the acoustic speeds (delta = max(0, l~ - l(UL), l(UR) - l~);
+  // |l~| < delta becomes (l~^2 + delta^2)/(2 delta)); mode 1: A~(UR-UL) with
+  // signed speeds (Roe's property: equals f(UR).nh - f(UL).nh); mode 2: |A~|(UR-UL)
+  // without the fix.
+  template <class T> void roe_matrix(const T* UL, const T* UR, const double* nh, int mode, T* D) const {
+    T rl, ul[3], pl, rr, ur[3], pr;
+    prim(UL, rl, ul, pl); prim(UR, rr, ur, pr);
+    const T HL = (UL[4] + pl) / rl, HR = (UR[4] + pr) / rr;
+    const T sl = sqrt(rl), sr = sqrt(rr), ws = sl + sr;
+    T um[3];
+    for (int d = 0; d < 3; ++d) um[d] = (sl * ul[d] + sr * ur[d]) / ws;
+    const T Hm = (sl * HL + sr * HR) / ws;
+    const T q2 = um[0] * um[0] + um[1] * um[1] + um[2] * um[2];
+    const T c2 = (C.gamma - 1.0) * (Hm - 0.5 * q2);
+    const T cm = sqrt(c2);
+    const T rm = sl * sr;
+    const T unm = um[0] * nh[0] + um[1] * nh[1] + um[2] * nh[2];
+    const T dr = rr - rl, dp = pr - pl;
+    T du[3];
+    for (int d = 0; d < 3; ++d) du[d] = ur[d] - ul[d];
+    const T dun = du[0] * nh[0] + du[1] * nh[1] + du[2] * nh[2];
+    const T a1 = (dp - rm * cm * dun) / (2.0 * c2);
+    const T a5 = (dp + rm * cm * dun) / (2.0 * c2);
+    const T a2 = dr - dp / c2;
+    T l1 = unm - cm, l2 = unm, l5 = unm + cm;
+    if (mode != 1) {
+      l2 = absv(l2);
+      T fix[2] = {l1, l5};
+      const T cl = sqrt(C.gamma * pl / rl), cr = sqrt(C.gamma * pr / rr);
+      const T unl = ul[0] * nh[0] + ul[1] * nh[1] + ul[2] * nh[2];
+      const T unr = ur[0] * nh[0] + ur[1] * nh[1] + ur[2] * nh[2];
+      const T lL[2] = {unl - cl, unl + cl}, lR[2] = {unr - cr, unr + cr};
+      for (int k = 0; k < 2; ++k) {
+        T a = absv(fix[k]);
+        if (mode == 0) {
+          const T delta = maxv(maxv(T(0.0), T(fix[k] - lL[k])), T(lR[k] - fix[k]));
+          if (val(a) < val(delta)) a = (fix[k] * fix[k] + delta * delta) / (2.0 * delta);
+        }
+        fix[k] = a;
+      }
+      l1 = fix[0]; l5 = fix[1];
+    }
+    // acoustic waves r1,5 = (1, u~ -+ c~ n, H~ -+ un~ c~), entropy wave (1, u~, q2/2),
+    // shear waves rho~ (0, du - dun n, u~.du - un~ dun)
+    const T udu = um[0] * du[0] + um[1] * du[1] + um[2] * du[2];
+    D[0] = l1 * a1 + l2 * a2 + l5 * a5;
+    for (int d = 0; d < 3; ++d)
+      D[1 + d] = l1 * a1 * (um[d] - cm * nh[d]) + l2 * (a2 * um[d] + rm * (du[d] - dun * nh[d])) +
+                 l5 * a5 * (um[d] + cm * nh[d]);
+    D[4] = l1 * a1 * (Hm - unm * cm) + l2 * (a2 * 0.5 * q2 + rm * (udu - unm * dun)) + l5 * a5 * (Hm + unm * cm);
   }
 
   // Manufactured solution of the convergence section:
@@ -657,16 +723,23 @@ struct Solver {
         flux_adv(UL, nv, FL); flux_adv(UR, nv, FR);
         for (int v = 0; v < 5; ++v) Fc[v] = 0.5 * (FL[v] + FR[v]);
       }
-      T lmax(0.0);
-      if (C.dissipation) {
-        T rl, ul[3], pl, rr, ur[3], pr;
-        prim(UL, rl, ul, pl); prim(UR, rr, ur, pr);
-        T cl = sqrt(C.gamma * pl / rl), cr = sqrt(C.gamma * pr / rr);
-        T unl = ul[0] * nh[0] + ul[1] * nh[1] + ul[2] * nh[2];
-        T unr = ur[0] * nh[0] + ur[1] * nh[1] + ur[2] * nh[2];
-        lmax = maxv(T(absv(unl) + cl), T(absv(unr) + cr));
+      if (C.dissipation == 2) {
+        // Roe: central part minus (1/2)|A~|(UR - UL), on the unit normal, times s
+        T D[5];
+        roe_matrix(UL, UR, nh, 0, D);
+        for (int v = 0; v < 5; ++v) Phi[(size_t)v * n2 + fi] = Fc[v] - 0.5 * sA * D[v];
+      } else {
+        T lmax(0.0);
+        if (C.dissipation) {
+          T rl, ul[3], pl, rr, ur[3], pr;
+          prim(UL, rl, ul, pl); prim(UR, rr, ur, pr);
+          T cl = sqrt(C.gamma * pl / rl), cr = sqrt(C.gamma * pr / rr);
+          T unl = ul[0] * nh[0] + ul[1] * nh[1] + ul[2] * nh[2];
+          T unr = ur[0] * nh[0] + ur[1] * nh[1] + ur[2] * nh[2];
+          lmax = maxv(T(absv(unl) + cl), T(absv(unr) + cr));
+        }
+        for (int v = 0; v < 5; ++v) Phi[(size_t)v * n2 + fi] = Fc[v] - 0.5 * (lmax * sA) * (UR[v] - UL[v]);
       }
-      for (int v = 0; v < 5; ++v) Phi[(size_t)v * n2 + fi] = Fc[v] - 0.5 * (lmax * sA) * (UR[v] - UL[v]);
       if (C.physics == 1) {
         T gL[12], gR[12];
         for (int c = 0; c < 12; ++c) {
@@ -859,7 +932,7 @@ struct Solver {
           sv += nrm2;
         }
         amax = std::max(amax, sa / J);
-        vmax = std::max(vmax, C.mu / rho * std::max(4.0 / 3.0, C.gamma / C.Pr) * sv / (J * J));
+        vmax = std::max(vmax, viscosity(p / (rho * C.R)) / rho * std::max(4.0 / 3.0, C.gamma / C.Pr) * sv / (J * J));
       }
     }
     // LSERK4-14: its stability region reaches 3.98 times further along the
@@ -878,8 +951,8 @@ using orc::Solver;
 
 // ---------------------------------------------------------------------------
 // C interface used by the test suite (through ctypes).
-// icfg = {N, nodes, form, physics, twopoint, dissipation, mms, integrator}
-// dcfg = {gamma, mu, Pr, R, mms_A, mms_a}
+// icfg = {N, nodes, form, physics, twopoint, dissipation, mms, integrator, viscosity}
+// dcfg = {gamma, mu, Pr, R, mms_A, mms_a, Tref, Ts}
 // ---------------------------------------------------------------------------
 extern "C" {
 
@@ -901,7 +974,9 @@ void* orc_create(const int* icfg, const double* dcfg, int nElems, int Ngeo, cons
   Solver* S = new Solver();
   S->C.N = icfg[0]; S->C.nodes = icfg[1]; S->C.form = icfg[2]; S->C.physics = icfg[3];
   S->C.twopoint = icfg[4]; S->C.dissipation = icfg[5]; S->C.mms = icfg[6]; S->C.integrator = icfg[7];
+  S->C.viscosity = icfg[8];
   S->C.gamma = dcfg[0]; S->C.mu = dcfg[1]; S->C.Pr = dcfg[2]; S->C.R = dcfg[3];
+  S->C.Tref = dcfg[6]; S->C.Ts = dcfg[7];
   S->C.mms_A = dcfg[4]; S->C.mms_a = dcfg[5];
   S->nElems = nElems; S->Ngeo = Ngeo; S->nSides = nSides;
   if (nElems <= 0 || Ngeo < 1 || nSides * 2 != nElems * 6) { g_err = "bad sizes"; delete S; return nullptr; }
@@ -1051,6 +1126,19 @@ void orc_flux_adv(const double* dcfg, const double* U, const double* nv, double*
 void orc_flux_visc(const double* dcfg, const double* U, const double* g, int n, double* G) {
   Solver S; S.C.gamma = dcfg[0]; S.C.mu = dcfg[1]; S.C.Pr = dcfg[2]; S.C.R = dcfg[3];
   S.flux_visc<double>(U, g, n, G);
+}
+void orc_flux_visc_law(const int* icfg, const double* dcfg, const double* U, const double* g, int n, double* G) {
+  Solver S; S.C.gamma = dcfg[0]; S.C.mu = dcfg[1]; S.C.Pr = dcfg[2]; S.C.R = dcfg[3];
+  S.C.viscosity = icfg[8]; S.C.Tref = dcfg[6]; S.C.Ts = dcfg[7];
+  S.flux_visc<double>(U, g, n, G);
+}
+double orc_viscosity(const int* icfg, const double* dcfg, double temp) {
+  Solver S; S.C.mu = dcfg[1]; S.C.viscosity = icfg[8]; S.C.Tref = dcfg[6]; S.C.Ts = dcfg[7];
+  return S.viscosity<double>(temp);
+}
+void orc_roe_matrix(const double* dcfg, const double* UL, const double* UR, const double* nh, int mode, double* D) {
+  Solver S; S.C.gamma = dcfg[0];
+  S.roe_matrix<double>(UL, UR, nh, mode, D);
 }
 double orc_logmean(double x, double y) {
   Solver S;

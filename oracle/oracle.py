@@ -62,6 +62,10 @@ def lib():
         L.orc_rhs_opcount.argtypes = [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_uint64)]
         L.orc_rk_coeffs.argtypes = [ctypes.c_int, _dp, _dp, _dp]
         L.orc_rk_coeffs.restype = ctypes.c_int
+        L.orc_viscosity.argtypes = [_ip, _dp, ctypes.c_double]
+        L.orc_viscosity.restype = ctypes.c_double
+        L.orc_roe_matrix.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_int, _dp]
+        L.orc_flux_visc_law.argtypes = [_ip, _dp, _dp, _dp, ctypes.c_int, _dp]
         L.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_lserk_coeffs.argtypes = [_dp, _dp, _dp]
         L.orc_flux_twopoint.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
@@ -110,11 +114,14 @@ def lserk_coeffs():
 
 
 def _cfg_arrays(cfg):
+    # the library's riemann key (0 Rusanov, 1 central, 2 Roe) maps onto the oracle's dissipation switch
+    diss = {0: 1, 1: 0, 2: 2}[cfg["riemann"]] if "riemann" in cfg else cfg.get("dissipation", 1)
     icfg = np.array([cfg.get("N", 3), cfg.get("nodes", 0), cfg.get("form", 0), cfg.get("physics", 0),
-                     cfg.get("twopoint", 0), cfg.get("dissipation", 1), cfg.get("mms", 0),
-                     cfg.get("integrator", 0)], dtype=np.int32)
+                     cfg.get("twopoint", 0), diss, cfg.get("mms", 0),
+                     cfg.get("integrator", 0), cfg.get("viscosity", 0)], dtype=np.int32)
     dcfg = np.array([cfg.get("gamma", 1.4), cfg.get("mu", 0.0), cfg.get("Pr", 0.72), cfg.get("R", 1.0),
-                     cfg.get("mms_A", 0.1), cfg.get("mms_a", 1.0)], dtype=np.float64)
+                     cfg.get("mms_A", 0.1), cfg.get("mms_a", 1.0), cfg.get("Tref", 1.0),
+                     cfg.get("Ts", 110.4 / 273.15)], dtype=np.float64)
     return icfg, dcfg
 
 
@@ -133,6 +140,29 @@ def flux_adv(U, nv, gamma=1.4):
     lib().orc_flux_adv(_d(dcfg), _d(np.ascontiguousarray(U, dtype=np.float64)),
                        _d(np.ascontiguousarray(nv, dtype=np.float64)), _d(F))
     return F
+
+
+def roe_matrix(UL, UR, nh, mode=0, gamma=1.4):
+    """mode 0: |A~|(UR-UL) with the Harten-Hyman fix; 1: A~(UR-UL) (signed); 2: |A~|(UR-UL) without the fix."""
+    _, dcfg = _cfg_arrays(dict(gamma=gamma))
+    D = np.zeros(5)
+    lib().orc_roe_matrix(_d(dcfg), _d(np.ascontiguousarray(UL, dtype=np.float64)),
+                         _d(np.ascontiguousarray(UR, dtype=np.float64)),
+                         _d(np.ascontiguousarray(nh, dtype=np.float64)), int(mode), _d(D))
+    return D
+
+
+def viscosity(temp, mu=1.0, law=1, Tref=1.0, Ts=110.4 / 273.15):
+    icfg, dcfg = _cfg_arrays(dict(mu=mu, viscosity=law, Tref=Tref, Ts=Ts))
+    return lib().orc_viscosity(_i(icfg), _d(dcfg), float(temp))
+
+
+def flux_visc_law(U, g, n, gamma=1.4, mu=1e-2, Pr=0.72, R=1.0, law=1, Tref=1.0, Ts=110.4 / 273.15):
+    icfg, dcfg = _cfg_arrays(dict(gamma=gamma, mu=mu, Pr=Pr, R=R, viscosity=law, Tref=Tref, Ts=Ts))
+    G = np.zeros(5)
+    lib().orc_flux_visc_law(_i(icfg), _d(dcfg), _d(np.ascontiguousarray(U, dtype=np.float64)),
+                            _d(np.ascontiguousarray(g, dtype=np.float64)), int(n), _d(G))
+    return G
 
 
 def flux_visc(U, g, n, gamma=1.4, mu=1e-2, Pr=0.72, R=1.0):
