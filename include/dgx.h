@@ -60,7 +60,14 @@ typedef enum {
 enum { DG_NODES_GAUSS = 0, DG_NODES_LOBATTO = 1 };
 enum { DG_FORM_WEAK = 0, DG_FORM_SPLIT = 1 };
 enum { DG_PHYS_EULER = 0, DG_PHYS_NAVIER_STOKES = 1 };
-enum { DG_RIEMANN_RUSANOV = 0, DG_RIEMANN_CENTRAL = 1 };
+/* Face flux dissipation: Rusanov (max wave speed), none (central part alone,
+ * tests), or Roe's linearisation with the Harten-Hyman entropy fix on the
+ * acoustic speeds, the paper's flux (§Governing Equations and Numerical Method). */
+enum { DG_RIEMANN_RUSANOV = 0, DG_RIEMANN_CENTRAL = 1, DG_RIEMANN_ROE = 2 };
+/* Viscosity law: constant mu, or Sutherland's law
+ * mu(T) = mu (T/Tref)^(3/2) (1 + Ts) / (T/Tref + Ts) (TGV section); the heat
+ * conductivity follows at constant Prandtl number. */
+enum { DG_VISC_CONSTANT = 0, DG_VISC_SUTHERLAND = 1 };
 enum { DG_TWOPOINT_CHANDRASHEKAR = 0, DG_TWOPOINT_CENTRAL = 1 };
 enum { DG_PREC_FP64 = 0, DG_PREC_FP32_FLUX = 1 };
 /* Low-storage explicit RK scheme (paper: time integration section): the
@@ -74,15 +81,18 @@ typedef struct {
   int nodes;        /* DG_NODES_*; the split form requires Lobatto nodes             */
   int volume_form;  /* DG_FORM_*                                                     */
   int physics;      /* DG_PHYS_*                                                     */
-  int riemann;      /* DG_RIEMANN_*: Rusanov, or its central part alone (tests)       */
+  int riemann;      /* DG_RIEMANN_*: Rusanov, Roe, or the central part alone (tests)  */
   int twopoint;     /* DG_TWOPOINT_*: Chandrashekar, or the flux average (tests)      */
   int precision;    /* DG_PREC_*: FP64, or FP32 flux arithmetic with FP64 state,
                        metrics, pressure recovery, metric contraction and update     */
   int integrator;   /* DG_RK_*: the low-storage RK scheme of dg_rk_step               */
+  int viscosity;    /* DG_VISC_*: constant mu, or Sutherland's law mu(T)              */
   double gamma;     /* ratio of specific heats                                        */
   double mu;        /* constant dynamic viscosity (Navier-Stokes)                     */
   double Pr;        /* Prandtl number                                                 */
   double R;         /* specific gas constant                                          */
+  double Tref;      /* Sutherland: temperature at which the viscosity is mu (> 0)     */
+  double Ts;        /* Sutherland: S / Tref, the Sutherland constant over Tref (>= 0) */
 } dg_config;
 
 /* Context ------------------------------------------------------------------ */

@@ -273,7 +273,11 @@ dg_status dg_create(const dg_config* cfg, dg_ctx** out) {
   if (c.nodes != DG_NODES_GAUSS && c.nodes != DG_NODES_LOBATTO) return fail(nullptr, DG_ERR_ARG, "dg_create: nodes");
   if (c.volume_form != DG_FORM_WEAK && c.volume_form != DG_FORM_SPLIT) return fail(nullptr, DG_ERR_ARG, "dg_create: volume_form");
   if (c.physics != DG_PHYS_EULER && c.physics != DG_PHYS_NAVIER_STOKES) return fail(nullptr, DG_ERR_ARG, "dg_create: physics");
-  if (c.riemann != DG_RIEMANN_RUSANOV && c.riemann != DG_RIEMANN_CENTRAL) return fail(nullptr, DG_ERR_ARG, "dg_create: riemann");
+  if (c.riemann != DG_RIEMANN_RUSANOV && c.riemann != DG_RIEMANN_CENTRAL && c.riemann != DG_RIEMANN_ROE)
+    return fail(nullptr, DG_ERR_ARG, "dg_create: riemann");
+  if (c.viscosity != DG_VISC_CONSTANT && c.viscosity != DG_VISC_SUTHERLAND) return fail(nullptr, DG_ERR_ARG, "dg_create: viscosity");
+  if (c.viscosity == DG_VISC_SUTHERLAND && (!(c.Tref > 0.0) || !(c.Ts >= 0.0) || !std::isfinite(c.Tref) || !std::isfinite(c.Ts)))
+    return fail(nullptr, DG_ERR_ARG, "dg_create: Sutherland constants");
   if (c.twopoint != DG_TWOPOINT_CHANDRASHEKAR && c.twopoint != DG_TWOPOINT_CENTRAL) return fail(nullptr, DG_ERR_ARG, "dg_create: twopoint");
   if (c.precision != DG_PREC_FP64 && c.precision != DG_PREC_FP32_FLUX) return fail(nullptr, DG_ERR_ARG, "dg_create: precision");
   if (c.integrator != DG_RK_LSERK45 && c.integrator != DG_RK_LSERK414) return fail(nullptr, DG_ERR_ARG, "dg_create: integrator");
@@ -291,6 +295,8 @@ dg_status dg_create(const dg_config* cfg, dg_ctx** out) {
   x->phys.lam = c.mu * c.gamma * c.R / ((c.gamma - 1.0) * c.Pr);
   x->phys.R = c.R; x->phys.Rinv = 1.0 / c.R; x->phys.Pr = c.Pr;
   x->phys.riemann = c.riemann; x->phys.twopoint = c.twopoint;
+  x->phys.kappa = c.gamma * c.R / ((c.gamma - 1.0) * c.Pr);
+  x->phys.visc_law = c.viscosity; x->phys.Tref = c.Tref; x->phys.Ts = c.Ts;
   host_basis(c.N, c.nodes, x->x, x->w);
   host_diff(x->x, x->D);
   const int n1 = x->n1;
@@ -619,6 +625,7 @@ static Cfg kcfg(const dg_ctx* c) {
   Cfg k;
   k.N = c->N; k.nodes = c->cfg.nodes; k.form = c->cfg.volume_form; k.physics = c->cfg.physics;
   k.precision = c->cfg.precision;
+  k.roe = c->cfg.riemann == DG_RIEMANN_ROE ? 1 : 0;
   return k;
 }
 
@@ -725,6 +732,8 @@ static dg_status ready_adjoint(dg_ctx* c, const char* who) {
   dg_status st = ready(c, who);
   if (st != DG_OK) return st;
   if (c->cfg.precision != DG_PREC_FP64) return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": FP64 contexts only");
+  if (c->cfg.riemann == DG_RIEMANN_ROE || c->cfg.viscosity == DG_VISC_SUTHERLAND)
+    return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": the adjoint covers the Rusanov flux and constant viscosity");
   if (c->ws_bytes < ws_layout(c).total_adjoint)
     return fail(c, DG_ERR_STATE, std::string(who) + ": bound workspace is smaller than dg_workspace_bytes_adjoint");
   return DG_OK;

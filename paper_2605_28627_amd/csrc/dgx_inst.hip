@@ -46,17 +46,27 @@ hipError_t DGX_NAME(launch_lift)(const Cfg& c, int emit, const Geo& g, const Phy
   return hipGetLastError();
 }
 
-template <int NODES, int FORM, int PHYS, int PREC>
-static void vol_mode(int mode, const Geo& g, const Phys& p, const double* U, const double* Utr, const double* gvn,
-                     const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next, double A, double B,
-                     double dt, hipStream_t s) {
+template <int NODES, int FORM, int PHYS, int PREC, int ROE>
+static void vol_mode_r(int mode, const Geo& g, const Phys& p, const double* U, const double* Utr, const double* gvn,
+                       const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next, double A, double B,
+                       double dt, hipStream_t s) {
   const dim3 grid(g.nElems), block(Shape<kN>::nth);
   if (mode == 0)
-    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, PREC, 0>), grid, block, 0, s, g, p, U, Utr, gvn, gvf, Ut,
-                       Uio, dU, Utr_next, A, B, dt);
+    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, PREC, 0, ROE>), grid, block, 0, s, g, p, U, Utr, gvn, gvf,
+                       Ut, Uio, dU, Utr_next, A, B, dt);
   else
-    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, PREC, 1>), grid, block, 0, s, g, p, U, Utr, gvn, gvf, Ut,
-                       Uio, dU, Utr_next, A, B, dt);
+    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, PREC, 1, ROE>), grid, block, 0, s, g, p, U, Utr, gvn, gvf,
+                       Ut, Uio, dU, Utr_next, A, B, dt);
+}
+
+template <int NODES, int FORM, int PHYS, int PREC>
+static void vol_mode(int mode, int roe, const Geo& g, const Phys& p, const double* U, const double* Utr,
+                     const double* gvn, const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next,
+                     double A, double B, double dt, hipStream_t s) {
+  if (roe)
+    vol_mode_r<NODES, FORM, PHYS, PREC, 1>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  else
+    vol_mode_r<NODES, FORM, PHYS, PREC, 0>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
 }
 
 template <int NODES, int FORM>
@@ -64,11 +74,11 @@ static void vol_phys(const Cfg& c, int mode, const Geo& g, const Phys& p, const 
                      const double* gvn, const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next,
                      double A, double B, double dt, hipStream_t s) {
   if (c.physics == 0) {
-    if (c.precision == 0) vol_mode<NODES, FORM, 0, 0>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
-    else vol_mode<NODES, FORM, 0, 1>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    if (c.precision == 0) vol_mode<NODES, FORM, 0, 0>(mode, c.roe, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    else vol_mode<NODES, FORM, 0, 1>(mode, c.roe, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   } else {
-    if (c.precision == 0) vol_mode<NODES, FORM, 1, 0>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
-    else vol_mode<NODES, FORM, 1, 1>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    if (c.precision == 0) vol_mode<NODES, FORM, 1, 0>(mode, c.roe, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    else vol_mode<NODES, FORM, 1, 1>(mode, c.roe, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   }
 }
 

@@ -40,8 +40,11 @@ __host__ __device__ inline void orient_to_master(int o, int N, int pp, int qq, i
 // Physical constants and switches seen by the kernels.
 struct Phys {
   double gamma, gm1, mu, lam, R, Rinv, Pr;  // lam = mu gamma R / ((gamma-1) Pr): heat conductivity
-  int riemann;                          // 0 Rusanov, 1 central part only
+  double kappa;                         // gamma R / ((gamma-1) Pr): conductivity over viscosity
+  double Tref, Ts;                      // Sutherland's law: reference temperature, S / Tref
+  int riemann;                          // 0 Rusanov, 1 central part only, 2 Roe (Harten-Hyman fix)
   int twopoint;                         // 0 Chandrashekar, 1 flux average
+  int visc_law;                         // 0 constant mu, 1 Sutherland
 };
 
 // Everything a kernel needs about the discretisation.
@@ -65,6 +68,7 @@ struct Work {
 
 struct Cfg {
   int N, nodes, form, physics, precision;
+  int roe;   // Roe's face flux (its own kernel instantiations)
 };
 
 // Launchers (defined in the kernel translation units).  Each returns the

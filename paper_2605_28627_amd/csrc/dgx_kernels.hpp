@@ -347,7 +347,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
 #define DGX_SYMMETRIC_PAIRS 1
 #endif
 
-template <int N, int NODES, int FORM, int PHYS, int PREC, int MODE>
+template <int N, int NODES, int FORM, int PHYS, int PREC, int MODE, int ROE>
 __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void k_volume(Geo G, Phys P, const double* __restrict__ U,
                                                           const double* __restrict__ Utr,
                                                           const double* __restrict__ gvn,
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
                           G.face[((size_t)2 * nS + side) * n2 + fi]};
     const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
     double Phi[5];
-    surface_flux_adv<FT, FORM>(UL, UR, nh, s, P, Phi);
+    surface_flux_adv<FT, FORM, ROE>(UL, UR, nh, s, P, Phi);
     if constexpr (PHYS == 1) {
       // face-normal viscous fluxes of the two sides, formed by the lifting
 #pragma unroll

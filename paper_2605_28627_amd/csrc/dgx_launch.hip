@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dgx_internal.hpp"
+#include "dgx_pointwise.hpp"
 
 namespace dgx {
 
@@ -230,7 +231,9 @@ __global__ void k_dt_partial(Geo G, Phys P, double visc_fac, int n1, const doubl
       sv += nrm2;
     }
     ma = fmax(ma, sa * sJ);
-    mv = fmax(mv, P.mu / rho * visc_fac * sv * sJ * sJ);
+    Prim q;
+    q.rho = rho; q.u[0] = u0; q.u[1] = u1; q.u[2] = u2; q.p = p;
+    mv = fmax(mv, visc_mu<double>(q, P) / rho * visc_fac * sv * sJ * sJ);
   }
   double a = block_max(ma, sh);
   double b = block_max(mv, sh);

@@ -185,12 +185,21 @@ __host__ __device__ inline void euler_flux(const double U[5], const Prim& q, con
   }
 }
 
+// Dynamic viscosity at the node's temperature T = p/(rho R): constant, or
+// Sutherland's law mu (T/Tref)^(3/2) (1 + Ts) / (T/Tref + Ts).
+template <typename FT>
+__host__ __device__ inline FT visc_mu(const Prim& q, const Phys& P) {
+  if (P.visc_law == 0) return FT(P.mu);
+  const FT th = FT(q.p * P.Rinv / (q.rho * P.Tref));
+  return FT(P.mu) * th * sqrt(th) * FT(1.0 + P.Ts) / (th + FT(P.Ts));
+}
+
 // Viscous flux G_d (d = 0..2) for the momentum and energy components (v = 1..4),
 // contracted with n: Gn[v-1] = sum_d n_d G_d[v].  g[3a+d] = dq_a/dx_d, q = (u,v,w,T).
 template <typename FT>
 __host__ __device__ inline void viscous_flux(const Prim& q, const double g[12], const Phys& P, const double n[3],
                                              double Gn[4]) {
-  const FT mu = FT(P.mu), lam = FT(P.lam);
+  const FT mu = visc_mu<FT>(q, P), lam = P.visc_law == 0 ? FT(P.lam) : mu * FT(P.kappa);
   FT gg[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) gg[c] = FT(g[c]);
@@ -214,9 +223,66 @@ __host__ __device__ inline void viscous_flux(const Prim& q, const double g[12], 
   Gn[0] = acc[0]; Gn[1] = acc[1]; Gn[2] = acc[2]; Gn[3] = acc[3];
 }
 
+// Roe's dissipation |A~|(UR - UL) on the unit normal nh (Roe 1981): Roe
+// averages (weights sqrt(rho)), wave strengths of the two acoustic, the
+// entropy and the two shear waves, with the Harten & Hyman (1983) entropy fix
+// on the acoustic speeds: delta = max(0, l~ - l(UL), l(UR) - l~), and where
+// |l~| < delta the speed (l~^2 + delta^2) / (2 delta).  FT arithmetic.
+template <typename FT>
+__host__ __device__ inline FT hh_speed(FT lm, FT lL, FT lR) {
+  const FT a = fabs(lm);
+  FT delta = lm - lL > lR - lm ? lm - lL : lR - lm;
+  delta = delta > FT(0) ? delta : FT(0);
+  return a < delta ? (lm * lm + delta * delta) / (FT(2) * delta) : a;
+}
+template <typename FT>
+__host__ __device__ inline void roe_dissipation(const double UL[5], const double UR[5], const Prim& qL, const Prim& qR,
+                                                const double nh[3], const Phys& P, double D[5]) {
+  const FT gam = FT(P.gamma);
+  const FT n[3] = {FT(nh[0]), FT(nh[1]), FT(nh[2])};
+  const FT rl = FT(qL.rho), rr = FT(qR.rho), pl = FT(qL.p), pr = FT(qR.p);
+  const FT ul[3] = {FT(qL.u[0]), FT(qL.u[1]), FT(qL.u[2])}, ur[3] = {FT(qR.u[0]), FT(qR.u[1]), FT(qR.u[2])};
+  const FT sl = sqrt(rl), sr = sqrt(rr);
+  const FT iw = FT(1) / (sl + sr);
+  const FT HL = (FT(UL[4]) + pl) / rl, HR = (FT(UR[4]) + pr) / rr;
+  FT um[3], du[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    um[d] = (sl * ul[d] + sr * ur[d]) * iw;
+    du[d] = ur[d] - ul[d];
+  }
+  const FT Hm = (sl * HL + sr * HR) * iw;
+  const FT q2 = um[0] * um[0] + um[1] * um[1] + um[2] * um[2];
+  const FT c2 = (gam - FT(1)) * (Hm - FT(0.5) * q2);
+  const FT cm = sqrt(c2), ic2 = FT(1) / c2;
+  const FT rm = sl * sr;
+  const FT unm = um[0] * n[0] + um[1] * n[1] + um[2] * n[2];
+  const FT dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+  const FT dp = pr - pl;
+  const FT a1 = FT(0.5) * (dp - rm * cm * dun) * ic2;
+  const FT a5 = FT(0.5) * (dp + rm * cm * dun) * ic2;
+  const FT a2 = (rr - rl) - dp * ic2;
+  const FT cl = sqrt(gam * pl / rl), cr = sqrt(gam * pr / rr);
+  const FT unl = ul[0] * n[0] + ul[1] * n[1] + ul[2] * n[2];
+  const FT unr = ur[0] * n[0] + ur[1] * n[1] + ur[2] * n[2];
+  const FT w1 = hh_speed<FT>(unm - cm, unl - cl, unr - cr) * a1;
+  const FT w5 = hh_speed<FT>(unm + cm, unl + cl, unr + cr) * a5;
+  const FT l2 = fabs(unm);
+  const FT w2 = l2 * a2, wsh = l2 * rm;
+  const FT udu = um[0] * du[0] + um[1] * du[1] + um[2] * du[2];
+  D[0] = double(w1 + w2 + w5);
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    D[1 + d] = double(w1 * (um[d] - cm * n[d]) + w2 * um[d] + wsh * (du[d] - dun * n[d]) + w5 * (um[d] + cm * n[d]));
+  D[4] = double(w1 * (Hm - unm * cm) + w2 * FT(0.5) * q2 + wsh * (udu - unm * dun) + w5 * (Hm + unm * cm));
+}
+
 // Advective part of the outward (master) surface flux at one face node:
 // Phi = [F*(UL,UR).n - lambda_max/2 (UR-UL)] s.
-template <typename FT, int FORM>
+// ROE selects Roe's dissipation at compile time (its temporaries would raise
+// the register count of every kernel as a run-time branch); otherwise
+// P.riemann chooses Rusanov or no dissipation.
+template <typename FT, int FORM, int ROE = 0>
 __host__ __device__ inline void surface_flux_adv(const double UL[5], const double UR[5], const double nh[3], double s,
                                                  const Phys& P, double Phi[5]) {
   const Prim qL = cons2prim(UL, P.gm1), qR = cons2prim(UR, P.gm1);
@@ -231,7 +297,13 @@ __host__ __device__ inline void surface_flux_adv(const double UL[5], const doubl
 #pragma unroll
     for (int v = 0; v < 5; ++v) Phi[v] = 0.5 * (FL[v] + FR[v]);
   }
-  if (P.riemann == 0) {
+  if constexpr (ROE == 1) {
+    double D[5];
+    roe_dissipation<FT>(UL, UR, qL, qR, nh, P, D);
+    const double hs = 0.5 * s;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Phi[v] -= hs * D[v];
+  } else if (P.riemann == 0) {
     const FT cL = sqrt(FT(P.gamma) * FT(qL.p) / FT(qL.rho));
     const FT cR = sqrt(FT(P.gamma) * FT(qR.p) / FT(qR.rho));
     const FT unL = FT(qL.u[0] * nh[0] + qL.u[1] * nh[1] + qL.u[2] * nh[2]);
@@ -250,7 +322,10 @@ template <typename FT, int FORM, int PHYS>
 __host__ __device__ inline void surface_flux(const double UL[5], const double UR[5], const double* gL,
                                              const double* gR, const double nh[3], double s, const Phys& P,
                                              double Phi[5]) {
-  surface_flux_adv<FT, FORM>(UL, UR, nh, s, P, Phi);
+  if (P.riemann == 2)
+    surface_flux_adv<FT, FORM, 1>(UL, UR, nh, s, P, Phi);
+  else
+    surface_flux_adv<FT, FORM, 0>(UL, UR, nh, s, P, Phi);
   if constexpr (PHYS == 1) {
     const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
     double GL[4], GR[4];

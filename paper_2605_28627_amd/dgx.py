@@ -28,6 +28,8 @@ _L = ctypes.CDLL(LIB_PATH)
 
 DG_OK, DG_ERR_ARG, DG_ERR_MESH, DG_ERR_HIP, DG_ERR_NONPHYSICAL, DG_ERR_NOMEM, DG_ERR_UNSUPPORTED, DG_ERR_STATE = range(8)
 DG_RK_LSERK45, DG_RK_LSERK414 = 0, 1
+DG_RIEMANN_RUSANOV, DG_RIEMANN_CENTRAL, DG_RIEMANN_ROE = 0, 1, 2
+DG_VISC_CONSTANT, DG_VISC_SUTHERLAND = 0, 1
 DG_RK_MAX_STAGES = 14
 STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_MESH", 3: "DG_ERR_HIP", 4: "DG_ERR_NONPHYSICAL",
                 5: "DG_ERR_NOMEM", 6: "DG_ERR_UNSUPPORTED", 7: "DG_ERR_STATE"}
@@ -43,9 +45,9 @@ SYMBOLS = ["dg_create", "dg_destroy", "dg_last_error", "dg_lserk_coefficients", 
 class dg_config(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("nodes", ctypes.c_int), ("volume_form", ctypes.c_int),
                 ("physics", ctypes.c_int), ("riemann", ctypes.c_int), ("twopoint", ctypes.c_int),
-                ("precision", ctypes.c_int), ("integrator", ctypes.c_int), ("gamma", ctypes.c_double),
-                ("mu", ctypes.c_double),
-                ("Pr", ctypes.c_double), ("R", ctypes.c_double)]
+                ("precision", ctypes.c_int), ("integrator", ctypes.c_int), ("viscosity", ctypes.c_int),
+                ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
+                ("Pr", ctypes.c_double), ("R", ctypes.c_double), ("Tref", ctypes.c_double), ("Ts", ctypes.c_double)]
 
 
 class DGError(RuntimeError):
@@ -127,9 +129,10 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_config(N, nodes=1, volume_form=0, physics=0, riemann=0, twopoint=0, precision=0, integrator=0, gamma=1.4,
-                mu=0.0, Pr=0.72, R=1.0):
-    return dg_config(N, nodes, volume_form, physics, riemann, twopoint, precision, integrator, gamma, mu, Pr, R)
+def make_config(N, nodes=1, volume_form=0, physics=0, riemann=0, twopoint=0, precision=0, integrator=0, viscosity=0,
+                gamma=1.4, mu=0.0, Pr=0.72, R=1.0, Tref=1.0, Ts=110.4 / 273.15):
+    return dg_config(N, nodes, volume_form, physics, riemann, twopoint, precision, integrator, viscosity, gamma, mu,
+                     Pr, R, Tref, Ts)
 
 
 def dg_create(cfg: dg_config):

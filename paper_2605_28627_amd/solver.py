@@ -10,8 +10,8 @@ import torch
 
 from . import dgx
 
-CONFIG_KEYS = ("N", "nodes", "volume_form", "physics", "riemann", "twopoint", "precision", "integrator", "gamma",
-               "mu", "Pr", "R")
+CONFIG_KEYS = ("N", "nodes", "volume_form", "physics", "riemann", "twopoint", "precision", "integrator", "viscosity",
+               "gamma", "mu", "Pr", "R", "Tref", "Ts")
 
 
 def config_from_dict(d: dict) -> dgx.dg_config:

@@ -140,6 +140,23 @@ def test_adjoint_rk14_step(S, orc, case):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("extra", [dict(riemann=2), dict(viscosity=1, Tref=1.0, Ts=0.4)], ids=str)
+def test_adjoint_refuses_roe_and_sutherland(S, orc, extra):
+    """The adjoint covers the Rusanov flux and constant viscosity; other
+    contexts get DG_ERR_UNSUPPORTED, not a wrong gradient."""
+    import torch
+    from paper_2605_28627_amd import dgx
+    o, s = _pair(S, orc, CASES[1], **extra)
+    U = s.to_device(I.smooth_random_state(o.coords(), 61, amp=0.2))
+    lam = torch.ones_like(U)
+    with pytest.raises(dgx.DGError) as ei:
+        s.adjoint_rhs(U, lam)
+    assert ei.value.status == dgx.DG_ERR_UNSUPPORTED
+    with pytest.raises(dgx.DGError) as ei:
+        s.adjoint_rk_step(U, lam.clone(), torch.empty_like(lam), 1e-3)
+    assert ei.value.status == dgx.DG_ERR_UNSUPPORTED
+
+
 @pytest.mark.parametrize("case", [(3, 1, 1, 0, 0.0, None), (3, 1, 1, 1, 0.1, 2)], ids=str)
 def test_trajectory_gradient_vs_oracle(S, orc, case):
     import torch

@@ -11,7 +11,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 G = 1.4
-C = np.array([G, 0.02, 0.72, 1.0, 0.0, 0.0])    # gamma, mu, Pr, R, riemann, twopoint
+C = np.array([G, 0.02, 0.72, 1.0, 0.0, 0.0, 0.0, 1.0, 0.4])    # gamma, mu, Pr, R, riemann, twopoint, visc law, Tref, Ts
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
@@ -66,6 +66,44 @@ def test_forward_matches_oracle(pw, orc):
     n = rng.normal(size=3)
     F32 = call(pw.pw_chandrashekar_f32, 5, a, b, n, C)
     assert np.allclose(F32, orc.flux_twopoint(a, b, n), rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_roe_surface_flux_matches_oracle(pw, orc, form):
+    """The library's Roe flux (Harten-Hyman fix) against the oracle's, on random
+    pairs and on pairs straddling a sonic point (where the fix acts)."""
+    rng = np.random.default_rng(21 + form)
+    c = C.copy()
+    c[4] = 2
+    g0 = np.zeros(12)
+    for it in range(40):
+        nh = rng.normal(size=3)
+        nh /= np.linalg.norm(nh)
+        if it % 2:
+            a, b = state(rng), state(rng)
+        else:                                   # un - c changes sign between the sides
+            cs = np.sqrt(G)
+            a = np.array([1.0, *((cs - 0.05) * nh), 1 / 0.4 + 0.5 * (cs - 0.05) ** 2])
+            b = np.array([1.0, *((cs + 0.05) * nh), 1 / 0.4 + 0.5 * (cs + 0.05) ** 2])
+        s = rng.uniform(0.5, 2.0)
+        out = np.zeros(5)
+        pw.pw_surface_flux(form, 0, P(a), P(b), P(g0), P(g0), P(nh), ctypes.c_double(s), P(c), P(out))
+        central = orc.flux_twopoint(a, b, nh * s) if form else 0.5 * (orc.flux_adv(a, nh * s) + orc.flux_adv(b, nh * s))
+        ref = central - 0.5 * s * orc.roe_matrix(a, b, nh, 0)
+        assert np.allclose(out, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max()), (out, ref)
+
+
+def test_sutherland_viscous_flux_matches_oracle(pw, orc):
+    rng = np.random.default_rng(23)
+    c = C.copy()
+    c[6], c[7], c[8] = 1.0, 0.7, 0.4
+    for _ in range(30):
+        a = state(rng)
+        n = rng.normal(size=3)
+        g = rng.normal(size=12)
+        Gn = call(pw.pw_viscous_flux, 4, a, g, n, c)
+        ref = sum(n[d] * orc.flux_visc_law(a, g, d, mu=c[1], Pr=c[2], law=1, Tref=0.7, Ts=0.4) for d in range(3))
+        assert np.allclose(Gn, ref[1:], rtol=1e-13, atol=1e-13)
 
 
 @pytest.mark.parametrize("near", [False, True], ids=["direct-branch", "series-branch"])
