@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--state", default=None, choices=[None, "freestream"], help="replace the initial state")
     ap.add_argument("--integrator", type=int, default=0, choices=[0, 1],
                     help="0 = LSERK4(5) (5 stages), 1 = LSERK4-14 (14 stages)")
+    ap.add_argument("--riemann", default="rusanov", choices=["rusanov", "roe"],
+                    help="face flux dissipation: Rusanov, or Roe with the Harten-Hyman entropy fix")
+    ap.add_argument("--viscosity", default="constant", choices=["constant", "sutherland"],
+                    help="constant mu, or Sutherland's law with Tref = the flow's reference temperature "
+                         "and S/Tref = 110.4/273.15 (air)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -133,8 +138,8 @@ def workload_cfg(name):
                    gamma=1.4, R=1.0)
 
 
-def volume_kernel_name(w, precision=0):
-    return f"void dgx::k_volume<{w['N']}, {w['nodes']}, {w['form']}, {w['physics']}, {precision}, 1>"
+def volume_kernel_name(w, precision=0, roe=0):
+    return f"void dgx::k_volume<{w['N']}, {w['nodes']}, {w['form']}, {w['physics']}, {precision}, 1, {roe}>"
 
 
 def volume_kernel_bytes_per_dof(w, precision=0):
@@ -177,6 +182,10 @@ def main():
     torch.cuda.set_device(dev)
     w, cfg = workload_cfg(args.workload)
     cfg["integrator"] = args.integrator
+    cfg["riemann"] = 2 if args.riemann == "roe" else 0
+    if args.viscosity == "sutherland":
+        # reference temperature of the initial state: T0 = p0 / (rho0 R) at Ma 0.1, rho0 = U0 = 1
+        cfg.update(viscosity=1, Tref=1.0 / (1.4 * 0.01), Ts=110.4 / 273.15)
     nst = len(dgx.dg_rk_coefficients(args.integrator)[0])
     K = tuple(int(x) for x in args.K.split(",")) if args.K else tuple(w["K"])
     _log("mesh", args.workload, K)
@@ -226,8 +235,10 @@ def main():
     lift_ms, lift_n = prof["lift"]
     bytes_launch = volume_kernel_bytes_per_dof(w) * dof
     achieved_gbs = bytes_launch / vol_avg_s / 1e9
-    kname = volume_kernel_name(w)
-    counters = profile_counters(args.workload, kname) if (args.K is None and args.state is None) else None
+    kname = volume_kernel_name(w, 0, 1 if args.riemann == "roe" else 0)
+    default_run = (args.K is None and args.state is None and args.integrator == 0 and args.riemann == "rusanov"
+                   and args.viscosity == "constant")
+    counters = profile_counters(args.workload, kname) if default_run else None
     form = ("split form" if w["form"] else "weak form") + (", Navier-Stokes" if w["physics"] else ", Euler")
 
     result = {
@@ -250,6 +261,7 @@ def main():
                    "elements": list(K), "dof": dof, "physics": "navier-stokes" if w["physics"] else "euler",
                    "volume_form": "split" if w["form"] else "weak", "curved": bool(w["curved"]), "dt": dt,
                    "integrator": ("LSERK4(5)", "LSERK4-14")[args.integrator], "stages_per_step": nst,
+                   "riemann": args.riemann, "viscosity": args.viscosity,
                    "state": args.state or w["state"]},
         "dof_updates_per_s": 1.0 / pid64,
         "simulated_time_per_wall_s": dt * args.steps / t64,
@@ -307,7 +319,9 @@ def main():
     del final64
     torch.cuda.empty_cache()
     _log("adjoint" if not args.no_adjoint else "adjoint skipped")
-    result["adjoint_forward_cost"] = adjoint_cost(cfg, mesh, dev, U0, dt, args) if not args.no_adjoint else None
+    adjoint_ok = args.riemann == "rusanov" and args.viscosity == "constant"
+    result["adjoint_forward_cost"] = (adjoint_cost(cfg, mesh, dev, U0, dt, args)
+                                      if not args.no_adjoint and adjoint_ok else None)
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(args, cfg, mesh, xyz, pid64)

@@ -626,6 +626,7 @@ static Cfg kcfg(const dg_ctx* c) {
   k.N = c->N; k.nodes = c->cfg.nodes; k.form = c->cfg.volume_form; k.physics = c->cfg.physics;
   k.precision = c->cfg.precision;
   k.roe = c->cfg.riemann == DG_RIEMANN_ROE ? 1 : 0;
+  k.visc = c->cfg.viscosity == DG_VISC_SUTHERLAND ? 1 : 0;
   return k;
 }
 

@@ -30,11 +30,15 @@ static void lift_emit(const Cfg& c, int emit, const Geo& g, const Phys& p, const
                       double* gout, double* gtr, hipStream_t s) {
   const dim3 grid(g.nElems), block(Shape<kN>::nth);
   if (emit == 0)
-    hipLaunchKernelGGL((k_lift<kN, NODES, 0, 0>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+    hipLaunchKernelGGL((k_lift<kN, NODES, 0, 0, 0>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+  else if (c.precision == 0 && c.visc == 0)
+    hipLaunchKernelGGL((k_lift<kN, NODES, 1, 0, 0>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
   else if (c.precision == 0)
-    hipLaunchKernelGGL((k_lift<kN, NODES, 1, 0>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+    hipLaunchKernelGGL((k_lift<kN, NODES, 1, 0, 1>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+  else if (c.visc == 0)
+    hipLaunchKernelGGL((k_lift<kN, NODES, 1, 1, 0>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
   else
-    hipLaunchKernelGGL((k_lift<kN, NODES, 1, 1>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+    hipLaunchKernelGGL((k_lift<kN, NODES, 1, 1, 1>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
 }
 
 hipError_t DGX_NAME(launch_lift)(const Cfg& c, int emit, const Geo& g, const Phys& p, const double* U,

@@ -69,6 +69,7 @@ struct Work {
 struct Cfg {
   int N, nodes, form, physics, precision;
   int roe;   // Roe's face flux (its own kernel instantiations)
+  int visc;  // viscosity law (0 constant, 1 Sutherland; its own lifting instantiations)
 };
 
 // Launchers (defined in the kernel translation units).  Each returns the

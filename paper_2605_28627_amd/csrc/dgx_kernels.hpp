@@ -132,9 +132,10 @@ __device__ inline double ld_visc(const double* p, size_t i) {
 //   gout[4r+v][nE][n3] = G~^r_v = Ja^r . G_v(q, g)      (contravariant viscous flux)
 //   gtr[slot][4][side][fi] = G_v(q_tr, g_tr) . n s       (per side, master normal)
 // with q_tr the state trace of that side; FT is the flux arithmetic type, and
-// with PREC 1 both are stored as float (st_visc).
+// with PREC 1 both are stored as float (st_visc).  VL is the viscosity law
+// (0 constant, 1 Sutherland) of the emitted fluxes.
 // ---------------------------------------------------------------------------
-template <int N, int NODES, int EMIT, int PREC>
+template <int N, int NODES, int EMIT, int PREC, int VL>
 __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const double* __restrict__ U,
                                                         const double* __restrict__ Utr, double* __restrict__ gout,
                                                         double* __restrict__ gtr) {
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
       for (int r = 0; r < 3; ++r) {
         const double jr[3] = {sja[(3 * r + 0) * n3 + t], sja[(3 * r + 1) * n3 + t], sja[(3 * r + 2) * n3 + t]};
         double Gr[4];
-        viscous_flux<FT>(q, acc, P, jr, Gr);
+        viscous_flux<FT, VL>(q, acc, P, jr, Gr);
 #pragma unroll
         for (int v = 0; v < 4; ++v) st_visc<PREC>(gout, ((size_t)(4 * r + v) * nE + e) * n3 + t, Gr[v]);
       }
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
     const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
     const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
     double Gn[4];
-    viscous_flux<FT>(cons2prim(ut, P.gm1), gf, P, nv, Gn);
+    viscous_flux<FT, VL>(cons2prim(ut, P.gm1), gf, P, nv, Gn);
 #pragma unroll
     for (int v = 0; v < 4; ++v) st_visc<PREC>(gtr, tr_index(slot, v, 4, nS, side, n2, fi), Gn[v]);
   };

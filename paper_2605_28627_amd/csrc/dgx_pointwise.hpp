@@ -196,10 +196,14 @@ __host__ __device__ inline FT visc_mu(const Prim& q, const Phys& P) {
 
 // Viscous flux G_d (d = 0..2) for the momentum and energy components (v = 1..4),
 // contracted with n: Gn[v-1] = sum_d n_d G_d[v].  g[3a+d] = dq_a/dx_d, q = (u,v,w,T).
-template <typename FT>
+// VL: the viscosity law at compile time (0 constant, 1 Sutherland), or -1 to
+// follow P.visc_law at run time.
+template <typename FT, int VL = -1>
 __host__ __device__ inline void viscous_flux(const Prim& q, const double g[12], const Phys& P, const double n[3],
                                              double Gn[4]) {
-  const FT mu = visc_mu<FT>(q, P), lam = P.visc_law == 0 ? FT(P.lam) : mu * FT(P.kappa);
+  const bool suth = VL == 1 || (VL == -1 && P.visc_law == 1);
+  const FT mu = suth ? visc_mu<FT>(q, P) : FT(P.mu);
+  const FT lam = suth ? mu * FT(P.kappa) : FT(P.lam);
   FT gg[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) gg[c] = FT(g[c]);
