@@ -320,3 +320,23 @@ def test_viscous_timestep_is_linearly_stable(orc, N):
     slow = lambda o: _uniform(o, (0.1, 0.0, 0.0), 1.0)
     assert _growth(orc, cfg, slow) < 1.002
     assert _growth(orc, cfg, slow, dt_fac=2.5) > 1.05
+
+
+def test_operation_count_is_per_dof(orc):
+    """The op-counting scalar's residual counts scale with the number of
+    elements (work per node does not depend on the mesh size, up to the
+    log-mean branch each pair takes), and the split
+    form costs more per node than the weak form at the same N."""
+    counts = []
+    for K in ((2, 2, 2), (2, 2, 4)):
+        mesh = I.box_mesh(K, (-PI,) * 3, (PI,) * 3)
+        o = orc.Oracle(dict(N=3, nodes=1, form=1, physics=1, mu=0.01), mesh)
+        c = o.opcount(I.smooth_random_state(o.coords(), 3, amp=0.2))
+        counts.append(c)
+    # (the log-mean branch taken varies with the state, hence 1 %)
+    for k in ("add", "mul", "div"):
+        assert abs(counts[1][k] - 2 * counts[0][k]) < 0.01 * 2 * counts[0][k], (k, counts)
+    mesh = I.box_mesh((2, 2, 2), (-PI,) * 3, (PI,) * 3)
+    weak = orc.Oracle(dict(N=3, nodes=1, form=0, physics=1, mu=0.01), mesh)
+    cw = weak.opcount(I.smooth_random_state(weak.coords(), 3, amp=0.2))
+    assert sum(counts[0].values()) > 1.5 * sum(cw.values())
