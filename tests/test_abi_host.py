@@ -116,6 +116,13 @@ def test_set_mesh_rejects_bad_meshes(dgx):
         with pytest.raises(dgx.DGError) as ei:
             dgx.dg_set_mesh(ctx, I.Mesh(mesh.nElems, mesh.Ngeo, mesh.X, mesh.sideElem, mesh.sideLoc, so))
         assert ei.value.status == dgx.DG_ERR_MESH
+        import ctypes
+        L = dgx.lib()
+        z = np.zeros(3 * 8)
+        zi = np.zeros(6, dtype=np.int32)
+        dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        assert L.dg_set_mesh(ctx, 0, 1, z.ctypes.data_as(dp), 0, zi.ctypes.data_as(ip), zi.ctypes.data_as(ip),
+                             zi.ctypes.data_as(ip)) == dgx.DG_ERR_ARG          # empty mesh
         dgx.dg_set_mesh(ctx, mesh)                         # and a good mesh still works afterwards
         assert dgx.dg_workspace_bytes(ctx) > 0
     finally:

@@ -194,6 +194,31 @@ def test_roe_and_sutherland_match_oracle(S, orc, case, extra):
     assert np.all(err < 1e-11), err
 
 
+DEGENERATE = [
+    # (N, nodes, form, physics), K: a single periodic element (each face its own
+    # element's neighbour) and one-element-thick slabs
+    ((3, 0, 0, 0), (1, 1, 1)),
+    ((7, 1, 1, 1), (1, 1, 1)),
+    ((1, 1, 0, 1), (1, 1, 1)),
+    ((5, 1, 1, 0), (4, 1, 1)),
+    ((2, 0, 0, 1), (1, 3, 1)),
+]
+
+
+@pytest.mark.parametrize("case,K", DEGENERATE, ids=[str(c) + str(k) for c, k in DEGENERATE])
+def test_degenerate_meshes_match_oracle(S, orc, case, K):
+    N, nodes, form, physics = case
+    _say("degenerate", case, K)
+    o, s, _ = _setup(S, orc, (N, nodes, form, physics, 0.0, 3), K=K)
+    U = I.random_state(s.state_shape[1:], 39)
+    err = rel_err_per_var(s.rhs(s.init_state(U)).cpu().numpy(), o.rhs(U))
+    assert np.all(err < 1e-12), err
+    # zero steps leave the state untouched
+    Ug = s.init_state(U)
+    s.rk_step(Ug, s.empty_state(), 1e-3, 0)
+    assert np.array_equal(Ug.cpu().numpy(), U)
+
+
 def test_init_state(S, orc, torch_cuda):
     """dg_init_state: host and device sources give the same bits, an aliased
     source only checks, and non-physical or non-finite states are refused."""
