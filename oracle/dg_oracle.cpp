@@ -16,7 +16,12 @@
 //     with the central face average;
 //   * the split-form (flux-differencing) volume integral with the
 //     Chandrashekar kinetic-energy-preserving, entropy-conservative two-point
-//     flux (LGL nodes);
+//     flux on LGL nodes;
+//   * its entropy-stable counterpart on LG nodes (the configuration of the
+//     paper's TGV and PID comparisons, which it attributes to Schwarz et al.
+//     2025 without stating the scheme): read here as the hybridised SBP
+//     operator with entropy projection of Chan, Del Rey Fernandez & Carpenter
+//     (SISC 2019), written out literally per line (hybrid_line);
 //   * the Rusanov surface flux (the paper's Roe flux is a later addition);
 //     the viscous surface flux is the arithmetic mean of both sides;
 //   * the low-storage RK4(5) scheme of Carpenter and Kennedy;
@@ -57,6 +62,7 @@ inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
 inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
 inline Dual& operator*=(Dual& a, Dual b) { a = a * b; return a; }
 inline Dual log(Dual a) { return Dual(std::log(a.v), a.d / a.v); }
+inline Dual exp(Dual a) { double e = std::exp(a.v); return Dual(e, a.d * e); }
 inline Dual sqrt(Dual a) { double s = std::sqrt(a.v); return Dual(s, a.d / (2.0 * s)); }
 inline double val(Dual a) { return a.v; }
 inline double val(double a) { return a; }
@@ -77,10 +83,12 @@ inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
 inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
 inline Cnt& operator*=(Cnt& a, Cnt b) { a = a * b; return a; }
 inline Cnt log(Cnt a) { ++Cnt::n_log; return Cnt(std::log(a.v)); }
+inline Cnt exp(Cnt a) { ++Cnt::n_log; return Cnt(std::exp(a.v)); }   // counted with log
 inline Cnt sqrt(Cnt a) { ++Cnt::n_sqrt; return Cnt(std::sqrt(a.v)); }
 inline double val(Cnt a) { return a.v; }
 
 using std::log;
+using std::exp;
 using std::sqrt;
 
 // max that keeps the first argument on ties; |x| by sign of the value.
@@ -179,11 +187,13 @@ static bool make_basis(int N, int type, Basis& B) {
       B.Lm[j] *= (-1.0 - B.x[k]) / (B.x[j] - B.x[k]);
       B.Lp[j] *= (1.0 - B.x[k]) / (B.x[j] - B.x[k]);
     }
+  // Split-form operator DS = M^-1 (Q - Q^T), Q = M D, written with the SBP
+  // property Q + Q^T = Lp Lp^T - Lm Lm^T as 2 D - M^-1 (Lp Lp^T - Lm Lm^T)
+  // (on LGL nodes Lm = e_0, Lp = e_N exactly).
   B.DS.assign(n * n, 0.0);
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) B.DS[i * n + j] = 2.0 * B.D[i * n + j];
-  B.DS[N * n + N] -= 1.0 / B.w[N];
-  B.DS[0] += 1.0 / B.w[0];
+    for (int j = 0; j < n; ++j)
+      B.DS[i * n + j] = 2.0 * B.D[i * n + j] - (B.Lp[i] * B.Lp[j] - B.Lm[i] * B.Lm[j]) / B.w[i];
   return true;
 }
 
@@ -205,6 +215,7 @@ struct Config {
   int mms = 0;          // 1 = add the manufactured-solution source
   int integrator = 0;   // 0 = LSERK4(5) (Carpenter & Kennedy), 1 = LSERK4-14 (Niegemann, Diehl & Busch)
   int viscosity = 0;    // 0 = constant mu, 1 = Sutherland's law mu(T)
+  int hybrid = 0;       // split form: 1 = hybridised/entropy-projection form also on LGL nodes (test switch)
   double gamma = 1.4, mu = 0.0, Pr = 0.72, R = 1.0;
   double Tref = 1.0, Ts = 110.4 / 273.15;   // Sutherland: reference temperature, S / Tref
   double mms_A = 0.1, mms_a = 1.0;
@@ -298,7 +309,7 @@ struct Solver {
     nstages = rk_coeffs(C.integrator, lsA, lsB, lsC);
     if (nstages == 0) { err = "unknown integrator"; return false; }
     if (!make_basis(C.N, C.nodes, B)) { err = "bad basis"; return false; }
-    if (C.form == 1 && C.nodes != 1) { err = "split form needs LGL nodes"; return false; }
+    if (C.form != 0 && C.form != 1) { err = "unknown volume form"; return false; }
     n1 = C.N + 1; n2 = n1 * n1; n3 = n2 * n1;
     std::vector<double> xg(Ngeo + 1);
     for (int m = 0; m <= Ngeo; ++m) xg[m] = -1.0 + 2.0 * m / Ngeo;
@@ -563,6 +574,37 @@ struct Solver {
     D[4] = l1 * a1 * (Hm - unm * cm) + l2 * (a2 * 0.5 * q2 + rm * (udu - unm * dun)) + l5 * a5 * (Hm + unm * cm);
   }
 
+  // Entropy variables of the mathematical entropy S = -rho s/(gamma-1),
+  // s = ln p - gamma ln rho (the entropy the Chandrashekar flux conserves):
+  // v = dS/dU = ((gamma - s)/(gamma-1) - rho|u|^2/(2p), rho u/p, -rho/p).
+  template <class T> void entropy_vars(const T* U, T* v) const {
+    T rho, u[3], p; prim(U, rho, u, p);
+    const T s = log(p) - C.gamma * log(rho);
+    const T b = rho / p;
+    v[0] = (C.gamma - s) / (C.gamma - 1.0) - 0.5 * b * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    for (int d = 0; d < 3; ++d) v[1 + d] = b * u[d];
+    v[4] = -b;
+  }
+  // Inverse of entropy_vars: with b = rho/p = -v_4 the velocity is v_{1..3}/b,
+  // s follows from v_0, and s = ln p - gamma ln rho with p = rho/b gives
+  // ln rho = -(s + ln b)/(gamma - 1).
+  template <class T> void cons_from_entropy(const T* v, T* U) const {
+    const T b = -v[4];
+    T u[3];
+    for (int d = 0; d < 3; ++d) u[d] = v[1 + d] / b;
+    const T q2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T s = C.gamma - (C.gamma - 1.0) * (v[0] + 0.5 * b * q2);
+    const T rho = exp(-(s + log(b)) / (C.gamma - 1.0));
+    const T p = rho / b;
+    U[0] = rho;
+    for (int d = 0; d < 3; ++d) U[1 + d] = rho * u[d];
+    U[4] = p / (C.gamma - 1.0) + 0.5 * rho * q2;
+  }
+  // Split form through the hybridised operator with entropy projection:
+  // always on LG nodes, on LGL nodes only when asked for (there it reduces
+  // to the plain split form).
+  bool hybrid() const { return C.form == 1 && (C.nodes == 0 || C.hybrid == 1); }
+
   // Manufactured solution of the convergence section:
   // rho = 2 + A sin(2 pi (x+y+z - a t)), rho u = rho, rho e = rho^2.
   void mms_source(double x, double y, double z, double t, double* Q) const {
@@ -587,6 +629,9 @@ struct Solver {
     std::vector<std::vector<T>> gtr;    // per side: [2][12][n2] gradient traces
   };
 
+  // Face traces of both sides.  Plain interpolation of U, or, in the
+  // hybridised split form, the entropy-projected state u(E v(U)): the
+  // entropy variables are interpolated and mapped back.
   template <class T> void side_traces(const T* U, int s, Work<T>& W) {
     if (!W.tr[s].empty()) return;
     W.tr[s].assign(2 * 5 * (size_t)n2, T(0.0));
@@ -597,14 +642,20 @@ struct Solver {
         for (int p = 0; p < n1; ++p) {
           int pp = p, qq = q;
           if (m == 1) orient_fwd(sideOrient[s], C.N, p, q, pp, qq);
-          for (int v = 0; v < 5; ++v) {
-            T acc(0.0);
-            for (int l = 0; l < n1; ++l) {
-              int i, j, k; vol_ijk(f, pp, qq, l, i, j, k);
-              acc += L[l] * U[uidx(v, e, node(i, j, k))];
-            }
-            W.tr[s][((size_t)m * 5 + v) * n2 + q * n1 + p] = acc;
+          T acc[5];
+          for (int v = 0; v < 5; ++v) acc[v] = T(0.0);
+          for (int l = 0; l < n1; ++l) {
+            int i, j, k; vol_ijk(f, pp, qq, l, i, j, k);
+            T Ul[5], x[5];
+            for (int v = 0; v < 5; ++v) Ul[v] = U[uidx(v, e, node(i, j, k))];
+            if (hybrid()) entropy_vars(Ul, x);
+            else for (int v = 0; v < 5; ++v) x[v] = Ul[v];
+            for (int v = 0; v < 5; ++v) acc[v] += L[l] * x[v];
           }
+          T tr[5];
+          if (hybrid()) cons_from_entropy(acc, tr);
+          else for (int v = 0; v < 5; ++v) tr[v] = acc[v];
+          for (int v = 0; v < 5; ++v) W.tr[s][((size_t)m * 5 + v) * n2 + q * n1 + p] = tr[v];
         }
     }
   }
@@ -794,7 +845,7 @@ struct Solver {
               // weak-form volume term: sum_l (w_l/w_a) D_{l a} Ftilde^r_l
               double c = B.w[l] / B.w[a] * B.D[l * n1 + a];
               for (int v = 0; v < 5; ++v) V[(size_t)v * n3 + tt] += c * Ft[(size_t)(5 * r + v) * n3 + tl];
-              if (C.form == 1 && l != a) {
+              if (C.form == 1 && !hybrid() && l != a) {
                 // flux differencing: -sum_l DS_{a l} F#(U_tt, U_tl) . avg(Ja^r)
                 T Ua[5], Ub[5]; Uat(tt, Ua); Uat(tl, Ub);
                 double nv[3];
@@ -807,6 +858,10 @@ struct Solver {
             }
           }
         }
+    if (hybrid())
+      for (int r = 0; r < 3; ++r)
+        for (int qq = 0; qq < n1; ++qq)
+          for (int pp = 0; pp < n1; ++pp) hybrid_line(U, e, r, pp, qq, V);
     // Surface term: -(1/w) l(+-1) Phi_out for each of the six faces.
     for (int f = 0; f < 6; ++f) {
       int s = elemSide[e * 6 + f], m = elemSlot[e * 6 + f];
@@ -836,6 +891,95 @@ struct Solver {
         mms_source(Xnode[e][tt], Xnode[e][n3 + tt], Xnode[e][2 * (size_t)n3 + tt], t, Q);
         for (int v = 0; v < 5; ++v) Ut[uidx(v, e, tt)] += Q[v];
       }
+    }
+  }
+
+  // Hybridised SBP operator of one line with nodes 0..N and the two faces
+  // (N+1: xi = -1, N+2: xi = +1), E = [Lm; Lp] the interpolation to the
+  // faces, Bf = diag(-1, +1):
+  //   Q_h = 1/2 [[Q - Q^T, E^T Bf], [-Bf E, Bf]],   Q = M D.
+  std::vector<double> hybrid_operator() const {
+    const int nh = n1 + 2;
+    std::vector<double> Qh((size_t)nh * nh, 0.0);
+    const double Bf[2] = {-1.0, 1.0};
+    const std::vector<double>* E[2] = {&B.Lm, &B.Lp};
+    for (int i = 0; i < n1; ++i)
+      for (int j = 0; j < n1; ++j) Qh[i * nh + j] = 0.5 * (B.w[i] * B.D[i * n1 + j] - B.w[j] * B.D[j * n1 + i]);
+    for (int f = 0; f < 2; ++f) {
+      for (int i = 0; i < n1; ++i) {
+        Qh[i * nh + n1 + f] = 0.5 * (*E[f])[i] * Bf[f];
+        Qh[(n1 + f) * nh + i] = -0.5 * Bf[f] * (*E[f])[i];
+      }
+      Qh[(n1 + f) * nh + n1 + f] = 0.5 * Bf[f];
+    }
+    return Qh;
+  }
+
+  // Volume contribution of one line of element e along direction r through
+  // the hybridised operator (Chan, Del Rey Fernandez & Carpenter 2019):
+  //   M dU/dt += -[I, E^T] 2 (Q_h o F) 1 - E^T Bf (f* - f(u~_f)),
+  // F_mn = F#(u~_m, u~_n) . (Ja_m + Ja_n)/2 over the hybrid node set, with
+  // u~ = U at the volume nodes, u~_f = u(E v(U)) at the faces, and the face
+  // metric Ja_f = E Ja^r.  This adds everything but the f* part, which the
+  // surface term supplies.
+  template <class T> void hybrid_line(const T* U, int e, int r, int pp, int qq, std::vector<T>& V) {
+    const int nh = n1 + 2;
+    const std::vector<double> Qh = hybrid_operator();
+    const std::vector<double>& M = Ja[e];
+    const std::vector<double>* E[2] = {&B.Lm, &B.Lp};
+    std::vector<int> tl(n1);
+    for (int l = 0; l < n1; ++l) {
+      int i, j, k; vol_ijk(2 * r, pp, qq, l, i, j, k);
+      tl[l] = node(i, j, k);
+    }
+    std::vector<T> Uh((size_t)5 * nh);
+    std::vector<double> Jh((size_t)3 * nh, 0.0);
+    for (int l = 0; l < n1; ++l) {
+      for (int v = 0; v < 5; ++v) Uh[(size_t)v * nh + l] = U[uidx(v, e, tl[l])];
+      for (int c = 0; c < 3; ++c) Jh[(size_t)c * nh + l] = M[(size_t)(3 * r + c) * n3 + tl[l]];
+    }
+    for (int f = 0; f < 2; ++f) {
+      T vf[5];
+      for (int v = 0; v < 5; ++v) vf[v] = T(0.0);
+      for (int l = 0; l < n1; ++l) {
+        T Ul[5], x[5];
+        for (int v = 0; v < 5; ++v) Ul[v] = Uh[(size_t)v * nh + l];
+        entropy_vars(Ul, x);
+        for (int v = 0; v < 5; ++v) vf[v] += (*E[f])[l] * x[v];
+        for (int c = 0; c < 3; ++c) Jh[(size_t)c * nh + n1 + f] += (*E[f])[l] * Jh[(size_t)c * nh + l];
+      }
+      T uf[5];
+      cons_from_entropy(vf, uf);
+      for (int v = 0; v < 5; ++v) Uh[(size_t)v * nh + n1 + f] = uf[v];
+    }
+    // r_h = 2 (Q_h o F) 1
+    std::vector<T> rh((size_t)5 * nh, T(0.0));
+    for (int m = 0; m < nh; ++m)
+      for (int n = 0; n < nh; ++n) {
+        const double q = Qh[m * nh + n];
+        if (q == 0.0) continue;
+        T Ua[5], Ub[5];
+        for (int v = 0; v < 5; ++v) { Ua[v] = Uh[(size_t)v * nh + m]; Ub[v] = Uh[(size_t)v * nh + n]; }
+        double nv[3];
+        for (int c = 0; c < 3; ++c) nv[c] = 0.5 * (Jh[(size_t)c * nh + m] + Jh[(size_t)c * nh + n]);
+        T F[5]; flux_twopoint(Ua, Ub, nv, F);
+        for (int v = 0; v < 5; ++v) rh[(size_t)v * nh + m] += 2.0 * q * F[v];
+      }
+    const double Bf[2] = {-1.0, 1.0};
+    for (int a = 0; a < n1; ++a)
+      for (int v = 0; v < 5; ++v) {
+        T acc = rh[(size_t)v * nh + a];
+        for (int f = 0; f < 2; ++f) acc += (*E[f])[a] * rh[(size_t)v * nh + n1 + f];
+        V[(size_t)v * n3 + tl[a]] -= acc / B.w[a];
+      }
+    // the f(u~_f) part of the surface correction
+    for (int f = 0; f < 2; ++f) {
+      T uf[5];
+      for (int v = 0; v < 5; ++v) uf[v] = Uh[(size_t)v * nh + n1 + f];
+      const double nv[3] = {Jh[n1 + f], Jh[(size_t)nh + n1 + f], Jh[2 * (size_t)nh + n1 + f]};
+      T Ff[5]; flux_adv(uf, nv, Ff);
+      for (int a = 0; a < n1; ++a)
+        for (int v = 0; v < 5; ++v) V[(size_t)v * n3 + tl[a]] += (*E[f])[a] * Bf[f] * Ff[v] / B.w[a];
     }
   }
 
@@ -951,7 +1095,7 @@ using orc::Solver;
 
 // ---------------------------------------------------------------------------
 // C interface used by the test suite (through ctypes).
-// icfg = {N, nodes, form, physics, twopoint, dissipation, mms, integrator, viscosity}
+// icfg = {N, nodes, form, physics, twopoint, dissipation, mms, integrator, viscosity, hybrid}
 // dcfg = {gamma, mu, Pr, R, mms_A, mms_a, Tref, Ts}
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -974,7 +1118,7 @@ void* orc_create(const int* icfg, const double* dcfg, int nElems, int Ngeo, cons
   Solver* S = new Solver();
   S->C.N = icfg[0]; S->C.nodes = icfg[1]; S->C.form = icfg[2]; S->C.physics = icfg[3];
   S->C.twopoint = icfg[4]; S->C.dissipation = icfg[5]; S->C.mms = icfg[6]; S->C.integrator = icfg[7];
-  S->C.viscosity = icfg[8];
+  S->C.viscosity = icfg[8]; S->C.hybrid = icfg[9];
   S->C.gamma = dcfg[0]; S->C.mu = dcfg[1]; S->C.Pr = dcfg[2]; S->C.R = dcfg[3];
   S->C.Tref = dcfg[6]; S->C.Ts = dcfg[7];
   S->C.mms_A = dcfg[4]; S->C.mms_a = dcfg[5];
@@ -1139,6 +1283,14 @@ double orc_viscosity(const int* icfg, const double* dcfg, double temp) {
 void orc_roe_matrix(const double* dcfg, const double* UL, const double* UR, const double* nh, int mode, double* D) {
   Solver S; S.C.gamma = dcfg[0];
   S.roe_matrix<double>(UL, UR, nh, mode, D);
+}
+void orc_entropy_vars(const double* dcfg, const double* U, double* v) {
+  Solver S; S.C.gamma = dcfg[0];
+  S.entropy_vars<double>(U, v);
+}
+void orc_cons_from_entropy(const double* dcfg, const double* v, double* U) {
+  Solver S; S.C.gamma = dcfg[0];
+  S.cons_from_entropy<double>(v, U);
 }
 double orc_logmean(double x, double y) {
   Solver S;

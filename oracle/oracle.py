@@ -71,6 +71,8 @@ def lib():
         L.orc_flux_twopoint.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
         L.orc_flux_adv.argtypes = [_dp, _dp, _dp, _dp]
         L.orc_flux_visc.argtypes = [_dp, _dp, _dp, ctypes.c_int, _dp]
+        L.orc_entropy_vars.argtypes = [_dp, _dp, _dp]
+        L.orc_cons_from_entropy.argtypes = [_dp, _dp, _dp]
         L.orc_logmean.restype = ctypes.c_double
         L.orc_logmean.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_mms_source.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
@@ -118,7 +120,7 @@ def _cfg_arrays(cfg):
     diss = {0: 1, 1: 0, 2: 2}[cfg["riemann"]] if "riemann" in cfg else cfg.get("dissipation", 1)
     icfg = np.array([cfg.get("N", 3), cfg.get("nodes", 0), cfg.get("form", 0), cfg.get("physics", 0),
                      cfg.get("twopoint", 0), diss, cfg.get("mms", 0),
-                     cfg.get("integrator", 0), cfg.get("viscosity", 0)], dtype=np.int32)
+                     cfg.get("integrator", 0), cfg.get("viscosity", 0), cfg.get("hybrid", 0)], dtype=np.int32)
     dcfg = np.array([cfg.get("gamma", 1.4), cfg.get("mu", 0.0), cfg.get("Pr", 0.72), cfg.get("R", 1.0),
                      cfg.get("mms_A", 0.1), cfg.get("mms_a", 1.0), cfg.get("Tref", 1.0),
                      cfg.get("Ts", 110.4 / 273.15)], dtype=np.float64)
@@ -171,6 +173,22 @@ def flux_visc(U, g, n, gamma=1.4, mu=1e-2, Pr=0.72, R=1.0):
     lib().orc_flux_visc(_d(dcfg), _d(np.ascontiguousarray(U, dtype=np.float64)),
                         _d(np.ascontiguousarray(g, dtype=np.float64)), int(n), _d(G))
     return G
+
+
+def entropy_vars(U, gamma=1.4):
+    """v = dS/dU for S = -rho s/(gamma-1), s = ln p - gamma ln rho."""
+    _, dcfg = _cfg_arrays(dict(gamma=gamma))
+    v = np.zeros(5)
+    lib().orc_entropy_vars(_d(dcfg), _d(np.ascontiguousarray(U, dtype=np.float64)), _d(v))
+    return v
+
+
+def cons_from_entropy(v, gamma=1.4):
+    """Inverse of entropy_vars."""
+    _, dcfg = _cfg_arrays(dict(gamma=gamma))
+    U = np.zeros(5)
+    lib().orc_cons_from_entropy(_d(dcfg), _d(np.ascontiguousarray(v, dtype=np.float64)), _d(U))
+    return U
 
 
 def logmean(x, y):

@@ -190,7 +190,7 @@ def _match_nodes(xyz_a, xyz_b):
 
 
 @pytest.mark.parametrize("N,nodes,form,physics,curved", [(3, 0, 0, 0, 0.0), (4, 1, 1, 1, 0.1), (3, 1, 0, 1, 0.1),
-                                                         (3, 0, 0, 1, 0.0)])
+                                                         (3, 0, 0, 1, 0.0), (3, 0, 1, 1, 0.0)])
 def test_rotation_invariance(orc, N, nodes, form, physics, curved):
     K = (3, 2, 3)
     Ngeo = N if curved else 1
