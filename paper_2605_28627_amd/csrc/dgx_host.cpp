@@ -285,8 +285,6 @@ dg_status dg_create(const dg_config* cfg, dg_ctx** out) {
       !std::isfinite(c.mu) || !std::isfinite(c.Pr) || !std::isfinite(c.R))
     return fail(nullptr, DG_ERR_ARG, "dg_create: gas constants");
   if (c.N < 1 || c.N > kMaxN) return fail(nullptr, DG_ERR_UNSUPPORTED, "dg_create: N must be in 1..7");
-  if (c.volume_form == DG_FORM_SPLIT && c.nodes != DG_NODES_LOBATTO)
-    return fail(nullptr, DG_ERR_UNSUPPORTED, "dg_create: the split form needs Lobatto nodes");
   dg_ctx* x = new (std::nothrow) dg_ctx();
   if (!x) return fail(nullptr, DG_ERR_NOMEM, "dg_create: host allocation");
   x->cfg = c;
@@ -309,11 +307,11 @@ dg_status dg_create(const dg_config* cfg, dg_ctx** out) {
     for (int l = 0; l < n1; ++l) {
       b.D[a * n1 + l] = x->D[a * n1 + l];
       b.Dhat[a * n1 + l] = x->w[l] / x->w[a] * x->D[l * n1 + a];
-      b.DS[a * n1 + l] = 2.0 * x->D[a * n1 + l];
+      // M^-1 (Q - Q^T) by the SBP property Q + Q^T = Lp Lp^T - Lm Lm^T (exactly
+      // 2D with the two corner terms on LGL nodes, where Lm = e_0, Lp = e_N)
+      b.DS[a * n1 + l] = 2.0 * x->D[a * n1 + l] - (x->Lp[a] * x->Lp[l] - x->Lm[a] * x->Lm[l]) / x->w[a];
     }
   }
-  b.DS[c.N * n1 + c.N] -= 1.0 / x->w[c.N];
-  b.DS[0] += 1.0 / x->w[0];
   *out = x;
   return DG_OK;
 }
@@ -681,7 +679,7 @@ dg_status dg_rhs(dg_ctx* c, const double* U, double* Ut, double t, void* stream)
   Work w = kwork(c);
   {
     ProfScope ps(c, FAM_TRACE, s);
-    LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), U, w.Utr[0], s));
+    LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), c->phys, U, w.Utr[0], s));
   }
   return stage(c, 0, U, Ut, nullptr, nullptr, 0, 0.0, 0.0, 0.0, s);
 }
@@ -693,7 +691,7 @@ dg_status dg_lift(dg_ctx* c, const double* U, double* gout, void* stream) {
   if (c->cfg.physics != DG_PHYS_NAVIER_STOKES) return fail(c, DG_ERR_ARG, "dg_lift: Navier-Stokes contexts only");
   hipStream_t s = (hipStream_t)stream;
   Work w = kwork(c);
-  LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), U, w.Utr[0], s));
+  LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), c->phys, U, w.Utr[0], s));
   LAUNCHCHK(c, launch_lift(kcfg(c), 0, kgeo(c), c->phys, U, w.Utr[0], gout, w.gtr, s));
   return DG_OK;
 }
@@ -717,7 +715,7 @@ dg_status dg_rk_step(dg_ctx* c, double* U, double* dU, double t, double dt, int 
   }
   {
     ProfScope ps(c, FAM_TRACE, s);
-    LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), U, w.Utr[0], s));
+    LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), c->phys, U, w.Utr[0], s));
   }
   int cur = 0;
   for (int step = 0; step < nsteps; ++step)
@@ -735,6 +733,8 @@ static dg_status ready_adjoint(dg_ctx* c, const char* who) {
   if (c->cfg.precision != DG_PREC_FP64) return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": FP64 contexts only");
   if (c->cfg.riemann == DG_RIEMANN_ROE || c->cfg.viscosity == DG_VISC_SUTHERLAND)
     return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": the adjoint covers the Rusanov flux and constant viscosity");
+  if (c->cfg.volume_form == DG_FORM_SPLIT && c->cfg.nodes == DG_NODES_GAUSS)
+    return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": the adjoint covers the split form on Lobatto nodes only");
   if (c->ws_bytes < ws_layout(c).total_adjoint)
     return fail(c, DG_ERR_STATE, std::string(who) + ": bound workspace is smaller than dg_workspace_bytes_adjoint");
   return DG_OK;
@@ -749,7 +749,7 @@ static dg_status adjoint_residual(dg_ctx* c, const double* U, const double* lam,
   double* gbar = k.physics == DG_PHYS_NAVIER_STOKES ? (double*)(c->ws + L.gbar) : nullptr;
   {
     ProfScope ps(c, FAM_TRACE, s);
-    LAUNCHCHK(c, launch_trace(k, g, U, w.Utr[0], s));
+    LAUNCHCHK(c, launch_trace(k, g, c->phys, U, w.Utr[0], s));
   }
   if (k.physics == DG_PHYS_NAVIER_STOKES) {
     ProfScope ps(c, FAM_LIFT, s);
@@ -794,7 +794,7 @@ dg_status dg_adjoint_rk_step(dg_ctx* c, const double* Un, double* lamU, double* 
   }
   {
     ProfScope ps(c, FAM_TRACE, s);
-    LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), Un, w.Utr[0], s));
+    LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), c->phys, Un, w.Utr[0], s));
   }
   int cur = 0;
   for (int k = 0; k + 1 < ns; ++k) {

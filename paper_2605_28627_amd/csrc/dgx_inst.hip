@@ -16,12 +16,15 @@ namespace dgx {
 
 constexpr int kN = DGX_INST_N;
 
-hipError_t DGX_NAME(launch_trace)(const Cfg& c, const Geo& g, const double* U, double* Utr, hipStream_t s) {
+hipError_t DGX_NAME(launch_trace)(const Cfg& c, const Geo& g, const Phys& p, const double* U, double* Utr,
+                                  hipStream_t s) {
   const dim3 grid(g.nElems), block(Shape<kN>::nth);
   if (c.nodes == 1)
-    hipLaunchKernelGGL((k_trace<kN, 1>), grid, block, 0, s, g, U, Utr);
+    hipLaunchKernelGGL((k_trace<kN, 1, 0>), grid, block, 0, s, g, p, U, Utr);
+  else if (c.form == 0)
+    hipLaunchKernelGGL((k_trace<kN, 0, 0>), grid, block, 0, s, g, p, U, Utr);
   else
-    hipLaunchKernelGGL((k_trace<kN, 0>), grid, block, 0, s, g, U, Utr);
+    hipLaunchKernelGGL((k_trace<kN, 0, 1>), grid, block, 0, s, g, p, U, Utr);
   return hipGetLastError();
 }
 
@@ -89,8 +92,10 @@ static void vol_phys(const Cfg& c, int mode, const Geo& g, const Phys& p, const 
 hipError_t DGX_NAME(launch_volume)(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U,
                                    const double* Utr, const double* gvn, const double* gvf, double* Ut, double* Uio,
                                    double* dU, double* Utr_next, double A, double B, double dt, hipStream_t s) {
-  if (c.nodes == 0)
+  if (c.nodes == 0 && c.form == 0)
     vol_phys<0, 0>(c, mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  else if (c.nodes == 0)
+    vol_phys<0, 1>(c, mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   else if (c.form == 0)
     vol_phys<1, 0>(c, mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   else

@@ -74,7 +74,8 @@ struct Cfg {
 
 // Launchers (defined in the kernel translation units).  Each returns the
 // result of hipGetLastError() after the launch.
-hipError_t launch_trace(const Cfg& c, const Geo& g, const double* U, double* Utr, hipStream_t s);
+// Face traces of U (entropy-projected for the split form on Gauss nodes).
+hipError_t launch_trace(const Cfg& c, const Geo& g, const Phys& p, const double* U, double* Utr, hipStream_t s);
 // BR1 lifting.  emit 0: gradients g [12][nE][n3] and their traces
 // [2][12][nSides][n2].  emit 1: the viscous fluxes the residual needs,
 // G~^r [4r+v][nE][n3] and the per-side face-normal fluxes [2][4][nSides][n2]

@@ -8,7 +8,10 @@
 //
 // Operators (paper, "Governing Equations and Numerical Method"):
 //   weak volume term   V_a += sum_l Dhat[a][l] F~^r_l,  Dhat[a][l] = (w_l/w_a) D_{l a}
-//   split volume term  V_a -= sum_l DS[a][l] F#(U_a, U_l) . avg(Ja^r)
+//   split volume term  V_a -= sum_l DS[a][l] F#(U_a, U_l) . avg(Ja^r),  DS = M^-1 (Q - Q^T)
+//   Gauss-node split   V_a -= (1/w_a) B_f l_f(a) (G_f(a) - sum_l l_f(l) G_f(l)),  f = -1, +1 ends,
+//   form coupling      G_f(l) = F#(U_l, u~_f) . avg(Ja^r_l, Ja^r_f): the hybridised SBP
+//                      operator with the entropy-projected face state u~_f = u(E v(U))
 //   surface term       V_a -= (1/w_a) (l_a(-1) Phi^- + l_a(+1) Phi^+)   (outward Phi)
 //   BR1 lifting        J g = -sum_l Dhat[a][l] (Ja^r_d q)_l + (1/w_a) l_a(+-1) {q} (n s)_d
 //   residual           U_t = (V + S) / J
@@ -53,9 +56,11 @@ __device__ __forceinline__ size_t tr_index(int slot, int v, int nvar, int nSides
 
 // ---------------------------------------------------------------------------
 // Trace kernel: U at the element faces -> Utr[slot][5][side][master (p,q)].
+// EP 1 (split form on Gauss nodes): the entropy-projected trace u(E v(U)),
+// the entropy variables interpolated to the face and mapped back.
 // ---------------------------------------------------------------------------
-template <int N, int NODES>
-__global__ __launch_bounds__(Shape<N>::nth) void k_trace(Geo G, const double* __restrict__ U,
+template <int N, int NODES, int EP>
+__global__ __launch_bounds__(Shape<N>::nth) void k_trace(Geo G, Phys P, const double* __restrict__ U,
                                                          double* __restrict__ Utr) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
@@ -85,9 +90,20 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace(Geo G, const double* __
     __shared__ double su[5 * n3];
     __shared__ DevBasis sb;
     load_basis(&sb, G.basis, t, S::nth);
-    if (t < n3)
+    if (t < n3) {
+      double u[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) su[v * n3 + t] = U[((size_t)v * nE + e) * n3 + t];
+      for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+      if constexpr (EP == 1) {
+        double w[5];
+        entropy_vars(cons2prim(u, P.gm1), P.gm1, w);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) su[v * n3 + t] = w[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) su[v * n3 + t] = u[v];
+      }
+    }
     __syncthreads();
     for (int ft = t; ft < S::nface; ft += S::nth) {
       const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
@@ -96,13 +112,21 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace(Geo G, const double* __
       const int side = efc_side(info), slot = efc_slot(info);
       int p = pp, q = qq;
       if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
+      double acc[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        double acc = 0.0;
+        acc[v] = 0.0;
 #pragma unroll
-        for (int a = 0; a < n1; ++a) acc += L[a] * su[v * n3 + line_node<N>(r, a, pp, qq)];
-        Utr[tr_index(slot, v, 5, nS, side, n2, q * n1 + p)] = acc;
+        for (int a = 0; a < n1; ++a) acc[v] += L[a] * su[v * n3 + line_node<N>(r, a, pp, qq)];
       }
+      if constexpr (EP == 1) {
+        double w[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) w[v] = acc[v];
+        entropy_to_cons(w, P.gm1, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Utr[tr_index(slot, v, 5, nS, side, n2, q * n1 + p)] = acc[v];
     }
   }
 }
@@ -360,7 +384,9 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
   using FT = typename std::conditional<PREC == 1, float, double>::type;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
   constexpr int NV = PHYS == 1 ? 4 : 0;                              // viscous values per node and direction
-  constexpr int SZ_SPLIT = (8 + 3 + NV) * n3;                        // aux + Ja^r + G~^r
+  // split form on Gauss nodes: the entropy-stable hybridised form (face coupling terms)
+  constexpr bool ES = FORM == 1 && NODES == 0;
+  constexpr int SZ_SPLIT = (8 + 3 + NV + (ES ? 10 : 0)) * n3;        // aux + Ja^r + G~^r (+ face coupling)
   constexpr int SZ_WEAK = 5 * n3;                                    // F~^r
   constexpr int SZ_V = FORM == 1 ? SZ_SPLIT : SZ_WEAK;
   constexpr int SZ = SZ_V > 5 * n3 ? SZ_V : 5 * n3;                  // also holds the new state (Gauss traces)
@@ -369,6 +395,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
   constexpr bool kSymLines = DGX_SYMMETRIC_PAIRS && (n1 == 4 || n1 == 8) && (n3 % 64 == 0);
   __shared__ double sphi[5 * S::nface];
   __shared__ double sm[SZ];
+  __shared__ double saf[ES ? 8 * S::nface : 1];   // two-point records of the own (projected) face states
   __shared__ DevBasis sb;
   const int e = blockIdx.x, t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
@@ -438,6 +465,12 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
     const double sgn = slot ? -1.0 : 1.0;
 #pragma unroll
     for (int v = 0; v < 5; ++v) sphi[(f * 5 + v) * n2 + rr] = sgn * Phi[v];
+    if constexpr (ES) {
+      const Aux a = make_aux(cons2prim(slot ? UR : UL, P.gm1));
+      double* d = saf + f * 8 * n2 + rr;
+      d[0] = a.rho; d[n2] = a.u[0]; d[2 * n2] = a.u[1]; d[3 * n2] = a.u[2];
+      d[4 * n2] = a.beta; d[5 * n2] = a.lrho; d[6 * n2] = a.lbeta; d[7 * n2] = a.k;
+    }
   }
   // 2. own state
   double acc[5] = {0, 0, 0, 0, 0};
@@ -473,18 +506,13 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
         if (r < 2) fetch_dir(r + 1);
         else fetch_end();
       }
+      double Gf[2][5];   // face coupling of this node (ES)
       if (act) {
         const int a = idx[r];
         const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
         const double c1 = 0.5 / P.gm1;
-        // two-point flux F#(U_a, U_l) . avg(Ja^r) with the partner node tl
-        auto pair_flux = [&](int tl, double F[5]) {
-          Aux ot;
-          ot.rho = sm[0 * n3 + tl]; ot.u[0] = sm[1 * n3 + tl]; ot.u[1] = sm[2 * n3 + tl];
-          ot.u[2] = sm[3 * n3 + tl]; ot.beta = sm[4 * n3 + tl]; ot.lrho = sm[5 * n3 + tl];
-          ot.lbeta = sm[6 * n3 + tl]; ot.k = sm[7 * n3 + tl];
-          const double nv[3] = {0.5 * (jr[0] + sja[0 * n3 + tl]), 0.5 * (jr[1] + sja[1 * n3 + tl]),
-                                0.5 * (jr[2] + sja[2 * n3 + tl])};
+        // two-point flux F#(U_a, ot) . nv
+        auto two_point = [&](const Aux& ot, const double nv[3], double F[5]) {
           if (P.twopoint == 0) {
             chandrashekar<FT>(me, ot, nv, c1, F);
           } else {
@@ -495,6 +523,16 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
 #pragma unroll
             for (int v = 0; v < 5; ++v) F[v] = 0.5 * (Fa[v] + Fb[v]);
           }
+        };
+        // two-point flux F#(U_a, U_l) . avg(Ja^r) with the partner node tl
+        auto pair_flux = [&](int tl, double F[5]) {
+          Aux ot;
+          ot.rho = sm[0 * n3 + tl]; ot.u[0] = sm[1 * n3 + tl]; ot.u[1] = sm[2 * n3 + tl];
+          ot.u[2] = sm[3 * n3 + tl]; ot.beta = sm[4 * n3 + tl]; ot.lrho = sm[5 * n3 + tl];
+          ot.lbeta = sm[6 * n3 + tl]; ot.k = sm[7 * n3 + tl];
+          const double nv[3] = {0.5 * (jr[0] + sja[0 * n3 + tl]), 0.5 * (jr[1] + sja[1 * n3 + tl]),
+                                0.5 * (jr[2] + sja[2 * n3 + tl])};
+          two_point(ot, nv, F);
         };
         if (kSymLines && (n1 == 4 || r < 2)) {
           // The line lies inside this wavefront, its nodes kStride apart in
@@ -544,6 +582,53 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
             const double ds = sb.DS[a * n1 + l];
 #pragma unroll
             for (int v = 0; v < 5; ++v) acc[v] -= ds * F[v];
+          }
+        }
+        if constexpr (ES) {
+          // Face coupling of the hybridised operator: G_f = F#(U_a, u~_f) . (Ja^r_a + Ja^r_f)/2
+          // with u~_f the projected face state and Ja^r_f the metric row
+          // interpolated to the end f of this line; l_f(a) G_f is staged for
+          // the line sums S_f = sum_l l_f(l) G_f(l).
+          double* shy = sm + (11 + NV) * n3;
+          const int rr = qq * n1 + pp;
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            const double* L = f ? sb.Lp : sb.Lm;
+            double jf[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int l = 0; l < n1; ++l) {
+              const int tl = line_node<N>(r, l, pp, qq);
+#pragma unroll
+              for (int c = 0; c < 3; ++c) jf[c] += L[l] * sja[c * n3 + tl];
+            }
+            const double* d = saf + (2 * r + f) * 8 * n2 + rr;
+            Aux of;
+            of.rho = d[0]; of.u[0] = d[n2]; of.u[1] = d[2 * n2]; of.u[2] = d[3 * n2];
+            of.beta = d[4 * n2]; of.lrho = d[5 * n2]; of.lbeta = d[6 * n2]; of.k = d[7 * n2];
+            const double nv[3] = {0.5 * (jr[0] + jf[0]), 0.5 * (jr[1] + jf[1]), 0.5 * (jr[2] + jf[2])};
+            two_point(of, nv, Gf[f]);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) shy[(f * 5 + v) * n3 + t] = L[a] * Gf[f][v];
+          }
+        }
+      }
+      if constexpr (ES) {
+        // dU_a -= (1/w_a) B_f l_f(a) (G_f(a) - S_f),  B_f = -1 at xi = -1, +1 at xi = +1
+        __syncthreads();
+        if (act) {
+          const double* shy = sm + (11 + NV) * n3;
+          const int a = idx[r];
+          const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            const double cf = (f ? 1.0 : -1.0) * sb.winv[a] * (f ? sb.Lp[a] : sb.Lm[a]);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+              double Sf = 0.0;
+#pragma unroll
+              for (int l = 0; l < n1; ++l) Sf += shy[(f * 5 + v) * n3 + line_node<N>(r, l, pp, qq)];
+              acc[v] -= cf * (Gf[f][v] - Sf);
+            }
           }
         }
       }
@@ -636,9 +721,18 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
         }
       }
     } else {
-      if (act)
+      // (entropy-projected traces in the split form)
+      if (act) {
+        double w[5];
+        if constexpr (ES) {
+          entropy_vars(cons2prim(Unew, P.gm1), P.gm1, w);
+        } else {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sm[v * n3 + t] = Unew[v];
+          for (int v = 0; v < 5; ++v) w[v] = Unew[v];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm[v * n3 + t] = w[v];
+      }
       __syncthreads();
       for (int ft = t; ft < S::nface; ft += S::nth) {
         const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
@@ -647,13 +741,21 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
         const int side = efc_side(info), slot = efc_slot(info);
         int p = pp, qm = qq;
         if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+        double s[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          double s = 0.0;
+          s[v] = 0.0;
 #pragma unroll
-          for (int a = 0; a < n1; ++a) s += L[a] * sm[v * n3 + line_node<N>(r, a, pp, qq)];
-          Utr_next[tr_index(slot, v, 5, nS, side, n2, qm * n1 + p)] = s;
+          for (int a = 0; a < n1; ++a) s[v] += L[a] * sm[v * n3 + line_node<N>(r, a, pp, qq)];
         }
+        if constexpr (ES) {
+          double w[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) w[v] = s[v];
+          entropy_to_cons(w, P.gm1, s);
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Utr_next[tr_index(slot, v, 5, nS, side, n2, qm * n1 + p)] = s[v];
       }
     }
   }

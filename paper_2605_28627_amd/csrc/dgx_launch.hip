@@ -8,7 +8,7 @@
 namespace dgx {
 
 #define DGX_DECL(n)                                                                                           \
-  hipError_t launch_trace_N##n(const Cfg&, const Geo&, const double*, double*, hipStream_t);                 \
+  hipError_t launch_trace_N##n(const Cfg&, const Geo&, const Phys&, const double*, double*, hipStream_t);   \
   hipError_t launch_lift_N##n(const Cfg&, int, const Geo&, const Phys&, const double*, const double*,      \
                               double*, double*, hipStream_t);                                                 \
   hipError_t launch_volume_N##n(const Cfg&, const Geo&, const Phys&, int, const double*, const double*,      \
@@ -37,8 +37,8 @@ DGX_DECL(7)
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_trace(const Cfg& c, const Geo& g, const double* U, double* Utr, hipStream_t s) {
-#define ARGS (c, g, U, Utr, s)
+hipError_t launch_trace(const Cfg& c, const Geo& g, const Phys& p, const double* U, double* Utr, hipStream_t s) {
+#define ARGS (c, g, p, U, Utr, s)
   DGX_SWITCH(launch_trace)
 #undef ARGS
 }

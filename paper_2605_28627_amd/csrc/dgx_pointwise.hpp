@@ -141,6 +141,30 @@ __host__ __device__ inline Aux make_aux(const Prim& q) {
   return a;
 }
 
+// Entropy variables of the entropy S = -rho s/(gamma-1), s = ln p - gamma ln rho,
+// that the Chandrashekar flux conserves: with b = rho/p,
+//   v = ((gamma - s)/(gamma-1) - b |u|^2/2,  b u,  -b).
+__host__ __device__ inline void entropy_vars(const Prim& q, double gm1, double v[5]) {
+  const double b = q.rho / q.p;
+  const double s = log(q.p) - (gm1 + 1.0) * log(q.rho);
+  v[0] = (gm1 + 1.0 - s) / gm1 - 0.5 * b * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
+  v[1] = b * q.u[0]; v[2] = b * q.u[1]; v[3] = b * q.u[2];
+  v[4] = -b;
+}
+// Conservative state of the entropy variables v: b = -v_4, u = v_{1..3}/b and,
+// with z = v_0 + b |u|^2/2 = (gamma - s)/(gamma-1), ln rho = z - (gamma + ln b)/(gamma-1).
+__host__ __device__ inline void entropy_to_cons(const double v[5], double gm1, double U[5]) {
+  const double b = -v[4];
+  const double ib = 1.0 / b;
+  const double u0 = v[1] * ib, u1 = v[2] * ib, u2 = v[3] * ib;
+  const double k = u0 * u0 + u1 * u1 + u2 * u2;
+  const double z = v[0] + 0.5 * b * k;
+  const double rho = exp(z - (gm1 + 1.0 + log(b)) / gm1);
+  U[0] = rho;
+  U[1] = rho * u0; U[2] = rho * u1; U[3] = rho * u2;
+  U[4] = rho * ib / gm1 + 0.5 * rho * k;
+}
+
 // Advective flux in direction n of the state described by a two-point record
 // (rho, u, beta = rho/(2p), |u|^2).
 template <typename FT>

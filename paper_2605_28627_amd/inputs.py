@@ -322,6 +322,13 @@ WORKLOADS = {
     # Euler split form, N=5 LGL, 8^3, TGV (adjoint workload)
     "euler_split_lgl_n5_8x8x8_tgv": dict(N=5, nodes=1, form=1, physics=0, mu=0.0, K=(8, 8, 8),
                                          lo=(-PI,) * 3, hi=(PI,) * 3, curved=0.0, state="tgv"),
+    # entropy-stable split form on Gauss nodes, N=3: the TGV setup (16^3) and the
+    # size of the CPU/GPU PID comparison (64^3 elements = 16.78 M DOFs, free stream)
+    "ns_split_lg_n3_16x16x16_tgv": dict(N=3, nodes=0, form=1, physics=1, mu=1.0 / 1600.0, K=(16, 16, 16),
+                                        lo=(-PI,) * 3, hi=(PI,) * 3, curved=0.0, state="tgv"),
+    "ns_split_lg_n3_64x64x64_freestream": dict(N=3, nodes=0, form=1, physics=1, mu=1.0 / 1600.0,
+                                               K=(64, 64, 64), lo=(-PI,) * 3, hi=(PI,) * 3, curved=0.0,
+                                               state="freestream"),
     # large single-GPU run: NS split N=7 LGL 64^3 (134 M nodes)
     "ns_split_lgl_n7_64x64x64_tgv": dict(N=7, nodes=1, form=1, physics=1, mu=1.0 / 1600.0, K=(64, 64, 64),
                                          lo=(-PI,) * 3, hi=(PI,) * 3, curved=0.0, state="tgv"),
@@ -344,6 +351,8 @@ def workload_state(name, xyz, gamma=1.4, state=None):
         return density_wave_state(xyz, 0.0, gamma)
     if w["state"] == "tgv":
         return tgv_state(xyz, gamma=gamma)
+    if w["state"] == "freestream":
+        return freestream_state(xyz, gamma)
     if w["state"] == "tgv_noise":
         return tgv_state(xyz, gamma=gamma, noise_amp=1e-3, noise_seed=3)
     raise KeyError(w["state"])

@@ -49,10 +49,13 @@ def test_create_validates_config(dgx):
         with pytest.raises(dgx.DGError) as ei:
             dgx.dg_create(dgx.make_config(3, **kw))
         assert ei.value.status == dgx.DG_ERR_ARG, kw
-    for kw in [dict(N=0), dict(N=8), dict(nodes=0, volume_form=1)]:
+    for kw in [dict(N=0), dict(N=8)]:
         with pytest.raises(dgx.DGError) as ei:
             dgx.dg_create(dgx.make_config(**({"N": 3} | kw)))
         assert ei.value.status == dgx.DG_ERR_UNSUPPORTED, kw
+    # the split form runs on both node sets (entropy-stable hybridised form on Gauss nodes)
+    for nodes in (0, 1):
+        dgx.dg_destroy(dgx.dg_create(dgx.make_config(3, nodes=nodes, volume_form=1)))
 
 
 def test_lserk_coefficients_match_oracle(dgx, orc):
