@@ -255,7 +255,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic (" + ("free stream" if args.state == "freestream" else
                                  {"tgv": "Taylor-Green vortex", "tgv_noise": "Taylor-Green vortex with seeded "
-                                  "velocity noise", "density_wave": "advected density wave"}[w["state"]]) +
+                                  "velocity noise", "density_wave": "advected density wave",
+                                  "freestream": "free stream"}[w["state"]]) +
                 " initial condition evaluated at the mesh nodes)",
         "config": {"workload": args.workload, "N": w["N"], "nodes": "LGL" if w["nodes"] else "LG",
                    "elements": list(K), "dof": dof, "physics": "navier-stokes" if w["physics"] else "euler",

@@ -571,7 +571,10 @@ static WsLayout ws_layout(const dg_ctx* c) {
   WsLayout L{};
   const size_t nf = (size_t)c->nSides * c->n2, nv = (size_t)c->nElems * c->n3;
   size_t off = 0;
-  for (int b = 0; b < 2; ++b) { L.utr[b] = off; off += align256(2 * 5 * nf * sizeof(double)); }
+  // U traces [2 slots][5][nf]; the split form on Gauss nodes appends the
+  // traces' ln rho, ln beta [2 slots][2][nf]
+  const bool es = c->cfg.volume_form == DG_FORM_SPLIT && c->cfg.nodes == DG_NODES_GAUSS;
+  for (int b = 0; b < 2; ++b) { L.utr[b] = off; off += align256(2 * (es ? 7 : 5) * nf * sizeof(double)); }
   const bool ns = c->cfg.physics == DG_PHYS_NAVIER_STOKES;
   L.gtr = off; off += ns ? align256(2 * 12 * nf * sizeof(double)) : 0;
   L.g = off; off += ns ? align256(12 * nv * sizeof(double)) : 0;

@@ -50,6 +50,20 @@ __device__ __forceinline__ void load_basis(DevBasis* dst, const DevBasis* src, i
   for (int x = t; x < nd; x += nth) d[x] = s[x];
 }
 
+// The entries of the basis the residual and lifting kernels read, at their
+// exact size (the LDS footprint decides how many elements share a CU).
+template <int N>
+struct VolBasis {
+  static constexpr int n1 = N + 1;
+  double winv[n1], Lm[n1], Lp[n1], Dhat[n1 * n1], DS[n1 * n1];
+};
+template <int N>
+__device__ __forceinline__ void load_vol_basis(VolBasis<N>* dst, const DevBasis* src, int t, int nth) {
+  constexpr int n1 = N + 1;
+  for (int x = t; x < n1; x += nth) { dst->winv[x] = src->winv[x]; dst->Lm[x] = src->Lm[x]; dst->Lp[x] = src->Lp[x]; }
+  for (int x = t; x < n1 * n1; x += nth) { dst->Dhat[x] = src->Dhat[x]; dst->DS[x] = src->DS[x]; }
+}
+
 __device__ __forceinline__ size_t tr_index(int slot, int v, int nvar, int nSides, int side, int n2, int fi) {
   return (((size_t)slot * nvar + v) * nSides + side) * n2 + fi;
 }
@@ -57,7 +71,13 @@ __device__ __forceinline__ size_t tr_index(int slot, int v, int nvar, int nSides
 // ---------------------------------------------------------------------------
 // Trace kernel: U at the element faces -> Utr[slot][5][side][master (p,q)].
 // EP 1 (split form on Gauss nodes): the entropy-projected trace u(E v(U)),
-// the entropy variables interpolated to the face and mapped back.
+// the entropy variables interpolated to the face and mapped back; its
+// ln rho and ln beta (by-products of the map) follow the five variables in
+// the same buffer: Utr + 10 nSides n2, layout [slot][2][side][(p,q)].
+__device__ __forceinline__ double* trace_logs(double* Utr, int nS, int n2) { return Utr + (size_t)10 * nS * n2; }
+__device__ __forceinline__ const double* trace_logs(const double* Utr, int nS, int n2) {
+  return Utr + (size_t)10 * nS * n2;
+}
 // ---------------------------------------------------------------------------
 template <int N, int NODES, int EP>
 __global__ __launch_bounds__(Shape<N>::nth) void k_trace(Geo G, Phys P, const double* __restrict__ U,
@@ -120,10 +140,13 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace(Geo G, Phys P, const do
         for (int a = 0; a < n1; ++a) acc[v] += L[a] * su[v * n3 + line_node<N>(r, a, pp, qq)];
       }
       if constexpr (EP == 1) {
-        double w[5];
+        double w[5], lg[2];
 #pragma unroll
         for (int v = 0; v < 5; ++v) w[v] = acc[v];
-        entropy_to_cons(w, P.gm1, acc);
+        entropy_to_cons(w, P.gm1, acc, lg);
+        double* Ltr = trace_logs(Utr, nS, n2);
+        Ltr[tr_index(slot, 0, 2, nS, side, n2, q * n1 + p)] = lg[0];
+        Ltr[tr_index(slot, 1, 2, nS, side, n2, q * n1 + p)] = lg[1];
       }
 #pragma unroll
       for (int v = 0; v < 5; ++v) Utr[tr_index(slot, v, 5, nS, side, n2, q * n1 + p)] = acc[v];
@@ -170,10 +193,10 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
   constexpr int SZ2 = (12 * n3 > SZ ? 12 * n3 : SZ);
   __shared__ double sm[SZ2];
   __shared__ double sf[7 * S::nface];
-  __shared__ DevBasis sb;
+  __shared__ VolBasis<N> sb;
   const int e = blockIdx.x, t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
-  load_basis(&sb, G.basis, t, S::nth);
+  load_vol_basis<N>(&sb, G.basis, t, S::nth);
   double* sq = sm;            // [4][n3]
   double* sja = sm + 4 * n3;  // [9][n3]
   const bool act = t < n3;
@@ -372,8 +395,26 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
 #define DGX_SYMMETRIC_PAIRS 1
 #endif
 
+// Waves per SIMD the residual kernel is compiled for (its register budget):
+// 4 for elements of 512 work-items; 3 for one-wavefront elements of the
+// Gauss split form, whose LDS footprint admits that many.
+#ifndef DGX_ES_WAVES
+#define DGX_ES_WAVES 3
+#endif
+// Gauss split form: the fluxes of faces 0..3 are formed in the first
+// direction pass (4 n2 face nodes: all 64 lanes of an N=3 element), those of
+// faces 4, 5 in the last pass, into the LDS slots of faces 0, 1, which the
+// earlier passes have consumed.  Four face slots instead of six keep the
+// element's LDS small enough for three waves per SIMD at N=3.
+__host__ __device__ constexpr int es_face_slot(int f) { return f < 4 ? f : f - 4; }
+constexpr int kEsFaceSlots = 4;
+template <int N, int NODES, int FORM>
+constexpr int volume_waves() {
+  return Shape<N>::nth >= 512 ? 4 : ((FORM == 1 && NODES == 0 && Shape<N>::nth == 64) ? DGX_ES_WAVES : 1);
+}
+
 template <int N, int NODES, int FORM, int PHYS, int PREC, int MODE, int ROE>
-__global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void k_volume(Geo G, Phys P, const double* __restrict__ U,
+__global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) void k_volume(Geo G, Phys P, const double* __restrict__ U,
                                                           const double* __restrict__ Utr,
                                                           const double* __restrict__ gvn,
                                                           const double* __restrict__ gvf, double* __restrict__ Ut,
@@ -386,20 +427,27 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
   constexpr int NV = PHYS == 1 ? 4 : 0;                              // viscous values per node and direction
   // split form on Gauss nodes: the entropy-stable hybridised form (face coupling terms)
   constexpr bool ES = FORM == 1 && NODES == 0;
-  constexpr int SZ_SPLIT = (8 + 3 + NV + (ES ? 10 : 0)) * n3;        // aux + Ja^r + G~^r (+ face coupling)
-  constexpr int SZ_WEAK = 5 * n3;                                    // F~^r
-  constexpr int SZ_V = FORM == 1 ? SZ_SPLIT : SZ_WEAK;
-  constexpr int SZ = SZ_V > 5 * n3 ? SZ_V : 5 * n3;                  // also holds the new state (Gauss traces)
   // lines along xi and eta (all three for n1 = 4) lie inside one wavefront
   // when n1 is a power of two and an element fills whole wavefronts
   constexpr bool kSymLines = DGX_SYMMETRIC_PAIRS && (n1 == 4 || n1 == 8) && (n3 % 64 == 0);
-  __shared__ double sphi[5 * S::nface];
+  // Gauss-node split form: the line sums of the face coupling go through LDS
+  // (10 values per node) unless every line lies inside a wavefront
+  constexpr bool kEsAllShfl = kSymLines && n1 == 4;
+  constexpr int SZ_SPLIT = (8 + 3 + NV + (ES && !kEsAllShfl ? 10 : 0)) * n3;   // aux + Ja^r + G~^r (+ face coupling)
+  constexpr int SZ_WEAK = 5 * n3;                                    // F~^r
+  constexpr int SZ_V = FORM == 1 ? SZ_SPLIT : SZ_WEAK;
+  constexpr int SZ = SZ_V > 5 * n3 ? SZ_V : 5 * n3;                  // also holds the new state (Gauss traces)
+  // Surface fluxes (outward, own face-local order): all six faces at once, or
+  // (Gauss split form) the two faces of each direction within its pass,
+  // together with the two-point records of the own projected face states.
+  constexpr int kFaces = ES ? kEsFaceSlots : 6;
+  __shared__ double sphi[5 * kFaces * n2];
   __shared__ double sm[SZ];
-  __shared__ double saf[ES ? 8 * S::nface : 1];   // two-point records of the own (projected) face states
-  __shared__ DevBasis sb;
+  __shared__ double saf[ES ? 8 * kFaces * n2 : 1];
+  __shared__ VolBasis<N> sb;
   const int e = blockIdx.x, t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
-  load_basis(&sb, G.basis, t, S::nth);
+  load_vol_basis<N>(&sb, G.basis, t, S::nth);
   const bool act = t < n3;
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   const int idx[3] = {i, j, k};
@@ -436,9 +484,9 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
     for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
     fetch_dir(0);
   }
-  // 1. surface fluxes (own face-local order, outward sign)
-  for (int ft = t; ft < S::nface; ft += S::nth) {
-    const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
+  // surface flux of face f at its node rr into LDS slot fs (and, ES, the own record)
+  auto face_node = [&](int f, int rr, int fs) {
+    const int pp = rr % n1, qq = rr / n1;
     const int info = G.efc[e * 6 + f];
     const int side = efc_side(info), slot = efc_slot(info);
     int p = pp, qm = qq;
@@ -454,7 +502,21 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
                           G.face[((size_t)2 * nS + side) * n2 + fi]};
     const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
     double Phi[5];
-    surface_flux_adv<FT, FORM, ROE>(UL, UR, nh, s, P, Phi);
+    Aux own;
+    if constexpr (ES) {
+      // the projected traces carry their ln rho, ln beta
+      const double* Ltr = trace_logs(Utr, nS, n2);
+      const double lg[4] = {Ltr[tr_index(0, 0, 2, nS, side, n2, fi)], Ltr[tr_index(0, 1, 2, nS, side, n2, fi)],
+                            Ltr[tr_index(1, 0, 2, nS, side, n2, fi)], Ltr[tr_index(1, 1, 2, nS, side, n2, fi)]};
+      surface_flux_adv<FT, FORM, ROE>(UL, UR, nh, s, P, Phi, &own, slot, lg);
+    } else {
+      surface_flux_adv<FT, FORM, ROE>(UL, UR, nh, s, P, Phi);
+    }
+    if constexpr (ES) {
+      double* d = saf + fs * 8 * n2 + rr;
+      d[0] = own.rho; d[n2] = own.u[0]; d[2 * n2] = own.u[1]; d[3 * n2] = own.u[2];
+      d[4 * n2] = own.beta; d[5 * n2] = own.lrho; d[6 * n2] = own.lbeta; d[7 * n2] = own.k;
+    }
     if constexpr (PHYS == 1) {
       // face-normal viscous fluxes of the two sides, formed by the lifting
 #pragma unroll
@@ -464,13 +526,11 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
     }
     const double sgn = slot ? -1.0 : 1.0;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) sphi[(f * 5 + v) * n2 + rr] = sgn * Phi[v];
-    if constexpr (ES) {
-      const Aux a = make_aux(cons2prim(slot ? UR : UL, P.gm1));
-      double* d = saf + f * 8 * n2 + rr;
-      d[0] = a.rho; d[n2] = a.u[0]; d[2 * n2] = a.u[1]; d[3 * n2] = a.u[2];
-      d[4 * n2] = a.beta; d[5 * n2] = a.lrho; d[6 * n2] = a.lbeta; d[7 * n2] = a.k;
-    }
+    for (int v = 0; v < 5; ++v) sphi[(fs * 5 + v) * n2 + rr] = sgn * Phi[v];
+  };
+  // 1. surface fluxes of the six faces (other forms)
+  if constexpr (!ES) {
+    for (int ft = t; ft < S::nface; ft += S::nth) face_node(ft / n2, ft % n2, ft / n2);
   }
   // 2. own state
   double acc[5] = {0, 0, 0, 0, 0};
@@ -493,6 +553,11 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
     if constexpr (FORM == 1) {
       double* sja = sm + 8 * n3;
       double* sgv = sm + 11 * n3;
+      if constexpr (ES) {
+        // the faces whose flux is formed in this pass: 0..3 in the first, 4, 5 in the last
+        constexpr int fa[3] = {0, 6, 4}, fb[3] = {4, 6, 6};
+        for (int ft = fa[r] * n2 + t; ft < fb[r] * n2; ft += S::nth) face_node(ft / n2, ft % n2, es_face_slot(ft / n2));
+      }
       if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) sja[c * n3 + t] = jr[c];
@@ -589,11 +654,16 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
           // with u~_f the projected face state and Ja^r_f the metric row
           // interpolated to the end f of this line; l_f(a) G_f is staged for
           // the line sums S_f = sum_l l_f(l) G_f(l).
+          // The surface term of this direction's two faces is applied here too.
           double* shy = sm + (11 + NV) * n3;
           const int rr = qq * n1 + pp;
 #pragma unroll
           for (int f = 0; f < 2; ++f) {
             const double* L = f ? sb.Lp : sb.Lm;
+            const double cs = sb.winv[a] * L[a];
+            const int fsl = es_face_slot(2 * r + f);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) acc[v] -= cs * sphi[(fsl * 5 + v) * n2 + rr];
             double jf[3] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int l = 0; l < n1; ++l) {
@@ -601,18 +671,31 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
 #pragma unroll
               for (int c = 0; c < 3; ++c) jf[c] += L[l] * sja[c * n3 + tl];
             }
-            const double* d = saf + (2 * r + f) * 8 * n2 + rr;
+            const double* d = saf + fsl * 8 * n2 + rr;
             Aux of;
             of.rho = d[0]; of.u[0] = d[n2]; of.u[1] = d[2 * n2]; of.u[2] = d[3 * n2];
             of.beta = d[4 * n2]; of.lrho = d[5 * n2]; of.lbeta = d[6 * n2]; of.k = d[7 * n2];
             const double nv[3] = {0.5 * (jr[0] + jf[0]), 0.5 * (jr[1] + jf[1]), 0.5 * (jr[2] + jf[2])};
             two_point(of, nv, Gf[f]);
+            if (kSymLines && (n1 == 4 || r < 2)) {
+              // line sum by a butterfly over the line's lanes (bits of a in the lane id)
+              const int str = r == 0 ? 1 : (r == 1 ? n1 : n2);
+              const double cf = (f ? 1.0 : -1.0) * sb.winv[a] * L[a];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) shy[(f * 5 + v) * n3 + t] = L[a] * Gf[f][v];
+              for (int v = 0; v < 5; ++v) {
+                double x = L[a] * Gf[f][v];
+#pragma unroll
+                for (int m = 1; m < n1; m <<= 1) x += __shfl_xor(x, m * str);
+                acc[v] -= cf * (Gf[f][v] - x);
+              }
+            } else {
+#pragma unroll
+              for (int v = 0; v < 5; ++v) shy[(f * 5 + v) * n3 + t] = L[a] * Gf[f][v];
+            }
           }
         }
       }
-      if constexpr (ES) {
+      if (ES && !(kSymLines && (n1 == 4 || r < 2))) {
         // dU_a -= (1/w_a) B_f l_f(a) (G_f(a) - S_f),  B_f = -1 at xi = -1, +1 at xi = +1
         __syncthreads();
         if (act) {
@@ -664,11 +747,11 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
       __syncthreads();
     }
   }
-  // 4. surface lift, Jacobian, output
+  // 4. surface lift (other forms), Jacobian, output
   double Unew[5];
   if (act) {
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+    for (int r = 0; r < (ES ? 0 : 3); ++r) {
       const int a = idx[r];
       const int rr = (r == 2 ? j : k) * n1 + (r == 0 ? j : i);
       if constexpr (NODES == 1) {
@@ -749,10 +832,13 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? 4 : 1)) void
           for (int a = 0; a < n1; ++a) s[v] += L[a] * sm[v * n3 + line_node<N>(r, a, pp, qq)];
         }
         if constexpr (ES) {
-          double w[5];
+          double w[5], lg[2];
 #pragma unroll
           for (int v = 0; v < 5; ++v) w[v] = s[v];
-          entropy_to_cons(w, P.gm1, s);
+          entropy_to_cons(w, P.gm1, s, lg);
+          double* Ltr = trace_logs(Utr_next, nS, n2);
+          Ltr[tr_index(slot, 0, 2, nS, side, n2, qm * n1 + p)] = lg[0];
+          Ltr[tr_index(slot, 1, 2, nS, side, n2, qm * n1 + p)] = lg[1];
         }
 #pragma unroll
         for (int v = 0; v < 5; ++v) Utr_next[tr_index(slot, v, 5, nS, side, n2, qm * n1 + p)] = s[v];

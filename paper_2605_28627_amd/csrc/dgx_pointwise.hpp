@@ -131,6 +131,17 @@ __host__ __device__ inline void chandrashekar(const Aux& a, const Aux& b, const 
   F[4] = Fr * double(X) + (um0 * F[1] + um1 * F[2] + um2 * F[3]);
 }
 
+// Two-point record with the logarithms supplied (ln rho, ln beta).
+__host__ __device__ inline Aux make_aux_logs(const Prim& q, double lrho, double lbeta) {
+  Aux a;
+  a.rho = q.rho; a.u[0] = q.u[0]; a.u[1] = q.u[1]; a.u[2] = q.u[2];
+  a.beta = 0.5 * q.rho / q.p;
+  a.lrho = lrho;
+  a.lbeta = lbeta;
+  a.k = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+  return a;
+}
+
 __host__ __device__ inline Aux make_aux(const Prim& q) {
   Aux a;
   a.rho = q.rho; a.u[0] = q.u[0]; a.u[1] = q.u[1]; a.u[2] = q.u[2];
@@ -153,13 +164,18 @@ __host__ __device__ inline void entropy_vars(const Prim& q, double gm1, double v
 }
 // Conservative state of the entropy variables v: b = -v_4, u = v_{1..3}/b and,
 // with z = v_0 + b |u|^2/2 = (gamma - s)/(gamma-1), ln rho = z - (gamma + ln b)/(gamma-1).
-__host__ __device__ inline void entropy_to_cons(const double v[5], double gm1, double U[5]) {
+// logs (optional) receives ln rho and ln beta = ln(b/2) (beta = rho/(2p)), the
+// two logarithms a two-point record needs, as by-products.
+__host__ __device__ inline void entropy_to_cons(const double v[5], double gm1, double U[5], double* logs = nullptr) {
   const double b = -v[4];
   const double ib = 1.0 / b;
   const double u0 = v[1] * ib, u1 = v[2] * ib, u2 = v[3] * ib;
   const double k = u0 * u0 + u1 * u1 + u2 * u2;
   const double z = v[0] + 0.5 * b * k;
-  const double rho = exp(z - (gm1 + 1.0 + log(b)) / gm1);
+  const double lb = log(b);
+  const double lrho = z - (gm1 + 1.0 + lb) / gm1;
+  const double rho = exp(lrho);
+  if (logs) { logs[0] = lrho; logs[1] = lb - 0.69314718055994530942; }
   U[0] = rho;
   U[1] = rho * u0; U[2] = rho * u1; U[3] = rho * u2;
   U[4] = rho * ib / gm1 + 0.5 * rho * k;
@@ -309,16 +325,22 @@ __host__ __device__ inline void roe_dissipation(const double UL[5], const double
 // Phi = [F*(UL,UR).n - lambda_max/2 (UR-UL)] s.
 // ROE selects Roe's dissipation at compile time (its temporaries would raise
 // the register count of every kernel as a run-time branch); otherwise
-// P.riemann chooses Rusanov or no dissipation.
+// P.riemann chooses Rusanov or no dissipation.  Split form: logs (optional)
+// supplies ln rho, ln beta of UL then UR; with aux the two-point record of UR
+// (side 1) or of UL (side 0) is returned in *aux.
 template <typename FT, int FORM, int ROE = 0>
 __host__ __device__ inline void surface_flux_adv(const double UL[5], const double UR[5], const double nh[3], double s,
-                                                 const Phys& P, double Phi[5]) {
+                                                 const Phys& P, double Phi[5], Aux* aux = nullptr, int side = 0,
+                                                 const double* logs = nullptr) {
   const Prim qL = cons2prim(UL, P.gm1), qR = cons2prim(UR, P.gm1);
   const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
   if (FORM == 1 && P.twopoint == 0) {
-    const Aux aL = make_aux(qL), aR = make_aux(qR);
+    const Aux aL = logs ? make_aux_logs(qL, logs[0], logs[1]) : make_aux(qL);
+    const Aux aR = logs ? make_aux_logs(qR, logs[2], logs[3]) : make_aux(qR);
     chandrashekar<FT>(aL, aR, nv, 0.5 / P.gm1, Phi);
+    if (aux) *aux = side ? aR : aL;
   } else {
+    if (FORM == 1 && aux) *aux = make_aux(side ? qR : qL);
     double FL[5], FR[5];
     euler_flux<FT>(UL, qL, nv, FL);
     euler_flux<FT>(UR, qR, nv, FR);
