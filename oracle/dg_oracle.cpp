@@ -38,6 +38,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <array>
 
 namespace orc {
 
@@ -216,6 +217,7 @@ struct Config {
   int integrator = 0;   // 0 = LSERK4(5) (Carpenter & Kennedy), 1 = LSERK4-14 (Niegemann, Diehl & Busch)
   int viscosity = 0;    // 0 = constant mu, 1 = Sutherland's law mu(T)
   int hybrid = 0;       // split form: 1 = hybridised/entropy-projection form also on LGL nodes (test switch)
+  int fv = 0;           // 1 = FV sub-cell elements enabled (Euler; per-element mask)
   double gamma = 1.4, mu = 0.0, Pr = 0.72, R = 1.0;
   double Tref = 1.0, Ts = 110.4 / 273.15;   // Sutherland: reference temperature, S / Tref
   double mms_A = 0.1, mms_a = 1.0;
@@ -298,6 +300,13 @@ struct Solver {
   std::vector<std::vector<double>> Jdet;     // per element: [n3]
   std::vector<std::vector<double>> Xnode;    // per element: [3][n3]
   std::vector<std::vector<double>> nvec;     // per side: [3][n2] master outward n*s
+  // FV sub-cells: (N+1)^3 equidistant sub-cells of the reference element
+  std::vector<double> Bsub, Bsubinv;         // Bsub[k*n1+i] = integral of l_i over sub-interval k; inverse
+  std::vector<double> Vleginv;               // inverse of Vleg[i*n1+m] = orthonormal Legendre m at node i
+  std::vector<int> fvmask;                   // per element: 1 = FV sub-cells
+  std::vector<std::vector<double>> Vsub;     // per element: [n3] sub-cell volumes
+  std::vector<std::vector<double>> Sint;     // per element: [3 r][3 c][N planes][n2] interior sub-face vectors (+xi_r)
+  std::vector<std::vector<double>> Sbnd;     // per side: [3 c][n2] master-outward sub-face vectors
   std::string err;
   double lsA[14], lsB[14], lsC[14];
   int nstages = 5;
@@ -326,6 +335,12 @@ struct Solver {
     for (size_t t = 0; t < elemSide.size(); ++t)
       if (elemSide[t] < 0) { err = "open face"; return false; }
     Ja.assign(nElems, {}); Jdet.assign(nElems, {}); Xnode.assign(nElems, {}); nvec.assign(nSides, {});
+    if (C.fv) {
+      if (C.physics != 0 || hybrid()) { err = "FV sub-cells: Euler with the weak form or the LGL split form"; return false; }
+      setup_fv_basis();
+      fvmask.assign(nElems, 0);
+      Vsub.assign(nElems, {}); Sint.assign(nElems, {}); Sbnd.assign(nSides, {});
+    }
     return true;
   }
 
@@ -894,6 +909,333 @@ struct Solver {
     }
   }
 
+  // -------------------------------------------------------------------------
+  // FV sub-cells (shock capturing; paper: "Governing Equations and Numerical
+  // Method", the FV sub-cell scheme of Sonntag & Munz with (N+1)^3 integral
+  // means per element).  Reading: equidistant reference sub-cells; DG <-> FV
+  // by exact sub-cell integral means of J U; sub-cell volumes and face
+  // vectors as exact integrals of the J and Ja^r interpolants; second-order
+  // MUSCL reconstruction of primitive variables with the minmod limiter, the
+  // neighbour element's first sub-cell layer serving as ghost cell; Rusanov
+  // flux on every sub-face; a face with an FV element on either side is
+  // evaluated on sub-faces from both sides' first two sub-cell layers (a DG
+  // side contributes its sub-cell means), and a DG element takes it back as
+  // the face polynomial with those sub-face integrals.
+  // -------------------------------------------------------------------------
+  static void invert(std::vector<double> A, int n, std::vector<double>& inv) {
+    inv.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < n; ++r)
+        if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+      for (int k = 0; k < n; ++k) { std::swap(A[c * n + k], A[piv * n + k]); std::swap(inv[c * n + k], inv[piv * n + k]); }
+      const double d = A[c * n + c];
+      for (int k = 0; k < n; ++k) { A[c * n + k] /= d; inv[c * n + k] /= d; }
+      for (int r = 0; r < n; ++r) {
+        if (r == c) continue;
+        const double f = A[r * n + c];
+        for (int k = 0; k < n; ++k) { A[r * n + k] -= f * A[c * n + k]; inv[r * n + k] -= f * inv[c * n + k]; }
+      }
+    }
+  }
+  // Sub-interval k of [-1,1]: [-1 + 2k/(N+1), -1 + 2(k+1)/(N+1)].
+  double sub_edge(int k) const { return -1.0 + 2.0 * k / n1; }
+  void setup_fv_basis() {
+    Basis G; make_basis(C.N, 0, G);   // Gauss rule, exact for the degree-N integrands
+    Bsub.assign((size_t)n1 * n1, 0.0);
+    for (int k = 0; k < n1; ++k) {
+      const double a = sub_edge(k), b = sub_edge(k + 1);
+      for (int i = 0; i < n1; ++i) {
+        double s = 0.0;
+        for (int g = 0; g < n1; ++g) s += G.w[g] * lagrange(B.x, i, a + 0.5 * (b - a) * (G.x[g] + 1.0));
+        Bsub[k * n1 + i] = 0.5 * (b - a) * s;
+      }
+    }
+    invert(Bsub, n1, Bsubinv);
+    std::vector<double> V((size_t)n1 * n1);
+    for (int i = 0; i < n1; ++i)
+      for (int m = 0; m < n1; ++m) {
+        double P, dP; legendre(m, B.x[i], P, dP);
+        V[i * n1 + m] = std::sqrt((2.0 * m + 1.0) / 2.0) * P;
+      }
+    invert(V, n1, Vleginv);
+  }
+  // Tensor-product application of a 1-D operator M (n1 x n1) along all three directions.
+  template <class T> void apply3(const std::vector<double>& M, const T* in, T* out) const {
+    std::vector<T> a((size_t)n3), b((size_t)n3);
+    for (int k = 0; k < n1; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+          T s(0.0);
+          for (int l = 0; l < n1; ++l) s += M[i * n1 + l] * in[node(l, j, k)];
+          a[node(i, j, k)] = s;
+        }
+    for (int k = 0; k < n1; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+          T s(0.0);
+          for (int l = 0; l < n1; ++l) s += M[j * n1 + l] * a[node(i, l, k)];
+          b[node(i, j, k)] = s;
+        }
+    for (int k = 0; k < n1; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+          T s(0.0);
+          for (int l = 0; l < n1; ++l) s += M[k * n1 + l] * b[node(i, j, l)];
+          out[node(i, j, k)] = s;
+        }
+  }
+  // Sub-cell volumes and interior sub-face vectors of element e.
+  void ensure_fv_geom(int e) {
+    if (!Vsub[e].empty()) return;
+    ensure_geom(e);
+    Vsub[e].assign(n3, 0.0);
+    apply3(Bsub, Jdet[e].data(), Vsub[e].data());
+    const int N = C.N;
+    Sint[e].assign((size_t)9 * N * n2, 0.0);
+    for (int r = 0; r < 3; ++r)
+      for (int kk = 0; kk < N; ++kk) {
+        const double xp = sub_edge(kk + 1);
+        std::vector<double> lp(n1);
+        for (int l = 0; l < n1; ++l) lp[l] = lagrange(B.x, l, xp);
+        for (int c = 0; c < 3; ++c) {
+          // Ja^r_c on the plane xi_r = xp at the tangential nodes, then integrated over each sub-face
+          std::vector<double> pl(n2, 0.0);
+          for (int b2 = 0; b2 < n1; ++b2)
+            for (int a2 = 0; a2 < n1; ++a2)
+              for (int l = 0; l < n1; ++l) {
+                int i, j, k; vol_ijk(2 * r, a2, b2, l, i, j, k);
+                pl[b2 * n1 + a2] += lp[l] * Ja[e][(size_t)(3 * r + c) * n3 + node(i, j, k)];
+              }
+          for (int q = 0; q < n1; ++q)
+            for (int p = 0; p < n1; ++p) {
+              double s = 0.0;
+              for (int b2 = 0; b2 < n1; ++b2)
+                for (int a2 = 0; a2 < n1; ++a2) s += Bsub[p * n1 + a2] * Bsub[q * n1 + b2] * pl[b2 * n1 + a2];
+              Sint[e][(((size_t)(3 * r + c)) * N + kk) * n2 + q * n1 + p] = s;
+            }
+        }
+      }
+  }
+  // Master-outward sub-face vectors of side s: the face's n s polynomial integrated over each sub-face.
+  void ensure_fv_side(int s) {
+    if (!Sbnd[s].empty()) return;
+    ensure_side(s);
+    Sbnd[s].assign(3 * (size_t)n2, 0.0);
+    for (int c = 0; c < 3; ++c)
+      for (int q = 0; q < n1; ++q)
+        for (int p = 0; p < n1; ++p) {
+          double v = 0.0;
+          for (int b2 = 0; b2 < n1; ++b2)
+            for (int a2 = 0; a2 < n1; ++a2) v += Bsub[p * n1 + a2] * Bsub[q * n1 + b2] * nvec[s][(size_t)c * n2 + b2 * n1 + a2];
+          Sbnd[s][(size_t)c * n2 + q * n1 + p] = v;
+        }
+  }
+  // Integral means (over the sub-cells) of the nodal state Ue [5][n3]: mean = B3 (J U) / V.
+  template <class T> void dg_to_fv(int e, const T* Ue, T* out) {
+    ensure_fv_geom(e);
+    std::vector<T> ju(n3), m(n3);
+    for (int v = 0; v < 5; ++v) {
+      for (int t = 0; t < n3; ++t) ju[t] = Jdet[e][t] * Ue[(size_t)v * n3 + t];
+      apply3(Bsub, ju.data(), m.data());
+      for (int t = 0; t < n3; ++t) out[(size_t)v * n3 + t] = m[t] / Vsub[e][t];
+    }
+  }
+  // Inverse: the nodal state whose sub-cell means are Ue: J U = B3^-1 (V mean).
+  template <class T> void fv_to_dg(int e, const T* Ue, T* out) {
+    ensure_fv_geom(e);
+    std::vector<T> vm(n3), ju(n3);
+    for (int v = 0; v < 5; ++v) {
+      for (int t = 0; t < n3; ++t) vm[t] = Vsub[e][t] * Ue[(size_t)v * n3 + t];
+      apply3(Bsubinv, vm.data(), ju.data());
+      for (int t = 0; t < n3; ++t) out[(size_t)v * n3 + t] = ju[t] / Jdet[e][t];
+    }
+  }
+  bool side_fv(int s) const { return C.fv && (fvmask[sideElem[2 * s]] || fvmask[sideElem[2 * s + 1]]); }
+  template <class T> static T minmod(const T& a, const T& b) {
+    if (val(a) * val(b) <= 0.0) return T(0.0);
+    return std::fabs(val(a)) <= std::fabs(val(b)) ? a : b;
+  }
+  template <class T> void cons_to_w(const T* U, T* W) const {
+    T rho, u[3], p; prim(U, rho, u, p);
+    W[0] = rho; W[1] = u[0]; W[2] = u[1]; W[3] = u[2]; W[4] = p;
+  }
+  template <class T> void w_to_cons(const T* W, T* U) const {
+    U[0] = W[0];
+    for (int d = 0; d < 3; ++d) U[1 + d] = W[0] * W[1 + d];
+    U[4] = W[4] / (C.gamma - 1.0) + 0.5 * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+  }
+  // Rusanov flux through the area vector S (not normalised) between primitive states.
+  template <class T> void rusanov_w(const T* WL, const T* WR, const double* S, T* F) const {
+    T UL[5], UR[5], FL[5], FR[5];
+    w_to_cons(WL, UL); w_to_cons(WR, UR);
+    flux_adv(UL, S, FL); flux_adv(UR, S, FR);
+    const double sA = std::sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+    const double nh[3] = {S[0] / sA, S[1] / sA, S[2] / sA};
+    T cl = sqrt(C.gamma * WL[4] / WL[0]), cr = sqrt(C.gamma * WR[4] / WR[0]);
+    T unl = WL[1] * nh[0] + WL[2] * nh[1] + WL[3] * nh[2];
+    T unr = WR[1] * nh[0] + WR[2] * nh[1] + WR[3] * nh[2];
+    T lmax = maxv(T(absv(unl) + cl), T(absv(unr) + cr));
+    for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * (lmax * sA) * (UR[v] - UL[v]);
+  }
+  // Sub-cell means of element e ([5][n3]): its state if FV, else its DG state's means (cached).
+  template <class T> const std::vector<T>& elem_means(const T* U, int e, std::vector<std::vector<T>>& cache) {
+    if (cache[e].empty()) {
+      cache[e].assign(5 * (size_t)n3, T(0.0));
+      std::vector<T> Ue(5 * (size_t)n3);
+      for (int v = 0; v < 5; ++v)
+        for (int t = 0; t < n3; ++t) Ue[(size_t)v * n3 + t] = U[uidx(v, e, t)];
+      if (fvmask[e]) cache[e] = Ue;
+      else dg_to_fv(e, Ue.data(), cache[e].data());
+    }
+    return cache[e];
+  }
+  // Primitive mean of the sub-cell in layer `layer` (0 = at the face) under face f, face-local (pp, qq).
+  template <class T> void layer_w(const std::vector<T>& M, int f, int pp, int qq, int layer, T* W) const {
+    const int l = (f % 2) ? C.N - layer : layer;
+    int i, j, k; vol_ijk(f, pp, qq, l, i, j, k);
+    T Uc[5];
+    for (int v = 0; v < 5; ++v) Uc[v] = M[(size_t)v * n3 + node(i, j, k)];
+    cons_to_w(Uc, W);
+  }
+  // Master-outward sub-face fluxes [5][n2] of an FV side (master sub-face indexing).
+  template <class T> void side_flux_fv(const T* U, int s, std::vector<std::vector<T>>& cache, std::vector<T>& F) {
+    ensure_fv_side(s);
+    F.assign(5 * (size_t)n2, T(0.0));
+    for (int q = 0; q < n1; ++q)
+      for (int p = 0; p < n1; ++p) {
+        T W0[2][5], W1[2][5];
+        for (int m = 0; m < 2; ++m) {
+          const int e = sideElem[2 * s + m], f = sideLoc[2 * s + m];
+          int pp = p, qq = q;
+          if (m == 1) orient_fwd(sideOrient[s], C.N, p, q, pp, qq);
+          const std::vector<T>& M = elem_means(U, e, cache);
+          layer_w(M, f, pp, qq, 0, W0[m]); layer_w(M, f, pp, qq, 1, W1[m]);
+        }
+        T Wf[2][5];
+        for (int m = 0; m < 2; ++m)
+          for (int v = 0; v < 5; ++v) {
+            const T sg = minmod(T(W0[m][v] - W1[m][v]), T(W0[1 - m][v] - W0[m][v]));
+            Wf[m][v] = W0[m][v] + 0.5 * sg;
+          }
+        const double S[3] = {Sbnd[s][q * n1 + p], Sbnd[s][(size_t)n2 + q * n1 + p], Sbnd[s][2 * (size_t)n2 + q * n1 + p]};
+        T Fs[5]; rusanov_w(Wf[0], Wf[1], S, Fs);
+        for (int v = 0; v < 5; ++v) F[(size_t)v * n2 + q * n1 + p] = Fs[v];
+      }
+  }
+  // DG side of an FV face: the nodal flux polynomial whose sub-face integrals are F (master indexing).
+  template <class T> void fv_face_to_nodal(const std::vector<T>& F, std::vector<T>& Phi) const {
+    Phi.assign(5 * (size_t)n2, T(0.0));
+    for (int v = 0; v < 5; ++v)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+          T s(0.0);
+          for (int q = 0; q < n1; ++q)
+            for (int p = 0; p < n1; ++p) s += Bsubinv[i * n1 + p] * Bsubinv[j * n1 + q] * F[(size_t)v * n2 + q * n1 + p];
+          Phi[(size_t)v * n2 + j * n1 + i] = s;
+        }
+  }
+  // Primitive layer-0 mean of the neighbour across face f of element e, at own face-local (pp, qq).
+  template <class T> void ghost_w(const T* U, int e, int f, int pp, int qq, std::vector<std::vector<T>>& cache, T* W) {
+    const int s = elemSide[e * 6 + f], m = elemSlot[e * 6 + f];
+    int p = pp, q = qq;
+    if (m == 1) orient_inv(sideOrient[s], C.N, pp, qq, p, q);
+    const int o = 1 - m;
+    const int eo = sideElem[2 * s + o], fo = sideLoc[2 * s + o];
+    int po = p, qo = q;
+    if (o == 1) orient_fwd(sideOrient[s], C.N, p, q, po, qo);
+    layer_w(elem_means(U, eo, cache), fo, po, qo, 0, W);
+  }
+  // FV residual of element e: dmean/dt = -(1/V) sum of outward sub-face fluxes.
+  template <class T> void residual_fv(const T* U, int e, std::vector<std::vector<T>>& cache,
+                                     std::vector<std::vector<T>>& sfv, T* Ut) {
+    ensure_fv_geom(e);
+    const int N = C.N;
+    const std::vector<T>& M = elem_means(U, e, cache);
+    std::vector<T> R(5 * (size_t)n3, T(0.0));
+    for (int r = 0; r < 3; ++r)
+      for (int qq = 0; qq < n1; ++qq)
+        for (int pp = 0; pp < n1; ++pp) {
+          // cells -1..N+1 along the line (ghosts from the neighbours)
+          std::vector<std::array<T, 5>> W(n1 + 2);
+          for (int l = 0; l < n1; ++l) {
+            int i, j, k; vol_ijk(2 * r, pp, qq, l, i, j, k);
+            T Uc[5];
+            for (int v = 0; v < 5; ++v) Uc[v] = M[(size_t)v * n3 + node(i, j, k)];
+            cons_to_w(Uc, W[l + 1].data());
+          }
+          ghost_w(U, e, 2 * r, pp, qq, cache, W[0].data());
+          ghost_w(U, e, 2 * r + 1, pp, qq, cache, W[n1 + 1].data());
+          std::vector<std::array<T, 5>> sg(n1);
+          for (int l = 0; l < n1; ++l)
+            for (int v = 0; v < 5; ++v) sg[l][v] = minmod(T(W[l + 2][v] - W[l + 1][v]), T(W[l + 1][v] - W[l][v]));
+          for (int kk = 0; kk < N; ++kk) {
+            T WL[5], WR[5];
+            for (int v = 0; v < 5; ++v) { WL[v] = W[kk + 1][v] + 0.5 * sg[kk][v]; WR[v] = W[kk + 2][v] - 0.5 * sg[kk + 1][v]; }
+            double S[3];
+            for (int c = 0; c < 3; ++c) S[c] = Sint[e][(((size_t)(3 * r + c)) * N + kk) * n2 + qq * n1 + pp];
+            T F[5]; rusanov_w(WL, WR, S, F);
+            int i, j, k; vol_ijk(2 * r, pp, qq, kk, i, j, k);
+            int i2, j2, k2; vol_ijk(2 * r, pp, qq, kk + 1, i2, j2, k2);
+            for (int v = 0; v < 5; ++v) {
+              R[(size_t)v * n3 + node(i, j, k)] -= F[v];
+              R[(size_t)v * n3 + node(i2, j2, k2)] += F[v];
+            }
+          }
+          // the element's two faces normal to r: outward sub-face fluxes
+          for (int end = 0; end < 2; ++end) {
+            const int f = 2 * r + end, s = elemSide[e * 6 + f], m = elemSlot[e * 6 + f];
+            int p = pp, q = qq;
+            if (m == 1) orient_inv(sideOrient[s], C.N, pp, qq, p, q);
+            int i, j, k; vol_ijk(f, pp, qq, end ? N : 0, i, j, k);
+            for (int v = 0; v < 5; ++v) {
+              const T Fo = (m == 0) ? sfv[s][(size_t)v * n2 + q * n1 + p] : T(-sfv[s][(size_t)v * n2 + q * n1 + p]);
+              R[(size_t)v * n3 + node(i, j, k)] -= Fo;
+            }
+          }
+        }
+    for (int v = 0; v < 5; ++v)
+      for (int t = 0; t < n3; ++t) Ut[uidx(v, e, t)] = R[(size_t)v * n3 + t] / Vsub[e][t];
+  }
+  // Persson-Peraire indicator: log10 of the share of the highest modes
+  // (max(i,j,k) = N in the orthonormal Legendre basis) in the energy of rho.
+  double indicator(const double* U, int e) {
+    std::vector<double> Ue(5 * (size_t)n3), Ud(5 * (size_t)n3);
+    for (int v = 0; v < 5; ++v)
+      for (int t = 0; t < n3; ++t) Ue[(size_t)v * n3 + t] = U[uidx(v, e, t)];
+    if (C.fv && fvmask[e]) fv_to_dg(e, Ue.data(), Ud.data());
+    else Ud = Ue;
+    std::vector<double> mod(n3);
+    apply3(Vleginv, Ud.data(), mod.data());
+    double Eall = 0.0, Etop = 0.0;
+    for (int k = 0; k < n1; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+          const double c2 = mod[node(i, j, k)] * mod[node(i, j, k)];
+          Eall += c2;
+          if (i == C.N || j == C.N || k == C.N) Etop += c2;
+        }
+    return std::log10(std::max(Etop / Eall, 1e-30));
+  }
+  // Element types to `newmask`, converting U (and dU) of the elements that change.
+  void fv_switch(double* U, double* dU, const int* newmask) {
+    std::vector<double> a(5 * (size_t)n3), b(5 * (size_t)n3);
+    for (int e = 0; e < nElems; ++e) {
+      if ((newmask[e] != 0) == (fvmask[e] != 0)) continue;
+      for (double* X : {U, dU}) {
+        if (!X) continue;
+        for (int v = 0; v < 5; ++v)
+          for (int t = 0; t < n3; ++t) a[(size_t)v * n3 + t] = X[uidx(v, e, t)];
+        if (newmask[e]) dg_to_fv(e, a.data(), b.data());
+        else fv_to_dg(e, a.data(), b.data());
+        for (int v = 0; v < 5; ++v)
+          for (int t = 0; t < n3; ++t) X[uidx(v, e, t)] = b[(size_t)v * n3 + t];
+      }
+      fvmask[e] = newmask[e] ? 1 : 0;
+    }
+  }
+
   // Hybridised SBP operator of one line with nodes 0..N and the two faces
   // (N+1: xi = -1, N+2: xi = +1), E = [Lm; Lp] the interpolation to the
   // faces, Bf = diag(-1, +1):
@@ -989,14 +1331,23 @@ struct Solver {
     std::vector<int> el = elist;
     if (el.empty()) { el.resize(nElems); for (int e = 0; e < nElems; ++e) el[e] = e; }
     std::vector<std::vector<T>> sflux(nSides);
+    std::vector<std::vector<T>> sfv(C.fv ? nSides : 0), fvcache(C.fv ? nElems : 0);
     for (int e : el) {
       if (C.physics == 1) lift_elem(U, e, W);
       for (int f = 0; f < 6; ++f) {
         int s = elemSide[e * 6 + f];
-        if (sflux[s].empty()) side_flux(U, s, W, sflux[s]);
+        if (C.fv && side_fv(s)) {
+          // FV face: sub-face fluxes; the DG side takes their face polynomial
+          if (sfv[s].empty()) { side_flux_fv(U, s, fvcache, sfv[s]); fv_face_to_nodal(sfv[s], sflux[s]); }
+        } else if (sflux[s].empty()) {
+          side_flux(U, s, W, sflux[s]);
+        }
       }
     }
-    for (int e : el) residual_elem(U, e, W, sflux, Ut, t);
+    for (int e : el) {
+      if (C.fv && fvmask[e]) residual_fv(U, e, fvcache, sfv, Ut);
+      else residual_elem(U, e, W, sflux, Ut, t);
+    }
   }
 
   template <class T> void lift_all(const T* U, T* gout) {
@@ -1095,7 +1446,7 @@ using orc::Solver;
 
 // ---------------------------------------------------------------------------
 // C interface used by the test suite (through ctypes).
-// icfg = {N, nodes, form, physics, twopoint, dissipation, mms, integrator, viscosity, hybrid}
+// icfg = {N, nodes, form, physics, twopoint, dissipation, mms, integrator, viscosity, hybrid, fv}
 // dcfg = {gamma, mu, Pr, R, mms_A, mms_a, Tref, Ts}
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1118,7 +1469,7 @@ void* orc_create(const int* icfg, const double* dcfg, int nElems, int Ngeo, cons
   Solver* S = new Solver();
   S->C.N = icfg[0]; S->C.nodes = icfg[1]; S->C.form = icfg[2]; S->C.physics = icfg[3];
   S->C.twopoint = icfg[4]; S->C.dissipation = icfg[5]; S->C.mms = icfg[6]; S->C.integrator = icfg[7];
-  S->C.viscosity = icfg[8]; S->C.hybrid = icfg[9];
+  S->C.viscosity = icfg[8]; S->C.hybrid = icfg[9]; S->C.fv = icfg[10];
   S->C.gamma = dcfg[0]; S->C.mu = dcfg[1]; S->C.Pr = dcfg[2]; S->C.R = dcfg[3];
   S->C.Tref = dcfg[6]; S->C.Ts = dcfg[7];
   S->C.mms_A = dcfg[4]; S->C.mms_a = dcfg[5];
@@ -1284,6 +1635,59 @@ void orc_roe_matrix(const double* dcfg, const double* UL, const double* UR, cons
   Solver S; S.C.gamma = dcfg[0];
   S.roe_matrix<double>(UL, UR, nh, mode, D);
 }
+// FV sub-cells: element types (1 = FV), conversions, indicator, geometry, operators.
+int orc_fv_set_mask(void* h, const int* mask) {
+  Solver* S = (Solver*)h;
+  if (!S->C.fv) { g_err = "FV sub-cells not enabled"; return 1; }
+  for (int e = 0; e < S->nElems; ++e) S->fvmask[e] = mask[e] ? 1 : 0;
+  return 0;
+}
+int orc_fv_switch(void* h, double* U, double* dU, const int* newmask) {
+  Solver* S = (Solver*)h;
+  if (!S->C.fv) { g_err = "FV sub-cells not enabled"; return 1; }
+  S->fv_switch(U, dU, newmask);
+  return 0;
+}
+void orc_fv_get_mask(void* h, int* mask) {
+  Solver* S = (Solver*)h;
+  for (int e = 0; e < S->nElems; ++e) mask[e] = S->C.fv ? S->fvmask[e] : 0;
+}
+int orc_fv_indicator(void* h, const double* U, double* ind) {
+  Solver* S = (Solver*)h;
+  for (int e = 0; e < S->nElems; ++e) { S->ensure_geom(e); ind[e] = S->indicator(U, e); }
+  return 0;
+}
+// Sub-cell volumes [nElems][n3], interior sub-face vectors [nElems][3][3][N][n2],
+// boundary sub-face vectors [nSides][3][n2].
+int orc_fv_geometry(void* h, double* V, double* Si, double* Sb) {
+  Solver* S = (Solver*)h;
+  if (!S->C.fv) { g_err = "FV sub-cells not enabled"; return 1; }
+  const size_t ni = (size_t)9 * S->C.N * S->n2;
+  for (int e = 0; e < S->nElems; ++e) {
+    S->ensure_fv_geom(e);
+    for (int t = 0; t < S->n3; ++t) V[(size_t)e * S->n3 + t] = S->Vsub[e][t];
+    for (size_t x = 0; x < ni; ++x) Si[(size_t)e * ni + x] = S->Sint[e][x];
+  }
+  for (int s = 0; s < S->nSides; ++s) {
+    S->ensure_fv_side(s);
+    for (int x = 0; x < 3 * S->n2; ++x) Sb[(size_t)s * 3 * S->n2 + x] = S->Sbnd[s][x];
+  }
+  return 0;
+}
+int orc_fv_operators(void* h, double* Bs, double* Bsi, double* Vli) {
+  Solver* S = (Solver*)h;
+  if (!S->C.fv) { g_err = "FV sub-cells not enabled"; return 1; }
+  for (int x = 0; x < S->n1 * S->n1; ++x) { Bs[x] = S->Bsub[x]; Bsi[x] = S->Bsubinv[x]; Vli[x] = S->Vleginv[x]; }
+  return 0;
+}
+// Element-wise DG -> FV (dir 0) or FV -> DG (dir 1) of a [5][n3] block.
+int orc_fv_convert(void* h, int e, int dir, const double* in, double* out) {
+  Solver* S = (Solver*)h;
+  if (!S->C.fv || e < 0 || e >= S->nElems) { g_err = "bad FV conversion request"; return 1; }
+  if (dir == 0) S->dg_to_fv(e, in, out); else S->fv_to_dg(e, in, out);
+  return 0;
+}
+
 void orc_entropy_vars(const double* dcfg, const double* U, double* v) {
   Solver S; S.C.gamma = dcfg[0];
   S.entropy_vars<double>(U, v);

@@ -71,6 +71,13 @@ def lib():
         L.orc_flux_twopoint.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
         L.orc_flux_adv.argtypes = [_dp, _dp, _dp, _dp]
         L.orc_flux_visc.argtypes = [_dp, _dp, _dp, ctypes.c_int, _dp]
+        L.orc_fv_set_mask.argtypes = [ctypes.c_void_p, _ip]
+        L.orc_fv_switch.argtypes = [ctypes.c_void_p, _dp, _dp, _ip]
+        L.orc_fv_get_mask.argtypes = [ctypes.c_void_p, _ip]
+        L.orc_fv_indicator.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_fv_geometry.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.orc_fv_operators.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.orc_fv_convert.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp, _dp]
         L.orc_entropy_vars.argtypes = [_dp, _dp, _dp]
         L.orc_cons_from_entropy.argtypes = [_dp, _dp, _dp]
         L.orc_logmean.restype = ctypes.c_double
@@ -120,7 +127,8 @@ def _cfg_arrays(cfg):
     diss = {0: 1, 1: 0, 2: 2}[cfg["riemann"]] if "riemann" in cfg else cfg.get("dissipation", 1)
     icfg = np.array([cfg.get("N", 3), cfg.get("nodes", 0), cfg.get("form", 0), cfg.get("physics", 0),
                      cfg.get("twopoint", 0), diss, cfg.get("mms", 0),
-                     cfg.get("integrator", 0), cfg.get("viscosity", 0), cfg.get("hybrid", 0)], dtype=np.int32)
+                     cfg.get("integrator", 0), cfg.get("viscosity", 0), cfg.get("hybrid", 0),
+                     cfg.get("fv", 0)], dtype=np.int32)
     dcfg = np.array([cfg.get("gamma", 1.4), cfg.get("mu", 0.0), cfg.get("Pr", 0.72), cfg.get("R", 1.0),
                      cfg.get("mms_A", 0.1), cfg.get("mms_a", 1.0), cfg.get("Tref", 1.0),
                      cfg.get("Ts", 110.4 / 273.15)], dtype=np.float64)
@@ -301,6 +309,54 @@ class Oracle:
 
     def timestep(self, U, cfl=0.9):
         return lib().orc_timestep(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), float(cfl))
+
+    # FV sub-cells (config fv=1, Euler)
+    def _chk(self, rc):
+        if rc:
+            raise ValueError(lib().orc_last_error().decode())
+
+    def fv_set_mask(self, mask):
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.int32).reshape(-1))
+        assert m.size == self.nElems
+        self._chk(lib().orc_fv_set_mask(self.h, _i(m)))
+
+    def fv_mask(self):
+        m = np.zeros(self.nElems, dtype=np.int32)
+        lib().orc_fv_get_mask(self.h, _i(m))
+        return m
+
+    def fv_switch(self, U, dU, newmask):
+        """Convert U (and dU) to the element types of newmask; returns copies."""
+        U = np.array(U, dtype=np.float64, copy=True, order="C")
+        dU = None if dU is None else np.array(dU, dtype=np.float64, copy=True, order="C")
+        m = np.ascontiguousarray(np.asarray(newmask, dtype=np.int32).reshape(-1))
+        self._chk(lib().orc_fv_switch(self.h, _d(U), _d(dU) if dU is not None else None, _i(m)))
+        return U, dU
+
+    def indicator(self, U):
+        ind = np.zeros(self.nElems)
+        lib().orc_fv_indicator(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), _d(ind))
+        return ind
+
+    def fv_geometry(self):
+        n = self.n1
+        V = np.zeros((self.nElems, n, n, n))
+        Si = np.zeros((self.nElems, 3, 3, self.N, n, n))
+        Sb = np.zeros((self.nSides, 3, n, n))
+        self._chk(lib().orc_fv_geometry(self.h, _d(V), _d(Si), _d(Sb)))
+        return V, Si, Sb
+
+    def fv_operators(self):
+        n = self.n1
+        B, Bi, Vi = np.zeros((n, n)), np.zeros((n, n)), np.zeros((n, n))
+        self._chk(lib().orc_fv_operators(self.h, _d(B), _d(Bi), _d(Vi)))
+        return B, Bi, Vi
+
+    def fv_convert(self, e, block, to_fv=True):
+        b = np.ascontiguousarray(block, dtype=np.float64)
+        out = np.zeros_like(b)
+        self._chk(lib().orc_fv_convert(self.h, int(e), 0 if to_fv else 1, _d(b), _d(out)))
+        return out
 
     def opcount(self, U):
         c = (ctypes.c_uint64 * 5)()
