@@ -78,7 +78,8 @@ enum { DG_RK_LSERK45 = 0, DG_RK_LSERK414 = 1 };
 
 typedef struct {
   int N;            /* polynomial degree, 1..7                                       */
-  int nodes;        /* DG_NODES_*; the split form requires Lobatto nodes             */
+  int nodes;        /* DG_NODES_*; on Gauss nodes the split form is the entropy-stable
+                       hybridised form with entropy-projected face states           */
   int volume_form;  /* DG_FORM_*                                                     */
   int physics;      /* DG_PHYS_*                                                     */
   int riemann;      /* DG_RIEMANN_*: Rusanov, Roe, or the central part alone (tests)  */
@@ -87,6 +88,8 @@ typedef struct {
                        metrics, pressure recovery, metric contraction and update     */
   int integrator;   /* DG_RK_*: the low-storage RK scheme of dg_rk_step               */
   int viscosity;    /* DG_VISC_*: constant mu, or Sutherland's law mu(T)              */
+  int fv;           /* 1: elements may be switched to FV sub-cells (shock capturing,
+                       dg_fv_*); Euler, FP64, Rusanov, weak form or LGL split form   */
   double gamma;     /* ratio of specific heats                                        */
   double mu;        /* constant dynamic viscosity (Navier-Stokes)                     */
   double Pr;        /* Prandtl number                                                 */
@@ -99,7 +102,8 @@ typedef struct {
 
 /* Validates cfg and creates a context (host memory only; no device work).
  * DG_ERR_ARG for bad enums or gamma <= 1, mu < 0, Pr <= 0, R <= 0;
- * DG_ERR_UNSUPPORTED for N outside the built range or split form on Gauss nodes. */
+ * DG_ERR_UNSUPPORTED for N outside the built range, or fv = 1 with Navier-Stokes,
+ * FP32 flux arithmetic, Roe's flux or the split form on Gauss nodes. */
 dg_status dg_create(const dg_config* cfg, dg_ctx** out);
 
 /* Frees all library-owned host and device memory of ctx (NULL is a no-op). */
@@ -238,6 +242,50 @@ dg_status dg_timestep(dg_ctx* ctx, const double* U, double cfl, double* dt_out, 
 /* DG_ERR_NONPHYSICAL if any node has rho <= 0, p <= 0 or a non-finite
  * conserved value; synchronises the stream. */
 dg_status dg_check_state(dg_ctx* ctx, const double* U, void* stream);
+
+/* FV sub-cell shock capturing ------------------------------------------------ */
+/* (paper: "Governing Equations and Numerical Method": troubled DG elements are
+ * replaced by a second-order FV scheme on (N+1)^3 integral means per element,
+ * detected with Persson and Peraire's modal indicator; "Intra-GPU
+ * Parallelism": the indicator and the switching as element-local kernels).
+ * Contexts created with cfg.fv = 1 only (else DG_ERR_STATE).  Every element
+ * is DG or FV; the state of an FV element holds its sub-cell means (the
+ * sub-cells are the equidistant (N+1)^3 sub-cubes of the reference element,
+ * U[v][e][k][j][i] the mean over sub-cell (i,j,k)), and dg_rhs returns their
+ * time derivative.  Reading of the scheme:
+ *   - DG -> FV: mean_s = (integral over s of J U) / V_s, V_s = integral of J,
+ *     both exact for the nodal interpolants; FV -> DG is its inverse.  Both
+ *     conserve sum V mean = sum w J U.
+ *   - Sub-cell face vectors: exact integrals of the metric interpolant Ja^r
+ *     over each sub-face; on element faces, of the master's face normal n s.
+ *   - MUSCL reconstruction of (rho, u, v, w, p) with the minmod limiter; the
+ *     neighbour element's first sub-cell layer is the ghost cell; Rusanov flux.
+ *   - A face with an FV element on either side is evaluated on its (N+1)^2
+ *     sub-faces from both sides' first two sub-cell layers (a DG side
+ *     contributes the means of its own state); the DG side takes back the
+ *     nodal face flux whose sub-face integrals are those fluxes.
+ *   - Indicator: log10 of the share of the modes with max(i,j,k) = N in the
+ *     energy of rho in the orthonormal Legendre basis (of the DG
+ *     reconstruction for FV elements), clamped below at -30.
+ * dg_timestep, dg_kinetic_energy and dg_check_state read FV elements' means
+ * as if they were nodal values. */
+
+/* Element types to mask_host[nElems] (host, 0 = DG, 1 = FV); converts U and,
+ * if dU is not NULL, the RK register dU (device, state length, in place) of
+ * every element whose type changes.  The mask copy is synchronous. */
+dg_status dg_fv_switch(dg_ctx* ctx, double* U, double* dU, const int* mask_host, void* stream);
+
+/* Persson indicator of every element of U into ind_dev[nElems] (device). */
+dg_status dg_fv_indicator(dg_ctx* ctx, const double* U, double* ind_dev, void* stream);
+
+/* Indicator-driven switch: an element becomes FV where its indicator exceeds
+ * ind_hi, DG where it is below ind_lo, and keeps its type in between; U and
+ * dU (may be NULL) are converted as by dg_fv_switch.  ind_lo <= ind_hi. */
+dg_status dg_fv_switch_by_indicator(dg_ctx* ctx, double* U, double* dU, double ind_lo, double ind_hi,
+                                    void* stream);
+
+/* Current element types (host, nElems ints); synchronises the stream. */
+dg_status dg_fv_mask(dg_ctx* ctx, int* mask_host, void* stream);
 
 /* Profiling ------------------------------------------------------------------- */
 

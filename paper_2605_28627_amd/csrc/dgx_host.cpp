@@ -39,6 +39,15 @@ struct dg_ctx {
   double* d_face = nullptr;
   int* d_efc = nullptr;
   DevBasis* d_basis = nullptr;
+  // FV sub-cells (cfg.fv): geometry, element types, side flags
+  std::vector<int> side_elem;           // [2*nSides] (host)
+  double* d_fvV = nullptr;
+  double* d_fvS = nullptr;
+  double* d_fvSb = nullptr;
+  int* d_etype = nullptr;
+  int* d_etype_new = nullptr;
+  int* d_sidefv = nullptr;
+  int* d_side_elem = nullptr;
   // workspace (caller-owned)
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -48,12 +57,12 @@ struct dg_ctx {
   struct Rec { int fam; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
-  double prof_ms[5] = {0, 0, 0, 0, 0};
-  long prof_n[5] = {0, 0, 0, 0, 0};
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  long prof_n[6] = {0, 0, 0, 0, 0, 0};
 };
 
-enum { FAM_TRACE = 0, FAM_LIFT = 1, FAM_VOLUME = 2, FAM_ADJOINT = 3, FAM_OTHER = 4 };
-static const char* kFamNames[5] = {"trace", "lift", "volume", "adjoint", "other"};
+enum { FAM_TRACE = 0, FAM_LIFT = 1, FAM_VOLUME = 2, FAM_ADJOINT = 3, FAM_OTHER = 4, FAM_FV = 5 };
+static const char* kFamNames[6] = {"trace", "lift", "volume", "adjoint", "other", "fv"};
 
 static hipEvent_t pool_event(dg_ctx* c) {
   if (!c->pool.empty()) { hipEvent_t e = c->pool.back(); c->pool.pop_back(); return e; }
@@ -266,6 +275,58 @@ dg_status dg_rk_coefficients(int integrator, double* A, double* B, double* c, in
   return fail(nullptr, DG_ERR_ARG, "dg_rk_coefficients: unknown integrator");
 }
 
+// ---------------------------------------------------------------------------
+// FV sub-cell operators: Bs[k][i] = integral of l_i over the k-th of the N+1
+// equal sub-intervals of [-1,1] (Gauss rule with N+1 points, exact for the
+// degree-N integrand), its inverse, and the inverse of the Vandermonde of the
+// orthonormal Legendre polynomials sqrt((2m+1)/2) P_m at the nodes.
+// ---------------------------------------------------------------------------
+static bool invert_small(std::vector<double> A, int n, double* inv) {
+  std::vector<double> I((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[(size_t)r * n + c]) > std::fabs(A[(size_t)piv * n + c])) piv = r;
+    if (A[(size_t)piv * n + c] == 0.0) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) { std::swap(A[(size_t)c * n + k], A[(size_t)piv * n + k]); std::swap(I[(size_t)c * n + k], I[(size_t)piv * n + k]); }
+    const double d = 1.0 / A[(size_t)c * n + c];
+    for (int k = 0; k < n; ++k) { A[(size_t)c * n + k] *= d; I[(size_t)c * n + k] *= d; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = A[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) { A[(size_t)r * n + k] -= f * A[(size_t)c * n + k]; I[(size_t)r * n + k] -= f * I[(size_t)c * n + k]; }
+    }
+  }
+  std::copy(I.begin(), I.end(), inv);
+  return true;
+}
+
+static void fv_operators(int n1, const std::vector<double>& x, DevBasis& b) {
+  std::vector<double> xg, wg;
+  host_basis(n1 - 1, DG_NODES_GAUSS, xg, wg);
+  std::vector<double> Bs((size_t)n1 * n1), V((size_t)n1 * n1);
+  for (int k = 0; k < n1; ++k) {
+    const double lo = -1.0 + 2.0 * k / n1, h = 2.0 / n1;
+    for (int i = 0; i < n1; ++i) {
+      double s = 0.0;
+      for (int g = 0; g < n1; ++g) s += wg[g] * lagrange_at(x, i, lo + 0.5 * h * (xg[g] + 1.0));
+      Bs[(size_t)k * n1 + i] = 0.5 * h * s;
+    }
+  }
+  for (int i = 0; i < n1; ++i)
+    for (int m = 0; m < n1; ++m) {
+      double P, dP, Pm, dPm;
+      leg_eval(m, x[i], &P, &dP, &Pm, &dPm);
+      V[(size_t)i * n1 + m] = std::sqrt((2.0 * m + 1.0) / 2.0) * P;
+    }
+  for (int t = 0; t < n1 * n1; ++t) b.Bs[t] = Bs[t];
+  invert_small(Bs, n1, b.Bsi);
+  invert_small(V, n1, b.Vli);
+}
+
 dg_status dg_create(const dg_config* cfg, dg_ctx** out) {
   if (!cfg || !out) return fail(nullptr, DG_ERR_ARG, "dg_create: null pointer");
   *out = nullptr;
@@ -285,6 +346,11 @@ dg_status dg_create(const dg_config* cfg, dg_ctx** out) {
       !std::isfinite(c.mu) || !std::isfinite(c.Pr) || !std::isfinite(c.R))
     return fail(nullptr, DG_ERR_ARG, "dg_create: gas constants");
   if (c.N < 1 || c.N > kMaxN) return fail(nullptr, DG_ERR_UNSUPPORTED, "dg_create: N must be in 1..7");
+  if (c.fv != 0 && c.fv != 1) return fail(nullptr, DG_ERR_ARG, "dg_create: fv");
+  if (c.fv && (c.physics != DG_PHYS_EULER || c.precision != DG_PREC_FP64 || c.riemann != DG_RIEMANN_RUSANOV ||
+               (c.volume_form == DG_FORM_SPLIT && c.nodes == DG_NODES_GAUSS)))
+    return fail(nullptr, DG_ERR_UNSUPPORTED,
+                "dg_create: FV sub-cells cover Euler, FP64, Rusanov, the weak form and the Lobatto split form");
   dg_ctx* x = new (std::nothrow) dg_ctx();
   if (!x) return fail(nullptr, DG_ERR_NOMEM, "dg_create: host allocation");
   x->cfg = c;
@@ -312,6 +378,7 @@ dg_status dg_create(const dg_config* cfg, dg_ctx** out) {
       b.DS[a * n1 + l] = 2.0 * x->D[a * n1 + l] - (x->Lp[a] * x->Lp[l] - x->Lm[a] * x->Lm[l]) / x->w[a];
     }
   }
+  if (c.fv) fv_operators(n1, x->x, b);
   *out = x;
   return DG_OK;
 }
@@ -329,6 +396,10 @@ static void free_device(dg_ctx* c) {
   if (c->d_face) (void)hipFree(c->d_face);
   if (c->d_efc) (void)hipFree(c->d_efc);
   if (c->d_basis) (void)hipFree(c->d_basis);
+  for (double** p : {&c->d_fvV, &c->d_fvS, &c->d_fvSb})
+    if (*p) { (void)hipFree(*p); *p = nullptr; }
+  for (int** p : {&c->d_etype, &c->d_etype_new, &c->d_sidefv, &c->d_side_elem})
+    if (*p) { (void)hipFree(*p); *p = nullptr; }
   c->d_Ja = c->d_sJ = c->d_face = nullptr;
   c->d_efc = nullptr;
   c->d_basis = nullptr;
@@ -451,6 +522,7 @@ dg_status dg_set_mesh(dg_ctx* c, int nElems, int Ngeo, const double* X, int nSid
   (void)N;
   c->nElems = nElems; c->nSides = nSides; c->Ngeo = Ngeo;
   c->efc.swap(efc); c->xyz.swap(xyz); c->Ja.swap(Ja); c->sJ.swap(sJ); c->nvec.swap(nvec); c->wJ.swap(wJ);
+  c->side_elem.assign(side_elem, side_elem + 2 * (size_t)nSides);
   c->volume = vol;
   c->mesh_set = true;
   c->ws = nullptr; c->ws_bytes = 0;
@@ -467,6 +539,64 @@ static dg_status upload_face(dg_ctx* c, const std::vector<double>& nvec) {
     face[t] = a / s; face[nf + t] = b / s; face[2 * nf + t] = d / s; face[3 * nf + t] = s;
   }
   HIPCHK(c, hipMemcpy(c->d_face, face.data(), face.size() * sizeof(double), hipMemcpyHostToDevice));
+  return DG_OK;
+}
+
+// FV sub-cell geometry from the current metrics: volumes V = B3 J, interior
+// sub-face vectors (Ja^r interpolated to the sub-cell planes, integrated over
+// each sub-face) and element-face sub-face vectors (the master's n s
+// integrated over each sub-face).
+static dg_status build_fv(dg_ctx* c) {
+  const int N = c->N, n1 = c->n1, n2 = c->n2, n3 = c->n3, nE = c->nElems, nS = c->nSides;
+  const double* Bs = c->hb.Bs;
+  std::vector<double> V((size_t)nE * n3), S((size_t)9 * nE * N * n2), Sb((size_t)3 * nS * n2);
+  std::vector<double> J((size_t)n3), t1((size_t)n3), t2((size_t)n3);
+  std::vector<double> Bm((size_t)n1 * n1);
+  for (int t = 0; t < n1 * n1; ++t) Bm[t] = Bs[t];
+  std::vector<double> lp((size_t)n1), pl((size_t)n2);
+  for (int e = 0; e < nE; ++e) {
+    for (int t = 0; t < n3; ++t) J[t] = 1.0 / c->sJ[(size_t)e * n3 + t];
+    apply_dim(Bm.data(), n1, n1, J.data(), n1, n1, n1, 0, t1.data());
+    apply_dim(Bm.data(), n1, n1, t1.data(), n1, n1, n1, 1, t2.data());
+    apply_dim(Bm.data(), n1, n1, t2.data(), n1, n1, n1, 2, &V[(size_t)e * n3]);
+    for (int r = 0; r < 3; ++r)
+      for (int a = 0; a < N; ++a) {
+        const double xp = -1.0 + 2.0 * (a + 1) / n1;
+        for (int l = 0; l < n1; ++l) lp[l] = lagrange_at(c->x, l, xp);
+        for (int comp = 0; comp < 3; ++comp) {
+          const double* Jr = &c->Ja[((size_t)(3 * r + comp) * nE + e) * n3];
+          for (int q = 0; q < n1; ++q)
+            for (int p = 0; p < n1; ++p) {
+              double v = 0.0;
+              for (int l = 0; l < n1; ++l) {
+                const int i = r == 0 ? l : p, j = r == 0 ? p : (r == 1 ? l : q), k = r == 2 ? l : q;
+                v += lp[l] * Jr[(k * n1 + j) * n1 + i];
+              }
+              pl[q * n1 + p] = v;
+            }
+          for (int q = 0; q < n1; ++q)
+            for (int p = 0; p < n1; ++p) {
+              double v = 0.0;
+              for (int b2 = 0; b2 < n1; ++b2)
+                for (int a2 = 0; a2 < n1; ++a2) v += Bs[p * n1 + a2] * Bs[q * n1 + b2] * pl[b2 * n1 + a2];
+              S[(((size_t)(3 * r + comp) * nE + e) * N + a) * n2 + q * n1 + p] = v;
+            }
+        }
+      }
+  }
+  for (int comp = 0; comp < 3; ++comp)
+    for (int s = 0; s < nS; ++s)
+      for (int q = 0; q < n1; ++q)
+        for (int p = 0; p < n1; ++p) {
+          double v = 0.0;
+          for (int b2 = 0; b2 < n1; ++b2)
+            for (int a2 = 0; a2 < n1; ++a2)
+              v += Bs[p * n1 + a2] * Bs[q * n1 + b2] * c->nvec[((size_t)comp * nS + s) * n2 + b2 * n1 + a2];
+          Sb[((size_t)comp * nS + s) * n2 + q * n1 + p] = v;
+        }
+  HIPCHK(c, hipMemcpy(c->d_fvV, V.data(), V.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_fvS, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_fvSb, Sb.data(), Sb.size() * sizeof(double), hipMemcpyHostToDevice));
   return DG_OK;
 }
 
@@ -492,6 +622,27 @@ dg_status dg_upload_mesh(dg_ctx* c, int nElems, int Ngeo, const double* X, int n
   HIPCHK(c, hipMemcpy(c->d_basis, &c->hb, sizeof(DevBasis), hipMemcpyHostToDevice));
   st = upload_face(c, c->nvec);
   if (st != DG_OK) return st;
+  if (c->cfg.fv) {
+    const size_t nE = c->nElems, nS = c->nSides;
+    if ((e = hipMalloc((void**)&c->d_fvV, nv * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&c->d_fvS, (size_t)9 * nE * c->N * c->n2 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&c->d_fvSb, 3 * nf * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&c->d_etype, nE * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc((void**)&c->d_etype_new, nE * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc((void**)&c->d_sidefv, nS * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc((void**)&c->d_side_elem, 2 * nS * sizeof(int))) != hipSuccess) {
+      free_device(c);
+      return fail(c, e == hipErrorOutOfMemory ? DG_ERR_NOMEM : DG_ERR_HIP,
+                  std::string("dg_upload_mesh: hipMalloc (FV): ") + hipGetErrorString(e));
+    }
+    std::vector<int> zeros(std::max(nE, nS), 0);
+    HIPCHK(c, hipMemcpy(c->d_etype, zeros.data(), nE * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_etype_new, zeros.data(), nE * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_sidefv, zeros.data(), nS * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_side_elem, c->side_elem.data(), 2 * nS * sizeof(int), hipMemcpyHostToDevice));
+    st = build_fv(c);
+    if (st != DG_OK) return st;
+  }
   c->mesh_on_device = true;
   return DG_OK;
 }
@@ -519,7 +670,9 @@ dg_status dg_upload_metrics(dg_ctx* c, const double* Ja, const double* sJ, const
       vol += c->wJ[u];
     }
   c->volume = vol;
-  return upload_face(c, nv3);
+  dg_status st = upload_face(c, nv3);
+  if (st != DG_OK || !c->cfg.fv) return st;
+  return build_fv(c);
 }
 
 dg_status dg_get_metrics(const dg_ctx* cc, double* xyz, double* Ja, double* sJ, double* nvec) {
@@ -549,7 +702,7 @@ dg_status dg_sizes(const dg_ctx* cc, int* nElems, int* nSides, int* npe, size_t*
 // Workspace
 // ---------------------------------------------------------------------------
 struct WsLayout {
-  size_t utr[2], gtr, g, red, flag, total;
+  size_t utr[2], gtr, g, red, fvind, flag, total;
   // adjoint region: recomputed stage states Y_1..Y_{S-1}, forward RK
   // register, adjoint residual, gradient adjoint (Navier-Stokes)
   size_t Y[DG_RK_MAX_STAGES - 1], dUf, aout, gbar, total_adjoint;
@@ -573,12 +726,15 @@ static WsLayout ws_layout(const dg_ctx* c) {
   size_t off = 0;
   // U traces [2 slots][5][nf]; the split form on Gauss nodes appends the
   // traces' ln rho, ln beta [2 slots][2][nf]
+  // (FV contexts: 10 values per face node, the DG trace or two primitive sub-cell layers)
   const bool es = c->cfg.volume_form == DG_FORM_SPLIT && c->cfg.nodes == DG_NODES_GAUSS;
-  for (int b = 0; b < 2; ++b) { L.utr[b] = off; off += align256(2 * (es ? 7 : 5) * nf * sizeof(double)); }
+  const int tv = c->cfg.fv ? 10 : (es ? 7 : 5);
+  for (int b = 0; b < 2; ++b) { L.utr[b] = off; off += align256(2 * (size_t)tv * nf * sizeof(double)); }
   const bool ns = c->cfg.physics == DG_PHYS_NAVIER_STOKES;
   L.gtr = off; off += ns ? align256(2 * 12 * nf * sizeof(double)) : 0;
   L.g = off; off += ns ? align256(12 * nv * sizeof(double)) : 0;
   L.red = off; off += align256((size_t)(2 * reduction_blocks() + 8) * sizeof(double));
+  L.fvind = off; off += c->cfg.fv ? align256((size_t)c->nElems * sizeof(double)) : 0;
   L.flag = off; off += 256;
   L.total = off;
   const size_t st = align256(5 * nv * sizeof(double));
@@ -628,6 +784,7 @@ static Cfg kcfg(const dg_ctx* c) {
   k.precision = c->cfg.precision;
   k.roe = c->cfg.riemann == DG_RIEMANN_ROE ? 1 : 0;
   k.visc = c->cfg.viscosity == DG_VISC_SUTHERLAND ? 1 : 0;
+  k.fv = c->cfg.fv;
   return k;
 }
 
@@ -635,6 +792,7 @@ static Geo kgeo(const dg_ctx* c) {
   Geo g;
   g.nElems = c->nElems; g.nSides = c->nSides;
   g.Ja = c->d_Ja; g.sJ = c->d_sJ; g.face = c->d_face; g.efc = c->d_efc; g.basis = c->d_basis;
+  g.etype = c->d_etype; g.sidefv = c->d_sidefv; g.fvV = c->d_fvV; g.fvS = c->d_fvS; g.fvSb = c->d_fvSb;
   return g;
 }
 
@@ -667,8 +825,23 @@ static dg_status stage(dg_ctx* c, int mode, const double* U, double* Ut, double*
     ProfScope ps(c, FAM_LIFT, s);
     LAUNCHCHK(c, launch_lift(k, 1, g, c->phys, U, w.Utr[cur], w.g, w.gtr, s));
   }
-  ProfScope ps(c, FAM_VOLUME, s);
-  LAUNCHCHK(c, launch_volume(k, g, c->phys, mode, U, w.Utr[cur], w.g, w.gtr, Ut, Uio, dU, w.Utr[cur ^ 1], A, B, dt, s));
+  {
+    ProfScope ps(c, FAM_VOLUME, s);
+    LAUNCHCHK(c, launch_volume(k, g, c->phys, mode, U, w.Utr[cur], w.g, w.gtr, Ut, Uio, dU, w.Utr[cur ^ 1], A, B, dt, s));
+  }
+  if (c->cfg.fv) {
+    // FV elements (the volume kernel above leaves them untouched)
+    ProfScope ps(c, FAM_FV, s);
+    LAUNCHCHK(c, launch_fv(k, g, c->phys, mode, U, w.Utr[cur], Ut, Uio, dU, w.Utr[cur ^ 1], A, B, dt, s));
+  }
+  return DG_OK;
+}
+
+// Face traces of U into Utr (the FV context's two-layer traces on FV faces).
+static dg_status traces(dg_ctx* c, const double* U, double* Utr, hipStream_t s) {
+  ProfScope ps(c, FAM_TRACE, s);
+  if (c->cfg.fv) LAUNCHCHK(c, launch_trace_fv(kcfg(c), kgeo(c), c->phys, U, Utr, s));
+  else LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), c->phys, U, Utr, s));
   return DG_OK;
 }
 
@@ -680,10 +853,8 @@ dg_status dg_rhs(dg_ctx* c, const double* U, double* Ut, double t, void* stream)
   (void)t;
   hipStream_t s = (hipStream_t)stream;
   Work w = kwork(c);
-  {
-    ProfScope ps(c, FAM_TRACE, s);
-    LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), c->phys, U, w.Utr[0], s));
-  }
+  st = traces(c, U, w.Utr[0], s);
+  if (st != DG_OK) return st;
   return stage(c, 0, U, Ut, nullptr, nullptr, 0, 0.0, 0.0, 0.0, s);
 }
 
@@ -716,10 +887,8 @@ dg_status dg_rk_step(dg_ctx* c, double* U, double* dU, double t, double dt, int 
     ProfScope ps(c, FAM_OTHER, s);
     LAUNCHCHK(c, launch_fill(dU, n, 0.0, s));
   }
-  {
-    ProfScope ps(c, FAM_TRACE, s);
-    LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), c->phys, U, w.Utr[0], s));
-  }
+  st = traces(c, U, w.Utr[0], s);
+  if (st != DG_OK) return st;
   int cur = 0;
   for (int step = 0; step < nsteps; ++step)
     for (int k = 0; k < ns; ++k) {
@@ -738,6 +907,7 @@ static dg_status ready_adjoint(dg_ctx* c, const char* who) {
     return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": the adjoint covers the Rusanov flux and constant viscosity");
   if (c->cfg.volume_form == DG_FORM_SPLIT && c->cfg.nodes == DG_NODES_GAUSS)
     return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": the adjoint covers the split form on Lobatto nodes only");
+  if (c->cfg.fv) return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": the adjoint does not cover FV sub-cells");
   if (c->ws_bytes < ws_layout(c).total_adjoint)
     return fail(c, DG_ERR_STATE, std::string(who) + ": bound workspace is smaller than dg_workspace_bytes_adjoint");
   return DG_OK;
@@ -893,10 +1063,79 @@ dg_status dg_check_state(dg_ctx* c, const double* U, void* stream) {
   return DG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// FV sub-cells: switching and indicator
+// ---------------------------------------------------------------------------
+static dg_status ready_fv(dg_ctx* c, const char* who) {
+  dg_status st = ready(c, who);
+  if (st != DG_OK) return st;
+  if (!c->cfg.fv) return fail(c, DG_ERR_STATE, std::string(who) + ": the context was created without fv");
+  return DG_OK;
+}
+
+// Converts U/dU to the types in d_etype_new, sets d_etype, then the side flags.
+static dg_status fv_apply(dg_ctx* c, double* U, double* dU, hipStream_t s) {
+  ProfScope ps(c, FAM_OTHER, s);
+  LAUNCHCHK(c, launch_fv_switch(kcfg(c), kgeo(c), U, dU, c->d_etype_new, c->d_etype, s));
+  LAUNCHCHK(c, launch_fv_side_flags(c->nSides, c->d_side_elem, c->d_etype, c->d_sidefv, s));
+  return DG_OK;
+}
+
+dg_status dg_fv_switch(dg_ctx* c, double* U, double* dU, const int* mask_host, void* stream) {
+  dg_status st = ready_fv(c, "dg_fv_switch");
+  if (st != DG_OK) return st;
+  if (!U || !mask_host) return fail(c, DG_ERR_ARG, "dg_fv_switch: null pointer");
+  if (U == dU) return fail(c, DG_ERR_ARG, "dg_fv_switch: U and dU alias");
+  std::vector<int> m(mask_host, mask_host + c->nElems);
+  for (int& v : m) {
+    if (v != 0 && v != 1) return fail(c, DG_ERR_ARG, "dg_fv_switch: mask entries must be 0 or 1");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(c, hipMemcpyAsync(c->d_etype_new, m.data(), m.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return fv_apply(c, U, dU, s);
+}
+
+dg_status dg_fv_indicator(dg_ctx* c, const double* U, double* ind_dev, void* stream) {
+  dg_status st = ready_fv(c, "dg_fv_indicator");
+  if (st != DG_OK) return st;
+  if (!U || !ind_dev) return fail(c, DG_ERR_ARG, "dg_fv_indicator: null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  ProfScope ps(c, FAM_OTHER, s);
+  LAUNCHCHK(c, launch_fv_indicator(kcfg(c), kgeo(c), U, ind_dev, s));
+  return DG_OK;
+}
+
+dg_status dg_fv_switch_by_indicator(dg_ctx* c, double* U, double* dU, double lo, double hi, void* stream) {
+  dg_status st = ready_fv(c, "dg_fv_switch_by_indicator");
+  if (st != DG_OK) return st;
+  if (!U) return fail(c, DG_ERR_ARG, "dg_fv_switch_by_indicator: null pointer");
+  if (U == dU) return fail(c, DG_ERR_ARG, "dg_fv_switch_by_indicator: U and dU alias");
+  if (!(lo <= hi)) return fail(c, DG_ERR_ARG, "dg_fv_switch_by_indicator: need ind_lo <= ind_hi");
+  hipStream_t s = (hipStream_t)stream;
+  double* ind = (double*)(c->ws + ws_layout(c).fvind);
+  {
+    ProfScope ps(c, FAM_OTHER, s);
+    LAUNCHCHK(c, launch_fv_indicator(kcfg(c), kgeo(c), U, ind, s));
+    LAUNCHCHK(c, launch_fv_decide(c->nElems, ind, lo, hi, c->d_etype, c->d_etype_new, s));
+  }
+  return fv_apply(c, U, dU, s);
+}
+
+dg_status dg_fv_mask(dg_ctx* c, int* mask_host, void* stream) {
+  dg_status st = ready_fv(c, "dg_fv_mask");
+  if (st != DG_OK) return st;
+  if (!mask_host) return fail(c, DG_ERR_ARG, "dg_fv_mask: null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(c, hipMemcpyAsync(mask_host, c->d_etype, (size_t)c->nElems * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return DG_OK;
+}
+
 dg_status dg_profile(dg_ctx* c, int enable) {
   if (!c) return fail(nullptr, DG_ERR_ARG, "dg_profile: null context");
   prof_collect(c);
-  for (int f = 0; f < 5; ++f) { c->prof_ms[f] = 0.0; c->prof_n[f] = 0; }
+  for (int f = 0; f < 6; ++f) { c->prof_ms[f] = 0.0; c->prof_n[f] = 0; }
   c->prof = enable != 0;
   return DG_OK;
 }
@@ -905,7 +1144,7 @@ dg_status dg_profile_query(dg_ctx* c, const char* kernel, double* total_ms, long
   if (!c) return fail(nullptr, DG_ERR_ARG, "dg_profile_query: null context");
   if (!kernel || !total_ms || !count) return fail(c, DG_ERR_ARG, "dg_profile_query: null pointer");
   int fam = -1;
-  for (int f = 0; f < 5; ++f)
+  for (int f = 0; f < 6; ++f)
     if (std::strcmp(kernel, kFamNames[f]) == 0) fam = f;
   if (fam < 0) return fail(c, DG_ERR_ARG, std::string("dg_profile_query: unknown kernel family ") + kernel);
   prof_collect(c);

@@ -89,9 +89,28 @@ static void vol_phys(const Cfg& c, int mode, const Geo& g, const Phys& p, const 
   }
 }
 
+// DG elements of an FV context (Euler, FP64, Rusanov)
+template <int NODES, int FORM>
+static void vol_fv(int mode, const Geo& g, const Phys& p, const double* U, const double* Utr, double* Ut, double* Uio,
+                   double* dU, double* Utr_next, double A, double B, double dt, hipStream_t s) {
+  const dim3 grid(g.nElems), block(Shape<kN>::nth);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, 0, 0, 0, 0, 1>), grid, block, 0, s, g, p, U, Utr, nullptr, nullptr,
+                       Ut, Uio, dU, Utr_next, A, B, dt);
+  else
+    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, 0, 0, 1, 0, 1>), grid, block, 0, s, g, p, U, Utr, nullptr, nullptr,
+                       Ut, Uio, dU, Utr_next, A, B, dt);
+}
+
 hipError_t DGX_NAME(launch_volume)(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U,
                                    const double* Utr, const double* gvn, const double* gvf, double* Ut, double* Uio,
                                    double* dU, double* Utr_next, double A, double B, double dt, hipStream_t s) {
+  if (c.fv) {
+    if (c.nodes == 0) vol_fv<0, 0>(mode, g, p, U, Utr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    else if (c.form == 0) vol_fv<1, 0>(mode, g, p, U, Utr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    else vol_fv<1, 1>(mode, g, p, U, Utr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    return hipGetLastError();
+  }
   if (c.nodes == 0 && c.form == 0)
     vol_phys<0, 0>(c, mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   else if (c.nodes == 0)
@@ -100,6 +119,41 @@ hipError_t DGX_NAME(launch_volume)(const Cfg& c, const Geo& g, const Phys& p, in
     vol_phys<1, 0>(c, mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   else
     vol_phys<1, 1>(c, mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  return hipGetLastError();
+}
+
+hipError_t DGX_NAME(launch_trace_fv)(const Cfg& c, const Geo& g, const Phys& p, const double* U, double* Utr,
+                                     hipStream_t s) {
+  const dim3 grid(g.nElems), block(Shape<kN>::nth);
+  if (c.nodes == 1)
+    hipLaunchKernelGGL((k_trace_fv<kN, 1>), grid, block, 0, s, g, p, U, Utr);
+  else
+    hipLaunchKernelGGL((k_trace_fv<kN, 0>), grid, block, 0, s, g, p, U, Utr);
+  return hipGetLastError();
+}
+
+hipError_t DGX_NAME(launch_fv)(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U,
+                               const double* Utr, double* Ut, double* Uio, double* dU, double* Utr_next, double A,
+                               double B, double dt, hipStream_t s) {
+  (void)c;
+  const dim3 grid(g.nElems), block(Shape<kN>::nth);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_fv<kN, 0>), grid, block, 0, s, g, p, U, Utr, Ut, Uio, dU, Utr_next, A, B, dt);
+  else
+    hipLaunchKernelGGL((k_fv<kN, 1>), grid, block, 0, s, g, p, U, Utr, Ut, Uio, dU, Utr_next, A, B, dt);
+  return hipGetLastError();
+}
+
+hipError_t DGX_NAME(launch_fv_indicator)(const Cfg& c, const Geo& g, const double* U, double* ind, hipStream_t s) {
+  (void)c;
+  hipLaunchKernelGGL((k_fv_indicator<kN>), dim3(g.nElems), dim3(Shape<kN>::nth), 0, s, g, U, ind);
+  return hipGetLastError();
+}
+
+hipError_t DGX_NAME(launch_fv_switch)(const Cfg& c, const Geo& g, double* U, double* dU, const int* etype_new,
+                                      int* etype, hipStream_t s) {
+  (void)c;
+  hipLaunchKernelGGL((k_fv_switch<kN>), dim3(g.nElems), dim3(Shape<kN>::nth), 0, s, g, U, dU, etype_new, etype);
   return hipGetLastError();
 }
 

@@ -21,6 +21,10 @@ struct DevBasis {
   double Dhat[kMaxN1 * kMaxN1];   // Dhat[a*n1+l] = (w_l / w_a) D_{l a}  (weak-form volume operator)
   double DS[kMaxN1 * kMaxN1];     // DS[a*n1+l] = 2 D_{a l} - e_N e_N^T / w_N + e_0 e_0^T / w_0  (split form)
   double D[kMaxN1 * kMaxN1];      // D[a*n1+l] = l_l'(x_a)
+  // FV sub-cells (zero unless enabled)
+  double Bs[kMaxN1 * kMaxN1];     // Bs[k*n1+i] = integral of l_i over sub-interval k of [-1,1]
+  double Bsi[kMaxN1 * kMaxN1];    // inverse of Bs
+  double Vli[kMaxN1 * kMaxN1];    // inverse of the orthonormal-Legendre Vandermonde V[i*n1+m] = P~_m(x_i)
 };
 
 // Per-element face table entry: side index, slot (0 master / 1 slave), orientation.
@@ -55,6 +59,12 @@ struct Geo {
   const double* face;    // [4][nSides][n2]: unit normal (3), surface element
   const int* efc;        // [nElems][6]
   const DevBasis* basis;
+  // FV sub-cells (null unless enabled)
+  const int* etype;      // [nElems]: 0 DG, 1 FV
+  const int* sidefv;     // [nSides]: 1 if either element of the side is FV
+  const double* fvV;     // [nElems][n3] sub-cell volumes
+  const double* fvS;     // [3 r * 3 c][nElems][N][n2] interior sub-face vectors (+xi_r)
+  const double* fvSb;    // [3 c][nSides][n2] master-outward element-face sub-face vectors
 };
 
 // Kernel-side workspace pointers.
@@ -68,6 +78,7 @@ struct Work {
 
 struct Cfg {
   int N, nodes, form, physics, precision;
+  int fv;    // FV sub-cells enabled (traces of 10 values, FV kernels)
   int roe;   // Roe's face flux (its own kernel instantiations)
   int visc;  // viscosity law (0 constant, 1 Sutherland; its own lifting instantiations)
 };
@@ -93,6 +104,22 @@ hipError_t launch_volume(const Cfg& c, const Geo& g, const Phys& p, int mode, co
 hipError_t launch_adjoint(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* lam,
                           const double* Utr, double* Lbar, const double* gin, double* gtr, double* out, double* gbar,
                           hipStream_t s);
+// FV sub-cells.  Traces of an FV context hold 10 values per face node: the DG
+// trace (values 0..4) on DG faces; on FV faces the primitive means of the
+// first (0..4) and second (5..9) sub-cell layers under the face.
+hipError_t launch_trace_fv(const Cfg& c, const Geo& g, const Phys& p, const double* U, double* Utr, hipStream_t s);
+// FV elements' residual (mode 0) or RK stage and next traces (mode 1).
+hipError_t launch_fv(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U, const double* Utr,
+                     double* Ut, double* Uio, double* dU, double* Utr_next, double A, double B, double dt,
+                     hipStream_t s);
+hipError_t launch_fv_indicator(const Cfg& c, const Geo& g, const double* U, double* ind, hipStream_t s);
+// Converts U and dU (may be null) of the elements whose type in etype_new
+// differs from etype, then sets etype = etype_new.
+hipError_t launch_fv_switch(const Cfg& c, const Geo& g, double* U, double* dU, const int* etype_new, int* etype,
+                            hipStream_t s);
+hipError_t launch_fv_decide(int nElems, const double* ind, double lo, double hi, const int* etype, int* etype_new,
+                            hipStream_t s);
+hipError_t launch_fv_side_flags(int nSides, const int* side_elem, const int* etype, int* sidefv, hipStream_t s);
 hipError_t launch_adj_rk_update(size_t n, const double* out, double* lamU, double* lamdU, double dt, double A,
                                 double Bnext, hipStream_t s);
 hipError_t launch_scale_copy(size_t n, const double* x, double* y, double a, hipStream_t s);

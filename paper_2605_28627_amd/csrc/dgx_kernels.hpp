@@ -21,52 +21,29 @@
 
 #include "dgx_internal.hpp"
 #include "dgx_pointwise.hpp"
+#include "dgx_tile.hpp"
+#include "dgx_fv.hpp"
 
 namespace dgx {
 
-template <int N>
-struct Shape {
-  static constexpr int n1 = N + 1;
-  static constexpr int n2 = n1 * n1;
-  static constexpr int n3 = n2 * n1;
-  static constexpr int nth = ((n3 + 63) / 64) * 64;   // work-items per element (whole wavefronts)
-  static constexpr int nface = 6 * n2;                 // face nodes of one element
-};
-
-template <int N>
-__device__ __forceinline__ int nidx(int i, int j, int k) { return (k * (N + 1) + j) * (N + 1) + i; }
-
-// Volume node at position a along reference direction r, tangential face indices (pp, qq).
-template <int N>
-__device__ __forceinline__ int line_node(int r, int a, int pp, int qq) {
-  return r == 0 ? nidx<N>(a, pp, qq) : (r == 1 ? nidx<N>(pp, a, qq) : nidx<N>(pp, qq, a));
-}
-
-// Copy the basis into LDS (cooperatively).
-__device__ __forceinline__ void load_basis(DevBasis* dst, const DevBasis* src, int t, int nth) {
-  const double* s = reinterpret_cast<const double*>(src);
-  double* d = reinterpret_cast<double*>(dst);
-  constexpr int nd = sizeof(DevBasis) / sizeof(double);
-  for (int x = t; x < nd; x += nth) d[x] = s[x];
-}
-
 // The entries of the basis the residual and lifting kernels read, at their
 // exact size (the LDS footprint decides how many elements share a CU).
-template <int N>
+// (FVB: also the FV sub-cell operators Bs, Bs^-1.)
+template <int N, bool FVB = false>
 struct VolBasis {
   static constexpr int n1 = N + 1;
-  double winv[n1], Lm[n1], Lp[n1], Dhat[n1 * n1], DS[n1 * n1];
+  static constexpr int nf = FVB ? n1 * n1 : 1;
+  double winv[n1], Lm[n1], Lp[n1], Dhat[n1 * n1], DS[n1 * n1], Bs[nf], Bsi[nf];
 };
-template <int N>
-__device__ __forceinline__ void load_vol_basis(VolBasis<N>* dst, const DevBasis* src, int t, int nth) {
+template <int N, bool FVB = false>
+__device__ __forceinline__ void load_vol_basis(VolBasis<N, FVB>* dst, const DevBasis* src, int t, int nth) {
   constexpr int n1 = N + 1;
   for (int x = t; x < n1; x += nth) { dst->winv[x] = src->winv[x]; dst->Lm[x] = src->Lm[x]; dst->Lp[x] = src->Lp[x]; }
   for (int x = t; x < n1 * n1; x += nth) { dst->Dhat[x] = src->Dhat[x]; dst->DS[x] = src->DS[x]; }
+  if constexpr (FVB)
+    for (int x = t; x < n1 * n1; x += nth) { dst->Bs[x] = src->Bs[x]; dst->Bsi[x] = src->Bsi[x]; }
 }
 
-__device__ __forceinline__ size_t tr_index(int slot, int v, int nvar, int nSides, int side, int n2, int fi) {
-  return (((size_t)slot * nvar + v) * nSides + side) * n2 + fi;
-}
 
 // ---------------------------------------------------------------------------
 // Trace kernel: U at the element faces -> Utr[slot][5][side][master (p,q)].
@@ -413,7 +390,11 @@ constexpr int volume_waves() {
   return Shape<N>::nth >= 512 ? 4 : ((FORM == 1 && NODES == 0 && Shape<N>::nth == 64) ? DGX_ES_WAVES : 1);
 }
 
-template <int N, int NODES, int FORM, int PHYS, int PREC, int MODE, int ROE>
+// FV (Euler contexts with FV sub-cells): DG elements only; faces with an FV
+// element on either side take the sub-face fluxes back as the nodal flux
+// polynomial (B^-1 x B^-1), and the RK epilogue writes two-layer primitive
+// traces there.
+template <int N, int NODES, int FORM, int PHYS, int PREC, int MODE, int ROE, int FV = 0>
 __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) void k_volume(Geo G, Phys P, const double* __restrict__ U,
                                                           const double* __restrict__ Utr,
                                                           const double* __restrict__ gvn,
@@ -436,7 +417,11 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   constexpr int SZ_SPLIT = (8 + 3 + NV + (ES && !kEsAllShfl ? 10 : 0)) * n3;   // aux + Ja^r + G~^r (+ face coupling)
   constexpr int SZ_WEAK = 5 * n3;                                    // F~^r
   constexpr int SZ_V = FORM == 1 ? SZ_SPLIT : SZ_WEAK;
-  constexpr int SZ = SZ_V > 5 * n3 ? SZ_V : 5 * n3;                  // also holds the new state (Gauss traces)
+  constexpr int SZ0 = SZ_V > 5 * n3 ? SZ_V : 5 * n3;                 // also holds the new state (Gauss traces)
+  // FV: sub-face fluxes of the six faces, and two buffers for the means of the new state
+  constexpr int SZ_FV = (5 * S::nface > 10 * n3 ? 5 * S::nface : 10 * n3);
+  constexpr int SZ = FV && SZ_FV > SZ0 ? SZ_FV : SZ0;
+  constexpr int TNV = FV ? kTrFV : 5;                                // trace values per face node
   // Surface fluxes (outward, own face-local order): all six faces at once, or
   // (Gauss split form) the two faces of each direction within its pass,
   // together with the two-point records of the own projected face states.
@@ -444,10 +429,13 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   __shared__ double sphi[5 * kFaces * n2];
   __shared__ double sm[SZ];
   __shared__ double saf[ES ? 8 * kFaces * n2 : 1];
-  __shared__ VolBasis<N> sb;
+  __shared__ VolBasis<N, FV != 0> sb;
   const int e = blockIdx.x, t = threadIdx.x;
+  if constexpr (FV) {
+    if (G.etype[e]) return;   // FV elements belong to the FV kernel
+  }
   const int nE = G.nElems, nS = G.nSides;
-  load_vol_basis<N>(&sb, G.basis, t, S::nth);
+  load_vol_basis<N, FV != 0>(&sb, G.basis, t, S::nth);
   const bool act = t < n3;
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   const int idx[3] = {i, j, k};
@@ -492,11 +480,22 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
     int p = pp, qm = qq;
     if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
     const int fi = qm * n1 + p;
+    const double sgn = slot ? -1.0 : 1.0;
+    if constexpr (FV) {
+      if (G.sidefv[side]) {
+        // FV face: the sub-face flux, outward, into the staging area (taken back below)
+        double F[5];
+        fv_face_flux(Utr, G.fvSb, nS, n2, side, fi, P, F);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm[(f * 5 + v) * n2 + rr] = sgn * F[v];
+        return;
+      }
+    }
     double UL[5], UR[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      UL[v] = Utr[tr_index(0, v, 5, nS, side, n2, fi)];
-      UR[v] = Utr[tr_index(1, v, 5, nS, side, n2, fi)];
+      UL[v] = Utr[tr_index(0, v, TNV, nS, side, n2, fi)];
+      UR[v] = Utr[tr_index(1, v, TNV, nS, side, n2, fi)];
     }
     const double nh[3] = {G.face[((size_t)0 * nS + side) * n2 + fi], G.face[((size_t)1 * nS + side) * n2 + fi],
                           G.face[((size_t)2 * nS + side) * n2 + fi]};
@@ -524,13 +523,30 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
 #pragma unroll
         for (int v = 0; v < 4; ++v) Phi[1 + v] -= 0.5 * ld_visc<PREC>(gvf, tr_index(sd, v, 4, nS, side, n2, fi));
     }
-    const double sgn = slot ? -1.0 : 1.0;
 #pragma unroll
     for (int v = 0; v < 5; ++v) sphi[(fs * 5 + v) * n2 + rr] = sgn * Phi[v];
   };
   // 1. surface fluxes of the six faces (other forms)
   if constexpr (!ES) {
     for (int ft = t; ft < S::nface; ft += S::nth) face_node(ft / n2, ft % n2, ft / n2);
+  }
+  if constexpr (FV) {
+    // FV faces: nodal flux polynomial with the sub-face integrals, Phi = (B^-1 x B^-1) F
+    __syncthreads();
+    for (int ft = t; ft < S::nface; ft += S::nth) {
+      const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
+      if (!G.sidefv[efc_side(G.efc[e * 6 + f])]) continue;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        double sacc = 0.0;
+        for (int q2 = 0; q2 < n1; ++q2)
+#pragma unroll
+          for (int p2 = 0; p2 < n1; ++p2)
+            sacc += sb.Bsi[pp * n1 + p2] * sb.Bsi[qq * n1 + q2] * sm[(f * 5 + v) * n2 + q2 * n1 + p2];
+        sphi[(f * 5 + v) * n2 + rr] = sacc;
+      }
+    }
+    __syncthreads();
   }
   // 2. own state
   double acc[5] = {0, 0, 0, 0, 0};
@@ -797,10 +813,11 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
           const int info = G.efc[e * 6 + f];
           const int side = efc_side(info), slot = efc_slot(info);
+          if (FV && G.sidefv[side]) continue;
           int p = pp, qm = qq;
           if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
 #pragma unroll
-          for (int v = 0; v < 5; ++v) Utr_next[tr_index(slot, v, 5, nS, side, n2, qm * n1 + p)] = Unew[v];
+          for (int v = 0; v < 5; ++v) Utr_next[tr_index(slot, v, TNV, nS, side, n2, qm * n1 + p)] = Unew[v];
         }
       }
     } else {
@@ -822,6 +839,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
         const double* L = (f & 1) ? sb.Lp : sb.Lm;
         const int info = G.efc[e * 6 + f];
         const int side = efc_side(info), slot = efc_slot(info);
+        if (FV && G.sidefv[side]) continue;
         int p = pp, qm = qq;
         if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
         double s[5];
@@ -841,7 +859,36 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           Ltr[tr_index(slot, 1, 2, nS, side, n2, qm * n1 + p)] = lg[1];
         }
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Utr_next[tr_index(slot, v, 5, nS, side, n2, qm * n1 + p)] = s[v];
+        for (int v = 0; v < 5; ++v) Utr_next[tr_index(slot, v, TNV, nS, side, n2, qm * n1 + p)] = s[v];
+      }
+    }
+    if constexpr (FV) {
+      // FV faces of this DG element: primitive means of its first two sub-cell layers
+      bool anyfv = false;
+#pragma unroll
+      for (int f = 0; f < 6; ++f) anyfv = anyfv || G.sidefv[efc_side(G.efc[e * 6 + f])];
+      if (anyfv) {
+        __syncthreads();
+        double* sa = sm;
+        double* sc = sm + 5 * n3;
+        if (act) {
+          const double J = 1.0 / sJn;
+#pragma unroll
+          for (int v = 0; v < 5; ++v) sa[v * n3 + t] = J * Unew[v];
+        }
+        __syncthreads();
+        tensor3<N>(sb.Bs, sa, sc, 5, t);
+        if (act) {
+          const double iv = 1.0 / G.fvV[(size_t)e * n3 + t];
+          double m[5], W[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) m[v] = sc[v * n3 + t] * iv;
+          cons_to_prim5(m, P.gm1, W);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) sc[v * n3 + t] = W[v];
+        }
+        __syncthreads();
+        write_fv_traces<N>(G, e, sc, Utr_next, true, t, S::nth);
       }
     }
   }

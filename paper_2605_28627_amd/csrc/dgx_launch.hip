@@ -15,7 +15,12 @@ namespace dgx {
                                 const double*, const double*, double*, double*, double*, double*, double,   \
                                 double, double, hipStream_t);                                                  \
   hipError_t launch_adjoint_N##n(const Cfg&, const Geo&, const Phys&, const double*, const double*,          \
-                                 const double*, double*, const double*, double*, double*, double*, hipStream_t);
+                                 const double*, double*, const double*, double*, double*, double*, hipStream_t); \
+  hipError_t launch_trace_fv_N##n(const Cfg&, const Geo&, const Phys&, const double*, double*, hipStream_t);   \
+  hipError_t launch_fv_N##n(const Cfg&, const Geo&, const Phys&, int, const double*, const double*, double*,   \
+                            double*, double*, double*, double, double, double, hipStream_t);                   \
+  hipError_t launch_fv_indicator_N##n(const Cfg&, const Geo&, const double*, double*, hipStream_t);           \
+  hipError_t launch_fv_switch_N##n(const Cfg&, const Geo&, double*, double*, const int*, int*, hipStream_t);
 DGX_DECL(1)
 DGX_DECL(2)
 DGX_DECL(3)
@@ -41,6 +46,61 @@ hipError_t launch_trace(const Cfg& c, const Geo& g, const Phys& p, const double*
 #define ARGS (c, g, p, U, Utr, s)
   DGX_SWITCH(launch_trace)
 #undef ARGS
+}
+
+hipError_t launch_trace_fv(const Cfg& c, const Geo& g, const Phys& p, const double* U, double* Utr, hipStream_t s) {
+#define ARGS (c, g, p, U, Utr, s)
+  DGX_SWITCH(launch_trace_fv)
+#undef ARGS
+}
+
+hipError_t launch_fv(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U, const double* Utr,
+                     double* Ut, double* Uio, double* dU, double* Utr_next, double A, double B, double dt,
+                     hipStream_t s) {
+#define ARGS (c, g, p, mode, U, Utr, Ut, Uio, dU, Utr_next, A, B, dt, s)
+  DGX_SWITCH(launch_fv)
+#undef ARGS
+}
+
+hipError_t launch_fv_indicator(const Cfg& c, const Geo& g, const double* U, double* ind, hipStream_t s) {
+#define ARGS (c, g, U, ind, s)
+  DGX_SWITCH(launch_fv_indicator)
+#undef ARGS
+}
+
+hipError_t launch_fv_switch(const Cfg& c, const Geo& g, double* U, double* dU, const int* etype_new, int* etype,
+                            hipStream_t s) {
+#define ARGS (c, g, U, dU, etype_new, etype, s)
+  DGX_SWITCH(launch_fv_switch)
+#undef ARGS
+}
+
+// New element types from the indicator: FV above hi, DG below lo, else unchanged.
+__global__ void k_fv_decide(int n, const double* __restrict__ ind, double lo, double hi, const int* __restrict__ et,
+                            int* __restrict__ et_new) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double x = ind[e];
+  et_new[e] = x > hi ? 1 : (x < lo ? 0 : et[e]);
+}
+
+// A side is an FV face if either of its elements is FV.
+__global__ void k_fv_side_flags(int n, const int* __restrict__ side_elem, const int* __restrict__ et,
+                                int* __restrict__ sidefv) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  sidefv[s] = (et[side_elem[2 * s]] | et[side_elem[2 * s + 1]]) ? 1 : 0;
+}
+
+hipError_t launch_fv_decide(int nElems, const double* ind, double lo, double hi, const int* etype, int* etype_new,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_fv_decide, dim3((nElems + 255) / 256), dim3(256), 0, s, nElems, ind, lo, hi, etype, etype_new);
+  return hipGetLastError();
+}
+
+hipError_t launch_fv_side_flags(int nSides, const int* side_elem, const int* etype, int* sidefv, hipStream_t s) {
+  hipLaunchKernelGGL(k_fv_side_flags, dim3((nSides + 255) / 256), dim3(256), 0, s, nSides, side_elem, etype, sidefv);
+  return hipGetLastError();
 }
 
 hipError_t launch_lift(const Cfg& c, int emit, const Geo& g, const Phys& p, const double* U, const double* Utr,

@@ -1,0 +1,42 @@
+// dgx_tile.hpp -- element-tile index helpers shared by the residual and FV
+// kernels: work-items per element, node and line indexing, the basis copy,
+// and the face-trace layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dgx_internal.hpp"
+
+namespace dgx {
+
+template <int N>
+struct Shape {
+  static constexpr int n1 = N + 1;
+  static constexpr int n2 = n1 * n1;
+  static constexpr int n3 = n2 * n1;
+  static constexpr int nth = ((n3 + 63) / 64) * 64;   // work-items per element (whole wavefronts)
+  static constexpr int nface = 6 * n2;                 // face nodes of one element
+};
+
+template <int N>
+__device__ __forceinline__ int nidx(int i, int j, int k) { return (k * (N + 1) + j) * (N + 1) + i; }
+
+// Volume node at position a along reference direction r, tangential face indices (pp, qq).
+template <int N>
+__device__ __forceinline__ int line_node(int r, int a, int pp, int qq) {
+  return r == 0 ? nidx<N>(a, pp, qq) : (r == 1 ? nidx<N>(pp, a, qq) : nidx<N>(pp, qq, a));
+}
+
+// Copy the basis into LDS (cooperatively).
+__device__ __forceinline__ void load_basis(DevBasis* dst, const DevBasis* src, int t, int nth) {
+  const double* s = reinterpret_cast<const double*>(src);
+  double* d = reinterpret_cast<double*>(dst);
+  constexpr int nd = sizeof(DevBasis) / sizeof(double);
+  for (int x = t; x < nd; x += nth) d[x] = s[x];
+}
+
+__device__ __forceinline__ size_t tr_index(int slot, int v, int nvar, int nSides, int side, int n2, int fi) {
+  return (((size_t)slot * nvar + v) * nSides + side) * n2 + fi;
+}
+
+}  // namespace dgx

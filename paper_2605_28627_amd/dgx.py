@@ -39,13 +39,14 @@ SYMBOLS = ["dg_create", "dg_destroy", "dg_last_error", "dg_lserk_coefficients", 
            "dg_upload_metrics", "dg_get_metrics", "dg_node_coords", "dg_sizes", "dg_workspace_bytes",
            "dg_workspace_bytes_adjoint", "dg_bind_workspace", "dg_init_state", "dg_rhs", "dg_lift", "dg_rk_step", "dg_adjoint_rhs", "dg_adjoint_rk_step",
            "dg_kinetic_energy", "dg_kinetic_energy_grad", "dg_timestep", "dg_check_state", "dg_profile",
-           "dg_profile_query"]
+           "dg_profile_query", "dg_fv_switch", "dg_fv_indicator", "dg_fv_switch_by_indicator", "dg_fv_mask"]
 
 
 class dg_config(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("nodes", ctypes.c_int), ("volume_form", ctypes.c_int),
                 ("physics", ctypes.c_int), ("riemann", ctypes.c_int), ("twopoint", ctypes.c_int),
                 ("precision", ctypes.c_int), ("integrator", ctypes.c_int), ("viscosity", ctypes.c_int),
+                ("fv", ctypes.c_int),
                 ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
                 ("Pr", ctypes.c_double), ("R", ctypes.c_double), ("Tref", ctypes.c_double), ("Ts", ctypes.c_double)]
 
@@ -85,6 +86,10 @@ _sig = {
     "dg_check_state": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
     "dg_profile_query": (ctypes.c_int, [_vp, ctypes.c_char_p, _dp, ctypes.POINTER(ctypes.c_long)]),
+    "dg_fv_switch": (ctypes.c_int, [_vp, _vp, _vp, _ip, _vp]),
+    "dg_fv_indicator": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "dg_fv_switch_by_indicator": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp]),
+    "dg_fv_mask": (ctypes.c_int, [_vp, _ip, _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_L, _name)
@@ -130,9 +135,9 @@ def _stream(stream):
 
 
 def make_config(N, nodes=1, volume_form=0, physics=0, riemann=0, twopoint=0, precision=0, integrator=0, viscosity=0,
-                gamma=1.4, mu=0.0, Pr=0.72, R=1.0, Tref=1.0, Ts=110.4 / 273.15):
-    return dg_config(N, nodes, volume_form, physics, riemann, twopoint, precision, integrator, viscosity, gamma, mu,
-                     Pr, R, Tref, Ts)
+                gamma=1.4, mu=0.0, Pr=0.72, R=1.0, Tref=1.0, Ts=110.4 / 273.15, fv=0):
+    return dg_config(N, nodes, volume_form, physics, riemann, twopoint, precision, integrator, viscosity, fv, gamma,
+                     mu, Pr, R, Tref, Ts)
 
 
 def dg_create(cfg: dg_config):
@@ -293,6 +298,33 @@ def dg_check_state(ctx, U, stream=None):
     if st not in (DG_OK, DG_ERR_NONPHYSICAL):
         _check(ctx, st)
     return st
+
+
+def dg_fv_switch(ctx, U, dU, mask, stream=None):
+    ne, _, _, n = dg_sizes(ctx)
+    m = np.ascontiguousarray(np.asarray(mask, dtype=np.int32).reshape(-1))
+    if m.size != ne:
+        raise ValueError(f"mask has {m.size} entries, expected {ne}")
+    _check(ctx, _L.dg_fv_switch(ctx, _dev(U, n, "U"), None if dU is None else _dev(dU, n, "dU"), _hi(m),
+                                _stream(stream)))
+
+
+def dg_fv_indicator(ctx, U, ind, stream=None):
+    ne, _, _, n = dg_sizes(ctx)
+    _check(ctx, _L.dg_fv_indicator(ctx, _dev(U, n, "U"), _dev(ind, ne, "ind"), _stream(stream)))
+
+
+def dg_fv_switch_by_indicator(ctx, U, dU, ind_lo, ind_hi, stream=None):
+    n = dg_sizes(ctx)[3]
+    _check(ctx, _L.dg_fv_switch_by_indicator(ctx, _dev(U, n, "U"), None if dU is None else _dev(dU, n, "dU"),
+                                             float(ind_lo), float(ind_hi), _stream(stream)))
+
+
+def dg_fv_mask(ctx, stream=None):
+    ne = dg_sizes(ctx)[0]
+    m = np.zeros(ne, dtype=np.int32)
+    _check(ctx, _L.dg_fv_mask(ctx, _hi(m), _stream(stream)))
+    return m
 
 
 def dg_profile(ctx, enable):

@@ -11,7 +11,7 @@ import torch
 from . import dgx
 
 CONFIG_KEYS = ("N", "nodes", "volume_form", "physics", "riemann", "twopoint", "precision", "integrator", "viscosity",
-               "gamma", "mu", "Pr", "R", "Tref", "Ts")
+               "gamma", "mu", "Pr", "R", "Tref", "Ts", "fv")
 
 
 def config_from_dict(d: dict) -> dgx.dg_config:
@@ -63,6 +63,21 @@ class DGSolver:
     @property
     def state_shape(self):
         return (5, self.nElems, self.n1, self.n1, self.n1)
+
+    # FV sub-cell shock capturing (contexts with fv=1)
+    def fv_switch(self, U: torch.Tensor, mask, dU: torch.Tensor | None = None):
+        dgx.dg_fv_switch(self.ctx, U, dU, mask)
+
+    def fv_indicator(self, U: torch.Tensor) -> torch.Tensor:
+        ind = torch.empty(self.nElems, dtype=torch.float64, device=self.device)
+        dgx.dg_fv_indicator(self.ctx, U, ind)
+        return ind
+
+    def fv_switch_by_indicator(self, U: torch.Tensor, ind_lo: float, ind_hi: float, dU: torch.Tensor | None = None):
+        dgx.dg_fv_switch_by_indicator(self.ctx, U, dU, ind_lo, ind_hi)
+
+    def fv_mask(self) -> np.ndarray:
+        return dgx.dg_fv_mask(self.ctx)
 
     def coords(self) -> np.ndarray:
         return dgx.dg_node_coords(self.ctx)

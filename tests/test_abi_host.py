@@ -56,6 +56,16 @@ def test_create_validates_config(dgx):
     # the split form runs on both node sets (entropy-stable hybridised form on Gauss nodes)
     for nodes in (0, 1):
         dgx.dg_destroy(dgx.dg_create(dgx.make_config(3, nodes=nodes, volume_form=1)))
+    # FV sub-cells: Euler, FP64, Rusanov, weak form or the Lobatto split form
+    for kw in [dict(nodes=0), dict(nodes=1), dict(nodes=1, volume_form=1)]:
+        dgx.dg_destroy(dgx.dg_create(dgx.make_config(3, fv=1, **kw)))
+    for kw in [dict(physics=1), dict(precision=1), dict(riemann=2), dict(nodes=0, volume_form=1)]:
+        with pytest.raises(dgx.DGError) as ei:
+            dgx.dg_create(dgx.make_config(3, fv=1, **kw))
+        assert ei.value.status == dgx.DG_ERR_UNSUPPORTED, kw
+    with pytest.raises(dgx.DGError) as ei:
+        dgx.dg_create(dgx.make_config(3, fv=2))
+    assert ei.value.status == dgx.DG_ERR_ARG
 
 
 def test_lserk_coefficients_match_oracle(dgx, orc):

@@ -1,0 +1,223 @@
+"""GPU parity of FV sub-cell shock capturing (FV elements, mixed DG/FV faces,
+Persson indicator, switching) against the oracle, through the C-ABI.
+
+* DG -> FV switching of a seeded state, then the residual with checkerboard,
+  all-FV and random element masks: LG and LGL, weak and split DG, N = 1..7,
+  curved and rotated meshes (oracle metrics uploaded): 1e-12 per variable;
+* three LSERK4(5) steps with a mask (the RK epilogues write the two-layer
+  traces of FV faces);
+* the indicator where it is above rounding level, the indicator-driven
+  switch (element types, converted U and dU) and the switch back;
+* free-stream preservation and conservation on the GPU's own residual;
+* the 64^3 N=3 free-stream workload with half the elements FV (checkerboard):
+  sampled elements against the oracle;
+* the adjoint refuses FV contexts; the FV calls refuse contexts without FV.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2605_28627_amd import inputs as I
+from tests.helpers import quad_weights3, rel_err_per_var
+
+pytestmark = pytest.mark.gpu
+PI = np.pi
+
+
+def _say(*a):
+    print("[gpu-fv]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def S(torch_cuda):
+    from paper_2605_28627_amd.solver import DGSolver
+    return DGSolver
+
+
+def _mask(kind, mesh, K, seed=0):
+    if kind == "all":
+        return np.ones(mesh.nElems, np.int32)
+    if kind == "random":
+        return np.random.default_rng(seed).integers(0, 2, mesh.nElems).astype(np.int32)
+    ex = np.arange(mesh.nElems) % K[0]
+    ey = (np.arange(mesh.nElems) // K[0]) % K[1]
+    ez = np.arange(mesh.nElems) // (K[0] * K[1])
+    return ((ex + ey + ez) % 2).astype(np.int32)
+
+
+CASES = [
+    # N, nodes, form, curved, rotate_seed, mask
+    (1, 0, 0, 0.0, 5, "checker"),
+    (2, 0, 0, 0.0, 5, "random"),
+    (3, 0, 0, 0.0, 7, "checker"),
+    (3, 1, 1, 0.1, 7, "all"),
+    (4, 1, 0, 0.1, 9, "random"),
+    (5, 1, 1, 0.1, 11, "checker"),
+    (6, 1, 0, 0.0, 4, "checker"),
+    (7, 1, 1, 0.0, 3, "random"),
+]
+
+
+def _setup(S, orc, case, K=(3, 2, 2), upload=True):
+    N, nodes, form, curved, rot, mk = case
+    mesh = I.box_mesh(K, (-PI,) * 3, (PI,) * 3, Ngeo=N if curved else 1, curved_amp=curved, rotate_seed=rot)
+    cfg = dict(N=N, nodes=nodes, form=form, physics=0, fv=1)
+    o = orc.Oracle(cfg, mesh)
+    s = S(cfg, mesh)
+    if upload:
+        _, J, Ja = o.geometry()
+        s.upload_metrics(Ja, 1.0 / J, o.face_normals())
+    return o, s, mesh, _mask(mk, mesh, K, seed=rot or 0)
+
+
+@pytest.mark.parametrize("case", CASES, ids=str)
+def test_switch_and_rhs_match_oracle(S, orc, case):
+    _say("rhs", case)
+    o, s, mesh, mask = _setup(S, orc, case)
+    U = I.smooth_random_state(o.coords(), 61, amp=0.2)
+    Uo, _ = o.fv_switch(U, None, mask)
+    Ug = s.init_state(U)
+    s.fv_switch(Ug, mask)
+    assert np.array_equal(s.fv_mask(), mask)
+    err_sw = rel_err_per_var(Ug.cpu().numpy(), Uo)
+    assert np.all(err_sw < 1e-13), err_sw
+    R_orc = o.rhs(Uo)
+    R_gpu = s.rhs(Ug).cpu().numpy()
+    err = rel_err_per_var(R_gpu, R_orc)
+    _say("rhs", case, "rel err", err)
+    assert np.all(err < 1e-12), err
+    assert np.array_equal(R_gpu, s.rhs(Ug).cpu().numpy())
+
+
+@pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[5]], ids=str)
+def test_rk_steps_match_oracle(S, orc, case):
+    _say("rk", case)
+    o, s, mesh, mask = _setup(S, orc, case)
+    U = I.smooth_random_state(o.coords(), 62, amp=0.2)
+    dt = o.timestep(U, 0.9)
+    Uo, _ = o.fv_switch(U, None, mask)
+    U_orc = o.lserk(Uo, 3, dt)
+    Ug = s.init_state(U)
+    s.fv_switch(Ug, mask)
+    s.rk_step(Ug, s.empty_state(), dt, 3)
+    err = rel_err_per_var(Ug.cpu().numpy() - Uo, U_orc - Uo)
+    _say("rk", case, err)
+    assert np.all(err < 1e-11), err
+
+
+@pytest.mark.parametrize("N,nodes", [(3, 1), (4, 0), (6, 1)])
+def test_indicator_and_switch_by_indicator(S, orc, torch_cuda, N, nodes):
+    K = (4, 2, 2)
+    mesh = I.box_mesh(K, (0.0,) * 3, (4.0,) * 3)
+    cfg = dict(N=N, nodes=nodes, form=0, physics=0, fv=1)
+    o, s = orc.Oracle(cfg, mesh), S(cfg, mesh)
+    _, J, Ja = o.geometry()
+    s.upload_metrics(Ja, 1.0 / J, o.face_normals())
+    xyz = o.coords()
+    rho = 1.0 + 0.1 * np.sin(0.5 * PI * xyz[0]) + 0.05 * np.cos(PI * xyz[1])
+    rho = np.where(xyz[0] > 2.5, rho + 0.5, rho)
+    U = I.prim_to_cons(rho, 0 * rho + 0.2, 0 * rho, 0 * rho, 0 * rho + 1.0, 1.4)
+    ind_o = o.indicator(U)
+    Ug = s.init_state(U)
+    ind_g = s.fv_indicator(Ug).cpu().numpy()
+    sig = ind_o > -12
+    assert sig.sum() >= mesh.nElems // 4
+    assert np.abs(ind_g[sig] - ind_o[sig]).max() < 1e-9, (ind_g, ind_o)
+    lo, hi = -5.0, -3.5          # jump elements near -3, smooth ones near -6
+    want = np.where(ind_o > hi, 1, 0).astype(np.int32)
+    assert 0 < want.sum() < mesh.nElems
+    dU = np.random.default_rng(4).normal(size=U.shape)
+    dUg = s.to_device(dU)
+    s.fv_switch_by_indicator(Ug, lo, hi, dU=dUg)
+    assert np.array_equal(s.fv_mask(), want)
+    Uo, dUo = o.fv_switch(U, dU, want)
+    assert np.all(rel_err_per_var(Ug.cpu().numpy(), Uo) < 1e-13)
+    assert np.all(rel_err_per_var(dUg.cpu().numpy(), dUo) < 1e-12)
+    # the indicator of the switched state is the same (FV elements through their DG reconstruction)
+    ind2 = s.fv_indicator(Ug).cpu().numpy()
+    assert np.abs(ind2[sig] - ind_o[sig]).max() < 1e-8
+    # and the mask switch back restores the DG state
+    s.fv_switch(Ug, np.zeros(mesh.nElems, np.int32), dU=dUg)
+    assert np.all(rel_err_per_var(Ug.cpu().numpy(), U) < 1e-12)
+    assert np.all(rel_err_per_var(dUg.cpu().numpy(), dU) < 1e-11)
+
+
+@pytest.mark.parametrize("N,form", [(3, 0), (5, 1)])
+def test_free_stream_and_conservation(S, orc, N, form):
+    K = (3, 3, 2)
+    mesh = I.box_mesh(K, (-PI,) * 3, (PI,) * 3, Ngeo=N, curved_amp=0.1)
+    cfg = dict(N=N, nodes=1, form=form, physics=0, fv=1)
+    o, s = orc.Oracle(cfg, mesh), S(cfg, mesh)
+    mask = _mask("checker", mesh, K)
+    xyz, Ja, sJ, _ = s.metrics()
+    Uc = np.zeros(s.state_shape)
+    Uc[:] = I.prim_to_cons(np.ones(1), np.full(1, 0.1), np.full(1, 0.2), np.full(1, -0.1), np.full(1, 71.43), 1.4)[
+        :, 0, None, None, None, None]
+    Ug = s.init_state(Uc)
+    s.fv_switch(Ug, mask)
+    R = s.rhs(Ug).cpu().numpy()
+    fmax = np.abs(orc.flux_adv(Uc[:, 0, 0, 0, 0], np.ones(3))).max()
+    b = orc.basis(N, 1)
+    Dhat = (b["w"][:, None] / b["w"][None, :]) * b["D"]
+    scale = 3 * fmax * np.abs(Ja).max() * max(np.abs(Dhat).sum(0).max(), N + 1) * sJ.max()
+    _say("fsp", N, np.abs(R).max() / scale)
+    assert np.abs(R).max() < 1e-13 * scale
+    s.fv_switch(Ug, np.zeros(mesh.nElems, np.int32))
+    Ug = s.init_state(I.smooth_random_state(xyz, 63, amp=0.2))
+    s.fv_switch(Ug, mask)
+    R = s.rhs(Ug).cpu().numpy()
+    V, _, _ = o.fv_geometry()
+    Wt = np.where(mask[:, None, None, None] == 1, V, quad_weights3(b["w"]) / sJ)
+    for v in range(5):
+        assert abs((Wt * R[v]).sum()) < 1e-13 * (Wt * np.abs(R[v])).sum()
+
+
+def test_half_fv_workload_full_size_sampled(S, orc, torch_cuda):
+    """Euler, N=3 LG weak form, 64^3 (16.78 M DOF), half the elements FV in a
+    checkerboard (the paper's 50 % FV row): sampled elements against the oracle."""
+    name = "euler_weak_lg_n3_64x64x64"
+    w = I.WORKLOADS[name]
+    K = tuple(w["K"])
+    mesh = I.workload_mesh(name)
+    cfg = dict(N=3, nodes=0, form=0, physics=0, fv=1)
+    _say("full size", name)
+    o = orc.Oracle(cfg, mesh)
+    xyz, J, Ja = o.geometry()
+    s = S(cfg, mesh)
+    s.upload_metrics(Ja, 1.0 / J, o.face_normals())
+    mask = _mask("checker", mesh, K)
+    U = I.random_state(xyz.shape[1:], 64, rho=(0.9, 1.1), vel=0.2, p=(0.9, 1.1))
+    Ug = s.init_state(U)
+    s.fv_switch(Ug, mask)
+    o.fv_set_mask(mask)
+    sample = [0, 1, 63, 64, 4095, 4096, 130000, 262143]
+    Um = Ug.cpu().numpy()
+    R_gpu = s.rhs(Ug).cpu().numpy()[:, sample]
+    R_orc = o.rhs_elems(Um, sample)
+    err = rel_err_per_var(R_gpu, R_orc)
+    _say("full size", err)
+    assert np.all(err < 1e-12), err
+
+
+def test_refusals(S, orc, torch_cuda):
+    from paper_2605_28627_amd import dgx
+    o, s, mesh, mask = _setup(S, orc, CASES[2])
+    U = s.init_state(I.smooth_random_state(o.coords(), 65, amp=0.2))
+    with pytest.raises(dgx.DGError) as ei:
+        s.adjoint_rhs(U, torch_cuda.ones_like(U))
+    assert ei.value.status == dgx.DG_ERR_UNSUPPORTED
+    mesh2 = I.box_mesh((2, 2, 2), (-PI,) * 3, (PI,) * 3)
+    s2 = S(dict(N=3, nodes=0, form=0, physics=0), mesh2)
+    U2 = s2.init_state(I.smooth_random_state(s2.coords(), 66, amp=0.2))
+    with pytest.raises(dgx.DGError) as ei:
+        s2.fv_switch(U2, np.zeros(8, np.int32))
+    assert ei.value.status == dgx.DG_ERR_STATE
