@@ -15,7 +15,9 @@ count, FP64 FLOPs from the committed rocprofv3 counters) and the serial FP64
 oracle timed on a bounded sample of the same workload on the host.
 
 Other workloads (--workload, --K, --state) and repetitions (--reps, median)
-serve the per-configuration measurements.
+serve the per-configuration measurements; --fv checker/all runs an Euler
+workload with half or all of its elements on FV sub-cells (shock
+capturing; the paper's 50 % FV row uses a checkerboard).
 """
 from __future__ import annotations
 
@@ -32,7 +34,8 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "ns_split_lgl_n7_16x16x16_tgv"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-KERNEL_SOURCES = ("dgx_kernels.hpp", "dgx_pointwise.hpp", "dgx_internal.hpp", "dgx_inst.hip")
+KERNEL_SOURCES = ("dgx_kernels.hpp", "dgx_pointwise.hpp", "dgx_internal.hpp", "dgx_inst.hip", "dgx_tile.hpp",
+                  "dgx_fv.hpp")
 
 
 def _log(*a):
@@ -59,6 +62,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--fv", default="none", choices=["none", "checker", "all"],
+                    help="FV sub-cell elements (Euler workloads): none, a checkerboard half, or all")
     ap.add_argument("--adjoint-steps", type=int, default=4)
     ap.add_argument("--checkpoint-every", type=int, default=None)
     ap.add_argument("--cpu-sample-elems", type=int, default=4096)
@@ -139,7 +144,7 @@ def workload_cfg(name):
 
 
 def volume_kernel_name(w, precision=0, roe=0):
-    return f"void dgx::k_volume<{w['N']}, {w['nodes']}, {w['form']}, {w['physics']}, {precision}, 1, {roe}>"
+    return f"void dgx::k_volume<{w['N']}, {w['nodes']}, {w['form']}, {w['physics']}, {precision}, 1, {roe}, 0>"
 
 
 def volume_kernel_bytes_per_dof(w, precision=0):
@@ -161,6 +166,31 @@ def volume_kernel_bytes_per_dof(w, precision=0):
     if w["physics"] == 1:
         reads += (12 + fpn * 8) * (0.5 if precision == 1 else 1.0)
     return 8.0 * (reads + writes)
+
+
+def fv_kernel_bytes_per_dof(w):
+    """Compulsory HBM bytes of one RK-stage launch of the FV kernel, per sub-cell.
+
+    Reads: U (5), the sub-cell volume (1), dU (5, 4 on average over the five
+    stages), the interior sub-face vectors (9 N / (N+1) per sub-cell), and
+    per element face node the sub-face vector (3) and both sides' two-layer
+    traces (2 x 10).  Writes: dU (5), U (5) and the element's own two-layer
+    traces (10 per face node).  8 bytes each.
+    """
+    n1 = w["N"] + 1
+    fpn = 6 * n1 * n1 / n1 ** 3
+    reads = 5 + 1 + 4 + 9 * w["N"] / n1 + fpn * (3 + 20)
+    writes = 5 + 5 + fpn * 10
+    return 8.0 * (reads + writes)
+
+
+def fv_mask(kind, K):
+    import numpy as np
+    ne = K[0] * K[1] * K[2]
+    if kind == "all":
+        return np.ones(ne, np.int32)
+    e = np.arange(ne)
+    return ((e % K[0] + (e // K[0]) % K[1] + e // (K[0] * K[1])) % 2).astype(np.int32)
 
 
 def main():
@@ -186,6 +216,12 @@ def main():
     if args.viscosity == "sutherland":
         # reference temperature of the initial state: T0 = p0 / (rho0 R) at Ma 0.1, rho0 = U0 = 1
         cfg.update(viscosity=1, Tref=1.0 / (1.4 * 0.01), Ts=110.4 / 273.15)
+    if args.fv != "none":
+        if w["physics"] != 0:
+            raise SystemExit("--fv needs an Euler workload (FV sub-cells cover Euler)")
+        cfg["fv"] = 1
+        args.no_fp32 = True      # FV contexts are FP64
+        args.no_adjoint = True   # the adjoint does not cover FV sub-cells
     nst = len(dgx.dg_rk_coefficients(args.integrator)[0])
     K = tuple(int(x) for x in args.K.split(",")) if args.K else tuple(w["K"])
     _log("mesh", args.workload, K)
@@ -196,6 +232,11 @@ def main():
     xyz = s.coords()
     U0 = s.init_state(I.workload_state(args.workload, xyz, state=args.state))
     dt = s.timestep(U0, 0.9)
+    nfv = 0
+    if args.fv != "none":
+        mask = fv_mask(args.fv, K)
+        s.fv_switch(U0, mask)
+        nfv = int(mask.sum())
 
     def timed(solver, profile, keep=None):
         """args.reps repetitions of (warmup, then args.steps timed steps) from U0;
@@ -217,7 +258,7 @@ def main():
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             if events:
-                for fam in ("trace", "lift", "volume", "other"):
+                for fam in ("trace", "lift", "volume", "fv", "other"):
                     prof[fam] = dgx.dg_profile_query(solver.ctx, fam)
                 dgx.dg_profile(solver.ctx, 0)
             if solver.check_state(U) != 0:
@@ -233,12 +274,21 @@ def main():
     vol_ms, vol_n = prof["volume"]
     vol_avg_s = vol_ms * 1e-3 / max(vol_n, 1)
     lift_ms, lift_n = prof["lift"]
-    bytes_launch = volume_kernel_bytes_per_dof(w) * dof
+    npe = (w["N"] + 1) ** 3
+    bytes_launch = volume_kernel_bytes_per_dof(w) * (dof - nfv * npe)
+    kfam = "k_volume"
+    if nfv:
+        # the roofline of the dominant family: DG elements (k_volume) or FV elements (k_fv)
+        fv_ms, fv_n = prof["fv"]
+        fv_avg_s = fv_ms * 1e-3 / max(fv_n, 1)
+        if fv_avg_s > vol_avg_s:
+            kfam, vol_avg_s, vol_n = "k_fv", fv_avg_s, fv_n
+            bytes_launch = fv_kernel_bytes_per_dof(w) * nfv * npe
     achieved_gbs = bytes_launch / vol_avg_s / 1e9
     kname = volume_kernel_name(w, 0, 1 if args.riemann == "roe" else 0)
     default_run = (args.K is None and args.state is None and args.integrator == 0 and args.riemann == "rusanov"
                    and args.viscosity == "constant")
-    counters = profile_counters(args.workload, kname) if default_run else None
+    counters = profile_counters(args.workload, kname) if default_run and not nfv else None
     form = ("split form" if w["form"] else "weak form") + (", Navier-Stokes" if w["physics"] else ", Euler")
 
     result = {
@@ -263,7 +313,8 @@ def main():
                    "volume_form": "split" if w["form"] else "weak", "curved": bool(w["curved"]), "dt": dt,
                    "integrator": ("LSERK4(5)", "LSERK4-14")[args.integrator], "stages_per_step": nst,
                    "riemann": args.riemann, "viscosity": args.viscosity,
-                   "state": args.state or w["state"]},
+                   "state": args.state or w["state"], "fv_elements": nfv,
+                   "fv_mask": args.fv},
         "dof_updates_per_s": 1.0 / pid64,
         "simulated_time_per_wall_s": dt * args.steps / t64,
         "reps": args.reps,
@@ -271,7 +322,8 @@ def main():
         "kernels_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in prof.items()},
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_volume ({form}, RK stage)",
+            "kernel": (f"k_volume ({form}, RK stage)" if kfam == "k_volume" else
+                       "k_fv (FV sub-cell elements, RK stage)"),
             "achieved": achieved_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -361,14 +413,18 @@ def adjoint_cost(cfg, mesh, dev, U0, dt, args):
             "note": "backward includes the recomputation of step and stage states"}
 
 
-def _oracle_sample_time(workload, K, state, nel, repeats):
+def _oracle_sample_time(workload, K, state, nel, repeats, fv="none"):
     """Seconds for `repeats` oracle residuals of elements 0..nel-1 of a workload
     (run in a process of its own for the all-cores figure)."""
     from oracle import oracle as O
     from paper_2605_28627_amd import inputs as I
     _, cfg = workload_cfg(workload)
     mesh = I.workload_mesh(workload, K=K)
+    if fv != "none":
+        cfg["fv"] = 1
     o = O.Oracle(cfg, mesh)
+    if fv != "none":
+        o.fv_set_mask(fv_mask(fv, K or tuple(I.WORKLOADS[workload]["K"])))
     U = I.workload_state(workload, o.coords(), state=state)
     el = list(range(nel))
     t0 = time.perf_counter()
@@ -384,6 +440,10 @@ def cpu_baseline(args, cfg, mesh, xyz, pid_gpu):
     from oracle import oracle as O
     from paper_2605_28627_amd import inputs as I
     o = O.Oracle(cfg, mesh)
+    if args.fv != "none":
+        # element types as on the GPU; the state's values do not change the work
+        K = tuple(int(x) for x in args.K.split(",")) if args.K else tuple(I.WORKLOADS[args.workload]["K"])
+        o.fv_set_mask(fv_mask(args.fv, K))
     U = I.workload_state(args.workload, xyz, state=args.state)
     nel = min(args.cpu_sample_elems, mesh.nElems)
     el = list(range(nel))
@@ -403,7 +463,7 @@ def cpu_baseline(args, cfg, mesh, xyz, pid_gpu):
         P = args.cpu_procs
         with mp.get_context("spawn").Pool(P) as pool:
             t0 = time.perf_counter()
-            ts = pool.starmap(_oracle_sample_time, [(args.workload, K, args.state, nel, args.cpu_repeats)] * P)
+            ts = pool.starmap(_oracle_sample_time, [(args.workload, K, args.state, nel, args.cpu_repeats, args.fv)] * P)
             wall = time.perf_counter() - t0
         pid_all = max(ts) / (P * args.cpu_repeats * nel * npe)
         out["all_cores"] = {"procs": P, "pid_aggregate": pid_all, "dof_updates_per_s": 1.0 / pid_all,

@@ -480,14 +480,14 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
     int p = pp, qm = qq;
     if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
     const int fi = qm * n1 + p;
-    const double sgn = slot ? -1.0 : 1.0;
     if constexpr (FV) {
       if (G.sidefv[side]) {
         // FV face: the sub-face flux, outward, into the staging area (taken back below)
         double F[5];
         fv_face_flux(Utr, G.fvSb, nS, n2, side, fi, P, F);
+        const double so = slot ? -1.0 : 1.0;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sm[(f * 5 + v) * n2 + rr] = sgn * F[v];
+        for (int v = 0; v < 5; ++v) sm[(f * 5 + v) * n2 + rr] = so * F[v];
         return;
       }
     }
@@ -523,6 +523,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
 #pragma unroll
         for (int v = 0; v < 4; ++v) Phi[1 + v] -= 0.5 * ld_visc<PREC>(gvf, tr_index(sd, v, 4, nS, side, n2, fi));
     }
+    const double sgn = slot ? -1.0 : 1.0;
 #pragma unroll
     for (int v = 0; v < 5; ++v) sphi[(fs * 5 + v) * n2 + rr] = sgn * Phi[v];
   };
