@@ -38,19 +38,19 @@ __device__ __forceinline__ void cons_to_prim5(const double U[5], double gm1, dou
 }
 
 // Rusanov flux F(WL, WR).S through the (not normalised) area vector S, from
-// primitive states.
-__device__ inline void rusanov_prim(const double WL[5], const double WR[5], const double S[3], double gm1, double gamma,
+// primitive states: the central part with S, and the dissipation
+// max(|u_L.S| + c_L |S|, |u_R.S| + c_R |S|)/2 (the largest wave speed normal
+// to the face times the face area) times the jump of U.
+__device__ inline void rusanov_prim(const double WL[5], const double WR[5], const double S[3], const Phys& P,
                                     double F[5]) {
   const double sA = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
-  const double inv = 1.0 / sA;
-  const double nh[3] = {S[0] * inv, S[1] * inv, S[2] * inv};
   double UL[5], UR[5];
   const double kL = WL[1] * WL[1] + WL[2] * WL[2] + WL[3] * WL[3];
   const double kR = WR[1] * WR[1] + WR[2] * WR[2] + WR[3] * WR[3];
   UL[0] = WL[0]; UL[1] = WL[0] * WL[1]; UL[2] = WL[0] * WL[2]; UL[3] = WL[0] * WL[3];
-  UL[4] = WL[4] / gm1 + 0.5 * WL[0] * kL;
+  UL[4] = WL[4] * P.igm1 + 0.5 * WL[0] * kL;
   UR[0] = WR[0]; UR[1] = WR[0] * WR[1]; UR[2] = WR[0] * WR[2]; UR[3] = WR[0] * WR[3];
-  UR[4] = WR[4] / gm1 + 0.5 * WR[0] * kR;
+  UR[4] = WR[4] * P.igm1 + 0.5 * WR[0] * kR;
   const double vL = WL[1] * S[0] + WL[2] * S[1] + WL[3] * S[2];
   const double vR = WR[1] * S[0] + WR[2] * S[1] + WR[3] * S[2];
   double FL[5], FR[5];
@@ -58,35 +58,41 @@ __device__ inline void rusanov_prim(const double WL[5], const double WR[5], cons
 #pragma unroll
   for (int d = 0; d < 3; ++d) { FL[1 + d] = UL[1 + d] * vL + WL[4] * S[d]; FR[1 + d] = UR[1 + d] * vR + WR[4] * S[d]; }
   FL[4] = (UL[4] + WL[4]) * vL; FR[4] = (UR[4] + WR[4]) * vR;
-  const double cL = sqrt(gamma * WL[4] / WL[0]), cR = sqrt(gamma * WR[4] / WR[0]);
-  const double uL = WL[1] * nh[0] + WL[2] * nh[1] + WL[3] * nh[2];
-  const double uR = WR[1] * nh[0] + WR[2] * nh[1] + WR[3] * nh[2];
-  const double lL = fabs(uL) + cL, lR = fabs(uR) + cR;
-  const double hs = 0.5 * ((lL >= lR ? lL : lR) * sA);
+  const double cL = sqrt(P.gamma * WL[4] / WL[0]), cR = sqrt(P.gamma * WR[4] / WR[0]);
+  const double lL = fabs(vL) + cL * sA, lR = fabs(vR) + cR * sA;
+  const double hs = 0.5 * (lL >= lR ? lL : lR);
 #pragma unroll
   for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - hs * (UR[v] - UL[v]);
 }
 
-// Flux through sub-face fi of an FV side (master-outward, master indexing),
-// from both sides' two layers: each side's face value is its first layer plus
-// half its limited outward slope, the other side's first layer as ghost.
-__device__ inline void fv_face_flux(const double* __restrict__ Utr, const double* __restrict__ fvSb, int nS, int n2,
-                                    int side, int fi, const Phys& P, double F[5]) {
-  double W0[2][5], Wf[2][5];
+// Face values of both sides of sub-face fi of an FV side (master first,
+// master indexing) from their two layers: each side's first layer plus half
+// its limited outward slope, the other side's first layer as ghost; and the
+// master-outward sub-face vector S.
+__device__ inline void fv_face_states(const double* __restrict__ Utr, const double* __restrict__ fvSb, int nS, int n2,
+                                      int side, int fi, double W0f[5], double W1f[5], double S[3]) {
+  double W0[2][5];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
     for (int v = 0; v < 5; ++v) W0[m][v] = Utr[tr_index(m, v, kTrFV, nS, side, n2, fi)];
 #pragma unroll
-  for (int m = 0; m < 2; ++m)
+  for (int v = 0; v < 5; ++v) {
+    const double w10 = Utr[tr_index(0, 5 + v, kTrFV, nS, side, n2, fi)];
+    const double w11 = Utr[tr_index(1, 5 + v, kTrFV, nS, side, n2, fi)];
+    W0f[v] = W0[0][v] + 0.5 * minmod(W0[0][v] - w10, W0[1][v] - W0[0][v]);
+    W1f[v] = W0[1][v] + 0.5 * minmod(W0[1][v] - w11, W0[0][v] - W0[1][v]);
+  }
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const double w1 = Utr[tr_index(m, 5 + v, kTrFV, nS, side, n2, fi)];
-      Wf[m][v] = W0[m][v] + 0.5 * minmod(W0[m][v] - w1, W0[1 - m][v] - W0[m][v]);
-    }
-  const double S[3] = {fvSb[((size_t)0 * nS + side) * n2 + fi], fvSb[((size_t)1 * nS + side) * n2 + fi],
-                       fvSb[((size_t)2 * nS + side) * n2 + fi]};
-  rusanov_prim(Wf[0], Wf[1], S, P.gm1, P.gamma, F);
+  for (int c = 0; c < 3; ++c) S[c] = fvSb[((size_t)c * nS + side) * n2 + fi];
+}
+
+// Flux through sub-face fi of an FV side, along the master normal.
+__device__ inline void fv_face_flux(const double* __restrict__ Utr, const double* __restrict__ fvSb, int nS, int n2,
+                                    int side, int fi, const Phys& P, double F[5]) {
+  double W0f[5], W1f[5], S[3];
+  fv_face_states(Utr, fvSb, nS, n2, side, fi, W0f, W1f, S);
+  rusanov_prim(W0f, W1f, S, P, F);
 }
 
 // a <- M_i a, M_j, M_k in turn (tensor product of the n1 x n1 matrix M along
@@ -249,6 +255,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_fv(Geo G, Phys P, const doubl
   __shared__ double sw[5 * n3];
   __shared__ double ssl[5 * n3];
   __shared__ double sfl[5 * n3];
+  __shared__ double sfe[3 * 5 * n2];   // outward fluxes through the upper element faces 1, 3, 5
   const bool act = t < n3;
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   const int idx[3] = {i, j, k};
@@ -258,6 +265,23 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_fv(Geo G, Phys P, const doubl
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
     V = G.fvV[(size_t)e * n3 + t];
+  }
+  // Fluxes through the three upper element faces (their loads overlap the
+  // state's).  The lower element face of each line rides along with the
+  // interior sub-faces below, so every direction takes one flux pass.
+  for (int ft = t; ft < 3 * n2; ft += S::nth) {
+    const int r = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
+    const int info = G.efc[e * 6 + 2 * r + 1];
+    const int side = efc_side(info), slot = efc_slot(info);
+    int p = pp, qm = qq;
+    if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+    double F[5];
+    fv_face_flux(Utr, G.fvSb, nS, n2, side, qm * n1 + p, P, F);
+    const double sg = slot ? -1.0 : 1.0;   // outward
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sfe[(r * 5 + v) * n2 + rr] = sg * F[v];
+  }
+  if (act) {
     cons_to_prim5(u, P.gm1, W);
 #pragma unroll
     for (int v = 0; v < 5; ++v) sw[v * n3 + t] = W[v];
@@ -290,37 +314,42 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_fv(Geo G, Phys P, const doubl
     }
     __syncthreads();
     if (act) {
-      if (a < N) {
-        double WL[5], WR[5];
+      // the flux through the lower face of sub-cell a: the interior sub-face
+      // (a-1 | a) along +xi_r, or for a = 0 the element face (master-outward)
+      double WL[5], WR[5], Sv[3];
+      if (a > 0) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          WL[v] = W[v] + 0.5 * ssl[v * n3 + t];
-          WR[v] = sw[v * n3 + t + str] - 0.5 * ssl[v * n3 + t + str];
+          WL[v] = sw[v * n3 + t - str] + 0.5 * ssl[v * n3 + t - str];
+          WR[v] = W[v] - 0.5 * ssl[v * n3 + t];
         }
-        const double Sv[3] = {G.fvS[(((size_t)(3 * r + 0) * nE + e) * N + a) * n2 + rr],
-                              G.fvS[(((size_t)(3 * r + 1) * nE + e) * N + a) * n2 + rr],
-                              G.fvS[(((size_t)(3 * r + 2) * nE + e) * N + a) * n2 + rr]};
-        double F[5];
-        rusanov_prim(WL, WR, Sv, P.gm1, P.gamma, F);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) { sfl[v * n3 + t] = F[v]; acc[v] -= F[v]; }
+        for (int c = 0; c < 3; ++c) Sv[c] = G.fvS[(((size_t)(3 * r + c) * nE + e) * N + a - 1) * n2 + rr];
+      } else {
+        fv_face_states(Utr, G.fvSb, nS, n2, side[0], fi[0], WL, WR, Sv);
       }
+      double F[5];
+      rusanov_prim(WL, WR, Sv, P, F);
+      if (a > 0) {
 #pragma unroll
-      for (int end = 0; end < 2; ++end) {
-        if (a != (end ? N : 0)) continue;
-        double F[5];
-        fv_face_flux(Utr, G.fvSb, nS, n2, side[end], fi[end], P, F);
-        const double sg = slot[end] ? -1.0 : 1.0;   // outward
+        for (int v = 0; v < 5; ++v) { sfl[v * n3 + t] = F[v]; acc[v] += F[v]; }
+      } else {
+        const double sg = slot[0] ? -1.0 : 1.0;   // outward
 #pragma unroll
         for (int v = 0; v < 5; ++v) acc[v] -= sg * F[v];
       }
     }
     __syncthreads();
-    if (act && a > 0) {
+    if (act) {
+      if (a < N) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) acc[v] += sfl[v * n3 + t - str];
+        for (int v = 0; v < 5; ++v) acc[v] -= sfl[v * n3 + t + str];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v] -= sfe[(r * 5 + v) * n2 + rr];
+      }
     }
-    __syncthreads();
+    // (no barrier: the next direction writes sfl only after its slope barrier)
   }
   double Unew[5];
   if (act) {

@@ -355,7 +355,7 @@ dg_status dg_create(const dg_config* cfg, dg_ctx** out) {
   if (!x) return fail(nullptr, DG_ERR_NOMEM, "dg_create: host allocation");
   x->cfg = c;
   x->N = c.N; x->n1 = c.N + 1; x->n2 = x->n1 * x->n1; x->n3 = x->n2 * x->n1;
-  x->phys.gamma = c.gamma; x->phys.gm1 = c.gamma - 1.0; x->phys.mu = c.mu;
+  x->phys.gamma = c.gamma; x->phys.gm1 = c.gamma - 1.0; x->phys.igm1 = 1.0 / (c.gamma - 1.0); x->phys.mu = c.mu;
   x->phys.lam = c.mu * c.gamma * c.R / ((c.gamma - 1.0) * c.Pr);
   x->phys.R = c.R; x->phys.Rinv = 1.0 / c.R; x->phys.Pr = c.Pr;
   x->phys.riemann = c.riemann; x->phys.twopoint = c.twopoint;

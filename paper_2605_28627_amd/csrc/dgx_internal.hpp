@@ -44,6 +44,7 @@ __host__ __device__ inline void orient_to_master(int o, int N, int pp, int qq, i
 // Physical constants and switches seen by the kernels.
 struct Phys {
   double gamma, gm1, mu, lam, R, Rinv, Pr;  // lam = mu gamma R / ((gamma-1) Pr): heat conductivity
+  double igm1;                          // 1 / (gamma - 1)
   double kappa;                         // gamma R / ((gamma-1) Pr): conductivity over viscosity
   double Tref, Ts;                      // Sutherland's law: reference temperature, S / Tref
   int riemann;                          // 0 Rusanov, 1 central part only, 2 Roe (Harten-Hyman fix)

@@ -8,7 +8,7 @@ using namespace dgx;
 static Phys make_phys(const double* c) {
   // c = {gamma, mu, Pr, R, riemann, twopoint, viscosity law, Tref, Ts}
   Phys P{};
-  P.gamma = c[0]; P.gm1 = c[0] - 1.0; P.mu = c[1]; P.Pr = c[2]; P.R = c[3]; P.Rinv = 1.0 / c[3];
+  P.gamma = c[0]; P.gm1 = c[0] - 1.0; P.igm1 = 1.0 / (c[0] - 1.0); P.mu = c[1]; P.Pr = c[2]; P.R = c[3]; P.Rinv = 1.0 / c[3];
   P.lam = c[1] * c[0] * c[3] / ((c[0] - 1.0) * c[2]);
   P.kappa = c[0] * c[3] / ((c[0] - 1.0) * c[2]);
   P.riemann = (int)c[4]; P.twopoint = (int)c[5];
