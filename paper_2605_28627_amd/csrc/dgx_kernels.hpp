@@ -414,7 +414,11 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   // Gauss-node split form: the line sums of the face coupling go through LDS
   // (10 values per node) unless every line lies inside a wavefront
   constexpr bool kEsAllShfl = kSymLines && n1 == 4;
-  constexpr int SZ_SPLIT = (8 + 3 + NV + (ES && !kEsAllShfl ? 10 : 0)) * n3;   // aux + Ja^r + G~^r (+ face coupling)
+  // split form, n1 = 4: the lines of all three directions lie inside the
+  // wavefront, and the D-hat sweep of G~^r reads the line's values by shuffles
+  // (no LDS staging: more elements share a CU)
+  constexpr bool kGvShfl = FORM == 1 && kSymLines && n1 == 4;
+  constexpr int SZ_SPLIT = (8 + 3 + (kGvShfl ? 0 : NV) + (ES && !kEsAllShfl ? 10 : 0)) * n3;   // aux + Ja^r (+ G~^r) (+ face coupling)
   constexpr int SZ_WEAK = 5 * n3;                                    // F~^r
   constexpr int SZ_V = FORM == 1 ? SZ_SPLIT : SZ_WEAK;
   constexpr int SZ0 = SZ_V > 5 * n3 ? SZ_V : 5 * n3;                 // also holds the new state (Gauss traces)
@@ -578,7 +582,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
       if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) sja[c * n3 + t] = jr[c];
-        if constexpr (PHYS == 1) {
+        if constexpr (PHYS == 1 && !kGvShfl) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) sgv[v * n3 + t] = gv[v];
         }
@@ -623,17 +627,23 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           // -DS[a+d][a] F to the lane of a+d, receiving the share of the pair
           // (a-d, a) in turn.  The pair at distance n1/2 is met from both ends
           // and each lane keeps its own share.
+          const int lane = t & 63;
+          const int str = r == 0 ? 1 : (r == 1 ? n1 : n2);
           if constexpr (PHYS == 1) {
             // viscous part in weak form: acc -= Dhat[a][l] G~^r_l
             for (int l = 0; l < n1; ++l) {
-              const int tl = line_node<N>(r, l, pp, qq);
               const double c = sb.Dhat[a * n1 + l];
+              if constexpr (kGvShfl) {
+                const int src = lane + (l - a) * str;
 #pragma unroll
-              for (int v = 0; v < 4; ++v) acc[1 + v] -= c * sgv[v * n3 + tl];
+                for (int v = 0; v < 4; ++v) acc[1 + v] -= c * __shfl(gv[v], src);
+              } else {
+                const int tl = line_node<N>(r, l, pp, qq);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[1 + v] -= c * sgv[v * n3 + tl];
+              }
             }
           }
-          const int lane = t & 63;
-          const int str = r == 0 ? 1 : (r == 1 ? n1 : n2);
 #pragma unroll 1
           for (int d = 1; d <= n1 / 2; ++d) {
             const int b = (a + d) & (n1 - 1);
@@ -672,7 +682,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           // interpolated to the end f of this line; l_f(a) G_f is staged for
           // the line sums S_f = sum_l l_f(l) G_f(l).
           // The surface term of this direction's two faces is applied here too.
-          double* shy = sm + (11 + NV) * n3;
+          double* shy = sm + (11 + (kGvShfl ? 0 : NV)) * n3;
           const int rr = qq * n1 + pp;
 #pragma unroll
           for (int f = 0; f < 2; ++f) {
@@ -716,7 +726,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
         // dU_a -= (1/w_a) B_f l_f(a) (G_f(a) - S_f),  B_f = -1 at xi = -1, +1 at xi = +1
         __syncthreads();
         if (act) {
-          const double* shy = sm + (11 + NV) * n3;
+          const double* shy = sm + (11 + (kGvShfl ? 0 : NV)) * n3;
           const int a = idx[r];
           const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
 #pragma unroll
