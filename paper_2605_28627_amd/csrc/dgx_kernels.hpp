@@ -278,17 +278,14 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
       }
     }
   }
-  // face-normal viscous flux of one side from the gradient trace gf
-  auto emit_face = [&](int slot, int side, int fi, const double gf[12]) {
-    double ut[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) ut[v] = Utr[tr_index(slot, v, 5, nS, side, n2, fi)];
+  // face-normal viscous flux of one side from its state trace qt and gradient trace gf
+  auto emit_face = [&](int slot, int side, int fi, const Prim& qt, const double gf[12]) {
     const double nh[3] = {G.face[((size_t)0 * nS + side) * n2 + fi], G.face[((size_t)1 * nS + side) * n2 + fi],
                           G.face[((size_t)2 * nS + side) * n2 + fi]};
     const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
     const double nv[3] = {nh[0] * s, nh[1] * s, nh[2] * s};
     double Gn[4];
-    viscous_flux<FT, VL>(cons2prim(ut, P.gm1), gf, P, nv, Gn);
+    viscous_flux<FT, VL>(qt, gf, P, nv, Gn);
 #pragma unroll
     for (int v = 0; v < 4; ++v) st_visc<PREC>(gtr, tr_index(slot, v, 4, nS, side, n2, fi), Gn[v]);
   };
@@ -310,7 +307,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
 #pragma unroll
           for (int c = 0; c < 12; ++c) gtr[tr_index(slot, c, 12, nS, side, n2, qm * n1 + p)] = acc[c];
         } else {
-          emit_face(slot, side, qm * n1 + p, acc);
+          emit_face(slot, side, qm * n1 + p, q, acc);   // LGL: the node's state is its trace
         }
       }
     }
@@ -343,7 +340,10 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
           for (int a = 0; a < n1; ++a) s += L[a] * sm[c * n3 + line_node<N>(r, a, pp, qq)];
           gf[c] = s;
         }
-        emit_face(slot, side, qm * n1 + p, gf);
+        double ut[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) ut[v] = Utr[tr_index(slot, v, 5, nS, side, n2, qm * n1 + p)];
+        emit_face(slot, side, qm * n1 + p, cons2prim(ut, P.gm1), gf);
       }
     }
   }
