@@ -17,7 +17,8 @@ oracle timed on a bounded sample of the same workload on the host.
 Other workloads (--workload, --K, --state) and repetitions (--reps, median)
 serve the per-configuration measurements; --fv checker/all runs an Euler
 workload with half or all of its elements on FV sub-cells (shock
-capturing; the paper's 50 % FV row uses a checkerboard).
+capturing; the paper's 50 % FV row uses a checkerboard), --fv zero the same
+FV-capable context with no element switched.
 """
 from __future__ import annotations
 
@@ -62,8 +63,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--fv", default="none", choices=["none", "checker", "all"],
-                    help="FV sub-cell elements (Euler workloads): none, a checkerboard half, or all")
+    ap.add_argument("--fv", default="none", choices=["none", "zero", "checker", "all"],
+                    help="FV sub-cell elements (Euler workloads): none (a DG-only context), zero (an FV "
+                         "context with every element on DG), a checkerboard half, or all")
     ap.add_argument("--adjoint-steps", type=int, default=4)
     ap.add_argument("--checkpoint-every", type=int, default=None)
     ap.add_argument("--cpu-sample-elems", type=int, default=4096)
@@ -189,6 +191,8 @@ def fv_mask(kind, K):
     ne = K[0] * K[1] * K[2]
     if kind == "all":
         return np.ones(ne, np.int32)
+    if kind == "zero":
+        return np.zeros(ne, np.int32)
     e = np.arange(ne)
     return ((e % K[0] + (e // K[0]) % K[1] + e // (K[0] * K[1])) % 2).astype(np.int32)
 
@@ -288,7 +292,7 @@ def main():
     kname = volume_kernel_name(w, 0, 1 if args.riemann == "roe" else 0)
     default_run = (args.K is None and args.state is None and args.integrator == 0 and args.riemann == "rusanov"
                    and args.viscosity == "constant")
-    counters = profile_counters(args.workload, kname) if default_run and not nfv else None
+    counters = profile_counters(args.workload, kname) if default_run and args.fv == "none" else None
     form = ("split form" if w["form"] else "weak form") + (", Navier-Stokes" if w["physics"] else ", Euler")
 
     result = {

@@ -47,6 +47,7 @@ struct dg_ctx {
   int* d_etype = nullptr;
   int* d_etype_new = nullptr;
   int* d_sidefv = nullptr;
+  int* d_efv = nullptr;
   int* d_side_elem = nullptr;
   // workspace (caller-owned)
   char* ws = nullptr;
@@ -398,7 +399,7 @@ static void free_device(dg_ctx* c) {
   if (c->d_basis) (void)hipFree(c->d_basis);
   for (double** p : {&c->d_fvV, &c->d_fvS, &c->d_fvSb})
     if (*p) { (void)hipFree(*p); *p = nullptr; }
-  for (int** p : {&c->d_etype, &c->d_etype_new, &c->d_sidefv, &c->d_side_elem})
+  for (int** p : {&c->d_etype, &c->d_etype_new, &c->d_sidefv, &c->d_efv, &c->d_side_elem})
     if (*p) { (void)hipFree(*p); *p = nullptr; }
   c->d_Ja = c->d_sJ = c->d_face = nullptr;
   c->d_efc = nullptr;
@@ -630,6 +631,7 @@ dg_status dg_upload_mesh(dg_ctx* c, int nElems, int Ngeo, const double* X, int n
         (e = hipMalloc((void**)&c->d_etype, nE * sizeof(int))) != hipSuccess ||
         (e = hipMalloc((void**)&c->d_etype_new, nE * sizeof(int))) != hipSuccess ||
         (e = hipMalloc((void**)&c->d_sidefv, nS * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc((void**)&c->d_efv, nE * sizeof(int))) != hipSuccess ||
         (e = hipMalloc((void**)&c->d_side_elem, 2 * nS * sizeof(int))) != hipSuccess) {
       free_device(c);
       return fail(c, e == hipErrorOutOfMemory ? DG_ERR_NOMEM : DG_ERR_HIP,
@@ -639,6 +641,7 @@ dg_status dg_upload_mesh(dg_ctx* c, int nElems, int Ngeo, const double* X, int n
     HIPCHK(c, hipMemcpy(c->d_etype, zeros.data(), nE * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_etype_new, zeros.data(), nE * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_sidefv, zeros.data(), nS * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_efv, zeros.data(), nE * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_side_elem, c->side_elem.data(), 2 * nS * sizeof(int), hipMemcpyHostToDevice));
     st = build_fv(c);
     if (st != DG_OK) return st;
@@ -792,7 +795,7 @@ static Geo kgeo(const dg_ctx* c) {
   Geo g;
   g.nElems = c->nElems; g.nSides = c->nSides;
   g.Ja = c->d_Ja; g.sJ = c->d_sJ; g.face = c->d_face; g.efc = c->d_efc; g.basis = c->d_basis;
-  g.etype = c->d_etype; g.sidefv = c->d_sidefv; g.fvV = c->d_fvV; g.fvS = c->d_fvS; g.fvSb = c->d_fvSb;
+  g.etype = c->d_etype; g.sidefv = c->d_sidefv; g.efv = c->d_efv; g.fvV = c->d_fvV; g.fvS = c->d_fvS; g.fvSb = c->d_fvSb;
   return g;
 }
 
@@ -1078,6 +1081,7 @@ static dg_status fv_apply(dg_ctx* c, double* U, double* dU, hipStream_t s) {
   ProfScope ps(c, FAM_OTHER, s);
   LAUNCHCHK(c, launch_fv_switch(kcfg(c), kgeo(c), U, dU, c->d_etype_new, c->d_etype, s));
   LAUNCHCHK(c, launch_fv_side_flags(c->nSides, c->d_side_elem, c->d_etype, c->d_sidefv, s));
+  LAUNCHCHK(c, launch_fv_elem_flags(c->nElems, c->d_efc, c->d_sidefv, c->d_etype, c->d_efv, s));
   return DG_OK;
 }
 

@@ -63,6 +63,7 @@ struct Geo {
   // FV sub-cells (null unless enabled)
   const int* etype;      // [nElems]: 0 DG, 1 FV
   const int* sidefv;     // [nSides]: 1 if either element of the side is FV
+  const int* efv;        // [nElems]: bit f (0..5) the side of face f is FV, bit 6 the element is FV
   const double* fvV;     // [nElems][n3] sub-cell volumes
   const double* fvS;     // [3 r * 3 c][nElems][N][n2] interior sub-face vectors (+xi_r)
   const double* fvSb;    // [3 c][nSides][n2] master-outward element-face sub-face vectors
@@ -121,6 +122,7 @@ hipError_t launch_fv_switch(const Cfg& c, const Geo& g, double* U, double* dU, c
 hipError_t launch_fv_decide(int nElems, const double* ind, double lo, double hi, const int* etype, int* etype_new,
                             hipStream_t s);
 hipError_t launch_fv_side_flags(int nSides, const int* side_elem, const int* etype, int* sidefv, hipStream_t s);
+hipError_t launch_fv_elem_flags(int nElems, const int* efc, const int* sidefv, const int* etype, int* efv, hipStream_t s);
 hipError_t launch_adj_rk_update(size_t n, const double* out, double* lamU, double* lamdU, double dt, double A,
                                 double Bnext, hipStream_t s);
 hipError_t launch_scale_copy(size_t n, const double* x, double* y, double a, hipStream_t s);

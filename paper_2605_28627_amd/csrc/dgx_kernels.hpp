@@ -435,9 +435,9 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   __shared__ double saf[ES ? 8 * kFaces * n2 : 1];
   __shared__ VolBasis<N, FV != 0> sb;
   const int e = blockIdx.x, t = threadIdx.x;
-  if constexpr (FV) {
-    if (G.etype[e]) return;   // FV elements belong to the FV kernel
-  }
+  // FV: which faces are FV (bits 0..5), and whether this element is (bit 6)
+  const int efl = FV ? G.efv[e] : 0;
+  if (FV && (efl & 64)) return;   // FV elements belong to the FV kernel
   const int nE = G.nElems, nS = G.nSides;
   load_vol_basis<N, FV != 0>(&sb, G.basis, t, S::nth);
   const bool act = t < n3;
@@ -485,7 +485,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
     if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
     const int fi = qm * n1 + p;
     if constexpr (FV) {
-      if (G.sidefv[side]) {
+      if ((efl >> f) & 1) {
         // FV face: the sub-face flux, outward, into the staging area (taken back below)
         double F[5];
         fv_face_flux(Utr, G.fvSb, nS, n2, side, fi, P, F);
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
     __syncthreads();
     for (int ft = t; ft < S::nface; ft += S::nth) {
       const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
-      if (!G.sidefv[efc_side(G.efc[e * 6 + f])]) continue;
+      if (!((efl >> f) & 1)) continue;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         double sacc = 0.0;
@@ -824,7 +824,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
           const int info = G.efc[e * 6 + f];
           const int side = efc_side(info), slot = efc_slot(info);
-          if (FV && G.sidefv[side]) continue;
+          if (FV && ((efl >> f) & 1)) continue;
           int p = pp, qm = qq;
           if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
 #pragma unroll
@@ -850,7 +850,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
         const double* L = (f & 1) ? sb.Lp : sb.Lm;
         const int info = G.efc[e * 6 + f];
         const int side = efc_side(info), slot = efc_slot(info);
-        if (FV && G.sidefv[side]) continue;
+        if (FV && ((efl >> f) & 1)) continue;
         int p = pp, qm = qq;
         if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
         double s[5];
@@ -875,9 +875,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
     }
     if constexpr (FV) {
       // FV faces of this DG element: primitive means of its first two sub-cell layers
-      bool anyfv = false;
-#pragma unroll
-      for (int f = 0; f < 6; ++f) anyfv = anyfv || G.sidefv[efc_side(G.efc[e * 6 + f])];
+      const bool anyfv = (efl & 63) != 0;
       if (anyfv) {
         __syncthreads();
         double* sa = sm;

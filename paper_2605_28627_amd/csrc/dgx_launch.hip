@@ -92,9 +92,24 @@ __global__ void k_fv_side_flags(int n, const int* __restrict__ side_elem, const 
   sidefv[s] = (et[side_elem[2 * s]] | et[side_elem[2 * s + 1]]) ? 1 : 0;
 }
 
+// Per element: which of its faces are FV (bits 0..5) and whether it is FV (bit 6).
+__global__ void k_fv_elem_flags(int n, const int* __restrict__ efc, const int* __restrict__ sidefv,
+                                const int* __restrict__ et, int* __restrict__ efv) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  int m = et[e] ? 64 : 0;
+  for (int f = 0; f < 6; ++f) m |= sidefv[efc_side(efc[e * 6 + f])] ? (1 << f) : 0;
+  efv[e] = m;
+}
+
 hipError_t launch_fv_decide(int nElems, const double* ind, double lo, double hi, const int* etype, int* etype_new,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_fv_decide, dim3((nElems + 255) / 256), dim3(256), 0, s, nElems, ind, lo, hi, etype, etype_new);
+  return hipGetLastError();
+}
+
+hipError_t launch_fv_elem_flags(int nElems, const int* efc, const int* sidefv, const int* etype, int* efv, hipStream_t s) {
+  hipLaunchKernelGGL(k_fv_elem_flags, dim3((nElems + 255) / 256), dim3(256), 0, s, nElems, efc, sidefv, etype, efv);
   return hipGetLastError();
 }
 
