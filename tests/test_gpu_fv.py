@@ -11,6 +11,7 @@ Persson indicator, switching) against the oracle, through the C-ABI.
 * free-stream preservation and conservation on the GPU's own residual;
 * the 64^3 N=3 free-stream workload with half the elements FV (checkerboard):
   sampled elements against the oracle;
+* a single periodic FV element and two-element slabs;
 * the adjoint refuses FV contexts; the FV calls refuse contexts without FV.
 """
 import sys
@@ -206,6 +207,31 @@ def test_half_fv_workload_full_size_sampled(S, orc, torch_cuda):
     err = rel_err_per_var(R_gpu, R_orc)
     _say("full size", err)
     assert np.all(err < 1e-12), err
+
+
+@pytest.mark.parametrize("N,nodes,form,K,mask", [(3, 0, 0, (1, 1, 1), [1]), (2, 1, 1, (2, 1, 1), [1, 0]),
+                                                  (4, 1, 0, (1, 2, 1), [0, 1])], ids=str)
+def test_degenerate_meshes_match_oracle(S, orc, N, nodes, form, K, mask):
+    """A single periodic FV element (its own neighbour across every face) and
+    two-element slabs with one FV element: residual and one RK step."""
+    _say("degenerate", N, K, mask)
+    mesh = I.box_mesh(K, (-PI,) * 3, (PI,) * 3, rotate_seed=3)
+    cfg = dict(N=N, nodes=nodes, form=form, physics=0, fv=1)
+    o, s = orc.Oracle(cfg, mesh), S(cfg, mesh)
+    _, J, Ja = o.geometry()
+    s.upload_metrics(Ja, 1.0 / J, o.face_normals())
+    mask = np.array(mask, np.int32)
+    U = I.random_state(s.state_shape[1:], 39)
+    Uo, _ = o.fv_switch(U, None, mask)
+    Ug = s.init_state(U)
+    s.fv_switch(Ug, mask)
+    err = rel_err_per_var(s.rhs(Ug).cpu().numpy(), o.rhs(Uo))
+    _say("degenerate", N, K, err)
+    assert np.all(err < 1e-12), err
+    dt = o.timestep(Uo, 0.5)
+    U1 = o.lserk(Uo, 1, dt)
+    s.rk_step(Ug, s.empty_state(), dt, 1)
+    assert np.all(rel_err_per_var(Ug.cpu().numpy() - Uo, U1 - Uo) < 1e-11)
 
 
 def test_refusals(S, orc, torch_cuda):
