@@ -1,21 +1,26 @@
-"""Full-length runs on the GPU: the Navier-Stokes Taylor-Green vortex (N=7
-LGL split form, 16^3 elements on [-pi, pi]^3, Re 1600, Ma 0.1) over its 1000
-LSERK4(5) steps at CFL 0.9, in FP64 and in the FP32-flux mode.
+"""Full-length runs on the GPU: the Navier-Stokes Taylor-Green vortex
+(Re 1600, Ma 0.1, 16^3 elements on [-pi, pi]^3) over 1000 LSERK4(5) steps at
+CFL 0.9, in FP64 and in the FP32-flux mode, with the kinetic-energy-preserving
+split form on LGL nodes (N = 7) and the entropy-stable split form on Gauss
+nodes (N = 3).
 
 No oracle run of this length is affordable, so the checks are properties that
 hold at any length:
 * the state stays physical (rho > 0, p > 0, finite);
 * the kinetic energy starts at 1/8 (in units of rho0 U0^2) and decreases on
-  every 100-step chunk: viscosity and the Rusanov face flux dissipate, the
-  kinetic-energy-preserving split form adds none, and at Ma 0.1 the
-  pressure-dilatation exchange is far below the viscous decay;
-* its decay rate over the first 100 steps (t < 0.072) is the initial
-  dissipation rate of the flow, nu <|omega|^2> = 3 nu / 4 for this velocity
-  field (vorticity components -cos x sin y sin z, -sin x cos y sin z and
+  every chunk of steps: viscosity and the Rusanov face flux dissipate, the
+  split forms add none, and at Ma 0.1 the pressure-dilatation exchange is far
+  below the viscous decay;
+* its decay rate over the first 0.07 time units is the initial dissipation
+  rate of the flow, nu <|omega|^2> = 3 nu / 4 for this velocity field
+  (vorticity components -cos x sin y sin z, -sin x cos y sin z and
   2 sin x sin y cos z; 1/8 + 1/8 + 1/2), within 1 % (the enstrophy barely
-  changes this early, and 128 nodes per direction resolve the field);
+  changes this early, and both discretisations resolve the field);
 * the FP32-flux run's kinetic-energy history stays within 1e-6 (relative)
-  of the FP64 one.
+  of the FP64 one;
+* the two discretisations, 128 LGL nodes per direction at N = 7 and 64 Gauss
+  nodes at N = 3, give the same kinetic energy at their common sample times
+  to 1e-6.
 """
 import sys
 
@@ -25,7 +30,8 @@ import pytest
 from paper_2605_28627_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
-NAME = "ns_split_lgl_n7_16x16x16_tgv"
+STEPS = 1000
+T_RATE = 0.0713   # time over which the initial decay rate is measured
 
 
 def _say(*a):
@@ -33,37 +39,65 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _history(precision):
+_RUNS = {}
+
+
+def _history(name, precision):
+    """E_k after the first n_rate steps (about T_RATE), then every 100 steps up to STEPS."""
+    if (name, precision) not in _RUNS:
+        _RUNS[(name, precision)] = _run(name, precision)
+    return _RUNS[(name, precision)]
+
+
+def _run(name, precision):
     import torch
     from paper_2605_28627_amd.solver import DGSolver
     assert torch.cuda.is_available()
-    w = I.WORKLOADS[NAME]
+    w = I.WORKLOADS[name]
     cfg = dict(N=w["N"], nodes=w["nodes"], form=w["form"], physics=w["physics"], mu=w["mu"], precision=precision)
-    s = DGSolver(cfg, I.workload_mesh(NAME))
-    U = s.init_state(I.workload_state(NAME, s.coords()))
+    s = DGSolver(cfg, I.workload_mesh(name))
+    U = s.init_state(I.workload_state(name, s.coords()))
     dU = torch.zeros_like(U)
     dt = s.timestep(U, 0.9)
+    n_rate = max(1, int(round(T_RATE / dt)))
+    sched = [n_rate] + [100] * ((STEPS - n_rate) // 100) + ([(STEPS - n_rate) % 100] if (STEPS - n_rate) % 100 else [])
     ek = [s.kinetic_energy(U).item()]
-    for _ in range(10):
-        s.rk_step(U, dU, dt, 100)
+    for n in sched:
+        s.rk_step(U, dU, dt, n)
         assert s.check_state(U) == 0
         ek.append(s.kinetic_energy(U).item())
     s.close()
-    return dt, np.array(ek)
+    return dt, n_rate, np.array(ek)
 
 
-def test_tgv_1000_steps():
-    dt, ek = _history(0)
-    _say("FP64 dt", dt, "t_end", 1000 * dt, "E_k", ek.tolist())
+@pytest.mark.parametrize("name", ["ns_split_lgl_n7_16x16x16_tgv", "ns_split_lg_n3_16x16x16_tgv"])
+def test_tgv_1000_steps(name):
+    dt, n_rate, ek = _history(name, 0)
+    _say(name, "FP64 dt", dt, "t_end", STEPS * dt, "E_k", ek.tolist())
     assert abs(ek[0] - 0.125) < 1e-12
     assert np.all(np.diff(ek) < 0), np.diff(ek)
-    rate = (ek[0] - ek[1]) / (100 * dt)
-    eps0 = 0.75 * I.WORKLOADS[NAME]["mu"]
-    _say("initial decay rate", rate, "against 3 nu / 4 =", eps0)
+    rate = (ek[0] - ek[1]) / (n_rate * dt)
+    eps0 = 0.75 * I.WORKLOADS[name]["mu"]
+    _say(name, "initial decay rate over", n_rate, "steps", rate, "against 3 nu / 4 =", eps0)
     assert abs(rate / eps0 - 1.0) < 0.01
-    dt32, ek32 = _history(1)
+    dt32, _, ek32 = _history(name, 1)
     rel = np.abs(ek32 - ek) / ek
-    _say("FP32-flux E_k", ek32.tolist(), "relative difference", rel.max())
+    _say(name, "FP32-flux E_k", ek32.tolist(), "relative difference", rel.max())
     assert dt32 == dt
     assert np.all(np.diff(ek32) < 0)
     assert rel.max() < 1e-6, rel
+
+
+def test_discretisations_agree():
+    """E_k(t) of the N = 7 LGL and the N = 3 Gauss runs at their common sample times."""
+    dt7, n7, ek7 = _history("ns_split_lgl_n7_16x16x16_tgv", 0)
+    dt3, n3, ek3 = _history("ns_split_lg_n3_16x16x16_tgv", 0)
+    t7 = np.cumsum([0] + [n7] + [100] * (len(ek7) - 2)) * dt7
+    t3 = np.cumsum([0] + [n3] + [100] * (len(ek3) - 2)) * dt3
+    # the step sizes differ by a factor 4 to 5e-5, so the sample times match to
+    # 1e-4; |dE_k/dt| < 1e-3 covers the mismatch
+    common = [(a, b) for a in range(len(t7)) for b in range(len(t3)) if abs(t7[a] - t3[b]) < 1e-4 * (1 + t7[a])]
+    _say("common sample times", [(t7[a], t3[b], ek7[a], ek3[b]) for a, b in common])
+    assert len(common) >= 3
+    for a, b in common:
+        assert abs(ek7[a] - ek3[b]) < 1e-6 * ek7[a] + 1e-3 * abs(t7[a] - t3[b]), (t7[a], ek7[a], ek3[b])
