@@ -373,8 +373,8 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
 #endif
 
 // Waves per SIMD the residual kernel is compiled for (its register budget):
-// 4 for elements of 512 work-items; 3 for one-wavefront elements of the
-// Gauss split form, whose LDS footprint admits that many.
+// 4 for elements of 512 work-items; 3 for the N = 3 Gauss split form (one
+// wavefront per element), whose LDS footprint admits that many.
 #ifndef DGX_ES_WAVES
 #define DGX_ES_WAVES 3
 #endif
@@ -387,7 +387,7 @@ __host__ __device__ constexpr int es_face_slot(int f) { return f < 4 ? f : f - 4
 constexpr int kEsFaceSlots = 4;
 template <int N, int NODES, int FORM>
 constexpr int volume_waves() {
-  return Shape<N>::nth >= 512 ? 4 : ((FORM == 1 && NODES == 0 && Shape<N>::nth == 64) ? DGX_ES_WAVES : 1);
+  return Shape<N>::nth >= 512 ? 4 : ((FORM == 1 && NODES == 0 && N == 3) ? DGX_ES_WAVES : 1);
 }
 
 // FV (Euler contexts with FV sub-cells): DG elements only; faces with an FV
