@@ -294,9 +294,14 @@ dg_status dg_fv_mask(dg_ctx* ctx, int* mask_host, void* stream);
  * context is bracketed by two hipEvents on its stream.  Enabling resets
  * the accumulated times.  dg_profile_query synchronises the device, then
  * returns the summed milliseconds and launch count of the kernel family
- * named by `kernel` ("trace", "lift", "volume", "adjoint", "other").
+ * named by `kernel` ("trace", "lift", "volume", "adjoint", "other", "fv").
  * Unknown names give DG_ERR_ARG. */
 dg_status dg_profile(dg_ctx* ctx, int enable);
+/* As dg_profile, but only the launches of the families in `mask` are
+ * bracketed (bit 0 trace, 1 lift, 2 volume, 3 adjoint, 4 other, 5 fv); 0
+ * disables.  Fewer events perturb a timed run less.  A mask outside 0..63
+ * gives DG_ERR_ARG. */
+dg_status dg_profile_families(dg_ctx* ctx, int mask);
 dg_status dg_profile_query(dg_ctx* ctx, const char* kernel, double* total_ms, long* count);
 
 #ifdef __cplusplus

@@ -55,6 +55,7 @@ struct dg_ctx {
   std::string err;
   // profiling: pairs of events per launch, grouped by kernel family
   bool prof = false;
+  int prof_mask = 0;   // families bracketed by events (bit f = family f)
   struct Rec { int fam; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
@@ -76,10 +77,10 @@ static hipEvent_t pool_event(dg_ctx* c) {
 struct ProfScope {
   dg_ctx* c; int fam; hipStream_t s; hipEvent_t a = nullptr, b = nullptr;
   ProfScope(dg_ctx* c_, int fam_, hipStream_t s_) : c(c_), fam(fam_), s(s_) {
-    if (c->prof) { a = pool_event(c); b = pool_event(c); if (a) (void)hipEventRecord(a, s); }
+    if (c->prof && ((c->prof_mask >> fam) & 1)) { a = pool_event(c); b = pool_event(c); if (a) (void)hipEventRecord(a, s); }
   }
   ~ProfScope() {
-    if (c->prof && a && b) { (void)hipEventRecord(b, s); c->recs.push_back({fam, a, b}); }
+    if (a && b) { (void)hipEventRecord(b, s); c->recs.push_back({fam, a, b}); }
   }
 };
 
@@ -1141,6 +1142,17 @@ dg_status dg_profile(dg_ctx* c, int enable) {
   prof_collect(c);
   for (int f = 0; f < 6; ++f) { c->prof_ms[f] = 0.0; c->prof_n[f] = 0; }
   c->prof = enable != 0;
+  c->prof_mask = 0x3f;
+  return DG_OK;
+}
+
+dg_status dg_profile_families(dg_ctx* c, int mask) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "dg_profile_families: null context");
+  if (mask < 0 || mask > 0x3f) return fail(c, DG_ERR_ARG, "dg_profile_families: mask outside 0..63");
+  prof_collect(c);
+  for (int f = 0; f < 6; ++f) { c->prof_ms[f] = 0.0; c->prof_n[f] = 0; }
+  c->prof = mask != 0;
+  c->prof_mask = mask;
   return DG_OK;
 }
 

@@ -39,7 +39,7 @@ SYMBOLS = ["dg_create", "dg_destroy", "dg_last_error", "dg_lserk_coefficients", 
            "dg_upload_metrics", "dg_get_metrics", "dg_node_coords", "dg_sizes", "dg_workspace_bytes",
            "dg_workspace_bytes_adjoint", "dg_bind_workspace", "dg_init_state", "dg_rhs", "dg_lift", "dg_rk_step", "dg_adjoint_rhs", "dg_adjoint_rk_step",
            "dg_kinetic_energy", "dg_kinetic_energy_grad", "dg_timestep", "dg_check_state", "dg_profile",
-           "dg_profile_query", "dg_fv_switch", "dg_fv_indicator", "dg_fv_switch_by_indicator", "dg_fv_mask"]
+           "dg_profile_families", "dg_profile_query", "dg_fv_switch", "dg_fv_indicator", "dg_fv_switch_by_indicator", "dg_fv_mask"]
 
 
 class dg_config(ctypes.Structure):
@@ -85,6 +85,7 @@ _sig = {
     "dg_timestep": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _dp, _vp]),
     "dg_check_state": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "dg_profile_families": (ctypes.c_int, [_vp, ctypes.c_int]),
     "dg_profile_query": (ctypes.c_int, [_vp, ctypes.c_char_p, _dp, ctypes.POINTER(ctypes.c_long)]),
     "dg_fv_switch": (ctypes.c_int, [_vp, _vp, _vp, _ip, _vp]),
     "dg_fv_indicator": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -329,6 +330,17 @@ def dg_fv_mask(ctx, stream=None):
 
 def dg_profile(ctx, enable):
     _check(ctx, _L.dg_profile(ctx, int(bool(enable))))
+
+
+PROFILE_FAMILIES = ("trace", "lift", "volume", "adjoint", "other", "fv")
+
+
+def dg_profile_families(ctx, families):
+    """Events only around the launches of the named kernel families (empty: off)."""
+    mask = 0
+    for f in families:
+        mask |= 1 << PROFILE_FAMILIES.index(f)
+    _check(ctx, _L.dg_profile_families(ctx, mask))
 
 
 def dg_profile_query(ctx, kernel):

@@ -352,3 +352,25 @@ def test_bench_workload_full_size_sampled(S, orc, torch_cuda):
         change = np.abs(W * (U1[v] - U[v])).sum()
         tol = 1e-12 * change + 1e-14 * (W * np.abs(U[v])).sum() + 1e-15
         assert abs((W * U1[v]).sum() - tot0[v]) < tol, (v, abs((W * U1[v]).sum() - tot0[v]), tol)
+
+
+def test_profile_families(S, orc, torch_cuda):
+    """dg_profile_families times only the chosen kernel families; dg_profile all of them."""
+    from paper_2605_28627_amd import dgx
+    o, s, _ = _setup(S, orc, (3, 1, 1, 1, 0.0, 3))
+    U = s.init_state(I.smooth_random_state(o.coords(), 71, amp=0.2))
+    dU = s.empty_state()
+    dgx.dg_profile_families(s.ctx, ("volume",))
+    s.rk_step(U, dU, 1e-4, 2)
+    assert dgx.dg_profile_query(s.ctx, "volume")[1] == 10
+    assert dgx.dg_profile_query(s.ctx, "lift")[1] == 0
+    assert dgx.dg_profile_query(s.ctx, "trace")[1] == 0
+    dgx.dg_profile(s.ctx, 1)
+    s.rk_step(U, dU, 1e-4, 2)
+    assert dgx.dg_profile_query(s.ctx, "volume")[1] == 10
+    assert dgx.dg_profile_query(s.ctx, "lift")[1] == 10
+    assert dgx.dg_profile_query(s.ctx, "trace")[1] == 1
+    dgx.dg_profile(s.ctx, 0)
+    with pytest.raises(dgx.DGError) as ei:
+        dgx._check(s.ctx, dgx._L.dg_profile_families(s.ctx, 64))
+    assert ei.value.status == dgx.DG_ERR_ARG
