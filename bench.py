@@ -207,8 +207,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this "
-                                   "build (the path shards by elements, see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the library has no multi-GPU path "
+                                   "(it would shard the mesh by elements, one process per GPU)", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2605_28627_amd import dgx

@@ -1,0 +1,49 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU refusal, the algorithmic
+byte models the roofline divides by (against the per-node tables of the
+kernels' reads and writes), and the FV element masks."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+from paper_2605_28627_amd import inputs as I  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    assert d["n_gpus"] == 2 and "one GPU" in d["error"]
+
+
+def test_byte_models():
+    # 8 B per value; 0.75 face nodes per volume node at N = 7, 1.5 at N = 3
+    c2 = I.WORKLOADS["ns_split_lgl_n7_16x16x16_tgv"]
+    # U 5, Ja + 1/J 10, dU 4 (five-stage average), G~ 12, traces 2x5 and face viscous fluxes 2x4 and
+    # face geometry 4 per face node; writes dU 5, U 5, traces 5 per face node
+    assert bench.volume_kernel_bytes_per_dof(c2) == 8 * (5 + 10 + 4 + 12 + 0.75 * (10 + 8 + 4) + 5 + 5 + 0.75 * 5)
+    assert bench.volume_kernel_bytes_per_dof(c2) == 490
+    c1 = I.WORKLOADS["euler_weak_lg_n3_64x64x64"]
+    assert bench.volume_kernel_bytes_per_dof(c1) == 460
+    assert bench.fv_kernel_bytes_per_dof(c1) == 610
+    es = I.WORKLOADS["ns_split_lg_n3_64x64x64_freestream"]
+    assert bench.volume_kernel_bytes_per_dof(es) == 652
+    # FP32-flux mode stores the viscous fluxes as float
+    assert bench.volume_kernel_bytes_per_dof(c2, precision=1) == 490 - 4 * (12 + 0.75 * 8)
+
+
+def test_fv_masks():
+    K = (4, 3, 2)
+    m = bench.fv_mask("checker", K)
+    assert m.sum() == 12 and m.dtype == np.int32
+    e = np.arange(24)
+    i, j, k = e % 4, (e // 4) % 3, e // 12
+    assert np.array_equal(m, (i + j + k) % 2)
+    assert bench.fv_mask("all", K).sum() == 24
+    assert bench.fv_mask("zero", K).sum() == 0
