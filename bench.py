@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -63,6 +64,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--fv-switch-every-step", action="store_true",
+                    help="with --fv: one dg_rk_step call per step, each followed by the indicator and the "
+                         "switch (hysteresis window (-inf, inf), so the element types stay as set), as a "
+                         "shock-capturing run does")
     ap.add_argument("--fv", default="none", choices=["none", "zero", "checker", "all"],
                     help="FV sub-cell elements (Euler workloads): none (a DG-only context), zero (an FV "
                          "context with every element on DG), a checkerboard half, or all")
@@ -224,6 +229,8 @@ def main():
     if args.viscosity == "sutherland":
         # reference temperature of the initial state: T0 = p0 / (rho0 R) at Ma 0.1, rho0 = U0 = 1
         cfg.update(viscosity=1, Tref=1.0 / (1.4 * 0.01), Ts=110.4 / 273.15)
+    if args.fv_switch_every_step and args.fv == "none":
+        raise SystemExit("--fv-switch-every-step needs --fv")
     if args.fv != "none":
         if w["physics"] != 0:
             raise SystemExit("--fv needs an Euler workload (FV sub-cells cover Euler)")
@@ -264,7 +271,12 @@ def main():
             if events:
                 dgx.dg_profile_families(solver.ctx, ROOF_FAMILIES)
             t0 = time.perf_counter()
-            solver.rk_step(U, dU, dt, args.steps)
+            if args.fv_switch_every_step:
+                for _ in range(args.steps):
+                    solver.rk_step(U, dU, dt, 1)
+                    solver.fv_switch_by_indicator(U, -math.inf, math.inf, dU=dU)
+            else:
+                solver.rk_step(U, dU, dt, args.steps)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             if events:
@@ -278,7 +290,12 @@ def main():
             Ub = U0.clone()
             dUb = torch.zeros_like(Ub)
             dgx.dg_profile(solver.ctx, 1)
-            solver.rk_step(Ub, dUb, dt, args.steps)
+            if args.fv_switch_every_step:
+                for _ in range(args.steps):
+                    solver.rk_step(Ub, dUb, dt, 1)
+                    solver.fv_switch_by_indicator(Ub, -math.inf, math.inf, dU=dUb)
+            else:
+                solver.rk_step(Ub, dUb, dt, args.steps)
             for fam in ("trace", "lift", "other"):
                 prof[fam] = dgx.dg_profile_query(solver.ctx, fam)
             dgx.dg_profile(solver.ctx, 0)
@@ -334,7 +351,7 @@ def main():
                    "integrator": ("LSERK4(5)", "LSERK4-14")[args.integrator], "stages_per_step": nst,
                    "riemann": args.riemann, "viscosity": args.viscosity,
                    "state": args.state or w["state"], "fv_elements": nfv,
-                   "fv_mask": args.fv},
+                   "fv_mask": args.fv, "fv_switch_every_step": bool(args.fv_switch_every_step)},
         "dof_updates_per_s": 1.0 / pid64,
         "simulated_time_per_wall_s": dt * args.steps / t64,
         "reps": args.reps,
