@@ -129,10 +129,10 @@ __device__ inline void tensor3(const double* M, double* a, double* b, int nvar, 
   __syncthreads();
 }
 
-// Writes the two-layer primitive traces of the six faces (or, with only_fv,
-// of the faces flagged FV) from the primitive means sw[5][n3] in LDS.
+// Writes the two-layer primitive traces of the faces in face_mask (bit f =
+// face f) from the primitive means sw[5][n3] in LDS.
 template <int N>
-__device__ inline void write_fv_traces(const Geo& G, int e, const double* sw, double* __restrict__ Utr, bool only_fv,
+__device__ inline void write_fv_traces(const Geo& G, int e, const double* sw, double* __restrict__ Utr, int face_mask,
                                        int t, int nth) {
   constexpr int n1 = N + 1, n2 = n1 * n1, n3 = n2 * n1;
   const int nS = G.nSides;
@@ -140,7 +140,7 @@ __device__ inline void write_fv_traces(const Geo& G, int e, const double* sw, do
     const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
     const int info = G.efc[e * 6 + f];
     const int side = efc_side(info), slot = efc_slot(info);
-    if (only_fv && !G.sidefv[side]) continue;
+    if (!((face_mask >> f) & 1)) continue;
     int p = pp, qm = qq;
     if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
     const int fi = qm * n1 + p;
@@ -173,10 +173,9 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace_fv(Geo G, Phys P, const
   const bool act = t < n3;
   load_basis(&sbb, G.basis, t, S::nth);
   for (int x = t; x < n1 * n1; x += S::nth) sBs[x] = G.basis->Bs[x];
-  const int et = G.etype[e];
-  bool anyfv = et != 0;
-#pragma unroll
-  for (int f = 0; f < 6; ++f) anyfv = anyfv || G.sidefv[efc_side(G.efc[e * 6 + f])];
+  const int efl = G.efv[e];        // bits 0..5: FV faces, bit 6: FV element
+  const int et = (efl >> 6) & 1;
+  const bool anyfv = efl != 0;
   double u[5] = {0, 0, 0, 0, 0};
   if (act) {
 #pragma unroll
@@ -213,7 +212,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace_fv(Geo G, Phys P, const
       }
     }
     __syncthreads();
-    write_fv_traces<N>(G, e, sb2, Utr, et == 0, t, S::nth);
+    write_fv_traces<N>(G, e, sb2, Utr, et ? 63 : (efl & 63), t, S::nth);
   }
   if (et) return;
   // DG faces of a DG element: the DG trace
@@ -221,7 +220,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace_fv(Geo G, Phys P, const
     const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
     const int info = G.efc[e * 6 + f];
     const int side = efc_side(info), slot = efc_slot(info);
-    if (G.sidefv[side]) continue;
+    if ((efl >> f) & 1) continue;
     int p = pp, q = qq;
     if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
 #pragma unroll
@@ -374,7 +373,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_fv(Geo G, Phys P, const doubl
   }
   if constexpr (MODE == 1) {
     __syncthreads();
-    write_fv_traces<N>(G, e, sw, Utr_next, false, t, S::nth);
+    write_fv_traces<N>(G, e, sw, Utr_next, 63, t, S::nth);
   }
 }
 

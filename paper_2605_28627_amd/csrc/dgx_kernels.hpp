@@ -897,7 +897,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           for (int v = 0; v < 5; ++v) sc[v * n3 + t] = W[v];
         }
         __syncthreads();
-        write_fv_traces<N>(G, e, sc, Utr_next, true, t, S::nth);
+        write_fv_traces<N>(G, e, sc, Utr_next, efl & 63, t, S::nth);
       }
     }
   }
