@@ -27,7 +27,12 @@
 //   * the low-storage RK4(5) scheme of Carpenter and Kennedy;
 //   * the integral kinetic energy E_k (TGV section) and its gradient;
 //   * forward-mode tangents (dual numbers) of the residual and of whole RK
-//     trajectories, from which adjoint checks are built by transposition.
+//     trajectories;
+//   * reverse mode: the transposed residual Jacobian applied to a vector
+//     (a taped scalar swept backwards), the gradient of E_k, and the reverse
+//     sweep of the 2N-storage RK stages over a whole trajectory (the
+//     adjoint the GPU path is checked against; not in the paper);
+//   * operation counts of the residual as written (a counting scalar).
 //
 // Function pins (closed forms, invariants, brute force) live in tests/.
 // Everything with no such pin is listed as "parity unpinned" below:
@@ -44,8 +49,9 @@ namespace orc {
 
 // ---------------------------------------------------------------------------
 // Scalar types.  The residual is written once as a template and evaluated
-// with plain doubles, with dual numbers (exact directional derivatives) and
-// with an operation-counting double.
+// with plain doubles, with dual numbers (exact directional derivatives), with
+// a taped reverse-mode scalar (exact transposed products) and with an
+// operation-counting double.
 // ---------------------------------------------------------------------------
 struct Dual {
   double v, d;
@@ -87,6 +93,66 @@ inline Cnt log(Cnt a) { ++Cnt::n_log; return Cnt(std::log(a.v)); }
 inline Cnt exp(Cnt a) { ++Cnt::n_log; return Cnt(std::exp(a.v)); }   // counted with log
 inline Cnt sqrt(Cnt a) { ++Cnt::n_sqrt; return Cnt(std::sqrt(a.v)); }
 inline double val(Cnt a) { return a.v; }
+
+// Reverse-mode scalar.  Every operation on a Rev whose operands depend on the
+// inputs appends one node to the tape: the indices of its (at most two)
+// operand nodes and the partial derivatives with respect to them.  Sweeping
+// the tape from the end with the outputs' adjoints as seeds gives the
+// vector-Jacobian product (dY/dX)^T lam exactly (up to rounding): the
+// transposed chain rule applied operation by operation.  Operations on
+// constants (node index -1) are not recorded.
+struct Tape {
+  struct Node {
+    int a, b;        // operand nodes (-1: none)
+    double da, db;   // partial derivatives with respect to them
+  };
+  std::vector<Node> nodes;
+  int push(int a, double da, int b, double db) {
+    nodes.push_back(Node{a, b, da, db});
+    return (int)nodes.size() - 1;
+  }
+  void clear() { nodes.clear(); }
+  size_t size() const { return nodes.size(); }
+  // adj holds one adjoint per node (seeded at the outputs); on return the
+  // adjoints of all nodes, in particular of the independent variables.
+  void sweep(std::vector<double>& adj) const {
+    for (size_t n = nodes.size(); n-- > 0;) {
+      const double x = adj[n];
+      if (x == 0.0) continue;
+      const Node& d = nodes[n];
+      if (d.a >= 0) adj[d.a] += d.da * x;
+      if (d.b >= 0) adj[d.b] += d.db * x;
+    }
+  }
+};
+static Tape g_tape;
+
+struct Rev {
+  double v;
+  int i;   // tape node, -1 for a constant
+  Rev(double a = 0.0) : v(a), i(-1) {}
+  Rev(double a, int node) : v(a), i(node) {}
+  static Rev input(double a) { return Rev(a, g_tape.push(-1, 0.0, -1, 0.0)); }
+};
+inline Rev rev_node(double v, int a, double da, int b, double db) {
+  if (a < 0 && b < 0) return Rev(v);
+  return Rev(v, g_tape.push(a, da, b, db));
+}
+inline Rev operator+(Rev a, Rev b) { return rev_node(a.v + b.v, a.i, 1.0, b.i, 1.0); }
+inline Rev operator-(Rev a, Rev b) { return rev_node(a.v - b.v, a.i, 1.0, b.i, -1.0); }
+inline Rev operator-(Rev a) { return rev_node(-a.v, a.i, -1.0, -1, 0.0); }
+inline Rev operator*(Rev a, Rev b) { return rev_node(a.v * b.v, a.i, b.v, b.i, a.v); }
+inline Rev operator/(Rev a, Rev b) {
+  const double q = a.v / b.v;
+  return rev_node(q, a.i, 1.0 / b.v, b.i, -q / b.v);
+}
+inline Rev& operator+=(Rev& a, Rev b) { a = a + b; return a; }
+inline Rev& operator-=(Rev& a, Rev b) { a = a - b; return a; }
+inline Rev& operator*=(Rev& a, Rev b) { a = a * b; return a; }
+inline Rev log(Rev a) { return rev_node(std::log(a.v), a.i, 1.0 / a.v, -1, 0.0); }
+inline Rev exp(Rev a) { const double e = std::exp(a.v); return rev_node(e, a.i, e, -1, 0.0); }
+inline Rev sqrt(Rev a) { const double r = std::sqrt(a.v); return rev_node(r, a.i, 0.5 / r, -1, 0.0); }
+inline double val(Rev a) { return a.v; }
 
 using std::log;
 using std::exp;
@@ -313,6 +379,14 @@ struct Solver {
 
   int node(int i, int j, int k) const { return (k * n1 + j) * n1 + i; }
   size_t uidx(int v, int e, int nd) const { return ((size_t)v * nElems + e) * n3 + nd; }
+  // Where the residual of (v, e, node) is written: the full-size layout, or,
+  // while outpos is set (a sampled evaluation), a compact [5][outn][n3] array
+  // with element e at position outpos[e].
+  std::vector<int> outpos;
+  int outn = 0;
+  size_t oidx(int v, int e, int nd) const {
+    return outpos.empty() ? uidx(v, e, nd) : ((size_t)v * outn + outpos[e]) * n3 + nd;
+  }
 
   bool setup() {
     nstages = rk_coeffs(C.integrator, lsA, lsB, lsC);
@@ -899,12 +973,12 @@ struct Solver {
         }
     }
     for (int v = 0; v < 5; ++v)
-      for (int tt = 0; tt < n3; ++tt) Ut[uidx(v, e, tt)] = V[(size_t)v * n3 + tt] / Jdet[e][tt];
+      for (int tt = 0; tt < n3; ++tt) Ut[oidx(v, e, tt)] = V[(size_t)v * n3 + tt] / Jdet[e][tt];
     if (C.mms) {
       for (int tt = 0; tt < n3; ++tt) {
         double Q[5];
         mms_source(Xnode[e][tt], Xnode[e][n3 + tt], Xnode[e][2 * (size_t)n3 + tt], t, Q);
-        for (int v = 0; v < 5; ++v) Ut[uidx(v, e, tt)] += Q[v];
+        for (int v = 0; v < 5; ++v) Ut[oidx(v, e, tt)] += Q[v];
       }
     }
   }
@@ -1196,7 +1270,7 @@ struct Solver {
           }
         }
     for (int v = 0; v < 5; ++v)
-      for (int t = 0; t < n3; ++t) Ut[uidx(v, e, t)] = R[(size_t)v * n3 + t] / Vsub[e][t];
+      for (int t = 0; t < n3; ++t) Ut[oidx(v, e, t)] = R[(size_t)v * n3 + t] / Vsub[e][t];
   }
   // Persson-Peraire indicator: log10 of the share of the highest modes
   // (max(i,j,k) = N in the orthonormal Legendre basis) in the energy of rho.
@@ -1379,6 +1453,85 @@ struct Solver {
     }
   }
 
+  // Transposed residual Jacobian applied to lam: out = (dR/dU)^T lam at U.
+  // R(U) is recorded on the tape (one node per input, then one per
+  // operation) and the tape is swept back from the outputs' seeds lam.
+  void rhs_vjp(const double* U, const double* lam, double* out, double t) {
+    const size_t n = (size_t)5 * nElems * n3;
+    for (int e = 0; e < nElems; ++e) ensure_geom(e);
+    for (int s = 0; s < nSides; ++s) ensure_side(s);
+    g_tape.clear();
+    std::vector<Rev> X(n), Y(n);
+    for (size_t i = 0; i < n; ++i) X[i] = Rev::input(U[i]);   // tape nodes 0..n-1
+    std::vector<int> all;
+    rhs<Rev>(X.data(), Y.data(), t, all);
+    std::vector<double> adj(g_tape.size(), 0.0);
+    for (size_t i = 0; i < n; ++i)
+      if (Y[i].i >= 0) adj[Y[i].i] += lam[i];
+    g_tape.sweep(adj);
+    for (size_t i = 0; i < n; ++i) out[i] = adj[i];
+    g_tape.clear();
+  }
+
+  // Gradient of E_k at U (scaled by `scale`), from the tape of kinetic_energy.
+  void kinetic_energy_grad(const double* U, double rho0U0sq, double* grad) {
+    const size_t n = (size_t)5 * nElems * n3;
+    for (int e = 0; e < nElems; ++e) ensure_geom(e);
+    g_tape.clear();
+    std::vector<Rev> X(n);
+    for (size_t i = 0; i < n; ++i) X[i] = Rev::input(U[i]);
+    Rev Ek = kinetic_energy<Rev>(X.data(), rho0U0sq);
+    std::vector<double> adj(g_tape.size(), 0.0);
+    if (Ek.i >= 0) adj[Ek.i] = 1.0;
+    g_tape.sweep(adj);
+    for (size_t i = 0; i < n; ++i) grad[i] = adj[i];
+    g_tape.clear();
+  }
+
+  // Reverse sweep of nsteps steps of the low-storage scheme started from U0.
+  // On entry lamU = dJ/dU at the final state, on exit dJ/dU0.  A stage reads
+  // Y_s (the stage input), dU <- A_s dU + dt R(Y_s, t + c_s dt) and
+  // Y_{s+1} = Y_s + B_s dU; its adjoint, taken for s = S-1 down to 0 with
+  // lamdU = 0 at the end of each step (dU enters a step multiplied by
+  // A_0 = 0), is
+  //   lamdU += B_s lamU;   lamU += dt (dR/dU(Y_s))^T lamdU;   lamdU <- A_s lamdU.
+  // The step states are recomputed forward and kept; each step's stage
+  // inputs are recomputed from its step state.
+  void lserk_adjoint(const double* U0, double* lamU, int nsteps, double dt, double t0) {
+    const size_t n = (size_t)5 * nElems * n3;
+    std::vector<std::vector<double>> Ustep(nsteps);
+    std::vector<double> U(U0, U0 + n);
+    for (int step = 0; step < nsteps; ++step) {
+      Ustep[step] = U;
+      lserk<double>(U.data(), 1, dt, t0 + step * dt);
+    }
+    std::vector<std::vector<double>> Y(nstages, std::vector<double>(n));
+    std::vector<double> dU(n), R(n), lamdU(n), vj(n);
+    std::vector<int> all;
+    for (int step = nsteps - 1; step >= 0; --step) {
+      const double ts = t0 + step * dt;
+      // stage inputs of this step
+      Y[0] = Ustep[step];
+      std::fill(dU.begin(), dU.end(), 0.0);
+      for (int s = 0; s + 1 < nstages; ++s) {
+        rhs<double>(Y[s].data(), R.data(), ts + lsC[s] * dt, all);
+        for (size_t i = 0; i < n; ++i) {
+          dU[i] = lsA[s] * dU[i] + dt * R[i];
+          Y[s + 1][i] = Y[s][i] + lsB[s] * dU[i];
+        }
+      }
+      std::fill(lamdU.begin(), lamdU.end(), 0.0);
+      for (int s = nstages - 1; s >= 0; --s) {
+        for (size_t i = 0; i < n; ++i) lamdU[i] += lsB[s] * lamU[i];
+        rhs_vjp(Y[s].data(), lamdU.data(), vj.data(), ts + lsC[s] * dt);
+        for (size_t i = 0; i < n; ++i) {
+          lamU[i] += dt * vj[i];
+          lamdU[i] = lsA[s] * lamdU[i];
+        }
+      }
+    }
+  }
+
   // Integral kinetic energy (TGV section) with collocated quadrature:
   // E_k = sum w_i w_j w_k J |m|^2/rho / (2 rho0 U0^2 |Omega|),  |Omega| = sum w J.
   template <class T> T kinetic_energy(const T* U, double rho0U0sq) {
@@ -1536,6 +1689,28 @@ int orc_rhs_elems(void* h, const double* U, double* Ut, double t, int nlist, con
   return 0;
 }
 
+// Residual of a list of distinct elements into a compact array out[5][nlist][n3]
+// (element list[i] at position i): the same arithmetic as orc_rhs_elems, with
+// no full-size output.
+int orc_rhs_sample(void* h, const double* U, double* out, double t, int nlist, const int* list) {
+  Solver* S = (Solver*)h;
+  std::vector<int> el(list, list + nlist);
+  std::vector<int> pos(S->nElems, -1);
+  for (int i = 0; i < nlist; ++i) {
+    const int e = el[i];
+    if (e < 0 || e >= S->nElems) { g_err = "element out of range"; return 1; }
+    if (pos[e] >= 0) { g_err = "element listed twice"; return 1; }
+    pos[e] = i;
+  }
+  if (el.empty()) return 0;
+  S->outpos.swap(pos);
+  S->outn = nlist;
+  S->rhs<double>(U, out, t, el);
+  S->outpos.clear();
+  S->outn = 0;
+  return 0;
+}
+
 // Lifted gradients [12][nElems][n3], component 3*a+d = d q_a / d x_d, q=(u,v,w,T).
 int orc_lift(void* h, const double* U, double* g) {
   Solver* S = (Solver*)h;
@@ -1589,6 +1764,25 @@ double orc_kinetic_energy_jvp(void* h, const double* U, const double* dU, double
 double orc_timestep(void* h, const double* U, double cfl) {
   Solver* S = (Solver*)h;
   return S->timestep(U, cfl);
+}
+
+// Transposed residual Jacobian: out = (dR/dU)^T lam (reverse mode, exact).
+int orc_rhs_vjp(void* h, const double* U, const double* lam, double* out, double t) {
+  ((Solver*)h)->rhs_vjp(U, lam, out, t);
+  return 0;
+}
+
+// Gradient of E_k at U (reverse mode).
+int orc_kinetic_energy_grad(void* h, const double* U, double rho0U0sq, double* grad) {
+  ((Solver*)h)->kinetic_energy_grad(U, rho0U0sq, grad);
+  return 0;
+}
+
+// Reverse sweep of a whole trajectory: lamU <- (dU(T)/dU0)^T lamU.
+int orc_lserk_adjoint(void* h, const double* U0, double* lamU, int nsteps, double dt, double t0) {
+  if (nsteps < 0) { g_err = "negative step count"; return 1; }
+  ((Solver*)h)->lserk_adjoint(U0, lamU, nsteps, dt, t0);
+  return 0;
 }
 
 // Operation counts of one residual evaluation: {add/sub, mul, div, sqrt, log}.
@@ -1696,6 +1890,25 @@ void orc_cons_from_entropy(const double* dcfg, const double* v, double* U) {
   Solver S; S.C.gamma = dcfg[0];
   S.cons_from_entropy<double>(v, U);
 }
+// Operation counts {add/sub, mul, div, sqrt, log} of one point function on
+// the counting scalar: kind 0 flux_adv(Ua, nv), 1 logmean(Ua[0], Ub[0]),
+// 2 flux_twopoint(Ua, Ub, nv) (Chandrashekar).
+int orc_opcount_point(int kind, const double* dcfg, const double* Ua, const double* Ub, const double* nv,
+                      uint64_t* counts) {
+  Solver S;
+  S.C.gamma = dcfg[0];
+  orc::Cnt a[5], b[5], F[5];
+  for (int v = 0; v < 5; ++v) { a[v] = orc::Cnt(Ua[v]); b[v] = orc::Cnt(Ub[v]); }
+  orc::Cnt::n_add = orc::Cnt::n_mul = orc::Cnt::n_div = orc::Cnt::n_sqrt = orc::Cnt::n_log = 0;
+  if (kind == 0) S.flux_adv<orc::Cnt>(a, nv, F);
+  else if (kind == 1) F[0] = S.logmean<orc::Cnt>(a[0], b[0]);
+  else if (kind == 2) S.flux_twopoint<orc::Cnt>(a, b, nv, F);
+  else { g_err = "unknown point function"; return 1; }
+  counts[0] = orc::Cnt::n_add; counts[1] = orc::Cnt::n_mul; counts[2] = orc::Cnt::n_div;
+  counts[3] = orc::Cnt::n_sqrt; counts[4] = orc::Cnt::n_log;
+  return 0;
+}
+
 double orc_logmean(double x, double y) {
   Solver S;
   return S.logmean<double>(x, y);

@@ -30,6 +30,16 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+def build_native(out_dir: str) -> str:
+    """The same source compiled with -O3 -march=native for the host it runs on
+    (timing of the CPU baseline only; the parity build above is the one the
+    tests use).  Built into out_dir, since the code is specific to this CPU."""
+    out = os.path.join(out_dir, "liboracle_native.so")
+    cmd = ["g++", "-O3", "-march=native", "-std=c++17", "-fPIC", "-shared", "-o", out, SRC]
+    subprocess.run(cmd, check=True)
+    return out
+
+
 _lib = None
 
 
@@ -38,53 +48,63 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = ctypes.CDLL(LIB)
-        L.orc_last_error.restype = ctypes.c_char_p
-        L.orc_create.restype = ctypes.c_void_p
-        L.orc_create.argtypes = [_ip, _dp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _ip, _ip, _ip]
-        for name in ("orc_destroy",):
-            getattr(L, name).argtypes = [ctypes.c_void_p]
-        L.orc_check_jacobians.argtypes = [ctypes.c_void_p]
-        L.orc_geometry.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
-        L.orc_face_normals.argtypes = [ctypes.c_void_p, _dp]
-        L.orc_rhs.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double]
-        L.orc_rhs_elems.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip]
-        L.orc_lift.argtypes = [ctypes.c_void_p, _dp, _dp]
-        L.orc_rhs_jvp.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.c_double]
-        L.orc_lserk.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
-        L.orc_lserk_jvp.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
-        L.orc_kinetic_energy.restype = ctypes.c_double
-        L.orc_kinetic_energy.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
-        L.orc_kinetic_energy_jvp.restype = ctypes.c_double
-        L.orc_kinetic_energy_jvp.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double]
-        L.orc_timestep.restype = ctypes.c_double
-        L.orc_timestep.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
-        L.orc_rhs_opcount.argtypes = [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_uint64)]
-        L.orc_rk_coeffs.argtypes = [ctypes.c_int, _dp, _dp, _dp]
-        L.orc_rk_coeffs.restype = ctypes.c_int
-        L.orc_viscosity.argtypes = [_ip, _dp, ctypes.c_double]
-        L.orc_viscosity.restype = ctypes.c_double
-        L.orc_roe_matrix.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_int, _dp]
-        L.orc_flux_visc_law.argtypes = [_ip, _dp, _dp, _dp, ctypes.c_int, _dp]
-        L.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
-        L.orc_lserk_coeffs.argtypes = [_dp, _dp, _dp]
-        L.orc_flux_twopoint.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
-        L.orc_flux_adv.argtypes = [_dp, _dp, _dp, _dp]
-        L.orc_flux_visc.argtypes = [_dp, _dp, _dp, ctypes.c_int, _dp]
-        L.orc_fv_set_mask.argtypes = [ctypes.c_void_p, _ip]
-        L.orc_fv_switch.argtypes = [ctypes.c_void_p, _dp, _dp, _ip]
-        L.orc_fv_get_mask.argtypes = [ctypes.c_void_p, _ip]
-        L.orc_fv_indicator.argtypes = [ctypes.c_void_p, _dp, _dp]
-        L.orc_fv_geometry.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
-        L.orc_fv_operators.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
-        L.orc_fv_convert.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp, _dp]
-        L.orc_entropy_vars.argtypes = [_dp, _dp, _dp]
-        L.orc_cons_from_entropy.argtypes = [_dp, _dp, _dp]
-        L.orc_logmean.restype = ctypes.c_double
-        L.orc_logmean.argtypes = [ctypes.c_double, ctypes.c_double]
-        L.orc_mms_source.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
-        _lib = L
+        _lib = load(LIB)
     return _lib
+
+
+def load(path):
+    """ctypes handle of an oracle build with every signature declared."""
+    L = ctypes.CDLL(path)
+    L.orc_last_error.restype = ctypes.c_char_p
+    L.orc_create.restype = ctypes.c_void_p
+    L.orc_create.argtypes = [_ip, _dp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _ip, _ip, _ip]
+    for name in ("orc_destroy",):
+        getattr(L, name).argtypes = [ctypes.c_void_p]
+    L.orc_check_jacobians.argtypes = [ctypes.c_void_p]
+    L.orc_geometry.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+    L.orc_face_normals.argtypes = [ctypes.c_void_p, _dp]
+    L.orc_rhs.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double]
+    L.orc_rhs_elems.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip]
+    L.orc_lift.argtypes = [ctypes.c_void_p, _dp, _dp]
+    L.orc_rhs_jvp.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.c_double]
+    L.orc_lserk.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    L.orc_lserk_jvp.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    L.orc_kinetic_energy.restype = ctypes.c_double
+    L.orc_kinetic_energy.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
+    L.orc_kinetic_energy_jvp.restype = ctypes.c_double
+    L.orc_kinetic_energy_jvp.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double]
+    L.orc_timestep.restype = ctypes.c_double
+    L.orc_timestep.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
+    L.orc_rhs_opcount.argtypes = [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_uint64)]
+    L.orc_rk_coeffs.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+    L.orc_rk_coeffs.restype = ctypes.c_int
+    L.orc_viscosity.argtypes = [_ip, _dp, ctypes.c_double]
+    L.orc_viscosity.restype = ctypes.c_double
+    L.orc_roe_matrix.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_int, _dp]
+    L.orc_flux_visc_law.argtypes = [_ip, _dp, _dp, _dp, ctypes.c_int, _dp]
+    L.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_lserk_coeffs.argtypes = [_dp, _dp, _dp]
+    L.orc_flux_twopoint.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
+    L.orc_flux_adv.argtypes = [_dp, _dp, _dp, _dp]
+    L.orc_flux_visc.argtypes = [_dp, _dp, _dp, ctypes.c_int, _dp]
+    L.orc_fv_set_mask.argtypes = [ctypes.c_void_p, _ip]
+    L.orc_fv_switch.argtypes = [ctypes.c_void_p, _dp, _dp, _ip]
+    L.orc_fv_get_mask.argtypes = [ctypes.c_void_p, _ip]
+    L.orc_fv_indicator.argtypes = [ctypes.c_void_p, _dp, _dp]
+    L.orc_fv_geometry.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+    L.orc_fv_operators.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+    L.orc_fv_convert.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp, _dp]
+    L.orc_entropy_vars.argtypes = [_dp, _dp, _dp]
+    L.orc_cons_from_entropy.argtypes = [_dp, _dp, _dp]
+    L.orc_logmean.restype = ctypes.c_double
+    L.orc_logmean.argtypes = [ctypes.c_double, ctypes.c_double]
+    L.orc_mms_source.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+    L.orc_rhs_sample.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip]
+    L.orc_opcount_point.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_uint64)]
+    L.orc_rhs_vjp.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_double]
+    L.orc_kinetic_energy_grad.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, _dp]
+    L.orc_lserk_adjoint.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    return L
 
 
 def _d(a):
@@ -199,6 +219,22 @@ def cons_from_entropy(v, gamma=1.4):
     return U
 
 
+def opcount_point(kind, Ua, Ub=None, nv=(1.0, 0.0, 0.0), gamma=1.4):
+    """Operation counts of one point function on the counting scalar: kind
+    "flux_adv" (Ua, nv), "logmean" (Ua[0], Ub[0]) or "twopoint" (Ua, Ub, nv)."""
+    _, dcfg = _cfg_arrays(dict(gamma=gamma))
+    k = {"flux_adv": 0, "logmean": 1, "twopoint": 2}[kind]
+    a = np.zeros(5)
+    a[:len(np.atleast_1d(Ua))] = np.atleast_1d(Ua)
+    b = np.zeros(5)
+    if Ub is not None:
+        b[:len(np.atleast_1d(Ub))] = np.atleast_1d(Ub)
+    c = (ctypes.c_uint64 * 5)()
+    if lib().orc_opcount_point(k, _d(dcfg), _d(a), _d(b), _d(np.ascontiguousarray(nv, dtype=np.float64)), c):
+        raise ValueError(lib().orc_last_error().decode())
+    return dict(add=c[0], mul=c[1], div=c[2], sqrt=c[3], log=c[4])
+
+
 def logmean(x, y):
     return lib().orc_logmean(float(x), float(y))
 
@@ -213,7 +249,8 @@ def mms_source(x, y, z, t, gamma=1.4, mu=1e-3, Pr=0.72, R=1.0, A=0.1, a=1.0):
 class Oracle:
     """One discretisation (config + mesh) in the oracle."""
 
-    def __init__(self, cfg: dict, mesh):
+    def __init__(self, cfg: dict, mesh, library=None):
+        self.L = library if library is not None else lib()
         self.cfg = dict(cfg)
         self.mesh = mesh
         self.N = int(cfg["N"])
@@ -223,16 +260,16 @@ class Oracle:
         icfg, dcfg = _cfg_arrays(cfg)
         X = np.ascontiguousarray(mesh.X, dtype=np.float64)
         self._keep = (X, mesh.sideElem, mesh.sideLoc, mesh.sideOrient)
-        h = lib().orc_create(_i(icfg), _d(dcfg), mesh.nElems, mesh.Ngeo, _d(X), mesh.nSides,
-                             _i(mesh.sideElem), _i(mesh.sideLoc), _i(mesh.sideOrient))
+        h = self.L.orc_create(_i(icfg), _d(dcfg), mesh.nElems, mesh.Ngeo, _d(X), mesh.nSides,
+                              _i(mesh.sideElem), _i(mesh.sideLoc), _i(mesh.sideOrient))
         if not h:
-            raise ValueError("oracle: " + lib().orc_last_error().decode())
+            raise ValueError("oracle: " + self.L.orc_last_error().decode())
         self.h = ctypes.c_void_p(h)
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and _lib is not None:
-            _lib.orc_destroy(h)
+        if h is not None and getattr(self, "L", None) is not None:
+            self.L.orc_destroy(h)
             self.h = None
 
     @property
@@ -240,15 +277,15 @@ class Oracle:
         return (5, self.nElems, self.n1, self.n1, self.n1)
 
     def check_jacobians(self):
-        if lib().orc_check_jacobians(self.h):
-            raise ValueError(lib().orc_last_error().decode())
+        if self.L.orc_check_jacobians(self.h):
+            raise ValueError(self.L.orc_last_error().decode())
 
     def geometry(self):
         n = self.n1
         xyz = np.zeros((3, self.nElems, n, n, n))
         J = np.zeros((self.nElems, n, n, n))
         Ja = np.zeros((9, self.nElems, n, n, n))
-        lib().orc_geometry(self.h, _d(xyz), _d(J), _d(Ja))
+        self.L.orc_geometry(self.h, _d(xyz), _d(J), _d(Ja))
         return xyz, J, Ja
 
     def coords(self):
@@ -256,13 +293,13 @@ class Oracle:
 
     def face_normals(self):
         nv = np.zeros((3, self.nSides, self.n1, self.n1))
-        lib().orc_face_normals(self.h, _d(nv))
+        self.L.orc_face_normals(self.h, _d(nv))
         return nv
 
     def rhs(self, U, t=0.0):
         U = np.ascontiguousarray(U, dtype=np.float64)
         Ut = np.zeros_like(U)
-        lib().orc_rhs(self.h, _d(U), _d(Ut), float(t))
+        self.L.orc_rhs(self.h, _d(U), _d(Ut), float(t))
         return Ut
 
     def rhs_elems(self, U, elems, t=0.0):
@@ -270,59 +307,92 @@ class Oracle:
         U = np.ascontiguousarray(U, dtype=np.float64)
         el = np.ascontiguousarray(np.asarray(elems, dtype=np.int32))
         Ut = np.zeros_like(U)
-        if lib().orc_rhs_elems(self.h, _d(U), _d(Ut), float(t), int(el.size), _i(el)):
-            raise ValueError(lib().orc_last_error().decode())
+        if self.L.orc_rhs_elems(self.h, _d(U), _d(Ut), float(t), int(el.size), _i(el)):
+            raise ValueError(self.L.orc_last_error().decode())
         return Ut[:, el]
+
+    def rhs_sample(self, U, elems, t=0.0):
+        """Residual of the listed (distinct) elements, written straight into an
+        array [5][len(elems)][n][n][n] (no full-size output)."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        el = np.ascontiguousarray(np.asarray(elems, dtype=np.int32))
+        n = self.n1
+        out = np.empty((5, el.size, n, n, n))
+        if self.L.orc_rhs_sample(self.h, _d(U), _d(out), float(t), int(el.size), _i(el)):
+            raise ValueError(self.L.orc_last_error().decode())
+        return out
 
     def lift(self, U):
         U = np.ascontiguousarray(U, dtype=np.float64)
         n = self.n1
         g = np.zeros((12, self.nElems, n, n, n))
-        lib().orc_lift(self.h, _d(U), _d(g))
+        self.L.orc_lift(self.h, _d(U), _d(g))
         return g
 
     def rhs_jvp(self, U, dU, t=0.0):
         U = np.ascontiguousarray(U, dtype=np.float64)
         dU = np.ascontiguousarray(dU, dtype=np.float64).reshape(U.shape)
         Ut, dUt = np.zeros_like(U), np.zeros_like(U)
-        lib().orc_rhs_jvp(self.h, _d(U), _d(dU), _d(Ut), _d(dUt), float(t))
+        self.L.orc_rhs_jvp(self.h, _d(U), _d(dU), _d(Ut), _d(dUt), float(t))
         return Ut, dUt
 
     def lserk(self, U, nsteps, dt, t0=0.0):
         U = np.array(U, dtype=np.float64, copy=True, order="C")
-        lib().orc_lserk(self.h, _d(U), int(nsteps), float(dt), float(t0))
+        self.L.orc_lserk(self.h, _d(U), int(nsteps), float(dt), float(t0))
         return U
 
     def lserk_jvp(self, U, dU, nsteps, dt, t0=0.0):
         U = np.array(U, dtype=np.float64, copy=True, order="C")
         dU = np.array(dU, dtype=np.float64, copy=True, order="C").reshape(U.shape)
-        lib().orc_lserk_jvp(self.h, _d(U), _d(dU), int(nsteps), float(dt), float(t0))
+        self.L.orc_lserk_jvp(self.h, _d(U), _d(dU), int(nsteps), float(dt), float(t0))
         return U, dU
 
+    def rhs_vjp(self, U, lam, t=0.0):
+        """(dR/dU)^T lam at U, by reverse-mode differentiation of the residual."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64).reshape(U.shape)
+        out = np.zeros_like(U)
+        self.L.orc_rhs_vjp(self.h, _d(U), _d(lam), _d(out), float(t))
+        return out
+
+    def kinetic_energy_grad(self, U, rho0U0sq=1.0):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        g = np.zeros_like(U)
+        self.L.orc_kinetic_energy_grad(self.h, _d(U), float(rho0U0sq), _d(g))
+        return g
+
+    def lserk_adjoint(self, U0, lamT, nsteps, dt, t0=0.0):
+        """(dU(T)/dU0)^T lamT through nsteps steps of the context's RK scheme
+        (the reverse sweep of the 2N-storage stages, stage inputs recomputed)."""
+        U0 = np.ascontiguousarray(U0, dtype=np.float64)
+        lam = np.array(lamT, dtype=np.float64, copy=True, order="C").reshape(U0.shape)
+        self._chk(self.L.orc_lserk_adjoint(self.h, _d(U0), _d(lam), int(nsteps), float(dt), float(t0)))
+        return lam
+
     def kinetic_energy(self, U, rho0U0sq=1.0):
-        return lib().orc_kinetic_energy(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), float(rho0U0sq))
+        return self.L.orc_kinetic_energy(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), float(rho0U0sq))
 
     def kinetic_energy_jvp(self, U, dU, rho0U0sq=1.0):
         U = np.ascontiguousarray(U, dtype=np.float64)
         dU = np.ascontiguousarray(dU, dtype=np.float64).reshape(U.shape)
-        return lib().orc_kinetic_energy_jvp(self.h, _d(U), _d(dU), float(rho0U0sq))
+        return self.L.orc_kinetic_energy_jvp(self.h, _d(U), _d(dU), float(rho0U0sq))
 
     def timestep(self, U, cfl=0.9):
-        return lib().orc_timestep(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), float(cfl))
+        return self.L.orc_timestep(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), float(cfl))
 
     # FV sub-cells (config fv=1, Euler)
     def _chk(self, rc):
         if rc:
-            raise ValueError(lib().orc_last_error().decode())
+            raise ValueError(self.L.orc_last_error().decode())
 
     def fv_set_mask(self, mask):
         m = np.ascontiguousarray(np.asarray(mask, dtype=np.int32).reshape(-1))
         assert m.size == self.nElems
-        self._chk(lib().orc_fv_set_mask(self.h, _i(m)))
+        self._chk(self.L.orc_fv_set_mask(self.h, _i(m)))
 
     def fv_mask(self):
         m = np.zeros(self.nElems, dtype=np.int32)
-        lib().orc_fv_get_mask(self.h, _i(m))
+        self.L.orc_fv_get_mask(self.h, _i(m))
         return m
 
     def fv_switch(self, U, dU, newmask):
@@ -330,12 +400,12 @@ class Oracle:
         U = np.array(U, dtype=np.float64, copy=True, order="C")
         dU = None if dU is None else np.array(dU, dtype=np.float64, copy=True, order="C")
         m = np.ascontiguousarray(np.asarray(newmask, dtype=np.int32).reshape(-1))
-        self._chk(lib().orc_fv_switch(self.h, _d(U), _d(dU) if dU is not None else None, _i(m)))
+        self._chk(self.L.orc_fv_switch(self.h, _d(U), _d(dU) if dU is not None else None, _i(m)))
         return U, dU
 
     def indicator(self, U):
         ind = np.zeros(self.nElems)
-        lib().orc_fv_indicator(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), _d(ind))
+        self.L.orc_fv_indicator(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), _d(ind))
         return ind
 
     def fv_geometry(self):
@@ -343,22 +413,22 @@ class Oracle:
         V = np.zeros((self.nElems, n, n, n))
         Si = np.zeros((self.nElems, 3, 3, self.N, n, n))
         Sb = np.zeros((self.nSides, 3, n, n))
-        self._chk(lib().orc_fv_geometry(self.h, _d(V), _d(Si), _d(Sb)))
+        self._chk(self.L.orc_fv_geometry(self.h, _d(V), _d(Si), _d(Sb)))
         return V, Si, Sb
 
     def fv_operators(self):
         n = self.n1
         B, Bi, Vi = np.zeros((n, n)), np.zeros((n, n)), np.zeros((n, n))
-        self._chk(lib().orc_fv_operators(self.h, _d(B), _d(Bi), _d(Vi)))
+        self._chk(self.L.orc_fv_operators(self.h, _d(B), _d(Bi), _d(Vi)))
         return B, Bi, Vi
 
     def fv_convert(self, e, block, to_fv=True):
         b = np.ascontiguousarray(block, dtype=np.float64)
         out = np.zeros_like(b)
-        self._chk(lib().orc_fv_convert(self.h, int(e), 0 if to_fv else 1, _d(b), _d(out)))
+        self._chk(self.L.orc_fv_convert(self.h, int(e), 0 if to_fv else 1, _d(b), _d(out)))
         return out
 
     def opcount(self, U):
         c = (ctypes.c_uint64 * 5)()
-        lib().orc_rhs_opcount(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), c)
+        self.L.orc_rhs_opcount(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), c)
         return dict(add=c[0], mul=c[1], div=c[2], sqrt=c[3], log=c[4])

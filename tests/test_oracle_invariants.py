@@ -322,21 +322,102 @@ def test_viscous_timestep_is_linearly_stable(orc, N):
     assert _growth(orc, cfg, slow, dt_fac=2.5) > 1.05
 
 
+# Hand counts of the oracle's arithmetic as written (an operation between two
+# plain doubles is not counted, an operation with a counted operand is; a
+# sign change is free).  (add, mul, div, sqrt, log):
+#   prim:      u = m/rho (3 div); |u|^2 (3 mul, 2 add); 0.5 rho |u|^2 (2 mul);
+#              E - that (1 add); (gamma-1) x (1 mul)           -> (3, 6, 3, 0, 0)
+#   flux_adv:  prim; u.n (3 mul, 2 add); rho u.n (1 mul);
+#              m u.n + p n (6 mul, 3 add); (E+p) u.n (1 add, 1 mul) -> (9, 17, 3, 0, 0)
+#   logmean:   f = (x-y)/(x+y) (2 add, 1 div), u = f^2 (1 mul); series branch:
+#              Horner in u (3 mul, 3 add), (x+y) (1 add), division (1 div)
+#              -> (6, 4, 2, 0, 0); log branch: (x-y), ln x - ln y (2 add, 2 log),
+#              division (1 div) -> (4, 1, 2, 0, 2)
+#   twopoint:  2 prim (6, 12, 6); beta = rho/(2p) twice (2 mul, 2 div); mean
+#              velocity (3 add, 3 mul); p^ = {rho}/(2{beta}) (2 add, 3 mul,
+#              1 div); {|u|^2} (5 add, 7 mul); {u}.n (2 add, 3 mul); F_rho
+#              (1 mul); F_m (3 add, 6 mul); F_E (4 add, 6 mul, 1 div)
+#              -> (25, 43, 10, 0, 0) plus two log means
+FLUX_ADV = (9, 17, 3, 0, 0)
+LOGMEAN_SERIES = (6, 4, 2, 0, 0)
+LOGMEAN_LOG = (4, 1, 2, 0, 2)
+TWOPOINT_BASE = (25, 43, 10, 0, 0)
+
+
+def _t(c):
+    return (c["add"], c["mul"], c["div"], c["sqrt"], c["log"])
+
+
+def _add(*xs, k=None):
+    out = [0] * 5
+    for i, x in enumerate(xs):
+        f = 1 if k is None else k[i]
+        for j in range(5):
+            out[j] += f * x[j]
+    return tuple(out)
+
+
+def test_operation_count_point_functions(orc):
+    U = [1.0, 0.1, 0.2, 0.3, 3.0]
+    nv = (0.3, 0.4, 0.5)
+    assert _t(orc.opcount_point("flux_adv", U, nv=nv)) == FLUX_ADV
+    assert _t(orc.opcount_point("logmean", [1.0], [1.001])) == LOGMEAN_SERIES
+    assert _t(orc.opcount_point("logmean", [1.0], [1.5])) == LOGMEAN_LOG
+    near = [1.001, 0.1, 0.2, 0.3, 3.001]      # both log means on the series branch
+    far = [1.5, 0.1, 0.2, 0.3, 4.0]           # both on the log branch
+    assert _t(orc.opcount_point("twopoint", U, near, nv=nv)) == _add(TWOPOINT_BASE, LOGMEAN_SERIES, LOGMEAN_SERIES)
+    assert _t(orc.opcount_point("twopoint", U, far, nv=nv)) == _add(TWOPOINT_BASE, LOGMEAN_LOG, LOGMEAN_LOG)
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_operation_count_single_element(orc, form):
+    """The whole residual of one periodic element at N = 1 (n1 = 2: 4 face
+    nodes per face, 8 nodes), Euler, Rusanov, LGL nodes, constant state (every
+    log mean on the series branch), counted by hand:
+
+    * traces, 3 sides x 2 slots x 4 face nodes x 2 line nodes x 5 variables,
+      acc += l x U: (240, 240, 0, 0, 0);
+    * surface flux per face node: central part (weak: two flux_adv and the
+      mean, 5 add + 5 mul; split: twopoint); Rusanov: two prim, two sound
+      speeds sqrt(gamma p / rho) (2 mul, 2 div, 2 sqrt), two u.n (4 add,
+      6 mul), |u.n| + c (2 add), Phi_v = F_v - 0.5 (lmax s)(UR_v - UL_v)
+      (10 add, 15 mul); 12 face nodes;
+    * volume: per node and direction F~^r (weak: flux_adv; split: none), the
+      D-hat sweep over 2 line nodes (10 add, 10 mul, also in the split form,
+      where F~ holds the zero viscous flux); split: the one pair per node and
+      direction, twopoint plus 5 add + 5 mul; 8 nodes;
+    * surface lift: 6 faces x 4 face nodes x 2 line nodes x 5 variables
+      (240 add, 240 mul); 1/J: 40 div.
+    """
+    mesh = I.box_mesh((1, 1, 1), (0.0,) * 3, (2.0,) * 3)
+    o = orc.Oracle(dict(N=1, nodes=1, form=form, physics=0), mesh)
+    U = np.zeros(o.state_shape)
+    U[0], U[1], U[2], U[3], U[4] = 1.0, 0.1, -0.2, 0.3, 2.5
+    prim = (3, 6, 3, 0, 0)
+    twop = _add(TWOPOINT_BASE, LOGMEAN_SERIES, LOGMEAN_SERIES)
+    central = _add(FLUX_ADV, FLUX_ADV, (5, 5, 0, 0, 0)) if form == 0 else twop
+    rusanov = _add(prim, prim, (0, 2, 2, 2, 0), (4, 6, 0, 0, 0), (2, 0, 0, 0, 0), (10, 15, 0, 0, 0))
+    traces = (240, 240, 0, 0, 0)
+    faces = _add(central, rusanov, k=(12, 12))
+    per_node = _add(FLUX_ADV, (10, 10, 0, 0, 0), k=(3, 3)) if form == 0 else \
+        _add((10, 10, 0, 0, 0), twop, (5, 5, 0, 0, 0), k=(3, 3, 3))
+    volume = _add(per_node, k=(8,))
+    lift = (240, 240, 40, 0, 0)
+    expect = _add(traces, faces, volume, lift)
+    assert _t(o.opcount(U)) == expect
+    assert expect == ((1476, 2016, 280, 24, 0) if form == 0 else (2436, 3096, 640, 24, 0))
+
+
 def test_operation_count_is_per_dof(orc):
-    """The op-counting scalar's residual counts scale with the number of
-    elements (work per node does not depend on the mesh size, up to the
-    log-mean branch each pair takes), and the split
-    form costs more per node than the weak form at the same N."""
+    """With a constant state every pair takes the same log-mean branch, so the
+    counts per node do not depend on the mesh: doubling the elements doubles
+    every count exactly."""
     counts = []
     for K in ((2, 2, 2), (2, 2, 4)):
         mesh = I.box_mesh(K, (-PI,) * 3, (PI,) * 3)
         o = orc.Oracle(dict(N=3, nodes=1, form=1, physics=1, mu=0.01), mesh)
-        c = o.opcount(I.smooth_random_state(o.coords(), 3, amp=0.2))
-        counts.append(c)
-    # (the log-mean branch taken varies with the state, hence 1 %)
-    for k in ("add", "mul", "div"):
-        assert abs(counts[1][k] - 2 * counts[0][k]) < 0.01 * 2 * counts[0][k], (k, counts)
-    mesh = I.box_mesh((2, 2, 2), (-PI,) * 3, (PI,) * 3)
-    weak = orc.Oracle(dict(N=3, nodes=1, form=0, physics=1, mu=0.01), mesh)
-    cw = weak.opcount(I.smooth_random_state(weak.coords(), 3, amp=0.2))
-    assert sum(counts[0].values()) > 1.3 * sum(cw.values())
+        U = np.zeros(o.state_shape)
+        U[0], U[1], U[4] = 1.0, 0.2, 2.5
+        counts.append(o.opcount(U))
+    for k in ("add", "mul", "div", "sqrt", "log"):
+        assert counts[1][k] == 2 * counts[0][k], (k, counts)
