@@ -2,10 +2,12 @@
 
 A step is one LSERK4(5) time step (five evaluations of the whole residual:
 BR1 lifting, surface fluxes, split-form volume integral, surface lift,
-Jacobian scaling, RK update) of the Navier-Stokes Taylor-Green vortex
-workload: N=7 on Lobatto nodes, 16^3 periodic hexahedra on [-pi,pi]^3,
-Ma 0.1, Re 1600, Pr 0.72, FP64.  The metric is the paper's PID
-(wall time / (RK stages * DOF), one GPU), lower is better.
+Jacobian scaling, RK update) of the large single-GPU Navier-Stokes
+Taylor-Green vortex workload: N=7 on Lobatto nodes, 64^3 periodic
+hexahedra on [-pi,pi]^3 (134 M nodes), Ma 0.1, Re 1600, Pr 0.72, FP64.  The
+metric is the paper's PID (wall time / (RK stages * DOF), one GPU), lower is
+better.  The adjoint/forward cost is taken over a 50-step trajectory whose
+checkpoint interval is sized to the free HBM.
 
 Printed as one JSON line.  Besides the contract fields it carries the
 FP32-flux PID on the same workload and its error against the FP64 path,
@@ -33,7 +35,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "ns_split_lgl_n7_16x16x16_tgv"
+WORKLOAD = "ns_split_lgl_n7_64x64x64_tgv"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 KERNEL_SOURCES = ("dgx_kernels.hpp", "dgx_pointwise.hpp", "dgx_internal.hpp", "dgx_inst.hip", "dgx_tile.hpp",
@@ -71,10 +73,13 @@ def parse():
     ap.add_argument("--fv", default="none", choices=["none", "zero", "checker", "all"],
                     help="FV sub-cell elements (Euler workloads): none (a DG-only context), zero (an FV "
                          "context with every element on DG), a checkerboard half, or all")
-    ap.add_argument("--adjoint-steps", type=int, default=4)
-    ap.add_argument("--checkpoint-every", type=int, default=None)
-    ap.add_argument("--cpu-sample-elems", type=int, default=4096)
-    ap.add_argument("--cpu-repeats", type=int, default=3)
+    ap.add_argument("--adjoint-steps", type=int, default=50)
+    ap.add_argument("--checkpoint-every", type=int, default=None,
+                    help="steps between checkpoints (default: sized to the free HBM)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="target length of the timed oracle sample (the element count follows from a warm call)")
+    ap.add_argument("--cpu-sample-elems", type=int, default=None, help="fixed oracle sample size (elements)")
+    ap.add_argument("--cpu-repeats", type=int, default=2)
     ap.add_argument("--cpu-procs", type=int, default=1,
                     help="also run this many independent oracle processes at once (aggregate host throughput)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -128,19 +133,53 @@ def profile_path(workload):
     return os.path.join(ROOT, "profiles", f"k_volume_{workload}.md")
 
 
-def profile_counters(workload, kernel):
-    """Counters of one kernel from the committed rocprofv3 summary of a workload:
-    calibrated HBM bytes read and written and FP64 FLOPs per launch, or None
-    when there is none or the kernel sources have changed since it was taken."""
+def profile_meta(workload):
+    """Machine-readable block of the committed rocprofv3 summary of a workload,
+    or None when there is none or the kernel sources have changed since it
+    was taken."""
     import re
     try:
         txt = open(profile_path(workload)).read()
         meta = json.loads(re.search(r"```json\n(.*?)\n```", txt, re.S).group(1))
         if kernel_source_hash() != meta["source_sha256_16"]:
             return None
-        return meta["kernels"][kernel]
+        return meta
     except (OSError, KeyError, AttributeError, ValueError):
         return None
+
+
+def profile_counters(workload, kernel):
+    """Counters of one kernel from the committed summary: calibrated HBM bytes
+    read and written and FP64 FLOPs per launch (None if absent or stale)."""
+    meta = profile_meta(workload)
+    try:
+        return meta["kernels"][kernel] if meta else None
+    except KeyError:
+        return None
+
+
+def kernel_counter_table(workload):
+    """Per-kernel rates from the committed summary: measured HBM bytes per
+    launch over the profiled average duration, and FP64 FLOP/s, each against
+    the chip's peak (None if absent or stale)."""
+    meta = profile_meta(workload)
+    if not meta:
+        return None
+    out = {}
+    for name, k in meta["kernels"].items():
+        us = k.get("avg_us") or 0.0
+        if us <= 0:
+            continue
+        gbs = (k["read"] + k["write"]) / (us * 1e-6) / 1e9
+        row = {"avg_us": us, "hbm_bytes": k["read"] + k["write"], "hbm_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+        if k.get("flops"):
+            tf = k["flops"] / (us * 1e-6) / 1e12
+            row.update(fp64_TFLOPs=tf, fp64_frac=tf / FP64_PEAK_TFLOPS)
+        if k.get("alg_bytes"):
+            row.update(alg_bytes=k["alg_bytes"], alg_GBs=k["alg_bytes"] / (us * 1e-6) / 1e9)
+        out[name] = row
+    return {"source": "committed rocprofv3 summary " + os.path.relpath(profile_path(workload), ROOT),
+            "kernels": out}
 
 
 def workload_cfg(name):
@@ -245,7 +284,8 @@ def main():
     s = DGSolver(cfg, mesh, dev)
     dof = s.nElems * s.npe
     xyz = s.coords()
-    U0 = s.init_state(I.workload_state(args.workload, xyz, state=args.state))
+    U_host = I.workload_state(args.workload, xyz, state=args.state)
+    U0 = s.init_state(U_host)
     dt = s.timestep(U0, 0.9)
     nfv = 0
     if args.fv != "none":
@@ -382,6 +422,8 @@ def main():
                                                   "from the committed rocprofv3 summary"}
     if lift_n:
         result["kernels_ms_per_launch"]["lift"] = lift_ms / lift_n
+    if default_run and args.fv == "none":
+        result["kernel_counters"] = kernel_counter_table(args.workload)
     if not args.no_fp32:
         cfg32 = dict(cfg, precision=1)
         s32 = DGSolver(cfg32, mesh, dev)
@@ -418,7 +460,7 @@ def main():
                                       if not args.no_adjoint and adjoint_ok else None)
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle)")
-        result["cpu_baseline"] = cpu_baseline(args, cfg, mesh, xyz, pid64)
+        result["cpu_baseline"] = cpu_baseline(args, cfg, mesh, U_host, pid64)
     print(json.dumps(result), flush=True)
     s.close()
 
@@ -433,12 +475,13 @@ def adjoint_cost(cfg, mesh, dev, U0, dt, args):
     n = args.adjoint_steps
     every = args.checkpoint_every or checkpoint_interval(sa, n)
     times = []
-    for rep in range(2):          # the first repetition warms up
-        _log("adjoint repetition", rep + 1, "of 2:", n, "steps, checkpoints every", every)
+    # a 2-step trajectory loads and warms the adjoint kernels; the 50-step one is timed
+    for rep, (ns, ev) in enumerate(((min(2, n), 1), (n, every))):
+        _log("adjoint", "warm-up:" if rep == 0 else "timed:", ns, "steps, checkpoints every", ev)
         U = U0.clone().requires_grad_(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        J = kinetic_energy(sa, trajectory(sa, U, dt, n, checkpoint_every=every))
+        J = kinetic_energy(sa, trajectory(sa, U, dt, ns, checkpoint_every=ev))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         J.backward()
@@ -452,69 +495,98 @@ def adjoint_cost(cfg, mesh, dev, U0, dt, args):
             "note": "backward includes the recomputation of step and stage states"}
 
 
-def _oracle_sample_time(workload, K, state, nel, repeats, fv="none"):
-    """Seconds for `repeats` oracle residuals of elements 0..nel-1 of a workload
-    (run in a process of its own for the all-cores figure)."""
+def host_info():
+    """Host CPU model, logical CPU count and the CPUs this process may run on."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        info["model"] = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return info
+
+
+def _oracle_sample(workload, K, state, fv, library, nel, repeats, U=None):
+    """Timed oracle residuals of elements 0..nel-1 of a workload, after an
+    untimed warm call over the same elements (it builds their lazily computed
+    geometry).  Each call writes only the sampled elements' residual."""
     from oracle import oracle as O
     from paper_2605_28627_amd import inputs as I
     _, cfg = workload_cfg(workload)
     mesh = I.workload_mesh(workload, K=K)
     if fv != "none":
         cfg["fv"] = 1
-    o = O.Oracle(cfg, mesh)
+    o = O.Oracle(cfg, mesh, library=O.load(library))
     if fv != "none":
         o.fv_set_mask(fv_mask(fv, K or tuple(I.WORKLOADS[workload]["K"])))
-    U = I.workload_state(workload, o.coords(), state=state)
+    if U is None:
+        U = I.workload_state(workload, o.coords(), state=state)
     el = list(range(nel))
+    o.rhs_sample(U, el)
     t0 = time.perf_counter()
     for _ in range(repeats):
-        o.rhs_elems(U, el)
+        o.rhs_sample(U, el)
     return time.perf_counter() - t0
 
 
-def cpu_baseline(args, cfg, mesh, xyz, pid_gpu):
-    """The serial FP64 oracle on the host: residual of a contiguous block of
-    elements of the same workload (one RK stage's worth of work per node), on
-    one thread; with --cpu-procs P > 1 also P such processes at once."""
+def cpu_baseline(args, cfg, mesh, U, pid_gpu):
+    """The serial FP64 oracle on the host, built -O3 -march=native for this
+    CPU: residuals of a contiguous block of elements of the same workload (one
+    RK stage's worth of work per node), on one thread, after an untimed warm
+    call; with --cpu-procs P > 1 also P such processes at once.  The block is
+    sized from a warm call on 64 elements so that the timed loop takes about
+    --cpu-seconds."""
+    import tempfile
     from oracle import oracle as O
     from paper_2605_28627_amd import inputs as I
-    o = O.Oracle(cfg, mesh)
+    tmp = tempfile.mkdtemp(prefix="dgx_oracle_")
+    library = O.build_native(tmp)
+    K = tuple(int(x) for x in args.K.split(",")) if args.K else tuple(I.WORKLOADS[args.workload]["K"])
+    o = O.Oracle(cfg, mesh, library=O.load(library))
     if args.fv != "none":
-        # element types as on the GPU; the state's values do not change the work
-        K = tuple(int(x) for x in args.K.split(",")) if args.K else tuple(I.WORKLOADS[args.workload]["K"])
         o.fv_set_mask(fv_mask(args.fv, K))
-    U = I.workload_state(args.workload, xyz, state=args.state)
-    nel = min(args.cpu_sample_elems, mesh.nElems)
+    npe = (cfg["N"] + 1) ** 3
+    nel = args.cpu_sample_elems
+    if nel is None:
+        probe = list(range(min(64, mesh.nElems)))
+        o.rhs_sample(U, probe)
+        t0 = time.perf_counter()
+        o.rhs_sample(U, probe)
+        per_el = (time.perf_counter() - t0) / len(probe)
+        nel = int(args.cpu_seconds / (args.cpu_repeats * per_el))
+    nel = max(1, min(nel, mesh.nElems))
     el = list(range(nel))
+    o.rhs_sample(U, el)                      # warm: the sample's geometry
     t0 = time.perf_counter()
     for _ in range(args.cpu_repeats):
-        o.rhs_elems(U, el)
+        o.rhs_sample(U, el)
     t = time.perf_counter() - t0
-    npe = (cfg["N"] + 1) ** 3
     pid = t / (args.cpu_repeats * nel * npe)
     out = {"value": pid, "unit": "s/(DOF*stage)", "cores": 1, "kind": "oracle",
            "sample": f"{args.cpu_repeats} residual evaluations of elements 0..{nel - 1} of the {mesh.nElems}-element "
-                     f"workload ({nel * npe} DOF each, serial, one thread), {t:.1f} s",
-           "gpu_over_cpu_per_rank": pid / pid_gpu}
+                     f"workload ({nel * npe} DOF each, serial, one thread, after one untimed warm call; only the "
+                     f"sampled elements' residual is written), {t:.1f} s",
+           "build": "g++ -O3 -march=native (the oracle source, built on this host)",
+           "gpu_over_cpu_per_rank": pid / pid_gpu,
+           "host": host_info()}
     if args.cpu_procs > 1:
         import multiprocessing as mp
-        K = tuple(int(x) for x in args.K.split(",")) if args.K else None
         P = args.cpu_procs
+        Kp = tuple(int(x) for x in args.K.split(",")) if args.K else None
         with mp.get_context("spawn").Pool(P) as pool:
             t0 = time.perf_counter()
-            ts = pool.starmap(_oracle_sample_time, [(args.workload, K, args.state, nel, args.cpu_repeats, args.fv)] * P)
+            ts = pool.starmap(_oracle_sample, [(args.workload, Kp, args.state, args.fv, library, nel,
+                                                args.cpu_repeats)] * P)
             wall = time.perf_counter() - t0
         pid_all = max(ts) / (P * args.cpu_repeats * nel * npe)
         out["all_cores"] = {"procs": P, "pid_aggregate": pid_all, "dof_updates_per_s": 1.0 / pid_all,
                             "per_process_s": ts, "wall_s_incl_setup": wall,
                             "gpu_over_all_cores": pid_all / pid_gpu,
                             "note": "independent oracle processes on the same sample at once; aggregate over the "
-                                    "slowest process's timed loop (set-up excluded)"}
-        try:
-            out["host"] = {"nproc": os.cpu_count(), "model": next(
-                l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))}
-        except (OSError, StopIteration):
-            pass
+                                    "slowest process's timed loop (set-up and warm call excluded)"}
     return out
 
 

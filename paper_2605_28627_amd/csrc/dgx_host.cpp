@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/dgx.h"
@@ -222,6 +223,16 @@ static void apply_dim(const double* M, int rows, int cols, const double* in, int
         }
         out[((size_t)k * oj + j) * oi + i] = s;
       }
+}
+
+// Host threads for element-parallel set-up work: up to the hardware's count
+// (at most 16), and at least `grain` elements per thread.
+static int host_threads(int nitems, int grain) {
+  int hw = (int)std::thread::hardware_concurrency();
+  if (hw < 1) hw = 1;
+  if (hw > 16) hw = 16;
+  int n = nitems / grain;
+  return n < 1 ? 1 : (n < hw ? n : hw);
 }
 
 // ---------------------------------------------------------------------------
@@ -452,75 +463,117 @@ dg_status dg_set_mesh(dg_ctx* c, int nElems, int Ngeo, const double* X, int nSid
   for (int a = 0; a < n1; ++a)
     for (int m = 0; m < g1; ++m) V[(size_t)a * g1 + m] = lagrange_at(xg, m, c->x[a]);
   std::vector<double> xyz((size_t)3 * nElems * n3), Ja((size_t)9 * nElems * n3), sJ((size_t)nElems * n3);
-  std::vector<double> t1((size_t)g1 * g1 * n1), t2((size_t)g1 * n1 * n1), Xe((size_t)3 * n3), dX((size_t)9 * n3),
-      prod((size_t)n3), dprod((size_t)n3), acc((size_t)n3), rel((size_t)g1 * g1 * g1);
-  for (int e = 0; e < nElems; ++e) {
-    for (int d = 0; d < 3; ++d) {
-      const double* src = X + ((size_t)d * nElems + e) * g1 * g1 * g1;
-      const double x0 = src[0];
-      for (int t = 0; t < g1 * g1 * g1; ++t) rel[t] = src[t] - x0;
-      apply_dim(V.data(), n1, g1, rel.data(), g1, g1, g1, 0, t1.data());
-      apply_dim(V.data(), n1, g1, t1.data(), n1, g1, g1, 1, t2.data());
-      apply_dim(V.data(), n1, g1, t2.data(), n1, n1, g1, 2, &Xe[(size_t)d * n3]);
-      for (int r = 0; r < 3; ++r) apply_dim(c->D.data(), n1, n1, &Xe[(size_t)d * n3], n1, n1, n1, r, &dX[(size_t)(3 * d + r) * n3]);
-      for (int t = 0; t < n3; ++t) xyz[((size_t)d * nElems + e) * n3 + t] = Xe[(size_t)d * n3 + t] + x0;
+  // Elements are independent: a contiguous block of elements per host thread,
+  // each with its own scratch.  The first element (in index order) with a
+  // non-positive Jacobian is reported, whatever the thread count.
+  auto elem_block = [&](int e0, int e1, int* bad_elem, double* bad_J) {
+    std::vector<double> t1((size_t)g1 * g1 * n1), t2((size_t)g1 * n1 * n1), Xe((size_t)3 * n3), dX((size_t)9 * n3),
+        prod((size_t)n3), dprod((size_t)n3), acc((size_t)n3), rel((size_t)g1 * g1 * g1);
+    for (int e = e0; e < e1; ++e) {
+      for (int d = 0; d < 3; ++d) {
+        const double* src = X + ((size_t)d * nElems + e) * g1 * g1 * g1;
+        const double x0 = src[0];
+        for (int t = 0; t < g1 * g1 * g1; ++t) rel[t] = src[t] - x0;
+        apply_dim(V.data(), n1, g1, rel.data(), g1, g1, g1, 0, t1.data());
+        apply_dim(V.data(), n1, g1, t1.data(), n1, g1, g1, 1, t2.data());
+        apply_dim(V.data(), n1, g1, t2.data(), n1, n1, g1, 2, &Xe[(size_t)d * n3]);
+        for (int r = 0; r < 3; ++r) apply_dim(c->D.data(), n1, n1, &Xe[(size_t)d * n3], n1, n1, n1, r, &dX[(size_t)(3 * d + r) * n3]);
+        for (int t = 0; t < n3; ++t) xyz[((size_t)d * nElems + e) * n3 + t] = Xe[(size_t)d * n3 + t] + x0;
+      }
+      for (int t = 0; t < n3; ++t) {
+        double a[3][3];
+        for (int d = 0; d < 3; ++d)
+          for (int r = 0; r < 3; ++r) a[d][r] = dX[(size_t)(3 * d + r) * n3 + t];
+        double J = a[0][0] * (a[1][1] * a[2][2] - a[2][1] * a[1][2]) + a[1][0] * (a[2][1] * a[0][2] - a[0][1] * a[2][2]) +
+                   a[2][0] * (a[0][1] * a[1][2] - a[1][1] * a[0][2]);
+        if (!(J > 0.0)) {
+          *bad_elem = e;
+          *bad_J = J;
+          return;
+        }
+        sJ[(size_t)e * n3 + t] = 1.0 / J;
+      }
+      // Conservative curl form: Ja^r_n = -[curl_xi (X_l grad_xi X_m)]_r with
+      // (n, m, l) cyclic; the product is collocated at the solution nodes.
+      for (int n = 0; n < 3; ++n) {
+        const int m = (n + 1) % 3, l = (n + 2) % 3;
+        for (int r = 0; r < 3; ++r) {
+          const int r1 = (r + 1) % 3, r2 = (r + 2) % 3;
+          // Ja^r_n = d_{r2}(X_l d_{r1} X_m) - d_{r1}(X_l d_{r2} X_m)
+          for (int t = 0; t < n3; ++t) prod[t] = Xe[(size_t)l * n3 + t] * dX[(size_t)(3 * m + r1) * n3 + t];
+          apply_dim(c->D.data(), n1, n1, prod.data(), n1, n1, n1, r2, acc.data());
+          for (int t = 0; t < n3; ++t) prod[t] = Xe[(size_t)l * n3 + t] * dX[(size_t)(3 * m + r2) * n3 + t];
+          apply_dim(c->D.data(), n1, n1, prod.data(), n1, n1, n1, r1, dprod.data());
+          for (int t = 0; t < n3; ++t) Ja[((size_t)(3 * r + n) * nElems + e) * n3 + t] = acc[t] - dprod[t];
+        }
+      }
     }
-    for (int t = 0; t < n3; ++t) {
-      double a[3][3];
-      for (int d = 0; d < 3; ++d)
-        for (int r = 0; r < 3; ++r) a[d][r] = dX[(size_t)(3 * d + r) * n3 + t];
-      double J = a[0][0] * (a[1][1] * a[2][2] - a[2][1] * a[1][2]) + a[1][0] * (a[2][1] * a[0][2] - a[0][1] * a[2][2]) +
-                 a[2][0] * (a[0][1] * a[1][2] - a[1][1] * a[0][2]);
-      if (!(J > 0.0)) {
+  };
+  {
+    const int nth = host_threads(nElems, 64);
+    std::vector<int> bad_elem(nth, -1);
+    std::vector<double> bad_J(nth, 0.0);
+    std::vector<std::thread> pool;
+    for (int th = 0; th < nth; ++th) {
+      const int e0 = (int)((long long)nElems * th / nth), e1 = (int)((long long)nElems * (th + 1) / nth);
+      pool.emplace_back(elem_block, e0, e1, &bad_elem[th], &bad_J[th]);
+    }
+    for (auto& th : pool) th.join();
+    for (int th = 0; th < nth; ++th)
+      if (bad_elem[th] >= 0) {
         char buf[128];
-        std::snprintf(buf, sizeof buf, "dg_set_mesh: non-positive Jacobian %g in element %d", J, e);
+        std::snprintf(buf, sizeof buf, "dg_set_mesh: non-positive Jacobian %g in element %d", bad_J[th], bad_elem[th]);
         return fail(c, DG_ERR_MESH, buf);
       }
-      sJ[(size_t)e * n3 + t] = 1.0 / J;
-    }
-    // Conservative curl form: Ja^r_n = -[curl_xi (X_l grad_xi X_m)]_r with
-    // (n, m, l) cyclic; the product is collocated at the solution nodes.
-    for (int n = 0; n < 3; ++n) {
-      const int m = (n + 1) % 3, l = (n + 2) % 3;
-      for (int r = 0; r < 3; ++r) {
-        const int r1 = (r + 1) % 3, r2 = (r + 2) % 3;
-        // Ja^r_n = d_{r2}(X_l d_{r1} X_m) - d_{r1}(X_l d_{r2} X_m)
-        for (int t = 0; t < n3; ++t) prod[t] = Xe[(size_t)l * n3 + t] * dX[(size_t)(3 * m + r1) * n3 + t];
-        apply_dim(c->D.data(), n1, n1, prod.data(), n1, n1, n1, r2, acc.data());
-        for (int t = 0; t < n3; ++t) prod[t] = Xe[(size_t)l * n3 + t] * dX[(size_t)(3 * m + r2) * n3 + t];
-        apply_dim(c->D.data(), n1, n1, prod.data(), n1, n1, n1, r1, dprod.data());
-        for (int t = 0; t < n3; ++t) Ja[((size_t)(3 * r + n) * nElems + e) * n3 + t] = acc[t] - dprod[t];
-      }
-    }
   }
   // master face normals from the volume metrics (extrapolated along the normal line)
   std::vector<double> nvec((size_t)3 * nSides * n2);
-  for (int s = 0; s < nSides; ++s) {
-    const int e = side_elem[2 * s], f = side_loc[2 * s], dir = f / 2;
-    const double sg = (f & 1) ? 1.0 : -1.0;
-    const std::vector<double>& L = (f & 1) ? c->Lp : c->Lm;
-    for (int q = 0; q < n1; ++q)
-      for (int p = 0; p < n1; ++p)
-        for (int comp = 0; comp < 3; ++comp) {
-          double v = 0.0;
-          for (int a = 0; a < n1; ++a) {
-            int i, j, k;
-            if (dir == 0) { i = a; j = p; k = q; } else if (dir == 1) { i = p; j = a; k = q; } else { i = p; j = q; k = a; }
-            v += L[a] * Ja[((size_t)(3 * dir + comp) * nElems + e) * n3 + (k * n1 + j) * n1 + i];
+  auto side_block = [&](int s0, int s1) {
+    for (int s = s0; s < s1; ++s) {
+      const int e = side_elem[2 * s], f = side_loc[2 * s], dir = f / 2;
+      const double sg = (f & 1) ? 1.0 : -1.0;
+      const std::vector<double>& L = (f & 1) ? c->Lp : c->Lm;
+      for (int q = 0; q < n1; ++q)
+        for (int p = 0; p < n1; ++p)
+          for (int comp = 0; comp < 3; ++comp) {
+            double v = 0.0;
+            for (int a = 0; a < n1; ++a) {
+              int i, j, k;
+              if (dir == 0) { i = a; j = p; k = q; } else if (dir == 1) { i = p; j = a; k = q; } else { i = p; j = q; k = a; }
+              v += L[a] * Ja[((size_t)(3 * dir + comp) * nElems + e) * n3 + (k * n1 + j) * n1 + i];
+            }
+            nvec[((size_t)comp * nSides + s) * n2 + q * n1 + p] = sg * v;
           }
-          nvec[((size_t)comp * nSides + s) * n2 + q * n1 + p] = sg * v;
-        }
+    }
+  };
+  // quadrature weights w_i w_j w_k J per node, and each element's volume
+  std::vector<double> wJ((size_t)nElems * n3), evol((size_t)nElems);
+  auto wj_block = [&](int e0, int e1) {
+    for (int e = e0; e < e1; ++e) {
+      double ve = 0.0;
+      for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+          for (int i = 0; i < n1; ++i) {
+            size_t t = (size_t)e * n3 + (k * n1 + j) * n1 + i;
+            wJ[t] = c->w[i] * c->w[j] * c->w[k] / sJ[t];
+            ve += wJ[t];
+          }
+      evol[e] = ve;
+    }
+  };
+  {
+    const int nth = host_threads(nElems, 64);
+    std::vector<std::thread> pool;
+    for (int th = 0; th < nth; ++th) {
+      const int s0 = (int)((long long)nSides * th / nth), s1 = (int)((long long)nSides * (th + 1) / nth);
+      const int e0 = (int)((long long)nElems * th / nth), e1 = (int)((long long)nElems * (th + 1) / nth);
+      pool.emplace_back([&, s0, s1, e0, e1]() { side_block(s0, s1); wj_block(e0, e1); });
+    }
+    for (auto& th : pool) th.join();
   }
-  std::vector<double> wJ((size_t)nElems * n3);
+  // |Omega|, summed element by element in index order (independent of the thread count)
   double vol = 0.0;
-  for (int e = 0; e < nElems; ++e)
-    for (int k = 0; k < n1; ++k)
-      for (int j = 0; j < n1; ++j)
-        for (int i = 0; i < n1; ++i) {
-          size_t t = (size_t)e * n3 + (k * n1 + j) * n1 + i;
-          wJ[t] = c->w[i] * c->w[j] * c->w[k] / sJ[t];
-          vol += wJ[t];
-        }
+  for (int e = 0; e < nElems; ++e) vol += evol[e];
   (void)N;
   c->nElems = nElems; c->nSides = nSides; c->Ngeo = Ngeo;
   c->efc.swap(efc); c->xyz.swap(xyz); c->Ja.swap(Ja); c->sJ.swap(sJ); c->nvec.swap(nvec); c->wJ.swap(wJ);
@@ -664,15 +717,19 @@ dg_status dg_upload_metrics(dg_ctx* c, const double* Ja, const double* sJ, const
   c->Ja.assign(Ja, Ja + 9 * nv);
   c->sJ.assign(sJ, sJ + nv);
   c->nvec = nv3;
+  // |Omega| as dg_set_mesh sums it: per element, then in element order
   double vol = 0.0;
   const int n1 = c->n1, n3 = c->n3;
-  for (int e = 0; e < c->nElems; ++e)
+  for (int e = 0; e < c->nElems; ++e) {
+    double ve = 0.0;
     for (int t = 0; t < n3; ++t) {
       int i = t % n1, j = (t / n1) % n1, k = t / (n1 * n1);
       size_t u = (size_t)e * n3 + t;
       c->wJ[u] = c->w[i] * c->w[j] * c->w[k] / sJ[u];
-      vol += c->wJ[u];
+      ve += c->wJ[u];
     }
+    vol += ve;
+  }
   c->volume = vol;
   dg_status st = upload_face(c, nv3);
   if (st != DG_OK || !c->cfg.fv) return st;

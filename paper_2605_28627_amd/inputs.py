@@ -112,6 +112,49 @@ def _orient_code(st_map):
     return o
 
 
+def _to_new(P, xi_old):
+    """Reference coordinates in an element's turned frame: xi_new = P^T xi_old."""
+    return [float(v) for v in (P.T @ np.array(xi_old, dtype=np.float64))]
+
+
+def _new_face(P, d, plus):
+    """Local face (in the turned frame P) of the undisplaced face at the +-1 end of direction d."""
+    xi = [0, 0, 0]
+    xi[d] = 1 if plus else -1
+    return _face_of(_to_new(P, xi))
+
+
+def _side_orientation(PM, fM, PS, fS, d):
+    """Orientation code of a side whose master (frame PM, local face fM) and
+    slave (frame PS, local face fS) meet across the undisplaced direction d:
+    two probe points inside the master face are carried to the slave's face."""
+    def st_map(st):
+        xi_m_old = PM @ np.array(_embed(fM, 0.5 * st[0], 0.5 * st[1]), dtype=np.float64)
+        xi_s_old = xi_m_old.copy()
+        xi_s_old[d] = -xi_m_old[d]   # same tangential position, opposite end
+        xi_s_new = _to_new(PS, xi_s_old)
+        assert _face_of(xi_s_new) == fS
+        a, b = _tangential(fS, xi_s_new)
+        return (int(round(2 * a)), int(round(2 * b)))
+    return _orient_code(st_map)
+
+
+def _frame_permutation(P, Ngeo):
+    """Flat node permutation of a turned element: node (c,b,a) of the new
+    frame is node perm[(c g1 + b) g1 + a] of the undisplaced one (xi_old = P xi_new)."""
+    g1 = Ngeo + 1
+    grid = np.arange(g1)
+    an, bn, cn = np.meshgrid(grid, grid, grid, indexing="ij")
+    new = [an, bn, cn]
+    old = []
+    for r in range(3):
+        col = int(np.nonzero(P[r])[0][0])
+        old.append(new[col] if P[r, col] > 0 else Ngeo - new[col])
+    perm = np.empty(g1 ** 3, dtype=np.int64)
+    perm[((cn * g1 + bn) * g1 + an).ravel()] = ((old[2] * g1 + old[1]) * g1 + old[0]).ravel()
+    return perm
+
+
 def box_mesh(K=(4, 4, 4), lo=(0.0, 0.0, 0.0), hi=(2.0, 2.0, 2.0), Ngeo=1,
              curved_amp=0.0, rotate_seed=None) -> Mesh:
     """Periodic box of Kx*Ky*Kz hexahedra in lexicographic order.
@@ -122,91 +165,78 @@ def box_mesh(K=(4, 4, 4), lo=(0.0, 0.0, 0.0), hi=(2.0, 2.0, 2.0), Ngeo=1,
     undisplaced position (the curved-mesh workload uses amp = 0.1 on
     [-pi, pi]^3, which keeps the periodic faces in place).  With
     ``rotate_seed`` each element's local frame is turned by a random proper
-    cube rotation and master/slave roles are drawn at random.
+    cube rotation (PCG64(rotate_seed), one draw of nElems rotation indices)
+    and master/slave roles are drawn at random (one further draw of nSides
+    bits).
+
+    Sides are numbered 3 e + d: element e (lexicographic) and its periodic
+    neighbour in the + direction d.  Everything is built with whole-array
+    operations, so the 64^3 boxes take a fraction of a second.
     """
     Kx, Ky, Kz = (int(k) for k in K)
     nE = Kx * Ky * Kz
     g1 = Ngeo + 1
     h = [(hi[d] - lo[d]) / K[d] for d in range(3)]
     s = np.arange(g1, dtype=np.float64) / Ngeo
+    kz, ky, kx = np.meshgrid(np.arange(Kz), np.arange(Ky), np.arange(Kx), indexing="ij")
+    kx, ky, kz = kx.ravel(), ky.ravel(), kz.ravel()        # element e = (kz Ky + ky) Kx + kx
     # element-local undisplaced coordinates, index order [c][b][a]
     X = np.empty((3, nE, g1, g1, g1))
-    for kz in range(Kz):
-        for ky in range(Ky):
-            for kx in range(Kx):
-                e = (kz * Ky + ky) * Kx + kx
-                x = lo[0] + (kx + s) * h[0]
-                y = lo[1] + (ky + s) * h[1]
-                z = lo[2] + (kz + s) * h[2]
-                X[0, e] = x[None, None, :]
-                X[1, e] = y[None, :, None]
-                X[2, e] = z[:, None, None]
+    X[0] = (lo[0] + (kx[:, None] + s[None, :]) * h[0])[:, None, None, :]
+    X[1] = (lo[1] + (ky[:, None] + s[None, :]) * h[1])[:, None, :, None]
+    X[2] = (lo[2] + (kz[:, None] + s[None, :]) * h[2])[:, :, None, None]
     if curved_amp != 0.0:
         bump = curved_amp * np.sin(X[0]) * np.sin(X[1]) * np.sin(X[2])
         X = X + bump[None]
     # structural sides: element e and its + neighbour in each direction
-    rng = np.random.Generator(np.random.PCG64(rotate_seed)) if rotate_seed is not None else None
-    rots = [np.eye(3, dtype=np.int64)] * nE
-    if rng is not None:
-        idx = rng.integers(0, 24, size=nE)
-        rots = [_ROT[i] for i in idx]
-        Xr = np.empty_like(X)
-        grid = np.arange(g1)
-        for e in range(nE):
-            P = rots[e]
-            # new index (a',b',c') -> old index: xi_old = P xi_new
-            an, bn, cn = np.meshgrid(grid, grid, grid, indexing="ij")
-            new = [an, bn, cn]
-            old = []
-            for r in range(3):
-                col = int(np.nonzero(P[r])[0][0])
-                old.append(new[col] if P[r, col] > 0 else Ngeo - new[col])
-            # X arrays are stored [c][b][a]
-            Xr[:, e, cn, bn, an] = X[:, e, old[2], old[1], old[0]]
-        X = Xr
-    sideElem, sideLoc, sideOrient = [], [], []
-    for kz in range(Kz):
-        for ky in range(Ky):
-            for kx in range(Kx):
-                e = (kz * Ky + ky) * Kx + kx
-                for d in range(3):
-                    kk = [kx, ky, kz]
-                    kk[d] = (kk[d] + 1) % K[d]
-                    en = (kk[2] * Ky + kk[1]) * Kx + kk[0]
-                    # element e: old face 2d+1 ; neighbour en: old face 2d
-                    PE, PN = rots[e], rots[en]
-
-                    def to_new(P, xi_old):
-                        return [float(v) for v in (P.T @ np.array(xi_old, dtype=np.float64))]
-
-                    old_f_e = [0, 0, 0]
-                    old_f_e[d] = 1
-                    fe = _face_of(to_new(PE, old_f_e))
-                    old_f_n = [0, 0, 0]
-                    old_f_n[d] = -1
-                    fn = _face_of(to_new(PN, old_f_n))
-                    master_is_e = True if rng is None else bool(rng.integers(0, 2))
-                    (mE, mF, mP), (sE, sF, sP) = (
-                        ((e, fe, PE), (en, fn, PN)) if master_is_e
-                        else ((en, fn, PN), (e, fe, PE)))
-
-                    def st_map(st, mF=mF, mP=mP, sF=sF, sP=sP):
-                        # probe points sit inside the face (half-way to an edge)
-                        xi_m_new = _embed(mF, 0.5 * st[0], 0.5 * st[1])
-                        xi_m_old = mP @ np.array(xi_m_new, dtype=np.float64)
-                        xi_s_old = xi_m_old.copy()
-                        xi_s_old[d] = -xi_m_old[d]   # same tangential position, opposite end
-                        xi_s_new = to_new(sP, xi_s_old)
-                        assert _face_of(xi_s_new) == sF
-                        a, b = _tangential(sF, xi_s_new)
-                        return (int(round(2 * a)), int(round(2 * b)))
-
-                    sideElem += [mE, sE]
-                    sideLoc += [mF, sF]
-                    sideOrient.append(_orient_code(st_map))
+    e = np.arange(nE)
+    nb = [((kz * Ky + ky) * Kx + (kx + 1) % Kx),
+          ((kz * Ky + (ky + 1) % Ky) * Kx + kx),
+          ((((kz + 1) % Kz) * Ky + ky) * Kx + kx)]
+    nS = 3 * nE
+    elemA = np.repeat(e, 3)                                  # owner of the + face, side 3e + d
+    elemB = np.stack(nb, axis=1).ravel()                     # its neighbour (- face)
+    dirs = np.tile(np.arange(3), nE)
+    if rotate_seed is None:
+        sideElem = np.stack([elemA, elemB], axis=1).ravel()
+        sideLoc = np.stack([2 * dirs + 1, 2 * dirs], axis=1).ravel()
+        sideOrient = np.zeros(nS, dtype=np.int64)
+    else:
+        rng = np.random.Generator(np.random.PCG64(rotate_seed))
+        rot = rng.integers(0, 24, size=nE)
+        master_is_a = rng.integers(0, 2, size=nS).astype(bool)
+        flat = X.reshape(3, nE, g1 ** 3)
+        for rid in np.unique(rot):
+            sel = np.nonzero(rot == rid)[0]
+            flat[:, sel] = flat[:, sel][:, :, _frame_permutation(_ROT[rid], Ngeo)]
+        X = flat.reshape(3, nE, g1, g1, g1)
+        # local faces in the turned frames, per (rotation, direction, end)
+        face_tab = np.array([[[_new_face(P, d, pl) for pl in (False, True)] for d in range(3)] for P in _ROT])
+        rA, rB = rot[elemA], rot[elemB]
+        fA, fB = face_tab[rA, dirs, 1], face_tab[rB, dirs, 0]
+        mE = np.where(master_is_a, elemA, elemB)
+        sE = np.where(master_is_a, elemB, elemA)
+        mF = np.where(master_is_a, fA, fB)
+        sF = np.where(master_is_a, fB, fA)
+        mR = np.where(master_is_a, rA, rB)
+        sR = np.where(master_is_a, rB, rA)
+        # orientation per distinct (master frame, master face, slave frame, slave face, direction)
+        key = (((mR * 6 + mF) * 24 + sR) * 6 + sF) * 3 + dirs
+        ukeys, inv = np.unique(key, return_inverse=True)
+        codes = np.empty(ukeys.size, dtype=np.int64)
+        for u, kk in enumerate(ukeys):
+            kk = int(kk)
+            d = kk % 3; kk //= 3
+            f_s = kk % 6; kk //= 6
+            r_s = kk % 24; kk //= 24
+            f_m = kk % 6; r_m = kk // 6
+            codes[u] = _side_orientation(_ROT[r_m], f_m, _ROT[r_s], f_s, d)
+        sideElem = np.stack([mE, sE], axis=1).ravel()
+        sideLoc = np.stack([mF, sF], axis=1).ravel()
+        sideOrient = codes[inv.ravel()]
     vol = float(np.prod([hi[d] - lo[d] for d in range(3)]))
-    return Mesh(nE, Ngeo, np.ascontiguousarray(X), np.asarray(sideElem, np.int32),
-                np.asarray(sideLoc, np.int32), np.asarray(sideOrient, np.int32), vol,
+    return Mesh(nE, Ngeo, np.ascontiguousarray(X), np.ascontiguousarray(sideElem, np.int32),
+                np.ascontiguousarray(sideLoc, np.int32), np.ascontiguousarray(sideOrient, np.int32), vol,
                 {"K": (Kx, Ky, Kz), "lo": tuple(lo), "hi": tuple(hi), "curved_amp": curved_amp,
                  "rotate_seed": rotate_seed})
 
@@ -222,6 +252,26 @@ def prim_to_cons(rho, u, v, w, p, gamma):
     return np.ascontiguousarray(np.stack([rho, rho * u, rho * v, rho * w, E]))
 
 
+def _by_element_chunks(fn, xyz, chunk=8192):
+    """fn(xyz[:, e0:e1]) -> [5][e1-e0][...] evaluated over blocks of elements
+    in host threads (numpy releases the GIL inside its array operations), so
+    that the 134 M-node states are built in seconds."""
+    nE = xyz.shape[1]
+    if nE <= chunk:
+        return fn(xyz)
+    import concurrent.futures as cf
+    import os
+    out = np.empty((5,) + xyz.shape[1:])
+    blocks = [(e0, min(nE, e0 + chunk)) for e0 in range(0, nE, chunk)]
+
+    def work(b):
+        out[:, b[0]:b[1]] = fn(xyz[:, b[0]:b[1]])
+
+    with cf.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(work, blocks))
+    return out
+
+
 def tgv_state(xyz, gamma=1.4, Ma=0.1, rho0=1.0, U0=1.0, L=1.0, noise_amp=0.0, noise_seed=3):
     """Taylor-Green vortex (paper eq. tgv_ic) at background Mach number Ma.
 
@@ -230,19 +280,24 @@ def tgv_state(xyz, gamma=1.4, Ma=0.1, rho0=1.0, U0=1.0, L=1.0, noise_amp=0.0, no
     (PCG64(noise_seed), drawn as one array of shape [3][...]) after the
     vortex is set, keeping rho and p.
     """
-    x, y, z = xyz[0] / L, xyz[1] / L, xyz[2] / L
     p0 = rho0 * U0 * U0 / (gamma * Ma * Ma)
-    u = U0 * np.sin(x) * np.cos(y) * np.cos(z)
-    v = -U0 * np.cos(x) * np.sin(y) * np.cos(z)
-    w = np.zeros_like(u)
-    p = p0 + rho0 * U0 * U0 / 16.0 * (np.cos(2 * x) + np.cos(2 * y)) * (2.0 + np.cos(2 * z))
-    rho = rho0 * p / p0
-    if noise_amp != 0.0:
-        rng = np.random.Generator(np.random.PCG64(noise_seed))
-        nz = rng.uniform(-1.0, 1.0, size=(3,) + u.shape)
-        u = u + noise_amp * nz[0]
-        v = v + noise_amp * nz[1]
-        w = w + noise_amp * nz[2]
+
+    def prim(xyz):
+        x, y, z = xyz[0] / L, xyz[1] / L, xyz[2] / L
+        u = U0 * np.sin(x) * np.cos(y) * np.cos(z)
+        v = -U0 * np.cos(x) * np.sin(y) * np.cos(z)
+        w = np.zeros_like(u)
+        p = p0 + rho0 * U0 * U0 / 16.0 * (np.cos(2 * x) + np.cos(2 * y)) * (2.0 + np.cos(2 * z))
+        return rho0 * p / p0, u, v, w, p
+
+    if noise_amp == 0.0:
+        return _by_element_chunks(lambda c: prim_to_cons(*prim(c), gamma), xyz)
+    rho, u, v, w, p = prim(xyz)
+    rng = np.random.Generator(np.random.PCG64(noise_seed))
+    nz = rng.uniform(-1.0, 1.0, size=(3,) + u.shape)
+    u = u + noise_amp * nz[0]
+    v = v + noise_amp * nz[1]
+    w = w + noise_amp * nz[2]
     return prim_to_cons(rho, u, v, w, p, gamma)
 
 

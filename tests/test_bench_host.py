@@ -47,3 +47,18 @@ def test_fv_masks():
     assert np.array_equal(m, (i + j + k) % 2)
     assert bench.fv_mask("all", K).sum() == 24
     assert bench.fv_mask("zero", K).sum() == 0
+
+
+def test_cpu_baseline_leg_runs_on_the_host():
+    """The oracle leg of the bench line (native build, warm call, sampled
+    residuals) on the smallest workload, with a short time target."""
+    import argparse
+    w, cfg = bench.workload_cfg("euler_weak_lg_n3_4x4x4")
+    mesh = I.workload_mesh("euler_weak_lg_n3_4x4x4")
+    from oracle import oracle as O
+    U = I.workload_state("euler_weak_lg_n3_4x4x4", O.Oracle(cfg, mesh).coords())
+    args = argparse.Namespace(workload="euler_weak_lg_n3_4x4x4", K=None, state=None, fv="none", cpu_seconds=0.2,
+                              cpu_sample_elems=None, cpu_repeats=2, cpu_procs=1)
+    out = bench.cpu_baseline(args, cfg, mesh, U, 1e-9)
+    assert out["kind"] == "oracle" and out["cores"] == 1 and out["value"] > 0
+    assert out["host"]["nproc"] >= 1 and "O3" in out["build"]

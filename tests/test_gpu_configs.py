@@ -12,11 +12,12 @@ the small meshes):
   reported (one JSON line per configuration, prefixed "RESULT"), with a loose
   bound that catches a broken mixed path.
 
-The 64^3, N=7 configuration (134 M nodes) needs minutes of host set-up and
-tens of GB of host memory; it runs only with DGX_LARGE=1.
+A second test runs each configuration with the library's own metrics (host
+curl-form metrics, no upload): the oracle computes its geometry for the
+sampled elements only, and the same bound applies.  The 64^3, N=7
+configuration (134 M nodes, 5.4 GB per state) is part of both.
 """
 import json
-import os
 import sys
 
 import numpy as np
@@ -32,9 +33,7 @@ CONFIGS = [
     "ns_split_lgl_n7_16x16x16_tgv",
     "ns_split_lgl_n5_32x32x32_curved_tgv",
     "euler_split_lgl_n5_8x8x8_tgv",
-    pytest.param("ns_split_lgl_n7_64x64x64_tgv",
-                 marks=pytest.mark.skipif(os.environ.get("DGX_LARGE") != "1",
-                                          reason="134 M nodes: minutes of host set-up; set DGX_LARGE=1")),
+    "ns_split_lgl_n7_64x64x64_tgv",
 ]
 
 
@@ -61,6 +60,17 @@ def S():
     return DGSolver
 
 
+def _flux_scale(orc, w, U, el, Ja, J):
+    """Size of the terms a residual entry is summed from: the largest row sum of
+    the volume operator times the largest flux over the sampled elements' first
+    nodes, times the largest metric entry over the smallest Jacobian."""
+    b = orc.basis(w["N"], w["nodes"])
+    # weak-form operator Dhat[a][l] = (w_l / w_a) D[l][a]; split operator D^S
+    D = b["DS"] if w["form"] == 1 else (b["w"][None, :] / b["w"][:, None]) * b["D"].T
+    fmax = max(np.abs(orc.flux_adv(U[:, e].reshape(5, -1)[:, 0], np.ones(3))).max() for e in el)
+    return np.abs(D).sum(1).max() * fmax * np.abs(Ja).max() / J.min()
+
+
 @pytest.mark.parametrize("name", CONFIGS)
 def test_config_fp64_parity_and_fp32_error(S, orc, name):
     import torch
@@ -75,13 +85,9 @@ def test_config_fp64_parity_and_fp32_error(S, orc, name):
     U = I.workload_state(name, xyz)
     el = _sample(mesh.nElems, w["K"])
     _say(name, "oracle residual of", len(el), "elements")
-    R_orc = o.rhs_elems(U, el)
+    R_orc = o.rhs_sample(U, el)
     del o
-    b = orc.basis(w["N"], w["nodes"])
-    # weak-form operator Dhat[a][l] = (w_l / w_a) D[l][a]; split operator D^S
-    D = b["DS"] if w["form"] == 1 else (b["w"][None, :] / b["w"][:, None]) * b["D"].T
-    fmax = max(np.abs(orc.flux_adv(U[:, e].reshape(5, -1)[:, 0], np.ones(3))).max() for e in el)
-    scale = np.abs(D).sum(1).max() * fmax * np.abs(Ja).max() / J.min()
+    scale = _flux_scale(orc, w, U, el, Ja, J)
     out = {"config": name, "dof": int(mesh.nElems * (w["N"] + 1) ** 3), "sampled_elements": len(el)}
     for prec in (0, 1):
         _say(name, "GPU precision", prec)
@@ -103,3 +109,35 @@ def test_config_fp64_parity_and_fp32_error(S, orc, name):
             out["fp32_flux_rel_l2_per_var"] = l2
             assert max(l2) < 5e-2, l2
     _say("RESULT", json.dumps(out))
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_config_library_metrics_sampled(S, orc, name):
+    """Full size with the library's own metrics: sampled elements against the oracle."""
+    import torch
+    w = I.WORKLOADS[name]
+    cfg = dict(N=w["N"], nodes=w["nodes"], form=w["form"], physics=w["physics"], mu=w["mu"])
+    _say(name, "library metrics: mesh and GPU set-up")
+    mesh = I.workload_mesh(name)
+    s = S(cfg, mesh)
+    xyz = s.coords()
+    U = I.workload_state(name, xyz)
+    Ug = s.init_state(U)
+    R = s.rhs(Ug)
+    el = _sample(mesh.nElems, w["K"])
+    R_gpu = R[:, torch.as_tensor(el, device=R.device)].cpu().numpy()
+    del R, Ug
+    _, Ja_lib, sJ_lib, _ = s.metrics()
+    Ja_s, J_s = Ja_lib[:, el], 1.0 / sJ_lib[el]
+    s.close()
+    del Ja_lib, sJ_lib
+    _say(name, "oracle residual of", len(el), "elements (oracle geometry of those elements)")
+    o = orc.Oracle(cfg, mesh)
+    R_orc = o.rhs_sample(U, el)
+    scale = _flux_scale(orc, w, U, el, Ja_s, J_s)
+    diff = np.abs(R_gpu - R_orc).max(axis=(1, 2, 3, 4))
+    ref = np.abs(R_orc).max(axis=(1, 2, 3, 4))
+    _say("RESULT", json.dumps({"config": name, "library_metrics": True, "sampled_elements": len(el),
+                               "fp64_max_abs_diff_per_var": diff.tolist(),
+                               "bound_per_var": (1e-12 * ref + 64 * 2.2e-16 * scale).tolist()}))
+    assert np.all(diff < 1e-12 * ref + 64 * 2.2e-16 * scale), (diff, ref, scale)
