@@ -198,6 +198,19 @@ dg_status dg_lift(dg_ctx* ctx, const double* U, double* g, void* stream);
  * (device, state length); it is zeroed by the call before the first stage. */
 dg_status dg_rk_step(dg_ctx* ctx, double* U, double* dU, double t, double dt, int nsteps, void* stream);
 
+/* dg_rk_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same steps, with the scratch in a static device array of the library
+ * (256 MiB, one per GPU, held until the process ends) instead of the bound
+ * workspace; no workspace needs to be bound.  The call allocates nothing
+ * (no hipMalloc, hipFree, event creation or allocating library routine);
+ * event profiling (dg_profile) does not see it.  DG_ERR_ARG if the mesh needs
+ * more scratch than the static array holds (dg_workspace_bytes above
+ * 256 MiB).  Every call on one GPU, from any context, shares that GPU's
+ * array, which keeps the last call's contents: calls that overlap in time on
+ * one GPU (other streams, other threads) race and give wrong results. */
+dg_status dg_rk_step_noalloc(dg_ctx* ctx, double* U, double* dU, double t, double dt, int nsteps, void* stream);
+
 /* Adjoint --------------------------------------------------------------------- */
 
 /* out = (dR/dU)^T lam at the state U (device arrays, state length; out must

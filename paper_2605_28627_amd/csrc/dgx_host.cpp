@@ -960,6 +960,35 @@ dg_status dg_rk_step(dg_ctx* c, double* U, double* dU, double t, double dt, int 
   return DG_OK;
 }
 
+dg_status dg_rk_step_noalloc(dg_ctx* c, double* U, double* dU, double t, double dt, int nsteps, void* stream) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "dg_rk_step_noalloc: null context");
+  if (!c->mesh_on_device) return fail(c, DG_ERR_STATE, "dg_rk_step_noalloc: no mesh uploaded");
+  const size_t need = ws_layout(c).total;
+  if (need > kStaticScratchBytes) {
+    char buf[192];
+    std::snprintf(buf, sizeof buf, "dg_rk_step_noalloc: the mesh needs %zu bytes of scratch, above the static %zu",
+                  need, kStaticScratchBytes);
+    return fail(c, DG_ERR_ARG, buf);
+  }
+  void* scr = nullptr;
+  HIPCHK(c, static_scratch(&scr));
+  // Run dg_rk_step on the static scratch in place of the bound workspace, with
+  // event profiling off (no event creation), and restore both afterwards.
+  struct Swap {
+    dg_ctx* c; char* ws; size_t bytes; bool prof;
+    ~Swap() { c->ws = ws; c->ws_bytes = bytes; c->prof = prof; }
+  } keep{c, c->ws, c->ws_bytes, c->prof};
+  c->ws = (char*)scr;
+  c->ws_bytes = kStaticScratchBytes;
+  c->prof = false;
+  dg_status st = dg_rk_step(c, U, dU, t, dt, nsteps, stream);
+  if (st != DG_OK) {
+    std::string m = c->err;
+    c->err = "dg_rk_step_noalloc: " + m;
+  }
+  return st;
+}
+
 static dg_status ready_adjoint(dg_ctx* c, const char* who) {
   dg_status st = ready(c, who);
   if (st != DG_OK) return st;

@@ -138,4 +138,9 @@ hipError_t launch_check_state(const Cfg& c, const Geo& g, const Phys& p, const d
                               hipStream_t s);
 int reduction_blocks();
 
+// Size of the static device scratch of dg_rk_step_noalloc, and its device
+// address on the current device (looked up on the first call per device).
+constexpr size_t kStaticScratchBytes = (size_t)256 << 20;
+hipError_t static_scratch(void** ptr);
+
 }  // namespace dgx

@@ -2,10 +2,43 @@
 // auxiliary kernels (fills, reductions for E_k and the time step, state check).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "dgx_internal.hpp"
 #include "dgx_pointwise.hpp"
 
 namespace dgx {
+
+// ---------------------------------------------------------------------------
+// Static scratch for dg_rk_step_noalloc: a file-scope device array of
+// kStaticScratchBytes, one copy per GPU, held until the process ends.  In
+// host code `scratch` only names the symbol; its device address is looked up
+// once per device (with that device current) and cached, and only that
+// address is ever handed to kernels or runtime calls.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void** ptr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 #define DGX_DECL(n)                                                                                           \
   hipError_t launch_trace_N##n(const Cfg&, const Geo&, const Phys&, const double*, double*, hipStream_t);   \

@@ -37,7 +37,7 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_MESH", 3: "DG_ERR_HIP", 
 # public symbols of include/dgx.h
 SYMBOLS = ["dg_create", "dg_destroy", "dg_last_error", "dg_lserk_coefficients", "dg_rk_coefficients", "dg_set_mesh", "dg_upload_mesh",
            "dg_upload_metrics", "dg_get_metrics", "dg_node_coords", "dg_sizes", "dg_workspace_bytes",
-           "dg_workspace_bytes_adjoint", "dg_bind_workspace", "dg_init_state", "dg_rhs", "dg_lift", "dg_rk_step", "dg_adjoint_rhs", "dg_adjoint_rk_step",
+           "dg_workspace_bytes_adjoint", "dg_bind_workspace", "dg_init_state", "dg_rhs", "dg_lift", "dg_rk_step", "dg_rk_step_noalloc", "dg_adjoint_rhs", "dg_adjoint_rk_step",
            "dg_kinetic_energy", "dg_kinetic_energy_grad", "dg_timestep", "dg_check_state", "dg_profile",
            "dg_profile_families", "dg_profile_query", "dg_fv_switch", "dg_fv_indicator", "dg_fv_switch_by_indicator", "dg_fv_mask"]
 
@@ -78,6 +78,7 @@ _sig = {
     "dg_rhs": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp]),
     "dg_lift": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "dg_rk_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _vp]),
+    "dg_rk_step_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _vp]),
     "dg_adjoint_rhs": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "dg_adjoint_rk_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp]),
     "dg_kinetic_energy": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _vp]),
@@ -261,6 +262,12 @@ def dg_rk_step(ctx, U, dU, t, dt, nsteps, stream=None):
     n = dg_sizes(ctx)[3]
     _check(ctx, _L.dg_rk_step(ctx, _dev(U, n, "U"), _dev(dU, n, "dU"), float(t), float(dt), int(nsteps),
                               _stream(stream)))
+
+
+def dg_rk_step_noalloc(ctx, U, dU, t, dt, nsteps, stream=None):
+    n = dg_sizes(ctx)[3]
+    _check(ctx, _L.dg_rk_step_noalloc(ctx, _dev(U, n, "U"), _dev(dU, n, "dU"), float(t), float(dt), int(nsteps),
+                                      _stream(stream)))
 
 
 def dg_adjoint_rhs(ctx, U, lam, out, stream=None):
