@@ -1660,6 +1660,23 @@ void orc_geometry(void* h, double* xyz, double* J, double* Ja) {
   }
 }
 
+// Geometry of a list of elements only, compact: xyz[3][nlist][n3], J[nlist][n3], Ja[9][nlist][n3].
+int orc_geometry_sample(void* h, int nlist, const int* list, double* xyz, double* J, double* Ja) {
+  Solver* S = (Solver*)h;
+  for (int i = 0; i < nlist; ++i)
+    if (list[i] < 0 || list[i] >= S->nElems) { g_err = "element out of range"; return 1; }
+  for (int i = 0; i < nlist; ++i) {
+    const int e = list[i];
+    S->ensure_geom(e);
+    for (int t = 0; t < S->n3; ++t) {
+      if (xyz) for (int d = 0; d < 3; ++d) xyz[((size_t)d * nlist + i) * S->n3 + t] = S->Xnode[e][(size_t)d * S->n3 + t];
+      if (J) J[(size_t)i * S->n3 + t] = S->Jdet[e][t];
+      if (Ja) for (int c = 0; c < 9; ++c) Ja[((size_t)c * nlist + i) * S->n3 + t] = S->Ja[e][(size_t)c * S->n3 + t];
+    }
+  }
+  return 0;
+}
+
 // Master-outward scaled normals n*s at face nodes: [3][nSides][n2].
 void orc_face_normals(void* h, double* nv) {
   Solver* S = (Solver*)h;

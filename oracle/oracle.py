@@ -101,6 +101,7 @@ def load(path):
     L.orc_mms_source.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
     L.orc_rhs_sample.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip]
     L.orc_opcount_point.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_uint64)]
+    L.orc_geometry_sample.argtypes = [ctypes.c_void_p, ctypes.c_int, _ip, _dp, _dp, _dp]
     L.orc_rhs_vjp.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_double]
     L.orc_kinetic_energy_grad.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, _dp]
     L.orc_lserk_adjoint.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
@@ -286,6 +287,15 @@ class Oracle:
         J = np.zeros((self.nElems, n, n, n))
         Ja = np.zeros((9, self.nElems, n, n, n))
         self.L.orc_geometry(self.h, _d(xyz), _d(J), _d(Ja))
+        return xyz, J, Ja
+
+    def geometry_sample(self, elems):
+        """Node coordinates, Jacobian and metrics of the listed elements only:
+        [3][n][...], [n][...], [9][n][...]."""
+        el = np.ascontiguousarray(np.asarray(elems, dtype=np.int32))
+        n = self.n1
+        xyz, J, Ja = np.zeros((3, el.size, n, n, n)), np.zeros((el.size, n, n, n)), np.zeros((9, el.size, n, n, n))
+        self._chk(self.L.orc_geometry_sample(self.h, int(el.size), _i(el), _d(xyz), _d(J), _d(Ja)))
         return xyz, J, Ja
 
     def coords(self):

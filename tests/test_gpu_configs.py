@@ -14,7 +14,10 @@ the small meshes):
 
 A second test runs each configuration with the library's own metrics (host
 curl-form metrics, no upload): the oracle computes its geometry for the
-sampled elements only, and the same bound applies.  The 64^3, N=7
+sampled elements only.  The two codes round the metric terms independently
+(relative differences of about 1e-13), and a Ma 0.1 residual is a small
+difference of O(p0) flux terms, so the bound adds the measured metric
+difference times the size of those terms.  The 64^3, N=7
 configuration (134 M nodes, 5.4 GB per state) is part of both.
 """
 import json
@@ -133,11 +136,18 @@ def test_config_library_metrics_sampled(S, orc, name):
     del Ja_lib, sJ_lib
     _say(name, "oracle residual of", len(el), "elements (oracle geometry of those elements)")
     o = orc.Oracle(cfg, mesh)
+    _, J_o, Ja_o = o.geometry_sample(el)
     R_orc = o.rhs_sample(U, el)
     scale = _flux_scale(orc, w, U, el, Ja_s, J_s)
+    # the two codes round the metric terms independently; the residual moves by
+    # the metric change times the flux terms (volume and surface term, 1/J)
+    metric_rel = max(np.abs(Ja_s - Ja_o).max() / np.abs(Ja_o).max(), np.abs(J_s - J_o).max() / np.abs(J_o).max())
     diff = np.abs(R_gpu - R_orc).max(axis=(1, 2, 3, 4))
     ref = np.abs(R_orc).max(axis=(1, 2, 3, 4))
+    bound = 1e-12 * ref + (64 * 2.2e-16 + 4 * metric_rel) * scale
     _say("RESULT", json.dumps({"config": name, "library_metrics": True, "sampled_elements": len(el),
+                               "metric_rel_diff": float(metric_rel), "flux_scale": float(scale),
                                "fp64_max_abs_diff_per_var": diff.tolist(),
-                               "bound_per_var": (1e-12 * ref + 64 * 2.2e-16 * scale).tolist()}))
-    assert np.all(diff < 1e-12 * ref + 64 * 2.2e-16 * scale), (diff, ref, scale)
+                               "diff_over_metric_scale": (diff / (metric_rel * scale)).tolist(),
+                               "bound_per_var": bound.tolist()}))
+    assert np.all(diff < bound), (diff, ref, scale, metric_rel)

@@ -251,14 +251,28 @@ def test_init_state(S, orc, torch_cuda):
 
 @pytest.mark.parametrize("case", [CASES[0], CASES[7], CASES[9]], ids=str)
 def test_library_metrics_parity(S, orc, case):
-    """With the library's own host metrics (which agree with the oracle's to
-    rounding) the residuals agree to the same 1e-12 per variable as with the
-    oracle's metrics uploaded."""
+    """With the library's own host metrics the residuals agree within 1e-12 per
+    variable plus the effect of the metric rounding: the two codes round the
+    curl-form metrics independently (measured here), and the residual moves
+    by that relative change times the flux terms it is summed from (operator
+    row sum x largest flux x largest metric entry / smallest J)."""
     o, s, _ = _setup(S, orc, case, upload=False)
     U = I.smooth_random_state(o.coords(), 35, amp=0.2)
-    err = rel_err_per_var(s.rhs(s.to_device(U)).cpu().numpy(), o.rhs(U))
-    _say("library metrics", case, err)
-    assert np.all(err < 1e-12), err
+    R_orc = o.rhs(U)
+    R_gpu = s.rhs(s.to_device(U)).cpu().numpy()
+    _, J_o, Ja_o = o.geometry()
+    _, Ja_l, sJ_l, _ = s.metrics()
+    metric_rel = max(np.abs(Ja_l - Ja_o).max() / np.abs(Ja_o).max(),
+                     np.abs(1.0 / sJ_l - J_o).max() / np.abs(J_o).max())
+    b = orc.basis(case[0], case[1])
+    D = b["DS"] if case[2] == 1 else (b["w"][None, :] / b["w"][:, None]) * b["D"].T
+    fmax = max(np.abs(orc.flux_adv(U[:, e, 0, 0, 0], np.ones(3))).max() for e in range(U.shape[1]))
+    scale = np.abs(D).sum(1).max() * fmax * np.abs(Ja_o).max() / J_o.min()
+    diff = np.abs(R_gpu - R_orc).max(axis=(1, 2, 3, 4))
+    ref = np.abs(R_orc).max(axis=(1, 2, 3, 4))
+    _say("library metrics", case, "rel err", diff / ref, "metric rel diff", metric_rel,
+         "diff / (metric rel diff x flux scale)", diff / (metric_rel * scale))
+    assert np.all(diff < 1e-12 * ref + (64 * 2.2e-16 + 4 * metric_rel) * scale), (diff, ref, metric_rel, scale)
 
 
 @pytest.mark.parametrize("case", [(5, 1, 1, 1, 0.1, 21), (5, 1, 0, 0, 0.1, 21), (3, 0, 0, 0, 0.0, 21)], ids=str)
