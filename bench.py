@@ -203,18 +203,31 @@ def volume_kernel_bytes_per_dof(w, precision=0):
     Reads: U (5), metrics Ja (9) and 1/J (1), dU (5, except in the first of
     the five stages, whose A is 0: 4 on average), and per face node of
     each of the element's 6 faces both sides' traces (2 x 5) and the face
-    normal + area (4); Navier-Stokes adds the contravariant viscous fluxes
-    G~^r (12) and both sides' face-normal viscous fluxes (2 x 4), formed by
-    the lifting kernel.  Writes: dU (5), U (5) and the element's own traces
-    of the new state (5 per face node).  8 bytes each, except the viscous
-    fluxes in the FP32-flux mode (4 bytes).
+    normal + area (4); Navier-Stokes adds the viscous volume term (4) and
+    both sides' face-normal viscous fluxes (2 x 4), formed by the lifting
+    kernel.  Writes: dU (5), U (5) and the element's own traces of the new
+    state (5 per face node).  8 bytes each, except the face viscous fluxes
+    in the FP32-flux mode (4 bytes).
     """
     n1 = w["N"] + 1
     fpn = 6 * n1 * n1 / n1 ** 3          # face nodes of one element per volume node
     reads = 5 + 9 + 1 + 4 + fpn * (10 + 4)
     writes = 5 + 5 + fpn * 5
     if w["physics"] == 1:
-        reads += (12 + fpn * 8) * (0.5 if precision == 1 else 1.0)
+        reads += 4 + fpn * 8 * (0.5 if precision == 1 else 1.0)
+    return 8.0 * (reads + writes)
+
+
+def lift_kernel_bytes_per_dof(w, precision=0):
+    """Compulsory HBM bytes of one launch of the lifting kernel (the forward
+    stages' variant), per node.  Reads: U (5), Ja (9), 1/J (1), and per face
+    node both sides' traces (2 x 5) and the face normal + area (4).  Writes:
+    the viscous volume term (4) and the element's own face-normal viscous
+    flux (4 per face node; 4 bytes each in the FP32-flux mode)."""
+    n1 = w["N"] + 1
+    fpn = 6 * n1 * n1 / n1 ** 3
+    reads = 5 + 9 + 1 + fpn * (10 + 4)
+    writes = 4 + fpn * 4 * (0.5 if precision == 1 else 1.0)
     return 8.0 * (reads + writes)
 
 
@@ -422,6 +435,12 @@ def main():
                                                   "from the committed rocprofv3 summary"}
     if lift_n:
         result["kernels_ms_per_launch"]["lift"] = lift_ms / lift_n
+        lb = lift_kernel_bytes_per_dof(w) * dof
+        lgbs = lb / (lift_ms * 1e-3 / lift_n) / 1e9
+        result["roofline_lift"] = {"bound": "hbm", "kernel": "k_lift (BR1 lifting, forward stages)",
+                                   "achieved": lgbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": lgbs / HBM_PEAK_GBS,
+                                   "algorithmic_bytes_per_launch": lb, "avg_launch_ms": lift_ms / lift_n,
+                                   "timing": "HIP events, untimed pass"}
     if default_run and args.fv == "none":
         result["kernel_counters"] = kernel_counter_table(args.workload)
     if not args.no_fp32:

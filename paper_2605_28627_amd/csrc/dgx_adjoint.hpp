@@ -25,7 +25,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_trace(Geo G, const double
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
   __shared__ double sl[5 * n3];
   __shared__ DevBasis sb;
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
   load_basis(&sb, G.basis, t, S::nth);
   if (t < n3) {
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
   __shared__ double sl[5 * n3];   // lam / J
   __shared__ double sB[SZ_B];     // surface adjoints, then aux + metric row
   __shared__ DevBasis sb;
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
   load_basis(&sb, G.basis, t, S::nth);
   const bool act = t < n3;
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_trace(Geo G, const d
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
   __shared__ double sg[12 * n3];
   __shared__ DevBasis sb;
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
   load_basis(&sb, G.basis, t, S::nth);
   if (t < n3) {
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_volume(Geo G, Phys P
   constexpr int SZ = 12 * n3 > 5 * S::nface ? 12 * n3 : 5 * S::nface;
   __shared__ double sm[SZ];
   __shared__ DevBasis sb;
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
   load_basis(&sb, G.basis, t, S::nth);
   const bool act = t < n3;

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace_fv(Geo G, Phys P, const
   __shared__ double sb2[5 * n3];
   __shared__ double sBs[n1 * n1];
   __shared__ DevBasis sbb;
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
   const bool act = t < n3;
   load_basis(&sbb, G.basis, t, S::nth);
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_fv(Geo G, Phys P, const doubl
                                                       double* __restrict__ Utr_next, double A, double B, double dt) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   if (!G.etype[e]) return;   // DG elements belong to the residual kernel
   const int nE = G.nElems, nS = G.nSides;
   __shared__ double sw[5 * n3];
@@ -391,7 +391,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_fv_indicator(Geo G, const dou
   __shared__ double sb2[n3];
   __shared__ double sM[2 * n1 * n1];
   __shared__ double sred[2 * S::nth];
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   const int nE = G.nElems;
   const bool act = t < n3;
   for (int x = t; x < n1 * n1; x += S::nth) { sM[x] = G.basis->Bsi[x]; sM[n1 * n1 + x] = G.basis->Vli[x]; }
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_fv_switch(Geo G, double* __re
                                                              int* __restrict__ etype) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, n3 = S::n3;
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   const int told = etype[e], tnew = etype_new[e];
   if (told == tnew) return;
   __shared__ double sa[5 * n3];

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace(Geo G, Phys P, const do
                                                          double* __restrict__ Utr) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
   if constexpr (NODES == 1) {
     if (t >= n3) return;
@@ -152,12 +152,14 @@ __device__ inline double ld_visc(const double* p, size_t i) {
 // ---------------------------------------------------------------------------
 // BR1 lifting kernel (paper eq. dgsem_lifted), g = grad (u, v, w, T).
 // EMIT 0: g -> gout[12][nE][n3] and its face traces -> gtr[slot][12][side][fi].
-// EMIT 1: what the residual consumes instead of g, formed here once per node:
-//   gout[4r+v][nE][n3] = G~^r_v = Ja^r . G_v(q, g)      (contravariant viscous flux)
+// EMIT 1: what the residual consumes instead of g, formed here:
+//   gout[v][nE][n3] = -sum_r sum_l Dhat[a_r][l] G~^r_v(l)   (v = 0..3: the
+//       viscous part of the weak-form volume term for rho u, rho v, rho w, rho e,
+//       with G~^r_v = Ja^r . G_v(q, g) the contravariant viscous flux; FP64)
 //   gtr[slot][4][side][fi] = G_v(q_tr, g_tr) . n s       (per side, master normal)
-// with q_tr the state trace of that side; FT is the flux arithmetic type, and
-// with PREC 1 both are stored as float (st_visc).  VL is the viscosity law
-// (0 constant, 1 Sutherland) of the emitted fluxes.
+// with q_tr the state trace of that side.  FT is the flux arithmetic type;
+// with PREC 1 the face fluxes are stored as float (st_visc).  VL is the
+// viscosity law (0 constant, 1 Sutherland) of the fluxes.
 // ---------------------------------------------------------------------------
 template <int N, int NODES, int EMIT, int PREC, int VL>
 __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const double* __restrict__ U,
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
   __shared__ double sm[SZ2];
   __shared__ double sf[7 * S::nface];
   __shared__ VolBasis<N> sb;
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
   load_vol_basis<N>(&sb, G.basis, t, S::nth);
   double* sq = sm;            // [4][n3]
@@ -267,15 +269,45 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
     if constexpr (EMIT == 0) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) gout[((size_t)c * nE + e) * n3 + t] = acc[c];
-    } else {
+    }
+  }
+  if constexpr (EMIT == 1) {
+    // Viscous part of the volume term: G~^r at every node into LDS (the
+    // gradient sweep's q and Ja tiles are dead once every work-item is past
+    // it), then the Dhat contraction along each node's three lines.
+    double jall[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) jall[c] = act ? sja[c * n3 + t] : 0.0;
+    __syncthreads();
+    double* sG = sm;   // [4 r + v][n3]
+    if (act) {
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        const double jr[3] = {sja[(3 * r + 0) * n3 + t], sja[(3 * r + 1) * n3 + t], sja[(3 * r + 2) * n3 + t]};
+        const double jr[3] = {jall[3 * r + 0], jall[3 * r + 1], jall[3 * r + 2]};
         double Gr[4];
         viscous_flux<FT, VL>(q, acc, P, jr, Gr);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) st_visc<PREC>(gout, ((size_t)(4 * r + v) * nE + e) * n3 + t, Gr[v]);
+        for (int v = 0; v < 4; ++v) sG[(4 * r + v) * n3 + t] = Gr[v];
       }
+    }
+    __syncthreads();
+    if (act) {
+      const int idx[3] = {i, j, k};
+      double vv[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int a = idx[r];
+        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+#pragma unroll
+        for (int l = 0; l < n1; ++l) {
+          const int tl = line_node<N>(r, l, pp, qq);
+          const double c = sb.Dhat[a * n1 + l];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) vv[v] -= c * sG[(4 * r + v) * n3 + tl];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) gout[((size_t)v * nE + e) * n3 + t] = vv[v];
     }
   }
   // face-normal viscous flux of one side from its state trace qt and gradient trace gf
@@ -354,16 +386,17 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
 // lift, Jacobian scaling; MODE 0 writes U_t, MODE 1 applies one LSERK stage
 // and writes the face traces of the new state for the next stage.
 //
-// Navier-Stokes: the viscous fluxes come from the lifting kernel (EMIT 1):
-// gvn holds G~^r at every node, gvf the face-normal flux of each side.
+// Navier-Stokes: the viscous terms come from the lifting kernel (EMIT 1):
+// gvn holds the viscous part of the volume term at every node (4 values),
+// gvf the face-normal viscous flux of each side.
 //
 // Phases, so that live ranges do not stack (registers and LDS decide how
 // many elements share a CU):
 //   1. surface fluxes of the six faces -> LDS (before any volume state is live);
 //   2. per-node two-point data -> LDS (split form);
-//   3. per direction r: the metric row Ja^r (and G~^r) -> LDS, then flux
-//      differencing along r (split) or the D-hat contraction of F~^r (weak);
-//   4. surface lift, 1/J, and the output or the RK stage;
+//   3. per direction r: the metric row Ja^r -> LDS, then flux differencing
+//      along r (split) or the D-hat contraction of F~^r (weak);
+//   4. surface lift, the viscous volume term, 1/J, and the output or the RK stage;
 //   5. face traces of the new state (RK stage).
 // ---------------------------------------------------------------------------
 // Symmetric evaluation of two-point pairs on lines that lie inside one
@@ -405,7 +438,6 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   using S = Shape<N>;
   using FT = typename std::conditional<PREC == 1, float, double>::type;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
-  constexpr int NV = PHYS == 1 ? 4 : 0;                              // viscous values per node and direction
   // split form on Gauss nodes: the entropy-stable hybridised form (face coupling terms)
   constexpr bool ES = FORM == 1 && NODES == 0;
   // lines along xi and eta (all three for n1 = 4) lie inside one wavefront
@@ -414,11 +446,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   // Gauss-node split form: the line sums of the face coupling go through LDS
   // (10 values per node) unless every line lies inside a wavefront
   constexpr bool kEsAllShfl = kSymLines && n1 == 4;
-  // split form, n1 = 4: the lines of all three directions lie inside the
-  // wavefront, and the D-hat sweep of G~^r reads the line's values by shuffles
-  // (no LDS staging: more elements share a CU)
-  constexpr bool kGvShfl = FORM == 1 && kSymLines && n1 == 4;
-  constexpr int SZ_SPLIT = (8 + 3 + (kGvShfl ? 0 : NV) + (ES && !kEsAllShfl ? 10 : 0)) * n3;   // aux + Ja^r (+ G~^r) (+ face coupling)
+  constexpr int SZ_SPLIT = (8 + 3 + (ES && !kEsAllShfl ? 10 : 0)) * n3;   // aux + Ja^r (+ face coupling)
   constexpr int SZ_WEAK = 5 * n3;                                    // F~^r
   constexpr int SZ_V = FORM == 1 ? SZ_SPLIT : SZ_WEAK;
   constexpr int SZ0 = SZ_V > 5 * n3 ? SZ_V : 5 * n3;                 // also holds the new state (Gauss traces)
@@ -434,7 +462,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   __shared__ double sm[SZ];
   __shared__ double saf[ES ? 8 * kFaces * n2 : 1];
   __shared__ VolBasis<N, FV != 0> sb;
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   // FV: which faces are FV (bits 0..5), and whether this element is (bit 6)
   const int efl = FV ? G.efv[e] : 0;
   if (FV && (efl & 64)) return;   // FV elements belong to the FV kernel
@@ -447,11 +475,12 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   // issued first, so that their latency overlaps the surface fluxes; each
   // direction then prefetches the next one's while it computes.
   double u[5] = {0, 0, 0, 0, 0};
-  using VT = typename std::conditional<PREC == 1, float, double>::type;   // stored viscous flux type
   double jn[3] = {0, 0, 0};
-  VT gn[4] = {0, 0, 0, 0};
   // the last direction prefetches what the RK update reads instead
   double sJn = 0.0, dUn[5] = {0, 0, 0, 0, 0}, Un[5] = {0, 0, 0, 0, 0};
+  // Navier-Stokes: the viscous volume term, fetched with the last direction's
+  // metric row and added to the accumulator when that direction starts
+  double vvn[4] = {0, 0, 0, 0};
   auto fetch_end = [&]() {
     sJn = G.sJ[(size_t)e * n3 + t];
     if constexpr (MODE == 1) {
@@ -467,8 +496,10 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
 #pragma unroll
     for (int c = 0; c < 3; ++c) jn[c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
     if constexpr (PHYS == 1) {
+      if (r == 2) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) gn[v] = reinterpret_cast<const VT*>(gvn)[((size_t)(4 * r + v) * nE + e) * n3 + t];
+        for (int v = 0; v < 4; ++v) vvn[v] = gvn[((size_t)v * nE + e) * n3 + t];
+      }
     }
   };
   if (act) {
@@ -570,10 +601,14 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     const double jr[3] = {jn[0], jn[1], jn[2]};
-    const double gv[4] = {double(gn[0]), double(gn[1]), double(gn[2]), double(gn[3])};
+    if constexpr (PHYS == 1) {
+      if (r == 2 && act) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[1 + v] += vvn[v];
+      }
+    }
     if constexpr (FORM == 1) {
       double* sja = sm + 8 * n3;
-      double* sgv = sm + 11 * n3;
       if constexpr (ES) {
         // the faces whose flux is formed in this pass: 0..3 in the first, 4, 5 in the last
         constexpr int fa[3] = {0, 6, 4}, fb[3] = {4, 6, 6};
@@ -582,10 +617,6 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
       if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) sja[c * n3 + t] = jr[c];
-        if constexpr (PHYS == 1 && !kGvShfl) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) sgv[v * n3 + t] = gv[v];
-        }
       }
       __syncthreads();
       if (act) {
@@ -629,21 +660,6 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           // and each lane keeps its own share.
           const int lane = t & 63;
           const int str = r == 0 ? 1 : (r == 1 ? n1 : n2);
-          if constexpr (PHYS == 1) {
-            // viscous part in weak form: acc -= Dhat[a][l] G~^r_l
-            for (int l = 0; l < n1; ++l) {
-              const double c = sb.Dhat[a * n1 + l];
-              if constexpr (kGvShfl) {
-                const int src = lane + (l - a) * str;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[1 + v] -= c * __shfl(gv[v], src);
-              } else {
-                const int tl = line_node<N>(r, l, pp, qq);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[1 + v] -= c * sgv[v * n3 + tl];
-              }
-            }
-          }
 #pragma unroll 1
           for (int d = 1; d <= n1 / 2; ++d) {
             const int b = (a + d) & (n1 - 1);
@@ -662,12 +678,6 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
         } else {
           for (int l = 0; l < n1; ++l) {
             const int tl = line_node<N>(r, l, pp, qq);
-            if constexpr (PHYS == 1) {
-              // viscous part in weak form: acc -= Dhat[a][l] G~^r_l
-              const double c = sb.Dhat[a * n1 + l];
-#pragma unroll
-              for (int v = 0; v < 4; ++v) acc[1 + v] -= c * sgv[v * n3 + tl];
-            }
             if (l == a) continue;
             double F[5];
             pair_flux(tl, F);
@@ -682,7 +692,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           // interpolated to the end f of this line; l_f(a) G_f is staged for
           // the line sums S_f = sum_l l_f(l) G_f(l).
           // The surface term of this direction's two faces is applied here too.
-          double* shy = sm + (11 + (kGvShfl ? 0 : NV)) * n3;
+          double* shy = sm + 11 * n3;
           const int rr = qq * n1 + pp;
 #pragma unroll
           for (int f = 0; f < 2; ++f) {
@@ -726,7 +736,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
         // dU_a -= (1/w_a) B_f l_f(a) (G_f(a) - S_f),  B_f = -1 at xi = -1, +1 at xi = +1
         __syncthreads();
         if (act) {
-          const double* shy = sm + (11 + (kGvShfl ? 0 : NV)) * n3;
+          const double* shy = sm + 11 * n3;
           const int a = idx[r];
           const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
 #pragma unroll
@@ -744,14 +754,11 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
       }
       __syncthreads();
     } else {
-      // weak form: F~^r = Ja^r . (f - G) at every node, then the Dhat contraction
+      // weak form: F~^r = Ja^r . f at every node, then the Dhat contraction
+      // (the viscous part comes contracted from the lifting kernel)
       if (act) {
         double F[5];
         euler_flux<FT>(u, q, jr, F);
-        if constexpr (PHYS == 1) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) F[1 + v] -= gv[v];
-        }
 #pragma unroll
         for (int v = 0; v < 5; ++v) sm[v * n3 + t] = F[v];
       }

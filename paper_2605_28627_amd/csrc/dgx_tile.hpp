@@ -35,6 +35,30 @@ __device__ __forceinline__ void load_basis(DevBasis* dst, const DevBasis* src, i
   for (int x = t; x < nd; x += nth) d[x] = s[x];
 }
 
+// Element of a one-element-per-workgroup launch.  Consecutive workgroups are
+// dealt round-robin to the chip's 8 XCDs, each with its own L2.  With
+// XCD-aware numbering XCD x walks a contiguous block of elements, so an
+// element and its lexicographic neighbours (which read the same face data:
+// traces, face geometry, face viscous fluxes) run on the same XCD close in
+// time and the second read can hit that XCD's L2.  XCD x gets
+// nE/8 (+1 for x < nE%8) elements starting at x (nE/8) + min(x, nE%8); the
+// map is a bijection of [0, nE) for any nE.
+#ifndef DGX_XCD_REMAP
+#define DGX_XCD_REMAP 1
+#endif
+__device__ __forceinline__ int elem_of_block(int bid, int nE) {
+  if constexpr (DGX_XCD_REMAP) {
+    constexpr int kXcd = 8;
+    const int q = nE / kXcd, r = nE - q * kXcd;
+    int x, slot;
+    if (bid < kXcd * q) { x = bid % kXcd; slot = bid / kXcd; }
+    else { x = bid - kXcd * q; slot = q; }
+    return x * q + (x < r ? x : r) + slot;
+  } else {
+    return bid;
+  }
+}
+
 __device__ __forceinline__ size_t tr_index(int slot, int v, int nvar, int nSides, int side, int n2, int fi) {
   return (((size_t)slot * nvar + v) * nSides + side) * n2 + fi;
 }

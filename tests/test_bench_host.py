@@ -25,17 +25,20 @@ def test_more_than_one_gpu_is_refused():
 def test_byte_models():
     # 8 B per value; 0.75 face nodes per volume node at N = 7, 1.5 at N = 3
     c2 = I.WORKLOADS["ns_split_lgl_n7_16x16x16_tgv"]
-    # U 5, Ja + 1/J 10, dU 4 (five-stage average), G~ 12, traces 2x5 and face viscous fluxes 2x4 and
-    # face geometry 4 per face node; writes dU 5, U 5, traces 5 per face node
-    assert bench.volume_kernel_bytes_per_dof(c2) == 8 * (5 + 10 + 4 + 12 + 0.75 * (10 + 8 + 4) + 5 + 5 + 0.75 * 5)
-    assert bench.volume_kernel_bytes_per_dof(c2) == 490
+    # U 5, Ja + 1/J 10, dU 4 (five-stage average), viscous volume term 4, traces 2x5 and face viscous
+    # fluxes 2x4 and face geometry 4 per face node; writes dU 5, U 5, traces 5 per face node
+    assert bench.volume_kernel_bytes_per_dof(c2) == 8 * (5 + 10 + 4 + 4 + 0.75 * (10 + 8 + 4) + 5 + 5 + 0.75 * 5)
+    assert bench.volume_kernel_bytes_per_dof(c2) == 426
     c1 = I.WORKLOADS["euler_weak_lg_n3_64x64x64"]
     assert bench.volume_kernel_bytes_per_dof(c1) == 460
     assert bench.fv_kernel_bytes_per_dof(c1) == 610
     es = I.WORKLOADS["ns_split_lg_n3_64x64x64_freestream"]
-    assert bench.volume_kernel_bytes_per_dof(es) == 652
-    # FP32-flux mode stores the viscous fluxes as float
-    assert bench.volume_kernel_bytes_per_dof(c2, precision=1) == 490 - 4 * (12 + 0.75 * 8)
+    assert bench.volume_kernel_bytes_per_dof(es) == 588
+    # FP32-flux mode stores the face viscous fluxes as float
+    assert bench.volume_kernel_bytes_per_dof(c2, precision=1) == 426 - 4 * 0.75 * 8
+    # lifting: reads U 5, Ja + 1/J 10, traces 2x5 and face geometry 4 per face node;
+    # writes the viscous volume term 4 and the own face viscous flux 4 per face node
+    assert bench.lift_kernel_bytes_per_dof(c2) == 8 * (15 + 0.75 * 14 + 4 + 0.75 * 4) == 260
 
 
 def test_fv_masks():
