@@ -410,7 +410,6 @@ struct Solver {
       if (elemSide[t] < 0) { err = "open face"; return false; }
     Ja.assign(nElems, {}); Jdet.assign(nElems, {}); Xnode.assign(nElems, {}); nvec.assign(nSides, {});
     if (C.fv) {
-      if (C.physics != 0 || hybrid()) { err = "FV sub-cells: Euler with the weak form or the LGL split form"; return false; }
       setup_fv_basis();
       fvmask.assign(nElems, 0);
       Vsub.assign(nElems, {}); Sint.assign(nElems, {}); Sbnd.assign(nSides, {});
@@ -716,6 +715,10 @@ struct Solver {
     std::vector<std::vector<T>> tr;     // per side: [2][5][n2] U traces (master indexing)
     std::vector<std::vector<T>> g;      // per element: [12][n3] lifted gradients
     std::vector<std::vector<T>> gtr;    // per side: [2][12][n2] gradient traces
+    // FV sub-cells: per element the sub-cell means [5][n3], and (Navier-Stokes)
+    // the sub-cell gradients [12][n3]: Green-Gauss for FV elements, the
+    // sub-cell means of the lifted gradient for DG elements
+    std::vector<std::vector<T>> fvc, fvg;
   };
 
   // Face traces of both sides.  Plain interpolation of U, or, in the
@@ -753,6 +756,7 @@ struct Solver {
     if (!W.g[e].empty()) return;
     ensure_geom(e);
     for (int f = 0; f < 6; ++f) { side_traces(U, elemSide[e * 6 + f], W); ensure_side(elemSide[e * 6 + f]); }
+    if (C.fv) ensure_fv_caches(W);
     std::vector<T> q(4 * (size_t)n3);
     for (int t = 0; t < n3; ++t) {
       T Ul[5]; for (int v = 0; v < 5; ++v) Ul[v] = U[uidx(v, e, t)];
@@ -798,6 +802,14 @@ struct Solver {
             T rho, u[3], pr; prim(Ul, rho, u, pr);
             T* qx = side == 0 ? qa : qb;
             qx[0] = u[0]; qx[1] = u[1]; qx[2] = u[2]; qx[3] = pr / (rho * C.R);
+          }
+          if (C.fv && side_fv(s)) {
+            // the other side is an FV element: its q at this face node is the
+            // face polynomial whose sub-face means are its layer-0 values
+            T qf[4];
+            fv_face_q(U, e, f, pp, qq, W, qf);
+            T* qo = (m == 0) ? qb : qa;
+            for (int a = 0; a < 4; ++a) qo[a] = qf[a];
           }
           double ns[3];
           for (int c = 0; c < 3; ++c) ns[c] = (m == 0 ? 1.0 : -1.0) * nvec[s][(size_t)c * n2 + fi];
@@ -1153,17 +1165,22 @@ struct Solver {
     T lmax = maxv(T(absv(unl) + cl), T(absv(unr) + cr));
     for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * (lmax * sA) * (UR[v] - UL[v]);
   }
+  template <class T> void ensure_fv_caches(Work<T>& W) const {
+    if (W.fvc.empty()) W.fvc.assign(nElems, {});
+    if (C.physics == 1 && W.fvg.empty()) W.fvg.assign(nElems, {});
+  }
   // Sub-cell means of element e ([5][n3]): its state if FV, else its DG state's means (cached).
-  template <class T> const std::vector<T>& elem_means(const T* U, int e, std::vector<std::vector<T>>& cache) {
-    if (cache[e].empty()) {
-      cache[e].assign(5 * (size_t)n3, T(0.0));
+  template <class T> const std::vector<T>& elem_means(const T* U, int e, Work<T>& W) {
+    std::vector<T>& c = W.fvc[e];
+    if (c.empty()) {
+      c.assign(5 * (size_t)n3, T(0.0));
       std::vector<T> Ue(5 * (size_t)n3);
       for (int v = 0; v < 5; ++v)
         for (int t = 0; t < n3; ++t) Ue[(size_t)v * n3 + t] = U[uidx(v, e, t)];
-      if (fvmask[e]) cache[e] = Ue;
-      else dg_to_fv(e, Ue.data(), cache[e].data());
+      if (fvmask[e]) c = Ue;
+      else dg_to_fv(e, Ue.data(), c.data());
     }
-    return cache[e];
+    return c;
   }
   // Primitive mean of the sub-cell in layer `layer` (0 = at the face) under face f, face-local (pp, qq).
   template <class T> void layer_w(const std::vector<T>& M, int f, int pp, int qq, int layer, T* W) const {
@@ -1173,28 +1190,144 @@ struct Solver {
     for (int v = 0; v < 5; ++v) Uc[v] = M[(size_t)v * n3 + node(i, j, k)];
     cons_to_w(Uc, W);
   }
-  // Master-outward sub-face fluxes [5][n2] of an FV side (master sub-face indexing).
-  template <class T> void side_flux_fv(const T* U, int s, std::vector<std::vector<T>>& cache, std::vector<T>& F) {
+  // Lifted variables q = (u, v, w, T) of a primitive state.
+  template <class T> void w_to_q(const T* W, T* q) const {
+    q[0] = W[1]; q[1] = W[2]; q[2] = W[3]; q[3] = W[4] / (W[0] * C.R);
+  }
+
+  // ---- Navier-Stokes on FV sub-cells (a reading; the paper names the FV
+  // sub-cell scheme without its viscous terms).  BR1's ingredients carried to
+  // the sub-cells: Green-Gauss gradients with central face values of
+  // q = (u, v, w, T), and the central mean of both sides' viscous fluxes on
+  // every sub-face.  Across an element face the other side is the neighbour's
+  // layer-0 sub-cell: its state means, and its gradient (Green-Gauss if FV,
+  // the sub-cell mean of its lifted gradient if DG).
+
+  // Sub-cell gradients of element e ([12][n3], component 3a+d = dq_a/dx_d):
+  //   FV element: g_s = (1/V_s) sum over its six sub-faces of 1/2 (q_s + q_s') S_out;
+  //   DG element: the sub-cell means of its lifted gradient, B3(J g)/V.
+  template <class T> const std::vector<T>& elem_grad(const T* U, int e, Work<T>& W) {
+    std::vector<T>& g = W.fvg[e];
+    if (!g.empty()) return g;
+    ensure_fv_geom(e);
+    g.assign(12 * (size_t)n3, T(0.0));
+    if (!fvmask[e]) {
+      lift_elem(U, e, W);
+      std::vector<T> jg(n3), m(n3);
+      for (int c = 0; c < 12; ++c) {
+        for (int t = 0; t < n3; ++t) jg[t] = Jdet[e][t] * W.g[e][(size_t)c * n3 + t];
+        apply3(Bsub, jg.data(), m.data());
+        for (int t = 0; t < n3; ++t) g[(size_t)c * n3 + t] = m[t] / Vsub[e][t];
+      }
+      return g;
+    }
+    const int N = C.N;
+    const std::vector<T>& M = elem_means(U, e, W);
+    std::vector<T> q(4 * (size_t)n3);
+    for (int t = 0; t < n3; ++t) {
+      T Uc[5], Wc[5], qc[4];
+      for (int v = 0; v < 5; ++v) Uc[v] = M[(size_t)v * n3 + t];
+      cons_to_w(Uc, Wc); w_to_q(Wc, qc);
+      for (int a = 0; a < 4; ++a) q[(size_t)a * n3 + t] = qc[a];
+    }
+    auto add = [&](int t, const T* qf, const double* S, double sg) {
+      for (int a = 0; a < 4; ++a)
+        for (int d = 0; d < 3; ++d) g[(size_t)(3 * a + d) * n3 + t] += sg * (qf[a] * S[d]);
+    };
+    for (int r = 0; r < 3; ++r)
+      for (int qq = 0; qq < n1; ++qq)
+        for (int pp = 0; pp < n1; ++pp) {
+          // interior sub-faces between layers kk and kk+1 along r
+          for (int kk = 0; kk < N; ++kk) {
+            int i, j, k; vol_ijk(2 * r, pp, qq, kk, i, j, k);
+            int i2, j2, k2; vol_ijk(2 * r, pp, qq, kk + 1, i2, j2, k2);
+            const int ta = node(i, j, k), tb = node(i2, j2, k2);
+            double S[3];
+            for (int c = 0; c < 3; ++c) S[c] = Sint[e][(((size_t)(3 * r + c)) * N + kk) * n2 + qq * n1 + pp];
+            T qf[4];
+            for (int a = 0; a < 4; ++a) qf[a] = 0.5 * (q[(size_t)a * n3 + ta] + q[(size_t)a * n3 + tb]);
+            add(ta, qf, S, 1.0);
+            add(tb, qf, S, -1.0);
+          }
+          // the two element faces normal to r
+          for (int end = 0; end < 2; ++end) {
+            const int f = 2 * r + end, s = elemSide[e * 6 + f], m = elemSlot[e * 6 + f];
+            int p = pp, qm = qq;
+            if (m == 1) orient_inv(sideOrient[s], C.N, pp, qq, p, qm);
+            ensure_fv_side(s);
+            double S[3];
+            for (int c = 0; c < 3; ++c) S[c] = (m == 0 ? 1.0 : -1.0) * Sbnd[s][(size_t)c * n2 + qm * n1 + p];
+            int i, j, k; vol_ijk(f, pp, qq, end ? N : 0, i, j, k);
+            const int t = node(i, j, k);
+            T Wg[5], qg[4], qf[4];
+            ghost_w(U, e, f, pp, qq, W, Wg);
+            w_to_q(Wg, qg);
+            for (int a = 0; a < 4; ++a) qf[a] = 0.5 * (q[(size_t)a * n3 + t] + qg[a]);
+            add(t, qf, S, 1.0);
+          }
+        }
+    for (size_t c = 0; c < 12; ++c)
+      for (int t = 0; t < n3; ++t) g[c * n3 + t] = g[c * n3 + t] / Vsub[e][t];
+    return g;
+  }
+  // Gradient of the sub-cell in layer 0 under face f of element e, face-local (pp, qq).
+  template <class T> void layer_g(const T* U, int e, int f, int pp, int qq, Work<T>& W, T* g) {
+    const std::vector<T>& G = elem_grad(U, e, W);
+    int i, j, k; vol_ijk(f, pp, qq, (f % 2) ? C.N : 0, i, j, k);
+    for (int c = 0; c < 12; ++c) g[c] = G[(size_t)c * n3 + node(i, j, k)];
+  }
+  // Viscous flux G(W, g) . S of a primitive state and a gradient through the area vector S.
+  template <class T> void visc_w(const T* Wp, const T* g, const double* S, T* F) const {
+    T Uc[5];
+    w_to_cons(Wp, Uc);
+    for (int v = 0; v < 5; ++v) F[v] = T(0.0);
+    for (int n = 0; n < 3; ++n) {
+      T Gn[5]; flux_visc(Uc, g, n, Gn);
+      for (int v = 0; v < 5; ++v) F[v] += Gn[v] * S[n];
+    }
+  }
+
+  // Master-outward sub-face fluxes [5][n2] of an FV side (master sub-face
+  // indexing): Rusanov between the MUSCL-reconstructed states, minus (Navier-
+  // Stokes) the central mean of both layer-0 sub-cells' viscous fluxes.
+  // Both sides' layer-0 means W0 and reconstructed face states Wf at master
+  // sub-face (p, q) of an FV side: Wf = W0 + 1/2 minmod(W0 - W1, W0' - W0),
+  // W1 the layer-1 mean, W0' the other side's layer-0 mean.
+  template <class T> void side_face_states(const T* U, int s, int p, int q, Work<T>& W, T W0[2][5], T Wf[2][5]) {
+    T W1[2][5];
+    for (int m = 0; m < 2; ++m) {
+      const int e = sideElem[2 * s + m], f = sideLoc[2 * s + m];
+      int pp = p, qq = q;
+      if (m == 1) orient_fwd(sideOrient[s], C.N, p, q, pp, qq);
+      const std::vector<T>& M = elem_means(U, e, W);
+      layer_w(M, f, pp, qq, 0, W0[m]); layer_w(M, f, pp, qq, 1, W1[m]);
+    }
+    for (int m = 0; m < 2; ++m)
+      for (int v = 0; v < 5; ++v) {
+        const T sg = minmod(T(W0[m][v] - W1[m][v]), T(W0[1 - m][v] - W0[m][v]));
+        Wf[m][v] = W0[m][v] + 0.5 * sg;
+      }
+  }
+  template <class T> void side_flux_fv(const T* U, int s, Work<T>& W, std::vector<T>& F) {
     ensure_fv_side(s);
     F.assign(5 * (size_t)n2, T(0.0));
     for (int q = 0; q < n1; ++q)
       for (int p = 0; p < n1; ++p) {
-        T W0[2][5], W1[2][5];
-        for (int m = 0; m < 2; ++m) {
-          const int e = sideElem[2 * s + m], f = sideLoc[2 * s + m];
-          int pp = p, qq = q;
-          if (m == 1) orient_fwd(sideOrient[s], C.N, p, q, pp, qq);
-          const std::vector<T>& M = elem_means(U, e, cache);
-          layer_w(M, f, pp, qq, 0, W0[m]); layer_w(M, f, pp, qq, 1, W1[m]);
-        }
-        T Wf[2][5];
-        for (int m = 0; m < 2; ++m)
-          for (int v = 0; v < 5; ++v) {
-            const T sg = minmod(T(W0[m][v] - W1[m][v]), T(W0[1 - m][v] - W0[m][v]));
-            Wf[m][v] = W0[m][v] + 0.5 * sg;
+        T W0[2][5], Wf[2][5], G0[2][12];
+        side_face_states(U, s, p, q, W, W0, Wf);
+        if (C.physics == 1)
+          for (int m = 0; m < 2; ++m) {
+            int pp = p, qq = q;
+            if (m == 1) orient_fwd(sideOrient[s], C.N, p, q, pp, qq);
+            layer_g(U, sideElem[2 * s + m], sideLoc[2 * s + m], pp, qq, W, G0[m]);
           }
         const double S[3] = {Sbnd[s][q * n1 + p], Sbnd[s][(size_t)n2 + q * n1 + p], Sbnd[s][2 * (size_t)n2 + q * n1 + p]};
         T Fs[5]; rusanov_w(Wf[0], Wf[1], S, Fs);
+        if (C.physics == 1) {
+          T GL[5], GR[5];
+          visc_w(W0[0], G0[0], S, GL); visc_w(W0[1], G0[1], S, GR);
+          for (int v = 0; v < 5; ++v) Fs[v] -= 0.5 * (GL[v] + GR[v]);
+        }
         for (int v = 0; v < 5; ++v) F[(size_t)v * n2 + q * n1 + p] = Fs[v];
       }
   }
@@ -1211,7 +1344,7 @@ struct Solver {
         }
   }
   // Primitive layer-0 mean of the neighbour across face f of element e, at own face-local (pp, qq).
-  template <class T> void ghost_w(const T* U, int e, int f, int pp, int qq, std::vector<std::vector<T>>& cache, T* W) {
+  template <class T> void ghost_w(const T* U, int e, int f, int pp, int qq, Work<T>& W, T* Wout) {
     const int s = elemSide[e * 6 + f], m = elemSlot[e * 6 + f];
     int p = pp, q = qq;
     if (m == 1) orient_inv(sideOrient[s], C.N, pp, qq, p, q);
@@ -1219,14 +1352,36 @@ struct Solver {
     const int eo = sideElem[2 * s + o], fo = sideLoc[2 * s + o];
     int po = p, qo = q;
     if (o == 1) orient_fwd(sideOrient[s], C.N, p, q, po, qo);
-    layer_w(elem_means(U, eo, cache), fo, po, qo, 0, W);
+    layer_w(elem_means(U, eo, W), fo, po, qo, 0, Wout);
   }
-  // FV residual of element e: dmean/dt = -(1/V) sum of outward sub-face fluxes.
-  template <class T> void residual_fv(const T* U, int e, std::vector<std::vector<T>>& cache,
-                                     std::vector<std::vector<T>>& sfv, T* Ut) {
+  // Lifting of a DG element on an FV face: the FV neighbour's q at the own
+  // face node (pp, qq) is the face polynomial whose reference sub-face means
+  // are the q of the FV side's reconstructed face states (those the face
+  // flux uses): q = h^2 (B^-1 x B^-1) q_f, h = 2/(N+1).  B integrates over the
+  // sub-intervals, so this is the degree-N polynomial with those means; for
+  // a linear field it is the field itself.
+  template <class T> void fv_face_q(const T* U, int e, int f, int pp, int qq, Work<T>& W, T* qf) {
+    const double h = 2.0 / n1;
+    const int s = elemSide[e * 6 + f], m = elemSlot[e * 6 + f];
+    for (int a = 0; a < 4; ++a) qf[a] = T(0.0);
+    for (int q2 = 0; q2 < n1; ++q2)
+      for (int p2 = 0; p2 < n1; ++p2) {
+        int p = p2, q = q2;
+        if (m == 1) orient_inv(sideOrient[s], C.N, p2, q2, p, q);
+        T W0[2][5], Wf[2][5], qg[4];
+        side_face_states(U, s, p, q, W, W0, Wf);
+        w_to_q(Wf[1 - m], qg);
+        const double c = h * h * Bsubinv[pp * n1 + p2] * Bsubinv[qq * n1 + q2];
+        for (int a = 0; a < 4; ++a) qf[a] += c * qg[a];
+      }
+  }
+  // FV residual of element e: dmean/dt = -(1/V) sum of outward sub-face fluxes
+  // (advective minus viscous).
+  template <class T> void residual_fv(const T* U, int e, Work<T>& Wk, std::vector<std::vector<T>>& sfv, T* Ut) {
     ensure_fv_geom(e);
     const int N = C.N;
-    const std::vector<T>& M = elem_means(U, e, cache);
+    const std::vector<T>& M = elem_means(U, e, Wk);
+    const std::vector<T>* Gp = C.physics == 1 ? &elem_grad(U, e, Wk) : nullptr;
     std::vector<T> R(5 * (size_t)n3, T(0.0));
     for (int r = 0; r < 3; ++r)
       for (int qq = 0; qq < n1; ++qq)
@@ -1239,8 +1394,8 @@ struct Solver {
             for (int v = 0; v < 5; ++v) Uc[v] = M[(size_t)v * n3 + node(i, j, k)];
             cons_to_w(Uc, W[l + 1].data());
           }
-          ghost_w(U, e, 2 * r, pp, qq, cache, W[0].data());
-          ghost_w(U, e, 2 * r + 1, pp, qq, cache, W[n1 + 1].data());
+          ghost_w(U, e, 2 * r, pp, qq, Wk, W[0].data());
+          ghost_w(U, e, 2 * r + 1, pp, qq, Wk, W[n1 + 1].data());
           std::vector<std::array<T, 5>> sg(n1);
           for (int l = 0; l < n1; ++l)
             for (int v = 0; v < 5; ++v) sg[l][v] = minmod(T(W[l + 2][v] - W[l + 1][v]), T(W[l + 1][v] - W[l][v]));
@@ -1252,6 +1407,16 @@ struct Solver {
             T F[5]; rusanov_w(WL, WR, S, F);
             int i, j, k; vol_ijk(2 * r, pp, qq, kk, i, j, k);
             int i2, j2, k2; vol_ijk(2 * r, pp, qq, kk + 1, i2, j2, k2);
+            if (Gp) {
+              // central viscous flux between the two sub-cells (means and their gradients)
+              T ga[12], gb[12], GL[5], GR[5];
+              for (int c = 0; c < 12; ++c) {
+                ga[c] = (*Gp)[(size_t)c * n3 + node(i, j, k)];
+                gb[c] = (*Gp)[(size_t)c * n3 + node(i2, j2, k2)];
+              }
+              visc_w(W[kk + 1].data(), ga, S, GL); visc_w(W[kk + 2].data(), gb, S, GR);
+              for (int v = 0; v < 5; ++v) F[v] -= 0.5 * (GL[v] + GR[v]);
+            }
             for (int v = 0; v < 5; ++v) {
               R[(size_t)v * n3 + node(i, j, k)] -= F[v];
               R[(size_t)v * n3 + node(i2, j2, k2)] += F[v];
@@ -1272,6 +1437,7 @@ struct Solver {
     for (int v = 0; v < 5; ++v)
       for (int t = 0; t < n3; ++t) Ut[oidx(v, e, t)] = R[(size_t)v * n3 + t] / Vsub[e][t];
   }
+
   // Persson-Peraire indicator: log10 of the share of the highest modes
   // (max(i,j,k) = N in the orthonormal Legendre basis) in the energy of rho.
   double indicator(const double* U, int e) {
@@ -1405,21 +1571,22 @@ struct Solver {
     std::vector<int> el = elist;
     if (el.empty()) { el.resize(nElems); for (int e = 0; e < nElems; ++e) el[e] = e; }
     std::vector<std::vector<T>> sflux(nSides);
-    std::vector<std::vector<T>> sfv(C.fv ? nSides : 0), fvcache(C.fv ? nElems : 0);
+    std::vector<std::vector<T>> sfv(C.fv ? nSides : 0);
+    if (C.fv) ensure_fv_caches(W);
     for (int e : el) {
-      if (C.physics == 1) lift_elem(U, e, W);
+      if (C.physics == 1 && !(C.fv && fvmask[e])) lift_elem(U, e, W);
       for (int f = 0; f < 6; ++f) {
         int s = elemSide[e * 6 + f];
         if (C.fv && side_fv(s)) {
           // FV face: sub-face fluxes; the DG side takes their face polynomial
-          if (sfv[s].empty()) { side_flux_fv(U, s, fvcache, sfv[s]); fv_face_to_nodal(sfv[s], sflux[s]); }
+          if (sfv[s].empty()) { side_flux_fv(U, s, W, sfv[s]); fv_face_to_nodal(sfv[s], sflux[s]); }
         } else if (sflux[s].empty()) {
           side_flux(U, s, W, sflux[s]);
         }
       }
     }
     for (int e : el) {
-      if (C.fv && fvmask[e]) residual_fv(U, e, fvcache, sfv, Ut);
+      if (C.fv && fvmask[e]) residual_fv(U, e, W, sfv, Ut);
       else residual_elem(U, e, W, sflux, Ut, t);
     }
   }
@@ -1889,6 +2056,22 @@ int orc_fv_operators(void* h, double* Bs, double* Bsi, double* Vli) {
   Solver* S = (Solver*)h;
   if (!S->C.fv) { g_err = "FV sub-cells not enabled"; return 1; }
   for (int x = 0; x < S->n1 * S->n1; ++x) { Bs[x] = S->Bsub[x]; Bsi[x] = S->Bsubinv[x]; Vli[x] = S->Vleginv[x]; }
+  return 0;
+}
+// Sub-cell gradients of every element [12][nElems][n3] (Navier-Stokes FV
+// contexts): Green-Gauss for FV elements, the sub-cell means of the lifted
+// gradient for DG elements.
+int orc_fv_gradients(void* h, const double* U, double* g) {
+  Solver* S = (Solver*)h;
+  if (!S->C.fv || S->C.physics != 1) { g_err = "FV gradients: Navier-Stokes FV contexts only"; return 1; }
+  Solver::Work<double> W;
+  W.tr.assign(S->nSides, {}); W.gtr.assign(S->nSides, {}); W.g.assign(S->nElems, {});
+  S->ensure_fv_caches(W);
+  for (int e = 0; e < S->nElems; ++e) {
+    const std::vector<double>& G = S->elem_grad(U, e, W);
+    for (int c = 0; c < 12; ++c)
+      for (int t = 0; t < S->n3; ++t) g[((size_t)c * S->nElems + e) * S->n3 + t] = G[(size_t)c * S->n3 + t];
+  }
   return 0;
 }
 // Element-wise DG -> FV (dir 0) or FV -> DG (dir 1) of a [5][n3] block.

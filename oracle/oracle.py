@@ -102,6 +102,7 @@ def load(path):
     L.orc_rhs_sample.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip]
     L.orc_opcount_point.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_uint64)]
     L.orc_geometry_sample.argtypes = [ctypes.c_void_p, ctypes.c_int, _ip, _dp, _dp, _dp]
+    L.orc_fv_gradients.argtypes = [ctypes.c_void_p, _dp, _dp]
     L.orc_rhs_vjp.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_double]
     L.orc_kinetic_energy_grad.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, _dp]
     L.orc_lserk_adjoint.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
@@ -417,6 +418,15 @@ class Oracle:
         ind = np.zeros(self.nElems)
         self.L.orc_fv_indicator(self.h, _d(np.ascontiguousarray(U, dtype=np.float64)), _d(ind))
         return ind
+
+    def fv_gradients(self, U):
+        """Sub-cell gradients [12][nElems][...] of a Navier-Stokes FV context:
+        Green-Gauss for FV elements, sub-cell means of the lifted gradient for DG."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        n = self.n1
+        g = np.zeros((12, self.nElems, n, n, n))
+        self._chk(self.L.orc_fv_gradients(self.h, _d(U), _d(g)))
+        return g
 
     def fv_geometry(self):
         n = self.n1
