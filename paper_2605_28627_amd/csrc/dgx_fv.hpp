@@ -87,12 +87,50 @@ __device__ inline void fv_face_states(const double* __restrict__ Utr, const doub
   for (int c = 0; c < 3; ++c) S[c] = fvSb[((size_t)c * nS + side) * n2 + fi];
 }
 
+// The reconstructed face value of slot m's side alone (as in fv_face_states).
+__device__ inline void fv_face_state_of(const double* __restrict__ Utr, int nS, int n2, int side, int fi, int m,
+                                        double Wf[5]) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double w0 = Utr[tr_index(m, v, kTrFV, nS, side, n2, fi)];
+    const double w1 = Utr[tr_index(m, 5 + v, kTrFV, nS, side, n2, fi)];
+    const double wg = Utr[tr_index(1 - m, v, kTrFV, nS, side, n2, fi)];
+    Wf[v] = w0 + 0.5 * minmod(w0 - w1, wg - w0);
+  }
+}
+
 // Flux through sub-face fi of an FV side, along the master normal.
 __device__ inline void fv_face_flux(const double* __restrict__ Utr, const double* __restrict__ fvSb, int nS, int n2,
                                     int side, int fi, const Phys& P, double F[5]) {
   double W0f[5], W1f[5], S[3];
   fv_face_states(Utr, fvSb, nS, n2, side, fi, W0f, W1f, S);
   rusanov_prim(W0f, W1f, S, P, F);
+}
+
+// Navier-Stokes FV contexts.  The layer-0 sub-cell gradients of both sides
+// of an FV face sit in gtr2[slot][12][side][fi] (component 3a+d = dq_a/dx_d,
+// q = (u, v, w, T)): Green-Gauss for an FV element, the sub-cell mean of the
+// lifted gradient for a DG element.  The viscous part of a sub-face flux is
+// the central mean of both layer-0 sub-cells' viscous fluxes.
+__device__ __forceinline__ Prim prim_of_w(const double W[5]) {
+  Prim q;
+  q.rho = W[0]; q.u[0] = W[1]; q.u[1] = W[2]; q.u[2] = W[3]; q.p = W[4];
+  return q;
+}
+// F -= 1/2 (G(W0_master, g0_master) + G(W0_slave, g0_slave)) . S on sub-face fi.
+__device__ inline void fv_face_visc(const double* __restrict__ Utr, const double* __restrict__ gtr2, int nS, int n2,
+                                    int side, int fi, const double S[3], const Phys& P, double F[5]) {
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    double W[5], g[12], Gn[4];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) W[v] = Utr[tr_index(m, v, kTrFV, nS, side, n2, fi)];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) g[c] = gtr2[tr_index(m, c, 12, nS, side, n2, fi)];
+    viscous_flux<double, 0>(prim_of_w(W), g, P, S, Gn);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) F[1 + v] -= 0.5 * Gn[v];
+  }
 }
 
 // a <- M_i a, M_j, M_k in turn (tensor product of the n1 x n1 matrix M along
@@ -239,11 +277,121 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace_fv(Geo G, Phys P, const
 }
 
 // ---------------------------------------------------------------------------
-// FV elements: residual (MODE 0) or one LSERK stage and the next traces (MODE 1).
+// Navier-Stokes, FV elements: Green-Gauss sub-cell gradients of q = (u, v, w, T),
+//   g_s = (1/V_s) sum over the six sub-faces of 1/2 (q_s + q_s') S_out,
+// with the neighbour element's layer-0 means across element faces (from the
+// traces).  All twelve components go to gout[c][e][n3] (the FV residual
+// kernel reads them), the layer-0 ones to gtr2[slot][12][side][fi].
 // ---------------------------------------------------------------------------
-template <int N, int MODE>
+template <int N>
+__global__ __launch_bounds__(Shape<N>::nth) void k_lift_fv(Geo G, Phys P, const double* __restrict__ U,
+                                                           const double* __restrict__ Utr, double* __restrict__ gout,
+                                                           double* __restrict__ gtr2) {
+  using S = Shape<N>;
+  constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
+  if (!G.etype[e]) return;   // DG elements belong to the lifting kernel
+  const int nE = G.nElems, nS = G.nSides;
+  __shared__ double sq[4 * n3];
+  const bool act = t < n3;
+  const int i = t % n1, j = (t / n1) % n1, k = t / n2;
+  const int idx[3] = {i, j, k};
+  double q[4] = {0, 0, 0, 0}, V = 1.0;
+  if (act) {
+    double u[5], W[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+    V = G.fvV[(size_t)e * n3 + t];
+    cons_to_prim5(u, P.gm1, W);
+    q[0] = W[1]; q[1] = W[2]; q[2] = W[3]; q[3] = W[4] / (W[0] * P.R);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sq[c * n3 + t] = q[c];
+  }
+  __syncthreads();
+  if (!act) return;
+  double g[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) g[c] = 0.0;
+  auto add = [&](const double qf[4], const double Sv[3], double sg) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) g[3 * a + d] += sg * (qf[a] * Sv[d]);
+  };
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int a = idx[r];
+    const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+    const int rr = qq * n1 + pp;
+    const int str = r == 0 ? 1 : (r == 1 ? n1 : n2);
+#pragma unroll
+    for (int end = 0; end < 2; ++end) {
+      double qf[4], Sv[3], sg;
+      const bool inner = end ? a < N : a > 0;
+      if (inner) {
+        // sub-face between layers kk and kk+1 along +xi_r
+        const int kk = end ? a : a - 1;
+        const int tn = end ? t + str : t - str;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Sv[c] = G.fvS[(((size_t)(3 * r + c) * nE + e) * N + kk) * n2 + rr];
+        // the mean of the lower and the upper sub-cell's q
+#pragma unroll
+        for (int c = 0; c < 4; ++c) qf[c] = end ? 0.5 * (q[c] + sq[c * n3 + tn]) : 0.5 * (sq[c * n3 + tn] + q[c]);
+        sg = end ? 1.0 : -1.0;
+      } else {
+        const int info = G.efc[e * 6 + 2 * r + end];
+        const int side = efc_side(info), slot = efc_slot(info);
+        int p = pp, qm = qq;
+        if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+        const int fi = qm * n1 + p;
+        double Wg[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Wg[v] = Utr[tr_index(1 - slot, v, kTrFV, nS, side, n2, fi)];
+        const double qg[4] = {Wg[1], Wg[2], Wg[3], Wg[4] / (Wg[0] * P.R)};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Sv[c] = G.fvSb[((size_t)c * nS + side) * n2 + fi];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) qf[c] = 0.5 * (q[c] + qg[c]);
+        sg = slot ? -1.0 : 1.0;   // outward from the master-outward vector
+      }
+      add(qf, Sv, sg);
+    }
+  }
+  const double iv = 1.0 / V;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    g[c] *= iv;
+    gout[((size_t)c * nE + e) * n3 + t] = g[c];
+  }
+  // layer-0 sub-cells: their gradient into the faces' gradient traces
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int a = idx[r];
+    if (a != 0 && a != N) continue;
+#pragma unroll
+    for (int end = 0; end < 2; ++end) {
+      if (a != (end ? N : 0)) continue;
+      const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+      const int info = G.efc[e * 6 + 2 * r + end];
+      const int side = efc_side(info), slot = efc_slot(info);
+      int p = pp, qm = qq;
+      if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) gtr2[tr_index(slot, c, 12, nS, side, n2, qm * n1 + p)] = g[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FV elements: residual (MODE 0) or one LSERK stage and the next traces (MODE 1).
+// Navier-Stokes (PHYS 1): the sub-face fluxes subtract the central mean of
+// both sub-cells' viscous fluxes; the gradients come from k_lift_fv (gin,
+// and gtr2 for the element faces).
+// ---------------------------------------------------------------------------
+template <int N, int MODE, int PHYS = 0>
 __global__ __launch_bounds__(Shape<N>::nth) void k_fv(Geo G, Phys P, const double* __restrict__ U,
-                                                      const double* __restrict__ Utr, double* __restrict__ Ut,
+                                                      const double* __restrict__ Utr, const double* __restrict__ gin,
+                                                      const double* __restrict__ gtr2, double* __restrict__ Ut,
                                                       double* __restrict__ Uio, double* __restrict__ dU,
                                                       double* __restrict__ Utr_next, double A, double B, double dt) {
   using S = Shape<N>;
@@ -255,15 +403,24 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_fv(Geo G, Phys P, const doubl
   __shared__ double ssl[5 * n3];
   __shared__ double sfl[5 * n3];
   __shared__ double sfe[3 * 5 * n2];   // outward fluxes through the upper element faces 1, 3, 5
+  __shared__ double sgr[PHYS == 1 ? 12 * n3 : 1];   // sub-cell gradients
   const bool act = t < n3;
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   const int idx[3] = {i, j, k};
   double u[5] = {0, 0, 0, 0, 0}, W[5] = {0, 0, 0, 0, 0}, acc[5] = {0, 0, 0, 0, 0};
   double V = 1.0;
+  double gme[PHYS == 1 ? 12 : 1];
   if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
     V = G.fvV[(size_t)e * n3 + t];
+    if constexpr (PHYS == 1) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        gme[c] = gin[((size_t)c * nE + e) * n3 + t];
+        sgr[c * n3 + t] = gme[c];
+      }
+    }
   }
   // Fluxes through the three upper element faces (their loads overlap the
   // state's).  The lower element face of each line rides along with the
@@ -274,8 +431,10 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_fv(Geo G, Phys P, const doubl
     const int side = efc_side(info), slot = efc_slot(info);
     int p = pp, qm = qq;
     if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
-    double F[5];
-    fv_face_flux(Utr, G.fvSb, nS, n2, side, qm * n1 + p, P, F);
+    double F[5], W0f[5], W1f[5], Sv[3];
+    fv_face_states(Utr, G.fvSb, nS, n2, side, qm * n1 + p, W0f, W1f, Sv);
+    rusanov_prim(W0f, W1f, Sv, P, F);
+    if constexpr (PHYS == 1) fv_face_visc(Utr, gtr2, nS, n2, side, qm * n1 + p, Sv, P, F);
     const double sg = slot ? -1.0 : 1.0;   // outward
 #pragma unroll
     for (int v = 0; v < 5; ++v) sfe[(r * 5 + v) * n2 + rr] = sg * F[v];
@@ -329,6 +488,22 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_fv(Geo G, Phys P, const doubl
       }
       double F[5];
       rusanov_prim(WL, WR, Sv, P, F);
+      if constexpr (PHYS == 1) {
+        if (a > 0) {
+          // central mean of the two sub-cells' viscous fluxes (cell means and gradients)
+          double Wl[5], gl[12], Gl[4], Gr[4];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Wl[v] = sw[v * n3 + t - str];
+#pragma unroll
+          for (int c = 0; c < 12; ++c) gl[c] = sgr[c * n3 + t - str];
+          viscous_flux<double, 0>(prim_of_w(Wl), gl, P, Sv, Gl);
+          viscous_flux<double, 0>(prim_of_w(W), gme, P, Sv, Gr);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) F[1 + v] -= 0.5 * (Gl[v] + Gr[v]);
+        } else {
+          fv_face_visc(Utr, gtr2, nS, n2, side[0], fi[0], Sv, P, F);
+        }
+      }
       if (a > 0) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) { sfl[v * n3 + t] = F[v]; acc[v] += F[v]; }

@@ -360,10 +360,12 @@ dg_status dg_create(const dg_config* cfg, dg_ctx** out) {
     return fail(nullptr, DG_ERR_ARG, "dg_create: gas constants");
   if (c.N < 1 || c.N > kMaxN) return fail(nullptr, DG_ERR_UNSUPPORTED, "dg_create: N must be in 1..7");
   if (c.fv != 0 && c.fv != 1) return fail(nullptr, DG_ERR_ARG, "dg_create: fv");
-  if (c.fv && (c.physics != DG_PHYS_EULER || c.precision != DG_PREC_FP64 || c.riemann != DG_RIEMANN_RUSANOV ||
-               (c.volume_form == DG_FORM_SPLIT && c.nodes == DG_NODES_GAUSS)))
+  if (c.fv && (c.precision != DG_PREC_FP64 || c.riemann != DG_RIEMANN_RUSANOV ||
+               (c.volume_form == DG_FORM_SPLIT && c.nodes == DG_NODES_GAUSS) ||
+               (c.physics == DG_PHYS_NAVIER_STOKES && c.viscosity != DG_VISC_CONSTANT)))
     return fail(nullptr, DG_ERR_UNSUPPORTED,
-                "dg_create: FV sub-cells cover Euler, FP64, Rusanov, the weak form and the Lobatto split form");
+                "dg_create: FV sub-cells cover FP64, Rusanov, the weak form and the Lobatto split form "
+                "(Navier-Stokes: constant viscosity)");
   dg_ctx* x = new (std::nothrow) dg_ctx();
   if (!x) return fail(nullptr, DG_ERR_NOMEM, "dg_create: host allocation");
   x->cfg = c;
@@ -792,7 +794,9 @@ static WsLayout ws_layout(const dg_ctx* c) {
   const int tv = c->cfg.fv ? 10 : (es ? 7 : 5);
   for (int b = 0; b < 2; ++b) { L.utr[b] = off; off += align256(2 * (size_t)tv * nf * sizeof(double)); }
   const bool ns = c->cfg.physics == DG_PHYS_NAVIER_STOKES;
-  L.gtr = off; off += ns ? align256(2 * 12 * nf * sizeof(double)) : 0;
+  // lifted face data [2 slots][12][nf]; FV contexts: the face-normal viscous
+  // fluxes [2][4][nf], then the layer-0 sub-cell gradients [2][12][nf]
+  L.gtr = off; off += ns ? align256(2 * (c->cfg.fv ? 16 : 12) * nf * sizeof(double)) : 0;
   L.g = off; off += ns ? align256(12 * nv * sizeof(double)) : 0;
   L.red = off; off += align256((size_t)(2 * reduction_blocks() + 8) * sizeof(double));
   L.fvind = off; off += c->cfg.fv ? align256((size_t)c->nElems * sizeof(double)) : 0;
@@ -893,7 +897,7 @@ static dg_status stage(dg_ctx* c, int mode, const double* U, double* Ut, double*
   if (c->cfg.fv) {
     // FV elements (the volume kernel above leaves them untouched)
     ProfScope ps(c, FAM_FV, s);
-    LAUNCHCHK(c, launch_fv(k, g, c->phys, mode, U, w.Utr[cur], Ut, Uio, dU, w.Utr[cur ^ 1], A, B, dt, s));
+    LAUNCHCHK(c, launch_fv(k, g, c->phys, mode, U, w.Utr[cur], w.g, w.gtr, Ut, Uio, dU, w.Utr[cur ^ 1], A, B, dt, s));
   }
   return DG_OK;
 }
@@ -924,6 +928,7 @@ dg_status dg_lift(dg_ctx* c, const double* U, double* gout, void* stream) {
   if (st != DG_OK) return st;
   if (!U || !gout) return fail(c, DG_ERR_ARG, "dg_lift: null pointer");
   if (c->cfg.physics != DG_PHYS_NAVIER_STOKES) return fail(c, DG_ERR_ARG, "dg_lift: Navier-Stokes contexts only");
+  if (c->cfg.fv) return fail(c, DG_ERR_UNSUPPORTED, "dg_lift: contexts with FV sub-cells are not covered");
   hipStream_t s = (hipStream_t)stream;
   Work w = kwork(c);
   LAUNCHCHK(c, launch_trace(kcfg(c), kgeo(c), c->phys, U, w.Utr[0], s));

@@ -46,6 +46,19 @@ static void lift_emit(const Cfg& c, int emit, const Geo& g, const Phys& p, const
 
 hipError_t DGX_NAME(launch_lift)(const Cfg& c, int emit, const Geo& g, const Phys& p, const double* U,
                                  const double* Utr, double* gout, double* gtr, hipStream_t s) {
+  if (c.fv) {
+    // FV contexts (FP64, constant viscosity): DG elements, then FV elements'
+    // Green-Gauss gradients; the layer-0 gradients go behind the face fluxes
+    const dim3 grid(g.nElems), block(Shape<kN>::nth);
+    double* gtr2 = gtr + (size_t)8 * g.nSides * Shape<kN>::n2;
+    if (emit != 1) return hipErrorInvalidValue;
+    if (c.nodes == 1)
+      hipLaunchKernelGGL((k_lift<kN, 1, 1, 0, 0, 1>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+    else
+      hipLaunchKernelGGL((k_lift<kN, 0, 1, 0, 0, 1>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+    hipLaunchKernelGGL((k_lift_fv<kN>), grid, block, 0, s, g, p, U, Utr, gout, gtr2);
+    return hipGetLastError();
+  }
   if (c.nodes == 1)
     lift_emit<1>(c, emit, g, p, U, Utr, gout, gtr, s);
   else
@@ -89,26 +102,35 @@ static void vol_phys(const Cfg& c, int mode, const Geo& g, const Phys& p, const 
   }
 }
 
-// DG elements of an FV context (Euler, FP64, Rusanov)
-template <int NODES, int FORM>
-static void vol_fv(int mode, const Geo& g, const Phys& p, const double* U, const double* Utr, double* Ut, double* Uio,
-                   double* dU, double* Utr_next, double A, double B, double dt, hipStream_t s) {
+// DG elements of an FV context (FP64, Rusanov; Navier-Stokes with constant viscosity)
+template <int NODES, int FORM, int PHYS>
+static void vol_fv(int mode, const Geo& g, const Phys& p, const double* U, const double* Utr, const double* gvn,
+                   const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next, double A, double B,
+                   double dt, hipStream_t s) {
   const dim3 grid(g.nElems), block(Shape<kN>::nth);
   if (mode == 0)
-    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, 0, 0, 0, 0, 1>), grid, block, 0, s, g, p, U, Utr, nullptr, nullptr,
+    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, 0, 0, 0, 1>), grid, block, 0, s, g, p, U, Utr, gvn, gvf,
                        Ut, Uio, dU, Utr_next, A, B, dt);
   else
-    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, 0, 0, 1, 0, 1>), grid, block, 0, s, g, p, U, Utr, nullptr, nullptr,
+    hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, 0, 1, 0, 1>), grid, block, 0, s, g, p, U, Utr, gvn, gvf,
                        Ut, Uio, dU, Utr_next, A, B, dt);
+}
+
+template <int PHYS>
+static void vol_fv_form(const Cfg& c, int mode, const Geo& g, const Phys& p, const double* U, const double* Utr,
+                        const double* gvn, const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next,
+                        double A, double B, double dt, hipStream_t s) {
+  if (c.nodes == 0) vol_fv<0, 0, PHYS>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  else if (c.form == 0) vol_fv<1, 0, PHYS>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  else vol_fv<1, 1, PHYS>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
 }
 
 hipError_t DGX_NAME(launch_volume)(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U,
                                    const double* Utr, const double* gvn, const double* gvf, double* Ut, double* Uio,
                                    double* dU, double* Utr_next, double A, double B, double dt, hipStream_t s) {
   if (c.fv) {
-    if (c.nodes == 0) vol_fv<0, 0>(mode, g, p, U, Utr, Ut, Uio, dU, Utr_next, A, B, dt, s);
-    else if (c.form == 0) vol_fv<1, 0>(mode, g, p, U, Utr, Ut, Uio, dU, Utr_next, A, B, dt, s);
-    else vol_fv<1, 1>(mode, g, p, U, Utr, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    if (c.physics == 0) vol_fv_form<0>(c, mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+    else vol_fv_form<1>(c, mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
     return hipGetLastError();
   }
   if (c.nodes == 0 && c.form == 0)
@@ -133,14 +155,23 @@ hipError_t DGX_NAME(launch_trace_fv)(const Cfg& c, const Geo& g, const Phys& p, 
 }
 
 hipError_t DGX_NAME(launch_fv)(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U,
-                               const double* Utr, double* Ut, double* Uio, double* dU, double* Utr_next, double A,
-                               double B, double dt, hipStream_t s) {
-  (void)c;
+                               const double* Utr, const double* gin, const double* gtr, double* Ut, double* Uio,
+                               double* dU, double* Utr_next, double A, double B, double dt, hipStream_t s) {
   const dim3 grid(g.nElems), block(Shape<kN>::nth);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_fv<kN, 0>), grid, block, 0, s, g, p, U, Utr, Ut, Uio, dU, Utr_next, A, B, dt);
-  else
-    hipLaunchKernelGGL((k_fv<kN, 1>), grid, block, 0, s, g, p, U, Utr, Ut, Uio, dU, Utr_next, A, B, dt);
+  if (c.physics == 1) {
+    const double* gtr2 = gtr + (size_t)8 * g.nSides * Shape<kN>::n2;
+    if (mode == 0)
+      hipLaunchKernelGGL((k_fv<kN, 0, 1>), grid, block, 0, s, g, p, U, Utr, gin, gtr2, Ut, Uio, dU, Utr_next, A, B, dt);
+    else
+      hipLaunchKernelGGL((k_fv<kN, 1, 1>), grid, block, 0, s, g, p, U, Utr, gin, gtr2, Ut, Uio, dU, Utr_next, A, B, dt);
+  } else {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_fv<kN, 0, 0>), grid, block, 0, s, g, p, U, Utr, nullptr, nullptr, Ut, Uio, dU, Utr_next, A,
+                         B, dt);
+    else
+      hipLaunchKernelGGL((k_fv<kN, 1, 0>), grid, block, 0, s, g, p, U, Utr, nullptr, nullptr, Ut, Uio, dU, Utr_next, A,
+                         B, dt);
+  }
   return hipGetLastError();
 }
 

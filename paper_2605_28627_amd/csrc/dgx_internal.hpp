@@ -111,9 +111,11 @@ hipError_t launch_adjoint(const Cfg& c, const Geo& g, const Phys& p, const doubl
 // first (0..4) and second (5..9) sub-cell layers under the face.
 hipError_t launch_trace_fv(const Cfg& c, const Geo& g, const Phys& p, const double* U, double* Utr, hipStream_t s);
 // FV elements' residual (mode 0) or RK stage and next traces (mode 1).
+// Navier-Stokes: gin holds the FV elements' sub-cell gradients [12][nElems][n3]
+// and gtr the lifting's face data (the layer-0 gradients behind 8 nSides n2).
 hipError_t launch_fv(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U, const double* Utr,
-                     double* Ut, double* Uio, double* dU, double* Utr_next, double A, double B, double dt,
-                     hipStream_t s);
+                     const double* gin, const double* gtr, double* Ut, double* Uio, double* dU, double* Utr_next,
+                     double A, double B, double dt, hipStream_t s);
 hipError_t launch_fv_indicator(const Cfg& c, const Geo& g, const double* U, double* ind, hipStream_t s);
 // Converts U and dU (may be null) of the elements whose type in etype_new
 // differs from etype, then sets etype = etype_new.

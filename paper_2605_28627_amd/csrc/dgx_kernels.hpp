@@ -160,8 +160,15 @@ __device__ inline double ld_visc(const double* p, size_t i) {
 // with q_tr the state trace of that side.  FT is the flux arithmetic type;
 // with PREC 1 the face fluxes are stored as float (st_visc).  VL is the
 // viscosity law (0 constant, 1 Sutherland) of the fluxes.
+//
+// FV 1 (Navier-Stokes contexts with FV sub-cells): DG elements only.  On a
+// face whose other side is an FV element the face average takes that side's
+// q as the face polynomial whose sub-face means are the q of its
+// reconstructed face states (h^2 (B^-1 x B^-1), h = 2/(N+1)), and instead of
+// the face-normal viscous flux the element writes the layer-0 sub-cell means
+// of its gradient, B3(J g)/V, to gtr + 8 nSides n2 ([slot][12][side][fi]).
 // ---------------------------------------------------------------------------
-template <int N, int NODES, int EMIT, int PREC, int VL>
+template <int N, int NODES, int EMIT, int PREC, int VL, int FV = 0>
 __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const double* __restrict__ U,
                                                         const double* __restrict__ Utr, double* __restrict__ gout,
                                                         double* __restrict__ gtr) {
@@ -170,54 +177,177 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
   constexpr int SZ = (13 * n3 > 7 * S::nface ? 13 * n3 : 7 * S::nface);
   constexpr int SZ2 = (12 * n3 > SZ ? 12 * n3 : SZ);
+  constexpr int TNV = FV ? kTrFV : 5;                  // trace values per face node
   __shared__ double sm[SZ2];
   __shared__ double sf[7 * S::nface];
-  __shared__ VolBasis<N> sb;
+  // FV contexts: per face node the other (FV) side's sub-face q and the own q;
+  // on Gauss nodes the element's state for its own traces
+  __shared__ double sfq[FV ? 8 * S::nface : 1];
+  __shared__ double su[FV && NODES == 0 ? 5 * n3 : 1];
+  __shared__ VolBasis<N, FV != 0> sb;
   const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
+  const int efl = FV ? G.efv[e] : 0;   // bits 0..5: FV faces, bit 6: FV element
+  if (FV && (efl & 64)) return;        // FV elements: k_lift_fv
   const int nE = G.nElems, nS = G.nSides;
-  load_vol_basis<N>(&sb, G.basis, t, S::nth);
+  load_vol_basis<N, FV != 0>(&sb, G.basis, t, S::nth);
   double* sq = sm;            // [4][n3]
   double* sja = sm + 4 * n3;  // [9][n3]
   const bool act = t < n3;
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   double sJ = 0.0;
   Prim q{};
+  // Face averages {q} and outward n s of face node ft into LDS.  On LGL nodes
+  // the element's own trace is its face node's state, so the own side's q is
+  // read from the LDS tile (the same bits its trace would give) and only the
+  // other side's trace comes from memory; on LG nodes both traces are read.
+  // UO holds the other side's trace (LGL) or the master's (LG), UR the slave's (LG).
+  auto face_avg = [&](int ft, int slot, const double UO[5], const double UR[5], const double nsf[4]) {
+    const int f = ft / n2, rr = ft % n2;
+    double qa[4], qb[4];
+    {
+      const Prim a = cons2prim(UO, P.gm1);
+      qa[0] = a.u[0]; qa[1] = a.u[1]; qa[2] = a.u[2]; qa[3] = a.p / (a.rho * P.R);
+    }
+    if constexpr (NODES == 1) {
+      const int pp = rr % n1, qq = rr / n1, r = f / 2;
+      const int tn = line_node<N>(r, (f & 1) ? N : 0, pp, qq);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) qb[c] = sq[c * n3 + tn];
+    } else {
+      const Prim b = cons2prim(UR, P.gm1);
+      qb[0] = b.u[0]; qb[1] = b.u[1]; qb[2] = b.u[2]; qb[3] = b.p / (b.rho * P.R);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sf[(f * 7 + c) * n2 + rr] = 0.5 * (qa[c] + qb[c]);
+    const double sgn = slot ? -1.0 : 1.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sf[(f * 7 + 4 + c) * n2 + rr] = sgn * (nsf[c] * nsf[3]);
+  };
+  auto face_load = [&](int ft, int& slot, double UO[5], double UR[5], double nsf[4]) {
+    const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
+    const int info = G.efc[e * 6 + f];
+    const int side = efc_side(info);
+    slot = efc_slot(info);
+    int p = pp, qm = qq;
+    if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+    const int fi = qm * n1 + p;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      if constexpr (NODES == 1) {
+        UO[v] = Utr[tr_index(1 - slot, v, TNV, nS, side, n2, fi)];
+      } else {
+        UO[v] = Utr[tr_index(0, v, TNV, nS, side, n2, fi)];
+        UR[v] = Utr[tr_index(1, v, TNV, nS, side, n2, fi)];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) nsf[c] = G.face[((size_t)c * nS + side) * n2 + fi];
+  };
+  // Every global load of this phase is issued before the first use: the
+  // node's state, metrics and 1/J, and (when each face node has a work-item
+  // of its own) its face node's traces and geometry.
+  constexpr bool kOneFaceNode = S::nface <= S::nth;
+  double u[5] = {0, 0, 0, 0, 0}, jl[9];
+  double fUL[5], fUR[5], fns[4];
+  int fslot = 0;
   if (act) {
-    double u[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) jl[c] = G.Ja[((size_t)c * nE + e) * n3 + t];
+    sJ = G.sJ[(size_t)e * n3 + t];
+  }
+  if constexpr (kOneFaceNode && !FV) {
+    if (t < S::nface) face_load(t, fslot, fUL, fUR, fns);
+  }
+  if (act) {
+    if constexpr (FV && NODES == 0) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) su[v * n3 + t] = u[v];
+    }
     q = cons2prim(u, P.gm1);
     sq[0 * n3 + t] = q.u[0];
     sq[1 * n3 + t] = q.u[1];
     sq[2 * n3 + t] = q.u[2];
     sq[3 * n3 + t] = q.p / (q.rho * P.R);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) sja[c * n3 + t] = G.Ja[((size_t)c * nE + e) * n3 + t];
-    sJ = G.sJ[(size_t)e * n3 + t];
+    for (int c = 0; c < 9; ++c) sja[c * n3 + t] = jl[c];
   }
-  // face averages {q} and outward n s for this element's faces
-  for (int ft = t; ft < S::nface; ft += S::nth) {
-    const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
-    const int info = G.efc[e * 6 + f];
-    const int side = efc_side(info), slot = efc_slot(info);
-    int p = pp, qm = qq;
-    if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
-    const int fi = qm * n1 + p;
-    double UL[5], UR[5];
+  // LGL: the face averages read the own q tile (FV contexts: and the own state)
+  if constexpr (NODES == 1 || FV) __syncthreads();
+  if constexpr (FV) {
+    // FV faces: the other side's reconstructed face state at each sub-face and
+    // the own trace's q into LDS; DG faces as usual
+    const double h = 2.0 / n1;
+    for (int ft = t; ft < S::nface; ft += S::nth) {
+      const int f = ft / n2, rr = ft % n2;
+      if (!((efl >> f) & 1)) {
+        int slot;
+        double UL[5], UR[5], nsf[4];
+        face_load(ft, slot, UL, UR, nsf);
+        face_avg(ft, slot, UL, UR, nsf);
+        continue;
+      }
+      const int pp = rr % n1, qq = rr / n1, r = f / 2;
+      const int info = G.efc[e * 6 + f];
+      const int side = efc_side(info), slot = efc_slot(info);
+      int p = pp, qm = qq;
+      if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+      const int fi = qm * n1 + p;
+      double Wo[5];   // the other side's reconstructed face state
+      fv_face_state_of(Utr, nS, n2, side, fi, 1 - slot, Wo);
+      sfq[(f * 8 + 0) * n2 + rr] = h * h * Wo[1];
+      sfq[(f * 8 + 1) * n2 + rr] = h * h * Wo[2];
+      sfq[(f * 8 + 2) * n2 + rr] = h * h * Wo[3];
+      sfq[(f * 8 + 3) * n2 + rr] = h * h * (Wo[4] / (Wo[0] * P.R));
+      double qo[4];
+      if constexpr (NODES == 1) {
+        const int tn = line_node<N>(r, (f & 1) ? N : 0, pp, qq);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      UL[v] = Utr[tr_index(0, v, 5, nS, side, n2, fi)];
-      UR[v] = Utr[tr_index(1, v, 5, nS, side, n2, fi)];
+        for (int c = 0; c < 4; ++c) qo[c] = sq[c * n3 + tn];
+      } else {
+        const double* L = (f & 1) ? sb.Lp : sb.Lm;
+        double ut[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          ut[v] = 0.0;
+#pragma unroll
+          for (int a = 0; a < n1; ++a) ut[v] += L[a] * su[v * n3 + line_node<N>(r, a, pp, qq)];
+        }
+        const Prim b = cons2prim(ut, P.gm1);
+        qo[0] = b.u[0]; qo[1] = b.u[1]; qo[2] = b.u[2]; qo[3] = b.p / (b.rho * P.R);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sfq[(f * 8 + 4 + c) * n2 + rr] = qo[c];
+      const double sgn = slot ? -1.0 : 1.0, sA = G.face[((size_t)3 * nS + side) * n2 + fi];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sf[(f * 7 + 4 + c) * n2 + rr] = sgn * (G.face[((size_t)c * nS + side) * n2 + fi] * sA);
     }
-    const Prim a = cons2prim(UL, P.gm1), b = cons2prim(UR, P.gm1);
-    sf[(f * 7 + 0) * n2 + rr] = 0.5 * (a.u[0] + b.u[0]);
-    sf[(f * 7 + 1) * n2 + rr] = 0.5 * (a.u[1] + b.u[1]);
-    sf[(f * 7 + 2) * n2 + rr] = 0.5 * (a.u[2] + b.u[2]);
-    sf[(f * 7 + 3) * n2 + rr] = 0.5 * (a.p / (a.rho * P.R) + b.p / (b.rho * P.R));
-    const double sgn = slot ? -1.0 : 1.0;
-    const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
+    if (efl & 63) {
+      __syncthreads();
+      for (int ft = t; ft < S::nface; ft += S::nth) {
+        const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
+        if (!((efl >> f) & 1)) continue;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) sf[(f * 7 + 4 + c) * n2 + rr] = sgn * (G.face[((size_t)c * nS + side) * n2 + fi] * s);
+        for (int c = 0; c < 4; ++c) {
+          double qf = 0.0;
+          for (int q2 = 0; q2 < n1; ++q2)
+#pragma unroll
+            for (int p2 = 0; p2 < n1; ++p2)
+              qf += sb.Bsi[pp * n1 + p2] * sb.Bsi[qq * n1 + q2] * sfq[(f * 8 + c) * n2 + q2 * n1 + p2];
+          sf[(f * 7 + c) * n2 + rr] = 0.5 * (sfq[(f * 8 + 4 + c) * n2 + rr] + qf);
+        }
+      }
+    }
+  } else if constexpr (kOneFaceNode) {
+    if (t < S::nface) face_avg(t, fslot, fUL, fUR, fns);
+  } else {
+    for (int ft = t; ft < S::nface; ft += S::nth) {
+      int slot;
+      double UL[5], UR[5], nsf[4];
+      face_load(ft, slot, UL, UR, nsf);
+      face_avg(ft, slot, UL, UR, nsf);
+    }
   }
   __syncthreads();
   double acc[12];
@@ -330,6 +460,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
         const int a = idx[r];
         if (a != 0 && a != N) continue;
         const int f = 2 * r + (a == N ? 1 : 0);
+        if (FV && ((efl >> f) & 1)) continue;
         const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
         const int info = G.efc[e * 6 + f];
         const int side = efc_side(info), slot = efc_slot(info);
@@ -351,6 +482,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
     __syncthreads();
     for (int ft = t; ft < S::nface; ft += S::nth) {
       const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
+      if (FV && ((efl >> f) & 1)) continue;
       const double* L = (f & 1) ? sb.Lp : sb.Lm;
       const int info = G.efc[e * 6 + f];
       const int side = efc_side(info), slot = efc_slot(info);
@@ -374,8 +506,54 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
         }
         double ut[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) ut[v] = Utr[tr_index(slot, v, 5, nS, side, n2, qm * n1 + p)];
+        for (int v = 0; v < 5; ++v) ut[v] = Utr[tr_index(slot, v, TNV, nS, side, n2, qm * n1 + p)];
         emit_face(slot, side, qm * n1 + p, cons2prim(ut, P.gm1), gf);
+      }
+    }
+  }
+  if constexpr (FV && EMIT == 1) {
+    // FV faces: layer-0 sub-cell means of the gradient, (B3 (J g))_s / V_s,
+    // by a contraction along the face normal and a tensor product over the face
+    if (efl & 63) {
+      double* sjg = sm;   // [12][n3]: J g
+      __syncthreads();
+      if (act) {
+        const double J = 1.0 / sJ;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) sjg[c * n3 + t] = J * acc[c];
+      }
+      double* gtr2 = gtr + (size_t)8 * nS * n2;
+      for (int f = 0; f < 6; ++f) {
+        if (!((efl >> f) & 1)) continue;
+        const int r = f / 2, an = (f & 1) ? N : 0;
+        __syncthreads();
+        for (int rr = t; rr < n2; rr += S::nth) {
+          const int pp = rr % n1, qq = rr / n1;
+#pragma unroll
+          for (int c = 0; c < 12; ++c) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int l = 0; l < n1; ++l) sacc += sb.Bs[an * n1 + l] * sjg[c * n3 + line_node<N>(r, l, pp, qq)];
+            sf[c * n2 + rr] = sacc;
+          }
+        }
+        __syncthreads();
+        for (int rr = t; rr < n2; rr += S::nth) {
+          const int pp = rr % n1, qq = rr / n1;
+          const int info = G.efc[e * 6 + f];
+          const int side = efc_side(info), slot = efc_slot(info);
+          int p = pp, qm = qq;
+          if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+          const double iv = 1.0 / G.fvV[(size_t)e * n3 + line_node<N>(r, an, pp, qq)];
+#pragma unroll
+          for (int c = 0; c < 12; ++c) {
+            double m = 0.0;
+            for (int q2 = 0; q2 < n1; ++q2)
+#pragma unroll
+              for (int p2 = 0; p2 < n1; ++p2) m += sb.Bs[pp * n1 + p2] * sb.Bs[qq * n1 + q2] * sf[c * n2 + q2 * n1 + p2];
+            gtr2[tr_index(slot, c, 12, nS, side, n2, qm * n1 + p)] = m * iv;
+          }
+        }
       }
     }
   }
@@ -423,10 +601,12 @@ constexpr int volume_waves() {
   return Shape<N>::nth >= 512 ? 4 : ((FORM == 1 && NODES == 0 && N == 3) ? DGX_ES_WAVES : 1);
 }
 
-// FV (Euler contexts with FV sub-cells): DG elements only; faces with an FV
+// FV (contexts with FV sub-cells): DG elements only; faces with an FV
 // element on either side take the sub-face fluxes back as the nodal flux
 // polynomial (B^-1 x B^-1), and the RK epilogue writes two-layer primitive
-// traces there.
+// traces there.  Navier-Stokes: those sub-face fluxes subtract the mean of
+// both layer-0 sub-cells' viscous fluxes, from the gradients at
+// gvf + 8 nSides n2.
 template <int N, int NODES, int FORM, int PHYS, int PREC, int MODE, int ROE, int FV = 0>
 __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) void k_volume(Geo G, Phys P, const double* __restrict__ U,
                                                           const double* __restrict__ Utr,
@@ -480,6 +660,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   double sJn = 0.0, dUn[5] = {0, 0, 0, 0, 0}, Un[5] = {0, 0, 0, 0, 0};
   // Navier-Stokes: the viscous volume term, fetched with the last direction's
   // metric row and added to the accumulator when that direction starts
+  // (Gauss split form: read at the end)
   double vvn[4] = {0, 0, 0, 0};
   auto fetch_end = [&]() {
     sJn = G.sJ[(size_t)e * n3 + t];
@@ -495,7 +676,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   auto fetch_dir = [&](int r) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) jn[c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
-    if constexpr (PHYS == 1) {
+    if constexpr (PHYS == 1 && !ES) {
       if (r == 2) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) vvn[v] = gvn[((size_t)v * nE + e) * n3 + t];
@@ -517,9 +698,12 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
     const int fi = qm * n1 + p;
     if constexpr (FV) {
       if ((efl >> f) & 1) {
-        // FV face: the sub-face flux, outward, into the staging area (taken back below)
-        double F[5];
-        fv_face_flux(Utr, G.fvSb, nS, n2, side, fi, P, F);
+        // FV face: the sub-face flux, outward, into the staging area (taken back below);
+        // Navier-Stokes: less the mean of both layer-0 sub-cells' viscous fluxes
+        double F[5], W0f[5], W1f[5], Sv[3];
+        fv_face_states(Utr, G.fvSb, nS, n2, side, fi, W0f, W1f, Sv);
+        rusanov_prim(W0f, W1f, Sv, P, F);
+        if constexpr (PHYS == 1) fv_face_visc(Utr, gvf + (size_t)8 * nS * n2, nS, n2, side, fi, Sv, P, F);
         const double so = slot ? -1.0 : 1.0;
 #pragma unroll
         for (int v = 0; v < 5; ++v) sm[(f * 5 + v) * n2 + rr] = so * F[v];
@@ -601,7 +785,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     const double jr[3] = {jn[0], jn[1], jn[2]};
-    if constexpr (PHYS == 1) {
+    if constexpr (PHYS == 1 && !ES) {
       if (r == 2 && act) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[1 + v] += vvn[v];
@@ -803,6 +987,11 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
         for (int v = 0; v < 5; ++v)
           acc[v] -= cm * sphi[((2 * r) * 5 + v) * n2 + rr] + cp * sphi[((2 * r + 1) * 5 + v) * n2 + rr];
       }
+    }
+    if constexpr (PHYS == 1 && ES) {
+      // (Gauss split form: read here, where fewer values are live)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[1 + v] += gvn[((size_t)v * nE + e) * n3 + t];
     }
     const double sJ = sJn;
     if constexpr (MODE == 0) {

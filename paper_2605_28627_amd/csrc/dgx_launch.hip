@@ -50,8 +50,9 @@ hipError_t static_scratch(void** ptr) {
   hipError_t launch_adjoint_N##n(const Cfg&, const Geo&, const Phys&, const double*, const double*,          \
                                  const double*, double*, const double*, double*, double*, double*, hipStream_t); \
   hipError_t launch_trace_fv_N##n(const Cfg&, const Geo&, const Phys&, const double*, double*, hipStream_t);   \
-  hipError_t launch_fv_N##n(const Cfg&, const Geo&, const Phys&, int, const double*, const double*, double*,   \
-                            double*, double*, double*, double, double, double, hipStream_t);                   \
+  hipError_t launch_fv_N##n(const Cfg&, const Geo&, const Phys&, int, const double*, const double*,         \
+                            const double*, const double*, double*, double*, double*, double*, double, double,  \
+                            double, hipStream_t);                                                              \
   hipError_t launch_fv_indicator_N##n(const Cfg&, const Geo&, const double*, double*, hipStream_t);           \
   hipError_t launch_fv_switch_N##n(const Cfg&, const Geo&, double*, double*, const int*, int*, hipStream_t);
 DGX_DECL(1)
@@ -88,9 +89,9 @@ hipError_t launch_trace_fv(const Cfg& c, const Geo& g, const Phys& p, const doub
 }
 
 hipError_t launch_fv(const Cfg& c, const Geo& g, const Phys& p, int mode, const double* U, const double* Utr,
-                     double* Ut, double* Uio, double* dU, double* Utr_next, double A, double B, double dt,
-                     hipStream_t s) {
-#define ARGS (c, g, p, mode, U, Utr, Ut, Uio, dU, Utr_next, A, B, dt, s)
+                     const double* gin, const double* gtr, double* Ut, double* Uio, double* dU, double* Utr_next,
+                     double A, double B, double dt, hipStream_t s) {
+#define ARGS (c, g, p, mode, U, Utr, gin, gtr, Ut, Uio, dU, Utr_next, A, B, dt, s)
   DGX_SWITCH(launch_fv)
 #undef ARGS
 }

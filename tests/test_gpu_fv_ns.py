@@ -1,0 +1,215 @@
+"""GPU parity of Navier-Stokes with FV sub-cells against the oracle, through the C-ABI.
+
+The viscous terms of an FV element use Green-Gauss sub-cell gradients of
+(u, v, w, T); a DG element next to an FV face lifts with the FV side's
+reconstructed face states and hands the layer-0 sub-cell means of its
+gradient to the shared sub-face flux, whose viscous part is the mean of both
+layer-0 sub-cells' viscous fluxes.  Checked here:
+
+* the residual with checkerboard, all-FV and random element masks: LG weak
+  form, LGL weak and split forms, N = 1..7, curved and rotated meshes
+  (oracle metrics uploaded): 1e-12 per variable against the oracle;
+* three LSERK4(5) steps with a mask;
+* free-stream preservation (LGL on curved, LG on straight-sided meshes) and
+  discrete conservation of the GPU's own residual (all five variables);
+* the Taylor-Green workload at N=7, 16^3 elements, with a checkerboard of
+  FV elements: sampled elements against the oracle;
+* dg_lift refuses FV contexts; FV contexts refuse Sutherland viscosity.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2605_28627_amd import inputs as I
+from tests.helpers import quad_weights3, rel_err_per_var
+
+pytestmark = pytest.mark.gpu
+PI = np.pi
+MU = 0.05
+
+
+def _say(*a):
+    print("[gpu-fv-ns]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def S(torch_cuda):
+    from paper_2605_28627_amd.solver import DGSolver
+    return DGSolver
+
+
+def _mask(kind, mesh, K, seed=0):
+    if kind == "all":
+        return np.ones(mesh.nElems, np.int32)
+    if kind == "random":
+        return np.random.default_rng(seed).integers(0, 2, mesh.nElems).astype(np.int32)
+    ex = np.arange(mesh.nElems) % K[0]
+    ey = (np.arange(mesh.nElems) // K[0]) % K[1]
+    ez = np.arange(mesh.nElems) // (K[0] * K[1])
+    return ((ex + ey + ez) % 2).astype(np.int32)
+
+
+CASES = [
+    # N, nodes, form, curved, rotate_seed, mask
+    (1, 0, 0, 0.0, 5, "checker"),
+    (2, 1, 1, 0.0, 5, "random"),
+    (3, 0, 0, 0.1, 7, "checker"),
+    (3, 1, 1, 0.1, 7, "random"),
+    (3, 1, 0, 0.0, 3, "all"),
+    (4, 0, 0, 0.1, 9, "random"),
+    (5, 1, 1, 0.1, 11, "checker"),
+    (6, 1, 0, 0.0, 4, "checker"),
+    (7, 1, 1, 0.0, 3, "random"),
+    (7, 0, 0, 0.0, 6, "checker"),
+]
+
+
+def _cfg(N, nodes, form):
+    return dict(N=N, nodes=nodes, form=form, physics=1, mu=MU, fv=1)
+
+
+def _setup(S, orc, case, K=(3, 2, 2)):
+    N, nodes, form, curved, rot, mk = case
+    mesh = I.box_mesh(K, (-PI,) * 3, (PI,) * 3, Ngeo=N if curved else 1, curved_amp=curved, rotate_seed=rot)
+    cfg = _cfg(N, nodes, form)
+    o = orc.Oracle(cfg, mesh)
+    s = S(cfg, mesh)
+    _, J, Ja = o.geometry()
+    s.upload_metrics(Ja, 1.0 / J, o.face_normals())
+    return o, s, mesh, _mask(mk, mesh, K, seed=rot)
+
+
+@pytest.mark.parametrize("case", CASES, ids=str)
+def test_rhs_matches_oracle(S, orc, case):
+    _say("rhs", case)
+    o, s, mesh, mask = _setup(S, orc, case)
+    U = I.smooth_random_state(o.coords(), 71, amp=0.2)
+    Uo, _ = o.fv_switch(U, None, mask)
+    Ug = s.init_state(U)
+    s.fv_switch(Ug, mask)
+    assert np.all(rel_err_per_var(Ug.cpu().numpy(), Uo) < 1e-13)
+    R_orc = o.rhs(Uo)
+    R_gpu = s.rhs(Ug).cpu().numpy()
+    err = rel_err_per_var(R_gpu, R_orc)
+    _say("rhs", case, "rel err", err)
+    assert np.all(err < 1e-12), err
+    assert np.array_equal(R_gpu, s.rhs(Ug).cpu().numpy())
+
+
+@pytest.mark.parametrize("case", [CASES[2], CASES[3], CASES[6]], ids=str)
+def test_rk_steps_match_oracle(S, orc, case):
+    _say("rk", case)
+    o, s, mesh, mask = _setup(S, orc, case)
+    U = I.smooth_random_state(o.coords(), 72, amp=0.2)
+    dt = o.timestep(U, 0.9)
+    Uo, _ = o.fv_switch(U, None, mask)
+    U_orc = o.lserk(Uo, 3, dt)
+    Ug = s.init_state(U)
+    s.fv_switch(Ug, mask)
+    s.rk_step(Ug, s.empty_state(), dt, 3)
+    err = rel_err_per_var(Ug.cpu().numpy() - Uo, U_orc - Uo)
+    _say("rk", case, err)
+    assert np.all(err < 1e-11), err
+
+
+# (Gauss nodes keep a free stream only on straight-sided elements: their
+# metric terms are not exact there on curved ones, with or without FV)
+@pytest.mark.parametrize("N,nodes,form,curved", [(3, 1, 1, 0.1), (5, 1, 0, 0.1), (4, 0, 0, 0.0)], ids=str)
+def test_free_stream_and_conservation(S, orc, N, nodes, form, curved):
+    K = (3, 3, 2)
+    mesh = I.box_mesh(K, (-PI,) * 3, (PI,) * 3, Ngeo=N if curved else 1, curved_amp=curved, rotate_seed=5)
+    cfg = _cfg(N, nodes, form)
+    o, s = orc.Oracle(cfg, mesh), S(cfg, mesh)
+    _, J, Ja = o.geometry()
+    s.upload_metrics(Ja, 1.0 / J, o.face_normals())
+    mask = _mask("checker", mesh, K)
+    xyz = o.coords()
+    Uc = np.zeros(s.state_shape)
+    Uc[:] = I.prim_to_cons(np.ones(1), np.full(1, 0.1), np.full(1, 0.2), np.full(1, -0.1), np.full(1, 71.43), 1.4)[
+        :, 0, None, None, None, None]
+    Ug = s.init_state(Uc)
+    s.fv_switch(Ug, mask)
+    R = s.rhs(Ug).cpu().numpy()
+    fmax = np.abs(orc.flux_adv(Uc[:, 0, 0, 0, 0], np.ones(3))).max()
+    b = orc.basis(N, nodes)
+    Dhat = (b["w"][:, None] / b["w"][None, :]) * b["D"]
+    scale = 3 * fmax * np.abs(Ja).max() * max(np.abs(Dhat).sum(0).max(), N + 1) / J.min()
+    _say("fsp", N, nodes, form, np.abs(R).max() / scale)
+    assert np.abs(R).max() < 1e-13 * scale
+    s.fv_switch(Ug, np.zeros(mesh.nElems, np.int32))
+    Ug = s.init_state(I.smooth_random_state(xyz, 73, amp=0.2))
+    s.fv_switch(Ug, mask)
+    R = s.rhs(Ug).cpu().numpy()
+    V, _, _ = o.fv_geometry()
+    Wt = np.where(mask[:, None, None, None] == 1, V, quad_weights3(b["w"]) * J)
+    for v in range(5):
+        tot = (Wt * R[v]).sum()
+        _say("conservation", v, tot / (Wt * np.abs(R[v])).sum())
+        assert abs(tot) < 1e-13 * (Wt * np.abs(R[v])).sum()
+
+
+def test_tgv_workload_sampled(S, orc, torch_cuda):
+    """Navier-Stokes, N=7 LGL split form, Taylor-Green vortex on 16^3 elements
+    (2.1 M DOF), half the elements FV in a checkerboard: sampled elements
+    (FV and DG, with FV and DG neighbours) against the oracle.
+
+    A DG element beside an FV face takes the sub-face fluxes back through
+    (B^-1 x B^-1), whose entries grow quickly with N; at Mach 0.1 the fluxes
+    are the pressure (71) times the area while the residual is O(1), so the
+    result is ill-conditioned there: one-ulp changes of the input move the
+    oracle's own residual by ~1e-9 (momentum) and ~3e-8 (energy).  The bound
+    is therefore 1e-12 of each variable's largest residual, plus 64 ulps of the
+    flux terms, plus four times that measured one-ulp sensitivity."""
+    name = "ns_split_lgl_n7_16x16x16_tgv"
+    w = I.WORKLOADS[name]
+    K = tuple(w["K"])
+    mesh = I.workload_mesh(name)
+    cfg = _cfg(w["N"], w["nodes"], w["form"])
+    cfg["mu"] = w["mu"]
+    _say("sampled", name)
+    o = orc.Oracle(cfg, mesh)
+    xyz, J, Ja = o.geometry()
+    s = S(cfg, mesh)
+    s.upload_metrics(Ja, 1.0 / J, o.face_normals())
+    U = I.workload_state(name, xyz)
+    Ug = s.init_state(U)
+    mask = _mask("checker", mesh, K)
+    s.fv_switch(Ug, mask)
+    o.fv_set_mask(mask)
+    Um = Ug.cpu().numpy()
+    sample = [0, 1, 15, 16, 255, 256, 2047, 2048, 3000, 4095]
+    R_gpu = s.rhs(Ug).cpu().numpy()[:, sample]
+    R_orc = o.rhs_sample(Um, sample)
+    b = orc.basis(w["N"], w["nodes"])
+    fmax = max(np.abs(orc.flux_adv(Um[:, e].reshape(5, -1)[:, 0], np.ones(3))).max() for e in sample)
+    scale = np.abs(b["DS"]).sum(1).max() * fmax * np.abs(Ja).max() / J.min()
+    rng = np.random.default_rng(0)
+    sens = np.zeros(5)
+    for _ in range(3):
+        Up = Um * (1.0 + rng.choice([-1.0, 0.0, 1.0], Um.shape) * 2.2e-16)
+        sens = np.maximum(sens, np.abs(o.rhs_sample(Up, sample) - R_orc).max(axis=(1, 2, 3, 4)))
+    diff = np.abs(R_gpu - R_orc).max(axis=(1, 2, 3, 4))
+    ref = np.abs(R_orc).max(axis=(1, 2, 3, 4))
+    _say("sampled", "diff", diff, "ref", ref, "flux scale", scale, "one-ulp sensitivity", sens)
+    assert np.all(diff < 1e-12 * ref + 64 * 2.2e-16 * scale + 4 * sens), (diff, ref, scale, sens)
+
+
+def test_refusals(S, orc, torch_cuda):
+    from paper_2605_28627_amd import dgx
+    o, s, mesh, mask = _setup(S, orc, CASES[2])
+    U = s.init_state(I.smooth_random_state(o.coords(), 74, amp=0.2))
+    with pytest.raises(dgx.DGError) as ei:
+        s.lift(U)
+    assert ei.value.status == dgx.DG_ERR_UNSUPPORTED
+    with pytest.raises(dgx.DGError) as ei:
+        S(dict(_cfg(3, 1, 1), viscosity=1, Tref=1.0, Ts=0.4), mesh)
+    assert ei.value.status == dgx.DG_ERR_UNSUPPORTED
