@@ -17,7 +17,7 @@ count, FP64 FLOPs from the committed rocprofv3 counters) and the serial FP64
 oracle timed on a bounded sample of the same workload on the host.
 
 Other workloads (--workload, --K, --state) and repetitions (--reps, median)
-serve the per-configuration measurements; --fv checker/all runs an Euler
+serve the per-configuration measurements; --fv checker/all runs a
 workload with half or all of its elements on FV sub-cells (shock
 capturing; the paper's 50 % FV row uses a checkerboard), --fv zero the same
 FV-capable context with no element switched.
@@ -238,12 +238,16 @@ def fv_kernel_bytes_per_dof(w):
     stages), the interior sub-face vectors (9 N / (N+1) per sub-cell), and
     per element face node the sub-face vector (3) and both sides' two-layer
     traces (2 x 10).  Writes: dU (5), U (5) and the element's own two-layer
-    traces (10 per face node).  8 bytes each.
+    traces (10 per face node).  Navier-Stokes adds the sub-cell gradients
+    (12) and per element face node both sides' layer-0 gradients (2 x 12).
+    8 bytes each.
     """
     n1 = w["N"] + 1
     fpn = 6 * n1 * n1 / n1 ** 3
     reads = 5 + 1 + 4 + 9 * w["N"] / n1 + fpn * (3 + 20)
     writes = 5 + 5 + fpn * 10
+    if w["physics"] == 1:
+        reads += 12 + fpn * 24
     return 8.0 * (reads + writes)
 
 
@@ -284,8 +288,8 @@ def main():
     if args.fv_switch_every_step and args.fv == "none":
         raise SystemExit("--fv-switch-every-step needs --fv")
     if args.fv != "none":
-        if w["physics"] != 0:
-            raise SystemExit("--fv needs an Euler workload (FV sub-cells cover Euler)")
+        if args.viscosity == "sutherland" or args.riemann == "roe":
+            raise SystemExit("--fv: FV contexts use the Rusanov flux and constant viscosity")
         cfg["fv"] = 1
         args.no_fp32 = True      # FV contexts are FP64
         args.no_adjoint = True   # the adjoint does not cover FV sub-cells

@@ -196,7 +196,9 @@ __device__ inline void write_fv_traces(const Geo& G, int e, const double* sw, do
 // Traces of an FV context: DG faces get the DG trace, FV faces the two
 // primitive sub-cell layers (a DG element's from the means of its state).
 // ---------------------------------------------------------------------------
-template <int N, int NODES>
+// EP 1 (split form on Gauss nodes): DG faces take the entropy-projected
+// trace, its ln rho, ln beta at trace_logs(Utr, nS, n2, kTrFV).
+template <int N, int NODES, int EP = 0>
 __global__ __launch_bounds__(Shape<N>::nth) void k_trace_fv(Geo G, Phys P, const double* __restrict__ U,
                                                             double* __restrict__ Utr) {
   using S = Shape<N>;
@@ -253,7 +255,16 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace_fv(Geo G, Phys P, const
     write_fv_traces<N>(G, e, sb2, Utr, et ? 63 : (efl & 63), t, S::nth);
   }
   if (et) return;
-  // DG faces of a DG element: the DG trace
+  // DG faces of a DG element: the DG trace (EP: of the entropy variables, mapped back)
+  if constexpr (EP == 1) {
+    if (act) {
+      double w[5];
+      entropy_vars(cons2prim(u, P.gm1), P.gm1, w);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) snod[v * n3 + t] = w[v];
+    }
+    __syncthreads();   // (efl is uniform: every work-item gets here)
+  }
   for (int ft = t; ft < S::nface; ft += S::nth) {
     const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
     const int info = G.efc[e * 6 + f];
@@ -261,18 +272,29 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_trace_fv(Geo G, Phys P, const
     if ((efl >> f) & 1) continue;
     int p = pp, q = qq;
     if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
+    double acc[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      double acc = 0.0;
+      acc[v] = 0.0;
       if constexpr (NODES == 1) {
-        acc = snod[v * n3 + line_node<N>(r, (f & 1) ? N : 0, pp, qq)];
+        acc[v] = snod[v * n3 + line_node<N>(r, (f & 1) ? N : 0, pp, qq)];
       } else {
         const double* L = (f & 1) ? sbb.Lp : sbb.Lm;
 #pragma unroll
-        for (int a = 0; a < n1; ++a) acc += L[a] * snod[v * n3 + line_node<N>(r, a, pp, qq)];
+        for (int a = 0; a < n1; ++a) acc[v] += L[a] * snod[v * n3 + line_node<N>(r, a, pp, qq)];
       }
-      Utr[tr_index(slot, v, kTrFV, nS, side, n2, q * n1 + p)] = acc;
     }
+    if constexpr (EP == 1) {
+      double w[5], lg[2];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) w[v] = acc[v];
+      entropy_to_cons(w, P.gm1, acc, lg);
+      double* Ltr = trace_logs(Utr, nS, n2, kTrFV);
+      Ltr[tr_index(slot, 0, 2, nS, side, n2, q * n1 + p)] = lg[0];
+      Ltr[tr_index(slot, 1, 2, nS, side, n2, q * n1 + p)] = lg[1];
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Utr[tr_index(slot, v, kTrFV, nS, side, n2, q * n1 + p)] = acc[v];
   }
 }
 

@@ -361,11 +361,9 @@ dg_status dg_create(const dg_config* cfg, dg_ctx** out) {
   if (c.N < 1 || c.N > kMaxN) return fail(nullptr, DG_ERR_UNSUPPORTED, "dg_create: N must be in 1..7");
   if (c.fv != 0 && c.fv != 1) return fail(nullptr, DG_ERR_ARG, "dg_create: fv");
   if (c.fv && (c.precision != DG_PREC_FP64 || c.riemann != DG_RIEMANN_RUSANOV ||
-               (c.volume_form == DG_FORM_SPLIT && c.nodes == DG_NODES_GAUSS) ||
                (c.physics == DG_PHYS_NAVIER_STOKES && c.viscosity != DG_VISC_CONSTANT)))
     return fail(nullptr, DG_ERR_UNSUPPORTED,
-                "dg_create: FV sub-cells cover FP64, Rusanov, the weak form and the Lobatto split form "
-                "(Navier-Stokes: constant viscosity)");
+                "dg_create: FV sub-cells cover FP64 and Rusanov (Navier-Stokes: constant viscosity)");
   dg_ctx* x = new (std::nothrow) dg_ctx();
   if (!x) return fail(nullptr, DG_ERR_NOMEM, "dg_create: host allocation");
   x->cfg = c;
@@ -789,9 +787,10 @@ static WsLayout ws_layout(const dg_ctx* c) {
   size_t off = 0;
   // U traces [2 slots][5][nf]; the split form on Gauss nodes appends the
   // traces' ln rho, ln beta [2 slots][2][nf]
-  // (FV contexts: 10 values per face node, the DG trace or two primitive sub-cell layers)
+  // (FV contexts: 10 values per face node, the DG trace or two primitive
+  // sub-cell layers, then the logs of the split form on Gauss nodes)
   const bool es = c->cfg.volume_form == DG_FORM_SPLIT && c->cfg.nodes == DG_NODES_GAUSS;
-  const int tv = c->cfg.fv ? 10 : (es ? 7 : 5);
+  const int tv = (c->cfg.fv ? 10 : 5) + (es ? 2 : 0);
   for (int b = 0; b < 2; ++b) { L.utr[b] = off; off += align256(2 * (size_t)tv * nf * sizeof(double)); }
   const bool ns = c->cfg.physics == DG_PHYS_NAVIER_STOKES;
   // lifted face data [2 slots][12][nf]; FV contexts: the face-normal viscous

@@ -54,8 +54,10 @@ hipError_t DGX_NAME(launch_lift)(const Cfg& c, int emit, const Geo& g, const Phy
     if (emit != 1) return hipErrorInvalidValue;
     if (c.nodes == 1)
       hipLaunchKernelGGL((k_lift<kN, 1, 1, 0, 0, 1>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
-    else
+    else if (c.form == 0)
       hipLaunchKernelGGL((k_lift<kN, 0, 1, 0, 0, 1>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+    else
+      hipLaunchKernelGGL((k_lift<kN, 0, 1, 0, 0, 2>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
     hipLaunchKernelGGL((k_lift_fv<kN>), grid, block, 0, s, g, p, U, Utr, gout, gtr2);
     return hipGetLastError();
   }
@@ -102,7 +104,8 @@ static void vol_phys(const Cfg& c, int mode, const Geo& g, const Phys& p, const 
   }
 }
 
-// DG elements of an FV context (FP64, Rusanov; Navier-Stokes with constant viscosity)
+// DG elements of an FV context (FP64, Rusanov; Navier-Stokes with constant
+// viscosity; the split form on Gauss nodes is the entropy-stable hybridised form)
 template <int NODES, int FORM, int PHYS>
 static void vol_fv(int mode, const Geo& g, const Phys& p, const double* U, const double* Utr, const double* gvn,
                    const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next, double A, double B,
@@ -120,7 +123,8 @@ template <int PHYS>
 static void vol_fv_form(const Cfg& c, int mode, const Geo& g, const Phys& p, const double* U, const double* Utr,
                         const double* gvn, const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next,
                         double A, double B, double dt, hipStream_t s) {
-  if (c.nodes == 0) vol_fv<0, 0, PHYS>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  if (c.nodes == 0 && c.form == 0) vol_fv<0, 0, PHYS>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
+  else if (c.nodes == 0) vol_fv<0, 1, PHYS>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   else if (c.form == 0) vol_fv<1, 0, PHYS>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
   else vol_fv<1, 1, PHYS>(mode, g, p, U, Utr, gvn, gvf, Ut, Uio, dU, Utr_next, A, B, dt, s);
 }
@@ -149,8 +153,10 @@ hipError_t DGX_NAME(launch_trace_fv)(const Cfg& c, const Geo& g, const Phys& p, 
   const dim3 grid(g.nElems), block(Shape<kN>::nth);
   if (c.nodes == 1)
     hipLaunchKernelGGL((k_trace_fv<kN, 1>), grid, block, 0, s, g, p, U, Utr);
-  else
+  else if (c.form == 0)
     hipLaunchKernelGGL((k_trace_fv<kN, 0>), grid, block, 0, s, g, p, U, Utr);
+  else
+    hipLaunchKernelGGL((k_trace_fv<kN, 0, 1>), grid, block, 0, s, g, p, U, Utr);
   return hipGetLastError();
 }
 

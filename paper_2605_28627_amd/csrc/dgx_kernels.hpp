@@ -49,12 +49,8 @@ __device__ __forceinline__ void load_vol_basis(VolBasis<N, FVB>* dst, const DevB
 // Trace kernel: U at the element faces -> Utr[slot][5][side][master (p,q)].
 // EP 1 (split form on Gauss nodes): the entropy-projected trace u(E v(U)),
 // the entropy variables interpolated to the face and mapped back; its
-// ln rho and ln beta (by-products of the map) follow the five variables in
-// the same buffer: Utr + 10 nSides n2, layout [slot][2][side][(p,q)].
-__device__ __forceinline__ double* trace_logs(double* Utr, int nS, int n2) { return Utr + (size_t)10 * nS * n2; }
-__device__ __forceinline__ const double* trace_logs(const double* Utr, int nS, int n2) {
-  return Utr + (size_t)10 * nS * n2;
-}
+// ln rho and ln beta (by-products of the map) follow the trace values in
+// the same buffer (trace_logs).
 // ---------------------------------------------------------------------------
 template <int N, int NODES, int EP>
 __global__ __launch_bounds__(Shape<N>::nth) void k_trace(Geo G, Phys P, const double* __restrict__ U,
@@ -161,7 +157,9 @@ __device__ inline double ld_visc(const double* p, size_t i) {
 // with PREC 1 the face fluxes are stored as float (st_visc).  VL is the
 // viscosity law (0 constant, 1 Sutherland) of the fluxes.
 //
-// FV 1 (Navier-Stokes contexts with FV sub-cells): DG elements only.  On a
+// FV 1 (Navier-Stokes contexts with FV sub-cells; FV 2 for the split form on
+// Gauss nodes, whose own face value is then the entropy-projected trace
+// u(E v(U))): DG elements only.  On a
 // face whose other side is an FV element the face average takes that side's
 // q as the face polynomial whose sub-face means are the q of its
 // reconstructed face states (h^2 (B^-1 x B^-1), h = 2/(N+1)), and instead of
@@ -261,9 +259,14 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
     if (t < S::nface) face_load(t, fslot, fUL, fUR, fns);
   }
   if (act) {
-    if constexpr (FV && NODES == 0) {
+    if constexpr (FV == 1 && NODES == 0) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) su[v * n3 + t] = u[v];
+    } else if constexpr (FV == 2) {
+      double w[5];
+      entropy_vars(cons2prim(u, P.gm1), P.gm1, w);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) su[v * n3 + t] = w[v];
     }
     q = cons2prim(u, P.gm1);
     sq[0 * n3 + t] = q.u[0];
@@ -313,6 +316,12 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
           ut[v] = 0.0;
 #pragma unroll
           for (int a = 0; a < n1; ++a) ut[v] += L[a] * su[v * n3 + line_node<N>(r, a, pp, qq)];
+        }
+        if constexpr (FV == 2) {
+          double w[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) w[v] = ut[v];
+          entropy_to_cons(w, P.gm1, ut);
         }
         const Prim b = cons2prim(ut, P.gm1);
         qo[0] = b.u[0]; qo[1] = b.u[1]; qo[2] = b.u[2]; qo[3] = b.p / (b.rho * P.R);
@@ -637,7 +646,8 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   // Surface fluxes (outward, own face-local order): all six faces at once, or
   // (Gauss split form) the two faces of each direction within its pass,
   // together with the two-point records of the own projected face states.
-  constexpr int kFaces = ES ? kEsFaceSlots : 6;
+  // (FV contexts of the Gauss split form keep all six slots)
+  constexpr int kFaces = ES && !FV ? kEsFaceSlots : 6;
   __shared__ double sphi[5 * kFaces * n2];
   __shared__ double sm[SZ];
   __shared__ double saf[ES ? 8 * kFaces * n2 : 1];
@@ -723,7 +733,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
     Aux own;
     if constexpr (ES) {
       // the projected traces carry their ln rho, ln beta
-      const double* Ltr = trace_logs(Utr, nS, n2);
+      const double* Ltr = trace_logs(Utr, nS, n2, TNV);
       const double lg[4] = {Ltr[tr_index(0, 0, 2, nS, side, n2, fi)], Ltr[tr_index(0, 1, 2, nS, side, n2, fi)],
                             Ltr[tr_index(1, 0, 2, nS, side, n2, fi)], Ltr[tr_index(1, 1, 2, nS, side, n2, fi)]};
       surface_flux_adv<FT, FORM, ROE>(UL, UR, nh, s, P, Phi, &own, slot, lg);
@@ -749,6 +759,42 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   // 1. surface fluxes of the six faces (other forms)
   if constexpr (!ES) {
     for (int ft = t; ft < S::nface; ft += S::nth) face_node(ft / n2, ft % n2, ft / n2);
+  }
+  if constexpr (ES && FV) {
+    if (efl & 63) {
+      // FV faces of the Gauss split form: the traces there hold sub-cell
+      // means, so the element forms the two-point records of its own
+      // entropy-projected face states u(E v(U)) for the face coupling here
+      // (the same arithmetic as its traces on DG faces), then the sub-face fluxes.
+      if (act) {
+        double w[5];
+        entropy_vars(cons2prim(u, P.gm1), P.gm1, w);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm[v * n3 + t] = w[v];
+      }
+      __syncthreads();
+      for (int ft = t; ft < S::nface; ft += S::nth) {
+        const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
+        if (!((efl >> f) & 1)) continue;
+        const double* L = (f & 1) ? sb.Lp : sb.Lm;
+        double w[5], uf[5], lg[2];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          w[v] = 0.0;
+#pragma unroll
+          for (int a = 0; a < n1; ++a) w[v] += L[a] * sm[v * n3 + line_node<N>(r, a, pp, qq)];
+        }
+        entropy_to_cons(w, P.gm1, uf, lg);
+        const Prim qf = cons2prim(uf, P.gm1);
+        const Aux own = P.twopoint == 0 ? make_aux_logs(qf, lg[0], lg[1]) : make_aux(qf);
+        double* d = saf + f * 8 * n2 + rr;
+        d[0] = own.rho; d[n2] = own.u[0]; d[2 * n2] = own.u[1]; d[3 * n2] = own.u[2];
+        d[4 * n2] = own.beta; d[5 * n2] = own.lrho; d[6 * n2] = own.lbeta; d[7 * n2] = own.k;
+      }
+      __syncthreads();
+      for (int ft = t; ft < S::nface; ft += S::nth)
+        if ((efl >> (ft / n2)) & 1) face_node(ft / n2, ft % n2, ft / n2);
+    }
   }
   if constexpr (FV) {
     // FV faces: nodal flux polynomial with the sub-face integrals, Phi = (B^-1 x B^-1) F
@@ -796,7 +842,10 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
       if constexpr (ES) {
         // the faces whose flux is formed in this pass: 0..3 in the first, 4, 5 in the last
         constexpr int fa[3] = {0, 6, 4}, fb[3] = {4, 6, 6};
-        for (int ft = fa[r] * n2 + t; ft < fb[r] * n2; ft += S::nth) face_node(ft / n2, ft % n2, es_face_slot(ft / n2));
+        for (int ft = fa[r] * n2 + t; ft < fb[r] * n2; ft += S::nth) {
+          if (FV && ((efl >> (ft / n2)) & 1)) continue;   // formed in step 1
+          face_node(ft / n2, ft % n2, FV ? ft / n2 : es_face_slot(ft / n2));
+        }
       }
       if (act) {
 #pragma unroll
@@ -882,7 +931,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           for (int f = 0; f < 2; ++f) {
             const double* L = f ? sb.Lp : sb.Lm;
             const double cs = sb.winv[a] * L[a];
-            const int fsl = es_face_slot(2 * r + f);
+            const int fsl = FV ? 2 * r + f : es_face_slot(2 * r + f);
 #pragma unroll
             for (int v = 0; v < 5; ++v) acc[v] -= cs * sphi[(fsl * 5 + v) * n2 + rr];
             double jf[3] = {0.0, 0.0, 0.0};
@@ -1061,7 +1110,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
 #pragma unroll
           for (int v = 0; v < 5; ++v) w[v] = s[v];
           entropy_to_cons(w, P.gm1, s, lg);
-          double* Ltr = trace_logs(Utr_next, nS, n2);
+          double* Ltr = trace_logs(Utr_next, nS, n2, TNV);
           Ltr[tr_index(slot, 0, 2, nS, side, n2, qm * n1 + p)] = lg[0];
           Ltr[tr_index(slot, 1, 2, nS, side, n2, qm * n1 + p)] = lg[1];
         }

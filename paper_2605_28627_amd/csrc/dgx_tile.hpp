@@ -63,4 +63,14 @@ __device__ __forceinline__ size_t tr_index(int slot, int v, int nvar, int nSides
   return (((size_t)slot * nvar + v) * nSides + side) * n2 + fi;
 }
 
+// Entropy-projected traces (split form on Gauss nodes): their ln rho and
+// ln beta sit behind the trace values, at Utr + 2 tnv nSides n2 (tnv values
+// per face node: 5, or 10 in FV contexts), layout [slot][2][side][(p,q)].
+__device__ __forceinline__ double* trace_logs(double* Utr, int nS, int n2, int tnv = 5) {
+  return Utr + (size_t)2 * tnv * nS * n2;
+}
+__device__ __forceinline__ const double* trace_logs(const double* Utr, int nS, int n2, int tnv = 5) {
+  return Utr + (size_t)2 * tnv * nS * n2;
+}
+
 }  // namespace dgx

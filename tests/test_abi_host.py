@@ -56,13 +56,13 @@ def test_create_validates_config(dgx):
     # the split form runs on both node sets (entropy-stable hybridised form on Gauss nodes)
     for nodes in (0, 1):
         dgx.dg_destroy(dgx.dg_create(dgx.make_config(3, nodes=nodes, volume_form=1)))
-    # FV sub-cells: FP64, Rusanov, weak form or the Lobatto split form; Euler or
-    # Navier-Stokes with constant viscosity
-    for kw in [dict(nodes=0), dict(nodes=1), dict(nodes=1, volume_form=1), dict(physics=1, mu=0.01),
-               dict(physics=1, mu=0.01, nodes=1, volume_form=1)]:
+    # FV sub-cells: FP64, Rusanov, any DG form; Euler or Navier-Stokes with
+    # constant viscosity
+    for kw in [dict(nodes=0), dict(nodes=1), dict(nodes=1, volume_form=1), dict(nodes=0, volume_form=1),
+               dict(physics=1, mu=0.01), dict(physics=1, mu=0.01, nodes=1, volume_form=1),
+               dict(physics=1, mu=0.01, nodes=0, volume_form=1)]:
         dgx.dg_destroy(dgx.dg_create(dgx.make_config(3, fv=1, **kw)))
-    for kw in [dict(precision=1), dict(riemann=2), dict(nodes=0, volume_form=1),
-               dict(physics=1, mu=0.01, viscosity=1, Tref=1.0, Ts=0.4)]:
+    for kw in [dict(precision=1), dict(riemann=2), dict(physics=1, mu=0.01, viscosity=1, Tref=1.0, Ts=0.4)]:
         with pytest.raises(dgx.DGError) as ei:
             dgx.dg_create(dgx.make_config(3, fv=1, **kw))
         assert ei.value.status == dgx.DG_ERR_UNSUPPORTED, kw

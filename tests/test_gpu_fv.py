@@ -2,8 +2,9 @@
 Persson indicator, switching) against the oracle, through the C-ABI.
 
 * DG -> FV switching of a seeded state, then the residual with checkerboard,
-  all-FV and random element masks: LG and LGL, weak and split DG, N = 1..7,
-  curved and rotated meshes (oracle metrics uploaded): 1e-12 per variable;
+  all-FV and random element masks: LG and LGL, weak and split DG (on Gauss
+  nodes the entropy-stable hybridised form), N = 1..7, curved and rotated
+  meshes (oracle metrics uploaded): 1e-12 per variable;
 * three LSERK4(5) steps with a mask (the RK epilogues write the two-layer
   traces of FV faces);
 * the indicator where it is above rounding level, the indicator-driven
@@ -65,6 +66,10 @@ CASES = [
     (5, 1, 1, 0.1, 11, "checker"),
     (6, 1, 0, 0.0, 4, "checker"),
     (7, 1, 1, 0.0, 3, "random"),
+    # the entropy-stable split form on Gauss nodes beside FV elements
+    (3, 0, 1, 0.0, 7, "checker"),
+    (2, 0, 1, 0.1, 5, "random"),
+    (5, 0, 1, 0.0, 9, "random"),
 ]
 
 
@@ -99,11 +104,14 @@ def test_switch_and_rhs_match_oracle(S, orc, case):
     assert np.array_equal(R_gpu, s.rhs(Ug).cpu().numpy())
 
 
-@pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[5]], ids=str)
+@pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[5], CASES[8]], ids=str)
 def test_rk_steps_match_oracle(S, orc, case):
     _say("rk", case)
     o, s, mesh, mask = _setup(S, orc, case)
-    U = I.smooth_random_state(o.coords(), 62, amp=0.2)
+    # (the Gauss split form's entropy-projected traces of this under-resolved
+    # state at amplitude 0.2 lose positivity within a step, FV or not: 0.1 there)
+    amp = 0.1 if case[1] == 0 and case[2] == 1 else 0.2
+    U = I.smooth_random_state(o.coords(), 62, amp=amp)
     dt = o.timestep(U, 0.9)
     Uo, _ = o.fv_switch(U, None, mask)
     U_orc = o.lserk(Uo, 3, dt)

@@ -7,13 +7,15 @@ gradient to the shared sub-face flux, whose viscous part is the mean of both
 layer-0 sub-cells' viscous fluxes.  Checked here:
 
 * the residual with checkerboard, all-FV and random element masks: LG weak
-  form, LGL weak and split forms, N = 1..7, curved and rotated meshes
-  (oracle metrics uploaded): 1e-12 per variable against the oracle;
+  form, LGL weak and split forms, and the entropy-stable split form on Gauss
+  nodes, N = 1..7, curved and rotated meshes (oracle metrics uploaded):
+  1e-12 per variable against the oracle;
 * three LSERK4(5) steps with a mask;
 * free-stream preservation (LGL on curved, LG on straight-sided meshes) and
   discrete conservation of the GPU's own residual (all five variables);
-* the Taylor-Green workload at N=7, 16^3 elements, with a checkerboard of
-  FV elements: sampled elements against the oracle;
+* the Taylor-Green workload at N=7, 16^3 elements, and the 64^3 N=3 Gauss
+  split-form workload (random state), each with a checkerboard of FV
+  elements: sampled elements against the oracle;
 * dg_lift refuses FV contexts; FV contexts refuse Sutherland viscosity.
 """
 import sys
@@ -70,6 +72,11 @@ CASES = [
     (6, 1, 0, 0.0, 4, "checker"),
     (7, 1, 1, 0.0, 3, "random"),
     (7, 0, 0, 0.0, 6, "checker"),
+    # the entropy-stable split form on Gauss nodes beside FV elements
+    (3, 0, 1, 0.0, 7, "checker"),
+    (3, 0, 1, 0.1, 5, "random"),
+    (2, 0, 1, 0.0, 4, "all"),
+    (6, 0, 1, 0.0, 11, "random"),
 ]
 
 
@@ -105,7 +112,7 @@ def test_rhs_matches_oracle(S, orc, case):
     assert np.array_equal(R_gpu, s.rhs(Ug).cpu().numpy())
 
 
-@pytest.mark.parametrize("case", [CASES[2], CASES[3], CASES[6]], ids=str)
+@pytest.mark.parametrize("case", [CASES[2], CASES[3], CASES[6], CASES[10]], ids=str)
 def test_rk_steps_match_oracle(S, orc, case):
     _say("rk", case)
     o, s, mesh, mask = _setup(S, orc, case)
@@ -123,7 +130,8 @@ def test_rk_steps_match_oracle(S, orc, case):
 
 # (Gauss nodes keep a free stream only on straight-sided elements: their
 # metric terms are not exact there on curved ones, with or without FV)
-@pytest.mark.parametrize("N,nodes,form,curved", [(3, 1, 1, 0.1), (5, 1, 0, 0.1), (4, 0, 0, 0.0)], ids=str)
+@pytest.mark.parametrize("N,nodes,form,curved", [(3, 1, 1, 0.1), (5, 1, 0, 0.1), (4, 0, 0, 0.0), (3, 0, 1, 0.0)],
+                         ids=str)
 def test_free_stream_and_conservation(S, orc, N, nodes, form, curved):
     K = (3, 3, 2)
     mesh = I.box_mesh(K, (-PI,) * 3, (PI,) * 3, Ngeo=N if curved else 1, curved_amp=curved, rotate_seed=5)
@@ -200,6 +208,48 @@ def test_tgv_workload_sampled(S, orc, torch_cuda):
     diff = np.abs(R_gpu - R_orc).max(axis=(1, 2, 3, 4))
     ref = np.abs(R_orc).max(axis=(1, 2, 3, 4))
     _say("sampled", "diff", diff, "ref", ref, "flux scale", scale, "one-ulp sensitivity", sens)
+    assert np.all(diff < 1e-12 * ref + 64 * 2.2e-16 * scale + 4 * sens), (diff, ref, scale, sens)
+
+
+def test_gauss_split_workload_full_size_sampled(S, orc, torch_cuda):
+    """Navier-Stokes, N=3 entropy-stable split form on Gauss nodes, 64^3
+    elements (16.78 M DOF), a checkerboard of FV elements and a random state:
+    sampled elements against the oracle, with the bound of the Taylor-Green
+    test (1e-12 of the largest residual, 64 ulps of the flux terms, four
+    times the oracle's measured one-ulp sensitivity)."""
+    name = "ns_split_lg_n3_64x64x64_freestream"
+    w = I.WORKLOADS[name]
+    K = tuple(w["K"])
+    mesh = I.workload_mesh(name)
+    cfg = _cfg(w["N"], w["nodes"], w["form"])
+    cfg["mu"] = w["mu"]
+    _say("full size", name)
+    o = orc.Oracle(cfg, mesh)
+    xyz, J, Ja = o.geometry()
+    s = S(cfg, mesh)
+    s.upload_metrics(Ja, 1.0 / J, o.face_normals())
+    U = I.random_state(xyz.shape[1:], 75, rho=(0.9, 1.1), vel=0.2, p=(0.9, 1.1))
+    Ug = s.init_state(U)
+    del U
+    mask = _mask("checker", mesh, K)
+    s.fv_switch(Ug, mask)
+    o.fv_set_mask(mask)
+    Um = Ug.cpu().numpy()
+    sample = [0, 1, 63, 64, 4095, 4096, 130000, 262143]
+    R_gpu = s.rhs(Ug).cpu().numpy()[:, sample]
+    R_orc = o.rhs_sample(Um, sample)
+    b = orc.basis(w["N"], w["nodes"])
+    fmax = max(np.abs(orc.flux_adv(Um[:, e].reshape(5, -1)[:, 0], np.ones(3))).max() for e in sample)
+    scale = np.abs(b["DS"]).sum(1).max() * fmax * np.abs(Ja).max() / J.min()
+    rng = np.random.default_rng(1)
+    sens = np.zeros(5)
+    for _ in range(2):
+        Up = Um * (1.0 + rng.choice([-1.0, 0.0, 1.0], Um.shape) * 2.2e-16)
+        sens = np.maximum(sens, np.abs(o.rhs_sample(Up, sample) - R_orc).max(axis=(1, 2, 3, 4)))
+        del Up
+    diff = np.abs(R_gpu - R_orc).max(axis=(1, 2, 3, 4))
+    ref = np.abs(R_orc).max(axis=(1, 2, 3, 4))
+    _say("full size", "diff", diff, "ref", ref, "flux scale", scale, "one-ulp sensitivity", sens)
     assert np.all(diff < 1e-12 * ref + 64 * 2.2e-16 * scale + 4 * sens), (diff, ref, scale, sens)
 
 
