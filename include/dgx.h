@@ -102,8 +102,9 @@ typedef struct {
 
 /* Validates cfg and creates a context (host memory only; no device work).
  * DG_ERR_ARG for bad enums or gamma <= 1, mu < 0, Pr <= 0, R <= 0;
- * DG_ERR_UNSUPPORTED for N outside the built range, or fv = 1 with Navier-Stokes,
- * FP32 flux arithmetic, Roe's flux or the split form on Gauss nodes. */
+ * DG_ERR_UNSUPPORTED for N outside the built range, or fv = 1 with FP32 flux
+ * arithmetic, Roe's flux or Sutherland's law (FV sub-cells: Rusanov, FP64,
+ * constant viscosity; any DG form, Euler or Navier-Stokes). */
 dg_status dg_create(const dg_config* cfg, dg_ctx** out);
 
 /* Frees all library-owned host and device memory of ctx (NULL is a no-op). */
@@ -216,10 +217,13 @@ dg_status dg_rk_step_noalloc(dg_ctx* ctx, double* U, double* dU, double t, doubl
 /* out = (dR/dU)^T lam at the state U (device arrays, state length; out must
  * not alias U or lam).  This is the transpose of the discrete residual's
  * Jacobian (not in the paper: a discrete adjoint of its residual); at the
- * kinks of the Rusanov flux (|u.n|, max of the two wave speeds) and of the
- * log-mean branch switch the branch taken by the forward evaluation is
- * differentiated, ties going to the master side.  FP64 contexts only; needs
- * a workspace of dg_workspace_bytes_adjoint bytes. */
+ * kinks of the Rusanov flux (|u.n|, max of the two wave speeds), of Roe's
+ * flux (|.| of the wave speeds, the Harten-Hyman fix) and of the log-mean
+ * branch switch the branch taken by the forward evaluation is
+ * differentiated, ties going to the master side.  Covers Rusanov and Roe,
+ * constant viscosity and Sutherland's law; DG_ERR_UNSUPPORTED for FP32 flux
+ * arithmetic, the split form on Gauss nodes and FV sub-cells.  Needs a
+ * workspace of dg_workspace_bytes_adjoint bytes. */
 dg_status dg_adjoint_rhs(dg_ctx* ctx, const double* U, const double* lam, double* out, void* stream);
 
 /* Reverse of one step of size dt of the context's RK scheme (S stages) from

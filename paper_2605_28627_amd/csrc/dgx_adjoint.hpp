@@ -10,7 +10,9 @@
 //             Jacobian of F#(U_m, U_l) in its first argument (F# is symmetric);
 //   lifting (Navier-Stokes): the gradient adjoint gb from the viscous terms
 //             flows back through g = lift(U) (k_adj_lift_trace/_volume).
-// The Rusanov kinks are differentiated on the branch the forward takes.
+// The kinks (Rusanov's max, Roe's |.| and Harten-Hyman fix) are
+// differentiated on the branch the forward takes; Sutherland's law adds the
+// temperature dependence of mu and lambda.
 #pragma once
 
 #include "dgx_kernels.hpp"
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_trace(Geo G, const double
 #ifndef DGX_ADJ_WAVES
 #define DGX_ADJ_WAVES 1
 #endif
-template <int N, int NODES, int FORM, int PHYS>
+template <int N, int NODES, int FORM, int PHYS, int ROE = 0, int VL = 0>
 __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVES : 1)) void k_adj_volume(
     Geo G, Phys P, const double* __restrict__ U, const double* __restrict__ lam, const double* __restrict__ Utr,
     const double* __restrict__ Lbar, const double* __restrict__ gin, const double* __restrict__ gtr,
@@ -129,14 +131,13 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
                           G.face[((size_t)2 * nS + side) * n2 + fi]};
     const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
     double ULb[5], URb[5], gLb[12], gRb[12];
-    surface_flux_vjp<FORM, PHYS>(UL, UR, gL, gR, nh, s, P, Phib, ULb, URb, gLb, gRb);
-    const double* mine = slot ? URb : ULb;
+    surface_flux_vjp<FORM, PHYS, ROE, VL>(UL, UR, gL, gR, nh, s, P, Phib, ULb, URb, gLb, gRb);
+    // (element-wise selects keep both sides' adjoints in registers)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) sB[(f * NF + v) * n2 + rr] = mine[v];
+    for (int v = 0; v < 5; ++v) sB[(f * NF + v) * n2 + rr] = slot ? URb[v] : ULb[v];
     if constexpr (PHYS == 1) {
-      const double* gm = slot ? gRb : gLb;
 #pragma unroll
-      for (int c = 0; c < 12; ++c) sB[(f * NF + 5 + c) * n2 + rr] = gm[c];
+      for (int c = 0; c < 12; ++c) sB[(f * NF + 5 + c) * n2 + rr] = slot ? gRb[c] : gLb[c];
     }
   }
   __syncthreads();
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
 #pragma unroll
       for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
       const Prim q = cons2prim(u, P.gm1);
-      double ub[3] = {0, 0, 0};
+      double ub[3] = {0, 0, 0}, rpb[2] = {0.0, 0.0};
       double gl[PHYS == 1 ? 12 : 1];
       if constexpr (PHYS == 1) {
 #pragma unroll
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
         if constexpr (PHYS == 1) {
           const double Gnb[4] = {-Lam[1], -Lam[2], -Lam[3], -Lam[4]};
           double gq[12], uq[3];
-          viscous_flux_vjp(q, gl, P, nv, Gnb, gq, uq);
+          viscous_flux_vjp<VL>(q, gl, P, nv, Gnb, gq, uq, rpb);
 #pragma unroll
           for (int c = 0; c < 12; ++c) gb[c] += gq[c];
           ub[0] += uq[0]; ub[1] += uq[1]; ub[2] += uq[2];
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
 #pragma unroll
         for (int c = 0; c < 12; ++c) gbar[((size_t)c * nE + e) * n3 + t] = gb[c];
         double Uu[5];
-        prim_vjp(q, P.gm1, 0.0, ub, 0.0, Uu);
+        prim_vjp(q, P.gm1, rpb[0], ub, rpb[1], Uu);
 #pragma unroll
         for (int v = 0; v < 5; ++v) Ub[v] += Uu[v];
       }

@@ -997,8 +997,6 @@ static dg_status ready_adjoint(dg_ctx* c, const char* who) {
   dg_status st = ready(c, who);
   if (st != DG_OK) return st;
   if (c->cfg.precision != DG_PREC_FP64) return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": FP64 contexts only");
-  if (c->cfg.riemann == DG_RIEMANN_ROE || c->cfg.viscosity == DG_VISC_SUTHERLAND)
-    return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": the adjoint covers the Rusanov flux and constant viscosity");
   if (c->cfg.volume_form == DG_FORM_SPLIT && c->cfg.nodes == DG_NODES_GAUSS)
     return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": the adjoint covers the split form on Lobatto nodes only");
   if (c->cfg.fv) return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": the adjoint does not cover FV sub-cells");

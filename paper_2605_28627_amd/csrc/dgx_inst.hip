@@ -204,8 +204,20 @@ hipError_t DGX_NAME(launch_adjoint)(const Cfg& c, const Geo& g, const Phys& p, c
   else
     hipLaunchKernelGGL((k_adj_trace<kN, 0>), grid, block, 0, s, g, lam, Lbar);
   // volume + surface adjoint
-#define DGX_ADJ(NODES, FORM, PHYS) \
-  hipLaunchKernelGGL((k_adj_volume<kN, NODES, FORM, PHYS>), grid, block, 0, s, g, p, U, lam, Utr, Lbar, gin, gtr, out, gbar)
+#define DGX_ADJ_V(NODES, FORM, PHYS, ROE, VL)                                                                  \
+  hipLaunchKernelGGL((k_adj_volume<kN, NODES, FORM, PHYS, ROE, VL>), grid, block, 0, s, g, p, U, lam, Utr, Lbar, gin, \
+                     gtr, out, gbar)
+  // (Sutherland's law only matters with viscous terms)
+#define DGX_ADJ(NODES, FORM, PHYS)                                       \
+  do {                                                                   \
+    if (c.roe) {                                                         \
+      if (PHYS == 1 && c.visc) DGX_ADJ_V(NODES, FORM, PHYS, 1, PHYS);     \
+      else DGX_ADJ_V(NODES, FORM, PHYS, 1, 0);                           \
+    } else {                                                             \
+      if (PHYS == 1 && c.visc) DGX_ADJ_V(NODES, FORM, PHYS, 0, PHYS);     \
+      else DGX_ADJ_V(NODES, FORM, PHYS, 0, 0);                           \
+    }                                                                    \
+  } while (0)
   if (c.nodes == 0) {
     if (c.physics == 0) DGX_ADJ(0, 0, 0); else DGX_ADJ(0, 0, 1);
   } else if (c.form == 0) {
@@ -214,6 +226,7 @@ hipError_t DGX_NAME(launch_adjoint)(const Cfg& c, const Geo& g, const Phys& p, c
     if (c.physics == 0) DGX_ADJ(1, 1, 0); else DGX_ADJ(1, 1, 1);
   }
 #undef DGX_ADJ
+#undef DGX_ADJ_V
   if (c.physics == 1) {
     // lifting adjoint; gtr has been consumed and now holds Qbar
     if (c.nodes == 1) {

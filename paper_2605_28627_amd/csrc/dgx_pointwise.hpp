@@ -272,12 +272,78 @@ __host__ __device__ inline void viscous_flux(const Prim& q, const double g[12], 
 // entropy and the two shear waves, with the Harten & Hyman (1983) entropy fix
 // on the acoustic speeds: delta = max(0, l~ - l(UL), l(UR) - l~), and where
 // |l~| < delta the speed (l~^2 + delta^2) / (2 delta).  FT arithmetic.
+// Dual numbers (value, derivative along one direction) for the adjoint of
+// Roe's dissipation: its Jacobian is taken column by column in forward mode,
+// through the same roe_core as the residual (kinks on the forward's branch).
+struct Dual {
+  double v, d;
+  __host__ __device__ Dual() : v(0.0), d(0.0) {}
+  __host__ __device__ explicit Dual(double x, double dx = 0.0) : v(x), d(dx) {}
+  // (found by argument-dependent lookup only, so that double arithmetic
+  // elsewhere in this namespace keeps ::sqrt and ::fabs)
+  friend __host__ __device__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+  friend __host__ __device__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+  friend __host__ __device__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+  friend __host__ __device__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+  friend __host__ __device__ Dual operator/(Dual a, Dual b) {
+    const double q = a.v / b.v;
+    return Dual(q, (a.d - q * b.d) / b.v);
+  }
+  friend __host__ __device__ Dual sqrt(Dual a) {
+    const double r = ::sqrt(a.v);
+    return Dual(r, 0.5 * a.d / r);
+  }
+  friend __host__ __device__ Dual fabs(Dual a) { return a.v < 0.0 ? -a : a; }
+  friend __host__ __device__ bool operator<(Dual a, Dual b) { return a.v < b.v; }
+  friend __host__ __device__ bool operator>(Dual a, Dual b) { return a.v > b.v; }
+};
+
 template <typename FT>
 __host__ __device__ inline FT hh_speed(FT lm, FT lL, FT lR) {
   const FT a = fabs(lm);
   FT delta = lm - lL > lR - lm ? lm - lL : lR - lm;
   delta = delta > FT(0) ? delta : FT(0);
   return a < delta ? (lm * lm + delta * delta) / (FT(2) * delta) : a;
+}
+// The dissipation itself on primitive inputs in T arithmetic: T = FT for the
+// residual, or the dual numbers of its adjoint (Dual below); EL, ER the total
+// energies.
+template <typename T>
+__host__ __device__ inline void roe_core(const T& EL, const T& ER, const T& rl, const T& rr, const T ul[3],
+                                         const T ur[3], const T& pl, const T& pr, const T n[3], const T& gam, T D[5]) {
+  const T sl = sqrt(rl), sr = sqrt(rr);
+  const T iw = T(1) / (sl + sr);
+  const T HL = (EL + pl) / rl, HR = (ER + pr) / rr;
+  T um[3], du[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    um[d] = (sl * ul[d] + sr * ur[d]) * iw;
+    du[d] = ur[d] - ul[d];
+  }
+  const T Hm = (sl * HL + sr * HR) * iw;
+  const T q2 = um[0] * um[0] + um[1] * um[1] + um[2] * um[2];
+  const T c2 = (gam - T(1)) * (Hm - T(0.5) * q2);
+  const T cm = sqrt(c2), ic2 = T(1) / c2;
+  const T rm = sl * sr;
+  const T unm = um[0] * n[0] + um[1] * n[1] + um[2] * n[2];
+  const T dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+  const T dp = pr - pl;
+  const T a1 = T(0.5) * (dp - rm * cm * dun) * ic2;
+  const T a5 = T(0.5) * (dp + rm * cm * dun) * ic2;
+  const T a2 = (rr - rl) - dp * ic2;
+  const T cl = sqrt(gam * pl / rl), cr = sqrt(gam * pr / rr);
+  const T unl = ul[0] * n[0] + ul[1] * n[1] + ul[2] * n[2];
+  const T unr = ur[0] * n[0] + ur[1] * n[1] + ur[2] * n[2];
+  const T w1 = hh_speed<T>(unm - cm, unl - cl, unr - cr) * a1;
+  const T w5 = hh_speed<T>(unm + cm, unl + cl, unr + cr) * a5;
+  const T l2 = fabs(unm);
+  const T w2 = l2 * a2, wsh = l2 * rm;
+  const T udu = um[0] * du[0] + um[1] * du[1] + um[2] * du[2];
+  D[0] = w1 + w2 + w5;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    D[1 + d] = w1 * (um[d] - cm * n[d]) + w2 * um[d] + wsh * (du[d] - dun * n[d]) + w5 * (um[d] + cm * n[d]);
+  D[4] = w1 * (Hm - unm * cm) + w2 * T(0.5) * q2 + wsh * (udu - unm * dun) + w5 * (Hm + unm * cm);
 }
 template <typename FT>
 __host__ __device__ inline void roe_dissipation(const double UL[5], const double UR[5], const Prim& qL, const Prim& qR,
@@ -286,39 +352,10 @@ __host__ __device__ inline void roe_dissipation(const double UL[5], const double
   const FT n[3] = {FT(nh[0]), FT(nh[1]), FT(nh[2])};
   const FT rl = FT(qL.rho), rr = FT(qR.rho), pl = FT(qL.p), pr = FT(qR.p);
   const FT ul[3] = {FT(qL.u[0]), FT(qL.u[1]), FT(qL.u[2])}, ur[3] = {FT(qR.u[0]), FT(qR.u[1]), FT(qR.u[2])};
-  const FT sl = sqrt(rl), sr = sqrt(rr);
-  const FT iw = FT(1) / (sl + sr);
-  const FT HL = (FT(UL[4]) + pl) / rl, HR = (FT(UR[4]) + pr) / rr;
-  FT um[3], du[3];
+  FT Df[5];
+  roe_core<FT>(FT(UL[4]), FT(UR[4]), rl, rr, ul, ur, pl, pr, n, gam, Df);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    um[d] = (sl * ul[d] + sr * ur[d]) * iw;
-    du[d] = ur[d] - ul[d];
-  }
-  const FT Hm = (sl * HL + sr * HR) * iw;
-  const FT q2 = um[0] * um[0] + um[1] * um[1] + um[2] * um[2];
-  const FT c2 = (gam - FT(1)) * (Hm - FT(0.5) * q2);
-  const FT cm = sqrt(c2), ic2 = FT(1) / c2;
-  const FT rm = sl * sr;
-  const FT unm = um[0] * n[0] + um[1] * n[1] + um[2] * n[2];
-  const FT dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
-  const FT dp = pr - pl;
-  const FT a1 = FT(0.5) * (dp - rm * cm * dun) * ic2;
-  const FT a5 = FT(0.5) * (dp + rm * cm * dun) * ic2;
-  const FT a2 = (rr - rl) - dp * ic2;
-  const FT cl = sqrt(gam * pl / rl), cr = sqrt(gam * pr / rr);
-  const FT unl = ul[0] * n[0] + ul[1] * n[1] + ul[2] * n[2];
-  const FT unr = ur[0] * n[0] + ur[1] * n[1] + ur[2] * n[2];
-  const FT w1 = hh_speed<FT>(unm - cm, unl - cl, unr - cr) * a1;
-  const FT w5 = hh_speed<FT>(unm + cm, unl + cl, unr + cr) * a5;
-  const FT l2 = fabs(unm);
-  const FT w2 = l2 * a2, wsh = l2 * rm;
-  const FT udu = um[0] * du[0] + um[1] * du[1] + um[2] * du[2];
-  D[0] = double(w1 + w2 + w5);
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-    D[1 + d] = double(w1 * (um[d] - cm * n[d]) + w2 * um[d] + wsh * (du[d] - dun * n[d]) + w5 * (um[d] + cm * n[d]));
-  D[4] = double(w1 * (Hm - unm * cm) + w2 * FT(0.5) * q2 + wsh * (udu - unm * dun) + w5 * (Hm + unm * cm));
+  for (int v = 0; v < 5; ++v) D[v] = double(Df[v]);
 }
 
 // Advective part of the outward (master) surface flux at one face node:
@@ -403,6 +440,40 @@ __host__ __device__ inline void prim_vjp(const Prim& q, double gm1, double rb, c
   Ub[2] = ub[1] * ri - gm1 * pb * q.u[1];
   Ub[3] = ub[2] * ri - gm1 * pb * q.u[2];
   Ub[0] = rb - (ub[0] * q.u[0] + ub[1] * q.u[1] + ub[2] * q.u[2]) * ri + 0.5 * gm1 * pb * k;
+}
+
+// Adjoint of Roe's dissipation D(UL, UR) on the unit normal nh: ULb, URb +=
+// (dD/dU)^T Db, one forward-mode column per entry of UL and UR (primitives by
+// the operations of cons2prim).
+__host__ __device__ inline void roe_dissipation_vjp(const double UL[5], const double UR[5], const double nh[3],
+                                                    const Phys& P, const double Db[5], double ULb[5], double URb[5]) {
+  const Dual gam(P.gamma);
+  const Dual n[3] = {Dual(nh[0]), Dual(nh[1]), Dual(nh[2])};
+#pragma unroll 1
+  for (int k = 0; k < 10; ++k) {
+    Dual uL[5], uR[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      uL[v] = Dual(UL[v], k == v ? 1.0 : 0.0);
+      uR[v] = Dual(UR[v], k == 5 + v ? 1.0 : 0.0);
+    }
+    const Dual riL = Dual(1.0) / uL[0], riR = Dual(1.0) / uR[0];
+    const Dual ul[3] = {uL[1] * riL, uL[2] * riL, uL[3] * riL}, ur[3] = {uR[1] * riR, uR[2] * riR, uR[3] * riR};
+    const Dual gm1(P.gm1);
+    const Dual pl = gm1 * (uL[4] - Dual(0.5) * uL[0] * (ul[0] * ul[0] + ul[1] * ul[1] + ul[2] * ul[2]));
+    const Dual pr = gm1 * (uR[4] - Dual(0.5) * uR[0] * (ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]));
+    Dual D[5];
+    roe_core<Dual>(uL[4], uR[4], uL[0], uR[0], ul, ur, pl, pr, n, gam, D);
+    double sdot = 0.0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sdot += Db[v] * D[v].d;
+    // (selects, not a run-time index, keep ULb and URb in registers)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      ULb[v] += k == v ? sdot : 0.0;
+      URb[v] += k == 5 + v ? sdot : 0.0;
+    }
+  }
 }
 
 // Adjoint of the lifted variables q = (u, v, w, T = p/(rho R)).
@@ -608,10 +679,16 @@ __host__ __device__ inline void euler_flux_vjp(const double U[5], const Prim& q,
 }
 
 // Adjoint of the contracted viscous flux Gn[v] = sum_d n_d G_d[1+v]:
-// gb[12] receives d(Gnb . Gn)/dg, ub[3] the velocity part (energy equation).
+// gb[12] receives d(Gnb . Gn)/dg, ub[3] the velocity part (energy equation),
+// and with Sutherland's law (VL 1) rpb[0], rpb[1] += the density and
+// pressure parts through mu(T), lambda(T), T = p/(rho R).
+template <int VL = 0>
 __host__ __device__ inline void viscous_flux_vjp(const Prim& q, const double g[12], const Phys& P, const double n[3],
-                                                 const double Gnb[4], double gb[12], double ub[3]) {
-  const double mu = P.mu, lam = P.lam;
+                                                 const double Gnb[4], double gb[12], double ub[3],
+                                                 double rpb[2] = nullptr) {
+  constexpr bool suth = VL == 1;
+  const double mu = suth ? visc_mu<double>(q, P) : P.mu;
+  const double lam = suth ? mu * P.kappa : P.lam;
   const double divu = g[0] + g[4] + g[8];
   double tau[3][3];
   for (int a = 0; a < 3; ++a)
@@ -637,10 +714,28 @@ __host__ __device__ inline void viscous_flux_vjp(const Prim& q, const double g[1
       gb[3 * d + a] += mu * taub[a][d];
     }
   gb[0] += divb; gb[4] += divb; gb[8] += divb;
+  if (suth && mu != 0.0) {
+    // d(Gnb . Gn)/d mu: Gn is linear in mu and lambda = kappa mu
+    double dmu = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) dmu += taub[a][d] * tau[a][d];
+    dmu /= mu;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dmu += P.kappa * n[d] * Gnb[3] * g[9 + d];
+    // mu = mu0 th^(3/2) (1 + Ts) / (th + Ts), th = p Rinv / (rho Tref)
+    const double th = q.p * P.Rinv / (q.rho * P.Tref);
+    const double thb = dmu * mu * (1.5 / th - 1.0 / (th + P.Ts));
+    rpb[1] += thb * P.Rinv / (q.rho * P.Tref);
+    rpb[0] -= thb * th / q.rho;
+  }
 }
 
 // Adjoint of the surface flux (FP64): ULb, URb, and for Navier-Stokes gLb, gRb.
-template <int FORM, int PHYS>
+// ROE 1: Roe's dissipation; VL 1: Sutherland's law (compile-time choices,
+// as in the residual).
+template <int FORM, int PHYS, int ROE = 0, int VL = 0>
 __host__ __device__ inline void surface_flux_vjp(const double UL[5], const double UR[5], const double* gL,
                                                  const double* gR, const double nh[3], double s, const Phys& P,
                                                  const double Phib[5], double ULb[5], double URb[5], double* gLb,
@@ -659,8 +754,14 @@ __host__ __device__ inline void surface_flux_vjp(const double UL[5], const doubl
     aux_vjp(qL, aL, bL, P.gm1, ULb);
     aux_vjp(qR, aR, bR, P.gm1, URb);
   }
+  // Roe's dissipation: Phi -= (s/2) D(UL, UR)
+  if constexpr (ROE == 1) {
+    const double Db[5] = {-0.5 * s * Phib[0], -0.5 * s * Phib[1], -0.5 * s * Phib[2], -0.5 * s * Phib[3],
+                          -0.5 * s * Phib[4]};
+    roe_dissipation_vjp(UL, UR, nh, P, Db, ULb, URb);
+  }
   // Rusanov dissipation
-  if (P.riemann == 0) {
+  if (ROE == 0 && P.riemann == 0) {
     const double cL = sqrt(P.gamma * qL.p / qL.rho), cR = sqrt(P.gamma * qR.p / qR.rho);
     const double unL = qL.u[0] * nh[0] + qL.u[1] * nh[1] + qL.u[2] * nh[2];
     const double unR = qR.u[0] * nh[0] + qR.u[1] * nh[1] + qR.u[2] * nh[2];
@@ -689,13 +790,13 @@ __host__ __device__ inline void surface_flux_vjp(const double UL[5], const doubl
   }
   if constexpr (PHYS == 1) {
     const double Gnb[4] = {-0.5 * Phib[1], -0.5 * Phib[2], -0.5 * Phib[3], -0.5 * Phib[4]};
-    double ubL[3], ubR[3];
-    viscous_flux_vjp(qL, gL, P, nv, Gnb, gLb, ubL);
-    viscous_flux_vjp(qR, gR, P, nv, Gnb, gRb, ubR);
+    double ubL[3], ubR[3], rpL[2] = {0.0, 0.0}, rpR[2] = {0.0, 0.0};
+    viscous_flux_vjp<VL>(qL, gL, P, nv, Gnb, gLb, ubL, rpL);
+    viscous_flux_vjp<VL>(qR, gR, P, nv, Gnb, gRb, ubR, rpR);
     double Ub[5];
-    prim_vjp(qL, P.gm1, 0.0, ubL, 0.0, Ub);
+    prim_vjp(qL, P.gm1, rpL[0], ubL, rpL[1], Ub);
     for (int v = 0; v < 5; ++v) ULb[v] += Ub[v];
-    prim_vjp(qR, P.gm1, 0.0, ubR, 0.0, Ub);
+    prim_vjp(qR, P.gm1, rpR[0], ubR, rpR[1], Ub);
     for (int v = 0; v < 5; ++v) URb[v] += Ub[v];
   }
 }

@@ -4,6 +4,8 @@
   tangent, for every discretisation variant; on a tiny mesh the whole
   transposed Jacobian is assembled column by column from oracle tangents and
   compared entry by entry;
+* Roe's flux (Harten-Hyman fix) and Sutherland's law: the adjoint against
+  the oracle's reverse sweep entry by entry, and a full transpose;
 * one reverse LSERK4(5) step against the oracle's trajectory tangent;
 * gradients of the final-time kinetic energy through torch.autograd
   (checkpointed recomputation) against the oracle's tangent of the whole
@@ -140,21 +142,52 @@ def test_adjoint_rk14_step(S, orc, case):
     assert err < 1e-12
 
 
-@pytest.mark.parametrize("extra", [dict(riemann=2), dict(viscosity=1, Tref=1.0, Ts=0.4)], ids=str)
-def test_adjoint_refuses_roe_and_sutherland(S, orc, extra):
-    """The adjoint covers the Rusanov flux and constant viscosity; other
-    contexts get DG_ERR_UNSUPPORTED, not a wrong gradient."""
-    import torch
-    from paper_2605_28627_amd import dgx
-    o, s = _pair(S, orc, CASES[1], **extra)
-    U = s.to_device(I.smooth_random_state(o.coords(), 61, amp=0.2))
-    lam = torch.ones_like(U)
-    with pytest.raises(dgx.DGError) as ei:
-        s.adjoint_rhs(U, lam)
-    assert ei.value.status == dgx.DG_ERR_UNSUPPORTED
-    with pytest.raises(dgx.DGError) as ei:
-        s.adjoint_rk_step(U, lam.clone(), torch.empty_like(lam), 1e-3)
-    assert ei.value.status == dgx.DG_ERR_UNSUPPORTED
+ROE_SUTH = [
+    # case, extra configuration
+    ((3, 0, 0, 0, 0.0, 7), dict(riemann=2)),
+    ((4, 1, 1, 1, 0.1, 9), dict(riemann=2)),
+    ((3, 1, 1, 1, 0.1, 5), dict(viscosity=1, Tref=1.0, Ts=0.4)),
+    ((3, 0, 0, 1, 0.0, 7), dict(riemann=2, viscosity=1, Tref=1.0, Ts=0.4)),
+]
+
+
+@pytest.mark.parametrize("case,extra", ROE_SUTH, ids=str)
+def test_adjoint_roe_and_sutherland_match_oracle(S, orc, case, extra):
+    """Roe's flux with the Harten-Hyman fix and Sutherland's law: the GPU
+    adjoint against the oracle's own reverse sweep (rhs_vjp) entry by entry,
+    and the dot product against its dual-number tangent.  The seeded state
+    keeps every face off the kinks (|u.n| > 0, distinct wave speeds)."""
+    o, s = _pair(S, orc, case, **extra)
+    U = I.smooth_random_state(o.coords(), 61, amp=0.2)
+    rng = np.random.default_rng(62)
+    lam = rng.normal(size=U.shape)
+    out = s.adjoint_rhs(s.to_device(U), s.to_device(lam)).cpu().numpy()
+    ref = o.rhs_vjp(U, lam)
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    d = rng.normal(size=U.shape)
+    _, jd = o.rhs_jvp(U, d)
+    dot = abs((out * d).sum() - (lam * jd).sum()) / np.abs(lam * jd).sum()
+    _say(case, extra, "vs oracle reverse sweep", err, "dot product", dot)
+    assert err < 1e-12 and dot < 1e-12
+
+
+def test_adjoint_roe_full_transpose(S, orc):
+    """Roe's flux on a two-element mesh at N=1: the whole transposed Jacobian
+    from oracle tangents, entry by entry."""
+    o, s = _pair(S, orc, (1, 0, 0, 0, 0.0, 4), K=(2, 1, 1), riemann=2)
+    U = I.smooth_random_state(o.coords(), 63, amp=0.2)
+    n = U.size
+    Jm = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        Jm[:, c] = o.rhs_jvp(U, e.reshape(U.shape))[1].ravel()
+    lam = np.random.default_rng(64).normal(size=U.shape)
+    ref = Jm.T @ lam.ravel()
+    out = s.adjoint_rhs(s.to_device(U), s.to_device(lam)).cpu().numpy().ravel()
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    _say("roe full transpose rel err", err)
+    assert err < 1e-12
 
 
 @pytest.mark.parametrize("case", [(3, 1, 1, 0, 0.0, None), (3, 1, 1, 1, 0.1, 2)], ids=str)
