@@ -65,6 +65,8 @@ def parse():
                          "and S/Tref = 110.4/273.15 (air)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--fp32-reference", default="workload", choices=["workload", "none"],
+                    help="reference state of the FP32-flux arithmetic: the workload's background, or none")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--fv-switch-every-step", action="store_true",
                     help="with --fv: one dg_rk_step call per step, each followed by the indicator and the "
@@ -450,6 +452,9 @@ def main():
     if not args.no_fp32:
         cfg32 = dict(cfg, precision=1)
         s32 = DGSolver(cfg32, mesh, dev)
+        ref32 = I.workload_reference(args.workload, state=args.state) if args.fp32_reference == "workload" else (0, 0)
+        s32.set_reference_state(*ref32)
+        result["fp32_reference_state"] = {"rho0": ref32[0], "p0": ref32[1]}
         final32 = []
         times32, prof32 = timed(s32, profile=True, keep=final32)
         t32 = statistics.median(times32)

@@ -110,6 +110,15 @@ dg_status dg_create(const dg_config* cfg, dg_ctx** out);
 /* Frees all library-owned host and device memory of ctx (NULL is a no-op). */
 dg_status dg_destroy(dg_ctx* ctx);
 
+/* Reference state (rho0 > 0, p0 > 0) of the FP32-flux mode (paper: "Mixed
+ * Precision"): its flux arithmetic rounds the deviations of p_hat, 1/beta^ln,
+ * p and the total enthalpy from this state in float and adds the state's own
+ * part in double, which keeps the float rounding small where p is large and
+ * nearly constant (low Mach numbers).  It changes rounding only; FP64
+ * contexts ignore it.  (0, 0) clears it (the default).  DG_ERR_ARG for other
+ * non-positive values. */
+dg_status dg_set_reference_state(dg_ctx* ctx, double rho0, double p0);
+
 /* Message of the last failing call on ctx, or of the calling thread when ctx is NULL. */
 const char* dg_last_error(const dg_ctx* ctx);
 

@@ -19,6 +19,19 @@
 
 namespace dgx {
 
+// Final value a of (dR/dU)^T lam at index gi: stored in out, or (up.lamU
+// set) the reverse LSERK update of the stage applied in place.  lam is
+// up.lamdU then; each index is read and written by its own work-item only.
+__device__ __forceinline__ void adj_store(const AdjUpd& up, double* out, size_t gi, double a) {
+  if (up.lamU) {
+    const double lu = up.lamU[gi] + up.dt * a;
+    up.lamU[gi] = lu;
+    up.lamdU[gi] = up.A * up.lamdU[gi] + up.Bnext * lu;
+  } else {
+    out[gi] = a;
+  }
+}
+
 // Per-element surface adjoint t = -(1/w_a) l_a(+-1) (sJ lam)_a summed along the normal line.
 template <int N, int NODES>
 __global__ __launch_bounds__(Shape<N>::nth) void k_adj_trace(Geo G, const double* __restrict__ lam,
@@ -80,9 +93,9 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_trace(Geo G, const double
 #endif
 template <int N, int NODES, int FORM, int PHYS, int ROE = 0, int VL = 0>
 __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVES : 1)) void k_adj_volume(
-    Geo G, Phys P, const double* __restrict__ U, const double* __restrict__ lam, const double* __restrict__ Utr,
+    Geo G, Phys P, const double* __restrict__ U, const double* lam, const double* __restrict__ Utr,
     const double* __restrict__ Lbar, const double* __restrict__ gin, const double* __restrict__ gtr,
-    double* __restrict__ out, double* __restrict__ gbar) {
+    double* __restrict__ out, double* __restrict__ gbar, AdjUpd up) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
   constexpr int NF = PHYS == 1 ? 17 : 5;                           // face adjoint values per face node
@@ -334,7 +347,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
   }
   if (act) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) out[((size_t)v * nE + e) * n3 + t] = Ub[v];
+    for (int v = 0; v < 5; ++v) adj_store(up, out, ((size_t)v * nE + e) * n3 + t, Ub[v]);
   }
 }
 
@@ -394,7 +407,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_volume(Geo G, Phys P
                                                                    const double* __restrict__ Utr,
                                                                    const double* __restrict__ gbar,
                                                                    const double* __restrict__ Qbar,
-                                                                   double* __restrict__ out) {
+                                                                   double* __restrict__ out, AdjUpd up) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
   constexpr int SZ = 12 * n3 > 5 * S::nface ? 12 * n3 : 5 * S::nface;
@@ -483,7 +496,10 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_volume(Geo G, Phys P
       }
     }
 #pragma unroll
-    for (int v = 0; v < 5; ++v) out[((size_t)v * nE + e) * n3 + t] += Ub[v];
+    for (int v = 0; v < 5; ++v) {
+      const size_t gi = ((size_t)v * nE + e) * n3 + t;
+      adj_store(up, out, gi, out[gi] + Ub[v]);
+    }
   }
 }
 

@@ -427,6 +427,20 @@ dg_status dg_destroy(dg_ctx* ctx) {
   return DG_OK;
 }
 
+dg_status dg_set_reference_state(dg_ctx* c, double rho0, double p0) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "dg_set_reference_state: null context");
+  if (rho0 == 0.0 && p0 == 0.0) {
+    c->phys.p0 = c->phys.ib0 = c->phys.h0 = 0.0;
+    return DG_OK;
+  }
+  if (!(rho0 > 0.0) || !(p0 > 0.0) || !std::isfinite(rho0) || !std::isfinite(p0))
+    return fail(c, DG_ERR_ARG, "dg_set_reference_state: need rho0 > 0 and p0 > 0 (or both 0)");
+  c->phys.p0 = p0;
+  c->phys.ib0 = 2.0 * p0 / rho0;
+  c->phys.h0 = c->cfg.gamma * p0 / (c->cfg.gamma - 1.0);
+  return DG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Mesh and metrics
 // ---------------------------------------------------------------------------
@@ -1006,7 +1020,8 @@ static dg_status ready_adjoint(dg_ctx* c, const char* who) {
 }
 
 // out = (dR/dU(U))^T lam, with the forward traces (and gradients) of U recomputed.
-static dg_status adjoint_residual(dg_ctx* c, const double* U, const double* lam, double* out, hipStream_t s) {
+static dg_status adjoint_residual(dg_ctx* c, const double* U, const double* lam, double* out, hipStream_t s,
+                                  const AdjUpd& up = AdjUpd{nullptr, nullptr, 0.0, 0.0, 0.0}) {
   Cfg k = kcfg(c);
   Geo g = kgeo(c);
   Work w = kwork(c);
@@ -1021,7 +1036,7 @@ static dg_status adjoint_residual(dg_ctx* c, const double* U, const double* lam,
     LAUNCHCHK(c, launch_lift(k, 0, g, c->phys, U, w.Utr[0], w.g, w.gtr, s));
   }
   ProfScope ps(c, FAM_ADJOINT, s);
-  LAUNCHCHK(c, launch_adjoint(k, g, c->phys, U, lam, w.Utr[0], w.Utr[1], w.g, w.gtr, out, gbar, s));
+  LAUNCHCHK(c, launch_adjoint(k, g, c->phys, U, lam, w.Utr[0], w.Utr[1], w.g, w.gtr, out, gbar, up, s));
   return DG_OK;
 }
 
@@ -1072,11 +1087,11 @@ dg_status dg_adjoint_rk_step(dg_ctx* c, const double* Un, double* lamU, double* 
     ProfScope ps(c, FAM_OTHER, s);
     LAUNCHCHK(c, launch_scale_copy(n, lamU, lamdU, B[ns - 1], s));
   }
+  // (the update is fused into the stage's last adjoint kernel)
   for (int k = ns - 1; k >= 0; --k) {
-    st = adjoint_residual(c, Y[k], lamdU, aout, s);
+    const AdjUpd up{lamU, lamdU, dt, A[k], k > 0 ? B[k - 1] : 0.0};
+    st = adjoint_residual(c, Y[k], lamdU, aout, s, up);
     if (st != DG_OK) return st;
-    ProfScope ps(c, FAM_OTHER, s);
-    LAUNCHCHK(c, launch_adj_rk_update(n, aout, lamU, lamdU, dt, A[k], k > 0 ? B[k - 1] : 0.0, s));
   }
   return DG_OK;
 }

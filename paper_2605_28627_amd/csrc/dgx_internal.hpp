@@ -50,6 +50,10 @@ struct Phys {
   int riemann;                          // 0 Rusanov, 1 central part only, 2 Roe (Harten-Hyman fix)
   int twopoint;                         // 0 Chandrashekar, 1 flux average
   int visc_law;                         // 0 constant mu, 1 Sutherland
+  // reference state of the FP32-flux mode (its fluxes round deviations from
+  // it): pressure, 1/beta = 2 p0/rho0, total enthalpy gamma p0/(gamma-1);
+  // all 0 = none
+  double p0, ib0, h0;
 };
 
 // Everything a kernel needs about the discretisation.
@@ -101,11 +105,22 @@ hipError_t launch_volume(const Cfg& c, const Geo& g, const Phys& p, int mode, co
                          const double* gvn, const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next,
                          double A, double B, double dt, hipStream_t s);
 
-// out = (dR/dU)^T lam; Utr holds the traces of U, Lbar/gtr/gbar are scratch
-// (Navier-Stokes: gin/gtr hold the forward lifted gradients and their traces).
+// The reverse LSERK update of one stage, fused into the last adjoint kernel:
+// with lamU set, that kernel applies lamU += dt a, lamdU = A lamdU + Bnext lamU
+// to a = (dR/dU)^T lam (lam being lamdU) instead of storing a in out.
+struct AdjUpd {
+  double* lamU;
+  double* lamdU;
+  double dt, A, Bnext;
+};
+
+// out = (dR/dU)^T lam (or, with up.lamU, the fused update); Utr holds the
+// traces of U, Lbar/gtr/gbar are scratch (Navier-Stokes: gin/gtr hold the
+// forward lifted gradients and their traces, and out is scratch too when
+// the update is fused).
 hipError_t launch_adjoint(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* lam,
                           const double* Utr, double* Lbar, const double* gin, double* gtr, double* out, double* gbar,
-                          hipStream_t s);
+                          const AdjUpd& up, hipStream_t s);
 // FV sub-cells.  Traces of an FV context hold 10 values per face node: the DG
 // trace (values 0..4) on DG faces; on FV faces the primitive means of the
 // first (0..4) and second (5..9) sub-cell layers under the face.
@@ -125,8 +140,6 @@ hipError_t launch_fv_decide(int nElems, const double* ind, double lo, double hi,
                             hipStream_t s);
 hipError_t launch_fv_side_flags(int nSides, const int* side_elem, const int* etype, int* sidefv, hipStream_t s);
 hipError_t launch_fv_elem_flags(int nElems, const int* efc, const int* sidefv, const int* etype, int* efv, hipStream_t s);
-hipError_t launch_adj_rk_update(size_t n, const double* out, double* lamU, double* lamdU, double dt, double A,
-                                double Bnext, hipStream_t s);
 hipError_t launch_scale_copy(size_t n, const double* x, double* y, double a, hipStream_t s);
 hipError_t launch_fill(double* x, size_t n, double v, hipStream_t s);
 hipError_t launch_fill_int(int* x, size_t n, int v, hipStream_t s);

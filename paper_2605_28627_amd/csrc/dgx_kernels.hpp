@@ -864,7 +864,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
         // two-point flux F#(U_a, ot) . nv
         auto two_point = [&](const Aux& ot, const double nv[3], double F[5]) {
           if (P.twopoint == 0) {
-            chandrashekar<FT>(me, ot, nv, c1, F);
+            chandrashekar<FT>(me, ot, nv, c1, F, P.p0, P.ib0);
           } else {
             // central average of the two physical fluxes (states rebuilt from the staged data)
             double Fa[5], Fb[5];
@@ -991,7 +991,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
       // (the viscous part comes contracted from the lifting kernel)
       if (act) {
         double F[5];
-        euler_flux<FT>(u, q, jr, F);
+        euler_flux<FT>(u, q, jr, F, P.p0, P.h0);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sm[v * n3 + t] = F[v];
       }

@@ -48,7 +48,8 @@ hipError_t static_scratch(void** ptr) {
                                 const double*, const double*, double*, double*, double*, double*, double,   \
                                 double, double, hipStream_t);                                                  \
   hipError_t launch_adjoint_N##n(const Cfg&, const Geo&, const Phys&, const double*, const double*,          \
-                                 const double*, double*, const double*, double*, double*, double*, hipStream_t); \
+                                 const double*, double*, const double*, double*, double*, double*,             \
+                                 const AdjUpd&, hipStream_t);                                                   \
   hipError_t launch_trace_fv_N##n(const Cfg&, const Geo&, const Phys&, const double*, double*, hipStream_t);   \
   hipError_t launch_fv_N##n(const Cfg&, const Geo&, const Phys&, int, const double*, const double*,         \
                             const double*, const double*, double*, double*, double*, double*, double, double,  \
@@ -169,8 +170,8 @@ hipError_t launch_volume(const Cfg& c, const Geo& g, const Phys& p, int mode, co
 
 hipError_t launch_adjoint(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* lam,
                           const double* Utr, double* Lbar, const double* gin, double* gtr, double* out, double* gbar,
-                          hipStream_t s) {
-#define ARGS (c, g, p, U, lam, Utr, Lbar, gin, gtr, out, gbar, s)
+                          const AdjUpd& up, hipStream_t s) {
+#define ARGS (c, g, p, U, lam, Utr, Lbar, gin, gtr, out, gbar, up, s)
   DGX_SWITCH(launch_adjoint)
 #undef ARGS
 }
@@ -189,16 +190,7 @@ __global__ void k_fill_int(int* x, size_t n, int v) {
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) x[t] = v;
 }
 
-// Reverse LSERK bookkeeping after the adjoint residual of stage s:
-// lamU += dt out; lamdU = A_s lamdU + Bnext lamU (Bnext = B_{s-1}, 0 after stage 0).
-__global__ void k_adj_rk_update(size_t n, const double* __restrict__ out, double* __restrict__ lamU,
-                                double* __restrict__ lamdU, double dt, double A, double Bnext) {
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    const double lu = lamU[t] + dt * out[t];
-    lamU[t] = lu;
-    lamdU[t] = A * lamdU[t] + Bnext * lu;
-  }
-}
+// y = a x (the reverse LSERK sweep starts with lamdU = B_{S-1} lamU).
 __global__ void k_scale_copy(size_t n, const double* __restrict__ x, double* __restrict__ y, double a) {
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
     y[t] = a * x[t];
@@ -210,11 +202,6 @@ static unsigned grid_for(size_t n) {
   return (unsigned)(nb ? nb : 1);
 }
 
-hipError_t launch_adj_rk_update(size_t n, const double* out, double* lamU, double* lamdU, double dt, double A,
-                                double Bnext, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_rk_update, dim3(grid_for(n)), dim3(256), 0, s, n, out, lamU, lamdU, dt, A, Bnext);
-  return hipGetLastError();
-}
 hipError_t launch_scale_copy(size_t n, const double* x, double* y, double a, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(256), 0, s, n, x, y, a);
   return hipGetLastError();

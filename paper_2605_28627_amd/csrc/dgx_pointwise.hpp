@@ -98,37 +98,72 @@ struct Aux {
 // The log means are evaluated with two reciprocals per pair, 1/(rho_a+rho_b)
 // and 1/(beta_a+beta_b) (the second also gives p_hat); the series branch
 // divides by P(u) through inv_series, the direct branch needs one more.
+//
+// In float (the FP32-flux mode) p_hat and 1/beta^ln are formed as deviations
+// from a reference state (p0, beta0 = 1/ib0), whose part is added in double:
+//   p_hat - p0      = (1/2) ((rho_a - 2 p0 beta_a) + (rho_b - 2 p0 beta_b)) / (beta_a + beta_b),
+//   1/beta^ln - ib0 = ((P - 2) - ((beta_a ib0 - 1) + (beta_b ib0 - 1))) / (beta_a + beta_b)
+// (series branch, P the series), the bracketed sums in double, and rho^ln
+// (series branch) as {rho} plus its float deviation -{rho} q/(1+q).  At low
+// Mach numbers p and 1/beta are large and nearly constant, so float then
+// rounds only their small deviations (the energy flux multiplies rho^ln by
+// 1/beta^ln).  p0 = ib0 = 0 is no reference state.
 template <typename FT>
-__host__ __device__ inline void chandrashekar(const Aux& a, const Aux& b, const double n[3], double c1, double F[5]) {
+__host__ __device__ inline void chandrashekar(const Aux& a, const Aux& b, const double n[3], double c1, double F[5],
+                                              double p0 = 0.0, double ib0 = 0.0) {
+  constexpr bool kRef = sizeof(FT) == 4;
   const FT thr = sizeof(FT) == 8 ? FT(1e-4) : FT(1e-2);
   const FT sr = FT(a.rho) + FT(b.rho), dr = FT(a.rho) - FT(b.rho);
   const FT sb = FT(a.beta) + FT(b.beta), db = FT(a.beta) - FT(b.beta);
   const FT rsr = rcp_nr(sr), rsb = rcp_nr(sb);
   const FT fr = dr * rsr, ur = fr * fr;
   const FT fb = db * rsb, ub2 = fb * fb;
-  FT rho_ln, ibeta_ln;
+  FT rho_ln, ibeta_ln;   // (kRef: 1/beta^ln - ib0)
+  double rho_lnd;        // rho^ln in double
   if (ur < thr) {
-    const FT P = FT(2) + ur * (FT(2.0 / 3.0) + ur * (FT(2.0 / 5.0) + ur * FT(2.0 / 7.0)));
-    rho_ln = sr * inv_series<FT>(P);
+    if constexpr (kRef) {
+      // rho^ln = {rho} / (1 + q), q = (P - 2)/2: the deviation -{rho} q/(1+q)
+      // in float (1/(1+q) = 1 - q + q^2 to float accuracy for q < 0.0034)
+      const FT q = ur * (FT(1.0 / 3.0) + ur * (FT(1.0 / 5.0) + ur * FT(1.0 / 7.0)));
+      rho_ln = -FT(0.5) * sr * q * (FT(1) - q + q * q);
+      rho_lnd = 0.5 * (a.rho + b.rho) + double(rho_ln);
+    } else {
+      const FT P = FT(2) + ur * (FT(2.0 / 3.0) + ur * (FT(2.0 / 5.0) + ur * FT(2.0 / 7.0)));
+      rho_ln = sr * inv_series<FT>(P);
+      rho_lnd = double(rho_ln);
+    }
   } else {
     rho_ln = dr * rcp_nr(FT(a.lrho) - FT(b.lrho));
+    rho_lnd = double(rho_ln);
   }
   if (ub2 < thr) {
-    ibeta_ln = (FT(2) + ub2 * (FT(2.0 / 3.0) + ub2 * (FT(2.0 / 5.0) + ub2 * FT(2.0 / 7.0)))) * rsb;
+    if constexpr (kRef) {
+      const FT Pm2 = ub2 * (FT(2.0 / 3.0) + ub2 * (FT(2.0 / 5.0) + ub2 * FT(2.0 / 7.0)));
+      const FT dsb = FT((a.beta * ib0 - 1.0) + (b.beta * ib0 - 1.0));
+      ibeta_ln = (Pm2 - dsb) * rsb;
+    } else {
+      ibeta_ln = (FT(2) + ub2 * (FT(2.0 / 3.0) + ub2 * (FT(2.0 / 5.0) + ub2 * FT(2.0 / 7.0)))) * rsb;
+    }
   } else {
     ibeta_ln = (FT(a.lbeta) - FT(b.lbeta)) * rcp_nr(db);
+    if constexpr (kRef) ibeta_ln -= FT(ib0);
   }
-  const FT phat = FT(0.5) * sr * rsb;
+  FT phat;
+  if constexpr (kRef)
+    phat = FT(0.5) * FT((a.rho - 2.0 * p0 * a.beta) + (b.rho - 2.0 * p0 * b.beta)) * rsb;
+  else
+    phat = FT(0.5) * sr * rsb;
   const FT X = ibeta_ln * FT(c1) - FT(0.25) * (FT(a.k) + FT(b.k));
   const double um0 = 0.5 * (a.u[0] + b.u[0]), um1 = 0.5 * (a.u[1] + b.u[1]), um2 = 0.5 * (a.u[2] + b.u[2]);
   const double umn = um0 * n[0] + um1 * n[1] + um2 * n[2];
-  const double Fr = double(rho_ln) * umn;
-  const double ph = double(phat);
+  const double Fr = rho_lnd * umn;
+  const double ph = kRef ? double(phat) + p0 : double(phat);
+  const double Xd = kRef ? double(X) + c1 * ib0 : double(X);
   F[0] = Fr;
   F[1] = ph * n[0] + um0 * Fr;
   F[2] = ph * n[1] + um1 * Fr;
   F[3] = ph * n[2] + um2 * Fr;
-  F[4] = Fr * double(X) + (um0 * F[1] + um1 * F[2] + um2 * F[3]);
+  F[4] = Fr * Xd + (um0 * F[1] + um1 * F[2] + um2 * F[3]);
 }
 
 // Two-point record with the logarithms supplied (ln rho, ln beta).
@@ -195,9 +230,12 @@ __host__ __device__ inline void aux_flux(const Aux& a, double gm1, const double 
   F[4] = H * un;
 }
 
-// Advective flux of U in direction n (not normalised).
+// Advective flux of U in direction n (not normalised).  In float the pressure
+// and the total enthalpy enter as deviations p - p0, H - h0 from a reference
+// state (h0 = gamma p0 / (gamma - 1)), whose part is added in double.
 template <typename FT>
-__host__ __device__ inline void euler_flux(const double U[5], const Prim& q, const double n[3], double F[5]) {
+__host__ __device__ inline void euler_flux(const double U[5], const Prim& q, const double n[3], double F[5],
+                                           double p0 = 0.0, double h0 = 0.0) {
   if constexpr (sizeof(FT) == 8) {
     const double un = q.u[0] * n[0] + q.u[1] * n[1] + q.u[2] * n[2];
     F[0] = U[0] * un;
@@ -207,8 +245,8 @@ __host__ __device__ inline void euler_flux(const double U[5], const Prim& q, con
     F[4] = (U[4] + q.p) * un;
   } else {
     // Cartesian flux components in float, contraction with the metric in double.
-    const float r = float(q.rho), u0 = float(q.u[0]), u1 = float(q.u[1]), u2 = float(q.u[2]), p = float(q.p);
-    const float H = float(U[4]) + p;
+    const float r = float(q.rho), u0 = float(q.u[0]), u1 = float(q.u[1]), u2 = float(q.u[2]), p = float(q.p - p0);
+    const float H = float((U[4] + q.p) - h0);
     const float uu[3] = {u0, u1, u2};
     double acc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
@@ -221,6 +259,9 @@ __host__ __device__ inline void euler_flux(const double U[5], const Prim& q, con
       acc[3] += n[d] * double(ru * u2 + (d == 2 ? p : 0.0f));
       acc[4] += n[d] * double(H * ud);
     }
+    const double un = q.u[0] * n[0] + q.u[1] * n[1] + q.u[2] * n[2];
+    acc[1] += p0 * n[0]; acc[2] += p0 * n[1]; acc[3] += p0 * n[2];
+    acc[4] += h0 * un;
     for (int v = 0; v < 5; ++v) F[v] = acc[v];
   }
 }
@@ -374,13 +415,13 @@ __host__ __device__ inline void surface_flux_adv(const double UL[5], const doubl
   if (FORM == 1 && P.twopoint == 0) {
     const Aux aL = logs ? make_aux_logs(qL, logs[0], logs[1]) : make_aux(qL);
     const Aux aR = logs ? make_aux_logs(qR, logs[2], logs[3]) : make_aux(qR);
-    chandrashekar<FT>(aL, aR, nv, 0.5 / P.gm1, Phi);
+    chandrashekar<FT>(aL, aR, nv, 0.5 / P.gm1, Phi, P.p0, P.ib0);
     if (aux) *aux = side ? aR : aL;
   } else {
     if (FORM == 1 && aux) *aux = make_aux(side ? qR : qL);
     double FL[5], FR[5];
-    euler_flux<FT>(UL, qL, nv, FL);
-    euler_flux<FT>(UR, qR, nv, FR);
+    euler_flux<FT>(UL, qL, nv, FL, P.p0, P.h0);
+    euler_flux<FT>(UR, qR, nv, FR, P.p0, P.h0);
 #pragma unroll
     for (int v = 0; v < 5; ++v) Phi[v] = 0.5 * (FL[v] + FR[v]);
   }

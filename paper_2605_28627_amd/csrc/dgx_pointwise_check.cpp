@@ -30,6 +30,19 @@ void pw_chandrashekar_f32(const double* Ua, const double* Ub, const double* n, c
   chandrashekar<float>(a, b, n, 0.5 / P.gm1, F);
 }
 
+// float flux about the reference state ref = (p0, ib0 = 2 p0 / rho0)
+void pw_chandrashekar_f32_ref(const double* Ua, const double* Ub, const double* n, const double* c, const double* ref,
+                              double* F) {
+  Phys P = make_phys(c);
+  Aux a = make_aux(cons2prim(Ua, P.gm1)), b = make_aux(cons2prim(Ub, P.gm1));
+  chandrashekar<float>(a, b, n, 0.5 / P.gm1, F, ref[0], ref[1]);
+}
+
+void pw_euler_flux_f32_ref(const double* U, const double* n, const double* c, const double* ref, double* F) {
+  Phys P = make_phys(c);
+  euler_flux<float>(U, cons2prim(U, P.gm1), n, F, ref[0], P.gamma * ref[0] / P.gm1);
+}
+
 void pw_chandrashekar_vjp_a(const double* Ua, const double* Ub, const double* n, const double* c, const double* w,
                             double* Uab) {
   Phys P = make_phys(c);

@@ -35,7 +35,7 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_MESH", 3: "DG_ERR_HIP", 
                 5: "DG_ERR_NOMEM", 6: "DG_ERR_UNSUPPORTED", 7: "DG_ERR_STATE"}
 
 # public symbols of include/dgx.h
-SYMBOLS = ["dg_create", "dg_destroy", "dg_last_error", "dg_lserk_coefficients", "dg_rk_coefficients", "dg_set_mesh", "dg_upload_mesh",
+SYMBOLS = ["dg_create", "dg_destroy", "dg_set_reference_state", "dg_last_error", "dg_lserk_coefficients", "dg_rk_coefficients", "dg_set_mesh", "dg_upload_mesh",
            "dg_upload_metrics", "dg_get_metrics", "dg_node_coords", "dg_sizes", "dg_workspace_bytes",
            "dg_workspace_bytes_adjoint", "dg_bind_workspace", "dg_init_state", "dg_rhs", "dg_lift", "dg_rk_step", "dg_rk_step_noalloc", "dg_adjoint_rhs", "dg_adjoint_rk_step",
            "dg_kinetic_energy", "dg_kinetic_energy_grad", "dg_timestep", "dg_check_state", "dg_profile",
@@ -62,6 +62,7 @@ _sz = ctypes.c_size_t
 _sig = {
     "dg_create": (ctypes.c_int, [ctypes.POINTER(dg_config), ctypes.POINTER(_vp)]),
     "dg_destroy": (ctypes.c_int, [_vp]),
+    "dg_set_reference_state": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
     "dg_last_error": (ctypes.c_char_p, [_vp]),
     "dg_lserk_coefficients": (ctypes.c_int, [_dp, _dp, _dp]),
     "dg_rk_coefficients": (ctypes.c_int, [ctypes.c_int, _dp, _dp, _dp, _ip]),
@@ -150,6 +151,10 @@ def dg_create(cfg: dg_config):
 
 def dg_destroy(ctx):
     _check(None, _L.dg_destroy(ctx))
+
+
+def dg_set_reference_state(ctx, rho0, p0):
+    _check(ctx, _L.dg_set_reference_state(ctx, float(rho0), float(p0)))
 
 
 def dg_last_error(ctx):

@@ -397,6 +397,17 @@ def workload_mesh(name, K=None):
     return box_mesh(K, w["lo"], w["hi"], Ngeo=Ngeo, curved_amp=w["curved"])
 
 
+def workload_reference(name, gamma=1.4, state=None):
+    """(rho0, p0) of a workload's background state: the reference state of
+    the FP32-flux arithmetic (Taylor-Green vortex and free stream at Mach 0.1:
+    p0 = rho0 U0^2 / (gamma Ma^2); density wave: rho 2, p 1)."""
+    w = WORKLOADS[name]
+    kind = "freestream" if state == "freestream" else w["state"]
+    if kind == "density_wave":
+        return 2.0, 1.0
+    return 1.0, 1.0 / (gamma * 0.1 * 0.1)
+
+
 def workload_state(name, xyz, gamma=1.4, state=None):
     """Initial state of a workload; state="freestream" replaces it by a free stream."""
     w = WORKLOADS[name]

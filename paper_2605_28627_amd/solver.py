@@ -60,6 +60,10 @@ class DGSolver:
         except Exception:
             pass
 
+    def set_reference_state(self, rho0: float, p0: float):
+        """Reference state of the FP32-flux arithmetic (rounding only)."""
+        dgx.dg_set_reference_state(self.ctx, rho0, p0)
+
     @property
     def state_shape(self):
         return (5, self.nElems, self.n1, self.n1, self.n1)

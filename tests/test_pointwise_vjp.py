@@ -201,3 +201,35 @@ def test_surface_flux_vjp(pw, form, phys, riemann):
                     fwd(UL - eps * dL, UR - eps * dR, gL - eps * dgL, gR - eps * dgR)) / (2 * eps))
         got = ULb @ dL + URb @ dR + (gLb @ dgL + gRb @ dgR if phys else 0.0)
         assert abs(got - ref) < 1e-6 * (1 + abs(ref)), (it, got, ref)
+
+
+def test_fp32_reference_state_rounds_deviations_only(pw):
+    """Low-Mach pairs (p ~ 71, small jumps): the float two-point and advective
+    fluxes about the reference state (p0, 2 p0/rho0) keep the momentum and
+    energy error near float rounding of the deviations, far below the float
+    evaluation without a reference state; the reference changes rounding only."""
+    rng = np.random.default_rng(31)
+    p0 = 1.0 / (G * 0.01)
+    ref, none = np.array([p0, 2.0 * p0]), np.array([0.0, 0.0])
+    e_ref, e_none, ea_ref, ea_none = [], [], [], []
+    for _ in range(500):
+        def st():
+            rho = 1 + 0.01 * rng.uniform(-1, 1)
+            u = rng.uniform(-1, 1, 3)
+            p = p0 + rng.uniform(-1, 1)
+            return np.array([rho, *(rho * u), p / (G - 1) + 0.5 * rho * u @ u])
+        a = st()
+        b = a + 0.01 * (st() - a)
+        n = rng.normal(size=3)
+        F = call(pw.pw_chandrashekar, 5, a, b, n, C)
+        e_ref.append(np.abs(call(pw.pw_chandrashekar_f32_ref, 5, a, b, n, C, ref) - F))
+        e_none.append(np.abs(call(pw.pw_chandrashekar_f32_ref, 5, a, b, n, C, none) - F))
+        E = call(pw.pw_euler_flux, 5, a, n, C)
+        ea_ref.append(np.abs(call(pw.pw_euler_flux_f32_ref, 5, a, n, C, ref) - E))
+        ea_none.append(np.abs(call(pw.pw_euler_flux_f32_ref, 5, a, n, C, none) - E))
+    e_ref, e_none = np.max(e_ref, 0), np.max(e_none, 0)
+    ea_ref, ea_none = np.max(ea_ref, 0), np.max(ea_none, 0)
+    assert np.all(e_ref[1:4] < 1e-6) and e_ref[4] < 1e-5, e_ref
+    assert np.all(e_ref[1:] * 20 < e_none[1:]), (e_ref, e_none)
+    assert np.all(ea_ref[1:] < 2e-6) and np.all(ea_ref[1:] * 10 < ea_none[1:]), (ea_ref, ea_none)
+
