@@ -85,6 +85,15 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_trace(Geo G, const double
 //      second-argument adjoint.  On lines inside one wavefront the lane of m
 //      evaluates (m, m+d) once and hands the partner's share over a shuffle,
 //      as the forward kernel does.
+// Split form on Gauss nodes (the entropy-stable hybridised form): the
+// element's own traces are the projected states u~_f = u(E v(U)).  Their
+// adjoints collect in LDS (sub) from the surface flux (phase 1) and from the
+// face coupling -(1/w_a) B_f l_f(a) (G_f(a) - S_f), G_f(a) = F#(U_a, u~_f) .
+// (Ja_a + Ja_f)/2, S_f = sum_l l_f(l) G_f(l) (phase 3): with w_a the
+// coupling's weight of lam_a, the coupling is sum_a (w_a - l_f(a) W) G_f(a),
+// W = sum_l w_l, so each node reverses its own G_f and the u~_f parts are
+// summed along the line.  Phase 4 maps them back through the projection:
+// (du/dv)^T at each face node, l_f along the lines, (dv/dU)^T at each node.
 // Waves per SIMD requested for 512-work-item adjoint kernels: 1 leaves the
 // register file to one element per CU (the Jacobian chain stays in registers),
 // 4 would cap it at 128 VGPRs for two elements per CU and spill.
@@ -98,13 +107,16 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
     double* __restrict__ out, double* __restrict__ gbar, AdjUpd up) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
+  constexpr bool ES = FORM == 1 && NODES == 0;
   constexpr int NF = PHYS == 1 ? 17 : 5;                           // face adjoint values per face node
   constexpr int SZ_F = NF * S::nface;
-  constexpr int SZ_V = FORM == 1 ? 11 * n3 : 0;                      // aux (8) + one metric row (3)
+  // aux (8) + one metric row (3) (+ ES: the coupling's u~_f parts of both faces, 10)
+  constexpr int SZ_V = FORM == 1 ? (ES ? 21 : 11) * n3 : 0;
   constexpr int SZ_B = SZ_F > SZ_V ? SZ_F : SZ_V;
   constexpr bool kSymLines = DGX_SYMMETRIC_PAIRS && (n1 == 4 || n1 == 8) && (n3 % 64 == 0);
   __shared__ double sl[5 * n3];   // lam / J
   __shared__ double sB[SZ_B];     // surface adjoints, then aux + metric row
+  __shared__ double sub[ES ? 5 * S::nface : 1];   // ES: adjoints of the own projected traces
   __shared__ DevBasis sb;
   const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   const int nE = G.nElems, nS = G.nSides;
@@ -148,6 +160,10 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
     // (element-wise selects keep both sides' adjoints in registers)
 #pragma unroll
     for (int v = 0; v < 5; ++v) sB[(f * NF + v) * n2 + rr] = slot ? URb[v] : ULb[v];
+    if constexpr (ES) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sub[(f * 5 + v) * n2 + rr] = slot ? URb[v] : ULb[v];
+    }
     if constexpr (PHYS == 1) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) sB[(f * NF + 5 + c) * n2 + rr] = slot ? gRb[c] : gLb[c];
@@ -173,8 +189,10 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
         } else {
           L = sd ? sb.Lp[a] : sb.Lm[a];
         }
+        if constexpr (!ES) {   // (ES: through the projection in phase 4)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Ub[v] += L * sB[(f * NF + v) * n2 + rr];
+          for (int v = 0; v < 5; ++v) Ub[v] += L * sB[(f * NF + v) * n2 + rr];
+        }
         if constexpr (PHYS == 1) {
 #pragma unroll
           for (int c = 0; c < 12; ++c) gb[c] += L * sB[(f * NF + 5 + c) * n2 + rr];
@@ -331,8 +349,75 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
             }
           }
         }
+        if constexpr (ES) {
+          // face coupling of this direction's two faces: node a reverses its
+          // G_f(a) with the weight w_a - l_f(a) W; the u~_f parts go to sred
+          double* sred = sB + 11 * n3;   // [2 faces][5][n3]
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            const double* L = f ? sb.Lp : sb.Lm;
+            const double sg = f ? -1.0 : 1.0;
+            const int info = G.efc[e * 6 + 2 * r + f];
+            const int side = efc_side(info), slot = efc_slot(info);
+            int p = pp, qm = qq;
+            if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+            double uf[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) uf[v] = Utr[tr_index(slot, v, 5, nS, side, n2, qm * n1 + p)];
+            const Prim qf = cons2prim(uf, P.gm1);
+            double jf[3] = {0.0, 0.0, 0.0}, W[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+            for (int l = 0; l < n1; ++l) {
+              const int tl = line_node<N>(r, l, pp, qq);
+              const double cw = sg * sb.winv[l] * L[l];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) jf[c] += L[l] * sja[c * n3 + tl];
+#pragma unroll
+              for (int v = 0; v < 5; ++v) W[v] += cw * sl[v * n3 + tl];
+            }
+            const double nv[3] = {0.5 * (jr[0] + jf[0]), 0.5 * (jr[1] + jf[1]), 0.5 * (jr[2] + jf[2])};
+            const double ca = sg * sb.winv[a] * L[a];
+            double om[5], Uf[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) om[v] = ca * lm[v] - L[a] * W[v];
+            if (P.twopoint == 0) {
+              const Aux af = make_aux(qf);
+              AuxBar da, dfb;
+              chandrashekar_vjp_ab(me, af, nv, c1, om, da, dfb);
+              ab.rho += da.rho; ab.u[0] += da.u[0]; ab.u[1] += da.u[1]; ab.u[2] += da.u[2];
+              ab.beta += da.beta; ab.lrho += da.lrho; ab.lbeta += da.lbeta; ab.k += da.k;
+              aux_vjp(qf, af, dfb, P.gm1, Uf);
+            } else {
+              double u[5];
+#pragma unroll
+              for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+              const double wh[5] = {0.5 * om[0], 0.5 * om[1], 0.5 * om[2], 0.5 * om[3], 0.5 * om[4]};
+              double Ue[5];
+              euler_flux_vjp(u, cons2prim(u, P.gm1), nv, wh, P.gm1, Ue);
+#pragma unroll
+              for (int v = 0; v < 5; ++v) Ub[v] += Ue[v];
+              euler_flux_vjp(uf, qf, nv, wh, P.gm1, Uf);
+            }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sred[(f * 5 + v) * n3 + t] = Uf[v];
+          }
+        }
       }
       __syncthreads();
+      if constexpr (ES) {
+        // the u~_f parts of this direction's faces, summed along each line
+        const double* sred = sB + 11 * n3;
+        for (int ft = t; ft < 2 * n2; ft += S::nth) {
+          const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < n1; ++l) acc += sred[(f * 5 + v) * n3 + line_node<N>(r, l, pp, qq)];
+            sub[((2 * r + f) * 5 + v) * n2 + rr] += acc;
+          }
+        }
+      }
     }
     if (act && P.twopoint == 0) {
       double u[5];
@@ -343,6 +428,47 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
       aux_vjp(q, me, ab, P.gm1, Ua);
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ub[v] += Ua[v];
+    }
+  }
+  if constexpr (ES) {
+    // 4. back through the projection: (du/dv)^T at each face node (v_f from
+    // the projected trace), then l_f along the lines and (dv/dU)^T at each node
+    __syncthreads();
+    for (int ft = t; ft < S::nface; ft += S::nth) {
+      const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
+      const int info = G.efc[e * 6 + f];
+      const int side = efc_side(info), slot = efc_slot(info);
+      int p = pp, qm = qq;
+      if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+      double uf[5], vf[5], ub[5], vb[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        uf[v] = Utr[tr_index(slot, v, 5, nS, side, n2, qm * n1 + p)];
+        ub[v] = sub[(f * 5 + v) * n2 + rr];
+      }
+      entropy_vars(cons2prim(uf, P.gm1), P.gm1, vf);
+      entropy_to_cons_vjp(vf, P.gm1, ub, vb);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sub[(f * 5 + v) * n2 + rr] = vb[v];
+    }
+    __syncthreads();
+    if (act) {
+      double vb[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int a = idx[r];
+        const int rr = (r == 2 ? j : k) * n1 + (r == 0 ? j : i);
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          const double L = f ? sb.Lp[a] : sb.Lm[a];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) vb[v] += L * sub[((2 * r + f) * 5 + v) * n2 + rr];
+        }
+      }
+      double u[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+      entropy_vars_vjp(u, P.gm1, vb, Ub);
     }
   }
   if (act) {
@@ -401,8 +527,11 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_trace(Geo G, const d
   }
 }
 
-// Lifting adjoint, volume and face parts: out += (dq/dU)^T qbar.
-template <int N, int NODES>
+// Lifting adjoint, volume and face parts: out += (dq/dU)^T qbar.  EP 1 (split
+// form on Gauss nodes): the face values are the projected traces, so their
+// adjoints go back through the projection ((du/dv)^T at the face node, l_f
+// along the line, (dv/dU)^T at the node).
+template <int N, int NODES, int EP = 0>
 __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_volume(Geo G, Phys P, const double* __restrict__ U,
                                                                    const double* __restrict__ Utr,
                                                                    const double* __restrict__ gbar,
@@ -472,11 +601,19 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_volume(Geo G, Phys P
       qb[qa] = 0.5 * (Qbar[tr_index(0, qa, 4, nS, side, n2, fi)] + Qbar[tr_index(1, qa, 4, nS, side, n2, fi)]);
     double Ut[5];
     qvars_vjp(cons2prim(Uo, P.gm1), P.gm1, P.Rinv, qb, Ut);
+    if constexpr (EP == 1) {
+      double vf[5], vb[5] = {0, 0, 0, 0, 0};
+      entropy_vars(cons2prim(Uo, P.gm1), P.gm1, vf);
+      entropy_to_cons_vjp(vf, P.gm1, Ut, vb);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ut[v] = vb[v];
+    }
 #pragma unroll
     for (int v = 0; v < 5; ++v) sfb[(f * 5 + v) * n2 + rr] = Ut[v];
   }
   __syncthreads();
   if (act) {
+    double Fb[5] = {0, 0, 0, 0, 0};   // the faces' part (EP: of the node's entropy variables)
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       const int a = idx[r];
@@ -492,8 +629,17 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_volume(Geo G, Phys P
           L = sd ? sb.Lp[a] : sb.Lm[a];
         }
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Ub[v] += L * sfb[(f * 5 + v) * n2 + rr];
+        for (int v = 0; v < 5; ++v) Fb[v] += L * sfb[(f * 5 + v) * n2 + rr];
       }
+    }
+    if constexpr (EP == 1) {
+      double u[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+      entropy_vars_vjp(u, P.gm1, Fb, Ub);
+    } else {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ub[v] += Fb[v];
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) {

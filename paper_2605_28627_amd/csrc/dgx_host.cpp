@@ -1011,8 +1011,6 @@ static dg_status ready_adjoint(dg_ctx* c, const char* who) {
   dg_status st = ready(c, who);
   if (st != DG_OK) return st;
   if (c->cfg.precision != DG_PREC_FP64) return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": FP64 contexts only");
-  if (c->cfg.volume_form == DG_FORM_SPLIT && c->cfg.nodes == DG_NODES_GAUSS)
-    return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": the adjoint covers the split form on Lobatto nodes only");
   if (c->cfg.fv) return fail(c, DG_ERR_UNSUPPORTED, std::string(who) + ": the adjoint does not cover FV sub-cells");
   if (c->ws_bytes < ws_layout(c).total_adjoint)
     return fail(c, DG_ERR_STATE, std::string(who) + ": bound workspace is smaller than dg_workspace_bytes_adjoint");

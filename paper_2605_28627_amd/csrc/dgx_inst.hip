@@ -222,8 +222,10 @@ hipError_t DGX_NAME(launch_adjoint)(const Cfg& c, const Geo& g, const Phys& p, c
       else DGX_ADJ_V(NODES, FORM, PHYS, 0, 0);                           \
     }                                                                    \
   } while (0)
-  if (c.nodes == 0) {
+  if (c.nodes == 0 && c.form == 0) {
     if (c.physics == 0) DGX_ADJ(0, 0, 0); else DGX_ADJ(0, 0, 1);
+  } else if (c.nodes == 0) {
+    if (c.physics == 0) DGX_ADJ(0, 1, 0); else DGX_ADJ(0, 1, 1);
   } else if (c.form == 0) {
     if (c.physics == 0) DGX_ADJ(1, 0, 0); else DGX_ADJ(1, 0, 1);
   } else {
@@ -238,7 +240,10 @@ hipError_t DGX_NAME(launch_adjoint)(const Cfg& c, const Geo& g, const Phys& p, c
       hipLaunchKernelGGL((k_adj_lift_volume<kN, 1>), grid, block, 0, s, g, p, U, Utr, gbar, gtr, out, up);
     } else {
       hipLaunchKernelGGL((k_adj_lift_trace<kN, 0>), grid, block, 0, s, g, gbar, gtr);
-      hipLaunchKernelGGL((k_adj_lift_volume<kN, 0>), grid, block, 0, s, g, p, U, Utr, gbar, gtr, out, up);
+      if (c.form == 1)
+        hipLaunchKernelGGL((k_adj_lift_volume<kN, 0, 1>), grid, block, 0, s, g, p, U, Utr, gbar, gtr, out, up);
+      else
+        hipLaunchKernelGGL((k_adj_lift_volume<kN, 0>), grid, block, 0, s, g, p, U, Utr, gbar, gtr, out, up);
     }
   }
   return hipGetLastError();

@@ -335,6 +335,12 @@ struct Dual {
     return Dual(r, 0.5 * a.d / r);
   }
   friend __host__ __device__ Dual fabs(Dual a) { return a.v < 0.0 ? -a : a; }
+  friend __host__ __device__ Dual log(Dual a) { return Dual(::log(a.v), a.d / a.v); }
+  friend __host__ __device__ Dual exp(Dual a) {
+    const double e = ::exp(a.v);
+    return Dual(e, e * a.d);
+  }
+  friend __host__ __device__ Dual operator*(double s, Dual a) { return Dual(s * a.v, s * a.d); }
   friend __host__ __device__ bool operator<(Dual a, Dual b) { return a.v < b.v; }
   friend __host__ __device__ bool operator>(Dual a, Dual b) { return a.v > b.v; }
 };
@@ -481,6 +487,50 @@ __host__ __device__ inline void prim_vjp(const Prim& q, double gm1, double rb, c
   Ub[2] = ub[1] * ri - gm1 * pb * q.u[1];
   Ub[3] = ub[2] * ri - gm1 * pb * q.u[2];
   Ub[0] = rb - (ub[0] * q.u[0] + ub[1] * q.u[1] + ub[2] * q.u[2]) * ri + 0.5 * gm1 * pb * k;
+}
+
+// Adjoints of the entropy projection of the split form on Gauss nodes
+// (u~ = u(E v(U))), by forward-mode columns of the two maps: Vb += (du/dv)^T Ub
+// at the entropy variables v, and Ub += (dv/dU)^T Vb at the state U.
+__host__ __device__ inline void entropy_to_cons_vjp(const double v[5], double gm1, const double Ub[5], double Vb[5]) {
+#pragma unroll 1
+  for (int k = 0; k < 5; ++k) {
+    Dual x[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) x[c] = Dual(v[c], c == k ? 1.0 : 0.0);
+    const Dual b = -x[4];
+    const Dual ib = Dual(1.0) / b;
+    const Dual u0 = x[1] * ib, u1 = x[2] * ib, u2 = x[3] * ib;
+    const Dual kk = u0 * u0 + u1 * u1 + u2 * u2;
+    const Dual z = x[0] + 0.5 * (b * kk);
+    const Dual rho = exp(z - (Dual(gm1 + 1.0) + log(b)) / Dual(gm1));
+    const Dual U[5] = {rho, rho * u0, rho * u1, rho * u2, rho * ib / Dual(gm1) + 0.5 * (rho * kk)};
+    double sdot = 0.0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sdot += Ub[c] * U[c].d;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Vb[c] += c == k ? sdot : 0.0;
+  }
+}
+__host__ __device__ inline void entropy_vars_vjp(const double Uin[5], double gm1, const double Vb[5], double Ub[5]) {
+#pragma unroll 1
+  for (int k = 0; k < 5; ++k) {
+    Dual x[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) x[c] = Dual(Uin[c], c == k ? 1.0 : 0.0);
+    const Dual ri = Dual(1.0) / x[0];
+    const Dual u0 = x[1] * ri, u1 = x[2] * ri, u2 = x[3] * ri;
+    const Dual kk = u0 * u0 + u1 * u1 + u2 * u2;
+    const Dual p = Dual(gm1) * (x[4] - 0.5 * (x[0] * kk));
+    const Dual b = x[0] / p;
+    const Dual s = log(p) - Dual(gm1 + 1.0) * log(x[0]);
+    const Dual v[5] = {(Dual(gm1 + 1.0) - s) / Dual(gm1) - 0.5 * (b * kk), b * u0, b * u1, b * u2, -b};
+    double sdot = 0.0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sdot += Vb[c] * v[c].d;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Ub[c] += c == k ? sdot : 0.0;
+  }
 }
 
 // Adjoint of Roe's dissipation D(UL, UR) on the unit normal nh: ULb, URb +=

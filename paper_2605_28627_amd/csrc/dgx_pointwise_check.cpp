@@ -64,6 +64,28 @@ void pw_chandrashekar_vjp_ab(const double* Ua, const double* Ub, const double* n
   aux_vjp(qb, b, bb, P.gm1, Ubb);
 }
 
+void pw_entropy_vars(const double* U, const double* c, double* v) {
+  Phys P = make_phys(c);
+  entropy_vars(cons2prim(U, P.gm1), P.gm1, v);
+}
+
+void pw_entropy_to_cons(const double* v, const double* c, double* U) {
+  Phys P = make_phys(c);
+  entropy_to_cons(v, P.gm1, U);
+}
+
+void pw_entropy_vars_vjp(const double* U, const double* c, const double* Vb, double* Ub) {
+  Phys P = make_phys(c);
+  for (int k = 0; k < 5; ++k) Ub[k] = 0.0;
+  entropy_vars_vjp(U, P.gm1, Vb, Ub);
+}
+
+void pw_entropy_to_cons_vjp(const double* v, const double* c, const double* Ub, double* Vb) {
+  Phys P = make_phys(c);
+  for (int k = 0; k < 5; ++k) Vb[k] = 0.0;
+  entropy_to_cons_vjp(v, P.gm1, Ub, Vb);
+}
+
 void pw_euler_flux(const double* U, const double* n, const double* c, double* F) {
   Phys P = make_phys(c);
   euler_flux<double>(U, cons2prim(U, P.gm1), n, F);

@@ -12,8 +12,8 @@ oracle, through the C-ABI.
 * on the GPU's own residual: entropy conservation with the central face flux,
   free-stream preservation and conservation with the library's metrics;
 * the TGV workload at full size (16^3, N=3): sampled elements;
-* a single periodic element and one-element slabs;
-* the adjoint refuses this form.
+* a single periodic element and one-element slabs
+(the adjoint of this form is checked with the other adjoint tests).
 """
 import sys
 
@@ -225,12 +225,3 @@ def test_degenerate_meshes_match_oracle(S, orc, case, K):
     Ug = s.init_state(U)
     s.rk_step(Ug, s.empty_state(), 1e-3, 0)
     assert np.array_equal(Ug.cpu().numpy(), U)
-
-
-def test_adjoint_refuses_gauss_split_form(S, orc, torch_cuda):
-    from paper_2605_28627_amd import dgx
-    o, s, _ = _setup(S, orc, CASES[2])
-    U = s.init_state(I.smooth_random_state(o.coords(), 58, amp=0.1))
-    with pytest.raises(dgx.DGError) as ei:
-        s.adjoint_rhs(U, torch_cuda.ones_like(U))
-    assert ei.value.status == dgx.DG_ERR_UNSUPPORTED

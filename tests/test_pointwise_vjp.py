@@ -233,3 +233,19 @@ def test_fp32_reference_state_rounds_deviations_only(pw):
     assert np.all(e_ref[1:] * 20 < e_none[1:]), (e_ref, e_none)
     assert np.all(ea_ref[1:] < 2e-6) and np.all(ea_ref[1:] * 10 < ea_none[1:]), (ea_ref, ea_none)
 
+
+def test_entropy_projection_vjps(pw):
+    """The adjoints of the two maps of the entropy projection, v(U) and its
+    inverse u(v), against central differences of the forward maps, and the
+    inverse pair round trip."""
+    rng = np.random.default_rng(41)
+    for _ in range(20):
+        U = state(rng)
+        v = call(pw.pw_entropy_vars, 5, U, C)
+        assert np.allclose(call(pw.pw_entropy_to_cons, 5, v, C), U, rtol=1e-12, atol=1e-12)
+        d, w = rng.normal(size=5), rng.normal(size=5)
+        ref = fd_dot(lambda x: call(pw.pw_entropy_vars, 5, x, C), U, d, w, eps=1e-7)
+        assert abs(call(pw.pw_entropy_vars_vjp, 5, U, C, w) @ d - ref) < 1e-7 * (1 + abs(ref))
+        ref = fd_dot(lambda x: call(pw.pw_entropy_to_cons, 5, x, C), v, d, w, eps=1e-7)
+        assert abs(call(pw.pw_entropy_to_cons_vjp, 5, v, C, w) @ d - ref) < 1e-7 * (1 + abs(ref))
+
