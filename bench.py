@@ -481,9 +481,8 @@ def main():
     del final64
     torch.cuda.empty_cache()
     _log("adjoint" if not args.no_adjoint else "adjoint skipped")
-    # the adjoint covers the Rusanov flux, constant viscosity and the Lobatto split form
-    adjoint_ok = (args.riemann == "rusanov" and args.viscosity == "constant"
-                  and not (w["form"] == 1 and w["nodes"] == 0))
+    # the adjoint covers every FP64 DG configuration (not FV sub-cells)
+    adjoint_ok = args.fv == "none"
     result["adjoint_forward_cost"] = (adjoint_cost(cfg, mesh, dev, U0, dt, args)
                                       if not args.no_adjoint and adjoint_ok else None)
     if not args.no_cpu_baseline:

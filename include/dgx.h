@@ -229,10 +229,12 @@ dg_status dg_rk_step_noalloc(dg_ctx* ctx, double* U, double* dU, double t, doubl
  * kinks of the Rusanov flux (|u.n|, max of the two wave speeds), of Roe's
  * flux (|.| of the wave speeds, the Harten-Hyman fix) and of the log-mean
  * branch switch the branch taken by the forward evaluation is
- * differentiated, ties going to the master side.  Covers Rusanov and Roe,
+ * differentiated, ties going to the master side.  Covers every FP64 DG
+ * configuration: weak and split forms on both node sets (on Gauss nodes the
+ * hybridised form with its entropy-projected traces), Rusanov and Roe,
  * constant viscosity and Sutherland's law; DG_ERR_UNSUPPORTED for FP32 flux
- * arithmetic, the split form on Gauss nodes and FV sub-cells.  Needs a
- * workspace of dg_workspace_bytes_adjoint bytes. */
+ * arithmetic and FV sub-cells.  Needs a workspace of
+ * dg_workspace_bytes_adjoint bytes. */
 dg_status dg_adjoint_rhs(dg_ctx* ctx, const double* U, const double* lam, double* out, void* stream);
 
 /* Reverse of one step of size dt of the context's RK scheme (S stages) from
