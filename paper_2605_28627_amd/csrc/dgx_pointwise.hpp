@@ -589,85 +589,54 @@ __host__ __device__ inline void aux_vjp(const Prim& q, const Aux& a, const AuxBa
   prim_vjp(q, gm1, rb, ub, pb, Ub);
 }
 
-// d/dx and d/dlx of the logarithmic mean (same branch as the forward).
-__host__ __device__ inline void log_mean_grad(double x, double y, double lx, double ly, double& dx, double& dlx) {
-  const double f = (x - y) / (x + y);
-  const double u = f * f;
+// The logarithmic mean L(x, y; lx, ly) and its partial derivatives, from the
+// sum s = x + y and is = 1/s (branch as in the forward; reciprocals by rcp_nr):
+//   series (u = ((x-y)/s)^2 < 1e-4): L = s/P(u), dL/dx = 1/P - c y, dL/dy = 1/P + c x,
+//     c = 4 f P'(u) / (P^2 s), f = (x-y)/s;
+//   direct: L = (x-y)/(lx-ly), dL/dx = -dL/dy = 1/(lx-ly), dL/dlx = -dL/dly = -L/(lx-ly).
+__host__ __device__ inline void log_mean_d(double x, double y, double lx, double ly, double s, double is, double& L,
+                                           double& dx, double& dy, double& dlx, double& dly) {
+  const double f = (x - y) * is, u = f * f;
   if (u < 1e-4) {
     const double P = 2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0)));
     const double dP = 2.0 / 3.0 + u * (4.0 / 5.0 + u * (6.0 / 7.0));
-    const double s = x + y;
-    const double du = 2.0 * f * (2.0 * y / (s * s));
-    dx = 1.0 / P - s / (P * P) * dP * du;
-    dlx = 0.0;
-  } else {
-    const double dl = lx - ly;
-    dx = 1.0 / dl;
-    dlx = -((x - y) / dl) / dl;
-  }
-}
-// d/dx and d/dlx of the reciprocal logarithmic mean.
-__host__ __device__ inline void inv_log_mean_grad(double x, double y, double lx, double ly, double& dx, double& dlx) {
-  const double f = (x - y) / (x + y);
-  const double u = f * f;
-  if (u < 1e-4) {
-    const double P = 2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0)));
-    const double dP = 2.0 / 3.0 + u * (4.0 / 5.0 + u * (6.0 / 7.0));
-    const double s = x + y;
-    const double du = 2.0 * f * (2.0 * y / (s * s));
-    dx = dP * du / s - P / (s * s);
-    dlx = 0.0;
-  } else {
-    const double d = x - y;
-    dx = -((lx - ly) / d) / d;
-    dlx = 1.0 / d;
-  }
-}
-
-// Both arguments' partial derivatives of the logarithmic mean L(x, y; lx, ly)
-// (same branch as the forward): d/dx, d/dlx, d/dy, d/dly.
-__host__ __device__ inline void log_mean_grad2(double x, double y, double lx, double ly, double& dx, double& dlx,
-                                               double& dy, double& dly) {
-  const double s = x + y;
-  const double f = (x - y) / s;
-  const double u = f * f;
-  if (u < 1e-4) {
-    const double P = 2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0)));
-    const double dP = 2.0 / 3.0 + u * (4.0 / 5.0 + u * (6.0 / 7.0));
-    const double iP = 1.0 / P;
-    const double c = s * iP * iP * dP * 4.0 * f / (s * s);   // s/P^2 dP/du * 2f * 2/s^2
+    const double iP = rcp_nr(P);
+    L = s * iP;
+    const double c = 4.0 * f * dP * iP * iP * is;
     dx = iP - c * y;
     dy = iP + c * x;
     dlx = 0.0;
     dly = 0.0;
   } else {
-    const double idl = 1.0 / (lx - ly);
-    const double q = (x - y) * idl * idl;
+    const double idl = rcp_nr(lx - ly);
+    L = (x - y) * idl;
+    const double q = L * idl;
     dx = idl;
     dy = -idl;
     dlx = -q;
     dly = q;
   }
 }
-// Both arguments' partial derivatives of the reciprocal logarithmic mean.
-__host__ __device__ inline void inv_log_mean_grad2(double x, double y, double lx, double ly, double& dx, double& dlx,
-                                                   double& dy, double& dly) {
-  const double s = x + y;
-  const double f = (x - y) / s;
-  const double u = f * f;
+// The reciprocal logarithmic mean I = 1/L and its partial derivatives:
+//   series: I = P/s, dI/dx = -P/s^2 + c y, dI/dy = -P/s^2 - c x, c = 4 f P'(u)/s^3;
+//   direct: I = (lx-ly)/(x-y), dI/dx = -dI/dy = -I/(x-y), dI/dlx = -dI/dly = 1/(x-y).
+__host__ __device__ inline void inv_log_mean_d(double x, double y, double lx, double ly, double s, double is,
+                                               double& I, double& dx, double& dy, double& dlx, double& dly) {
+  const double f = (x - y) * is, u = f * f;
   if (u < 1e-4) {
     const double P = 2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0)));
     const double dP = 2.0 / 3.0 + u * (4.0 / 5.0 + u * (6.0 / 7.0));
-    const double is = 1.0 / s;
-    const double c = dP * 4.0 * f * is * is * is;             // dP/du * 2f * 2/s^2 / s
-    const double base = -P * is * is;
+    I = P * is;
+    const double c = 4.0 * f * dP * is * is * is;
+    const double base = -I * is;
     dx = base + c * y;
     dy = base - c * x;
     dlx = 0.0;
     dly = 0.0;
   } else {
-    const double id = 1.0 / (x - y);
-    const double q = (lx - ly) * id * id;
+    const double id = rcp_nr(x - y);
+    I = (lx - ly) * id;
+    const double q = I * id;
     dx = -q;
     dy = q;
     dlx = id;
@@ -677,14 +646,17 @@ __host__ __device__ inline void inv_log_mean_grad2(double x, double y, double lx
 
 // d(w . F#(a, b; n))/d aux_a and d aux_b for Chandrashekar's flux in one
 // reverse sweep (FP64 forward).  The averages are symmetric, so the two
-// argument adjoints share every term except the log-mean derivatives.
+// argument adjoints share every term except the log-mean derivatives; three
+// reciprocals (1/(rho_a+rho_b), 1/(beta_a+beta_b), and the log mean's own)
+// serve the whole sweep.
 __host__ __device__ inline void chandrashekar_vjp_ab(const Aux& a, const Aux& b, const double n[3], double c1,
                                                      const double w[5], AuxBar& aa, AuxBar& bb) {
-  const double rho_ln = log_mean<double>(a.rho, b.rho, a.lrho, b.lrho);
-  const double ibl = inv_log_mean<double>(a.beta, b.beta, a.lbeta, b.lbeta);
-  const double S = a.beta + b.beta;
-  const double iS = 1.0 / S;
-  const double phat = 0.5 * (a.rho + b.rho) * iS;
+  const double sr = a.rho + b.rho, isr = rcp_nr(sr);
+  const double S = a.beta + b.beta, iS = rcp_nr(S);
+  double rho_ln, rdx, rdy, rdlx, rdly, ibl, bdx, bdy, bdlx, bdly;
+  log_mean_d(a.rho, b.rho, a.lrho, b.lrho, sr, isr, rho_ln, rdx, rdy, rdlx, rdly);
+  inv_log_mean_d(a.beta, b.beta, a.lbeta, b.lbeta, S, iS, ibl, bdx, bdy, bdlx, bdly);
+  const double phat = 0.5 * sr * iS;
   const double X = ibl * c1 - 0.25 * (a.k + b.k);
   const double um[3] = {0.5 * (a.u[0] + b.u[0]), 0.5 * (a.u[1] + b.u[1]), 0.5 * (a.u[2] + b.u[2])};
   const double umn = um[0] * n[0] + um[1] * n[1] + um[2] * n[2];
@@ -705,32 +677,29 @@ __host__ __device__ inline void chandrashekar_vjp_ab(const Aux& a, const Aux& b,
   const double iblb = c1 * Xb;
   aa.k = bb.k = -0.25 * Xb;
   const double rho_p = 0.5 * phatb * iS, beta_p = -phatb * phat * iS;
-  double dx, dlx, dy, dly;
-  log_mean_grad2(a.rho, b.rho, a.lrho, b.lrho, dx, dlx, dy, dly);
-  aa.rho = rho_p + rlnb * dx;
-  bb.rho = rho_p + rlnb * dy;
-  aa.lrho = rlnb * dlx;
-  bb.lrho = rlnb * dly;
-  inv_log_mean_grad2(a.beta, b.beta, a.lbeta, b.lbeta, dx, dlx, dy, dly);
-  aa.beta = beta_p + iblb * dx;
-  bb.beta = beta_p + iblb * dy;
-  aa.lbeta = iblb * dlx;
-  bb.lbeta = iblb * dly;
+  aa.rho = rho_p + rlnb * rdx;
+  bb.rho = rho_p + rlnb * rdy;
+  aa.lrho = rlnb * rdlx;
+  bb.lrho = rlnb * rdly;
+  aa.beta = beta_p + iblb * bdx;
+  bb.beta = beta_p + iblb * bdy;
+  aa.lbeta = iblb * bdlx;
+  bb.lbeta = iblb * bdly;
 }
 
 // d(w . F#(a, b; n))/d aux_a for Chandrashekar's flux (FP64 forward).
 __host__ __device__ inline void chandrashekar_vjp_a(const Aux& a, const Aux& b, const double n[3], double c1,
                                                     const double w[5], AuxBar& ab) {
-  const double rho_ln = log_mean<double>(a.rho, b.rho, a.lrho, b.lrho);
-  const double ibl = inv_log_mean<double>(a.beta, b.beta, a.lbeta, b.lbeta);
-  const double S = a.beta + b.beta;
-  const double phat = 0.5 * (a.rho + b.rho) / S;
+  const double sr = a.rho + b.rho, isr = rcp_nr(sr);
+  const double S = a.beta + b.beta, iS = rcp_nr(S);
+  double rho_ln, rdx, rdy, rdlx, rdly, ibl, bdx, bdy, bdlx, bdly;
+  log_mean_d(a.rho, b.rho, a.lrho, b.lrho, sr, isr, rho_ln, rdx, rdy, rdlx, rdly);
+  inv_log_mean_d(a.beta, b.beta, a.lbeta, b.lbeta, S, iS, ibl, bdx, bdy, bdlx, bdly);
+  const double phat = 0.5 * sr * iS;
   const double X = ibl * c1 - 0.25 * (a.k + b.k);
   const double um[3] = {0.5 * (a.u[0] + b.u[0]), 0.5 * (a.u[1] + b.u[1]), 0.5 * (a.u[2] + b.u[2])};
   const double umn = um[0] * n[0] + um[1] * n[1] + um[2] * n[2];
   const double Fr = rho_ln * umn;
-  double Fm[3];
-  for (int d = 0; d < 3; ++d) Fm[d] = phat * n[d] + um[d] * Fr;
   // reverse sweep
   double Fmb[3];
   for (int d = 0; d < 3; ++d) Fmb[d] = w[1 + d] + w[4] * um[d];
@@ -739,20 +708,16 @@ __host__ __device__ inline void chandrashekar_vjp_a(const Aux& a, const Aux& b, 
   const double phatb = Fmb[0] * n[0] + Fmb[1] * n[1] + Fmb[2] * n[2];
   const double rlnb = Frb * umn;
   const double umnb = Frb * rho_ln;
-  double umb[3];
-  for (int d = 0; d < 3; ++d) umb[d] = w[4] * Fm[d] + Fmb[d] * Fr + umnb * n[d];
-  for (int d = 0; d < 3; ++d) ab.u[d] = 0.5 * umb[d];
+  for (int d = 0; d < 3; ++d) {
+    const double Fm = phat * n[d] + um[d] * Fr;
+    ab.u[d] = 0.5 * (w[4] * Fm + Fmb[d] * Fr + umnb * n[d]);
+  }
   const double iblb = c1 * Xb;
   ab.k = -0.25 * Xb;
-  ab.rho = 0.5 * phatb / S;
-  ab.beta = -phatb * phat / S;
-  double dx, dlx;
-  log_mean_grad(a.rho, b.rho, a.lrho, b.lrho, dx, dlx);
-  ab.rho += rlnb * dx;
-  ab.lrho = rlnb * dlx;
-  inv_log_mean_grad(a.beta, b.beta, a.lbeta, b.lbeta, dx, dlx);
-  ab.beta += iblb * dx;
-  ab.lbeta = iblb * dlx;
+  ab.rho = 0.5 * phatb * iS + rlnb * rdx;
+  ab.lrho = rlnb * rdlx;
+  ab.beta = -phatb * phat * iS + iblb * bdx;
+  ab.lbeta = iblb * bdlx;
 }
 
 // d(w . f(U).n)/dU for the advective flux in direction n (FP64 forward).
