@@ -479,6 +479,8 @@ def main():
         s32.close()
         del s32
     del final64
+    # (the forward context is done: its workspace goes back to the checkpoints of the adjoint)
+    s.close()
     torch.cuda.empty_cache()
     _log("adjoint" if not args.no_adjoint else "adjoint skipped")
     # the adjoint covers every FP64 DG configuration (not FV sub-cells)
@@ -489,26 +491,29 @@ def main():
         _log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(args, cfg, mesh, U_host, pid64)
     print(json.dumps(result), flush=True)
-    s.close()
 
 
 def adjoint_cost(cfg, mesh, dev, U0, dt, args):
     """Backward (reverse sweep with recomputation) over forward time of the
     gradient of E_k(T) through args.adjoint_steps steps of the same workload."""
     import torch
-    from paper_2605_28627_amd.autograd import checkpoint_interval, kinetic_energy, trajectory
+    from paper_2605_28627_amd.autograd import checkpoint_plan, kinetic_energy, trajectory
     from paper_2605_28627_amd.solver import DGSolver
     sa = DGSolver(cfg, mesh, dev, adjoint=True)
     n = args.adjoint_steps
-    every = args.checkpoint_every or checkpoint_interval(sa, n)
+    if args.checkpoint_every:
+        every, keep = args.checkpoint_every, args.checkpoint_every - 1
+    else:
+        every, keep = checkpoint_plan(sa, n)
     times = []
     # a 2-step trajectory loads and warms the adjoint kernels; the 50-step one is timed
-    for rep, (ns, ev) in enumerate(((min(2, n), 1), (n, every))):
-        _log("adjoint", "warm-up:" if rep == 0 else "timed:", ns, "steps, checkpoints every", ev)
+    for rep, (ns, ev, kp) in enumerate(((min(2, n), 2, 1), (n, every, keep))):
+        _log("adjoint", "warm-up:" if rep == 0 else "timed:", ns, "steps, checkpoints every", ev,
+             "stage states kept for", kp, "steps per segment")
         U = U0.clone().requires_grad_(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        J = kinetic_energy(sa, trajectory(sa, U, dt, ns, checkpoint_every=ev))
+        J = kinetic_energy(sa, trajectory(sa, U, dt, ns, checkpoint_every=ev, keep_stages=kp))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         J.backward()
@@ -518,8 +523,10 @@ def adjoint_cost(cfg, mesh, dev, U0, dt, args):
         del U, J
     sa.close()
     tf, tb = times[-1]
-    return {"value": tb / tf, "steps": n, "checkpoint_every": every, "forward_s": tf, "backward_s": tb,
-            "note": "backward includes the recomputation of step and stage states"}
+    return {"value": tb / tf, "steps": n, "checkpoint_every": every, "stage_states_kept_per_segment": keep,
+            "forward_s": tf, "backward_s": tb,
+            "note": "backward includes the recomputation of the step states from checkpoints, keeping their stage "
+                    "states (the last step of each segment recomputes its own)"}
 
 
 def host_info():

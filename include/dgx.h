@@ -208,6 +208,14 @@ dg_status dg_lift(dg_ctx* ctx, const double* U, double* g, void* stream);
  * (device, state length); it is zeroed by the call before the first stage. */
 dg_status dg_rk_step(dg_ctx* ctx, double* U, double* dU, double t, double dt, int nsteps, void* stream);
 
+/* One step of dg_rk_step (same arithmetic) that also keeps its stage inputs
+ * Y_1..Y_{S-1} in Y (device, caller-owned, S-1 state lengths, stage k at
+ * Y + (k-1) * state length; S = 5 or 14) for dg_adjoint_rk_step_stages, which
+ * then skips recomputing them (not in the paper: a memory-for-time trade of
+ * the discrete adjoint).  U, dU and Y must not alias.  DG_ERR_UNSUPPORTED for
+ * contexts with FV sub-cells. */
+dg_status dg_rk_step_stages(dg_ctx* ctx, double* U, double* dU, double t, double dt, double* Y, void* stream);
+
 /* dg_rk_step for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation): the
  * same steps, with the scratch in a static device array of the library
@@ -246,6 +254,11 @@ dg_status dg_adjoint_rhs(dg_ctx* ctx, const double* U, const double* lam, double
  * Needs a workspace of dg_workspace_bytes_adjoint bytes. */
 dg_status dg_adjoint_rk_step(dg_ctx* ctx, const double* Un, double* lamU, double* lamdU, double t, double dt,
                              void* stream);
+
+/* dg_adjoint_rk_step with the step's stage inputs Y_1..Y_{S-1} supplied (as
+ * dg_rk_step_stages leaves them in Y) instead of recomputed from Un. */
+dg_status dg_adjoint_rk_step_stages(dg_ctx* ctx, const double* Un, const double* Y, double* lamU, double* lamdU,
+                                    double t, double dt, void* stream);
 
 /* Functionals and checks ------------------------------------------------------ */
 

@@ -978,6 +978,38 @@ dg_status dg_rk_step(dg_ctx* c, double* U, double* dU, double t, double dt, int 
   return DG_OK;
 }
 
+dg_status dg_rk_step_stages(dg_ctx* c, double* U, double* dU, double t, double dt, double* Y, void* stream) {
+  dg_status st = ready(c, "dg_rk_step_stages");
+  if (st != DG_OK) return st;
+  if (!U || !dU || !Y) return fail(c, DG_ERR_ARG, "dg_rk_step_stages: null pointer");
+  if (U == dU || Y == U || Y == dU) return fail(c, DG_ERR_ARG, "dg_rk_step_stages: aliasing arrays");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, DG_ERR_ARG, "dg_rk_step_stages: dt");
+  if (c->cfg.fv) return fail(c, DG_ERR_UNSUPPORTED, "dg_rk_step_stages: contexts with FV sub-cells are not covered");
+  (void)t;
+  hipStream_t s = (hipStream_t)stream;
+  double A[DG_RK_MAX_STAGES], B[DG_RK_MAX_STAGES];
+  const int ns = rk_scheme(c, A, B);
+  Work w = kwork(c);
+  const size_t n = (size_t)5 * c->nElems * c->n3;
+  {
+    ProfScope ps(c, FAM_OTHER, s);
+    LAUNCHCHK(c, launch_fill(dU, n, 0.0, s));
+  }
+  st = traces(c, U, w.Utr[0], s);
+  if (st != DG_OK) return st;
+  // stage k reads its input (U, then Y_k) and writes the next stage's input
+  // (Y_{k+1}, the last one U): the same arithmetic as in place
+  int cur = 0;
+  for (int k = 0; k < ns; ++k) {
+    const double* in = k == 0 ? U : Y + (size_t)(k - 1) * n;
+    double* outp = k == ns - 1 ? U : Y + (size_t)k * n;
+    st = stage(c, 1, in, nullptr, outp, dU, cur, A[k], B[k], dt, s);
+    if (st != DG_OK) return st;
+    cur ^= 1;
+  }
+  return DG_OK;
+}
+
 dg_status dg_rk_step_noalloc(dg_ctx* c, double* U, double* dU, double t, double dt, int nsteps, void* stream) {
   if (!c) return fail(nullptr, DG_ERR_ARG, "dg_rk_step_noalloc: null context");
   if (!c->mesh_on_device) return fail(c, DG_ERR_STATE, "dg_rk_step_noalloc: no mesh uploaded");
@@ -1046,13 +1078,41 @@ dg_status dg_adjoint_rhs(dg_ctx* c, const double* U, const double* lam, double* 
   return adjoint_residual(c, U, lam, out, (hipStream_t)stream);
 }
 
+// Reverse sweep of one RK step over the stage inputs Y[0..S-1]:
+// lamdU = B_{S-1} lamU; per stage s: lamU += dt J(Y_s)^T lamdU; lamdU = A_s lamdU + B_{s-1} lamU.
+static dg_status reverse_sweep(dg_ctx* c, const double* const* Y, double* lamU, double* lamdU, double dt,
+                               hipStream_t s) {
+  double A[DG_RK_MAX_STAGES], B[DG_RK_MAX_STAGES];
+  const int ns = rk_scheme(c, A, B);
+  const size_t n = (size_t)5 * c->nElems * c->n3;
+  double* aout = (double*)(c->ws + ws_layout(c).aout);
+  {
+    ProfScope ps(c, FAM_OTHER, s);
+    LAUNCHCHK(c, launch_scale_copy(n, lamU, lamdU, B[ns - 1], s));
+  }
+  // (the update is fused into the stage's last adjoint kernel)
+  for (int k = ns - 1; k >= 0; --k) {
+    const AdjUpd up{lamU, lamdU, dt, A[k], k > 0 ? B[k - 1] : 0.0};
+    dg_status st = adjoint_residual(c, Y[k], lamdU, aout, s, up);
+    if (st != DG_OK) return st;
+  }
+  return DG_OK;
+}
+
+static dg_status adjoint_step_checks(dg_ctx* c, const char* who, const double* Un, double* lamU, double* lamdU,
+                                     double dt) {
+  dg_status st = ready_adjoint(c, who);
+  if (st != DG_OK) return st;
+  if (!Un || !lamU || !lamdU) return fail(c, DG_ERR_ARG, std::string(who) + ": null pointer");
+  if (lamU == lamdU || Un == lamU || Un == lamdU) return fail(c, DG_ERR_ARG, std::string(who) + ": aliasing arrays");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, DG_ERR_ARG, std::string(who) + ": dt");
+  return DG_OK;
+}
+
 dg_status dg_adjoint_rk_step(dg_ctx* c, const double* Un, double* lamU, double* lamdU, double t, double dt,
                              void* stream) {
-  dg_status st = ready_adjoint(c, "dg_adjoint_rk_step");
+  dg_status st = adjoint_step_checks(c, "dg_adjoint_rk_step", Un, lamU, lamdU, dt);
   if (st != DG_OK) return st;
-  if (!Un || !lamU || !lamdU) return fail(c, DG_ERR_ARG, "dg_adjoint_rk_step: null pointer");
-  if (lamU == lamdU || Un == lamU || Un == lamdU) return fail(c, DG_ERR_ARG, "dg_adjoint_rk_step: aliasing arrays");
-  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, DG_ERR_ARG, "dg_adjoint_rk_step: dt");
   (void)t;
   hipStream_t s = (hipStream_t)stream;
   double A[DG_RK_MAX_STAGES], B[DG_RK_MAX_STAGES];
@@ -1064,7 +1124,6 @@ dg_status dg_adjoint_rk_step(dg_ctx* c, const double* Un, double* lamU, double* 
   Y[0] = Un;
   for (int k = 0; k + 1 < ns; ++k) Y[k + 1] = (const double*)(c->ws + L.Y[k]);
   double* dUf = (double*)(c->ws + L.dUf);
-  double* aout = (double*)(c->ws + L.aout);
   // recompute the stage inputs Y_1..Y_{S-1} of this step
   {
     ProfScope ps(c, FAM_OTHER, s);
@@ -1080,18 +1139,23 @@ dg_status dg_adjoint_rk_step(dg_ctx* c, const double* Un, double* lamU, double* 
     if (st != DG_OK) return st;
     cur ^= 1;
   }
-  // reverse sweep: lamdU = B_{S-1} lamU; per stage s: lamU += dt J(Y_s)^T lamdU; lamdU = A_s lamdU + B_{s-1} lamU
-  {
-    ProfScope ps(c, FAM_OTHER, s);
-    LAUNCHCHK(c, launch_scale_copy(n, lamU, lamdU, B[ns - 1], s));
-  }
-  // (the update is fused into the stage's last adjoint kernel)
-  for (int k = ns - 1; k >= 0; --k) {
-    const AdjUpd up{lamU, lamdU, dt, A[k], k > 0 ? B[k - 1] : 0.0};
-    st = adjoint_residual(c, Y[k], lamdU, aout, s, up);
-    if (st != DG_OK) return st;
-  }
-  return DG_OK;
+  return reverse_sweep(c, Y, lamU, lamdU, dt, s);
+}
+
+dg_status dg_adjoint_rk_step_stages(dg_ctx* c, const double* Un, const double* Ystages, double* lamU, double* lamdU,
+                                    double t, double dt, void* stream) {
+  dg_status st = adjoint_step_checks(c, "dg_adjoint_rk_step_stages", Un, lamU, lamdU, dt);
+  if (st != DG_OK) return st;
+  if (!Ystages) return fail(c, DG_ERR_ARG, "dg_adjoint_rk_step_stages: null pointer");
+  if (Ystages == lamU || Ystages == lamdU) return fail(c, DG_ERR_ARG, "dg_adjoint_rk_step_stages: aliasing arrays");
+  (void)t;
+  double A[DG_RK_MAX_STAGES], B[DG_RK_MAX_STAGES];
+  const int ns = rk_scheme(c, A, B);
+  const size_t n = (size_t)5 * c->nElems * c->n3;
+  const double* Y[DG_RK_MAX_STAGES];
+  Y[0] = Un;
+  for (int k = 0; k + 1 < ns; ++k) Y[k + 1] = Ystages + (size_t)k * n;
+  return reverse_sweep(c, Y, lamU, lamdU, dt, (hipStream_t)stream);
 }
 
 dg_status dg_kinetic_energy(dg_ctx* c, const double* U, double rho0U0sq, double* out_dev, void* stream) {

@@ -37,7 +37,8 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_MESH", 3: "DG_ERR_HIP", 
 # public symbols of include/dgx.h
 SYMBOLS = ["dg_create", "dg_destroy", "dg_set_reference_state", "dg_last_error", "dg_lserk_coefficients", "dg_rk_coefficients", "dg_set_mesh", "dg_upload_mesh",
            "dg_upload_metrics", "dg_get_metrics", "dg_node_coords", "dg_sizes", "dg_workspace_bytes",
-           "dg_workspace_bytes_adjoint", "dg_bind_workspace", "dg_init_state", "dg_rhs", "dg_lift", "dg_rk_step", "dg_rk_step_noalloc", "dg_adjoint_rhs", "dg_adjoint_rk_step",
+           "dg_workspace_bytes_adjoint", "dg_bind_workspace", "dg_init_state", "dg_rhs", "dg_lift", "dg_rk_step", "dg_rk_step_noalloc", "dg_rk_step_stages", "dg_adjoint_rhs", "dg_adjoint_rk_step",
+           "dg_adjoint_rk_step_stages",
            "dg_kinetic_energy", "dg_kinetic_energy_grad", "dg_timestep", "dg_check_state", "dg_profile",
            "dg_profile_families", "dg_profile_query", "dg_fv_switch", "dg_fv_indicator", "dg_fv_switch_by_indicator", "dg_fv_mask"]
 
@@ -82,6 +83,8 @@ _sig = {
     "dg_rk_step_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _vp]),
     "dg_adjoint_rhs": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "dg_adjoint_rk_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp]),
+    "dg_rk_step_stages": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]),
+    "dg_adjoint_rk_step_stages": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp]),
     "dg_kinetic_energy": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _vp]),
     "dg_kinetic_energy_grad": (ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]),
     "dg_timestep": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _dp, _vp]),
@@ -284,6 +287,19 @@ def dg_adjoint_rk_step(ctx, Un, lamU, lamdU, t, dt, stream=None):
     n = dg_sizes(ctx)[3]
     _check(ctx, _L.dg_adjoint_rk_step(ctx, _dev(Un, n, "Un"), _dev(lamU, n, "lamU"), _dev(lamdU, n, "lamdU"),
                                       float(t), float(dt), _stream(stream)))
+
+
+def dg_rk_step_stages(ctx, U, dU, t, dt, Y, nstages, stream=None):
+    n = dg_sizes(ctx)[3]
+    _check(ctx, _L.dg_rk_step_stages(ctx, _dev(U, n, "U"), _dev(dU, n, "dU"), float(t), float(dt),
+                                     _dev(Y, (nstages - 1) * n, "Y"), _stream(stream)))
+
+
+def dg_adjoint_rk_step_stages(ctx, Un, Y, lamU, lamdU, t, dt, nstages, stream=None):
+    n = dg_sizes(ctx)[3]
+    _check(ctx, _L.dg_adjoint_rk_step_stages(ctx, _dev(Un, n, "Un"), _dev(Y, (nstages - 1) * n, "Y"),
+                                             _dev(lamU, n, "lamU"), _dev(lamdU, n, "lamdU"), float(t), float(dt),
+                                             _stream(stream)))
 
 
 def dg_kinetic_energy(ctx, U, out, rho0U0sq=1.0, stream=None):

@@ -119,6 +119,21 @@ class DGSolver:
     def rk_step(self, U: torch.Tensor, dU: torch.Tensor, dt: float, nsteps: int = 1, t: float = 0.0):
         dgx.dg_rk_step(self.ctx, U, dU, t, dt, nsteps)
 
+    @property
+    def rk_stages(self) -> int:
+        return len(dgx.dg_rk_coefficients(self.cfg.get("integrator", 0))[0])
+
+    def stage_buffer(self) -> torch.Tensor:
+        """Device buffer for the S-1 stage inputs of one step (rk_step_stages)."""
+        return torch.empty((self.rk_stages - 1,) + self.state_shape, dtype=torch.float64, device=self.device)
+
+    def rk_step_stages(self, U: torch.Tensor, dU: torch.Tensor, dt: float, Y: torch.Tensor, t: float = 0.0):
+        dgx.dg_rk_step_stages(self.ctx, U, dU, t, dt, Y, self.rk_stages)
+
+    def adjoint_rk_step_stages(self, Un: torch.Tensor, Y: torch.Tensor, lamU: torch.Tensor, lamdU: torch.Tensor,
+                               dt: float, t: float = 0.0):
+        dgx.dg_adjoint_rk_step_stages(self.ctx, Un, Y, lamU, lamdU, t, dt, self.rk_stages)
+
     def adjoint_rhs(self, U: torch.Tensor, lam: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         out = self.empty_state() if out is None else out
         dgx.dg_adjoint_rhs(self.ctx, U, lam, out)

@@ -128,6 +128,28 @@ def test_adjoint_rk_step(S, orc, case, ):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("case,integrator", [(CASES[5], 0), (CASES[8], 0), (CASES[0], 1)], ids=str)
+def test_stored_stages_match_recomputed(S, orc, case, integrator):
+    """dg_rk_step_stages advances U exactly as dg_rk_step does and keeps the
+    stage inputs; the reverse step over those equals the one that recomputes
+    them, bit for bit."""
+    import torch
+    o, s = _pair(S, orc, case, integrator=integrator)
+    U = s.to_device(I.smooth_random_state(o.coords(), 65, amp=0.1))
+    dt = s.timestep(U, 0.5)
+    U1, U2 = U.clone(), U.clone()
+    s.rk_step(U1, torch.empty_like(U), dt, 1)
+    Y = s.stage_buffer()
+    s.rk_step_stages(U2, torch.empty_like(U), dt, Y)
+    assert torch.equal(U1, U2)
+    lam = torch.randn_like(U)
+    la, lb = lam.clone(), lam.clone()
+    s.adjoint_rk_step(U, la, torch.empty_like(U), dt)
+    s.adjoint_rk_step_stages(U, Y, lb, torch.empty_like(U), dt)
+    _say(case, integrator, "stored vs recomputed stages, max |diff|", float((la - lb).abs().max()))
+    assert torch.equal(la, lb)
+
+
 @pytest.mark.parametrize("case", [CASES[0], CASES[6]], ids=str)
 def test_adjoint_rk14_step(S, orc, case):
     """Reverse of one LSERK4-14 step (13 recomputed stage states) against the
@@ -201,8 +223,11 @@ def test_adjoint_roe_full_transpose(S, orc):
     assert err < 1e-12
 
 
-@pytest.mark.parametrize("case", [(3, 1, 1, 0, 0.0, None), (3, 1, 1, 1, 0.1, 2)], ids=str)
-def test_trajectory_gradient_vs_oracle(S, orc, case):
+@pytest.mark.parametrize("case,keep", [((3, 1, 1, 0, 0.0, None), 2), ((3, 1, 1, 1, 0.1, 2), 1),
+                                       ((3, 1, 1, 1, 0.1, 2), 0)], ids=str)
+def test_trajectory_gradient_vs_oracle(S, orc, case, keep):
+    """Segments of 3 steps keeping the stage states of all (2), one or none of
+    their recomputed steps."""
     import torch
     from paper_2605_28627_amd.autograd import kinetic_energy, trajectory
     o, s = _pair(S, orc, case)
@@ -213,7 +238,7 @@ def test_trajectory_gradient_vs_oracle(S, orc, case):
     dt = o.timestep(U0, 0.9)
     nsteps = 7
     U0g = s.to_device(U0).requires_grad_(True)
-    J = kinetic_energy(s, trajectory(s, U0g, dt, nsteps, checkpoint_every=3))
+    J = kinetic_energy(s, trajectory(s, U0g, dt, nsteps, checkpoint_every=3, keep_stages=keep))
     J.backward()
     grad = U0g.grad.cpu().numpy()
     UT = o.lserk(U0, nsteps, dt)
@@ -225,7 +250,7 @@ def test_trajectory_gradient_vs_oracle(S, orc, case):
         UT2, dT = o.lserk_jvp(U0, d, nsteps, dt)
         ref = o.kinetic_energy_jvp(UT2, dT)
         worst = max(worst, abs((grad * d).sum() - ref) / abs(ref))
-    _say(case, "trajectory gradient vs oracle tangent", worst)
+    _say(case, keep, "trajectory gradient vs oracle tangent", worst)
     assert worst < 1e-10
 
 
