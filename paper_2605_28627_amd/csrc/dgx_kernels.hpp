@@ -591,6 +591,12 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
 #ifndef DGX_SYMMETRIC_PAIRS
 #define DGX_SYMMETRIC_PAIRS 1
 #endif
+// Symmetric evaluation of the pairs on the zeta lines of an N = 7 element
+// (they cross its eight wavefronts) with the partner shares exchanged
+// through LDS; 0 evaluates every ordered pair there.
+#ifndef DGX_ZETA_EXCHANGE
+#define DGX_ZETA_EXCHANGE 1
+#endif
 
 // Waves per SIMD the residual kernel is compiled for (its register budget):
 // 4 for elements of 512 work-items; 3 for the N = 3 Gauss split form (one
@@ -635,7 +641,9 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   // Gauss-node split form: the line sums of the face coupling go through LDS
   // (10 values per node) unless every line lies inside a wavefront
   constexpr bool kEsAllShfl = kSymLines && n1 == 4;
-  constexpr int SZ_SPLIT = (8 + 3 + (ES && !kEsAllShfl ? 10 : 0)) * n3;   // aux + Ja^r (+ face coupling)
+  // the two-point record of every node (7 values; |u|^2 is recomputed from u)
+  constexpr int kAuxV = 7;
+  constexpr int SZ_SPLIT = (kAuxV + 3 + (ES && !kEsAllShfl ? 10 : 0)) * n3;   // aux + Ja^r (+ face coupling)
   constexpr int SZ_WEAK = 5 * n3;                                    // F~^r
   constexpr int SZ_V = FORM == 1 ? SZ_SPLIT : SZ_WEAK;
   constexpr int SZ0 = SZ_V > 5 * n3 ? SZ_V : 5 * n3;                 // also holds the new state (Gauss traces)
@@ -648,8 +656,11 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   // together with the two-point records of the own projected face states.
   // (FV contexts of the Gauss split form keep all six slots)
   constexpr int kFaces = ES && !FV ? kEsFaceSlots : 6;
+  // Lobatto split form at N = 7: symmetric zeta pairs, partner shares through sx
+  constexpr bool kZetaX = DGX_ZETA_EXCHANGE && FORM == 1 && !ES && n1 == 8 && S::nth == n3;
   __shared__ double sphi[5 * kFaces * n2];
   __shared__ double sm[SZ];
+  __shared__ double sx[kZetaX ? 5 * n3 : 1];
   __shared__ double saf[ES ? 8 * kFaces * n2 : 1];
   __shared__ VolBasis<N, FV != 0> sb;
   const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
@@ -823,7 +834,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
     if (act) {
       me = make_aux(q);
       sm[0 * n3 + t] = me.rho; sm[1 * n3 + t] = me.u[0]; sm[2 * n3 + t] = me.u[1]; sm[3 * n3 + t] = me.u[2];
-      sm[4 * n3 + t] = me.beta; sm[5 * n3 + t] = me.lrho; sm[6 * n3 + t] = me.lbeta; sm[7 * n3 + t] = me.k;
+      sm[4 * n3 + t] = me.beta; sm[5 * n3 + t] = me.lrho; sm[6 * n3 + t] = me.lbeta;
     }
   }
   // 3. volume integral, one reference direction at a time (unrolled: the
@@ -838,7 +849,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
       }
     }
     if constexpr (FORM == 1) {
-      double* sja = sm + 8 * n3;
+      double* sja = sm + kAuxV * n3;
       if constexpr (ES) {
         // the faces whose flux is formed in this pass: 0..3 in the first, 4, 5 in the last
         constexpr int fa[3] = {0, 6, 4}, fb[3] = {4, 6, 6};
@@ -879,7 +890,8 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           Aux ot;
           ot.rho = sm[0 * n3 + tl]; ot.u[0] = sm[1 * n3 + tl]; ot.u[1] = sm[2 * n3 + tl];
           ot.u[2] = sm[3 * n3 + tl]; ot.beta = sm[4 * n3 + tl]; ot.lrho = sm[5 * n3 + tl];
-          ot.lbeta = sm[6 * n3 + tl]; ot.k = sm[7 * n3 + tl];
+          ot.lbeta = sm[6 * n3 + tl];
+          ot.k = ot.u[0] * ot.u[0] + ot.u[1] * ot.u[1] + ot.u[2] * ot.u[2];
           const double nv[3] = {0.5 * (jr[0] + sja[0 * n3 + tl]), 0.5 * (jr[1] + sja[1 * n3 + tl]),
                                 0.5 * (jr[2] + sja[2 * n3 + tl])};
           two_point(ot, nv, F);
@@ -908,6 +920,30 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
               for (int v = 0; v < 5; ++v) acc[v] += __shfl(-dba * F[v], src);
             }
           }
+        } else if (kZetaX && r == 2) {
+          // The zeta line crosses the element's waves: the pair (a, a+d) is
+          // evaluated once, by the node of a, which hands -DS[a+d][a] F to
+          // the node of a+d through sx (every node of the block takes part:
+          // the element fills it).  Distance n1/2 is met from both ends.
+#pragma unroll 1
+          for (int d = 1; d <= n1 / 2; ++d) {
+            const int b = (a + d) & (n1 - 1);
+            const int tb = line_node<N>(r, b, pp, qq);
+            double F[5];
+            pair_flux(tb, F);
+            const double dab = sb.DS[a * n1 + b];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) acc[v] -= dab * F[v];
+            if (d < n1 / 2) {
+              const double dba = sb.DS[b * n1 + a];
+#pragma unroll
+              for (int v = 0; v < 5; ++v) sx[v * n3 + tb] = -dba * F[v];
+              __syncthreads();
+#pragma unroll
+              for (int v = 0; v < 5; ++v) acc[v] += sx[v * n3 + t];
+              __syncthreads();
+            }
+          }
         } else {
           for (int l = 0; l < n1; ++l) {
             const int tl = line_node<N>(r, l, pp, qq);
@@ -925,7 +961,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           // interpolated to the end f of this line; l_f(a) G_f is staged for
           // the line sums S_f = sum_l l_f(l) G_f(l).
           // The surface term of this direction's two faces is applied here too.
-          double* shy = sm + 11 * n3;
+          double* shy = sm + (kAuxV + 3) * n3;
           const int rr = qq * n1 + pp;
 #pragma unroll
           for (int f = 0; f < 2; ++f) {
@@ -969,7 +1005,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
         // dU_a -= (1/w_a) B_f l_f(a) (G_f(a) - S_f),  B_f = -1 at xi = -1, +1 at xi = +1
         __syncthreads();
         if (act) {
-          const double* shy = sm + 11 * n3;
+          const double* shy = sm + (kAuxV + 3) * n3;
           const int a = idx[r];
           const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
 #pragma unroll
