@@ -9,7 +9,8 @@
 //             -sum_l J_A(m,l)^T (DS[m][l] lt_m + DS[l][m] lt_l), J_A the
 //             Jacobian of F#(U_m, U_l) in its first argument (F# is symmetric);
 //   lifting (Navier-Stokes): the gradient adjoint gb from the viscous terms
-//             flows back through g = lift(U) (k_adj_lift_trace/_volume).
+//             flows back through g = lift(U) (face values Qbar formed at the
+//             end of the volume adjoint, then k_adj_lift_volume).
 // The kinks (Rusanov's max, Roe's |.| and Harten-Hyman fix) are
 // differentiated on the branch the forward takes; Sutherland's law adds the
 // temperature dependence of mu and lambda.
@@ -22,33 +23,26 @@ namespace dgx {
 // Final value a of (dR/dU)^T lam at index gi: stored in out, or (up.lamU
 // set) the reverse LSERK update of the stage applied in place.  lam is
 // up.lamdU then; each index is read and written by its own work-item only.
-__device__ __forceinline__ void adj_store(const AdjUpd& up, double* out, size_t gi, double a) {
+__device__ __forceinline__ double adj_store(const AdjUpd& up, double* out, size_t gi, double a) {
   if (up.lamU) {
     const double lu = up.lamU[gi] + up.dt * a;
     up.lamU[gi] = lu;
-    up.lamdU[gi] = up.A * up.lamdU[gi] + up.Bnext * lu;
-  } else {
-    out[gi] = a;
+    const double ld = up.A * up.lamdU[gi] + up.Bnext * lu;
+    up.lamdU[gi] = ld;
+    return ld;
   }
+  out[gi] = a;
+  return a;
 }
 
-// Per-element surface adjoint t = -(1/w_a) l_a(+-1) (sJ lam)_a summed along the normal line.
+// Per-element surface adjoint t = -(1/w_a) l_a(+-1) (sJ lam)_a summed along
+// the normal line, from sl = sJ lam [5][n3] in LDS (the element's nodes).
 template <int N, int NODES>
-__global__ __launch_bounds__(Shape<N>::nth) void k_adj_trace(Geo G, const double* __restrict__ lam,
-                                                             double* __restrict__ Lbar) {
+__device__ inline void adj_surface_of(const Geo& G, const DevBasis& sb, const double* sl, int e, int t,
+                                      double* __restrict__ Lbar) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
-  __shared__ double sl[5 * n3];
-  __shared__ DevBasis sb;
-  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
-  const int nE = G.nElems, nS = G.nSides;
-  load_basis(&sb, G.basis, t, S::nth);
-  if (t < n3) {
-    const double sJ = G.sJ[(size_t)e * n3 + t];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) sl[v * n3 + t] = sJ * lam[((size_t)v * nE + e) * n3 + t];
-  }
-  __syncthreads();
+  const int nS = G.nSides;
   for (int ft = t; ft < S::nface; ft += S::nth) {
     const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
     const int info = G.efc[e * 6 + f];
@@ -71,13 +65,36 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_trace(Geo G, const double
   }
 }
 
+template <int N, int NODES>
+__global__ __launch_bounds__(Shape<N>::nth) void k_adj_trace(Geo G, const double* __restrict__ lam,
+                                                             double* __restrict__ Lbar) {
+  using S = Shape<N>;
+  constexpr int n3 = S::n3;
+  __shared__ double sl[5 * n3];
+  __shared__ DevBasis sb;
+  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
+  const int nE = G.nElems;
+  load_basis(&sb, G.basis, t, S::nth);
+  if (t < n3) {
+    const double sJ = G.sJ[(size_t)e * n3 + t];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sl[v * n3 + t] = sJ * lam[((size_t)v * nE + e) * n3 + t];
+  }
+  __syncthreads();
+  adj_surface_of<N, NODES>(G, sb, sl, e, t, Lbar);
+}
+
 // Volume and surface adjoint of the residual; Navier-Stokes also writes the
-// gradient adjoint gbar[12][e][node] (from the viscous volume and surface terms).
+// gradient adjoint gbar[12][e][node] (from the viscous volume and surface
+// terms) and the face part of the lifting adjoint,
+//   Qbar[slot][4][side][fi] = sum_a (1/w_a) l_a(+-1) sum_d (sJ gbar)_{q,d} (n s)_d,out
+// along each face node's normal line (element-local once gbar is known).
 //
 // Phases, so that live ranges do not stack:
 //   1. each side's flux adjoint (own part) -> LDS, accumulated by the nodes;
 //   2. the weak-form parts along every line (Euler weak form; the viscous
 //      volume term), after which gbar is written and the gradients are dead;
+//      (Navier-Stokes) sJ gbar -> LDS and the faces' Qbar;
 //   3. split form: per direction r the metric row -> LDS, then the pairs.
 //      The weight of the pair (m, l) is w = -(DS[m][l] lt_m + DS[l][m] lt_l)
 //      for both of its nodes, and F# is symmetric, so one reverse sweep of
@@ -104,7 +121,7 @@ template <int N, int NODES, int FORM, int PHYS, int ROE = 0, int VL = 0>
 __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVES : 1)) void k_adj_volume(
     Geo G, Phys P, const double* __restrict__ U, const double* lam, const double* __restrict__ Utr,
     const double* __restrict__ Lbar, const double* __restrict__ gin, const double* __restrict__ gtr,
-    double* __restrict__ out, double* __restrict__ gbar, AdjUpd up) {
+    double* __restrict__ out, double* __restrict__ gbar, double* __restrict__ Qbar, AdjUpd up) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
   constexpr bool ES = FORM == 1 && NODES == 0;
@@ -124,12 +141,46 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
   const bool act = t < n3;
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   const int idx[3] = {i, j, k};
+  const double sJ = act ? G.sJ[(size_t)e * n3 + t] : 0.0;
   if (act) {
-    const double sJ = G.sJ[(size_t)e * n3 + t];
 #pragma unroll
     for (int v = 0; v < 5; ++v) sl[v * n3 + t] = sJ * lam[((size_t)v * nE + e) * n3 + t];
   }
-  // 1. surface: adjoint of each side's flux, own trace part into LDS
+  // The node's own operands of phases 2 and 3: state, metric rows, lifted
+  // gradient.  In the LGL split form with one 512-work-item element per CU
+  // (N = 7) the registers hold them from the start, so that their latency
+  // overlaps the surface phase; elsewhere each is (re)loaded where it is
+  // used, which keeps the other kernels' occupancy and spill-free budgets.
+  constexpr bool kPrefetch = S::nth >= 512 && ROE == 0 && NODES == 1 && FORM == 1;
+  double un[5] = {0, 0, 0, 0, 0}, jn[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double gn[PHYS == 1 ? 12 : 1];
+#pragma unroll
+  for (int c = 0; c < (PHYS == 1 ? 12 : 1); ++c) gn[c] = 0.0;
+  auto load_u = [&]() {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) un[v] = U[((size_t)v * nE + e) * n3 + t];
+  };
+  auto load_row = [&](int r) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) jn[3 * r + c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
+  };
+  auto load_g = [&]() {
+    if constexpr (PHYS == 1) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) gn[c] = gin[((size_t)c * nE + e) * n3 + t];
+    }
+  };
+  if (kPrefetch && act) {
+    load_u();
+    load_row(0); load_row(1); load_row(2);
+    load_g();
+  }
+  // 1. surface: adjoint of each side's flux, own trace part into LDS.  When
+  // every face node has a work-item of its own, that work-item keeps the
+  // outward n s and the Qbar index of its face node for the lifting adjoint.
+  constexpr bool kOneFaceNode = S::nface <= S::nth;
+  double fno[3] = {0, 0, 0};
+  size_t fqi = 0;
   for (int ft = t; ft < S::nface; ft += S::nth) {
     const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1;
     const int info = G.efc[e * 6 + f];
@@ -155,6 +206,12 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
     const double nh[3] = {G.face[((size_t)0 * nS + side) * n2 + fi], G.face[((size_t)1 * nS + side) * n2 + fi],
                           G.face[((size_t)2 * nS + side) * n2 + fi]};
     const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
+    if constexpr (kOneFaceNode && PHYS == 1) {
+      const double sgn = slot ? -1.0 : 1.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) fno[c] = sgn * (nh[c] * s);
+      fqi = tr_index(slot, 0, 4, nS, side, n2, fi);
+    }
     double ULb[5], URb[5], gLb[12], gRb[12];
     surface_flux_vjp<FORM, PHYS, ROE, VL>(UL, UR, gL, gR, nh, s, P, Phib, ULb, URb, gLb, gRb);
     // (element-wise selects keep both sides' adjoints in registers)
@@ -204,16 +261,18 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
   // 2. weak-form parts: Lam^r = sum_a Dhat[a][l] lt_a along each line
   if (FORM == 0 || PHYS == 1) {
     if (act) {
-      double u[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+      if (!kPrefetch) {
+        load_u();
+        load_g();
+      }
+      const double* u = un;
       const Prim q = cons2prim(u, P.gm1);
       double ub[3] = {0, 0, 0}, rpb[2] = {0.0, 0.0};
-      double gl[PHYS == 1 ? 12 : 1];
-      if constexpr (PHYS == 1) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) gl[c] = gin[((size_t)c * nE + e) * n3 + t];
-      }
+      const double* gl = gn;
+      // constant viscosity: the three directions' viscous weights, summed into
+      // one flux-tensor adjoint (with Sutherland's law one per direction
+      // keeps fewer values live)
+      double Mv[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         const int l = idx[r];
@@ -226,15 +285,20 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
 #pragma unroll
           for (int v = 0; v < 5; ++v) Lam[v] += c * sl[v * n3 + ta];
         }
-        const double nv[3] = {G.Ja[((size_t)(3 * r) * nE + e) * n3 + t], G.Ja[((size_t)(3 * r + 1) * nE + e) * n3 + t],
-                              G.Ja[((size_t)(3 * r + 2) * nE + e) * n3 + t]};
+        if (!kPrefetch) load_row(r);
+        const double nv[3] = {jn[3 * r], jn[3 * r + 1], jn[3 * r + 2]};
         if constexpr (FORM == 0) {
           double Ue[5];
           euler_flux_vjp(u, q, nv, Lam, P.gm1, Ue);
 #pragma unroll
           for (int v = 0; v < 5; ++v) Ub[v] += Ue[v];
         }
-        if constexpr (PHYS == 1) {
+        if constexpr (PHYS == 1 && VL == 0) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Mv[d][v] -= nv[d] * Lam[1 + v];
+        } else if constexpr (PHYS == 1) {
           const double Gnb[4] = {-Lam[1], -Lam[2], -Lam[3], -Lam[4]};
           double gq[12], uq[3];
           viscous_flux_vjp<VL>(q, gl, P, nv, Gnb, gq, uq, rpb);
@@ -243,15 +307,70 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
           ub[0] += uq[0]; ub[1] += uq[1]; ub[2] += uq[2];
         }
       }
+      if constexpr (PHYS == 1 && VL == 0) {
+        double gq[12], uq[3];
+        viscous_tensor_vjp<VL>(q, gl, P, Mv, gq, uq, rpb);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gb[c] += gq[c];
+        ub[0] += uq[0]; ub[1] += uq[1]; ub[2] += uq[2];
+      }
       if constexpr (PHYS == 1) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) gbar[((size_t)c * nE + e) * n3 + t] = gb[c];
+        for (int c = 0; c < 12; ++c) {
+          gbar[((size_t)c * nE + e) * n3 + t] = gb[c];
+          sB[c * n3 + t] = sJ * gb[c];   // (the surface adjoints in sB are consumed)
+        }
         double Uu[5];
         prim_vjp(q, P.gm1, rpb[0], ub, rpb[1], Uu);
 #pragma unroll
         for (int v = 0; v < 5; ++v) Ub[v] += Uu[v];
       }
     }
+  }
+  if constexpr (PHYS == 1) {
+    // the lifting adjoint's face values of this element's faces
+    __syncthreads();
+    const double* sg = sB;
+    for (int ft = t; ft < S::nface; ft += S::nth) {
+      const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
+      double no[3];
+      size_t qi;
+      if constexpr (kOneFaceNode) {
+        no[0] = fno[0]; no[1] = fno[1]; no[2] = fno[2];
+        qi = fqi;
+      } else {
+        const int info = G.efc[e * 6 + f];
+        const int side = efc_side(info), slot = efc_slot(info);
+        int p = pp, qm = qq;
+        if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+        const int fi = qm * n1 + p;
+        const double sgn = slot ? -1.0 : 1.0;
+        const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) no[c] = sgn * (G.face[((size_t)c * nS + side) * n2 + fi] * s);
+        qi = tr_index(slot, 0, 4, nS, side, n2, fi);
+      }
+      double acc[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < n1; ++a) {
+        double L;
+        if constexpr (NODES == 1) {
+          if (a != ((f & 1) ? N : 0)) continue;
+          L = sb.winv[a];
+        } else {
+          L = sb.winv[a] * ((f & 1) ? sb.Lp[a] : sb.Lm[a]);
+        }
+        const int ta = line_node<N>(r, a, pp, qq);
+#pragma unroll
+        for (int qa = 0; qa < 4; ++qa)
+          acc[qa] += L * (sg[(3 * qa) * n3 + ta] * no[0] + sg[(3 * qa + 1) * n3 + ta] * no[1] +
+                          sg[(3 * qa + 2) * n3 + ta] * no[2]);
+      }
+      // (values qa of one face node are nS n2 apart in the [slot][4][side][fi] layout)
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa) Qbar[qi + (size_t)qa * nS * n2] = acc[qa];
+    }
+    __syncthreads();
   }
   // 3. split form: flux differencing adjoint
   if constexpr (FORM == 1) {
@@ -260,10 +379,8 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
     Aux me{};
     double lm[5] = {0, 0, 0, 0, 0};
     if (act) {
-      double u[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
-      me = make_aux(cons2prim(u, P.gm1));
+      if (!kPrefetch) load_u();
+      me = make_aux(cons2prim(un, P.gm1));
       saux[0 * n3 + t] = me.rho; saux[1 * n3 + t] = me.u[0]; saux[2 * n3 + t] = me.u[1];
       saux[3 * n3 + t] = me.u[2]; saux[4 * n3 + t] = me.beta; saux[5 * n3 + t] = me.lrho;
       saux[6 * n3 + t] = me.lbeta; saux[7 * n3 + t] = me.k;
@@ -278,7 +395,8 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
       if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          jr[c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
+          if (!kPrefetch) jn[3 * r + c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
+          jr[c] = jn[3 * r + c];
           sja[c * n3 + t] = jr[c];
         }
       }
@@ -337,10 +455,9 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
               ab.rho += d.rho; ab.u[0] += d.u[0]; ab.u[1] += d.u[1]; ab.u[2] += d.u[2];
               ab.beta += d.beta; ab.lrho += d.lrho; ab.lbeta += d.lbeta; ab.k += d.k;
             } else {
-              // central average: d/dU_m of 1/2 f(U_m).n (own state re-read from cache)
-              double u[5];
-#pragma unroll
-              for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+              // central average: d/dU_m of 1/2 f(U_m).n
+              if (!kPrefetch) load_u();
+              const double* u = un;
               const double wh[5] = {0.5 * w[0], 0.5 * w[1], 0.5 * w[2], 0.5 * w[3], 0.5 * w[4]};
               double Ue[5];
               euler_flux_vjp(u, cons2prim(u, P.gm1), nv, wh, P.gm1, Ue);
@@ -388,9 +505,8 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
               ab.beta += da.beta; ab.lrho += da.lrho; ab.lbeta += da.lbeta; ab.k += da.k;
               aux_vjp(qf, af, dfb, P.gm1, Uf);
             } else {
-              double u[5];
-#pragma unroll
-              for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+              if (!kPrefetch) load_u();
+              const double* u = un;
               const double wh[5] = {0.5 * om[0], 0.5 * om[1], 0.5 * om[2], 0.5 * om[3], 0.5 * om[4]};
               double Ue[5];
               euler_flux_vjp(u, cons2prim(u, P.gm1), nv, wh, P.gm1, Ue);
@@ -420,9 +536,8 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
       }
     }
     if (act && P.twopoint == 0) {
-      double u[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+      if (!kPrefetch) load_u();
+      const double* u = un;
       const Prim q = cons2prim(u, P.gm1);
       double Ua[5];
       aux_vjp(q, me, ab, P.gm1, Ua);
@@ -465,65 +580,14 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
           for (int v = 0; v < 5; ++v) vb[v] += L * sub[((2 * r + f) * 5 + v) * n2 + rr];
         }
       }
-      double u[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
+      if (!kPrefetch) load_u();
+      const double* u = un;
       entropy_vars_vjp(u, P.gm1, vb, Ub);
     }
   }
   if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) adj_store(up, out, ((size_t)v * nE + e) * n3 + t, Ub[v]);
-  }
-}
-
-// Lifting adjoint, face part: Qbar[slot][4][side][fi] = sum_a (1/w_a) l_a(+-1) sum_d (sJ gbar)_{q,d} (n s)_d,out.
-template <int N, int NODES>
-__global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_trace(Geo G, const double* __restrict__ gbar,
-                                                                  double* __restrict__ Qbar) {
-  using S = Shape<N>;
-  constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
-  __shared__ double sg[12 * n3];
-  __shared__ DevBasis sb;
-  const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
-  const int nE = G.nElems, nS = G.nSides;
-  load_basis(&sb, G.basis, t, S::nth);
-  if (t < n3) {
-    const double sJ = G.sJ[(size_t)e * n3 + t];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) sg[c * n3 + t] = sJ * gbar[((size_t)c * nE + e) * n3 + t];
-  }
-  __syncthreads();
-  for (int ft = t; ft < S::nface; ft += S::nth) {
-    const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
-    const int info = G.efc[e * 6 + f];
-    const int side = efc_side(info), slot = efc_slot(info);
-    int p = pp, q = qq;
-    if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, q);
-    const int fi = q * n1 + p;
-    const double sgn = slot ? -1.0 : 1.0;
-    const double s = G.face[((size_t)3 * nS + side) * n2 + fi];
-    double no[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) no[c] = sgn * (G.face[((size_t)c * nS + side) * n2 + fi] * s);
-    double acc[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int a = 0; a < n1; ++a) {
-      double L;
-      if constexpr (NODES == 1) {
-        if (a != ((f & 1) ? N : 0)) continue;
-        L = sb.winv[a];
-      } else {
-        L = sb.winv[a] * ((f & 1) ? sb.Lp[a] : sb.Lm[a]);
-      }
-      const int ta = line_node<N>(r, a, pp, qq);
-#pragma unroll
-      for (int qa = 0; qa < 4; ++qa)
-        acc[qa] += L * (sg[(3 * qa) * n3 + ta] * no[0] + sg[(3 * qa + 1) * n3 + ta] * no[1] +
-                        sg[(3 * qa + 2) * n3 + ta] * no[2]);
-    }
-#pragma unroll
-    for (int qa = 0; qa < 4; ++qa) Qbar[tr_index(slot, qa, 4, nS, side, n2, fi)] = acc[qa];
   }
 }
 
@@ -549,8 +613,8 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_volume(Geo G, Phys P
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   const int idx[3] = {i, j, k};
   double* sg = sm;
+  const double sJ = act ? G.sJ[(size_t)e * n3 + t] : 0.0;
   if (act) {
-    const double sJ = G.sJ[(size_t)e * n3 + t];
 #pragma unroll
     for (int c = 0; c < 12; ++c) sg[c * n3 + t] = sJ * gbar[((size_t)c * nE + e) * n3 + t];
   }
@@ -641,11 +705,24 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_volume(Geo G, Phys P
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ub[v] += Fb[v];
     }
+  }
+  double ldn[5] = {0, 0, 0, 0, 0};   // the updated lamdU (fused update)
+  if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const size_t gi = ((size_t)v * nE + e) * n3 + t;
-      adj_store(up, out, gi, out[gi] + Ub[v]);
+      ldn[v] = adj_store(up, out, gi, out[gi] + Ub[v]);
     }
+  }
+  if (up.lamU && up.Lnext) {
+    // the next stage's lam is the updated lamdU: its surface adjoint too
+    __syncthreads();   // (sm is free once every node has read its face parts)
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sm[v * n3 + t] = sJ * ldn[v];
+    }
+    __syncthreads();
+    adj_surface_of<N, NODES>(G, sb, sm, e, t, up.Lnext);
   }
 }
 

@@ -780,7 +780,7 @@ struct WsLayout {
   size_t utr[2], gtr, g, red, fvind, flag, total;
   // adjoint region: recomputed stage states Y_1..Y_{S-1}, forward RK
   // register, adjoint residual, gradient adjoint (Navier-Stokes)
-  size_t Y[DG_RK_MAX_STAGES - 1], dUf, aout, gbar, total_adjoint;
+  size_t Y[DG_RK_MAX_STAGES - 1], dUf, aout, gbar, qbar, total_adjoint;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -820,6 +820,7 @@ static WsLayout ws_layout(const dg_ctx* c) {
   L.dUf = off; off += st;
   L.aout = off; off += st;
   L.gbar = off; off += ns ? align256(12 * nv * sizeof(double)) : 0;
+  L.qbar = off; off += ns ? align256(2 * 4 * nf * sizeof(double)) : 0;
   L.total_adjoint = off;
   return L;
 }
@@ -1057,6 +1058,7 @@ static dg_status adjoint_residual(dg_ctx* c, const double* U, const double* lam,
   Work w = kwork(c);
   WsLayout L = ws_layout(c);
   double* gbar = k.physics == DG_PHYS_NAVIER_STOKES ? (double*)(c->ws + L.gbar) : nullptr;
+  double* qbar = k.physics == DG_PHYS_NAVIER_STOKES ? (double*)(c->ws + L.qbar) : nullptr;
   {
     ProfScope ps(c, FAM_TRACE, s);
     LAUNCHCHK(c, launch_trace(k, g, c->phys, U, w.Utr[0], s));
@@ -1066,7 +1068,7 @@ static dg_status adjoint_residual(dg_ctx* c, const double* U, const double* lam,
     LAUNCHCHK(c, launch_lift(k, 0, g, c->phys, U, w.Utr[0], w.g, w.gtr, s));
   }
   ProfScope ps(c, FAM_ADJOINT, s);
-  LAUNCHCHK(c, launch_adjoint(k, g, c->phys, U, lam, w.Utr[0], w.Utr[1], w.g, w.gtr, out, gbar, up, s));
+  LAUNCHCHK(c, launch_adjoint(k, g, c->phys, U, lam, w.Utr[0], w.Utr[1], w.g, w.gtr, out, gbar, qbar, up, s));
   return DG_OK;
 }
 
@@ -1090,9 +1092,15 @@ static dg_status reverse_sweep(dg_ctx* c, const double* const* Y, double* lamU, 
     ProfScope ps(c, FAM_OTHER, s);
     LAUNCHCHK(c, launch_scale_copy(n, lamU, lamdU, B[ns - 1], s));
   }
-  // (the update is fused into the stage's last adjoint kernel)
+  // (the update is fused into the stage's last adjoint kernel, which for
+  // Navier-Stokes also writes the next stage's surface adjoint into Lbar:
+  // nothing else touches that buffer before the next stage reads it)
+  const bool visc = c->cfg.physics == DG_PHYS_NAVIER_STOKES;
+  double* Lbar = kwork(c).Utr[1];
   for (int k = ns - 1; k >= 0; --k) {
-    const AdjUpd up{lamU, lamdU, dt, A[k], k > 0 ? B[k - 1] : 0.0};
+    AdjUpd up{lamU, lamdU, dt, A[k], k > 0 ? B[k - 1] : 0.0};
+    up.Lnext = visc && k > 0 ? Lbar : nullptr;
+    up.lbar_ready = visc && k < ns - 1 ? 1 : 0;
     dg_status st = adjoint_residual(c, Y[k], lamdU, aout, s, up);
     if (st != DG_OK) return st;
   }

@@ -195,22 +195,24 @@ hipError_t DGX_NAME(launch_fv_switch)(const Cfg& c, const Geo& g, double* U, dou
 }
 
 hipError_t DGX_NAME(launch_adjoint)(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* lam,
-                                    const double* Utr, double* Lbar, const double* gin, double* gtr, double* out,
-                                    double* gbar, const AdjUpd& up, hipStream_t s) {
+                                    const double* Utr, double* Lbar, const double* gin, const double* gtr,
+                                    double* out, double* gbar, double* qbar, const AdjUpd& up, hipStream_t s) {
   // the fused RK update goes into the last kernel: the volume adjoint (Euler)
   // or the lifting adjoint (Navier-Stokes)
   const AdjUpd none{nullptr, nullptr, 0.0, 0.0, 0.0};
   const AdjUpd& upv = c.physics == 1 ? none : up;
   const dim3 grid(g.nElems), block(Shape<kN>::nth);
-  // per-element surface adjoints
-  if (c.nodes == 1)
-    hipLaunchKernelGGL((k_adj_trace<kN, 1>), grid, block, 0, s, g, lam, Lbar);
-  else
-    hipLaunchKernelGGL((k_adj_trace<kN, 0>), grid, block, 0, s, g, lam, Lbar);
+  // per-element surface adjoints (unless the previous stage's last kernel wrote them)
+  if (!up.lbar_ready) {
+    if (c.nodes == 1)
+      hipLaunchKernelGGL((k_adj_trace<kN, 1>), grid, block, 0, s, g, lam, Lbar);
+    else
+      hipLaunchKernelGGL((k_adj_trace<kN, 0>), grid, block, 0, s, g, lam, Lbar);
+  }
   // volume + surface adjoint
 #define DGX_ADJ_V(NODES, FORM, PHYS, ROE, VL)                                                                  \
   hipLaunchKernelGGL((k_adj_volume<kN, NODES, FORM, PHYS, ROE, VL>), grid, block, 0, s, g, p, U, lam, Utr, Lbar, gin, \
-                     gtr, out, gbar, upv)
+                     gtr, out, gbar, qbar, upv)
   // (Sutherland's law only matters with viscous terms)
 #define DGX_ADJ(NODES, FORM, PHYS)                                       \
   do {                                                                   \
@@ -234,17 +236,13 @@ hipError_t DGX_NAME(launch_adjoint)(const Cfg& c, const Geo& g, const Phys& p, c
 #undef DGX_ADJ
 #undef DGX_ADJ_V
   if (c.physics == 1) {
-    // lifting adjoint; gtr has been consumed and now holds Qbar
-    if (c.nodes == 1) {
-      hipLaunchKernelGGL((k_adj_lift_trace<kN, 1>), grid, block, 0, s, g, gbar, gtr);
-      hipLaunchKernelGGL((k_adj_lift_volume<kN, 1>), grid, block, 0, s, g, p, U, Utr, gbar, gtr, out, up);
-    } else {
-      hipLaunchKernelGGL((k_adj_lift_trace<kN, 0>), grid, block, 0, s, g, gbar, gtr);
-      if (c.form == 1)
-        hipLaunchKernelGGL((k_adj_lift_volume<kN, 0, 1>), grid, block, 0, s, g, p, U, Utr, gbar, gtr, out, up);
-      else
-        hipLaunchKernelGGL((k_adj_lift_volume<kN, 0>), grid, block, 0, s, g, p, U, Utr, gbar, gtr, out, up);
-    }
+    // lifting adjoint (its face values in qbar, written by the volume adjoint)
+    if (c.nodes == 1)
+      hipLaunchKernelGGL((k_adj_lift_volume<kN, 1>), grid, block, 0, s, g, p, U, Utr, gbar, qbar, out, up);
+    else if (c.form == 1)
+      hipLaunchKernelGGL((k_adj_lift_volume<kN, 0, 1>), grid, block, 0, s, g, p, U, Utr, gbar, qbar, out, up);
+    else
+      hipLaunchKernelGGL((k_adj_lift_volume<kN, 0>), grid, block, 0, s, g, p, U, Utr, gbar, qbar, out, up);
   }
   return hipGetLastError();
 }

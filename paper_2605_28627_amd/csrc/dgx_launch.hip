@@ -48,8 +48,8 @@ hipError_t static_scratch(void** ptr) {
                                 const double*, const double*, double*, double*, double*, double*, double,   \
                                 double, double, hipStream_t);                                                  \
   hipError_t launch_adjoint_N##n(const Cfg&, const Geo&, const Phys&, const double*, const double*,          \
-                                 const double*, double*, const double*, double*, double*, double*,             \
-                                 const AdjUpd&, hipStream_t);                                                   \
+                                 const double*, double*, const double*, const double*, double*, double*,       \
+                                 double*, const AdjUpd&, hipStream_t);                                          \
   hipError_t launch_trace_fv_N##n(const Cfg&, const Geo&, const Phys&, const double*, double*, hipStream_t);   \
   hipError_t launch_fv_N##n(const Cfg&, const Geo&, const Phys&, int, const double*, const double*,         \
                             const double*, const double*, double*, double*, double*, double*, double, double,  \
@@ -169,9 +169,9 @@ hipError_t launch_volume(const Cfg& c, const Geo& g, const Phys& p, int mode, co
 }
 
 hipError_t launch_adjoint(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* lam,
-                          const double* Utr, double* Lbar, const double* gin, double* gtr, double* out, double* gbar,
-                          const AdjUpd& up, hipStream_t s) {
-#define ARGS (c, g, p, U, lam, Utr, Lbar, gin, gtr, out, gbar, up, s)
+                          const double* Utr, double* Lbar, const double* gin, const double* gtr, double* out,
+                          double* gbar, double* qbar, const AdjUpd& up, hipStream_t s) {
+#define ARGS (c, g, p, U, lam, Utr, Lbar, gin, gtr, out, gbar, qbar, up, s)
   DGX_SWITCH(launch_adjoint)
 #undef ARGS
 }

@@ -734,14 +734,16 @@ __host__ __device__ inline void euler_flux_vjp(const double U[5], const Prim& q,
   for (int v = 0; v < 5; ++v) Ub[v] = Ud[v] + Up[v];
 }
 
-// Adjoint of the contracted viscous flux Gn[v] = sum_d n_d G_d[1+v]:
-// gb[12] receives d(Gnb . Gn)/dg, ub[3] the velocity part (energy equation),
-// and with Sutherland's law (VL 1) rpb[0], rpb[1] += the density and
-// pressure parts through mu(T), lambda(T), T = p/(rho R).
+// Adjoint of the viscous flux tensor G_d[1+v] (d = 0..2, v = 0..3) with the
+// weights M[d][v]: gb[12] receives d(sum M[d][v] G_d[1+v])/dg, ub[3] the
+// velocity part (energy equation), and with Sutherland's law (VL 1) rpb[0],
+// rpb[1] += the density and pressure parts through mu(T), lambda(T),
+// T = p/(rho R).  The contracted flux Gn = sum_d n_d G_d takes M = n (x) Gnb;
+// several contractions of the same flux take the sum of their M.
 template <int VL = 0>
-__host__ __device__ inline void viscous_flux_vjp(const Prim& q, const double g[12], const Phys& P, const double n[3],
-                                                 const double Gnb[4], double gb[12], double ub[3],
-                                                 double rpb[2] = nullptr) {
+__host__ __device__ inline void viscous_tensor_vjp(const Prim& q, const double g[12], const Phys& P,
+                                                   const double M[3][4], double gb[12], double ub[3],
+                                                   double rpb[2] = nullptr) {
   constexpr bool suth = VL == 1;
   const double mu = suth ? visc_mu<double>(q, P) : P.mu;
   const double lam = suth ? mu * P.kappa : P.lam;
@@ -751,17 +753,16 @@ __host__ __device__ inline void viscous_flux_vjp(const Prim& q, const double g[1
     for (int d = 0; d < 3; ++d) tau[a][d] = mu * (g[3 * a + d] + g[3 * d + a]);
   const double t2 = (2.0 / 3.0) * mu * divu;
   tau[0][0] -= t2; tau[1][1] -= t2; tau[2][2] -= t2;
+  // taub[a][d]: weight of tau[a][d] (momentum rows, and the energy row's u . tau)
   double taub[3][3];
   for (int a = 0; a < 3; ++a)
-    for (int d = 0; d < 3; ++d) taub[a][d] = n[d] * Gnb[a];
-  for (int d = 0; d < 3; ++d)
-    for (int a = 0; a < 3; ++a) taub[d][a] += n[d] * Gnb[3] * q.u[a];
+    for (int d = 0; d < 3; ++d) taub[a][d] = M[d][a] + M[d][3] * q.u[a];
   for (int a = 0; a < 3; ++a) {
     ub[a] = 0.0;
-    for (int d = 0; d < 3; ++d) ub[a] += n[d] * Gnb[3] * tau[d][a];
+    for (int d = 0; d < 3; ++d) ub[a] += M[d][3] * tau[d][a];
   }
   for (int c = 0; c < 12; ++c) gb[c] = 0.0;
-  for (int d = 0; d < 3; ++d) gb[9 + d] = lam * n[d] * Gnb[3];
+  for (int d = 0; d < 3; ++d) gb[9 + d] = lam * M[d][3];
   double divb = 0.0;
   for (int a = 0; a < 3; ++a) divb -= (2.0 / 3.0) * mu * taub[a][a];
   for (int a = 0; a < 3; ++a)
@@ -771,7 +772,7 @@ __host__ __device__ inline void viscous_flux_vjp(const Prim& q, const double g[1
     }
   gb[0] += divb; gb[4] += divb; gb[8] += divb;
   if (suth && mu != 0.0) {
-    // d(Gnb . Gn)/d mu: Gn is linear in mu and lambda = kappa mu
+    // d(weighted flux)/d mu: G is linear in mu and lambda = kappa mu
     double dmu = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -779,13 +780,25 @@ __host__ __device__ inline void viscous_flux_vjp(const Prim& q, const double g[1
       for (int d = 0; d < 3; ++d) dmu += taub[a][d] * tau[a][d];
     dmu /= mu;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) dmu += P.kappa * n[d] * Gnb[3] * g[9 + d];
+    for (int d = 0; d < 3; ++d) dmu += P.kappa * M[d][3] * g[9 + d];
     // mu = mu0 th^(3/2) (1 + Ts) / (th + Ts), th = p Rinv / (rho Tref)
     const double th = q.p * P.Rinv / (q.rho * P.Tref);
     const double thb = dmu * mu * (1.5 / th - 1.0 / (th + P.Ts));
     rpb[1] += thb * P.Rinv / (q.rho * P.Tref);
     rpb[0] -= thb * th / q.rho;
   }
+}
+
+// Adjoint of the contracted viscous flux Gn[v] = sum_d n_d G_d[1+v] with the
+// weights Gnb[4] (viscous_tensor_vjp with M = n (x) Gnb).
+template <int VL = 0>
+__host__ __device__ inline void viscous_flux_vjp(const Prim& q, const double g[12], const Phys& P, const double n[3],
+                                                 const double Gnb[4], double gb[12], double ub[3],
+                                                 double rpb[2] = nullptr) {
+  double M[3][4];
+  for (int d = 0; d < 3; ++d)
+    for (int v = 0; v < 4; ++v) M[d][v] = n[d] * Gnb[v];
+  viscous_tensor_vjp<VL>(q, g, P, M, gb, ub, rpb);
 }
 
 // Adjoint of the surface flux (FP64): ULb, URb, and for Navier-Stokes gLb, gRb.

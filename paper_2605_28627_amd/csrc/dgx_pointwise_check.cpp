@@ -110,6 +110,22 @@ void pw_viscous_flux_vjp(const double* U, const double* g, const double* n, cons
   prim_vjp(q, P.gm1, 0.0, ub, 0.0, Ub);
 }
 
+// d(sum_d sum_v M[d][v] G_d[1+v])/d(g, U) for the weights M[3][4] (row-major),
+// with the viscosity law of c (constant or Sutherland).
+void pw_viscous_tensor_vjp(const double* U, const double* g, const double* M, const double* c, double* gb,
+                           double* Ub) {
+  Phys P = make_phys(c);
+  Prim q = cons2prim(U, P.gm1);
+  double Mm[3][4], ub[3], rpb[2] = {0.0, 0.0};
+  for (int d = 0; d < 3; ++d)
+    for (int v = 0; v < 4; ++v) Mm[d][v] = M[4 * d + v];
+  if (P.visc_law == 1)
+    viscous_tensor_vjp<1>(q, g, P, Mm, gb, ub, rpb);
+  else
+    viscous_tensor_vjp<0>(q, g, P, Mm, gb, ub, rpb);
+  prim_vjp(q, P.gm1, rpb[0], ub, rpb[1], Ub);
+}
+
 void pw_qvars(const double* U, const double* c, double* qv) {
   Phys P = make_phys(c);
   Prim q = cons2prim(U, P.gm1);

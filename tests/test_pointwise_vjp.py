@@ -168,6 +168,33 @@ def test_euler_and_viscous_vjp(pw):
         assert abs(vq @ d - ref_q) < 1e-8 * (1 + abs(ref_q))
 
 
+@pytest.mark.parametrize("law", [0, 1])
+def test_viscous_tensor_vjp(pw, law):
+    """One adjoint of the whole viscous flux tensor with weights M[d][v] (the
+    adjoint residual sums its three directions' weights into one M) against
+    central differences of sum_d M[d] . G(n = e_d), constant and Sutherland."""
+    rng = np.random.default_rng(5 + law)
+    c = C.copy()
+    c[6] = law
+    E = np.eye(3)
+    for _ in range(30):
+        U = state(rng)
+        g = rng.normal(size=12)
+        M = rng.normal(size=(3, 4))
+        gb, Ub = np.zeros(12), np.zeros(5)
+        pw.pw_viscous_tensor_vjp(P(U), P(g), P(M), P(c), P(gb), P(Ub))
+
+        def fwd(Ux, gx):
+            return sum(M[d] @ call(pw.pw_viscous_flux, 4, Ux, gx, E[d], c) for d in range(3))
+
+        dg, dU = rng.normal(size=12), rng.normal(size=5)
+        eps = 1e-6
+        ref_g = (fwd(U, g + eps * dg) - fwd(U, g - eps * dg)) / (2 * eps)
+        ref_U = (fwd(U + eps * dU, g) - fwd(U - eps * dU, g)) / (2 * eps)
+        assert abs(gb @ dg - ref_g) < 1e-8 * (1 + abs(ref_g))
+        assert abs(Ub @ dU - ref_U) < 1e-8 * (1 + abs(ref_U))
+
+
 @pytest.mark.parametrize("form,phys", [(0, 0), (1, 0), (0, 1), (1, 1)])
 @pytest.mark.parametrize("riemann", [0, 1])
 def test_surface_flux_vjp(pw, form, phys, riemann):
