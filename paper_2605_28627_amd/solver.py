@@ -34,6 +34,7 @@ class DGSolver:
                 dgx.dg_upload_mesh(self.ctx, mesh)
             self.nElems, self.nSides, self.npe, self.state_len = dgx.dg_sizes(self.ctx)
             self.n1 = round(self.npe ** (1 / 3))
+            self._stages = len(dgx.dg_rk_coefficients(self.cfg.get("integrator", 0))[0])
             nb = dgx.dg_workspace_bytes_adjoint(self.ctx) if adjoint else dgx.dg_workspace_bytes(self.ctx)
             self.adjoint = adjoint
             # over-allocate so the bound pointer is 256-byte aligned
@@ -121,7 +122,7 @@ class DGSolver:
 
     @property
     def rk_stages(self) -> int:
-        return len(dgx.dg_rk_coefficients(self.cfg.get("integrator", 0))[0])
+        return self._stages
 
     def stage_buffer(self) -> torch.Tensor:
         """Device buffer for the S-1 stage inputs of one step (rk_step_stages)."""
