@@ -37,14 +37,17 @@ __device__ __forceinline__ void load_basis(DevBasis* dst, const DevBasis* src, i
 
 // Element of a one-element-per-workgroup launch.  Consecutive workgroups are
 // dealt round-robin to the chip's 8 XCDs, each with its own L2.  With
-// XCD-aware numbering XCD x walks a contiguous block of elements, so an
-// element and its lexicographic neighbours (which read the same face data:
-// traces, face geometry, face viscous fluxes) run on the same XCD close in
-// time and the second read can hit that XCD's L2.  XCD x gets
+// XCD-aware numbering (DGX_XCD_REMAP 1) XCD x walks a contiguous block of
+// elements, so an element and its lexicographic neighbours (which read the
+// same face data) run on the same XCD close in time.  XCD x then gets
 // nE/8 (+1 for x < nE%8) elements starting at x (nE/8) + min(x, nE%8); the
-// map is a bijection of [0, nE) for any nE.
+// map is a bijection of [0, nE) for any nE.  Measured, it gains nothing at
+// N = 7 and costs 2-8 % at N = 3 (plausibly because in plain order the
+// eight XCDs work on neighbouring elements at the same time and share the
+// face data through the chip-wide last-level cache), so plain order (0) is
+// the default.
 #ifndef DGX_XCD_REMAP
-#define DGX_XCD_REMAP 1
+#define DGX_XCD_REMAP 0
 #endif
 __device__ __forceinline__ int elem_of_block(int bid, int nE) {
   if constexpr (DGX_XCD_REMAP) {
