@@ -522,7 +522,9 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
   }
   if constexpr (FV && EMIT == 1) {
     // FV faces: layer-0 sub-cell means of the gradient, (B3 (J g))_s / V_s,
-    // by a contraction along the face normal and a tensor product over the face
+    // by a contraction along the face normal and a tensor product over the
+    // face; all FV faces at once, the contractions of faces 0-2 in sf and of
+    // faces 3-5 in sfq (both dead by now)
     if (efl & 63) {
       double* sjg = sm;   // [12][n3]: J g
       __syncthreads();
@@ -531,37 +533,41 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
 #pragma unroll
         for (int c = 0; c < 12; ++c) sjg[c * n3 + t] = J * acc[c];
       }
-      double* gtr2 = gtr + (size_t)8 * nS * n2;
-      for (int f = 0; f < 6; ++f) {
+      __syncthreads();
+      static_assert(7 * S::nface >= 36 * n2 && 8 * S::nface >= 36 * n2, "contraction buffers");
+      auto contracted = [&](int f) { return f < 3 ? sf + f * 12 * n2 : sfq + (f - 3) * 12 * n2; };
+      for (int ft = t; ft < S::nface; ft += S::nth) {
+        const int f = ft / n2, rr = ft % n2;
         if (!((efl >> f) & 1)) continue;
-        const int r = f / 2, an = (f & 1) ? N : 0;
-        __syncthreads();
-        for (int rr = t; rr < n2; rr += S::nth) {
-          const int pp = rr % n1, qq = rr / n1;
+        const int r = f / 2, an = (f & 1) ? N : 0, pp = rr % n1, qq = rr / n1;
+        double* T = contracted(f);
 #pragma unroll
-          for (int c = 0; c < 12; ++c) {
-            double sacc = 0.0;
+        for (int c = 0; c < 12; ++c) {
+          double sacc = 0.0;
 #pragma unroll
-            for (int l = 0; l < n1; ++l) sacc += sb.Bs[an * n1 + l] * sjg[c * n3 + line_node<N>(r, l, pp, qq)];
-            sf[c * n2 + rr] = sacc;
-          }
+          for (int l = 0; l < n1; ++l) sacc += sb.Bs[an * n1 + l] * sjg[c * n3 + line_node<N>(r, l, pp, qq)];
+          T[c * n2 + rr] = sacc;
         }
-        __syncthreads();
-        for (int rr = t; rr < n2; rr += S::nth) {
-          const int pp = rr % n1, qq = rr / n1;
-          const int info = G.efc[e * 6 + f];
-          const int side = efc_side(info), slot = efc_slot(info);
-          int p = pp, qm = qq;
-          if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
-          const double iv = 1.0 / G.fvV[(size_t)e * n3 + line_node<N>(r, an, pp, qq)];
+      }
+      __syncthreads();
+      double* gtr2 = gtr + (size_t)8 * nS * n2;
+      for (int ft = t; ft < S::nface; ft += S::nth) {
+        const int f = ft / n2, rr = ft % n2;
+        if (!((efl >> f) & 1)) continue;
+        const int r = f / 2, an = (f & 1) ? N : 0, pp = rr % n1, qq = rr / n1;
+        const double* T = contracted(f);
+        const int info = G.efc[e * 6 + f];
+        const int side = efc_side(info), slot = efc_slot(info);
+        int p = pp, qm = qq;
+        if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
+        const double iv = 1.0 / G.fvV[(size_t)e * n3 + line_node<N>(r, an, pp, qq)];
 #pragma unroll
-          for (int c = 0; c < 12; ++c) {
-            double m = 0.0;
-            for (int q2 = 0; q2 < n1; ++q2)
+        for (int c = 0; c < 12; ++c) {
+          double m = 0.0;
+          for (int q2 = 0; q2 < n1; ++q2)
 #pragma unroll
-              for (int p2 = 0; p2 < n1; ++p2) m += sb.Bs[pp * n1 + p2] * sb.Bs[qq * n1 + q2] * sf[c * n2 + q2 * n1 + p2];
-            gtr2[tr_index(slot, c, 12, nS, side, n2, qm * n1 + p)] = m * iv;
-          }
+            for (int p2 = 0; p2 < n1; ++p2) m += sb.Bs[pp * n1 + p2] * sb.Bs[qq * n1 + q2] * T[c * n2 + q2 * n1 + p2];
+          gtr2[tr_index(slot, c, 12, nS, side, n2, qm * n1 + p)] = m * iv;
         }
       }
     }
