@@ -47,11 +47,16 @@ static void lift_emit(const Cfg& c, int emit, const Geo& g, const Phys& p, const
 hipError_t DGX_NAME(launch_lift)(const Cfg& c, int emit, const Geo& g, const Phys& p, const double* U,
                                  const double* Utr, double* gout, double* gtr, hipStream_t s) {
   if (c.fv) {
-    // FV contexts (FP64, constant viscosity): DG elements, then FV elements'
-    // Green-Gauss gradients; the layer-0 gradients go behind the face fluxes
+    // FV contexts (FP64, constant viscosity): DG elements without an FV face
+    // (lean kernel), DG elements with one, then FV elements' Green-Gauss
+    // gradients; the layer-0 gradients go behind the face fluxes
     const dim3 grid(g.nElems), block(Shape<kN>::nth);
     double* gtr2 = gtr + (size_t)8 * g.nSides * Shape<kN>::n2;
     if (emit != 1) return hipErrorInvalidValue;
+    if (c.nodes == 1)
+      hipLaunchKernelGGL((k_lift<kN, 1, 1, 0, 0, 3>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
+    else
+      hipLaunchKernelGGL((k_lift<kN, 0, 1, 0, 0, 3>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
     if (c.nodes == 1)
       hipLaunchKernelGGL((k_lift<kN, 1, 1, 0, 0, 1>), grid, block, 0, s, g, p, U, Utr, gout, gtr);
     else if (c.form == 0)
@@ -105,18 +110,28 @@ static void vol_phys(const Cfg& c, int mode, const Geo& g, const Phys& p, const 
 }
 
 // DG elements of an FV context (FP64, Rusanov; Navier-Stokes with constant
-// viscosity; the split form on Gauss nodes is the entropy-stable hybridised form)
+// viscosity; the split form on Gauss nodes is the entropy-stable hybridised
+// form).  Navier-Stokes: those without an FV face in the lean kernel (FV 2),
+// then those with one (FV 1), each kernel skipping the other's elements (the
+// FV-face variants need far more registers and LDS there); Euler: one kernel.
 template <int NODES, int FORM, int PHYS>
 static void vol_fv(int mode, const Geo& g, const Phys& p, const double* U, const double* Utr, const double* gvn,
                    const double* gvf, double* Ut, double* Uio, double* dU, double* Utr_next, double A, double B,
                    double dt, hipStream_t s) {
   const dim3 grid(g.nElems), block(Shape<kN>::nth);
-  if (mode == 0)
+  if (mode == 0) {
+    if constexpr (PHYS == 1)
+      hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, 0, 0, 0, 2>), grid, block, 0, s, g, p, U, Utr, gvn, gvf,
+                         Ut, Uio, dU, Utr_next, A, B, dt);
     hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, 0, 0, 0, 1>), grid, block, 0, s, g, p, U, Utr, gvn, gvf,
                        Ut, Uio, dU, Utr_next, A, B, dt);
-  else
+  } else {
+    if constexpr (PHYS == 1)
+      hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, 0, 1, 0, 2>), grid, block, 0, s, g, p, U, Utr, gvn, gvf,
+                         Ut, Uio, dU, Utr_next, A, B, dt);
     hipLaunchKernelGGL((k_volume<kN, NODES, FORM, PHYS, 0, 1, 0, 1>), grid, block, 0, s, g, p, U, Utr, gvn, gvf,
                        Ut, Uio, dU, Utr_next, A, B, dt);
+  }
 }
 
 template <int PHYS>

@@ -159,7 +159,8 @@ __device__ inline double ld_visc(const double* p, size_t i) {
 //
 // FV 1 (Navier-Stokes contexts with FV sub-cells; FV 2 for the split form on
 // Gauss nodes, whose own face value is then the entropy-projected trace
-// u(E v(U))): DG elements only.  On a
+// u(E v(U))): DG elements with an FV face only (FV 3: the DG elements
+// without one, which need only the FV context's trace layout).  On a
 // face whose other side is an FV element the face average takes that side's
 // q as the face polynomial whose sub-face means are the q of its
 // reconstructed face states (h^2 (B^-1 x B^-1), h = 2/(N+1)), and instead of
@@ -175,19 +176,24 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
   constexpr int SZ = (13 * n3 > 7 * S::nface ? 13 * n3 : 7 * S::nface);
   constexpr int SZ2 = (12 * n3 > SZ ? 12 * n3 : SZ);
-  constexpr int TNV = FV ? kTrFV : 5;                  // trace values per face node
+  // FV 1, 2: DG elements of an FV context with an FV face (the FV-face code);
+  // FV 3: those without one, in the FV context's trace layout only
+  constexpr bool kCtx = FV != 0, kFvf = FV == 1 || FV == 2;
+  constexpr int TNV = kCtx ? kTrFV : 5;                // trace values per face node
   __shared__ double sm[SZ2];
   __shared__ double sf[7 * S::nface];
   // FV contexts: per face node the other (FV) side's sub-face q and the own q;
   // on Gauss nodes the element's state for its own traces
-  __shared__ double sfq[FV ? 8 * S::nface : 1];
-  __shared__ double su[FV && NODES == 0 ? 5 * n3 : 1];
-  __shared__ VolBasis<N, FV != 0> sb;
+  __shared__ double sfq[kFvf ? 8 * S::nface : 1];
+  __shared__ double su[kFvf && NODES == 0 ? 5 * n3 : 1];
+  __shared__ VolBasis<N, kFvf> sb;
   const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
-  const int efl = FV ? G.efv[e] : 0;   // bits 0..5: FV faces, bit 6: FV element
-  if (FV && (efl & 64)) return;        // FV elements: k_lift_fv
+  const int efl = kCtx ? G.efv[e] : 0;   // bits 0..5: FV faces, bit 6: FV element
+  if (kCtx && (efl & 64)) return;        // FV elements: k_lift_fv
+  if (kFvf && !(efl & 63)) return;       // (no FV face: the FV 3 variant)
+  if (FV == 3 && (efl & 63)) return;
   const int nE = G.nElems, nS = G.nSides;
-  load_vol_basis<N, FV != 0>(&sb, G.basis, t, S::nth);
+  load_vol_basis<N, kFvf>(&sb, G.basis, t, S::nth);
   double* sq = sm;            // [4][n3]
   double* sja = sm + 4 * n3;  // [9][n3]
   const bool act = t < n3;
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
     for (int c = 0; c < 9; ++c) jl[c] = G.Ja[((size_t)c * nE + e) * n3 + t];
     sJ = G.sJ[(size_t)e * n3 + t];
   }
-  if constexpr (kOneFaceNode && !FV) {
+  if constexpr (kOneFaceNode && !kFvf) {
     if (t < S::nface) face_load(t, fslot, fUL, fUR, fns);
   }
   if (act) {
@@ -277,8 +283,8 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
     for (int c = 0; c < 9; ++c) sja[c * n3 + t] = jl[c];
   }
   // LGL: the face averages read the own q tile (FV contexts: and the own state)
-  if constexpr (NODES == 1 || FV) __syncthreads();
-  if constexpr (FV) {
+  if constexpr (NODES == 1 || kFvf) __syncthreads();
+  if constexpr (kFvf) {
     // FV faces: the other side's reconstructed face state at each sub-face and
     // the own trace's q into LDS; DG faces as usual
     const double h = 2.0 / n1;
@@ -469,7 +475,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
         const int a = idx[r];
         if (a != 0 && a != N) continue;
         const int f = 2 * r + (a == N ? 1 : 0);
-        if (FV && ((efl >> f) & 1)) continue;
+        if (kFvf && ((efl >> f) & 1)) continue;
         const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
         const int info = G.efc[e * 6 + f];
         const int side = efc_side(info), slot = efc_slot(info);
@@ -491,7 +497,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
     __syncthreads();
     for (int ft = t; ft < S::nface; ft += S::nth) {
       const int f = ft / n2, rr = ft % n2, pp = rr % n1, qq = rr / n1, r = f / 2;
-      if (FV && ((efl >> f) & 1)) continue;
+      if (kFvf && ((efl >> f) & 1)) continue;
       const double* L = (f & 1) ? sb.Lp : sb.Lm;
       const int info = G.efc[e * 6 + f];
       const int side = efc_side(info), slot = efc_slot(info);
@@ -520,7 +526,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
       }
     }
   }
-  if constexpr (FV && EMIT == 1) {
+  if constexpr (kFvf && EMIT == 1) {
     // FV faces: layer-0 sub-cell means of the gradient, (B3 (J g))_s / V_s,
     // by a contraction along the face normal and a tensor product over the
     // face; all FV faces at once, the contractions of faces 0-2 in sf and of
@@ -622,10 +628,12 @@ constexpr int volume_waves() {
   return Shape<N>::nth >= 512 ? 4 : ((FORM == 1 && NODES == 0 && N == 3) ? DGX_ES_WAVES : 1);
 }
 
-// FV (contexts with FV sub-cells): DG elements only; faces with an FV
-// element on either side take the sub-face fluxes back as the nodal flux
-// polynomial (B^-1 x B^-1), and the RK epilogue writes two-layer primitive
-// traces there.  Navier-Stokes: those sub-face fluxes subtract the mean of
+// FV 1 (contexts with FV sub-cells): the DG elements; for Navier-Stokes only
+// those with an FV face, and FV 2 the others (which need only the FV
+// context's trace layout, and run at the plain kernel's occupancy).  Faces
+// with an FV element on either side take the sub-face fluxes back as the
+// nodal flux polynomial (B^-1 x B^-1), and the RK epilogue writes two-layer
+// primitive traces there.  Navier-Stokes: those sub-face fluxes subtract the mean of
 // both layer-0 sub-cells' viscous fluxes, from the gradients at
 // gvf + 8 nSides n2.
 template <int N, int NODES, int FORM, int PHYS, int PREC, int MODE, int ROE, int FV = 0>
@@ -655,26 +663,32 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   constexpr int SZ0 = SZ_V > 5 * n3 ? SZ_V : 5 * n3;                 // also holds the new state (Gauss traces)
   // FV: sub-face fluxes of the six faces, and two buffers for the means of the new state
   constexpr int SZ_FV = (5 * S::nface > 10 * n3 ? 5 * S::nface : 10 * n3);
-  constexpr int SZ = FV && SZ_FV > SZ0 ? SZ_FV : SZ0;
-  constexpr int TNV = FV ? kTrFV : 5;                                // trace values per face node
+  // FV 1: DG elements of an FV context (the FV-face code; Navier-Stokes:
+  // those with an FV face); FV 2: Navier-Stokes DG elements without one, in
+  // the FV context's trace layout only
+  constexpr bool kCtx = FV != 0, kFvf = FV == 1;
+  constexpr int SZ = kFvf && SZ_FV > SZ0 ? SZ_FV : SZ0;
+  constexpr int TNV = kCtx ? kTrFV : 5;                              // trace values per face node
   // Surface fluxes (outward, own face-local order): all six faces at once, or
   // (Gauss split form) the two faces of each direction within its pass,
   // together with the two-point records of the own projected face states.
   // (FV contexts of the Gauss split form keep all six slots)
-  constexpr int kFaces = ES && !FV ? kEsFaceSlots : 6;
+  constexpr int kFaces = ES && !kFvf ? kEsFaceSlots : 6;
   // Lobatto split form at N = 7: symmetric zeta pairs, partner shares through sx
   constexpr bool kZetaX = DGX_ZETA_EXCHANGE && FORM == 1 && !ES && n1 == 8 && S::nth == n3;
   __shared__ double sphi[5 * kFaces * n2];
   __shared__ double sm[SZ];
   __shared__ double sx[kZetaX ? 5 * n3 : 1];
   __shared__ double saf[ES ? 8 * kFaces * n2 : 1];
-  __shared__ VolBasis<N, FV != 0> sb;
+  __shared__ VolBasis<N, kFvf> sb;
   const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
   // FV: which faces are FV (bits 0..5), and whether this element is (bit 6)
-  const int efl = FV ? G.efv[e] : 0;
-  if (FV && (efl & 64)) return;   // FV elements belong to the FV kernel
+  const int efl = kCtx ? G.efv[e] : 0;
+  if (kCtx && (efl & 64)) return;   // FV elements belong to the FV kernel
+  if (FV == 1 && PHYS == 1 && !(efl & 63)) return;
+  if (FV == 2 && (efl & 63)) return;
   const int nE = G.nElems, nS = G.nSides;
-  load_vol_basis<N, FV != 0>(&sb, G.basis, t, S::nth);
+  load_vol_basis<N, kFvf>(&sb, G.basis, t, S::nth);
   const bool act = t < n3;
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   const int idx[3] = {i, j, k};
@@ -723,7 +737,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
     int p = pp, qm = qq;
     if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
     const int fi = qm * n1 + p;
-    if constexpr (FV) {
+    if constexpr (kFvf) {
       if ((efl >> f) & 1) {
         // FV face: the sub-face flux, outward, into the staging area (taken back below);
         // Navier-Stokes: less the mean of both layer-0 sub-cells' viscous fluxes
@@ -777,7 +791,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   if constexpr (!ES) {
     for (int ft = t; ft < S::nface; ft += S::nth) face_node(ft / n2, ft % n2, ft / n2);
   }
-  if constexpr (ES && FV) {
+  if constexpr (ES && kFvf) {
     if (efl & 63) {
       // FV faces of the Gauss split form: the traces there hold sub-cell
       // means, so the element forms the two-point records of its own
@@ -813,7 +827,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
         if ((efl >> (ft / n2)) & 1) face_node(ft / n2, ft % n2, ft / n2);
     }
   }
-  if constexpr (FV) {
+  if constexpr (kFvf) {
     // FV faces: nodal flux polynomial with the sub-face integrals, Phi = (B^-1 x B^-1) F
     __syncthreads();
     for (int ft = t; ft < S::nface; ft += S::nth) {
@@ -860,8 +874,8 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
         // the faces whose flux is formed in this pass: 0..3 in the first, 4, 5 in the last
         constexpr int fa[3] = {0, 6, 4}, fb[3] = {4, 6, 6};
         for (int ft = fa[r] * n2 + t; ft < fb[r] * n2; ft += S::nth) {
-          if (FV && ((efl >> (ft / n2)) & 1)) continue;   // formed in step 1
-          face_node(ft / n2, ft % n2, FV ? ft / n2 : es_face_slot(ft / n2));
+          if (kFvf && ((efl >> (ft / n2)) & 1)) continue;   // formed in step 1
+          face_node(ft / n2, ft % n2, kFvf ? ft / n2 : es_face_slot(ft / n2));
         }
       }
       if (act) {
@@ -973,7 +987,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           for (int f = 0; f < 2; ++f) {
             const double* L = f ? sb.Lp : sb.Lm;
             const double cs = sb.winv[a] * L[a];
-            const int fsl = FV ? 2 * r + f : es_face_slot(2 * r + f);
+            const int fsl = kFvf ? 2 * r + f : es_face_slot(2 * r + f);
 #pragma unroll
             for (int v = 0; v < 5; ++v) acc[v] -= cs * sphi[(fsl * 5 + v) * n2 + rr];
             double jf[3] = {0.0, 0.0, 0.0};
@@ -1111,7 +1125,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
           const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
           const int info = G.efc[e * 6 + f];
           const int side = efc_side(info), slot = efc_slot(info);
-          if (FV && ((efl >> f) & 1)) continue;
+          if (kFvf && ((efl >> f) & 1)) continue;
           int p = pp, qm = qq;
           if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
 #pragma unroll
@@ -1137,7 +1151,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
         const double* L = (f & 1) ? sb.Lp : sb.Lm;
         const int info = G.efc[e * 6 + f];
         const int side = efc_side(info), slot = efc_slot(info);
-        if (FV && ((efl >> f) & 1)) continue;
+        if (kFvf && ((efl >> f) & 1)) continue;
         int p = pp, qm = qq;
         if (slot) orient_to_master(efc_orient(info), N, pp, qq, p, qm);
         double s[5];
@@ -1160,7 +1174,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
         for (int v = 0; v < 5; ++v) Utr_next[tr_index(slot, v, TNV, nS, side, n2, qm * n1 + p)] = s[v];
       }
     }
-    if constexpr (FV) {
+    if constexpr (kFvf) {
       // FV faces of this DG element: primitive means of its first two sub-cell layers
       const bool anyfv = (efl & 63) != 0;
       if (anyfv) {
