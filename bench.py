@@ -241,24 +241,27 @@ def adjoint_kernel_bytes_per_dof(w):
       k_trace (the stage state's traces): U 5; writes 5 fpn;
       k_lift, gradients (Navier-Stokes): U 5, Ja 9, 1/J 1, both traces 10 fpn,
         face 4 fpn; writes g 12 and the own gradient traces 12 fpn;
-      k_adj_trace: lambda 5, 1/J 1; writes the surface adjoint 5 fpn;
+      k_adj_trace: lambda 5, 1/J 1; writes the surface adjoint 5 fpn
+        (Navier-Stokes: first stage of a step only, the later ones take it
+        from the fused update);
       k_adj_volume: lambda 5, 1/J 1, U 5, Ja 9, both traces, both surface
         adjoints and the face 24 fpn (Navier-Stokes: g 12, both gradient
-        traces 24 fpn; writes out 5, gbar 12 and the lifting adjoint's face
-        values Qbar 4 fpn; Euler: lamU 5 read, lamU and lamdU 10 written);
-      k_adj_lift_volume: gbar 12, 1/J 1, U 5, Ja 9, the own trace 5 fpn,
-        both Qbar 8 fpn, out 5, lamU 5, lamdU 5; writes lamU and lamdU 10."""
+        traces 24 fpn; writes out 5 and the lifting adjoint's face values
+        Qbar 4 fpn; Euler: lamU 5 read, lamU and lamdU 10 written);
+      k_adj_lift_volume (Navier-Stokes): 1/J 1, the own trace 5 fpn, both
+        Qbar 8 fpn, out 5, lamU 5, lamdU 5; writes lamU and lamdU 10 and the
+        next stage's surface adjoint 5 fpn."""
     n1 = w["N"] + 1
     fpn = 6 * n1 * n1 / n1 ** 3
     ns = w["physics"] == 1
     b = {"k_trace": 5 + 5 * fpn,
          "k_adj_trace": 6 + 5 * fpn}
     vol_r = 5 + 1 + 5 + 9 + 24 * fpn + (12 + 24 * fpn if ns else 5)
-    vol_w = 17 + 4 * fpn if ns else 10
+    vol_w = 5 + 4 * fpn if ns else 10
     b["k_adj_volume"] = vol_r + vol_w
     if ns:
         b["k_lift_gradients"] = 15 + 14 * fpn + 12 + 12 * fpn
-        b["k_adj_lift_volume"] = 27 + 13 * fpn + 15 + 10
+        b["k_adj_lift_volume"] = 16 + 13 * fpn + 10 + 5 * fpn
     return {k: 8.0 * v for k, v in b.items()}
 
 

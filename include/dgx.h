@@ -169,7 +169,7 @@ size_t dg_workspace_bytes(const dg_ctx* ctx);
 /* Bytes of device scratch that the adjoint calls need (the forward scratch
  * plus the recomputed stage states, four for LSERK4(5) and thirteen for
  * LSERK4-14, an RK register, an adjoint residual and, for Navier-Stokes, the
- * gradient adjoint and its face values).  Valid after a mesh is set. */
+ * face values of the gradient adjoint).  Valid after a mesh is set. */
 size_t dg_workspace_bytes_adjoint(const dg_ctx* ctx);
 
 /* Binds caller-owned device memory of at least dg_workspace_bytes bytes,

@@ -84,17 +84,20 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_trace(Geo G, const double
   adj_surface_of<N, NODES>(G, sb, sl, e, t, Lbar);
 }
 
-// Volume and surface adjoint of the residual; Navier-Stokes also writes the
-// gradient adjoint gbar[12][e][node] (from the viscous volume and surface
-// terms) and the face part of the lifting adjoint,
+// Volume and surface adjoint of the residual.  Navier-Stokes: the gradient
+// adjoint gbar (from the viscous volume and surface terms) flows back through
+// the lifting g = lift(U) here as far as that is element-local: its volume
+// part, out += (dq/dU)^T qbar with qbar = -sum_r Ja^r . sum_a Dhat[a][l]
+// (sJ gbar)_a along the lines, and the face values of its surface part,
 //   Qbar[slot][4][side][fi] = sum_a (1/w_a) l_a(+-1) sum_d (sJ gbar)_{q,d} (n s)_d,out
-// along each face node's normal line (element-local once gbar is known).
+// along each face node's normal line, which k_adj_lift_volume takes from
+// both sides of every face.
 //
 // Phases, so that live ranges do not stack:
 //   1. each side's flux adjoint (own part) -> LDS, accumulated by the nodes;
 //   2. the weak-form parts along every line (Euler weak form; the viscous
-//      volume term), after which gbar is written and the gradients are dead;
-//      (Navier-Stokes) sJ gbar -> LDS and the faces' Qbar;
+//      volume term), after which the gradients are dead; (Navier-Stokes)
+//      sJ gbar -> LDS, the lifting adjoint's volume part and the faces' Qbar;
 //   3. split form: per direction r the metric row -> LDS, then the pairs.
 //      The weight of the pair (m, l) is w = -(DS[m][l] lt_m + DS[l][m] lt_l)
 //      for both of its nodes, and F# is symmetric, so one reverse sweep of
@@ -121,7 +124,7 @@ template <int N, int NODES, int FORM, int PHYS, int ROE = 0, int VL = 0>
 __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVES : 1)) void k_adj_volume(
     Geo G, Phys P, const double* __restrict__ U, const double* lam, const double* __restrict__ Utr,
     const double* __restrict__ Lbar, const double* __restrict__ gin, const double* __restrict__ gtr,
-    double* __restrict__ out, double* __restrict__ gbar, double* __restrict__ Qbar, AdjUpd up) {
+    double* __restrict__ out, double* __restrict__ Qbar, AdjUpd up) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
   constexpr bool ES = FORM == 1 && NODES == 0;
@@ -316,10 +319,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
       }
       if constexpr (PHYS == 1) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          gbar[((size_t)c * nE + e) * n3 + t] = gb[c];
-          sB[c * n3 + t] = sJ * gb[c];   // (the surface adjoints in sB are consumed)
-        }
+        for (int c = 0; c < 12; ++c) sB[c * n3 + t] = sJ * gb[c];   // (the surface adjoints in sB are consumed)
         double Uu[5];
         prim_vjp(q, P.gm1, rpb[0], ub, rpb[1], Uu);
 #pragma unroll
@@ -369,6 +369,34 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
       // (values qa of one face node are nS n2 apart in the [slot][4][side][fi] layout)
 #pragma unroll
       for (int qa = 0; qa < 4; ++qa) Qbar[qi + (size_t)qa * nS * n2] = acc[qa];
+    }
+    // the lifting adjoint's volume part: qbar = -sum_r Ja^r . (Dhat^T (sJ gbar))_r
+    if (act) {
+      if (!kPrefetch) load_u();
+      double qb[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int l = idx[r];
+        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+        if (!kPrefetch) load_row(r);
+        double T[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) T[c] = 0.0;
+#pragma unroll
+        for (int a = 0; a < n1; ++a) {
+          const double c = sb.Dhat[a * n1 + l];
+          const int ta = line_node<N>(r, a, pp, qq);
+#pragma unroll
+          for (int cc = 0; cc < 12; ++cc) T[cc] += c * sg[cc * n3 + ta];
+        }
+#pragma unroll
+        for (int qa = 0; qa < 4; ++qa)
+          qb[qa] -= jn[3 * r] * T[3 * qa] + jn[3 * r + 1] * T[3 * qa + 1] + jn[3 * r + 2] * T[3 * qa + 2];
+      }
+      double Uq[5];
+      qvars_vjp(cons2prim(un, P.gm1), P.gm1, P.Rinv, qb, Uq);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ub[v] += Uq[v];
     }
     __syncthreads();
   }
@@ -591,19 +619,21 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
   }
 }
 
-// Lifting adjoint, volume and face parts: out += (dq/dU)^T qbar.  EP 1 (split
-// form on Gauss nodes): the face values are the projected traces, so their
-// adjoints go back through the projection ((du/dv)^T at the face node, l_f
-// along the line, (dv/dU)^T at the node).
+// Lifting adjoint, face part (the volume part is in k_adj_volume):
+// out += (dq/dU)^T qbar at each face node's own trace, with qbar the mean of
+// both sides' Qbar.  EP 1 (split form on Gauss nodes): the face values are
+// the projected traces, so their adjoints go back through the projection
+// ((du/dv)^T at the face node, l_f along the line, (dv/dU)^T at the node).
+// With up.lamU it is the stage's last kernel: it applies the reverse RK
+// update and writes the surface adjoint of the new lamdU to up.Lnext.
 template <int N, int NODES, int EP = 0>
 __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_volume(Geo G, Phys P, const double* __restrict__ U,
                                                                    const double* __restrict__ Utr,
-                                                                   const double* __restrict__ gbar,
                                                                    const double* __restrict__ Qbar,
                                                                    double* __restrict__ out, AdjUpd up) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, n2 = S::n2, n3 = S::n3;
-  constexpr int SZ = 12 * n3 > 5 * S::nface ? 12 * n3 : 5 * S::nface;
+  constexpr int SZ = 5 * S::nface > 5 * n3 ? 5 * S::nface : 5 * n3;
   __shared__ double sm[SZ];
   __shared__ DevBasis sb;
   const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
@@ -612,42 +642,8 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_volume(Geo G, Phys P
   const bool act = t < n3;
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   const int idx[3] = {i, j, k};
-  double* sg = sm;
   const double sJ = act ? G.sJ[(size_t)e * n3 + t] : 0.0;
-  if (act) {
-#pragma unroll
-    for (int c = 0; c < 12; ++c) sg[c * n3 + t] = sJ * gbar[((size_t)c * nE + e) * n3 + t];
-  }
-  __syncthreads();
   double Ub[5] = {0, 0, 0, 0, 0};
-  if (act) {
-    double u[5], ja[9];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) ja[c] = G.Ja[((size_t)c * nE + e) * n3 + t];
-    double qb[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const int l = idx[r];
-      const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
-      double T[12];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) T[c] = 0.0;
-#pragma unroll
-      for (int a = 0; a < n1; ++a) {
-        const double c = sb.Dhat[a * n1 + l];
-        const int ta = line_node<N>(r, a, pp, qq);
-#pragma unroll
-        for (int cc = 0; cc < 12; ++cc) T[cc] += c * sg[cc * n3 + ta];
-      }
-#pragma unroll
-      for (int qa = 0; qa < 4; ++qa)
-        qb[qa] -= ja[3 * r] * T[3 * qa] + ja[3 * r + 1] * T[3 * qa + 1] + ja[3 * r + 2] * T[3 * qa + 2];
-    }
-    const Prim q = cons2prim(u, P.gm1);
-    qvars_vjp(q, P.gm1, P.Rinv, qb, Ub);
-  }
   __syncthreads();
   double* sfb = sm;  // [6][5][n2]
   for (int ft = t; ft < S::nface; ft += S::nth) {

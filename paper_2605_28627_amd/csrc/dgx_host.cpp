@@ -779,8 +779,9 @@ dg_status dg_sizes(const dg_ctx* cc, int* nElems, int* nSides, int* npe, size_t*
 struct WsLayout {
   size_t utr[2], gtr, g, red, fvind, flag, total;
   // adjoint region: recomputed stage states Y_1..Y_{S-1}, forward RK
-  // register, adjoint residual, gradient adjoint (Navier-Stokes)
-  size_t Y[DG_RK_MAX_STAGES - 1], dUf, aout, gbar, qbar, total_adjoint;
+  // register, adjoint residual, face values of the gradient adjoint
+  // (Navier-Stokes)
+  size_t Y[DG_RK_MAX_STAGES - 1], dUf, aout, qbar, total_adjoint;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -819,7 +820,6 @@ static WsLayout ws_layout(const dg_ctx* c) {
   for (int k = 0; k + 1 < rk_stages(c); ++k) { L.Y[k] = off; off += st; }
   L.dUf = off; off += st;
   L.aout = off; off += st;
-  L.gbar = off; off += ns ? align256(12 * nv * sizeof(double)) : 0;
   L.qbar = off; off += ns ? align256(2 * 4 * nf * sizeof(double)) : 0;
   L.total_adjoint = off;
   return L;
@@ -1057,7 +1057,6 @@ static dg_status adjoint_residual(dg_ctx* c, const double* U, const double* lam,
   Geo g = kgeo(c);
   Work w = kwork(c);
   WsLayout L = ws_layout(c);
-  double* gbar = k.physics == DG_PHYS_NAVIER_STOKES ? (double*)(c->ws + L.gbar) : nullptr;
   double* qbar = k.physics == DG_PHYS_NAVIER_STOKES ? (double*)(c->ws + L.qbar) : nullptr;
   {
     ProfScope ps(c, FAM_TRACE, s);
@@ -1068,7 +1067,7 @@ static dg_status adjoint_residual(dg_ctx* c, const double* U, const double* lam,
     LAUNCHCHK(c, launch_lift(k, 0, g, c->phys, U, w.Utr[0], w.g, w.gtr, s));
   }
   ProfScope ps(c, FAM_ADJOINT, s);
-  LAUNCHCHK(c, launch_adjoint(k, g, c->phys, U, lam, w.Utr[0], w.Utr[1], w.g, w.gtr, out, gbar, qbar, up, s));
+  LAUNCHCHK(c, launch_adjoint(k, g, c->phys, U, lam, w.Utr[0], w.Utr[1], w.g, w.gtr, out, qbar, up, s));
   return DG_OK;
 }
 

@@ -211,7 +211,7 @@ hipError_t DGX_NAME(launch_fv_switch)(const Cfg& c, const Geo& g, double* U, dou
 
 hipError_t DGX_NAME(launch_adjoint)(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* lam,
                                     const double* Utr, double* Lbar, const double* gin, const double* gtr,
-                                    double* out, double* gbar, double* qbar, const AdjUpd& up, hipStream_t s) {
+                                    double* out, double* qbar, const AdjUpd& up, hipStream_t s) {
   // the fused RK update goes into the last kernel: the volume adjoint (Euler)
   // or the lifting adjoint (Navier-Stokes)
   const AdjUpd none{nullptr, nullptr, 0.0, 0.0, 0.0};
@@ -227,7 +227,7 @@ hipError_t DGX_NAME(launch_adjoint)(const Cfg& c, const Geo& g, const Phys& p, c
   // volume + surface adjoint
 #define DGX_ADJ_V(NODES, FORM, PHYS, ROE, VL)                                                                  \
   hipLaunchKernelGGL((k_adj_volume<kN, NODES, FORM, PHYS, ROE, VL>), grid, block, 0, s, g, p, U, lam, Utr, Lbar, gin, \
-                     gtr, out, gbar, qbar, upv)
+                     gtr, out, qbar, upv)
   // (Sutherland's law only matters with viscous terms)
 #define DGX_ADJ(NODES, FORM, PHYS)                                       \
   do {                                                                   \
@@ -253,11 +253,11 @@ hipError_t DGX_NAME(launch_adjoint)(const Cfg& c, const Geo& g, const Phys& p, c
   if (c.physics == 1) {
     // lifting adjoint (its face values in qbar, written by the volume adjoint)
     if (c.nodes == 1)
-      hipLaunchKernelGGL((k_adj_lift_volume<kN, 1>), grid, block, 0, s, g, p, U, Utr, gbar, qbar, out, up);
+      hipLaunchKernelGGL((k_adj_lift_volume<kN, 1>), grid, block, 0, s, g, p, U, Utr, qbar, out, up);
     else if (c.form == 1)
-      hipLaunchKernelGGL((k_adj_lift_volume<kN, 0, 1>), grid, block, 0, s, g, p, U, Utr, gbar, qbar, out, up);
+      hipLaunchKernelGGL((k_adj_lift_volume<kN, 0, 1>), grid, block, 0, s, g, p, U, Utr, qbar, out, up);
     else
-      hipLaunchKernelGGL((k_adj_lift_volume<kN, 0>), grid, block, 0, s, g, p, U, Utr, gbar, qbar, out, up);
+      hipLaunchKernelGGL((k_adj_lift_volume<kN, 0>), grid, block, 0, s, g, p, U, Utr, qbar, out, up);
   }
   return hipGetLastError();
 }

@@ -121,13 +121,13 @@ struct AdjUpd {
 };
 
 // out = (dR/dU)^T lam (or, with up.lamU, the fused update); Utr holds the
-// traces of U, Lbar/gbar/qbar are scratch (Navier-Stokes: gin/gtr hold the
+// traces of U, Lbar/qbar are scratch (Navier-Stokes: gin/gtr hold the
 // forward lifted gradients and their traces, qbar [2][4][nSides][n2] takes
 // the lifting adjoint's face values, and out is scratch too when the update
 // is fused).
 hipError_t launch_adjoint(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* lam,
                           const double* Utr, double* Lbar, const double* gin, const double* gtr, double* out,
-                          double* gbar, double* qbar, const AdjUpd& up, hipStream_t s);
+                          double* qbar, const AdjUpd& up, hipStream_t s);
 // FV sub-cells.  Traces of an FV context hold 10 values per face node: the DG
 // trace (values 0..4) on DG faces; on FV faces the primitive means of the
 // first (0..4) and second (5..9) sub-cell layers under the face.

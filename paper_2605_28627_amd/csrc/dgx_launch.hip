@@ -49,7 +49,7 @@ hipError_t static_scratch(void** ptr) {
                                 double, double, hipStream_t);                                                  \
   hipError_t launch_adjoint_N##n(const Cfg&, const Geo&, const Phys&, const double*, const double*,          \
                                  const double*, double*, const double*, const double*, double*, double*,       \
-                                 double*, const AdjUpd&, hipStream_t);                                          \
+                                 const AdjUpd&, hipStream_t);                                                   \
   hipError_t launch_trace_fv_N##n(const Cfg&, const Geo&, const Phys&, const double*, double*, hipStream_t);   \
   hipError_t launch_fv_N##n(const Cfg&, const Geo&, const Phys&, int, const double*, const double*,         \
                             const double*, const double*, double*, double*, double*, double*, double, double,  \
@@ -170,8 +170,8 @@ hipError_t launch_volume(const Cfg& c, const Geo& g, const Phys& p, int mode, co
 
 hipError_t launch_adjoint(const Cfg& c, const Geo& g, const Phys& p, const double* U, const double* lam,
                           const double* Utr, double* Lbar, const double* gin, const double* gtr, double* out,
-                          double* gbar, double* qbar, const AdjUpd& up, hipStream_t s) {
-#define ARGS (c, g, p, U, lam, Utr, Lbar, gin, gtr, out, gbar, qbar, up, s)
+                          double* qbar, const AdjUpd& up, hipStream_t s) {
+#define ARGS (c, g, p, U, lam, Utr, Lbar, gin, gtr, out, qbar, up, s)
   DGX_SWITCH(launch_adjoint)
 #undef ARGS
 }
