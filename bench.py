@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--fp32-reference", default="workload", choices=["workload", "none"],
                     help="reference state of the FP32-flux arithmetic: the workload's background, or none")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-element-metrics", action="store_true",
+                    help="every element reads its metric terms from the node arrays (the paper's per-node "
+                         "storage), also where they are constant over the element")
     ap.add_argument("--fv-switch-every-step", action="store_true",
                     help="with --fv: one dg_rk_step call per step, each followed by the indicator and the "
                          "switch (hysteresis window (-inf, inf), so the element types stay as set), as a "
@@ -199,10 +202,20 @@ def volume_kernel_name(w, precision=0, roe=0):
     return f"void dgx::k_volume<{w['N']}, {w['nodes']}, {w['form']}, {w['physics']}, {precision}, 1, {roe}, 0>"
 
 
-def volume_kernel_bytes_per_dof(w, precision=0):
+def metric_values_per_dof(w, elem_frac=0.0, nvals=10):
+    """Metric values a kernel reads per node: nvals (Ja 9 and 1/J 1, or 1/J
+    alone) at every node of an element that reads the node arrays, and once
+    per element (nvals / (N+1)^3 per node) for the fraction elem_frac of
+    elements with constant terms, which read the per-element copy."""
+    n3 = (w["N"] + 1) ** 3
+    return nvals * (1.0 - elem_frac) + nvals * elem_frac / n3
+
+
+def volume_kernel_bytes_per_dof(w, precision=0, elem_frac=0.0):
     """Compulsory HBM bytes of one launch of the residual/RK kernel, per node.
 
-    Reads: U (5), metrics Ja (9) and 1/J (1), dU (5, except in the first of
+    Reads: U (5), metrics Ja (9) and 1/J (1) (metric_values_per_dof: once per
+    element where they are constant), dU (5, except in the first of
     the five stages, whose A is 0: 4 on average), and per face node of
     each of the element's 6 faces both sides' traces (2 x 5) and the face
     normal + area (4); Navier-Stokes adds the viscous volume term (4) and
@@ -213,27 +226,28 @@ def volume_kernel_bytes_per_dof(w, precision=0):
     """
     n1 = w["N"] + 1
     fpn = 6 * n1 * n1 / n1 ** 3          # face nodes of one element per volume node
-    reads = 5 + 9 + 1 + 4 + fpn * (10 + 4)
+    reads = 5 + metric_values_per_dof(w, elem_frac) + 4 + fpn * (10 + 4)
     writes = 5 + 5 + fpn * 5
     if w["physics"] == 1:
         reads += 4 + fpn * 8 * (0.5 if precision == 1 else 1.0)
     return 8.0 * (reads + writes)
 
 
-def lift_kernel_bytes_per_dof(w, precision=0):
+def lift_kernel_bytes_per_dof(w, precision=0, elem_frac=0.0):
     """Compulsory HBM bytes of one launch of the lifting kernel (the forward
-    stages' variant), per node.  Reads: U (5), Ja (9), 1/J (1), and per face
+    stages' variant), per node.  Reads: U (5), Ja (9), 1/J (1) (as in the
+    residual kernel), and per face
     node both sides' traces (2 x 5) and the face normal + area (4).  Writes:
     the viscous volume term (4) and the element's own face-normal viscous
     flux (4 per face node; 4 bytes each in the FP32-flux mode)."""
     n1 = w["N"] + 1
     fpn = 6 * n1 * n1 / n1 ** 3
-    reads = 5 + 9 + 1 + fpn * (10 + 4)
+    reads = 5 + metric_values_per_dof(w, elem_frac) + fpn * (10 + 4)
     writes = 4 + fpn * 4 * (0.5 if precision == 1 else 1.0)
     return 8.0 * (reads + writes)
 
 
-def adjoint_kernel_bytes_per_dof(w):
+def adjoint_kernel_bytes_per_dof(w, elem_frac=0.0):
     """Compulsory HBM bytes per node of one launch of each kernel of an
     adjoint stage (dg_adjoint_rk_step; the stage's reverse RK update fused
     into its last kernel), 8 bytes per value, per face node values times
@@ -250,18 +264,20 @@ def adjoint_kernel_bytes_per_dof(w):
         Qbar 4 fpn; Euler: lamU 5 read, lamU and lamdU 10 written);
       k_adj_lift_volume (Navier-Stokes): 1/J 1, the own trace 5 fpn, both
         Qbar 8 fpn, out 5, lamU 5, lamdU 5; writes lamU and lamdU 10 and the
-        next stage's surface adjoint 5 fpn."""
+        next stage's surface adjoint 5 fpn.
+    Ja and 1/J as in the residual kernel (metric_values_per_dof)."""
     n1 = w["N"] + 1
     fpn = 6 * n1 * n1 / n1 ** 3
     ns = w["physics"] == 1
+    m10, m1 = metric_values_per_dof(w, elem_frac), metric_values_per_dof(w, elem_frac, 1)
     b = {"k_trace": 5 + 5 * fpn,
-         "k_adj_trace": 6 + 5 * fpn}
-    vol_r = 5 + 1 + 5 + 9 + 24 * fpn + (12 + 24 * fpn if ns else 5)
+         "k_adj_trace": 5 + m1 + 5 * fpn}
+    vol_r = 5 + 5 + m10 + 24 * fpn + (12 + 24 * fpn if ns else 5)
     vol_w = 5 + 4 * fpn if ns else 10
     b["k_adj_volume"] = vol_r + vol_w
     if ns:
-        b["k_lift_gradients"] = 15 + 14 * fpn + 12 + 12 * fpn
-        b["k_adj_lift_volume"] = 16 + 13 * fpn + 10 + 5 * fpn
+        b["k_lift_gradients"] = 5 + m10 + 14 * fpn + 12 + 12 * fpn
+        b["k_adj_lift_volume"] = m1 + 15 + 13 * fpn + 10 + 5 * fpn
     return {k: 8.0 * v for k, v in b.items()}
 
 
@@ -333,6 +349,9 @@ def main():
     mesh = I.workload_mesh(args.workload, K=K)
     _log("solver set-up")
     s = DGSolver(cfg, mesh, dev)
+    if args.no_element_metrics:
+        s.set_element_metrics(False)
+    n_elem_metric = s.element_metric_count()
     dof = s.nElems * s.npe
     xyz = s.coords()
     U_host = I.workload_state(args.workload, xyz, state=args.state)
@@ -403,7 +422,9 @@ def main():
     vol_avg_s = vol_ms * 1e-3 / max(vol_n, 1)
     lift_ms, lift_n = prof["lift"]
     npe = (w["N"] + 1) ** 3
-    bytes_launch = volume_kernel_bytes_per_dof(w) * (dof - nfv * npe)
+    # (FV contexts: the residual kernel reads the node arrays)
+    elem_frac = 0.0 if args.fv != "none" else n_elem_metric / s.nElems
+    bytes_launch = volume_kernel_bytes_per_dof(w, elem_frac=elem_frac) * (dof - nfv * npe)
     kfam = "k_volume"
     if nfv:
         # the roofline of the dominant family: DG elements (k_volume) or FV elements (k_fv)
@@ -442,7 +463,8 @@ def main():
                    "integrator": ("LSERK4(5)", "LSERK4-14")[args.integrator], "stages_per_step": nst,
                    "riemann": args.riemann, "viscosity": args.viscosity,
                    "state": args.state or w["state"], "fv_elements": nfv,
-                   "fv_mask": args.fv, "fv_switch_every_step": bool(args.fv_switch_every_step)},
+                   "fv_mask": args.fv, "fv_switch_every_step": bool(args.fv_switch_every_step),
+                   "elements_with_element_metrics": n_elem_metric},
         "dof_updates_per_s": 1.0 / pid64,
         "simulated_time_per_wall_s": dt * args.steps / t64,
         "reps": args.reps,
@@ -473,7 +495,7 @@ def main():
                                                   "from the committed rocprofv3 summary"}
     if lift_n:
         result["kernels_ms_per_launch"]["lift"] = lift_ms / lift_n
-        lb = lift_kernel_bytes_per_dof(w) * dof
+        lb = lift_kernel_bytes_per_dof(w, elem_frac=n_elem_metric / s.nElems) * dof
         lgbs = lb / (lift_ms * 1e-3 / lift_n) / 1e9
         result["roofline_lift"] = {"bound": "hbm", "kernel": "k_lift (BR1 lifting, forward stages)",
                                    "achieved": lgbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": lgbs / HBM_PEAK_GBS,
@@ -484,6 +506,8 @@ def main():
     if not args.no_fp32:
         cfg32 = dict(cfg, precision=1)
         s32 = DGSolver(cfg32, mesh, dev)
+        if args.no_element_metrics:
+            s32.set_element_metrics(False)
         ref32 = I.workload_reference(args.workload, state=args.state) if args.fp32_reference == "workload" else (0, 0)
         s32.set_reference_state(*ref32)
         result["fp32_reference_state"] = {"rho0": ref32[0], "p0": ref32[1]}
@@ -532,6 +556,8 @@ def adjoint_cost(cfg, mesh, dev, U0, dt, args):
     from paper_2605_28627_amd.autograd import checkpoint_plan, kinetic_energy, trajectory
     from paper_2605_28627_amd.solver import DGSolver
     sa = DGSolver(cfg, mesh, dev, adjoint=True)
+    if args.no_element_metrics:
+        sa.set_element_metrics(False)
     n = args.adjoint_steps
     if args.checkpoint_every:
         every, keep = args.checkpoint_every, args.checkpoint_every - 1

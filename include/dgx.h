@@ -136,7 +136,10 @@ dg_status dg_rk_coefficients(int integrator, double* A, double* B, double* c, in
  * metric terms in conservative curl form (paper: mapping chi, Jacobian J,
  * contravariant fluxes; Kopriva 2006 curl form), the Jacobian and the master
  * face normals.  No device work.  DG_ERR_MESH on bad connectivity or a
- * non-positive Jacobian at any node. */
+ * non-positive Jacobian at any node.  An element whose nine metric components
+ * and 1/J each vary by at most 1e-12 of their largest magnitude over its nodes
+ * (an affine element: the exact terms are constant) gets their node mean at
+ * every node, so that its terms are exactly constant. */
 dg_status dg_set_mesh(dg_ctx* ctx, int nElems, int Ngeo, const double* X, int nSides,
                       const int* side_elem, const int* side_loc, const int* side_orient);
 
@@ -153,6 +156,20 @@ dg_status dg_upload_metrics(dg_ctx* ctx, const double* Ja, const double* sJ, con
 /* Host copies of the metrics computed by dg_set_mesh (any pointer may be NULL):
  * xyz[3][nElems][n3], Ja[9][nElems][n3], sJ[nElems][n3], nvec[3][nSides][n2]. */
 dg_status dg_get_metrics(const dg_ctx* ctx, double* xyz, double* Ja, double* sJ, double* nvec);
+
+/* Per-element metric terms.  An element whose metric terms (Ja and 1/J) are
+ * bitwise the same at all of its nodes has them stored once more, per
+ * element, and the residual, lifting and adjoint kernels read that copy
+ * instead of the node arrays: 80 bytes per node less per kernel, with
+ * results bitwise equal to the node-array path.  On by default; enable = 0
+ * sends every element to the node arrays (the paper's per-node storage).
+ * Takes effect at once when a mesh is on the device, else at its upload;
+ * metrics replaced by dg_upload_metrics are examined again. */
+dg_status dg_set_element_metrics(dg_ctx* ctx, int enable);
+
+/* Number of elements whose kernels read the per-element metric terms.
+ * DG_ERR_STATE before dg_upload_mesh. */
+dg_status dg_element_metric_count(const dg_ctx* ctx, int* count);
 
 /* Node coordinates xyz[3][nElems][n3] (host) for building initial states. */
 dg_status dg_node_coords(const dg_ctx* ctx, double* xyz_host);

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_trace(Geo G, const double
   const int nE = G.nElems;
   load_basis(&sb, G.basis, t, S::nth);
   if (t < n3) {
-    const double sJ = G.sJ[(size_t)e * n3 + t];
+    const double sJ = node_metric(G, e, n3, t).sj();
 #pragma unroll
     for (int v = 0; v < 5; ++v) sl[v * n3 + t] = sJ * lam[((size_t)v * nE + e) * n3 + t];
   }
@@ -144,7 +144,8 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
   const bool act = t < n3;
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   const int idx[3] = {i, j, k};
-  const double sJ = act ? G.sJ[(size_t)e * n3 + t] : 0.0;
+  const NodeMetric nm = node_metric(G, e, n3, t);
+  const double sJ = act ? nm.sj() : 0.0;
   if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) sl[v * n3 + t] = sJ * lam[((size_t)v * nE + e) * n3 + t];
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
   };
   auto load_row = [&](int r) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) jn[3 * r + c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
+    for (int c = 0; c < 3; ++c) jn[3 * r + c] = nm.ja(3 * r + c);
   };
   auto load_g = [&]() {
     if constexpr (PHYS == 1) {
@@ -423,7 +424,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
       if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          if (!kPrefetch) jn[3 * r + c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
+          if (!kPrefetch) jn[3 * r + c] = nm.ja(3 * r + c);
           jr[c] = jn[3 * r + c];
           sja[c * n3 + t] = jr[c];
         }
@@ -642,7 +643,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_adj_lift_volume(Geo G, Phys P
   const bool act = t < n3;
   const int i = t % n1, j = (t / n1) % n1, k = t / n2;
   const int idx[3] = {i, j, k};
-  const double sJ = act ? G.sJ[(size_t)e * n3 + t] : 0.0;
+  const double sJ = act ? node_metric(G, e, n3, t).sj() : 0.0;
   double Ub[5] = {0, 0, 0, 0, 0};
   __syncthreads();
   double* sfb = sm;  // [6][5][n2]

@@ -35,8 +35,11 @@ struct dg_ctx {
   std::vector<double> wJ;               // quadrature weight times J: [nE][n3]
   double volume = 0.0;
   // device (library-owned)
-  double* d_Ja = nullptr;
+  double* d_Ja = nullptr;               // [10][nE][n3]: Ja, then 1/J (d_sJ = d_Ja + 9 nE n3)
   double* d_sJ = nullptr;
+  double* d_em = nullptr;               // [10][nE]: constant metric terms per element (Geo::em)
+  bool elem_metrics = true;             // kernels take constant elements' terms from d_em
+  int n_const_metric = 0;               // elements with constant metric terms in d_em
   double* d_face = nullptr;
   int* d_efc = nullptr;
   DevBasis* d_basis = nullptr;
@@ -404,8 +407,8 @@ static void free_events(dg_ctx* c) {
 }
 
 static void free_device(dg_ctx* c) {
-  if (c->d_Ja) (void)hipFree(c->d_Ja);
-  if (c->d_sJ) (void)hipFree(c->d_sJ);
+  if (c->d_Ja) (void)hipFree(c->d_Ja);   // (d_sJ lies in the same allocation)
+  if (c->d_em) (void)hipFree(c->d_em);
   if (c->d_face) (void)hipFree(c->d_face);
   if (c->d_efc) (void)hipFree(c->d_efc);
   if (c->d_basis) (void)hipFree(c->d_basis);
@@ -413,7 +416,8 @@ static void free_device(dg_ctx* c) {
     if (*p) { (void)hipFree(*p); *p = nullptr; }
   for (int** p : {&c->d_etype, &c->d_etype_new, &c->d_sidefv, &c->d_efv, &c->d_side_elem})
     if (*p) { (void)hipFree(*p); *p = nullptr; }
-  c->d_Ja = c->d_sJ = c->d_face = nullptr;
+  c->d_Ja = c->d_sJ = c->d_em = c->d_face = nullptr;
+  c->n_const_metric = 0;
   c->d_efc = nullptr;
   c->d_basis = nullptr;
   c->mesh_on_device = false;
@@ -444,6 +448,65 @@ dg_status dg_set_reference_state(dg_ctx* c, double rho0, double p0) {
 // ---------------------------------------------------------------------------
 // Mesh and metrics
 // ---------------------------------------------------------------------------
+// An affine element (x = x0 + A xi) has constant metric terms, Ja = cof(A)
+// and J = det(A); computed node by node they still differ in the last bits
+// (the curl form sums D-weighted products).  When every one of the nine
+// components and 1/J stays within 1e-12 of its largest magnitude over the
+// element's nodes, every node is given the element's mean instead: the
+// terms then are exactly constant, which the kernels recognise (elem_metrics).
+// Ja points at component 0 of the element (components stride cs), sJ at its 1/J.
+static void snap_affine(double* Ja, size_t cs, double* sJ, int n3) {
+  double mean[10];
+  for (int c = 0; c < 10; ++c) {
+    const double* v = c < 9 ? Ja + c * cs : sJ;
+    double s = 0.0;
+    for (int t = 0; t < n3; ++t) s += v[t];
+    mean[c] = s / n3;
+  }
+  double scale = 0.0;   // largest metric entry of the element
+  for (int c = 0; c < 9; ++c)
+    for (int t = 0; t < n3; ++t) scale = std::max(scale, std::fabs(Ja[c * cs + t]));
+  for (int c = 0; c < 10; ++c) {
+    const double* v = c < 9 ? Ja + c * cs : sJ;
+    const double tol = 1e-12 * (c < 9 ? scale : std::fabs(mean[9]));
+    for (int t = 0; t < n3; ++t)
+      if (!(std::fabs(v[t] - mean[c]) <= tol)) return;
+  }
+  for (int c = 0; c < 10; ++c) {
+    double* v = c < 9 ? Ja + c * cs : sJ;
+    for (int t = 0; t < n3; ++t) v[t] = mean[c];
+  }
+}
+
+// The per-element copy of the metric terms (Geo::em, [10][nE]: Ja^r_n at
+// 3r+n, 1/J at 9) for every element whose terms are bitwise the same at all
+// of its nodes; 1/J = 0 marks the others, whose kernels read the node arrays.
+static dg_status upload_elem_metrics(dg_ctx* c) {
+  const size_t nE = c->nElems, n3 = c->n3;
+  if (!c->d_em) {
+    hipError_t e = hipMalloc((void**)&c->d_em, 10 * nE * sizeof(double));
+    if (e != hipSuccess)
+      return fail(c, e == hipErrorOutOfMemory ? DG_ERR_NOMEM : DG_ERR_HIP,
+                  std::string("element metrics: hipMalloc: ") + hipGetErrorString(e));
+  }
+  std::vector<double> em(10 * nE, 0.0);
+  int count = 0;
+  for (size_t e = 0; e < nE && c->elem_metrics; ++e) {
+    bool same = true;
+    for (int comp = 0; comp < 10 && same; ++comp) {
+      const double* v = comp < 9 ? &c->Ja[(comp * nE + e) * n3] : &c->sJ[e * n3];
+      for (size_t t = 1; t < n3 && same; ++t) same = v[t] == v[0];
+    }
+    if (!same) continue;
+    for (int comp = 0; comp < 9; ++comp) em[comp * nE + e] = c->Ja[(comp * nE + e) * n3];
+    em[9 * nE + e] = c->sJ[e * n3];
+    ++count;
+  }
+  HIPCHK(c, hipMemcpy(c->d_em, em.data(), em.size() * sizeof(double), hipMemcpyHostToDevice));
+  c->n_const_metric = count;
+  return DG_OK;
+}
+
 dg_status dg_set_mesh(dg_ctx* c, int nElems, int Ngeo, const double* X, int nSides, const int* side_elem,
                       const int* side_loc, const int* side_orient) {
   if (!c) return fail(nullptr, DG_ERR_ARG, "dg_set_mesh: null context");
@@ -521,6 +584,7 @@ dg_status dg_set_mesh(dg_ctx* c, int nElems, int Ngeo, const double* X, int nSid
           for (int t = 0; t < n3; ++t) Ja[((size_t)(3 * r + n) * nElems + e) * n3 + t] = acc[t] - dprod[t];
         }
       }
+      snap_affine(&Ja[(size_t)e * n3], (size_t)nElems * n3, &sJ[(size_t)e * n3], n3);
     }
   };
   {
@@ -676,8 +740,7 @@ dg_status dg_upload_mesh(dg_ctx* c, int nElems, int Ngeo, const double* X, int n
   free_device(c);
   const size_t nv = (size_t)c->nElems * c->n3, nf = (size_t)c->nSides * c->n2;
   hipError_t e;
-  if ((e = hipMalloc((void**)&c->d_Ja, 9 * nv * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc((void**)&c->d_sJ, nv * sizeof(double))) != hipSuccess ||
+  if ((e = hipMalloc((void**)&c->d_Ja, 10 * nv * sizeof(double))) != hipSuccess ||
       (e = hipMalloc((void**)&c->d_face, 4 * nf * sizeof(double))) != hipSuccess ||
       (e = hipMalloc((void**)&c->d_efc, (size_t)c->nElems * 6 * sizeof(int))) != hipSuccess ||
       (e = hipMalloc((void**)&c->d_basis, sizeof(DevBasis))) != hipSuccess) {
@@ -685,11 +748,14 @@ dg_status dg_upload_mesh(dg_ctx* c, int nElems, int Ngeo, const double* X, int n
     return fail(c, e == hipErrorOutOfMemory ? DG_ERR_NOMEM : DG_ERR_HIP,
                 std::string("dg_upload_mesh: hipMalloc: ") + hipGetErrorString(e));
   }
+  c->d_sJ = c->d_Ja + 9 * nv;
   HIPCHK(c, hipMemcpy(c->d_Ja, c->Ja.data(), 9 * nv * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_sJ, c->sJ.data(), nv * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_efc, c->efc.data(), (size_t)c->nElems * 6 * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_basis, &c->hb, sizeof(DevBasis), hipMemcpyHostToDevice));
   st = upload_face(c, c->nvec);
+  if (st != DG_OK) return st;
+  st = upload_elem_metrics(c);
   if (st != DG_OK) return st;
   if (c->cfg.fv) {
     const size_t nE = c->nElems, nS = c->nSides;
@@ -746,6 +812,7 @@ dg_status dg_upload_metrics(dg_ctx* c, const double* Ja, const double* sJ, const
   }
   c->volume = vol;
   dg_status st = upload_face(c, nv3);
+  if (st == DG_OK) st = upload_elem_metrics(c);
   if (st != DG_OK || !c->cfg.fv) return st;
   return build_fv(c);
 }
@@ -758,6 +825,19 @@ dg_status dg_get_metrics(const dg_ctx* cc, double* xyz, double* Ja, double* sJ, 
   if (Ja) std::memcpy(Ja, c->Ja.data(), c->Ja.size() * sizeof(double));
   if (sJ) std::memcpy(sJ, c->sJ.data(), c->sJ.size() * sizeof(double));
   if (nvec) std::memcpy(nvec, c->nvec.data(), c->nvec.size() * sizeof(double));
+  return DG_OK;
+}
+
+dg_status dg_set_element_metrics(dg_ctx* c, int enable) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "dg_set_element_metrics: null context");
+  c->elem_metrics = enable != 0;
+  return c->mesh_on_device ? upload_elem_metrics(c) : DG_OK;
+}
+
+dg_status dg_element_metric_count(const dg_ctx* c, int* count) {
+  if (!c || !count) return fail(const_cast<dg_ctx*>(c), DG_ERR_ARG, "dg_element_metric_count: null pointer");
+  if (!c->mesh_on_device) return fail(const_cast<dg_ctx*>(c), DG_ERR_STATE, "dg_element_metric_count: no mesh on the device");
+  *count = c->n_const_metric;
   return DG_OK;
 }
 
@@ -870,7 +950,7 @@ static Cfg kcfg(const dg_ctx* c) {
 static Geo kgeo(const dg_ctx* c) {
   Geo g;
   g.nElems = c->nElems; g.nSides = c->nSides;
-  g.Ja = c->d_Ja; g.sJ = c->d_sJ; g.face = c->d_face; g.efc = c->d_efc; g.basis = c->d_basis;
+  g.Ja = c->d_Ja; g.sJ = c->d_sJ; g.em = c->d_em; g.face = c->d_face; g.efc = c->d_efc; g.basis = c->d_basis;
   g.etype = c->d_etype; g.sidefv = c->d_sidefv; g.efv = c->d_efv; g.fvV = c->d_fvV; g.fvS = c->d_fvS; g.fvSb = c->d_fvSb;
   return g;
 }

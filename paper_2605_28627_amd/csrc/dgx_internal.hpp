@@ -59,8 +59,12 @@ struct Phys {
 // Everything a kernel needs about the discretisation.
 struct Geo {
   int nElems, nSides;
-  const double* Ja;      // [9][nElems][n3]
-  const double* sJ;      // [nElems][n3]
+  const double* Ja;      // [9][nElems][n3], followed by sJ
+  const double* sJ;      // [nElems][n3] (= Ja + 9 nElems n3)
+  // [10][nElems]: an element's metric terms when they are the same at all of
+  // its nodes (affine elements): Ja^r_n at 3r+n, 1/J at 9; 1/J = 0 (the
+  // sign test em[9][e] > 0) sends the element's kernels to Ja and sJ
+  const double* em;
   const double* face;    // [4][nSides][n2]: unit normal (3), surface element
   const int* efc;        // [nElems][6]
   const DevBasis* basis;

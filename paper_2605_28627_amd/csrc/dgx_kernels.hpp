@@ -254,12 +254,13 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
   double u[5] = {0, 0, 0, 0, 0}, jl[9];
   double fUL[5], fUR[5], fns[4];
   int fslot = 0;
+  const NodeMetric nm = node_metric(G, e, n3, t);
   if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) jl[c] = G.Ja[((size_t)c * nE + e) * n3 + t];
-    sJ = G.sJ[(size_t)e * n3 + t];
+    for (int c = 0; c < 9; ++c) jl[c] = nm.ja(c);
+    sJ = nm.sj();
   }
   if constexpr (kOneFaceNode && !kFvf) {
     if (t < S::nface) face_load(t, fslot, fUL, fUR, fns);
@@ -703,8 +704,14 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   // metric row and added to the accumulator when that direction starts
   // (Gauss split form: read at the end)
   double vvn[4] = {0, 0, 0, 0};
+  // (FV contexts: the node arrays, which keeps the FV-face variants at N = 3
+  // and 5 within four waves per SIMD)
+  const NodeMetric nm = node_metric<FV == 0>(G, e, n3, t);
   auto fetch_end = [&]() {
-    sJn = G.sJ[(size_t)e * n3 + t];
+    if constexpr (FV == 0)
+      sJn = nm.sj();
+    else
+      sJn = G.sJ[(size_t)e * n3 + t];
     if constexpr (MODE == 1) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -716,7 +723,12 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   };
   auto fetch_dir = [&](int r) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) jn[c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
+    for (int c = 0; c < 3; ++c) {
+      if constexpr (FV == 0)
+        jn[c] = nm.ja(3 * r + c);
+      else
+        jn[c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
+    }
     if constexpr (PHYS == 1 && !ES) {
       if (r == 2) {
 #pragma unroll

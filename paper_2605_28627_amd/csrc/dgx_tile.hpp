@@ -35,6 +35,32 @@ __device__ __forceinline__ void load_basis(DevBasis* dst, const DevBasis* src, i
   for (int x = t; x < nd; x += nth) d[x] = s[x];
 }
 
+// Where node t of element e finds its metric terms: component c (Ja^r_n at
+// c = 3r+n, 1/J at c = 9) at base[off + c st].  Both stores are [10][...]:
+// the node arrays (Ja, then sJ) and, for every element whose terms are the
+// same at all of its nodes (affine), the per-element copy G.em, whose 1/J is
+// positive exactly for those elements.  Such an element's nodes all read the
+// copy and the node arrays are not touched (same values, same results).
+// Selects only, no branches; base and st are uniform over the workgroup.
+struct NodeMetric {
+  const double* base;
+  size_t off, st;
+  __device__ __forceinline__ double ja(int c) const { return base[off + c * st]; }
+  __device__ __forceinline__ double sj() const { return base[off + 9 * st]; }
+};
+// ELEM = false: always the node arrays (kernels whose register budget has no
+// room for the selects).
+template <bool ELEM = true>
+__device__ __forceinline__ NodeMetric node_metric(const Geo& G, int e, int n3, int t) {
+  const size_t nE = G.nElems;
+  const bool el = ELEM && G.em[9 * nE + e] > 0.0;
+  NodeMetric m;
+  m.base = el ? G.em : G.Ja;
+  m.off = el ? (size_t)e : (size_t)e * n3 + t;
+  m.st = el ? nE : nE * n3;
+  return m;
+}
+
 // Element of a one-element-per-workgroup launch.  Consecutive workgroups are
 // dealt round-robin to the chip's 8 XCDs, each with its own L2.  With
 // XCD-aware numbering (DGX_XCD_REMAP 1) XCD x walks a contiguous block of

@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_MESH", 3: "DG_ERR_HIP", 
 
 # public symbols of include/dgx.h
 SYMBOLS = ["dg_create", "dg_destroy", "dg_set_reference_state", "dg_last_error", "dg_lserk_coefficients", "dg_rk_coefficients", "dg_set_mesh", "dg_upload_mesh",
-           "dg_upload_metrics", "dg_get_metrics", "dg_node_coords", "dg_sizes", "dg_workspace_bytes",
+           "dg_upload_metrics", "dg_get_metrics", "dg_set_element_metrics", "dg_element_metric_count", "dg_node_coords", "dg_sizes", "dg_workspace_bytes",
            "dg_workspace_bytes_adjoint", "dg_bind_workspace", "dg_init_state", "dg_rhs", "dg_lift", "dg_rk_step", "dg_rk_step_noalloc", "dg_rk_step_stages", "dg_adjoint_rhs", "dg_adjoint_rk_step",
            "dg_adjoint_rk_step_stages",
            "dg_kinetic_energy", "dg_kinetic_energy_grad", "dg_timestep", "dg_check_state", "dg_profile",
@@ -71,6 +71,8 @@ _sig = {
     "dg_upload_mesh": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _ip, _ip, _ip]),
     "dg_upload_metrics": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "dg_get_metrics": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
+    "dg_set_element_metrics": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "dg_element_metric_count": (ctypes.c_int, [_vp, _ip]),
     "dg_node_coords": (ctypes.c_int, [_vp, _dp]),
     "dg_sizes": (ctypes.c_int, [_vp, _ip, _ip, _ip, ctypes.POINTER(_sz)]),
     "dg_workspace_bytes": (_sz, [_vp]),
@@ -217,6 +219,16 @@ def dg_get_metrics(ctx):
     nv = np.zeros((3, ns, n1, n1))
     _check(ctx, _L.dg_get_metrics(ctx, _hd(xyz), _hd(Ja), _hd(sJ), _hd(nv)))
     return xyz, Ja, sJ, nv
+
+
+def dg_set_element_metrics(ctx, enable: bool):
+    _check(ctx, _L.dg_set_element_metrics(ctx, 1 if enable else 0))
+
+
+def dg_element_metric_count(ctx) -> int:
+    n = ctypes.c_int(0)
+    _check(ctx, _L.dg_element_metric_count(ctx, ctypes.byref(n)))
+    return n.value
 
 
 def dg_node_coords(ctx):

@@ -93,6 +93,13 @@ class DGSolver:
     def upload_metrics(self, Ja, sJ, nvec):
         dgx.dg_upload_metrics(self.ctx, Ja, sJ, nvec)
 
+    def set_element_metrics(self, enable: bool):
+        """Per-element metric terms for elements whose terms are constant (default on)."""
+        dgx.dg_set_element_metrics(self.ctx, enable)
+
+    def element_metric_count(self) -> int:
+        return dgx.dg_element_metric_count(self.ctx)
+
     def to_device(self, U: np.ndarray) -> torch.Tensor:
         """Any host array of the state shape (a state, an adjoint vector, a direction) on the device."""
         return torch.from_numpy(np.ascontiguousarray(U, dtype=np.float64)).to(self.device).reshape(self.state_shape)
