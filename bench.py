@@ -236,13 +236,15 @@ def volume_kernel_bytes_per_dof(w, precision=0, elem_frac=0.0):
 def lift_kernel_bytes_per_dof(w, precision=0, elem_frac=0.0):
     """Compulsory HBM bytes of one launch of the lifting kernel (the forward
     stages' variant), per node.  Reads: U (5), Ja (9), 1/J (1) (as in the
-    residual kernel), and per face
-    node both sides' traces (2 x 5) and the face normal + area (4).  Writes:
-    the viscous volume term (4) and the element's own face-normal viscous
-    flux (4 per face node; 4 bytes each in the FP32-flux mode)."""
+    residual kernel), and per face node the other side's trace (5; on Gauss
+    nodes both sides', 2 x 5: on LGL nodes the own trace is the face node's
+    state, which the kernel has in LDS) and the face normal + area (4).
+    Writes: the viscous volume term (4) and the element's own face-normal
+    viscous flux (4 per face node; 4 bytes each in the FP32-flux mode)."""
     n1 = w["N"] + 1
     fpn = 6 * n1 * n1 / n1 ** 3
-    reads = 5 + metric_values_per_dof(w, elem_frac) + fpn * (10 + 4)
+    traces = 5 if w["nodes"] == 1 else 10
+    reads = 5 + metric_values_per_dof(w, elem_frac) + fpn * (traces + 4)
     writes = 4 + fpn * 4 * (0.5 if precision == 1 else 1.0)
     return 8.0 * (reads + writes)
 
@@ -253,7 +255,8 @@ def adjoint_kernel_bytes_per_dof(w, elem_frac=0.0):
     into its last kernel), 8 bytes per value, per face node values times
     the face nodes per volume node (fpn):
       k_trace (the stage state's traces): U 5; writes 5 fpn;
-      k_lift, gradients (Navier-Stokes): U 5, Ja 9, 1/J 1, both traces 10 fpn,
+      k_lift, gradients (Navier-Stokes): U 5, Ja 9, 1/J 1, the traces (as in
+        lift_kernel_bytes_per_dof: 5 fpn on LGL nodes, 10 fpn on Gauss nodes),
         face 4 fpn; writes g 12 and the own gradient traces 12 fpn;
       k_adj_trace: lambda 5, 1/J 1; writes the surface adjoint 5 fpn
         (Navier-Stokes: first stage of a step only, the later ones take it
@@ -276,7 +279,8 @@ def adjoint_kernel_bytes_per_dof(w, elem_frac=0.0):
     vol_w = 5 + 4 * fpn if ns else 10
     b["k_adj_volume"] = vol_r + vol_w
     if ns:
-        b["k_lift_gradients"] = 5 + m10 + 14 * fpn + 12 + 12 * fpn
+        traces = 5 if w["nodes"] == 1 else 10
+        b["k_lift_gradients"] = 5 + m10 + (traces + 4) * fpn + 12 + 12 * fpn
         b["k_adj_lift_volume"] = m1 + 15 + 13 * fpn + 10 + 5 * fpn
     return {k: 8.0 * v for k, v in b.items()}
 

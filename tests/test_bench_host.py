@@ -37,12 +37,15 @@ def test_byte_models():
     assert bench.volume_kernel_bytes_per_dof(es) == 588
     # FP32-flux mode stores the face viscous fluxes as float
     assert bench.volume_kernel_bytes_per_dof(c2, precision=1) == 426 - 4 * 0.75 * 8
-    # lifting: reads U 5, Ja + 1/J 10, traces 2x5 and face geometry 4 per face node;
-    # writes the viscous volume term 4 and the own face viscous flux 4 per face node
-    assert bench.lift_kernel_bytes_per_dof(c2) == 8 * (15 + 0.75 * 14 + 4 + 0.75 * 4) == 260
+    # lifting: reads U 5, Ja + 1/J 10, the other side's trace 5 (LGL: the own trace is the
+    # face node's state) and face geometry 4 per face node; writes the viscous volume term 4
+    # and the own face viscous flux 4 per face node
+    assert bench.lift_kernel_bytes_per_dof(c2) == 8 * (15 + 0.75 * 9 + 4 + 0.75 * 4) == 230
+    # Gauss nodes: both sides' traces (2 x 5), 1.5 face nodes per node at N = 3
+    assert bench.lift_kernel_bytes_per_dof(es) == 8 * (15 + 1.5 * 14 + 4 + 1.5 * 4)
     # elements with constant metric terms read Ja + 1/J once per element (10 values per 512 nodes)
     assert bench.volume_kernel_bytes_per_dof(c2, elem_frac=1.0) == pytest.approx(426 - 8 * (10 - 10 / 512))
-    assert bench.lift_kernel_bytes_per_dof(c2, elem_frac=0.5) == pytest.approx(260 - 8 * 0.5 * (10 - 10 / 512))
+    assert bench.lift_kernel_bytes_per_dof(c2, elem_frac=0.5) == pytest.approx(230 - 8 * 0.5 * (10 - 10 / 512))
     a0, a1 = bench.adjoint_kernel_bytes_per_dof(c2), bench.adjoint_kernel_bytes_per_dof(c2, elem_frac=1.0)
     assert a0["k_adj_volume"] - a1["k_adj_volume"] == pytest.approx(8 * (10 - 10 / 512))
     assert a0["k_adj_trace"] - a1["k_adj_trace"] == pytest.approx(8 * (1 - 1 / 512))
