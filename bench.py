@@ -426,8 +426,8 @@ def main():
     vol_avg_s = vol_ms * 1e-3 / max(vol_n, 1)
     lift_ms, lift_n = prof["lift"]
     npe = (w["N"] + 1) ** 3
-    # (FV contexts: the residual kernel reads the node arrays)
-    elem_frac = 0.0 if args.fv != "none" else n_elem_metric / s.nElems
+    # (Navier-Stokes FV contexts: the residual kernel reads the node arrays)
+    elem_frac = 0.0 if args.fv != "none" and w["physics"] == 1 else n_elem_metric / s.nElems
     bytes_launch = volume_kernel_bytes_per_dof(w, elem_frac=elem_frac) * (dof - nfv * npe)
     kfam = "k_volume"
     if nfv:

@@ -704,11 +704,12 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   // metric row and added to the accumulator when that direction starts
   // (Gauss split form: read at the end)
   double vvn[4] = {0, 0, 0, 0};
-  // (FV contexts: the node arrays, which keeps the FV-face variants at N = 3
-  // and 5 within four waves per SIMD)
-  const NodeMetric nm = node_metric<FV == 0>(G, e, n3, t);
+  // (Navier-Stokes FV contexts: the node arrays, which keeps their FV-face
+  // variants at N = 3 and 5 within four waves per SIMD)
+  constexpr bool kElemM = FV == 0 || PHYS == 0;
+  const NodeMetric nm = node_metric<kElemM>(G, e, n3, t);
   auto fetch_end = [&]() {
-    if constexpr (FV == 0)
+    if constexpr (kElemM)
       sJn = nm.sj();
     else
       sJn = G.sJ[(size_t)e * n3 + t];
@@ -724,7 +725,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (volume_waves<N, NODES, FORM>())) vo
   auto fetch_dir = [&](int r) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      if constexpr (FV == 0)
+      if constexpr (kElemM)
         jn[c] = nm.ja(3 * r + c);
       else
         jn[c] = G.Ja[((size_t)(3 * r + c) * nE + e) * n3 + t];
