@@ -255,6 +255,7 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
   double fUL[5], fUR[5], fns[4];
   int fslot = 0;
   const NodeMetric nm = node_metric(G, e, n3, t);
+  const bool elm = G.em[(size_t)9 * nE + e] > 0.0;   // constant metric terms (uniform)
   if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = U[((size_t)v * nE + e) * n3 + t];
@@ -375,17 +376,38 @@ __global__ __launch_bounds__(Shape<N>::nth) void k_lift(Geo G, Phys P, const dou
     for (int r = 0; r < 3; ++r) {
       const int a = idx[r];
       const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+      if (elm) {
+        // constant metric terms: Ja^r times the line derivative of q, which
+        // equals the contraction of Ja^r q then (4 LDS reads per line node
+        // instead of 7, a third of the multiplies)
+        double dq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int l = 0; l < n1; ++l) {
-        const int tl = line_node<N>(r, l, pp, qq);
-        const double c = sb.Dhat[a * n1 + l];
-        const double j0 = sja[(3 * r + 0) * n3 + tl], j1 = sja[(3 * r + 1) * n3 + tl], j2 = sja[(3 * r + 2) * n3 + tl];
+        for (int l = 0; l < n1; ++l) {
+          const int tl = line_node<N>(r, l, pp, qq);
+          const double c = sb.Dhat[a * n1 + l];
+#pragma unroll
+          for (int qa = 0; qa < 4; ++qa) dq[qa] -= c * sq[qa * n3 + tl];
+        }
+        const double j0 = sja[(3 * r + 0) * n3 + t], j1 = sja[(3 * r + 1) * n3 + t], j2 = sja[(3 * r + 2) * n3 + t];
 #pragma unroll
         for (int qa = 0; qa < 4; ++qa) {
-          const double cq = c * sq[qa * n3 + tl];
-          acc[3 * qa + 0] -= cq * j0;
-          acc[3 * qa + 1] -= cq * j1;
-          acc[3 * qa + 2] -= cq * j2;
+          acc[3 * qa + 0] += dq[qa] * j0;
+          acc[3 * qa + 1] += dq[qa] * j1;
+          acc[3 * qa + 2] += dq[qa] * j2;
+        }
+      } else {
+#pragma unroll
+        for (int l = 0; l < n1; ++l) {
+          const int tl = line_node<N>(r, l, pp, qq);
+          const double c = sb.Dhat[a * n1 + l];
+          const double j0 = sja[(3 * r + 0) * n3 + tl], j1 = sja[(3 * r + 1) * n3 + tl], j2 = sja[(3 * r + 2) * n3 + tl];
+#pragma unroll
+          for (int qa = 0; qa < 4; ++qa) {
+            const double cq = c * sq[qa * n3 + tl];
+            acc[3 * qa + 0] -= cq * j0;
+            acc[3 * qa + 1] -= cq * j1;
+            acc[3 * qa + 2] -= cq * j2;
+          }
         }
       }
       // surface terms of the two faces normal to r

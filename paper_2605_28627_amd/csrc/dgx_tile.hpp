@@ -40,7 +40,7 @@ __device__ __forceinline__ void load_basis(DevBasis* dst, const DevBasis* src, i
 // the node arrays (Ja, then sJ) and, for every element whose terms are the
 // same at all of its nodes (affine), the per-element copy G.em, whose 1/J is
 // positive exactly for those elements.  Such an element's nodes all read the
-// copy and the node arrays are not touched (same values, same results).
+// copy and the node arrays are not touched (same values).
 // Selects only, no branches; base and st are uniform over the workgroup.
 struct NodeMetric {
   const double* base;

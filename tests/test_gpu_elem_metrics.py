@@ -3,9 +3,12 @@
 An affine element's metric terms are constant; the mesh set-up makes them
 exactly constant (node mean, when they agree to 1e-12), and the kernels of
 such an element then read one copy per element instead of the node arrays.
-The values are the same, so the residual, the lifted gradients, RK steps and
-the adjoint must be bitwise equal with the per-element copy on and off; on
-curved elements nothing changes (no element qualifies).
+The values are the same, so Euler residuals, RK steps and the adjoint must be
+bitwise equal with the per-element copy on and off.  The lifting of such an
+element forms its gradient as Ja^r (Dhat q) instead of Dhat (Ja^r q), equal
+in exact arithmetic for constant Ja: Navier-Stokes results agree to rounding
+(1e-12 of each output's largest entry).  On curved elements nothing changes
+(no element qualifies).
 """
 import sys
 
@@ -86,7 +89,12 @@ def test_element_metrics_bitwise_equal(S, case):
     finally:
         s.close()
     for k in on:
-        assert np.array_equal(on[k], off[k]), (k, np.abs(on[k] - off[k]).max())
+        if physics == 0 or curved:
+            assert np.array_equal(on[k], off[k]), (k, np.abs(on[k] - off[k]).max())
+        else:
+            diff, ref = np.abs(on[k] - off[k]).max(), np.abs(off[k]).max()
+            _say(k, "max |diff|", diff, "of", ref)
+            assert diff <= 1e-12 * ref, (k, diff, ref)
         assert np.array_equal(on[k], again[k]), k
         assert np.isfinite(on[k]).all(), k
 
