@@ -134,8 +134,13 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
   constexpr int SZ_V = FORM == 1 ? (ES ? 21 : 11) * n3 : 0;
   constexpr int SZ_B = SZ_F > SZ_V ? SZ_F : SZ_V;
   constexpr bool kSymLines = DGX_SYMMETRIC_PAIRS && (n1 == 4 || n1 == 8) && (n3 % 64 == 0);
+  // N = 7 LGL split form, Navier-Stokes: the lifting adjoint of an element
+  // with constant metric terms contracts w_r = Ja^r . (gbar/J) (4 values per
+  // direction and node, in sw) along the lines instead of gbar/J (12)
+  constexpr bool kW = S::nth >= 512 && ROE == 0 && NODES == 1 && FORM == 1 && PHYS == 1;
   __shared__ double sl[5 * n3];   // lam / J
   __shared__ double sB[SZ_B];     // surface adjoints, then aux + metric row
+  __shared__ double sw[kW ? 12 * n3 : 1];
   __shared__ double sub[ES ? 5 * S::nface : 1];   // ES: adjoints of the own projected traces
   __shared__ DevBasis sb;
   const int e = elem_of_block(blockIdx.x, G.nElems), t = threadIdx.x;
@@ -156,6 +161,7 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
   // overlaps the surface phase; elsewhere each is (re)loaded where it is
   // used, which keeps the other kernels' occupancy and spill-free budgets.
   constexpr bool kPrefetch = S::nth >= 512 && ROE == 0 && NODES == 1 && FORM == 1;
+  const bool elm = kW && G.em[(size_t)9 * nE + e] > 0.0;   // constant metric terms (uniform)
   double un[5] = {0, 0, 0, 0, 0}, jn[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   double gn[PHYS == 1 ? 12 : 1];
 #pragma unroll
@@ -321,6 +327,16 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
       if constexpr (PHYS == 1) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) sB[c * n3 + t] = sJ * gb[c];   // (the surface adjoints in sB are consumed)
+        if constexpr (kW) {
+          if (elm) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+              for (int qa = 0; qa < 4; ++qa)
+                sw[(4 * r + qa) * n3 + t] = jn[3 * r] * (sJ * gb[3 * qa]) + jn[3 * r + 1] * (sJ * gb[3 * qa + 1]) +
+                                            jn[3 * r + 2] * (sJ * gb[3 * qa + 2]);
+          }
+        }
         double Uu[5];
         prim_vjp(q, P.gm1, rpb[0], ub, rpb[1], Uu);
 #pragma unroll
@@ -372,7 +388,27 @@ __global__ __launch_bounds__(Shape<N>::nth, (Shape<N>::nth >= 512 ? DGX_ADJ_WAVE
       for (int qa = 0; qa < 4; ++qa) Qbar[qi + (size_t)qa * nS * n2] = acc[qa];
     }
     // the lifting adjoint's volume part: qbar = -sum_r Ja^r . (Dhat^T (sJ gbar))_r
-    if (act) {
+    // (constant metric terms: -sum_r Dhat^T w_r, the transpose of the
+    // lifting's factored gradient)
+    if (act && kW && elm) {
+      double qb[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int l = idx[r];
+        const int pp = r == 0 ? j : i, qq = r == 2 ? j : k;
+#pragma unroll
+        for (int a = 0; a < n1; ++a) {
+          const double c = sb.Dhat[a * n1 + l];
+          const int ta = line_node<N>(r, a, pp, qq);
+#pragma unroll
+          for (int qa = 0; qa < 4; ++qa) qb[qa] -= c * sw[(4 * r + qa) * n3 + ta];
+        }
+      }
+      double Uq[5];
+      qvars_vjp(cons2prim(un, P.gm1), P.gm1, P.Rinv, qb, Uq);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ub[v] += Uq[v];
+    } else if (act) {
       if (!kPrefetch) load_u();
       double qb[4] = {0, 0, 0, 0};
 #pragma unroll
