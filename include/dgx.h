@@ -162,8 +162,9 @@ dg_status dg_get_metrics(const dg_ctx* ctx, double* xyz, double* Ja, double* sJ,
  * element, and the residual, lifting and adjoint kernels read that copy
  * instead of the node arrays: 80 bytes per node less per kernel.  The
  * lifting of such an element forms the gradient's volume part as
- * Ja^r (Dhat q) rather than Dhat (Ja^r q) (equal for constant Ja); every other
- * result is bitwise equal to the node-array path.  On by default; enable = 0
+ * Ja^r (Dhat q) rather than Dhat (Ja^r q) (equal for constant Ja), and the
+ * adjoint uses its transpose: Euler results are bitwise equal to the
+ * node-array path, Navier-Stokes results agree to rounding.  On by default; enable = 0
  * sends every element to the node arrays (the paper's per-node storage).
  * Takes effect at once when a mesh is on the device, else at its upload;
  * metrics replaced by dg_upload_metrics are examined again. */
