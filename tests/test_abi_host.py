@@ -163,3 +163,33 @@ def test_hot_path_calls_need_a_device_mesh(dgx):
         assert L.dg_rhs(None, p, p, 0.0, None) == dgx.DG_ERR_ARG
     finally:
         dgx.dg_destroy(ctx)
+
+
+@pytest.mark.parametrize("N,nodes,rot", [(3, 0, None), (7, 1, None), (5, 1, 11)])
+def test_affine_metrics_snapped_constant(dgx, orc, N, nodes, rot):
+    """dg_set_mesh gives every element of an affine mesh (a box, also rotated)
+    metric terms that are exactly constant over its nodes (their node mean),
+    within the curl form's rounding of the oracle's; curved elements keep
+    their node values."""
+    mesh = I.box_mesh((3, 2, 2), (-PI,) * 3, (PI,) * 3, rotate_seed=rot)
+    ctx = dgx.dg_create(dgx.make_config(N, nodes=nodes))
+    try:
+        dgx.dg_set_mesh(ctx, mesh)
+        _, Ja, sJ, _ = dgx.dg_get_metrics(ctx)
+    finally:
+        dgx.dg_destroy(ctx)
+    nE = Ja.shape[1]
+    Jr, s = Ja.reshape(9, nE, -1), sJ.reshape(nE, -1)
+    assert (Jr == Jr[:, :, :1]).all() and (s == s[:, :1]).all()
+    _, Jo, Jao = orc.Oracle(dict(N=N, nodes=nodes), mesh).geometry()
+    assert np.abs(Ja - Jao).max() < 1e-12 * np.abs(Jao).max()
+    assert np.abs(1.0 / sJ - Jo).max() < 1e-12 * np.abs(Jo).max()
+    curved = I.box_mesh((2, 2, 2), (-PI,) * 3, (PI,) * 3, Ngeo=N, curved_amp=0.1, rotate_seed=rot)
+    ctx = dgx.dg_create(dgx.make_config(N, nodes=nodes))
+    try:
+        dgx.dg_set_mesh(ctx, curved)
+        _, Jc, _, _ = dgx.dg_get_metrics(ctx)
+    finally:
+        dgx.dg_destroy(ctx)
+    Jc = Jc.reshape(9, curved.nElems, -1)
+    assert not (Jc == Jc[:, :, :1]).all(axis=(0, 2)).any()
